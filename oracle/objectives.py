@@ -1,0 +1,95 @@
+"""Relaxed objectives and their gradients in float64 (the truth).
+
+Sec. 3 defines, for the adjacency matrix A (notation paragraph of Sec. 2):
+  * MIS, Eq. (3):           h(x)   = 1^T x - (gamma/2) x^T A x,  gamma > 1,
+                            grad h = 1 - gamma A x          (proof of Prop. 3.1)
+  * MaxCut Laplacian, Eq. (4): f_L(x) = (1/4) x^T L x, L = D - A; on {-1,1}^n
+                            it is the cut value.
+  * MaxCut perturbed Laplacian, Eq. (5): f_P(x) = x^T (L + lambda I) x.
+  * MaxCut adjacency, Eq. (6): f_A(x) = -x^T A x.
+  * MaxCut perturbed bias, Eq. (7): f_B(x) = -lambda 1^T x - x^T A x,
+                            grad f_B = -2 A x - lambda 1    (proof of Thm. 3.6)
+Weighted MaxCut (the +-1 torus) uses A_uv = w_uv.
+
+Columns of X are independent iterates (the batch of Alg. 3 / Alg. 4).
+Test infrastructure only.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+MIS = "mis"
+MAXCUT = "maxcut"
+
+
+def adjacency(graph, dtype=np.float64) -> sp.csr_matrix:
+    """A as a scipy CSR matrix (weights if present, else ones)."""
+    data = np.ones(graph.nnz, dtype=dtype) if graph.weight is None else graph.weight.astype(dtype)
+    return sp.csr_matrix((data, graph.col_idx.astype(np.int64), graph.row_ptr.astype(np.int64)),
+                         shape=(graph.n, graph.n))
+
+
+def h(X, A, gamma):
+    """Eq. (3) per column: 1^T x - (gamma/2) x^T A x."""
+    X = np.asarray(X, dtype=np.float64)
+    return X.sum(axis=0) - 0.5 * gamma * np.einsum("vb,vb->b", X, A @ X)
+
+
+def grad_h(X, A, gamma):
+    """1 - gamma A x (derivative in the proof of Prop. 3.1)."""
+    return 1.0 - gamma * (A @ np.asarray(X, dtype=np.float64))
+
+
+def f_B(X, A, lam):
+    """Eq. (7) per column: -lambda 1^T x - x^T A x."""
+    X = np.asarray(X, dtype=np.float64)
+    return -lam * X.sum(axis=0) - np.einsum("vb,vb->b", X, A @ X)
+
+
+def grad_f_B(X, A, lam):
+    """-2 A x - lambda 1 (proof of Thm. 3.6 (i))."""
+    return -2.0 * (A @ np.asarray(X, dtype=np.float64)) - lam
+
+
+def f_A(X, A):
+    """Eq. (6): -x^T A x."""
+    X = np.asarray(X, dtype=np.float64)
+    return -np.einsum("vb,vb->b", X, A @ X)
+
+
+def laplacian(A):
+    d = np.asarray(A.sum(axis=1)).ravel()
+    return sp.diags(d) - A
+
+
+def f_L(X, A):
+    """Eq. (4): (1/4) x^T L x."""
+    X = np.asarray(X, dtype=np.float64)
+    return 0.25 * np.einsum("vb,vb->b", X, laplacian(A) @ X)
+
+
+def f_P(X, A, lam):
+    """Eq. (5): x^T (L + lambda I) x."""
+    X = np.asarray(X, dtype=np.float64)
+    return np.einsum("vb,vb->b", X, laplacian(A) @ X) + lam * np.einsum("vb,vb->b", X, X)
+
+
+def objective(kind, X, A, param):
+    """The objective the path ascends: h for MIS, f_B for MaxCut."""
+    return h(X, A, param) if kind == MIS else f_B(X, A, param)
+
+
+def gradient(kind, X, A, param):
+    return grad_h(X, A, param) if kind == MIS else grad_f_B(X, A, param)
+
+
+def box(kind):
+    """Projection box of the PGA update (Sec. 3): [0,1] for MIS, [-1,1] for MaxCut."""
+    return (0.0, 1.0) if kind == MIS else (-1.0, 1.0)
+
+
+def linear_and_hessian(kind, param):
+    """Objective written as c^T x + (1/2) x^T H x with H = eta A:
+    MIS c = 1, eta = -gamma; MaxCut c = -lambda, eta = -2."""
+    return (1.0, -param) if kind == MIS else (-param, -2.0)
