@@ -1,0 +1,168 @@
+"""Benchmark of the batched PGA hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME]
+
+A "step" of this benchmark is one complete batched solve of the workload
+(every round: reset, PGA steps, rounding, local search, exact evaluation,
+acceptance) on synthetic inputs resident in HBM.  Prints ONE JSON line.
+
+value      = edge updates per second of the whole solve, edge update =
+             one stored CSR entry applied to one trajectory in one PGA step
+plain      = the same trajectories one at a time (B = 1 kernels, captured
+             step loops), whose incumbents must equal the batched ones
+roofline   = the dominant kernel (the one that runs the PGA steps),
+             algorithmic bytes per launch over its HIP-event launch time
+cpu_baseline = the CPU oracle on a bounded sample of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12  # bytes/s, MI355X
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def step_bytes(g, B, momentum=False):
+    """Compulsory bytes of one PGA step over every graph: the CSR once,
+    the iterate read once and written once (and the momentum)."""
+    n, nnz = g.n, g.nnz
+    b = 4 * (n + g.num_graphs) + 4 * nnz + 8 * n * B
+    if g.weight is not None:
+        b += 4 * nnz
+    if momentum:
+        b += 8 * n * B
+    return b
+
+
+def cpu_baseline(wl, g, budget_s=15.0):
+    """The oracle (float32 replay, as used for parity) on a bounded sample:
+    the first graph, a few trajectories, whole rounds until ~budget_s."""
+    from oracle import solver as osolver
+    sub = g.subgraph(0)
+    cols = np.arange(min(wl.batch, 8))
+    p = osolver.Params(batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=1, alpha=wl.alpha, seed=wl.seed,
+                       gamma=wl.gamma, lam=wl.lam, rho=wl.rho, reset_mode=wl.reset_mode,
+                       local_search=wl.local_search)
+    t0 = time.perf_counter()
+    rounds = 0
+    while True:
+        p.rounds = rounds + 1
+        osolver.solve_graph(wl.problem, sub, p, 0, cols=cols)
+        rounds += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or rounds >= wl.rounds:
+            break
+    # solve_graph recomputes all rounds each call: count the work of every call
+    total_rounds = rounds * (rounds + 1) // 2
+    eu = sub.nnz * len(cols) * wl.steps_per_round * total_rounds
+    return dict(value=eu / el, unit="edge-updates/s", cores=1, kind="oracle",
+                sample=f"graph 0 of {g.num_graphs} (n={sub.n}, nnz={sub.nnz}), trajectories 0..{len(cols) - 1} "
+                       f"of {wl.batch}, rounds 1..{rounds} of {wl.rounds} ({wl.steps_per_round} steps each), "
+                       f"float32 replay, single-threaded numpy, {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="reg3_maxcut")
+    ap.add_argument("--plan", default="auto")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); trajectories are independent, "
+              f"so N GPUs would each run B/N of them with no per-step communication", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from synth.workloads import WORKLOADS
+    from paper_2605_06921_amd import mqo
+
+    wl = WORKLOADS[args.workload]
+    log(f"[bench] building graph {wl.name}")
+    g = wl.make_graph()
+    dev = torch.device("cuda:0")
+    dg = mqo.DeviceGraph(g, dev)
+    kw = dict(batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=wl.rounds, alpha=wl.alpha, gamma=wl.gamma,
+              lam=wl.lam, rho=wl.rho, reset_mode=wl.reset_mode, local_search=wl.local_search, seed=wl.seed)
+    ws = mqo.Workspace(dev)
+    for i in range(args.warmup):
+        out = mqo.solve(wl.problem, dg, plan=args.plan, workspace=ws, **kw)
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {i}: plan={out['plan']} T={out['tile_cols']} threads={out['tile_threads']} "
+            f"best={out['best_value'][:4].tolist()}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eu = 0
+    kms, klaunch = 0.0, 0
+    for i in range(args.steps):
+        out = mqo.solve(wl.problem, dg, plan=args.plan, workspace=ws, **kw)
+        eu += out["edge_updates"]
+        kms += out["step_kernel_ms"]
+        klaunch += out["step_kernel_launches"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = eu / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+    log(f"[bench] timed {args.steps} solves: {ms_per_step:.3f} ms/solve, {value:.4e} EU/s")
+
+    res = dict(metric="edge-updates/s batched PGA vs plain at equal best MIS size / cut; HBM GB/s",
+               value=value, unit="edge-updates/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=ms_per_step, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+               data="synthetic",
+               config=dict(workload=wl.name, description=wl.description, graphs=g.num_graphs, n=g.n, nnz=g.nnz,
+                           batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=wl.rounds, alpha=wl.alpha,
+                           rho=wl.rho, plan=out["plan"], tile_cols=out["tile_cols"],
+                           tile_threads=out["tile_threads"], parallelism="dp1"))
+
+    # dominant kernel: the launches that run the PGA steps
+    steps_per_launch = wl.steps_per_round * wl.rounds / max(1, out["step_kernel_launches"])
+    per_launch_bytes = step_bytes(g, wl.batch) * steps_per_launch
+    avg_launch_s = kms / 1e3 / max(1, klaunch)
+    achieved = per_launch_bytes / avg_launch_s
+    res["roofline"] = dict(bound="hbm", achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
+                           frac=achieved / HBM_PEAK, traffic=None,
+                           kernel="k_tile_round" if out["plan"] == "persistent" else "k_pga_step",
+                           avg_launch_ms=avg_launch_s * 1e3, algorithmic_bytes_per_launch=per_launch_bytes)
+
+    if not args.no_plain:
+        log("[bench] plain per-trajectory solve")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pout = mqo.solve(wl.problem, dg, plan="plain", workspace=ws, **kw)
+        torch.cuda.synchronize()
+        pel = time.perf_counter() - t1
+        equal = bool(torch.equal(pout["traj_best_value"], out["traj_best_value"]) and
+                     torch.equal(pout["best_value"], out["best_value"]))
+        pval = pout["edge_updates"] / pel
+        res["plain"] = dict(value=pval, unit="edge-updates/s", seconds=pel, equal_best=equal,
+                            batched_over_plain=value / pval)
+        log(f"[bench] plain {pval:.4e} EU/s, batched/plain = {value / pval:.1f}x, equal best: {equal}")
+        if not equal:
+            raise SystemExit("plain and batched incumbents differ")
+    res["best_value"] = out["best_value"].cpu().tolist()[:8]
+
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        res["cpu_baseline"] = cpu_baseline(wl, g, args.cpu_budget)
+        log(f"[bench] cpu oracle {res['cpu_baseline']['value']:.4e} EU/s")
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

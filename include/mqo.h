@@ -1,0 +1,231 @@
+/*
+ * mqo.h -- C-ABI of libmqo, the MI355X (gfx950) implementation of the
+ * data-parallel hot path of mutation-guided quadratic optimisation for
+ * Maximum Independent Set and MaxCut (arXiv 2605.06921).
+ *
+ * Conventions (every entry point):
+ *   - Array arguments are DEVICE pointers unless marked (host).  The caller
+ *     allocates and owns every buffer; the library keeps no device memory
+ *     between calls except its launch-plan and hipGraph caches, released by
+ *     mqo_clear_caches().  Scratch memory is the caller's workspace.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Every function returns an mqo_status; no C++ exception crosses the
+ *     ABI.  On failure nothing was enqueued unless the status is
+ *     MQO_ERR_HIP, and mqo_last_error() (thread-local) holds the detail.
+ *   - Iterates are float32, vertex-major: X[v * B + b] is vertex v of
+ *     trajectory b.  Binary solutions are int8 in the same layout: MIS z in
+ *     {0,1}, MaxCut s in {-1,+1}.
+ *   - Trajectory b of graph g has the id t = g * B + b; random draws are
+ *     keyed by (seed, purpose, t, round, local vertex index), so results do
+ *     not depend on the launch plan or on the graph's position in a batch.
+ *   - Float32 steps follow one fixed operation order (per row, neighbours
+ *     summed in ascending CSR order with one rounding per add, no fused
+ *     multiply-add), so every launch plan gives bit-identical iterates.
+ */
+#ifndef MQO_H
+#define MQO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MQO_VERSION 100
+
+typedef enum {
+  MQO_OK = 0,
+  MQO_ERR_INVALID_ARG = -1,   /* a parameter or pointer is out of range      */
+  MQO_ERR_INVALID_GRAPH = -2, /* the CSR is not canonical (see mqo_graph)    */
+  MQO_ERR_WORKSPACE = -3,     /* workspace NULL or smaller than required     */
+  MQO_ERR_HIP = -4,           /* a HIP runtime call failed                   */
+  MQO_ERR_UNSUPPORTED = -5,   /* valid request this build does not implement */
+  MQO_ERR_INTERNAL = -6       /* an internal invariant failed                */
+} mqo_status;
+
+/* The relaxed objective that is ascended.
+ * MQO_OBJ_MIS_H:     h(x) = 1^T x - (gamma/2) x^T A x on [0,1]^n, gamma > 1
+ *                    (Sec. 3, Eq. (3)); grad = 1 - gamma A x.
+ * MQO_OBJ_MAXCUT_FB: f_B(x) = -lambda 1^T x - x^T A x on [-1,1]^n,
+ *                    0 < lambda < 2 (Sec. 3, Eq. (7), Thm. 3.6);
+ *                    grad = -2 A x - lambda.  A_uv = w_uv when weighted. */
+typedef enum { MQO_OBJ_MIS_H = 0, MQO_OBJ_MAXCUT_FB = 1 } mqo_objective;
+
+enum { MQO_INIT_UNIFORM = 0, MQO_INIT_DEGREE = 1 };
+enum { MQO_RESET_ZERO = 0, MQO_RESET_FLIP = 1 };
+enum { MQO_LS_NONE = 0, MQO_LS_ONE_FLIP = 1 };
+enum { MQO_PLAN_AUTO = 0, MQO_PLAN_PLAIN = 1, MQO_PLAN_BATCHED = 2, MQO_PLAN_PERSISTENT = 3 };
+
+/* Graph (notation of Sec. 2): one undirected graph, or G graphs as one
+ * block-diagonal CSR with global column indices.  Canonical form: row_ptr
+ * monotone with row_ptr[0] = 0 and row_ptr[n_total] = nnz_total; columns
+ * strictly ascending inside a row; symmetric; no self loops; every column
+ * inside its own graph's vertex range; weight (MaxCut only) symmetric. */
+typedef struct {
+  int32_t num_graphs;         /* G >= 1                                       */
+  const int64_t *vtx_offset;  /* (host) [G+1], vtx_offset[0] = 0, increasing  */
+  int64_t n_total;            /* = vtx_offset[G]                              */
+  int64_t nnz_total;          /* stored entries = 2 |E|, < 2^31               */
+  const int32_t *row_ptr;     /* [n_total + 1]                                */
+  const int32_t *col_idx;     /* [nnz_total]                                  */
+  const int32_t *weight;      /* [nnz_total] or NULL (unit weights)           */
+} mqo_graph;
+
+/* Search parameters.  Fill with mqo_params_default() first. */
+typedef struct {
+  uint32_t struct_size;    /* sizeof(mqo_params)                                */
+  int32_t batch;           /* B >= 1 trajectories per graph                     */
+  int32_t steps_per_round; /* PGA steps per round, >= 0                         */
+  int32_t rounds;          /* >= 1; round 0 starts from x0, later rounds from
+                              the incumbent after the reset of Sec. 4         */
+  int32_t check_every;     /* 0 (early exit on the checker is not offered)      */
+  float alpha;             /* step size, > 0                                    */
+  float momentum;          /* heavy-ball coefficient in [0, 1); 0 = plain PGA   */
+  float gamma;             /* MIS edge penalty, > 1                             */
+  float lambda;            /* MaxCut bias, in (0, 2)                            */
+  double rho;              /* reset fraction in [0, 1); |R| = floor(rho * n_g)  */
+  float init_sigma;        /* noise of the degree-based initialisation, >= 0    */
+  int32_t init_mode;       /* MQO_INIT_*                                        */
+  int32_t reset_mode;      /* MQO_RESET_*                                       */
+  int32_t local_search;    /* MQO_LS_*                                          */
+  int32_t plan;            /* MQO_PLAN_*                                        */
+  int32_t tile_cols;       /* persistent plan: trajectories per workgroup, a
+                              power of two <= 64, or 0 = autotune             */
+  int32_t tile_threads;    /* persistent plan: 256, 512 or 1024, 0 = autotune   */
+  uint64_t seed;
+  double time_budget_s;    /* 0 = none; otherwise no round starts after it      */
+} mqo_params;
+
+/* Outputs of a solve.  Device arrays are written; host fields are set. */
+typedef struct {
+  int8_t *best_x;              /* [n_total]: answer of each graph             */
+  int64_t *best_value;         /* [G]: MIS size / cut weight (-1 = none)       */
+  int64_t *traj_best_value;    /* [G*B] incumbent values, or NULL             */
+  int8_t *traj_best_x;         /* [n_total*B] incumbents, or NULL             */
+  int64_t edge_updates;        /* (host) sum_g nnz_g * B * steps executed      */
+  int64_t steps_executed;      /* (host) PGA steps per trajectory              */
+  int32_t rounds_executed;     /* (host)                                       */
+  int32_t plan_used;           /* (host) MQO_PLAN_PLAIN/BATCHED/PERSISTENT     */
+  int32_t tile_cols_used;      /* (host) persistent plan choice, else 0        */
+  int32_t tile_threads_used;   /* (host)                                       */
+  int64_t ls_iterations;       /* (host) local-search iterations summed over
+                                  rounds (per round: the largest count of any
+                                  graph / trajectory tile)                   */
+  double step_kernel_ms;       /* (host) HIP-event time of the launches that
+                                  run the PGA steps (persistent plan: the
+                                  whole-round tile kernel), on the stream
+                                  they run on                               */
+  int64_t step_kernel_launches;/* (host) number of such launches            */
+} mqo_result;
+
+void mqo_params_default(mqo_params *p);
+
+/* Bytes of workspace a solve needs (0 on invalid input).  The same size
+ * covers every plan. */
+size_t mqo_workspace_size(const mqo_graph *g, const mqo_params *p, mqo_objective obj);
+
+/* Batched mutation-guided search (Alg. 1 for MIS, Alg. 2 for MaxCut, run as
+ * B independent trajectories per graph, the batch form of Alg. 3 / 4).
+ * Round r of trajectory t: r = 0 starts from x0 (or the init rule), r > 0
+ * from the incumbent with floor(rho n) uniformly chosen coordinates set to 0
+ * (Sec. 4); then steps_per_round PGA steps x <- Pi(x + alpha grad);
+ * threshold rounding (x > 0.5 / x > 0, Sec. 3); optional 1-flip local
+ * search; exact int64 evaluation (MIS size if independent else -1; cut
+ * weight); the incumbent is replaced only on strict improvement (Sec. 4).
+ * x0: [n_total*B] start iterate or NULL.  Blocks until done; validates the
+ * graph on the device first.  ws must hold mqo_workspace_size() bytes. */
+int mqo_solve_mis(const mqo_graph *g, const mqo_params *p, const float *x0,
+                  mqo_result *r, void *ws, size_t ws_bytes, void *stream);
+int mqo_solve_maxcut(const mqo_graph *g, const mqo_params *p, const float *x0,
+                     mqo_result *r, void *ws, size_t ws_bytes, void *stream);
+
+/* Objective and gradient (Eq. (3) / Eq. (7)) of B iterates per graph:
+ * f_out[g*B+b] = c^T x + (1/2) x^T H x accumulated in float64 (H = -gamma A,
+ * c = 1 for MIS; H = -2A, c = -lambda for MaxCut), and
+ * grad_out = scale_b * (c + H x) in float32 (the SpMM gradient).  Either
+ * output may be NULL.  scale: [G*B] or NULL (= 1).  Asynchronous on
+ * `stream`; the graph is assumed canonical (see mqo_validate_graph).
+ * ws: mqo_objective_workspace_size() bytes (may be NULL when f_out is). */
+size_t mqo_objective_workspace_size(const mqo_graph *g, int32_t B);
+int mqo_objective_grad(const mqo_graph *g, mqo_objective obj, float param,
+                       const float *X, int32_t B, const float *scale,
+                       double *f_out, float *grad_out,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* K unrolled PGA steps x_{k+1} = Pi(x_k + alpha grad(x_k)) (momentum 0).
+ * Forward stores x_{j*ckpt_every} in ckpt[j] ([K/ckpt_every][n_total*B])
+ * and x_K in XK.  K must be a multiple of ckpt_every.  Backward takes
+ * dL/dx_K and returns dL/dx_0 and dL/dalpha per trajectory ([G*B], float64),
+ * recomputing each segment from its checkpoint.  Clip derivative: 1 iff
+ * lo <= x + alpha grad <= hi.  Asynchronous on `stream`; ws holds
+ * mqo_unrolled_workspace_size() bytes. */
+size_t mqo_unrolled_workspace_size(const mqo_graph *g, int32_t B, int32_t ckpt_every);
+int mqo_pga_unrolled_forward(const mqo_graph *g, mqo_objective obj, float param, float alpha,
+                             int32_t K, int32_t ckpt_every, const float *X0, float *ckpt,
+                             float *XK, int32_t B, void *ws, size_t ws_bytes, void *stream);
+int mqo_pga_unrolled_backward(const mqo_graph *g, mqo_objective obj, float param, float alpha,
+                              int32_t K, int32_t ckpt_every, const float *ckpt,
+                              const float *dL_dXK, float *dL_dX0, double *dL_dalpha,
+                              int32_t B, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- building blocks of one round (asynchronous, stream-ordered) ---- */
+
+/* x0 by the initialisation rule: MQO_INIT_UNIFORM draws u ~ U[0,1) with 24
+ * random bits (MIS x = u; MaxCut x = 2u - 1); MQO_INIT_DEGREE is
+ * Pi(d_base + N(0, sigma^2)) of Alg. 1 / Alg. 2.  Uses p->batch, seed,
+ * init_mode, init_sigma. */
+int mqo_init_iterate(const mqo_graph *g, mqo_objective obj, const mqo_params *p,
+                     float *X, void *stream);
+
+/* `nsteps` PGA steps in place on X (and V, the momentum, when
+ * p->momentum != 0; V may be NULL otherwise).  Uses p->batch, alpha,
+ * momentum, gamma / lambda.  tmp: [n_total*B] float scratch. */
+int mqo_pga_steps(const mqo_graph *g, mqo_objective obj, const mqo_params *p,
+                  float *X, float *V, float *tmp, int32_t nsteps, void *stream);
+
+/* The building blocks below take the workspace of a solve with the same
+ * graph and batch (mqo_workspace_size). */
+
+/* Threshold rounding and exact evaluation of X ([n_total*B]):
+ * Z = rounding (int8), value[G*B] as in mqo_solve_*, and for MIS
+ * conflicts[G*B] (edges inside I, or NULL) and fixed[G*B] (int8, the
+ * checker of Eq. (8): 1 iff I is a maximal independent set; or NULL). */
+int mqo_round_evaluate(const mqo_graph *g, mqo_objective obj, const float *X, int32_t B,
+                       int8_t *Z, int64_t *value, int64_t *conflicts, int8_t *fixed,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* 1-flip local search in place on Z (parallel independent-set rule: every
+ * iteration flips the positive-gain vertices whose key (gain, Philox
+ * priority, -v) beats all positive-gain neighbours; stops when no gain is
+ * positive).  `round` keys the priorities.  iterations: (host) out or NULL.
+ * Blocks (the stopping test reads a device flag). */
+int mqo_local_search(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t seed,
+                     int32_t round, int8_t *Z, int64_t *iterations,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* Mutation reset (Sec. 4): X = Zbest as float, then in every trajectory the
+ * k = floor(rho n_g) vertices with the smallest (key, v) are set to 0
+ * (MQO_RESET_ZERO) or to the complement (MQO_RESET_FLIP).  key = Philox
+ * draw (seed, round) or, when keys != NULL, keys[v*B+b] (uint32). */
+int mqo_reset(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t seed, int32_t round,
+              double rho, int32_t mode, const int8_t *Zbest, const uint32_t *keys,
+              float *X, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- validation and misc ---- */
+
+/* Canonical-form check of a host CSR (no GPU needed). */
+int mqo_validate_graph_host(int64_t n, int64_t nnz, const int32_t *row_ptr,
+                            const int32_t *col_idx, const int32_t *weight);
+/* The same check on the device arrays of g; blocks. */
+int mqo_validate_graph(const mqo_graph *g, void *stream);
+
+const char *mqo_status_string(int status);
+const char *mqo_last_error(void);
+int mqo_version(void);
+void mqo_clear_caches(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MQO_H */

@@ -42,11 +42,15 @@ class Params:
     init_sigma: float = 0.0
 
 
-def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32", trace=None):
+def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32", trace=None, cols=None):
     """Run the search on one graph (local indices).  Returns
-    (traj_best_value int64[B], traj_best_z int8[n][B])."""
-    n, B = graph.n, p.batch
-    traj = graph_index * B + np.arange(B, dtype=np.int64)
+    (traj_best_value int64[B], traj_best_z int8[n][B]).  Trajectories are
+    independent, so ``cols`` may select a subset b of them (x0 then holds
+    only those columns); the outputs hold the selected columns in order."""
+    n = graph.n
+    cols = np.arange(p.batch, dtype=np.int64) if cols is None else np.asarray(cols, dtype=np.int64)
+    B = len(cols)
+    traj = graph_index * p.batch + cols
     param = p.gamma if kind == obj.MIS else p.lam
     A = obj.adjacency(graph) if precision == "fp64" else None
     k = discrete.reset_count(p.rho, n)

@@ -1,0 +1,1133 @@
+// libmqo host runtime: argument and graph validation, workspace layout,
+// launch plans (persistent tile, batched with hipGraph-captured step
+// loops, plain per trajectory), the tile autotuner, and the C-ABI entry
+// points declared in include/mqo.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/mqo.h"
+#include "kernels.h"
+
+using namespace mqo;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return status;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t _e = (expr);                                                                \
+    if (_e != hipSuccess)                                                                  \
+      return fail(MQO_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, \
+                  __LINE__);                                                               \
+  } while (0)
+
+#define TRY(expr)               \
+  do {                          \
+    int _s = (expr);            \
+    if (_s != MQO_OK) return _s; \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// process-wide resources: a private stream (default priority) for blocking
+// entry points, pinned readback memory, and plan caches
+// ---------------------------------------------------------------------------
+struct Resources {
+  std::mutex mu;
+  hipStream_t stream = nullptr;
+  int32_t *pinned = nullptr;  // 1024 ints
+  int32_t *small = nullptr;   // 64 device ints of scratch for entry points without a workspace
+  int device = -1;
+  int lds_limit = 0;
+  std::map<std::string, std::pair<int, int>> tile_tuning;  // key -> (T, threads)
+};
+
+Resources &res() {
+  static Resources r;
+  return r;
+}
+
+int ensure_resources() {
+  Resources &r = res();
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (r.device == dev && r.stream) return MQO_OK;
+  if (r.stream) {
+    (void)hipStreamDestroy(r.stream);
+    r.stream = nullptr;
+  }
+  if (!r.pinned) HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&r.pinned), 1024 * sizeof(int32_t), 0));
+  HIP_TRY(hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking));
+  if (r.small) (void)hipFree(r.small);
+  HIP_TRY(hipMalloc(reinterpret_cast<void **>(&r.small), 64 * sizeof(int32_t)));
+  int lds = 0;
+  HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  r.lds_limit = lds;
+  r.device = dev;
+  return MQO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+int check_graph_args(const mqo_graph *g, bool need_weight_free) {
+  if (!g) return fail(MQO_ERR_INVALID_ARG, "graph is NULL");
+  if (g->num_graphs < 1) return fail(MQO_ERR_INVALID_ARG, "num_graphs must be >= 1");
+  if (!g->vtx_offset) return fail(MQO_ERR_INVALID_ARG, "vtx_offset is NULL");
+  if (g->vtx_offset[0] != 0) return fail(MQO_ERR_INVALID_GRAPH, "vtx_offset[0] must be 0");
+  for (int32_t i = 0; i < g->num_graphs; ++i)
+    if (g->vtx_offset[i + 1] <= g->vtx_offset[i])
+      return fail(MQO_ERR_INVALID_GRAPH, "graph %d has no vertices (vtx_offset must increase)", i);
+  if (g->vtx_offset[g->num_graphs] != g->n_total)
+    return fail(MQO_ERR_INVALID_GRAPH, "vtx_offset[G] != n_total");
+  if (g->n_total < 1 || g->n_total >= (int64_t)1 << 31) return fail(MQO_ERR_INVALID_GRAPH, "n_total out of range");
+  if (g->nnz_total < 0 || g->nnz_total >= (int64_t)1 << 31) return fail(MQO_ERR_INVALID_GRAPH, "nnz out of range");
+  if (!g->row_ptr) return fail(MQO_ERR_INVALID_ARG, "row_ptr is NULL");
+  if (g->nnz_total > 0 && !g->col_idx) return fail(MQO_ERR_INVALID_ARG, "col_idx is NULL");
+  if (need_weight_free && g->weight) return fail(MQO_ERR_INVALID_ARG, "the MIS objective takes an unweighted graph");
+  return MQO_OK;
+}
+
+int check_params(const mqo_params *p, mqo_objective obj) {
+  if (!p) return fail(MQO_ERR_INVALID_ARG, "params is NULL");
+  if (p->struct_size != sizeof(mqo_params)) return fail(MQO_ERR_INVALID_ARG, "params.struct_size mismatch");
+  if (p->batch < 1) return fail(MQO_ERR_INVALID_ARG, "batch must be >= 1");
+  if (p->steps_per_round < 0) return fail(MQO_ERR_INVALID_ARG, "steps_per_round must be >= 0");
+  if (p->rounds < 1) return fail(MQO_ERR_INVALID_ARG, "rounds must be >= 1");
+  if (p->check_every != 0) return fail(MQO_ERR_UNSUPPORTED, "check_every must be 0");
+  if (!(p->alpha > 0.0f) || !std::isfinite(p->alpha)) return fail(MQO_ERR_INVALID_ARG, "alpha must be > 0");
+  if (!(p->momentum >= 0.0f && p->momentum < 1.0f)) return fail(MQO_ERR_INVALID_ARG, "momentum must be in [0,1)");
+  if (obj == MQO_OBJ_MIS_H && !(p->gamma > 1.0f && std::isfinite(p->gamma)))
+    return fail(MQO_ERR_INVALID_ARG, "gamma must be > 1 (Eq. 3)");
+  if (obj == MQO_OBJ_MAXCUT_FB && !(p->lambda > 0.0f && p->lambda < 2.0f))
+    return fail(MQO_ERR_INVALID_ARG, "lambda must be in (0, 2) (Thm. 3.6)");
+  if (!(p->rho >= 0.0 && p->rho < 1.0)) return fail(MQO_ERR_INVALID_ARG, "rho must be in [0, 1)");
+  if (!(p->init_sigma >= 0.0f) || !std::isfinite(p->init_sigma))
+    return fail(MQO_ERR_INVALID_ARG, "init_sigma must be >= 0");
+  if (p->init_mode != MQO_INIT_UNIFORM && p->init_mode != MQO_INIT_DEGREE)
+    return fail(MQO_ERR_INVALID_ARG, "bad init_mode");
+  if (p->reset_mode != MQO_RESET_ZERO && p->reset_mode != MQO_RESET_FLIP)
+    return fail(MQO_ERR_INVALID_ARG, "bad reset_mode");
+  if (p->local_search != MQO_LS_NONE && p->local_search != MQO_LS_ONE_FLIP)
+    return fail(MQO_ERR_INVALID_ARG, "bad local_search");
+  if (p->plan < MQO_PLAN_AUTO || p->plan > MQO_PLAN_PERSISTENT) return fail(MQO_ERR_INVALID_ARG, "bad plan");
+  if (p->tile_cols != 0 && (p->tile_cols < 1 || p->tile_cols > 64 || (p->tile_cols & (p->tile_cols - 1))))
+    return fail(MQO_ERR_INVALID_ARG, "tile_cols must be 0 or a power of two <= 64");
+  if (p->tile_threads != 0 && p->tile_threads != 256 && p->tile_threads != 512 && p->tile_threads != 1024)
+    return fail(MQO_ERR_INVALID_ARG, "tile_threads must be 0, 256, 512 or 1024");
+  if (p->time_budget_s < 0.0) return fail(MQO_ERR_INVALID_ARG, "time_budget_s must be >= 0");
+  return MQO_OK;
+}
+
+int64_t max_graph_rows(const mqo_graph *g) {
+  int64_t m = 0;
+  for (int32_t i = 0; i < g->num_graphs; ++i) m = std::max(m, g->vtx_offset[i + 1] - g->vtx_offset[i]);
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout (one layout covers every plan)
+// ---------------------------------------------------------------------------
+struct Layout {
+  size_t X, Xt, V, Z, Zb, NB, PRIO, F, value, best, acc, act, voff, rpat, bestb, dmax, err, reset, tzs, tnb, tprio,
+      tfl, tvm, tls, pX, pXt, pV, total;
+};
+
+Layout make_layout(const mqo_graph *g, int32_t B) {
+  Layout L{};
+  const int64_t n = g->n_total, G = g->num_graphs, nb = n * B;
+  const int64_t tiles_elems = G * (int64_t)(B + 63) * max_graph_rows(g);  // tile scratch, any T <= 64
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.X = take(nb * 4);
+  L.Xt = take(nb * 4);
+  L.V = take(nb * 4);
+  L.Z = take(nb);
+  L.Zb = take(nb);
+  L.NB = take(nb * 4);
+  L.PRIO = take(nb * 4);
+  L.F = take(nb);
+  L.value = take(G * B * 8);
+  L.best = take(G * B * 8);
+  L.acc = take(3 * (size_t)B * 8);
+  L.act = take(64 * 4);
+  L.voff = take((G + 1) * 8);
+  L.rpat = take((G + 1) * 4);
+  L.bestb = take(G * 4);
+  L.dmax = take(64);
+  L.err = take(64);
+  L.reset = take(reset_scratch_bytes(B));
+  L.tzs = take(tiles_elems);
+  L.tnb = take(tiles_elems * 4);
+  L.tprio = take(tiles_elems * 4);
+  L.tfl = take(tiles_elems);
+  L.tvm = take(tiles_elems * 4);
+  L.tls = take(G * (int64_t)(B + 63) * 4);
+  L.pX = take(n * 4);  // plain plan: one trajectory as contiguous vectors
+  L.pXt = take(n * 4);
+  L.pV = take(n * 4);
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+T *at(void *ws, size_t off) {
+  return reinterpret_cast<T *>(reinterpret_cast<char *>(ws) + off);
+}
+
+GraphView view_of(const mqo_graph *g, int32_t i) {
+  GraphView v;
+  v.row_ptr = g->row_ptr;
+  v.col_idx = g->col_idx;
+  v.weight = g->weight;
+  v.lo = g->vtx_offset[i];
+  v.n = g->vtx_offset[i + 1] - g->vtx_offset[i];
+  return v;
+}
+
+int read_back_i32(const int32_t *dev, int count, std::vector<int32_t> &out, hipStream_t s) {
+  Resources &r = res();
+  out.resize(count);
+  for (int off = 0; off < count; off += 1024) {
+    const int c = std::min(1024, count - off);
+    HIP_TRY(hipMemcpyAsync(r.pinned, dev + off, c * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(out.data() + off, r.pinned, c * sizeof(int32_t));
+  }
+  return MQO_OK;
+}
+
+// device-side canonical-form check; voff_dev must already hold vtx_offset
+int validate_on_device(const mqo_graph *g, int64_t *voff_dev, int32_t *err_dev, hipStream_t s) {
+  launch_fill_i32(err_dev, 1, 0, s);
+  launch_validate_rows(g->row_ptr, g->n_total, g->nnz_total, err_dev, s);
+  HIP_TRY(hipGetLastError());
+  std::vector<int32_t> e;
+  TRY(read_back_i32(err_dev, 1, e, s));
+  if (e[0]) return fail(MQO_ERR_INVALID_GRAPH, "row_ptr is not monotone within [0, nnz]");
+  if (g->nnz_total > 0) {
+    launch_validate_cols(g->row_ptr, g->col_idx, g->weight, voff_dev, g->num_graphs, g->n_total, err_dev, s);
+    HIP_TRY(hipGetLastError());
+    TRY(read_back_i32(err_dev, 1, e, s));
+    if (e[0] & 2) return fail(MQO_ERR_INVALID_GRAPH, "a column index leaves its graph's vertex range");
+    if (e[0] & 4) return fail(MQO_ERR_INVALID_GRAPH, "self loop");
+    if (e[0] & 8) return fail(MQO_ERR_INVALID_GRAPH, "columns not strictly ascending within a row");
+    if (e[0] & 16) return fail(MQO_ERR_INVALID_GRAPH, "adjacency not symmetric");
+    if (e[0] & 32) return fail(MQO_ERR_INVALID_GRAPH, "weights not symmetric");
+  }
+  return MQO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the solve
+// ---------------------------------------------------------------------------
+struct Solve {
+  const mqo_graph *g;
+  const mqo_params *p;
+  mqo_objective obj;
+  bool maxcut;
+  float param;
+  int32_t B, G;
+  int64_t n_max;
+  std::vector<int64_t> nnz_g;
+  void *ws;
+  Layout L;
+  hipStream_t s;
+  const float *x0;
+  int64_t ls_iters = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;  // around the step launches
+
+  int begin_timed(hipEvent_t *e0) {
+    HIP_TRY(hipEventCreate(e0));
+    HIP_TRY(hipEventRecord(*e0, s));
+    return MQO_OK;
+  }
+  int end_timed(hipEvent_t e0) {
+    hipEvent_t e1;
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e1, s));
+    timed.push_back({e0, e1});
+    return MQO_OK;
+  }
+  // after the stream is synchronised
+  double timed_ms() {
+    double total = 0.0;
+    for (auto &p : timed) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, p.first, p.second) == hipSuccess) total += ms;
+    }
+    return total;
+  }
+  ~Solve() {
+    for (auto &p : timed) {
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
+    }
+  }
+};
+
+int k_of(const Solve &S, int64_t n) { return (int)std::floor(S.p->rho * (double)n); }
+
+// initial iterate of every graph into X ([n][B]) unless x0 is given
+int init_x(Solve &S, float *X) {
+  for (int32_t gi = 0; gi < S.G; ++gi) {
+    const GraphView gv = view_of(S.g, gi);
+    if (S.p->init_mode == MQO_INIT_UNIFORM)
+      launch_init_uniform(S.maxcut, X, gv.lo, gv.n, S.B, S.B, S.p->seed, (uint64_t)gi * S.B, S.s);
+    else
+      launch_init_degree(S.maxcut, X, S.g->row_ptr, at<int32_t>(S.ws, S.L.dmax), gv.lo, gv.n, S.B, S.B, S.p->seed,
+                         (uint64_t)gi * S.B, S.p->init_sigma, S.s);
+  }
+  HIP_TRY(hipGetLastError());
+  return MQO_OK;
+}
+
+// 1-flip local search on columns [traj0, traj0+ncols) of one graph (arrays
+// at ld).  Iterations are enqueued Q at a time; each one is skipped on the
+// device once an earlier one found no positive gain, and the host reads the
+// Q flags to decide whether to continue.
+int ls_core(bool maxcut, const GraphView &gv, int64_t nnz_total, uint64_t seed, int32_t round, int8_t *Z, int32_t *NB,
+            uint32_t *PRIO, int8_t *F, int32_t *act, long long *acc, int64_t *value_scratch, int32_t ncols,
+            int32_t ld, uint64_t traj0, hipStream_t s, int64_t *iters_out) {
+  // neighbour counts for the current Z (the values computed here are discarded)
+  launch_evaluate(maxcut, gv, Z, NB, acc, value_scratch, nullptr, nullptr, ncols, ld, s);
+  launch_ls_prio(PRIO, gv.lo, gv.n, ncols, ld, seed, traj0, (uint64_t)round, s);
+  const int Q = 8;
+  int64_t iters = 0;
+  const int64_t cap = 4 * (gv.n + nnz_total) + 64;  // never reached: every iteration gains
+  std::vector<int32_t> flags;
+  while (true) {
+    launch_fill_i32(act, Q, 0, s);
+    for (int q = 0; q < Q; ++q)
+      launch_ls_iteration(maxcut, gv, Z, NB, PRIO, F, act + q, q ? act + q - 1 : nullptr, ncols, ld, s);
+    HIP_TRY(hipGetLastError());
+    TRY(read_back_i32(act, Q, flags, s));
+    int done = 0;
+    for (int q = 0; q < Q; ++q) {
+      if (flags[q])
+        ++iters;
+      else {
+        done = 1;
+        break;
+      }
+    }
+    if (done) break;
+    if (iters > cap) return fail(MQO_ERR_INTERNAL, "local search did not terminate");
+  }
+  if (iters_out) *iters_out = iters;
+  return MQO_OK;
+}
+
+int run_local_search(Solve &S, const GraphView &gv, int8_t *Z, int32_t *NB, uint32_t *PRIO, int8_t *F, int32_t ncols,
+                     int32_t ld, uint64_t traj0, int32_t round, int64_t *iters_out) {
+  return ls_core(S.maxcut, gv, S.g->nnz_total, S.p->seed, round, Z, NB, PRIO, F, at<int32_t>(S.ws, S.L.act),
+                 at<long long>(S.ws, S.L.acc), at<int64_t>(S.ws, S.L.value), ncols, ld, traj0, S.s, iters_out);
+}
+
+// steps on one graph, ping-pong X <-> Xt, result back in X
+struct StepLoop {
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  ~StepLoop() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+void enqueue_steps(Solve &S, const GraphView &gv, float *X, float *Xt, float *V, int32_t ncols, int32_t ld,
+                   int32_t steps) {
+  const StepCfg cfg = default_step_cfg(ncols, ld);
+  float *a = X, *b = Xt;
+  for (int32_t st = 0; st < steps; ++st) {
+    launch_pga_step(S.maxcut, gv, a, b, V, ncols, ld, cfg, S.p->alpha, S.p->momentum, S.param, S.s);
+    std::swap(a, b);
+  }
+  if (a != X) launch_copy_f32(a + gv.lo * ld, X + gv.lo * ld, gv.n * ld, S.s);
+}
+
+int run_steps(Solve &S, StepLoop &loop, bool use_graph, const GraphView &gv, float *X, float *Xt, float *V,
+              int32_t ncols, int32_t ld) {
+  const int32_t steps = S.p->steps_per_round;
+  if (steps == 0) return MQO_OK;
+  if (!use_graph) {
+    enqueue_steps(S, gv, X, Xt, V, ncols, ld, steps);
+    HIP_TRY(hipGetLastError());
+    return MQO_OK;
+  }
+  if (!loop.exec) {
+    HIP_TRY(hipStreamBeginCapture(S.s, hipStreamCaptureModeThreadLocal));
+    enqueue_steps(S, gv, X, Xt, V, ncols, ld, steps);
+    hipError_t e = hipStreamEndCapture(S.s, &loop.graph);
+    if (e != hipSuccess) return fail(MQO_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    HIP_TRY(hipGraphInstantiate(&loop.exec, loop.graph, nullptr, nullptr, 0));
+  }
+  HIP_TRY(hipGraphLaunch(loop.exec, S.s));
+  return MQO_OK;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// one round of one graph on columns [traj0, traj0+ncols); arrays at ld,
+// incumbents at Zb (ldb) / best / value (offset to traj0 already)
+int grid_round(Solve &S, StepLoop &loop, bool use_graph, const GraphView &gv, int32_t r, float *X, float *Xt,
+               float *V, int8_t *Z, int8_t *Zb, int32_t ldb, int32_t *NB, uint32_t *PRIO, int8_t *F, int64_t *value,
+               int64_t *best, int32_t ncols, int32_t ld, uint64_t traj0) {
+  const bool mom = S.p->momentum != 0.0f;
+  if (r > 0) {
+    launch_reset(S.maxcut, Zb, ldb, nullptr, X, mom ? V : nullptr, gv.lo, gv.n, ncols, ld, S.p->seed, traj0,
+                 (uint64_t)r, k_of(S, gv.n), S.p->reset_mode, at<void>(S.ws, S.L.reset), S.s);
+  } else if (mom) {
+    launch_fill_f32(V + gv.lo * ld, gv.n * ld, 0.0f, S.s);
+  }
+  if (S.p->steps_per_round > 0) {
+    hipEvent_t e0;
+    TRY(S.begin_timed(&e0));
+    TRY(run_steps(S, loop, use_graph, gv, X, Xt, mom ? V : nullptr, ncols, ld));
+    TRY(S.end_timed(e0));
+  }
+  launch_round(S.maxcut, X, Z, gv.lo, gv.n, ncols, ld, S.s);
+  if (S.p->local_search == MQO_LS_ONE_FLIP) {
+    int64_t it = 0;
+    TRY(run_local_search(S, gv, Z, NB, PRIO, F, ncols, ld, traj0, r, &it));
+    S.ls_iters += it;
+  }
+  launch_evaluate(S.maxcut, gv, Z, NB, at<long long>(S.ws, S.L.acc), value, nullptr, nullptr, ncols, ld, S.s);
+  launch_accept(Z, Zb, value, best, gv.lo, gv.n, ncols, ld, ldb, r == 0, S.s);
+  HIP_TRY(hipGetLastError());
+  return MQO_OK;
+}
+
+int solve_batched(Solve &S, int32_t *rounds_done) {
+  float *X = at<float>(S.ws, S.L.X), *Xt = at<float>(S.ws, S.L.Xt), *V = at<float>(S.ws, S.L.V);
+  int8_t *Z = at<int8_t>(S.ws, S.L.Z), *Zb = at<int8_t>(S.ws, S.L.Zb), *F = at<int8_t>(S.ws, S.L.F);
+  int32_t *NB = at<int32_t>(S.ws, S.L.NB);
+  uint32_t *PRIO = at<uint32_t>(S.ws, S.L.PRIO);
+  int64_t *value = at<int64_t>(S.ws, S.L.value), *best = at<int64_t>(S.ws, S.L.best);
+  const int32_t B = S.B;
+  if (S.x0)
+    HIP_TRY(hipMemcpyAsync(X, S.x0, S.g->n_total * B * sizeof(float), hipMemcpyDeviceToDevice, S.s));
+  else
+    TRY(init_x(S, X));
+  const bool use_graph = S.G <= 16 && S.p->steps_per_round >= 4;
+  std::vector<StepLoop> loops(S.G);
+  const double t0 = now_s();
+  int32_t r = 0;
+  for (r = 0; r < S.p->rounds; ++r) {
+    if (r > 0 && S.p->time_budget_s > 0.0) {
+      HIP_TRY(hipStreamSynchronize(S.s));
+      if (now_s() - t0 >= S.p->time_budget_s) break;
+    }
+    for (int32_t gi = 0; gi < S.G; ++gi) {
+      const GraphView gv = view_of(S.g, gi);
+      const int64_t t = (int64_t)gi * B;
+      TRY(grid_round(S, loops[gi], use_graph, gv, r, X, Xt, V, Z, Zb, B, NB, PRIO, F, value + t, best + t, B, B,
+                     (uint64_t)t));
+    }
+  }
+  *rounds_done = r;
+  return MQO_OK;
+}
+
+int solve_plain(Solve &S, int32_t *rounds_done) {
+  // One trajectory at a time on contiguous vectors (ld = 1) with the same
+  // kernels; incumbents go straight into column b of Zb ([n][B]).
+  float *X = at<float>(S.ws, S.L.pX), *Xt = at<float>(S.ws, S.L.pXt), *V = at<float>(S.ws, S.L.pV);
+  int8_t *Z = at<int8_t>(S.ws, S.L.Z), *Zb = at<int8_t>(S.ws, S.L.Zb), *F = at<int8_t>(S.ws, S.L.F);
+  int32_t *NB = at<int32_t>(S.ws, S.L.NB);
+  uint32_t *PRIO = at<uint32_t>(S.ws, S.L.PRIO);
+  int64_t *value = at<int64_t>(S.ws, S.L.value), *best = at<int64_t>(S.ws, S.L.best);
+  const int32_t B = S.B;
+  const float *start = S.x0;
+  if (!start) {
+    TRY(init_x(S, at<float>(S.ws, S.L.X)));
+    start = at<float>(S.ws, S.L.X);
+  }
+  const bool use_graph = S.p->steps_per_round >= 4;
+  const double t0 = now_s();
+  int32_t rmax = 0;
+  bool out_of_time = false;
+  for (int32_t gi = 0; gi < S.G && !out_of_time; ++gi) {
+    const GraphView gv = view_of(S.g, gi);
+    StepLoop loop;  // the captured step loop serves every trajectory of the graph
+    for (int32_t b = 0; b < B && !out_of_time; ++b) {
+      const int64_t t = (int64_t)gi * B + b;
+      launch_strided_copy_f32(start, B, b, X, 1, 0, gv.lo, gv.n, S.s);
+      int32_t r = 0;
+      for (r = 0; r < S.p->rounds; ++r) {
+        if (r > 0 && S.p->time_budget_s > 0.0) {
+          HIP_TRY(hipStreamSynchronize(S.s));
+          if (now_s() - t0 >= S.p->time_budget_s) {
+            out_of_time = true;
+            break;
+          }
+        }
+        TRY(grid_round(S, loop, use_graph, gv, r, X, Xt, V, Z, Zb + b, B, NB, PRIO, F, value + t, best + t, 1, 1,
+                       (uint64_t)t));
+      }
+      rmax = std::max(rmax, r);
+    }
+  }
+  *rounds_done = rmax;
+  return MQO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// persistent tile plan + autotuner
+// ---------------------------------------------------------------------------
+int tile_lds_budget() {
+  const int static_lds = 4 * 64 * 4 + 3 * 64 * 8 + 64 * 4 + 2 * 4 + 256;
+  return std::min(res().lds_limit, 160 * 1024) - static_lds;
+}
+
+bool tile_feasible(int64_t n_max, int T, int threads) {
+  return tile_shape_ok(n_max, T, threads) && (int64_t)tile_lds_bytes(n_max, T) <= tile_lds_budget();
+}
+
+TileArgs tile_args(Solve &S, int T, const float *x0) {
+  TileArgs a{};
+  a.row_ptr = S.g->row_ptr;
+  a.col_idx = S.g->col_idx;
+  a.weight = S.g->weight;
+  a.vtx_off = at<int64_t>(S.ws, S.L.voff);
+  a.G = S.G;
+  a.B = S.B;
+  a.T = T;
+  a.log2T = 0;
+  while ((1 << a.log2T) < T) ++a.log2T;
+  a.tiles = (S.B + T - 1) / T;
+  a.n_max = (int32_t)S.n_max;
+  a.steps = S.p->steps_per_round;
+  a.reset_mode = S.p->reset_mode;
+  a.ls = S.p->local_search == MQO_LS_ONE_FLIP;
+  a.alpha = S.p->alpha;
+  a.mu = S.p->momentum;
+  a.param = S.param;
+  a.rho = S.p->rho;
+  a.seed = S.p->seed;
+  a.x0 = x0;
+  a.zbest = at<int8_t>(S.ws, S.L.Zb);
+  a.best = at<int64_t>(S.ws, S.L.best);
+  a.zs = at<int8_t>(S.ws, S.L.tzs);
+  a.nb = at<int32_t>(S.ws, S.L.tnb);
+  a.prio = at<uint32_t>(S.ws, S.L.tprio);
+  a.fl = at<int8_t>(S.ws, S.L.tfl);
+  a.vm = at<float>(S.ws, S.L.tvm);
+  a.ls_iters = at<int32_t>(S.ws, S.L.tls);
+  a.err = at<int32_t>(S.ws, S.L.err);
+  return a;
+}
+
+std::string tile_key(const Solve &S) {
+  char buf[256];
+  const double deg = (double)S.g->nnz_total / (double)S.g->n_total;
+  snprintf(buf, sizeof(buf), "%d|%d|%d|%lld|%d|%d|%d|%d|%d", (int)S.maxcut, S.g->weight != nullptr,
+           S.p->momentum != 0.0f, (long long)S.n_max, (int)std::lround(std::log2(deg + 1.0) * 4), S.B, S.G,
+           S.p->local_search, res().device);
+  return buf;
+}
+
+int tune_tile(Solve &S, const float *x0, int *T_out, int *threads_out) {
+  Resources &R = res();
+  const std::string key = tile_key(S);
+  {
+    std::lock_guard<std::mutex> lk(R.mu);
+    auto it = R.tile_tuning.find(key);
+    if (it != R.tile_tuning.end()) {
+      *T_out = it->second.first;
+      *threads_out = it->second.second;
+      return MQO_OK;
+    }
+  }
+  int Tmax = 1;
+  while (Tmax < S.B && Tmax < 64) Tmax <<= 1;
+  std::vector<std::pair<int, int>> cands;
+  for (int T = 1; T <= Tmax; T <<= 1)
+    for (int th : {256, 512, 1024})
+      if (tile_feasible(S.n_max, T, th)) cands.push_back({T, th});
+  if (cands.empty()) return fail(MQO_ERR_UNSUPPORTED, "graphs too large for the persistent plan");
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  double best_t = 1e30;
+  std::pair<int, int> best_c = cands[0];
+  const bool mc = S.maxcut, w = S.g->weight != nullptr, m = S.p->momentum != 0.0f;
+  for (auto c : cands) {
+    TileArgs a = tile_args(S, c.first, x0);
+    a.r0 = 0;
+    a.r1 = 1;
+    a.steps = std::min(S.p->steps_per_round, 32);
+    float ms = 0.f;
+    hipError_t e = launch_tile_round(mc, w, m, a, c.second, S.s);  // warm-up
+    if (e != hipSuccess) continue;
+    HIP_TRY(hipEventRecord(e0, S.s));
+    for (int rep = 0; rep < 2; ++rep) (void)launch_tile_round(mc, w, m, a, c.second, S.s);
+    HIP_TRY(hipEventRecord(e1, S.s));
+    HIP_TRY(hipEventSynchronize(e1));
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_t) {
+      best_t = ms;
+      best_c = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  {
+    std::lock_guard<std::mutex> lk(R.mu);
+    R.tile_tuning[key] = best_c;
+  }
+  *T_out = best_c.first;
+  *threads_out = best_c.second;
+  return MQO_OK;
+}
+
+int solve_tile(Solve &S, int32_t *rounds_done, int *T_used, int *th_used) {
+  const float *x0 = S.x0;
+  if (!x0) {
+    float *X = at<float>(S.ws, S.L.X);
+    TRY(init_x(S, X));
+    x0 = X;
+  }
+  int T = S.p->tile_cols, th = S.p->tile_threads;
+  if (T == 0 || th == 0) {
+    int Tt = 0, tht = 0;
+    TRY(tune_tile(S, x0, &Tt, &tht));
+    if (T == 0) T = Tt;
+    if (th == 0) th = tht;
+  }
+  if (!tile_feasible(S.n_max, T, th))
+    return fail(MQO_ERR_UNSUPPORTED, "tile_cols=%d, tile_threads=%d do not fit graphs of %lld vertices", T, th,
+                (long long)S.n_max);
+  *T_used = T;
+  *th_used = th;
+  launch_fill_i32(at<int32_t>(S.ws, S.L.err), 1, 0, S.s);
+  TileArgs a = tile_args(S, T, x0);
+  const bool mc = S.maxcut, w = S.g->weight != nullptr, m = S.p->momentum != 0.0f;
+  const int nwg = S.G * a.tiles;
+  std::vector<int32_t> lsi;
+  int32_t r = 0;
+  if (S.p->time_budget_s <= 0.0) {
+    a.r0 = 0;
+    a.r1 = S.p->rounds;
+    hipEvent_t e0;
+    TRY(S.begin_timed(&e0));
+    hipError_t e = launch_tile_round(mc, w, m, a, th, S.s);
+    if (e != hipSuccess) return fail(MQO_ERR_HIP, "tile launch: %s", hipGetErrorString(e));
+    TRY(S.end_timed(e0));
+    r = S.p->rounds;
+    TRY(read_back_i32(a.ls_iters, nwg, lsi, S.s));
+    int64_t mx = 0;
+    for (int32_t x : lsi) mx = std::max<int64_t>(mx, x);
+    S.ls_iters += mx;
+  } else {
+    const double t0 = now_s();
+    for (r = 0; r < S.p->rounds; ++r) {
+      if (r > 0) {
+        HIP_TRY(hipStreamSynchronize(S.s));
+        if (now_s() - t0 >= S.p->time_budget_s) break;
+      }
+      a.r0 = r;
+      a.r1 = r + 1;
+      hipEvent_t e0;
+      TRY(S.begin_timed(&e0));
+      hipError_t e = launch_tile_round(mc, w, m, a, th, S.s);
+      if (e != hipSuccess) return fail(MQO_ERR_HIP, "tile launch: %s", hipGetErrorString(e));
+      TRY(S.end_timed(e0));
+      TRY(read_back_i32(a.ls_iters, nwg, lsi, S.s));
+      int64_t mx = 0;
+      for (int32_t x : lsi) mx = std::max<int64_t>(mx, x);
+      S.ls_iters += mx;
+    }
+  }
+  std::vector<int32_t> err;
+  TRY(read_back_i32(at<int32_t>(S.ws, S.L.err), 1, err, S.s));
+  if (err[0]) return fail(MQO_ERR_INTERNAL, "local search did not terminate");
+  *rounds_done = r;
+  return MQO_OK;
+}
+
+int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_result *r, void *ws, size_t ws_bytes,
+                 void *stream, mqo_objective obj) {
+  TRY(check_graph_args(g, obj == MQO_OBJ_MIS_H));
+  TRY(check_params(p, obj));
+  if (!r || !r->best_x || !r->best_value) return fail(MQO_ERR_INVALID_ARG, "result arrays best_x/best_value required");
+  const Layout L = make_layout(g, p->batch);
+  if (!ws || ws_bytes < L.total) return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", L.total);
+  TRY(ensure_resources());
+  hipStream_t s = res().stream;
+  if (stream) HIP_TRY(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  else HIP_TRY(hipDeviceSynchronize());
+
+  Solve S;
+  S.g = g;
+  S.p = p;
+  S.obj = obj;
+  S.maxcut = obj == MQO_OBJ_MAXCUT_FB;
+  S.param = S.maxcut ? p->lambda : p->gamma;
+  S.B = p->batch;
+  S.G = g->num_graphs;
+  S.n_max = max_graph_rows(g);
+  S.ws = ws;
+  S.L = L;
+  S.s = s;
+  S.x0 = x0;
+
+  int64_t *voff = at<int64_t>(ws, L.voff);
+  HIP_TRY(hipMemcpyAsync(voff, g->vtx_offset, (g->num_graphs + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  TRY(validate_on_device(g, voff, at<int32_t>(ws, L.err), s));
+  launch_gather_rowptr(g->row_ptr, voff, S.G, at<int32_t>(ws, L.rpat), s);
+  std::vector<int32_t> rp;
+  TRY(read_back_i32(at<int32_t>(ws, L.rpat), S.G + 1, rp, s));
+  S.nnz_g.resize(S.G);
+  for (int32_t i = 0; i < S.G; ++i) S.nnz_g[i] = rp[i + 1] - rp[i];
+
+  int plan = p->plan;
+  if (plan == MQO_PLAN_AUTO) {
+    bool fits = false;
+    for (int T = 1; T <= 64 && !fits; T <<= 1)
+      for (int th : {256, 512, 1024}) fits = fits || tile_feasible(S.n_max, T, th);
+    plan = fits ? MQO_PLAN_PERSISTENT : MQO_PLAN_BATCHED;
+  }
+  int32_t rounds_done = 0;
+  int T_used = 0, th_used = 0;
+  if (plan == MQO_PLAN_PERSISTENT)
+    TRY(solve_tile(S, &rounds_done, &T_used, &th_used));
+  else if (plan == MQO_PLAN_BATCHED)
+    TRY(solve_batched(S, &rounds_done));
+  else
+    TRY(solve_plain(S, &rounds_done));
+
+  int64_t *best = at<int64_t>(ws, L.best);
+  int32_t *bestb = at<int32_t>(ws, L.bestb);
+  launch_pick_best(best, S.G, S.B, r->best_value, bestb, s);
+  launch_copy_best_x(at<int8_t>(ws, L.Zb), S.B, voff, S.G, bestb, r->best_x, g->n_total, s);
+  if (r->traj_best_value)
+    HIP_TRY(hipMemcpyAsync(r->traj_best_value, best, (size_t)S.G * S.B * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+  if (r->traj_best_x)
+    HIP_TRY(hipMemcpyAsync(r->traj_best_x, at<int8_t>(ws, L.Zb), (size_t)g->n_total * S.B, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  int64_t nnz_sum = 0;
+  for (int64_t x : S.nnz_g) nnz_sum += x;
+  r->rounds_executed = rounds_done;
+  r->steps_executed = (int64_t)rounds_done * p->steps_per_round;
+  r->edge_updates = nnz_sum * S.B * r->steps_executed;
+  r->plan_used = plan;
+  r->tile_cols_used = T_used;
+  r->tile_threads_used = th_used;
+  r->ls_iterations = S.ls_iters;
+  r->step_kernel_ms = S.timed_ms();
+  r->step_kernel_launches = (int64_t)S.timed.size();
+  return MQO_OK;
+}
+
+// per-graph helper for the asynchronous entry points
+int check_async(const mqo_graph *g, mqo_objective obj, int32_t B) {
+  TRY(check_graph_args(g, obj == MQO_OBJ_MIS_H));
+  if (obj != MQO_OBJ_MIS_H && obj != MQO_OBJ_MAXCUT_FB) return fail(MQO_ERR_INVALID_ARG, "bad objective");
+  if (B < 1) return fail(MQO_ERR_INVALID_ARG, "B must be >= 1");
+  return MQO_OK;
+}
+
+int check_param(mqo_objective obj, float param) {
+  if (obj == MQO_OBJ_MIS_H && !(param > 1.0f && std::isfinite(param)))
+    return fail(MQO_ERR_INVALID_ARG, "gamma must be > 1 (Eq. 3)");
+  if (obj == MQO_OBJ_MAXCUT_FB && !(param > 0.0f && param < 2.0f))
+    return fail(MQO_ERR_INVALID_ARG, "lambda must be in (0, 2) (Thm. 3.6)");
+  return MQO_OK;
+}
+
+size_t partial_count(const mqo_graph *g, int32_t B) {
+  const StepCfg cfg = default_step_cfg(B, B);
+  return (size_t)grid_blocks_x(max_graph_rows(g), cfg) * B;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+void mqo_params_default(mqo_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->struct_size = sizeof(mqo_params);
+  p->batch = 1;
+  p->steps_per_round = 200;
+  p->rounds = 1;
+  p->check_every = 0;
+  p->alpha = 0.01f;
+  p->momentum = 0.0f;
+  p->gamma = 2.0f;
+  p->lambda = 1e-3f;
+  p->rho = 0.05;
+  p->init_sigma = 0.0f;
+  p->init_mode = MQO_INIT_UNIFORM;
+  p->reset_mode = MQO_RESET_ZERO;
+  p->local_search = MQO_LS_ONE_FLIP;
+  p->plan = MQO_PLAN_AUTO;
+  p->seed = 0;
+  p->time_budget_s = 0.0;
+}
+
+size_t mqo_workspace_size(const mqo_graph *g, const mqo_params *p, mqo_objective obj) {
+  if (check_graph_args(g, obj == MQO_OBJ_MIS_H) != MQO_OK || !p || p->batch < 1) return 0;
+  return make_layout(g, p->batch).total;
+}
+
+int mqo_solve_mis(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_result *r, void *ws,
+                  size_t ws_bytes, void *stream) {
+  try {
+    return solve_common(g, p, x0, r, ws, ws_bytes, stream, MQO_OBJ_MIS_H);
+  } catch (...) {
+    return fail(MQO_ERR_INTERNAL, "unexpected exception");
+  }
+}
+
+int mqo_solve_maxcut(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_result *r, void *ws,
+                     size_t ws_bytes, void *stream) {
+  try {
+    return solve_common(g, p, x0, r, ws, ws_bytes, stream, MQO_OBJ_MAXCUT_FB);
+  } catch (...) {
+    return fail(MQO_ERR_INTERNAL, "unexpected exception");
+  }
+}
+
+size_t mqo_objective_workspace_size(const mqo_graph *g, int32_t B) {
+  if (check_graph_args(g, false) != MQO_OK || B < 1) return 0;
+  return align_up(partial_count(g, B) * sizeof(double));
+}
+
+int mqo_objective_grad(const mqo_graph *g, mqo_objective obj, float param, const float *X, int32_t B,
+                       const float *scale, double *f_out, float *grad_out, void *ws, size_t ws_bytes, void *stream) {
+  TRY(check_async(g, obj, B));
+  TRY(check_param(obj, param));
+  if (!X) return fail(MQO_ERR_INVALID_ARG, "X is NULL");
+  if (f_out && (!ws || ws_bytes < mqo_objective_workspace_size(g, B)))
+    return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", mqo_objective_workspace_size(g, B));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool mc = obj == MQO_OBJ_MAXCUT_FB;
+  const StepCfg cfg = default_step_cfg(B, B);
+  for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
+    const GraphView gv = view_of(g, gi);
+    const float *sc = scale ? scale + (int64_t)gi * B : nullptr;
+    double *part = f_out ? reinterpret_cast<double *>(ws) : nullptr;
+    launch_objective_grad(mc, gv, X, sc, grad_out, part, B, B, cfg, param, s);
+    if (f_out) launch_reduce_partials(part, grid_blocks_x(gv.n, cfg), B, f_out + (int64_t)gi * B, false, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return MQO_OK;
+}
+
+size_t mqo_unrolled_workspace_size(const mqo_graph *g, int32_t B, int32_t ckpt_every) {
+  if (check_graph_args(g, false) != MQO_OK || B < 1 || ckpt_every < 1) return 0;
+  const size_t nb = (size_t)g->n_total * B * sizeof(float);
+  return align_up(nb) * (size_t)(ckpt_every + 3) + align_up(partial_count(g, B) * sizeof(double));
+}
+
+int mqo_pga_unrolled_forward(const mqo_graph *g, mqo_objective obj, float param, float alpha, int32_t K,
+                             int32_t ckpt_every, const float *X0, float *ckpt, float *XK, int32_t B, void *ws,
+                             size_t ws_bytes, void *stream) {
+  TRY(check_async(g, obj, B));
+  TRY(check_param(obj, param));
+  if (!(alpha > 0.0f) || !std::isfinite(alpha)) return fail(MQO_ERR_INVALID_ARG, "alpha must be > 0");
+  if (K < 1 || ckpt_every < 1 || K % ckpt_every)
+    return fail(MQO_ERR_INVALID_ARG, "K must be a positive multiple of ckpt_every");
+  if (!X0 || !ckpt || !XK) return fail(MQO_ERR_INVALID_ARG, "X0, ckpt and XK are required");
+  if (!ws || ws_bytes < mqo_unrolled_workspace_size(g, B, ckpt_every))
+    return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", mqo_unrolled_workspace_size(g, B, ckpt_every));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool mc = obj == MQO_OBJ_MAXCUT_FB;
+  const StepCfg cfg = default_step_cfg(B, B);
+  const int64_t nb = g->n_total * B;
+  float *W = reinterpret_cast<float *>(ws);
+  const int32_t nseg = K / ckpt_every;
+  for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
+    const GraphView gv = view_of(g, gi);
+    launch_copy_f32(X0 + gv.lo * B, ckpt + gv.lo * B, gv.n * B, s);
+    for (int32_t j = 0; j < nseg; ++j) {
+      // segment j runs x_{jc} -> x_{(j+1)c}; intermediates alternate between
+      // the segment's target and W so that the last step lands on the target
+      const float *src = ckpt + (int64_t)j * nb;
+      float *target = j == nseg - 1 ? XK : ckpt + (int64_t)(j + 1) * nb;
+      for (int32_t i = 1; i <= ckpt_every; ++i) {
+        float *dst = ((ckpt_every - i) % 2 == 0) ? target : W;
+        launch_pga_step(mc, gv, src, dst, nullptr, B, B, cfg, alpha, 0.0f, param, s);
+        src = dst;
+      }
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return MQO_OK;
+}
+
+int mqo_pga_unrolled_backward(const mqo_graph *g, mqo_objective obj, float param, float alpha, int32_t K,
+                              int32_t ckpt_every, const float *ckpt, const float *dL_dXK, float *dL_dX0,
+                              double *dL_dalpha, int32_t B, void *ws, size_t ws_bytes, void *stream) {
+  TRY(check_async(g, obj, B));
+  TRY(check_param(obj, param));
+  if (!(alpha > 0.0f) || !std::isfinite(alpha)) return fail(MQO_ERR_INVALID_ARG, "alpha must be > 0");
+  if (K < 1 || ckpt_every < 1 || K % ckpt_every)
+    return fail(MQO_ERR_INVALID_ARG, "K must be a positive multiple of ckpt_every");
+  if (!ckpt || !dL_dXK || !dL_dX0 || !dL_dalpha) return fail(MQO_ERR_INVALID_ARG, "NULL array argument");
+  if (!ws || ws_bytes < mqo_unrolled_workspace_size(g, B, ckpt_every))
+    return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", mqo_unrolled_workspace_size(g, B, ckpt_every));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool mc = obj == MQO_OBJ_MAXCUT_FB;
+  const StepCfg cfg = default_step_cfg(B, B);
+  const int64_t nb = g->n_total * B;
+  const size_t slot = align_up((size_t)nb * sizeof(float));
+  char *base = reinterpret_cast<char *>(ws);
+  std::vector<float *> states(ckpt_every);
+  for (int32_t i = 1; i < ckpt_every; ++i) states[i] = reinterpret_cast<float *>(base + slot * (i - 1));
+  float *lamA = reinterpret_cast<float *>(base + slot * (ckpt_every - 1));
+  float *lamB = reinterpret_cast<float *>(base + slot * ckpt_every);
+  float *mu = reinterpret_cast<float *>(base + slot * (ckpt_every + 1));
+  double *part = reinterpret_cast<double *>(base + slot * (ckpt_every + 2));
+  const int32_t nseg = K / ckpt_every;
+  for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
+    const GraphView gv = view_of(g, gi);
+    const int64_t nblk = grid_blocks_x(gv.n, cfg);
+    launch_copy_f32(dL_dXK + gv.lo * B, lamA + gv.lo * B, gv.n * B, s);
+    launch_fill_i64(reinterpret_cast<int64_t *>(dL_dalpha + (int64_t)gi * B), B, 0, s);  // +0.0
+    float *cur = lamA, *nxt = lamB;
+    for (int32_t j = nseg - 1; j >= 0; --j) {
+      states[0] = const_cast<float *>(ckpt + (int64_t)j * nb);
+      for (int32_t i = 1; i < ckpt_every; ++i)
+        launch_pga_step(mc, gv, states[i - 1], states[i], nullptr, B, B, cfg, alpha, 0.0f, param, s);
+      for (int32_t i = ckpt_every - 1; i >= 0; --i) {
+        launch_adjoint_step(mc, gv, states[i], cur, mu, nxt, part, B, B, cfg, alpha, param, s);
+        launch_reduce_partials(part, nblk, B, dL_dalpha + (int64_t)gi * B, true, s);
+        std::swap(cur, nxt);
+      }
+    }
+    launch_copy_f32(cur + gv.lo * B, dL_dX0 + gv.lo * B, gv.n * B, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return MQO_OK;
+}
+
+// ---- building blocks ----
+
+int mqo_init_iterate(const mqo_graph *g, mqo_objective obj, const mqo_params *p, float *X, void *stream) {
+  TRY(check_async(g, obj, p ? p->batch : 0));
+  TRY(check_params(p, obj));
+  if (!X) return fail(MQO_ERR_INVALID_ARG, "X is NULL");
+  TRY(ensure_resources());
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool mc = obj == MQO_OBJ_MAXCUT_FB;
+  const int32_t B = p->batch;
+  for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
+    const GraphView gv = view_of(g, gi);
+    if (p->init_mode == MQO_INIT_UNIFORM)
+      launch_init_uniform(mc, X, gv.lo, gv.n, B, B, p->seed, (uint64_t)gi * B, s);
+    else
+      launch_init_degree(mc, X, g->row_ptr, res().small, gv.lo, gv.n, B, B, p->seed, (uint64_t)gi * B,
+                         p->init_sigma, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return MQO_OK;
+}
+
+int mqo_pga_steps(const mqo_graph *g, mqo_objective obj, const mqo_params *p, float *X, float *V, float *tmp,
+                  int32_t nsteps, void *stream) {
+  TRY(check_async(g, obj, p ? p->batch : 0));
+  TRY(check_params(p, obj));
+  if (!X || !tmp || nsteps < 0) return fail(MQO_ERR_INVALID_ARG, "X and tmp are required, nsteps >= 0");
+  if (p->momentum != 0.0f && !V) return fail(MQO_ERR_INVALID_ARG, "V is required when momentum != 0");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool mc = obj == MQO_OBJ_MAXCUT_FB;
+  const int32_t B = p->batch;
+  const float param = mc ? p->lambda : p->gamma;
+  const StepCfg cfg = default_step_cfg(B, B);
+  for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
+    const GraphView gv = view_of(g, gi);
+    float *a = X, *b = tmp;
+    for (int32_t st = 0; st < nsteps; ++st) {
+      launch_pga_step(mc, gv, a, b, p->momentum != 0.0f ? V : nullptr, B, B, cfg, p->alpha, p->momentum, param, s);
+      std::swap(a, b);
+    }
+    if (a != X) launch_copy_f32(a + gv.lo * B, X + gv.lo * B, gv.n * B, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return MQO_OK;
+}
+
+int mqo_round_evaluate(const mqo_graph *g, mqo_objective obj, const float *X, int32_t B, int8_t *Z, int64_t *value,
+                       int64_t *conflicts, int8_t *fixed, void *ws, size_t ws_bytes, void *stream) {
+  TRY(check_async(g, obj, B));
+  if (!X || !Z || !value) return fail(MQO_ERR_INVALID_ARG, "X, Z and value are required");
+  const Layout L = make_layout(g, B);
+  if (!ws || ws_bytes < L.total) return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", L.total);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool mc = obj == MQO_OBJ_MAXCUT_FB;
+  for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
+    const GraphView gv = view_of(g, gi);
+    const int64_t t = (int64_t)gi * B;
+    launch_round(mc, X, Z, gv.lo, gv.n, B, B, s);
+    launch_evaluate(mc, gv, Z, at<int32_t>(ws, L.NB), at<long long>(ws, L.acc), value + t,
+                    conflicts ? conflicts + t : nullptr, fixed ? fixed + t : nullptr, B, B, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return MQO_OK;
+}
+
+int mqo_local_search(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t seed, int32_t round, int8_t *Z,
+                     int64_t *iterations, void *ws, size_t ws_bytes, void *stream) {
+  TRY(check_async(g, obj, B));
+  if (!Z) return fail(MQO_ERR_INVALID_ARG, "Z is NULL");
+  const Layout L = make_layout(g, B);
+  if (!ws || ws_bytes < L.total) return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", L.total);
+  TRY(ensure_resources());
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool mc = obj == MQO_OBJ_MAXCUT_FB;
+  int64_t total = 0;
+  for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
+    const GraphView gv = view_of(g, gi);
+    int64_t it = 0;
+    TRY(ls_core(mc, gv, g->nnz_total, seed, round, Z, at<int32_t>(ws, L.NB), at<uint32_t>(ws, L.PRIO),
+                at<int8_t>(ws, L.F), at<int32_t>(ws, L.act), at<long long>(ws, L.acc), at<int64_t>(ws, L.value), B, B,
+                (uint64_t)gi * B, s, &it));
+    total = std::max(total, it);
+  }
+  if (iterations) *iterations = total;
+  return MQO_OK;
+}
+
+int mqo_reset(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t seed, int32_t round, double rho,
+              int32_t mode, const int8_t *Zbest, const uint32_t *keys, float *X, void *ws, size_t ws_bytes,
+              void *stream) {
+  TRY(check_async(g, obj, B));
+  if (!(rho >= 0.0 && rho < 1.0)) return fail(MQO_ERR_INVALID_ARG, "rho must be in [0, 1)");
+  if (mode != MQO_RESET_ZERO && mode != MQO_RESET_FLIP) return fail(MQO_ERR_INVALID_ARG, "bad reset mode");
+  if (!Zbest || !X) return fail(MQO_ERR_INVALID_ARG, "Zbest and X are required");
+  const Layout L = make_layout(g, B);
+  if (!ws || ws_bytes < L.total) return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", L.total);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool mc = obj == MQO_OBJ_MAXCUT_FB;
+  for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
+    const GraphView gv = view_of(g, gi);
+    const int32_t k = (int32_t)std::floor(rho * (double)gv.n);
+    launch_reset(mc, Zbest, B, keys, X, nullptr, gv.lo, gv.n, B, B, seed, (uint64_t)gi * B, (uint64_t)round, k, mode,
+                 at<void>(ws, L.reset), s);
+  }
+  HIP_TRY(hipGetLastError());
+  return MQO_OK;
+}
+
+// ---- validation and misc ----
+
+int mqo_validate_graph_host(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                            const int32_t *weight) {
+  if (n < 1 || n >= (int64_t)1 << 31) return fail(MQO_ERR_INVALID_GRAPH, "n out of range");
+  if (nnz < 0 || nnz >= (int64_t)1 << 31) return fail(MQO_ERR_INVALID_GRAPH, "nnz out of range");
+  if (!row_ptr || (nnz > 0 && !col_idx)) return fail(MQO_ERR_INVALID_ARG, "NULL array");
+  if (row_ptr[0] != 0 || row_ptr[n] != nnz) return fail(MQO_ERR_INVALID_GRAPH, "row_ptr must run from 0 to nnz");
+  for (int64_t v = 0; v < n; ++v)
+    if (row_ptr[v] > row_ptr[v + 1]) return fail(MQO_ERR_INVALID_GRAPH, "row_ptr not monotone at %lld", (long long)v);
+  for (int64_t v = 0; v < n; ++v) {
+    for (int32_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) {
+      const int64_t c = col_idx[j];
+      if (c < 0 || c >= n) return fail(MQO_ERR_INVALID_GRAPH, "column out of range in row %lld", (long long)v);
+      if (c == v) return fail(MQO_ERR_INVALID_GRAPH, "self loop at %lld", (long long)v);
+      if (j > row_ptr[v] && col_idx[j - 1] >= c)
+        return fail(MQO_ERR_INVALID_GRAPH, "row %lld not strictly ascending", (long long)v);
+    }
+  }
+  for (int64_t v = 0; v < n; ++v) {
+    for (int32_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) {
+      const int64_t c = col_idx[j];
+      const int32_t *b = col_idx + row_ptr[c], *e = col_idx + row_ptr[c + 1];
+      const int32_t *f = std::lower_bound(b, e, (int32_t)v);
+      if (f == e || *f != v) return fail(MQO_ERR_INVALID_GRAPH, "edge (%lld,%lld) has no reverse", (long long)v, (long long)c);
+      if (weight && weight[f - col_idx] != weight[j])
+        return fail(MQO_ERR_INVALID_GRAPH, "weight of (%lld,%lld) not symmetric", (long long)v, (long long)c);
+    }
+  }
+  return MQO_OK;
+}
+
+int mqo_validate_graph(const mqo_graph *g, void *stream) {
+  TRY(check_graph_args(g, false));
+  TRY(ensure_resources());
+  hipStream_t s = res().stream;
+  if (stream) HIP_TRY(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  void *buf = nullptr;
+  const size_t bytes = align_up((g->num_graphs + 1) * sizeof(int64_t)) + 256;
+  HIP_TRY(hipMalloc(&buf, bytes));
+  int64_t *voff = reinterpret_cast<int64_t *>(buf);
+  int32_t *err = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(buf) + bytes - 256);
+  int st = MQO_OK;
+  hipError_t e = hipMemcpyAsync(voff, g->vtx_offset, (g->num_graphs + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess)
+    st = fail(MQO_ERR_HIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
+  else
+    st = validate_on_device(g, voff, err, s);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  return st;
+}
+
+const char *mqo_status_string(int status) {
+  switch (status) {
+    case MQO_OK:
+      return "ok";
+    case MQO_ERR_INVALID_ARG:
+      return "invalid argument";
+    case MQO_ERR_INVALID_GRAPH:
+      return "invalid graph";
+    case MQO_ERR_WORKSPACE:
+      return "workspace too small";
+    case MQO_ERR_HIP:
+      return "HIP runtime error";
+    case MQO_ERR_UNSUPPORTED:
+      return "unsupported";
+    case MQO_ERR_INTERNAL:
+      return "internal error";
+    default:
+      return "unknown status";
+  }
+}
+
+const char *mqo_last_error(void) { return g_last_error.c_str(); }
+
+int mqo_version(void) { return MQO_VERSION; }
+
+void mqo_clear_caches(void) {
+  Resources &r = res();
+  std::lock_guard<std::mutex> lk(r.mu);
+  r.tile_tuning.clear();
+}
+
+
+}  // extern "C"

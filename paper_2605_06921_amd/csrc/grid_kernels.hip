@@ -1,0 +1,1035 @@
+// Grid-wide kernels of libmqo: one graph per launch, rows of the graph x
+// columns (trajectories) of the batch.  Used by the batched and plain plans,
+// by the building-block entry points and by differentiation.
+//
+// Element (v, c) of an [n][ld] array lives at v * ld + c with v the GLOBAL
+// row; random draws use the local index v - lo and the trajectory id
+// traj0 + c.
+#include "common.h"
+#include "kernels.h"
+
+namespace mqo {
+
+static inline int lanes_log2_for(int cols) {
+  int w = 1, l = 0;
+  while (w < cols && w < 64) {
+    w <<= 1;
+    ++l;
+  }
+  return l;
+}
+
+static inline dim3 grid_rows(int64_t nrows, int ncols, int lanes_log2, int vec, int threads) {
+  const int lanes = 1 << lanes_log2;
+  const int64_t rpb = threads >> lanes_log2;
+  const int64_t gx = (nrows + rpb - 1) / rpb;
+  const int gy = (ncols + lanes * vec - 1) / (lanes * vec);
+  return dim3((unsigned)(gx > 0 ? gx : 1), (unsigned)(gy > 0 ? gy : 1), 1);
+}
+
+// ---------------------------------------------------------------------------
+// initialisation
+// ---------------------------------------------------------------------------
+template <bool MAXCUT>
+__global__ __launch_bounds__(256) void k_init_uniform(float *__restrict__ X, int64_t lo, int64_t n, int32_t ncols,
+                                                      int32_t ld, uint64_t seed, uint64_t traj0) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nvb = (n + 7) >> 3;
+  if (idx >= nvb * ncols) return;
+  const int32_t c = (int32_t)(idx % ncols);
+  const int64_t vb = idx / ncols;
+  uint32_t r[8];
+  philox_block8(r, seed, PURPOSE_INIT, traj0 + c, 0, (uint64_t)vb);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int64_t v = vb * 8 + i;
+    if (v < n) {
+      const float u = unit_f32(r[i]);
+      float x;
+      if (MAXCUT) {
+        const float t = 2.0f * u;
+        x = t - 1.0f;
+      } else {
+        x = u;
+      }
+      X[(lo + v) * ld + c] = x;
+    }
+  }
+}
+
+template <bool MAXCUT>
+__global__ __launch_bounds__(256) void k_init_degree(float *__restrict__ X, const int32_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ dmax_p, int64_t lo, int64_t n,
+                                                     int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0,
+                                                     float sigma) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * ncols) return;
+  const int32_t c = (int32_t)(idx % ncols);
+  const int64_t v = idx / ncols;
+  const int32_t dmax = *dmax_p;
+  const float d = (float)(row_ptr[lo + v + 1] - row_ptr[lo + v]);
+  float base = dmax == 0 ? 1.0f : 1.0f - d / (float)dmax;
+  if (MAXCUT) base = 2.0f * base - 1.0f;
+  uint64_t w[4] = {(uint64_t)v >> 2, traj0 + c, 0, 0};
+  philox4x64_10(w, seed, PURPOSE_NOISE);
+  const uint64_t word = w[v & 3];
+  const float u1 = ((float)((uint32_t)word >> 8) + 1.0f) * (1.0f / 16777216.0f);
+  const float u2 = (float)((uint32_t)(word >> 32) >> 8) * (1.0f / 16777216.0f);
+  const float z = sqrtf(-2.0f * logf(u1)) * cosf(6.283185307179586f * u2);
+  X[(lo + v) * ld + c] = clip_box<MAXCUT>(base + sigma * z);
+}
+
+__global__ void k_degree_max(const int32_t *__restrict__ row_ptr, int64_t lo, int64_t n, int32_t *out) {
+  int32_t m = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    m = max(m, row_ptr[lo + v + 1] - row_ptr[lo + v]);
+  atomicMax(out, m);
+}
+
+// ---------------------------------------------------------------------------
+// fused PGA step: S = A X (CSR order), g, momentum, Pi.  X and Xn differ.
+// ---------------------------------------------------------------------------
+template <int VEC>
+struct VecT;
+template <>
+struct VecT<1> {
+  using T = float;
+};
+template <>
+struct VecT<2> {
+  using T = float2;
+};
+template <>
+struct VecT<4> {
+  using T = float4;
+};
+
+template <int VEC>
+__device__ __forceinline__ void load_vec(const float *p, float (&o)[VEC]) {
+  if constexpr (VEC == 1) {
+    o[0] = *p;
+  } else if constexpr (VEC == 2) {
+    const float2 t = *reinterpret_cast<const float2 *>(p);
+    o[0] = t.x;
+    o[1] = t.y;
+  } else {
+    const float4 t = *reinterpret_cast<const float4 *>(p);
+    o[0] = t.x;
+    o[1] = t.y;
+    o[2] = t.z;
+    o[3] = t.w;
+  }
+}
+
+template <int VEC>
+__device__ __forceinline__ void store_vec(float *p, const float (&o)[VEC]) {
+  if constexpr (VEC == 1) {
+    *p = o[0];
+  } else if constexpr (VEC == 2) {
+    *reinterpret_cast<float2 *>(p) = make_float2(o[0], o[1]);
+  } else {
+    *reinterpret_cast<float4 *>(p) = make_float4(o[0], o[1], o[2], o[3]);
+  }
+}
+
+// acc[i] = sum over the row's neighbours, ascending CSR order, one rounding per add
+template <int VEC, bool WEIGHTED>
+__device__ __forceinline__ void row_gather(const GraphView &g, const float *__restrict__ X, int64_t v, int32_t col,
+                                           int32_t ld, float (&acc)[VEC]) {
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
+  const int32_t beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+#pragma unroll 4
+  for (int32_t j = beg; j < end; ++j) {
+    const int64_t u = g.col_idx[j];
+    float x[VEC];
+    load_vec<VEC>(X + u * ld + col, x);
+    if (WEIGHTED) {
+      const float w = (float)g.weight[j];
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) {
+        const float p = w * x[i];
+        acc[i] = acc[i] + p;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + x[i];
+    }
+  }
+}
+
+template <int VEC, bool MAXCUT, bool WEIGHTED, bool MOMENTUM>
+__global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__restrict__ X, float *__restrict__ Xn,
+                                                  float *__restrict__ V, int32_t ncols, int32_t ld,
+                                                  int32_t lanes_log2, float alpha, float mu, float param) {
+  const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2);
+  if (!m.active) return;
+  const int64_t v = g.lo + m.row;
+  float acc[VEC];
+  row_gather<VEC, WEIGHTED>(g, X, v, m.col, ld, acc);
+  float x[VEC], vv[VEC];
+  load_vec<VEC>(X + v * ld + m.col, x);
+  if (MOMENTUM) load_vec<VEC>(V + v * ld + m.col, vv);
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) {
+    const float gr = grad_from_sum<MAXCUT>(acc[i], param);
+    float d = gr;
+    if (MOMENTUM) {
+      const float t = mu * vv[i];
+      vv[i] = t + gr;
+      d = vv[i];
+    }
+    const float s = alpha * d;
+    const float y = x[i] + s;
+    x[i] = clip_box<MAXCUT>(y);
+  }
+  store_vec<VEC>(Xn + v * ld + m.col, x);
+  if (MOMENTUM) store_vec<VEC>(V + v * ld + m.col, vv);
+}
+
+__global__ void k_copy_f32(const float *__restrict__ a, float *__restrict__ b, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+__global__ void k_strided_copy_f32(const float *__restrict__ src, int32_t lds, int32_t cs, float *__restrict__ dst,
+                                   int32_t ldd, int32_t cd, int64_t lo, int64_t n) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) dst[(lo + v) * ldd + cd] = src[(lo + v) * lds + cs];
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t count, int32_t value) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+__global__ void k_fill_i64(int64_t *p, int64_t count, int64_t value) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+__global__ void k_fill_f32(float *p, int64_t count, float value) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+// ---------------------------------------------------------------------------
+// rounding and exact evaluation
+// ---------------------------------------------------------------------------
+template <bool MAXCUT>
+__global__ __launch_bounds__(256) void k_round(const float *__restrict__ X, int8_t *__restrict__ Z, int64_t lo,
+                                               int64_t n, int32_t ncols, int32_t ld) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * ncols) return;
+  const int64_t v = lo + idx / ncols;
+  const int32_t c = (int32_t)(idx % ncols);
+  Z[v * ld + c] = round_x<MAXCUT>(X[v * ld + c]);
+}
+
+// NB = A Z (int32) and per-column accumulators acc[3][ncols] (int64):
+// MIS  : acc0 = |I|, acc1 = sum z m = 2 * edges inside I, acc2 = #{v: z=0, m=0}
+// MaxCut: acc0 = sum_v (W_v - s_v t_v) = 4 Cut(S)   (W_v = sum of row weights)
+template <bool MAXCUT, bool WEIGHTED>
+__global__ __launch_bounds__(256) void k_nbr_eval(GraphView g, const int8_t *__restrict__ Z, int32_t *__restrict__ NB,
+                                                  unsigned long long *__restrict__ acc, int32_t ncols, int32_t ld,
+                                                  int32_t lanes_log2) {
+  __shared__ unsigned long long sacc[3][64];
+  const int lanes = 1 << lanes_log2;
+  if (threadIdx.x < 3 * 64) sacc[threadIdx.x / 64][threadIdx.x % 64] = 0ull;
+  __syncthreads();
+  const RowMap m = map_rows<1>(g.n, ncols, lanes_log2);
+  if (m.active) {
+    const int64_t v = g.lo + m.row;
+    const int32_t beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+    int32_t s = 0, wsum = 0;
+    for (int32_t j = beg; j < end; ++j) {
+      const int64_t u = g.col_idx[j];
+      const int32_t zu = Z[u * ld + m.col];
+      if (WEIGHTED) {
+        const int32_t w = g.weight[j];
+        s += w * zu;
+        wsum += w;
+      } else {
+        s += zu;
+      }
+    }
+    if (!WEIGHTED) wsum = end - beg;
+    if (NB) NB[v * ld + m.col] = s;
+    const int32_t zv = Z[v * ld + m.col];
+    const int lane = threadIdx.x & (lanes - 1);
+    if (MAXCUT) {
+      const long long a0 = (long long)wsum - (long long)zv * s;
+      if (a0) atomicAdd(&sacc[0][lane], (unsigned long long)a0);
+    } else {
+      if (zv) {
+        atomicAdd(&sacc[0][lane], 1ull);
+        if (s) atomicAdd(&sacc[1][lane], (unsigned long long)s);
+      } else if (s == 0) {
+        atomicAdd(&sacc[2][lane], 1ull);
+      }
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < lanes) {
+    const int32_t c = blockIdx.y * lanes + threadIdx.x;
+    if (c < ncols) {
+      for (int k = 0; k < (MAXCUT ? 1 : 3); ++k)
+        if (sacc[k][threadIdx.x]) atomicAdd(&acc[k * ncols + c], sacc[k][threadIdx.x]);
+    }
+  }
+}
+
+template <bool MAXCUT>
+__global__ void k_value_finalize(const long long *__restrict__ acc, int32_t ncols, int64_t *__restrict__ value,
+                                 int64_t *__restrict__ conflicts, int8_t *__restrict__ fixed) {
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  if (MAXCUT) {
+    value[c] = acc[c] / 4;
+  } else {
+    const long long size = acc[c], conf = acc[ncols + c] / 2, freev = acc[2 * ncols + c];
+    value[c] = conf == 0 ? size : -1;
+    if (conflicts) conflicts[c] = conf;
+    if (fixed) fixed[c] = (conf == 0 && freev == 0) ? 1 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1-flip local search, parallel rule
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ls_prio(uint32_t *__restrict__ PRIO, int64_t lo, int64_t n, int32_t ncols,
+                                                 int32_t ld, uint64_t seed, uint64_t traj0, uint64_t round) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nvb = (n + 7) >> 3;
+  if (idx >= nvb * ncols) return;
+  const int32_t c = (int32_t)(idx % ncols);
+  const int64_t vb = idx / ncols;
+  uint32_t r[8];
+  philox_block8(r, seed, PURPOSE_LS, traj0 + c, round, (uint64_t)vb);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int64_t v = vb * 8 + i;
+    if (v < n) PRIO[(lo + v) * ld + c] = r[i];
+  }
+}
+
+// F[v] = v in P and its key beats every neighbour in P.  active[0] is set
+// when P is non-empty.  When prev_active is given and *prev_active == 0
+// the search has already stopped and the kernel does nothing.
+template <bool MAXCUT>
+__global__ __launch_bounds__(256) void k_ls_select(GraphView g, const int8_t *__restrict__ Z,
+                                                   const int32_t *__restrict__ NB, const uint32_t *__restrict__ PRIO,
+                                                   int8_t *__restrict__ F, int32_t *active,
+                                                   const int32_t *prev_active, int32_t ncols, int32_t ld,
+                                                   int32_t lanes_log2) {
+  if (prev_active && *prev_active == 0) return;
+  const RowMap m = map_rows<1>(g.n, ncols, lanes_log2);
+  if (!m.active) return;
+  const int64_t v = g.lo + m.row;
+  const int64_t e = v * ld + m.col;
+  int32_t k1;
+  const bool p = ls_candidate_t<MAXCUT>(Z[e], NB[e], k1);
+  int8_t f = 0;
+  if (p) {
+    *active = 1;
+    const uint32_t pv = PRIO[e];
+    f = 1;
+    const int32_t beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+    for (int32_t j = beg; j < end; ++j) {
+      const int64_t u = g.col_idx[j];
+      const int64_t eu = u * ld + m.col;
+      int32_t k1u;
+      if (ls_candidate_t<MAXCUT>(Z[eu], NB[eu], k1u) && key_beats(k1u, PRIO[eu], u, k1, pv, v)) {
+        f = 0;
+        break;
+      }
+    }
+  }
+  F[e] = f;
+}
+
+template <bool MAXCUT, bool WEIGHTED>
+__global__ __launch_bounds__(256) void k_ls_apply(GraphView g, const int8_t *__restrict__ F, int8_t *__restrict__ Z,
+                                                  int32_t *__restrict__ NB, const int32_t *active, int32_t ncols,
+                                                  int32_t ld, int32_t lanes_log2) {
+  if (*active == 0) return;
+  const RowMap m = map_rows<1>(g.n, ncols, lanes_log2);
+  if (!m.active) return;
+  const int64_t v = g.lo + m.row;
+  const int64_t e = v * ld + m.col;
+  if (!F[e]) return;
+  const int32_t z = Z[e];
+  const int32_t zn = MAXCUT ? -z : 1 - z;
+  Z[e] = (int8_t)zn;
+  const int32_t d = zn - z;
+  const int32_t beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+  for (int32_t j = beg; j < end; ++j) {
+    const int64_t u = g.col_idx[j];
+    atomicAdd(&NB[u * ld + m.col], WEIGHTED ? d * g.weight[j] : d);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// acceptance: strict improvement, round 0 always (Sec. 4)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_accept_copy(const int8_t *__restrict__ Z, int8_t *__restrict__ Zb,
+                                                     const int64_t *__restrict__ value,
+                                                     const int64_t *__restrict__ best, int64_t lo, int64_t n,
+                                                     int32_t ncols, int32_t ld, int32_t ldb, int32_t first) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * ncols) return;
+  const int32_t c = (int32_t)(idx % ncols);
+  const int64_t v = lo + idx / ncols;
+  if (first || value[c] > best[c]) Zb[v * ldb + c] = Z[v * ld + c];
+}
+
+__global__ void k_accept_best(const int64_t *__restrict__ value, int64_t *__restrict__ best, int32_t ncols,
+                              int32_t first) {
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  if (first || value[c] > best[c]) best[c] = value[c];
+}
+
+// ---------------------------------------------------------------------------
+// mutation reset: k smallest (key, v) per column by a 4 x 8-bit radix select
+// ---------------------------------------------------------------------------
+struct SelState {
+  uint32_t prefix, krem, cnteq, tie;
+};
+
+__global__ void k_reset_init(SelState *st, uint32_t *hist, int32_t ncols, uint32_t k, uint32_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ncols) st[i] = SelState{0u, k, 0u, n};
+  if (i < (int64_t)ncols * 256) hist[i] = 0u;
+}
+
+__device__ __forceinline__ uint32_t reset_key(const uint32_t *keys, int64_t lo, int64_t v, int32_t c, int32_t ld,
+                                              uint64_t seed, uint64_t traj, uint64_t round) {
+  if (keys) return keys[(lo + v) * ld + c];
+  return philox_vertex(seed, PURPOSE_RESET, traj, round, (uint64_t)v);
+}
+
+__global__ __launch_bounds__(256) void k_reset_hist(const SelState *__restrict__ st, uint32_t *__restrict__ hist,
+                                                    const uint32_t *__restrict__ keys, int64_t lo, int64_t n,
+                                                    int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0,
+                                                    uint64_t round, int32_t pass) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nvb = (n + 7) >> 3;
+  if (idx >= nvb * ncols) return;
+  const int32_t c = (int32_t)(idx % ncols);
+  const int64_t vb = idx / ncols;
+  uint32_t r[8];
+  if (!keys) philox_block8(r, seed, PURPOSE_RESET, traj0 + c, round, (uint64_t)vb);
+  const uint32_t prefix = st[c].prefix;
+  const int hs = 32 - 8 * pass, ds = 24 - 8 * pass;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int64_t v = vb * 8 + i;
+    if (v >= n) break;
+    const uint32_t key = keys ? keys[(lo + v) * ld + c] : r[i];
+    if (pass == 0 || (key >> hs) == prefix) atomicAdd(&hist[c * 256 + ((key >> ds) & 255u)], 1u);
+  }
+}
+
+__global__ void k_reset_digit(SelState *st, uint32_t *hist, int32_t ncols) {
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  SelState s = st[c];
+  uint32_t cum = 0, d = 0, h = 0;
+  for (d = 0; d < 256; ++d) {
+    h = hist[c * 256 + d];
+    if (cum + h >= s.krem) break;
+    cum += h;
+  }
+  if (d > 255) d = 255;  // unreachable when krem <= count
+  s.prefix = (s.prefix << 8) | d;
+  s.krem -= cum;
+  s.cnteq = h;
+  st[c] = s;
+  for (int i = 0; i < 256; ++i) hist[c * 256 + i] = 0u;
+}
+
+// Columns whose threshold key is shared by more vertices than remain to be
+// taken keep the lowest indices: tie = largest v taken among equal keys.
+__global__ __launch_bounds__(256) void k_reset_ties(SelState *st, const uint32_t *__restrict__ keys, int64_t lo,
+                                                    int64_t n, int32_t ld, uint64_t seed, uint64_t traj0,
+                                                    uint64_t round) {
+  const int32_t c = blockIdx.x;
+  __shared__ uint32_t s_cnt[256];
+  __shared__ uint32_t s_base;
+  __shared__ int32_t s_done;
+  SelState s = st[c];
+  if (s.cnteq == s.krem) return;  // uniform over the block
+  if (threadIdx.x == 0) {
+    s_base = 0;
+    s_done = 0;
+  }
+  __syncthreads();
+  for (int64_t v0 = 0; v0 < n; v0 += blockDim.x) {
+    const int64_t v = v0 + threadIdx.x;
+    uint32_t eq = 0;
+    if (v < n) eq = reset_key(keys, lo, v, c, ld, seed, traj0 + c, round) == s.prefix ? 1u : 0u;
+    s_cnt[threadIdx.x] = eq;
+    __syncthreads();
+    // inclusive scan (Hillis-Steele)
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+      const uint32_t t = threadIdx.x >= (unsigned)off ? s_cnt[threadIdx.x - off] : 0u;
+      __syncthreads();
+      s_cnt[threadIdx.x] += t;
+      __syncthreads();
+    }
+    const uint32_t incl = s_base + s_cnt[threadIdx.x];
+    if (eq && incl == s.krem) {
+      st[c].tie = (uint32_t)v;
+      s_done = 1;
+    }
+    __syncthreads();
+    if (s_done) break;
+    if (threadIdx.x == blockDim.x - 1) s_base = incl;
+    __syncthreads();
+  }
+}
+
+template <bool MAXCUT>
+__global__ __launch_bounds__(256) void k_reset_apply(const SelState *__restrict__ st, const uint32_t *__restrict__ keys,
+                                                     const int8_t *__restrict__ Zb, float *__restrict__ X,
+                                                     float *__restrict__ V, int64_t lo, int64_t n, int32_t ncols,
+                                                     int32_t ld, int32_t ldb, uint64_t seed, uint64_t traj0,
+                                                     uint64_t round, int32_t k, int32_t mode) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nvb = (n + 7) >> 3;
+  if (idx >= nvb * ncols) return;
+  const int32_t c = (int32_t)(idx % ncols);
+  const int64_t vb = idx / ncols;
+  uint32_t r[8];
+  if (k > 0 && !keys) philox_block8(r, seed, PURPOSE_RESET, traj0 + c, round, (uint64_t)vb);
+  SelState s = k > 0 ? st[c] : SelState{0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int64_t v = vb * 8 + i;
+    if (v >= n) break;
+    const float base = (float)Zb[(lo + v) * ldb + c];
+    float x = base;
+    if (k > 0) {
+      const uint32_t key = keys ? keys[(lo + v) * ld + c] : r[i];
+      const bool sel = key < s.prefix || (key == s.prefix && (uint32_t)v <= s.tie);
+      if (sel) x = mode == 0 ? 0.0f : (MAXCUT ? -base : 1.0f - base);
+    }
+    X[(lo + v) * ld + c] = x;
+    if (V) V[(lo + v) * ld + c] = 0.0f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// answer per graph: best incumbent, ties to the lowest trajectory
+// ---------------------------------------------------------------------------
+__global__ void k_pick_best(const int64_t *__restrict__ best, int32_t G, int32_t B, int64_t *__restrict__ best_value,
+                            int32_t *__restrict__ best_b) {
+  const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  int64_t bv = best[(int64_t)g * B];
+  int32_t bb = 0;
+  for (int32_t b = 1; b < B; ++b) {
+    const int64_t x = best[(int64_t)g * B + b];
+    if (x > bv) {
+      bv = x;
+      bb = b;
+    }
+  }
+  best_value[g] = bv;
+  best_b[g] = bb;
+}
+
+__global__ void k_copy_best_x(const int8_t *__restrict__ Zb, int32_t B, const int64_t *__restrict__ voff, int32_t G,
+                              const int32_t *__restrict__ best_b, int8_t *__restrict__ out, int64_t n_total) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n_total) return;
+  int32_t lo = 0, hi = G;  // find g with voff[g] <= v < voff[g+1]
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (voff[mid] <= v)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  out[v] = Zb[v * B + best_b[lo]];
+}
+
+__global__ void k_gather_rowptr(const int32_t *__restrict__ row_ptr, const int64_t *__restrict__ voff, int32_t G,
+                                int32_t *__restrict__ out) {
+  const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g <= G) out[g] = row_ptr[voff[g]];
+}
+
+// ---------------------------------------------------------------------------
+// graph validation (two phases: row_ptr first, then columns)
+// ---------------------------------------------------------------------------
+__global__ void k_validate_rows(const int32_t *__restrict__ row_ptr, int64_t n, int64_t nnz, int32_t *err) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v == 0 && (row_ptr[0] != 0 || (int64_t)row_ptr[n] != nnz)) atomicOr(err, 1);
+  if (v < n) {
+    const int32_t a = row_ptr[v], b = row_ptr[v + 1];
+    if (a > b || a < 0 || (int64_t)b > nnz) atomicOr(err, 1);
+  }
+}
+
+__global__ void k_validate_cols(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+                                const int32_t *__restrict__ weight, const int64_t *__restrict__ voff, int32_t G,
+                                int64_t n, int32_t *err) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int32_t glo = 0, ghi = G;
+  while (ghi - glo > 1) {
+    const int32_t mid = (glo + ghi) >> 1;
+    if (voff[mid] <= v)
+      glo = mid;
+    else
+      ghi = mid;
+  }
+  const int64_t lo = voff[glo], hi = voff[glo + 1];
+  const int32_t beg = row_ptr[v], end = row_ptr[v + 1];
+  int64_t prev = -1;
+  for (int32_t j = beg; j < end; ++j) {
+    const int64_t c = col_idx[j];
+    if (c < lo || c >= hi) {
+      atomicOr(err, 2);  // out of the graph's range
+      return;
+    }
+    if (c == v) atomicOr(err, 4);     // self loop
+    if (c <= prev) atomicOr(err, 8);  // unsorted or duplicate
+    prev = c;
+    // symmetry: v must appear in row c (binary search; rows are checked sorted)
+    int32_t a = row_ptr[c], b = row_ptr[c + 1] - 1;
+    bool found = false;
+    while (a <= b) {
+      const int32_t mid = (a + b) >> 1;
+      const int64_t x = col_idx[mid];
+      if (x == v) {
+        found = true;
+        if (weight && weight[mid] != weight[j]) atomicOr(err, 32);
+        break;
+      }
+      if (x < v)
+        a = mid + 1;
+      else
+        b = mid - 1;
+    }
+    if (!found) atomicOr(err, 16);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// differentiation
+// ---------------------------------------------------------------------------
+// Deterministic per-block column partial sums: vals[threadIdx] summed over
+// the block's rows in fixed order into part[blockIdx.x][col].
+template <int VEC>
+__device__ __forceinline__ void block_column_partials(const double (&val)[VEC], bool active, int32_t col,
+                                                      int32_t ncols, int32_t lanes_log2, double *part) {
+  __shared__ double s[256 * 4];
+  const int lanes = 1 << lanes_log2;
+  const int rpb = blockDim.x >> lanes_log2;
+  const int r = threadIdx.x >> lanes_log2, l = threadIdx.x & (lanes - 1);
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) s[(r * lanes + l) * VEC + i] = active ? val[i] : 0.0;
+  __syncthreads();
+  if (r == 0 && col < ncols) {
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      double t = 0.0;
+      for (int rr = 0; rr < rpb; ++rr) t += s[(rr * lanes + l) * VEC + i];
+      part[(int64_t)blockIdx.x * ncols + col + i] = t;
+    }
+  }
+}
+
+template <int VEC, bool MAXCUT, bool WEIGHTED>
+__global__ __launch_bounds__(256) void k_objective_grad(GraphView g, const float *__restrict__ X,
+                                                        const float *__restrict__ scale, float *__restrict__ grad,
+                                                        double *__restrict__ part, int32_t ncols, int32_t ld,
+                                                        int32_t lanes_log2, float param) {
+  const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2);
+  double fv[VEC];
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) fv[i] = 0.0;
+  if (m.active) {
+    const int64_t v = g.lo + m.row;
+    float acc[VEC];
+    row_gather<VEC, WEIGHTED>(g, X, v, m.col, ld, acc);
+    float x[VEC];
+    load_vec<VEC>(X + v * ld + m.col, x);
+    const double c = MAXCUT ? -(double)param : 1.0;
+    const double eta = MAXCUT ? -2.0 : -(double)param;
+    float gr[VEC];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      const float gg = grad_from_sum<MAXCUT>(acc[i], param);
+      gr[i] = scale ? scale[m.col + i] * gg : gg;
+      fv[i] = (double)x[i] * (c + 0.5 * eta * (double)acc[i]);
+    }
+    if (grad) store_vec<VEC>(grad + v * ld + m.col, gr);
+  }
+  if (part) block_column_partials<VEC>(fv, m.active, m.col, ncols, lanes_log2, part);
+}
+
+// out[c] (+)= sum over nblk partials, fixed tree order (one block per column)
+__global__ __launch_bounds__(256) void k_reduce_partials(const double *__restrict__ part, int64_t nblk, int32_t ncols,
+                                                         double *__restrict__ out, int32_t accumulate) {
+  __shared__ double s[256];
+  const int32_t c = blockIdx.x;
+  double t = 0.0;
+  for (int64_t b = threadIdx.x; b < nblk; b += blockDim.x) t += part[b * ncols + c];
+  s[threadIdx.x] = t;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = accumulate ? out[c] + s[0] : s[0];
+}
+
+// adjoint, part 1: recompute g(x_k), the clip mask, mu = mask * lam_next,
+// and per-block partials of <mu, g> for dL/dalpha
+template <int VEC, bool MAXCUT, bool WEIGHTED>
+__global__ __launch_bounds__(256) void k_adj_mu(GraphView g, const float *__restrict__ Xk,
+                                                const float *__restrict__ lam_next, float *__restrict__ mu_out,
+                                                double *__restrict__ part, int32_t ncols, int32_t ld,
+                                                int32_t lanes_log2, float alpha, float param) {
+  const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2);
+  double dv[VEC];
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) dv[i] = 0.0;
+  if (m.active) {
+    const int64_t v = g.lo + m.row;
+    float acc[VEC];
+    row_gather<VEC, WEIGHTED>(g, Xk, v, m.col, ld, acc);
+    float x[VEC], ln[VEC], mu[VEC];
+    load_vec<VEC>(Xk + v * ld + m.col, x);
+    load_vec<VEC>(lam_next + v * ld + m.col, ln);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      const float gr = grad_from_sum<MAXCUT>(acc[i], param);
+      const float s = alpha * gr;
+      const float z = x[i] + s;
+      const bool mask = z >= box_lo<MAXCUT>() && z <= box_hi();
+      mu[i] = mask ? ln[i] : 0.0f;
+      dv[i] = (double)mu[i] * (double)gr;
+    }
+    store_vec<VEC>(mu_out + v * ld + m.col, mu);
+  }
+  block_column_partials<VEC>(dv, m.active, m.col, ncols, lanes_log2, part);
+}
+
+// adjoint, part 2: lam_k = mu + alpha * (eta * (A mu))
+template <int VEC, bool WEIGHTED>
+__global__ __launch_bounds__(256) void k_adj_lambda(GraphView g, const float *__restrict__ mu, float *__restrict__ lam,
+                                                    int32_t ncols, int32_t ld, int32_t lanes_log2, float alpha,
+                                                    float eta) {
+  const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2);
+  if (!m.active) return;
+  const int64_t v = g.lo + m.row;
+  float acc[VEC], mv[VEC], out[VEC];
+  row_gather<VEC, WEIGHTED>(g, mu, v, m.col, ld, acc);
+  load_vec<VEC>(mu + v * ld + m.col, mv);
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) {
+    const float t1 = eta * acc[i];
+    const float t2 = alpha * t1;
+    out[i] = mv[i] + t2;
+  }
+  store_vec<VEC>(lam + v * ld + m.col, out);
+}
+
+// ===========================================================================
+// host launchers
+// ===========================================================================
+#define MQO_LAUNCH(kernel, grid, block, shmem, stream, ...) \
+  hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__)
+
+static inline unsigned blocks_for(int64_t count, int threads = 256) {
+  int64_t b = (count + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > 2147483647LL) b = 2147483647LL;
+  return (unsigned)b;
+}
+
+void launch_init_uniform(bool maxcut, float *X, int64_t lo, int64_t n, int32_t ncols, int32_t ld, uint64_t seed,
+                         uint64_t traj0, hipStream_t s) {
+  const int64_t count = ((n + 7) >> 3) * ncols;
+  if (maxcut)
+    MQO_LAUNCH(k_init_uniform<true>, dim3(blocks_for(count)), dim3(256), 0, s, X, lo, n, ncols, ld, seed, traj0);
+  else
+    MQO_LAUNCH(k_init_uniform<false>, dim3(blocks_for(count)), dim3(256), 0, s, X, lo, n, ncols, ld, seed, traj0);
+}
+
+void launch_init_degree(bool maxcut, float *X, const int32_t *row_ptr, int32_t *dmax_scratch, int64_t lo, int64_t n,
+                        int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0, float sigma, hipStream_t s) {
+  MQO_LAUNCH(k_fill_i32, dim3(1), dim3(64), 0, s, dmax_scratch, (int64_t)1, 0);
+  MQO_LAUNCH(k_degree_max, dim3(blocks_for(n < 65536 ? n : 65536)), dim3(256), 0, s, row_ptr, lo, n, dmax_scratch);
+  const int64_t count = n * ncols;
+  if (maxcut)
+    MQO_LAUNCH(k_init_degree<true>, dim3(blocks_for(count)), dim3(256), 0, s, X, row_ptr, dmax_scratch, lo, n, ncols,
+               ld, seed, traj0, sigma);
+  else
+    MQO_LAUNCH(k_init_degree<false>, dim3(blocks_for(count)), dim3(256), 0, s, X, row_ptr, dmax_scratch, lo, n,
+               ncols, ld, seed, traj0, sigma);
+}
+
+StepCfg default_step_cfg(int32_t ncols, int32_t ld) {
+  StepCfg c;
+  c.vec = 1;
+  if (ncols % 4 == 0 && ld % 4 == 0 && ncols >= 16)
+    c.vec = 4;
+  else if (ncols % 2 == 0 && ld % 2 == 0 && ncols >= 8)
+    c.vec = 2;
+  c.lanes_log2 = lanes_log2_for((ncols + c.vec - 1) / c.vec);
+  return c;
+}
+
+template <int VEC, bool MC, bool W, bool M>
+static void step_t(const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols, int32_t ld, int ll,
+                   float alpha, float mu, float param, hipStream_t s) {
+  MQO_LAUNCH((k_pga_step<VEC, MC, W, M>), grid_rows(g.n, ncols, ll, VEC, 256), dim3(256), 0, s, g, X, Xn, V, ncols,
+             ld, ll, alpha, mu, param);
+}
+
+template <int VEC>
+static void step_v(bool mc, bool w, bool m, const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols,
+                   int32_t ld, int ll, float alpha, float mu, float param, hipStream_t s) {
+  if (mc) {
+    if (w) {
+      if (m)
+        step_t<VEC, true, true, true>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, s);
+      else
+        step_t<VEC, true, true, false>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, s);
+    } else {
+      if (m)
+        step_t<VEC, true, false, true>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, s);
+      else
+        step_t<VEC, true, false, false>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, s);
+    }
+  } else {
+    if (m)
+      step_t<VEC, false, false, true>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, s);
+    else
+      step_t<VEC, false, false, false>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, s);
+  }
+}
+
+void launch_pga_step(bool maxcut, const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols, int32_t ld,
+                     StepCfg cfg, float alpha, float mu, float param, hipStream_t s) {
+  const bool w = g.weight != nullptr, m = mu != 0.0f;
+  switch (cfg.vec) {
+    case 4:
+      step_v<4>(maxcut, w, m, g, X, Xn, V, ncols, ld, cfg.lanes_log2, alpha, mu, param, s);
+      break;
+    case 2:
+      step_v<2>(maxcut, w, m, g, X, Xn, V, ncols, ld, cfg.lanes_log2, alpha, mu, param, s);
+      break;
+    default:
+      step_v<1>(maxcut, w, m, g, X, Xn, V, ncols, ld, cfg.lanes_log2, alpha, mu, param, s);
+      break;
+  }
+}
+
+void launch_copy_f32(const float *a, float *b, int64_t count, hipStream_t s) {
+  MQO_LAUNCH(k_copy_f32, dim3(blocks_for(count < (1 << 24) ? count : (1 << 24))), dim3(256), 0, s, a, b, count);
+}
+
+void launch_strided_copy_f32(const float *src, int32_t lds, int32_t cs, float *dst, int32_t ldd, int32_t cd,
+                             int64_t lo, int64_t n, hipStream_t s) {
+  MQO_LAUNCH(k_strided_copy_f32, dim3(blocks_for(n)), dim3(256), 0, s, src, lds, cs, dst, ldd, cd, lo, n);
+}
+
+void launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s) {
+  MQO_LAUNCH(k_fill_i32, dim3(blocks_for(count < (1 << 24) ? count : (1 << 24))), dim3(256), 0, s, p, count, v);
+}
+
+void launch_fill_i64(int64_t *p, int64_t count, int64_t v, hipStream_t s) {
+  MQO_LAUNCH(k_fill_i64, dim3(blocks_for(count < (1 << 24) ? count : (1 << 24))), dim3(256), 0, s, p, count, v);
+}
+
+void launch_fill_f32(float *p, int64_t count, float v, hipStream_t s) {
+  MQO_LAUNCH(k_fill_f32, dim3(blocks_for(count < (1 << 24) ? count : (1 << 24))), dim3(256), 0, s, p, count, v);
+}
+
+void launch_round(bool maxcut, const float *X, int8_t *Z, int64_t lo, int64_t n, int32_t ncols, int32_t ld,
+                  hipStream_t s) {
+  const int64_t count = n * ncols;
+  if (maxcut)
+    MQO_LAUNCH(k_round<true>, dim3(blocks_for(count)), dim3(256), 0, s, X, Z, lo, n, ncols, ld);
+  else
+    MQO_LAUNCH(k_round<false>, dim3(blocks_for(count)), dim3(256), 0, s, X, Z, lo, n, ncols, ld);
+}
+
+void launch_evaluate(bool maxcut, const GraphView &g, const int8_t *Z, int32_t *NB, long long *acc, int64_t *value,
+                     int64_t *conflicts, int8_t *fixed, int32_t ncols, int32_t ld, hipStream_t s) {
+  launch_fill_i64(reinterpret_cast<int64_t *>(acc), 3LL * ncols, 0, s);
+  const int ll = lanes_log2_for(ncols);
+  const dim3 grid = grid_rows(g.n, ncols, ll, 1, 256);
+  unsigned long long *a = reinterpret_cast<unsigned long long *>(acc);
+  const bool w = g.weight != nullptr;
+  if (maxcut) {
+    if (w)
+      MQO_LAUNCH((k_nbr_eval<true, true>), grid, dim3(256), 0, s, g, Z, NB, a, ncols, ld, ll);
+    else
+      MQO_LAUNCH((k_nbr_eval<true, false>), grid, dim3(256), 0, s, g, Z, NB, a, ncols, ld, ll);
+    MQO_LAUNCH(k_value_finalize<true>, dim3(blocks_for(ncols)), dim3(256), 0, s, acc, ncols, value, conflicts,
+               fixed);
+  } else {
+    MQO_LAUNCH((k_nbr_eval<false, false>), grid, dim3(256), 0, s, g, Z, NB, a, ncols, ld, ll);
+    MQO_LAUNCH(k_value_finalize<false>, dim3(blocks_for(ncols)), dim3(256), 0, s, acc, ncols, value, conflicts,
+               fixed);
+  }
+}
+
+void launch_ls_prio(uint32_t *PRIO, int64_t lo, int64_t n, int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0,
+                    uint64_t round, hipStream_t s) {
+  const int64_t count = ((n + 7) >> 3) * ncols;
+  MQO_LAUNCH(k_ls_prio, dim3(blocks_for(count)), dim3(256), 0, s, PRIO, lo, n, ncols, ld, seed, traj0, round);
+}
+
+void launch_ls_iteration(bool maxcut, const GraphView &g, int8_t *Z, int32_t *NB, const uint32_t *PRIO, int8_t *F,
+                         int32_t *active, const int32_t *prev_active, int32_t ncols, int32_t ld, hipStream_t s) {
+  const int ll = lanes_log2_for(ncols);
+  const dim3 grid = grid_rows(g.n, ncols, ll, 1, 256);
+  const bool w = g.weight != nullptr;
+  if (maxcut) {
+    MQO_LAUNCH(k_ls_select<true>, grid, dim3(256), 0, s, g, Z, NB, PRIO, F, active, prev_active, ncols, ld, ll);
+    if (w)
+      MQO_LAUNCH((k_ls_apply<true, true>), grid, dim3(256), 0, s, g, F, Z, NB, active, ncols, ld, ll);
+    else
+      MQO_LAUNCH((k_ls_apply<true, false>), grid, dim3(256), 0, s, g, F, Z, NB, active, ncols, ld, ll);
+  } else {
+    MQO_LAUNCH(k_ls_select<false>, grid, dim3(256), 0, s, g, Z, NB, PRIO, F, active, prev_active, ncols, ld, ll);
+    MQO_LAUNCH((k_ls_apply<false, false>), grid, dim3(256), 0, s, g, F, Z, NB, active, ncols, ld, ll);
+  }
+}
+
+void launch_accept(const int8_t *Z, int8_t *Zb, const int64_t *value, int64_t *best, int64_t lo, int64_t n,
+                   int32_t ncols, int32_t ld, int32_t ldb, bool first, hipStream_t s) {
+  MQO_LAUNCH(k_accept_copy, dim3(blocks_for(n * ncols)), dim3(256), 0, s, Z, Zb, value, best, lo, n, ncols, ld, ldb,
+             (int32_t)first);
+  MQO_LAUNCH(k_accept_best, dim3(blocks_for(ncols)), dim3(256), 0, s, value, best, ncols, (int32_t)first);
+}
+
+size_t reset_scratch_bytes(int32_t ncols) { return (size_t)ncols * (sizeof(SelState) + 256 * sizeof(uint32_t)); }
+
+void launch_reset(bool maxcut, const int8_t *Zb, int32_t ldb, const uint32_t *keys, float *X, float *V, int64_t lo,
+                  int64_t n, int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0, uint64_t round, int32_t k,
+                  int32_t mode, void *scratch, hipStream_t s) {
+  SelState *st = reinterpret_cast<SelState *>(scratch);
+  uint32_t *hist = reinterpret_cast<uint32_t *>(st + ncols);
+  const int64_t cnt = ((n + 7) >> 3) * ncols;
+  if (k > 0) {
+    MQO_LAUNCH(k_reset_init, dim3(blocks_for((int64_t)ncols * 256)), dim3(256), 0, s, st, hist, ncols, (uint32_t)k,
+               (uint32_t)n);
+    for (int pass = 0; pass < 4; ++pass) {
+      MQO_LAUNCH(k_reset_hist, dim3(blocks_for(cnt)), dim3(256), 0, s, st, hist, keys, lo, n, ncols, ld, seed, traj0,
+                 round, pass);
+      MQO_LAUNCH(k_reset_digit, dim3(blocks_for(ncols)), dim3(256), 0, s, st, hist, ncols);
+    }
+    MQO_LAUNCH(k_reset_ties, dim3(ncols), dim3(256), 0, s, st, keys, lo, n, ld, seed, traj0, round);
+  }
+  if (maxcut)
+    MQO_LAUNCH(k_reset_apply<true>, dim3(blocks_for(cnt)), dim3(256), 0, s, st, keys, Zb, X, V, lo, n, ncols, ld, ldb,
+               seed, traj0, round, k, mode);
+  else
+    MQO_LAUNCH(k_reset_apply<false>, dim3(blocks_for(cnt)), dim3(256), 0, s, st, keys, Zb, X, V, lo, n, ncols, ld,
+               ldb, seed, traj0, round, k, mode);
+}
+
+void launch_pick_best(const int64_t *best, int32_t G, int32_t B, int64_t *best_value, int32_t *best_b,
+                      hipStream_t s) {
+  MQO_LAUNCH(k_pick_best, dim3(blocks_for(G)), dim3(256), 0, s, best, G, B, best_value, best_b);
+}
+
+void launch_copy_best_x(const int8_t *Zb, int32_t B, const int64_t *voff, int32_t G, const int32_t *best_b,
+                        int8_t *out, int64_t n_total, hipStream_t s) {
+  MQO_LAUNCH(k_copy_best_x, dim3(blocks_for(n_total)), dim3(256), 0, s, Zb, B, voff, G, best_b, out, n_total);
+}
+
+void launch_gather_rowptr(const int32_t *row_ptr, const int64_t *voff, int32_t G, int32_t *out, hipStream_t s) {
+  MQO_LAUNCH(k_gather_rowptr, dim3(blocks_for(G + 1)), dim3(256), 0, s, row_ptr, voff, G, out);
+}
+
+void launch_validate_rows(const int32_t *row_ptr, int64_t n, int64_t nnz, int32_t *err, hipStream_t s) {
+  MQO_LAUNCH(k_validate_rows, dim3(blocks_for(n)), dim3(256), 0, s, row_ptr, n, nnz, err);
+}
+
+void launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, const int32_t *weight, const int64_t *voff,
+                          int32_t G, int64_t n, int32_t *err, hipStream_t s) {
+  MQO_LAUNCH(k_validate_cols, dim3(blocks_for(n)), dim3(256), 0, s, row_ptr, col_idx, weight, voff, G, n, err);
+}
+
+int64_t grid_blocks_x(int64_t nrows, StepCfg cfg) { return grid_rows(nrows, 1, cfg.lanes_log2, 1, 256).x; }
+
+template <int VEC, bool MC, bool W>
+static void obj_t(const GraphView &g, const float *X, const float *scale, float *grad, double *part, int32_t ncols,
+                  int32_t ld, int ll, float param, hipStream_t s) {
+  MQO_LAUNCH((k_objective_grad<VEC, MC, W>), grid_rows(g.n, ncols, ll, VEC, 256), dim3(256), 0, s, g, X, scale, grad,
+             part, ncols, ld, ll, param);
+}
+
+void launch_objective_grad(bool maxcut, const GraphView &g, const float *X, const float *scale, float *grad,
+                           double *part, int32_t ncols, int32_t ld, StepCfg cfg, float param, hipStream_t s) {
+  const bool w = g.weight != nullptr;
+  const int ll = cfg.lanes_log2;
+#define MQO_OBJ(V)                                                    \
+  if (maxcut) {                                                       \
+    if (w)                                                            \
+      obj_t<V, true, true>(g, X, scale, grad, part, ncols, ld, ll, param, s);  \
+    else                                                              \
+      obj_t<V, true, false>(g, X, scale, grad, part, ncols, ld, ll, param, s); \
+  } else {                                                            \
+    obj_t<V, false, false>(g, X, scale, grad, part, ncols, ld, ll, param, s);  \
+  }
+  if (cfg.vec == 4) {
+    MQO_OBJ(4)
+  } else if (cfg.vec == 2) {
+    MQO_OBJ(2)
+  } else {
+    MQO_OBJ(1)
+  }
+#undef MQO_OBJ
+}
+
+void launch_reduce_partials(const double *part, int64_t nblk, int32_t ncols, double *out, bool accumulate,
+                            hipStream_t s) {
+  MQO_LAUNCH(k_reduce_partials, dim3(ncols), dim3(256), 0, s, part, nblk, ncols, out, (int32_t)accumulate);
+}
+
+template <int VEC, bool MC, bool W>
+static void adj_t(const GraphView &g, const float *Xk, const float *lam_next, float *mu, float *lam, double *part,
+                  int32_t ncols, int32_t ld, int ll, float alpha, float param, hipStream_t s) {
+  const dim3 grid = grid_rows(g.n, ncols, ll, VEC, 256);
+  MQO_LAUNCH((k_adj_mu<VEC, MC, W>), grid, dim3(256), 0, s, g, Xk, lam_next, mu, part, ncols, ld, ll, alpha, param);
+  const float eta = MC ? -2.0f : -param;
+  MQO_LAUNCH((k_adj_lambda<VEC, W>), grid, dim3(256), 0, s, g, mu, lam, ncols, ld, ll, alpha, eta);
+}
+
+void launch_adjoint_step(bool maxcut, const GraphView &g, const float *Xk, const float *lam_next, float *mu,
+                         float *lam, double *part, int32_t ncols, int32_t ld, StepCfg cfg, float alpha, float param,
+                         hipStream_t s) {
+  const bool w = g.weight != nullptr;
+  const int ll = cfg.lanes_log2;
+#define MQO_ADJ(V)                                                                 \
+  if (maxcut) {                                                                    \
+    if (w)                                                                         \
+      adj_t<V, true, true>(g, Xk, lam_next, mu, lam, part, ncols, ld, ll, alpha, param, s);  \
+    else                                                                           \
+      adj_t<V, true, false>(g, Xk, lam_next, mu, lam, part, ncols, ld, ll, alpha, param, s); \
+  } else {                                                                         \
+    adj_t<V, false, false>(g, Xk, lam_next, mu, lam, part, ncols, ld, ll, alpha, param, s);  \
+  }
+  if (cfg.vec == 4) {
+    MQO_ADJ(4)
+  } else if (cfg.vec == 2) {
+    MQO_ADJ(2)
+  } else {
+    MQO_ADJ(1)
+  }
+#undef MQO_ADJ
+}
+
+}  // namespace mqo

@@ -1,0 +1,95 @@
+// Host-side launchers of the libmqo kernels (internal interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace mqo {
+
+// Step-kernel shape: each lane owns `vec` consecutive columns, 2^lanes_log2
+// lanes share one row.
+struct StepCfg {
+  int vec;
+  int lanes_log2;
+};
+
+StepCfg default_step_cfg(int32_t ncols, int32_t ld);
+int64_t grid_blocks_x(int64_t nrows, StepCfg cfg);
+
+void launch_init_uniform(bool maxcut, float *X, int64_t lo, int64_t n, int32_t ncols, int32_t ld, uint64_t seed,
+                         uint64_t traj0, hipStream_t s);
+void launch_init_degree(bool maxcut, float *X, const int32_t *row_ptr, int32_t *dmax_scratch, int64_t lo, int64_t n,
+                        int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0, float sigma, hipStream_t s);
+void launch_pga_step(bool maxcut, const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols, int32_t ld,
+                     StepCfg cfg, float alpha, float mu, float param, hipStream_t s);
+void launch_copy_f32(const float *a, float *b, int64_t count, hipStream_t s);
+void launch_strided_copy_f32(const float *src, int32_t lds, int32_t cs, float *dst, int32_t ldd, int32_t cd,
+                             int64_t lo, int64_t n, hipStream_t s);
+void launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
+void launch_fill_i64(int64_t *p, int64_t count, int64_t v, hipStream_t s);
+void launch_fill_f32(float *p, int64_t count, float v, hipStream_t s);
+void launch_round(bool maxcut, const float *X, int8_t *Z, int64_t lo, int64_t n, int32_t ncols, int32_t ld,
+                  hipStream_t s);
+// acc: 3 * ncols int64 scratch
+void launch_evaluate(bool maxcut, const GraphView &g, const int8_t *Z, int32_t *NB, long long *acc, int64_t *value,
+                     int64_t *conflicts, int8_t *fixed, int32_t ncols, int32_t ld, hipStream_t s);
+void launch_ls_prio(uint32_t *PRIO, int64_t lo, int64_t n, int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0,
+                    uint64_t round, hipStream_t s);
+void launch_ls_iteration(bool maxcut, const GraphView &g, int8_t *Z, int32_t *NB, const uint32_t *PRIO, int8_t *F,
+                         int32_t *active, const int32_t *prev_active, int32_t ncols, int32_t ld, hipStream_t s);
+void launch_accept(const int8_t *Z, int8_t *Zb, const int64_t *value, int64_t *best, int64_t lo, int64_t n,
+                   int32_t ncols, int32_t ld, int32_t ldb, bool first, hipStream_t s);
+size_t reset_scratch_bytes(int32_t ncols);
+void launch_reset(bool maxcut, const int8_t *Zb, int32_t ldb, const uint32_t *keys, float *X, float *V, int64_t lo,
+                  int64_t n, int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0, uint64_t round, int32_t k,
+                  int32_t mode, void *scratch, hipStream_t s);
+void launch_pick_best(const int64_t *best, int32_t G, int32_t B, int64_t *best_value, int32_t *best_b, hipStream_t s);
+void launch_copy_best_x(const int8_t *Zb, int32_t B, const int64_t *voff, int32_t G, const int32_t *best_b,
+                        int8_t *out, int64_t n_total, hipStream_t s);
+void launch_gather_rowptr(const int32_t *row_ptr, const int64_t *voff, int32_t G, int32_t *out, hipStream_t s);
+void launch_validate_rows(const int32_t *row_ptr, int64_t n, int64_t nnz, int32_t *err, hipStream_t s);
+void launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, const int32_t *weight, const int64_t *voff,
+                          int32_t G, int64_t n, int32_t *err, hipStream_t s);
+void launch_objective_grad(bool maxcut, const GraphView &g, const float *X, const float *scale, float *grad,
+                           double *part, int32_t ncols, int32_t ld, StepCfg cfg, float param, hipStream_t s);
+void launch_reduce_partials(const double *part, int64_t nblk, int32_t ncols, double *out, bool accumulate,
+                            hipStream_t s);
+void launch_adjoint_step(bool maxcut, const GraphView &g, const float *Xk, const float *lam_next, float *mu,
+                         float *lam, double *part, int32_t ncols, int32_t ld, StepCfg cfg, float alpha, float param,
+                         hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// persistent tile plan: one workgroup owns (graph, T trajectories) with the
+// iterate tile resident in LDS for a whole round
+// ---------------------------------------------------------------------------
+struct TileArgs {
+  const int32_t *row_ptr;
+  const int32_t *col_idx;
+  const int32_t *weight;
+  const int64_t *vtx_off;  // device [G+1]
+  int32_t G, B, T, log2T, tiles;
+  int32_t n_max;  // scratch stride (rows)
+  int32_t steps, r0, r1, reset_mode, ls;
+  float alpha, mu, param;
+  double rho;
+  uint64_t seed;
+  const float *x0;  // [n_total][B], read when r0 == 0
+  int8_t *zbest;    // [n_total][B]
+  int64_t *best;    // [G*B]
+  int8_t *zs;       // private scratch, n_max*T per workgroup
+  int32_t *nb;
+  uint32_t *prio;
+  int8_t *fl;
+  float *vm;          // momentum, same layout (used when mu != 0)
+  int32_t *ls_iters;  // [workgroups]
+  int32_t *err;
+};
+
+bool tile_shape_ok(int64_t n_max, int T, int threads);
+size_t tile_lds_bytes(int64_t n_max, int T);
+hipError_t launch_tile_round(bool maxcut, bool weighted, bool momentum, const TileArgs &a, int threads,
+                             hipStream_t s);
+
+}  // namespace mqo

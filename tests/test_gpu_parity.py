@@ -1,0 +1,372 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Bit-exact: initial iterates, float32 steps (against the oracle's float32
+replay), rounding, evaluation, checker, local search, reset sets and whole
+solves under every launch plan.  Tolerances: one step and the gradient
+against float64 within 1e-5 relative; objective values, adjoints as stated
+per test."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from synth import graphs, arrays  # noqa: E402
+from oracle import objectives as obj, pga, discrete, solver  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def mqo():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_06921_amd import mqo as m
+    return m
+
+
+DEV = "cuda:0"
+
+
+def _graph_cases():
+    # ragged sizes, isolated vertices, a batch of graphs, weighted torus
+    return {
+        "er300": ("mis", graphs.erdos_renyi(300, 0.03, 11)),
+        "er_batch": ("mis", graphs.concat([graphs.erdos_renyi(97, 0.08, 12), graphs.empty(3),
+                                           graphs.erdos_renyi(180, 0.05, 13), graphs.star(40)])),
+        "reg3": ("maxcut", graphs.random_regular(250, 3, 14)),
+        "torus": ("maxcut", graphs.torus_pm1(13, 15)),
+        "cut_batch": ("maxcut", graphs.concat([graphs.erdos_renyi(120, 0.05, 16), graphs.cycle(33),
+                                               graphs.path(2)])),
+    }
+
+
+CASES = _graph_cases()
+
+
+def _x(kind, n, B, seed):
+    lo, hi = obj.box(kind)
+    return arrays.uniform((n, B), lo, hi, seed)
+
+
+# --------------------------------------------------------------------------
+# a2 init, a3-a5 step
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("B", [1, 3, 8, 64])
+def test_init_uniform_bit_exact(mqo, name, B):
+    kind, g = CASES[name]
+    dg = mqo.DeviceGraph(g, DEV)
+    X = mqo.init_iterate(kind, dg, B, seed=123).cpu().numpy()
+    for gi in range(g.num_graphs):
+        lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+        ref = pga.init_uniform(kind, hi - lo, gi * B + np.arange(B), 123)
+        assert np.array_equal(X[lo:hi], ref)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("B", [1, 2, 5, 16, 32, 100, 256])
+def test_one_step_bit_exact_and_within_1e5_of_fp64(mqo, name, B):
+    kind, g = CASES[name]
+    dg = mqo.DeviceGraph(g, DEV)
+    X0 = _x(kind, g.n, B, 21 + B)
+    param = 2.0 if kind == "mis" else 1e-3
+    X = torch.from_numpy(X0).to(DEV)
+    mqo.pga_steps(kind, dg, X, 1, alpha=0.01, gamma=2.0, lam=1e-3)
+    got = X.cpu().numpy()
+    ref32, _ = pga.step32(g, X0, kind, 0.01, param)
+    assert np.array_equal(got, ref32)
+    ref64, _ = pga.step64(X0.astype(np.float64), obj.adjacency(g), kind, 0.01, param)
+    assert np.abs(got - ref64).max() / max(1.0, np.abs(ref64).max()) <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["er300", "torus", "cut_batch"])
+def test_many_steps_with_momentum_bit_exact(mqo, name):
+    kind, g = CASES[name]
+    dg = mqo.DeviceGraph(g, DEV)
+    B = 12
+    X0 = _x(kind, g.n, B, 31)
+    param = 2.0 if kind == "mis" else 1e-3
+    for mu in (0.0, 0.6):
+        X = torch.from_numpy(X0).to(DEV)
+        V = torch.zeros_like(X)
+        mqo.pga_steps(kind, dg, X, 37, alpha=0.02, gamma=2.0, lam=1e-3, momentum=mu, V=V)
+        ref, Vr = X0, None
+        for _ in range(37):
+            ref, Vr = pga.step32(g, ref, kind, 0.02, param, mu, Vr)
+        assert np.array_equal(X.cpu().numpy(), ref)
+        if mu:
+            assert np.array_equal(V.cpu().numpy(), Vr)
+
+
+# --------------------------------------------------------------------------
+# a6 rounding, a7 evaluation and checker
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("B", [1, 7, 64])
+def test_round_evaluate_bit_exact(mqo, name, B):
+    kind, g = CASES[name]
+    dg = mqo.DeviceGraph(g, DEV)
+    X0 = _x(kind, g.n, B, 41)
+    # include the thresholds themselves
+    X0[::7, 0] = 0.5 if kind == "mis" else 0.0
+    Z, value, conf, fixed = mqo.round_evaluate(kind, dg, torch.from_numpy(X0).to(DEV))
+    Zr = discrete.round_x(kind, X0)
+    assert np.array_equal(Z.cpu().numpy(), Zr)
+    for gi in range(g.num_graphs):
+        sub = g.subgraph(gi)
+        lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+        zg = Zr[lo:hi]
+        assert np.array_equal(value.cpu().numpy()[gi * B:(gi + 1) * B], discrete.value(kind, sub, zg))
+        if kind == "mis":
+            _, c = discrete.evaluate_mis(sub, zg)
+            assert np.array_equal(conf.cpu().numpy()[gi * B:(gi + 1) * B], c)
+            fx = discrete.is_pga_fixed_mis(sub, zg, 2.0, 0.01)
+            assert np.array_equal(fixed.cpu().numpy()[gi * B:(gi + 1) * B].astype(bool), fx)
+
+
+def test_checker_on_maximal_sets(mqo):
+    g = graphs.erdos_renyi(60, 0.1, 51)
+    Z0 = arrays.binary01((60, 16), 52)
+    Zm, _ = discrete.local_search("mis", g, Z0, 3, np.arange(16), 0)  # maximal independent sets
+    Zmix = np.concatenate([Zm, Z0], axis=1).astype(np.float32)
+    dg = mqo.DeviceGraph(g, DEV)
+    _, value, conf, fixed = mqo.round_evaluate("mis", dg, torch.from_numpy(Zmix).to(DEV))
+    fx = fixed.cpu().numpy().astype(bool)
+    assert fx[:16].all()
+    assert np.array_equal(fx, discrete.is_pga_fixed_mis(g, Zmix.astype(np.int8), 2.0, 0.01))
+
+
+# --------------------------------------------------------------------------
+# a8 local search
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("B", [1, 9, 64])
+def test_local_search_bit_exact(mqo, name, B):
+    kind, g = CASES[name]
+    dg = mqo.DeviceGraph(g, DEV)
+    Z0 = arrays.binary01((g.n, B), 61) if kind == "mis" else arrays.spins((g.n, B), 61)
+    Z = torch.from_numpy(Z0.copy()).to(DEV)
+    it = mqo.local_search(kind, dg, Z, seed=99, rnd=4)
+    got = Z.cpu().numpy()
+    its = []
+    for gi in range(g.num_graphs):
+        sub = g.subgraph(gi)
+        lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+        ref, i = discrete.local_search(kind, sub, Z0[lo:hi], 99, gi * B + np.arange(B), 4)
+        assert np.array_equal(got[lo:hi], ref)
+        its.append(i)
+    assert it == max(its)
+
+
+# --------------------------------------------------------------------------
+# a10 reset
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("B", [1, 6, 64])
+@pytest.mark.parametrize("mode", ["zero", "flip"])
+def test_reset_bit_exact(mqo, name, B, mode):
+    kind, g = CASES[name]
+    dg = mqo.DeviceGraph(g, DEV)
+    Zb = arrays.binary01((g.n, B), 71) if kind == "mis" else arrays.spins((g.n, B), 71)
+    for rho in (0.0, 0.05, 0.37):
+        X = mqo.reset(kind, dg, torch.from_numpy(Zb).to(DEV), seed=5, rnd=3, rho=rho, mode=mode).cpu().numpy()
+        for gi in range(g.num_graphs):
+            lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+            n = hi - lo
+            mask = discrete.reset_set(n, discrete.reset_count(rho, n), 5, gi * B + np.arange(B), 3)
+            ref = discrete.reset_apply(kind, Zb[lo:hi], mask, mode)
+            assert np.array_equal(X[lo:hi], ref), (gi, rho)
+
+
+def test_reset_ties_with_given_keys(mqo):
+    g = graphs.erdos_renyi(700, 0.01, 81)
+    dg = mqo.DeviceGraph(g, DEV)
+    B = 5
+    keys = arrays.integers((700, B), 0, 6, 82)  # heavy ties
+    keys[:, 4] = 3  # every key equal
+    Zb = arrays.binary01((700, B), 83)
+    X = mqo.reset("mis", dg, torch.from_numpy(Zb).to(DEV), seed=0, rnd=1, rho=0.1,
+                  keys=torch.from_numpy(keys.astype(np.int32)).to(DEV)).cpu().numpy()
+    mask = discrete.reset_set(700, 70, 0, np.arange(B), 1, keys=keys)
+    assert np.array_equal(X, discrete.reset_apply("mis", Zb, mask, "zero"))
+
+
+# --------------------------------------------------------------------------
+# a9, a11, a12 whole solves under every plan
+# --------------------------------------------------------------------------
+
+SOLVE_CASES = [
+    ("mis", "er300", dict(batch=6, steps_per_round=40, rounds=4, alpha=0.01, rho=0.05)),
+    ("mis", "er_batch", dict(batch=5, steps_per_round=30, rounds=3, alpha=0.02, rho=0.1)),
+    ("maxcut", "reg3", dict(batch=10, steps_per_round=50, rounds=4, alpha=0.01, rho=0.05)),
+    ("maxcut", "torus", dict(batch=4, steps_per_round=40, rounds=3, alpha=0.02, rho=0.2, reset_mode="flip")),
+    ("maxcut", "cut_batch", dict(batch=3, steps_per_round=25, rounds=3, alpha=0.03, rho=0.3, momentum=0.5)),
+    ("mis", "er300", dict(batch=4, steps_per_round=20, rounds=2, alpha=0.05, rho=0.0, local_search=False)),
+    ("mis", "er_batch", dict(batch=2, steps_per_round=0, rounds=2, alpha=0.05, rho=0.2)),
+]
+
+
+def _oracle_solve(kind, g, kw, x0=None):
+    p = solver.Params(batch=kw["batch"], steps_per_round=kw["steps_per_round"], rounds=kw["rounds"],
+                      alpha=kw["alpha"], seed=kw.get("seed", 17), mu=kw.get("momentum", 0.0), rho=kw["rho"],
+                      reset_mode=kw.get("reset_mode", "zero"), local_search=kw.get("local_search", True))
+    return solver.solve(kind, g, p, x0=x0)
+
+
+@pytest.mark.parametrize("ci", range(len(SOLVE_CASES)))
+@pytest.mark.parametrize("plan", ["persistent", "batched", "plain"])
+def test_solve_bit_exact_every_plan(mqo, ci, plan):
+    kind, name, kw = SOLVE_CASES[ci]
+    g = CASES[name][1]
+    kw = dict(kw, seed=17)
+    dg = mqo.DeviceGraph(g, DEV)
+    out = mqo.solve(kind, dg, plan=plan, **kw)
+    ref = _oracle_solve(kind, g, kw)
+    assert out["plan"] == plan
+    assert np.array_equal(out["traj_best_value"].cpu().numpy(), ref["traj_best_value"])
+    assert np.array_equal(out["traj_best_x"].cpu().numpy(), ref["traj_best_x"])
+    assert np.array_equal(out["best_value"].cpu().numpy(), ref["best_value"])
+    assert np.array_equal(out["best_x"].cpu().numpy(), ref["best_x"])
+    assert out["edge_updates"] == g.nnz * kw["batch"] * kw["steps_per_round"] * kw["rounds"]
+
+
+@pytest.mark.parametrize("T", [1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("threads", [256, 1024])
+def test_persistent_tile_shapes_agree(mqo, T, threads):
+    kind, g = CASES["reg3"]
+    kw = dict(batch=37, steps_per_round=30, rounds=3, alpha=0.01, rho=0.05, seed=3)
+    dg = mqo.DeviceGraph(g, DEV)
+    ref = mqo.solve(kind, dg, plan="batched", **kw)
+    out = mqo.solve(kind, dg, plan="persistent", tile_cols=T, tile_threads=threads, **kw)
+    assert out["tile_cols"] == T and out["tile_threads"] == threads
+    assert torch.equal(out["traj_best_value"], ref["traj_best_value"])
+    assert torch.equal(out["traj_best_x"], ref["traj_best_x"])
+
+
+def test_solve_with_given_x0_degree_init(mqo):
+    g = graphs.erdos_renyi(150, 0.06, 91)
+    B = 8
+    x0 = pga.init_degree("mis", g.degrees(), np.arange(B), 4, 0.1).astype(np.float32)
+    kw = dict(batch=B, steps_per_round=30, rounds=3, alpha=0.02, rho=0.1, seed=4)
+    dg = mqo.DeviceGraph(g, DEV)
+    ref = _oracle_solve("mis", g, kw, x0=x0)
+    for plan in ("persistent", "batched", "plain"):
+        out = mqo.solve("mis", dg, x0=torch.from_numpy(x0.ravel()).to(DEV), plan=plan, **kw)
+        assert np.array_equal(out["traj_best_value"].cpu().numpy(), ref["traj_best_value"])
+        assert np.array_equal(out["traj_best_x"].cpu().numpy(), ref["traj_best_x"])
+
+
+def test_degree_init_close_to_oracle(mqo):
+    g = graphs.barabasi_albert(500, 3, 92)
+    dg = mqo.DeviceGraph(g, DEV)
+    for kind in ("mis", "maxcut"):
+        X = mqo.init_iterate(kind, dg, 16, seed=8, init_mode="degree", init_sigma=0.2).cpu().numpy()
+        ref = pga.init_degree(kind, g.degrees(), np.arange(16), 8, 0.2)
+        assert np.abs(X - ref).max() < 1e-5
+
+
+def test_time_budget_stops_early(mqo):
+    g = graphs.erdos_renyi(300, 0.03, 93)
+    dg = mqo.DeviceGraph(g, DEV)
+    for plan in ("persistent", "batched"):
+        out = mqo.solve("mis", dg, batch=4, steps_per_round=10, rounds=1000, alpha=0.01, seed=1, plan=plan,
+                        time_budget_s=1e-9)
+        assert out["rounds_executed"] == 1
+        assert out["steps_executed"] == 10
+
+
+def test_invalid_graph_rejected_before_launch(mqo):
+    g = graphs.erdos_renyi(50, 0.1, 94)
+    bad = graphs.Graph(g.n, g.row_ptr.copy(), g.col_idx.copy())
+    bad.col_idx[0] = (bad.col_idx[0] + 1) % 50  # breaks symmetry or ordering
+    dg = mqo.DeviceGraph(bad, DEV)
+    with pytest.raises(mqo.MqoError) as e:
+        mqo.solve("mis", dg, batch=2, steps_per_round=5, rounds=1)
+    assert e.value.status == -2
+    with pytest.raises(mqo.MqoError):
+        dg.validate()
+    mqo.DeviceGraph(g, DEV).validate()
+    with pytest.raises(mqo.MqoError) as e:
+        mqo.solve("maxcut", mqo.DeviceGraph(g, DEV), batch=2, lam=2.5)
+    assert e.value.status == -1
+
+
+# --------------------------------------------------------------------------
+# a13 objective and SpMM-gradient backward, a14 unrolled adjoint
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("B", [1, 4, 64])
+def test_objective_and_gradient(mqo, name, B):
+    kind, g = CASES[name]
+    dg = mqo.DeviceGraph(g, DEV)
+    param = 2.0 if kind == "mis" else 1e-3
+    X0 = _x(kind, g.n, B, 101)
+    scale = arrays.uniform((g.num_graphs * B,), -2, 2, 102)
+    f, grad = mqo.objective_grad(kind, dg, torch.from_numpy(X0).to(DEV), param,
+                                 scale=torch.from_numpy(scale).to(DEV))
+    f = f.cpu().numpy()
+    grad = grad.cpu().numpy()
+    for gi in range(g.num_graphs):
+        sub = g.subgraph(gi)
+        lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+        fr, gr = pga.objective_and_grad(sub, kind, param, X0[lo:hi].astype(np.float64), scale[gi * B:(gi + 1) * B])
+        # f: float32 neighbour sums (relative error <= deg * 2^-24), float64 accumulation
+        assert np.allclose(f[gi * B:(gi + 1) * B], fr, rtol=1e-5, atol=1e-5 * np.abs(X0[lo:hi]).sum())
+        assert np.abs(grad[lo:hi] - gr).max() / max(1.0, np.abs(gr).max()) <= 1e-5
+
+
+def test_autograd_objective_backward_matches_closed_form(mqo):
+    kind, g = CASES["torus"]
+    dg = mqo.DeviceGraph(g, DEV)
+    X0 = _x(kind, g.n, 8, 111)
+    X = torch.from_numpy(X0).to(DEV).requires_grad_(True)
+    f = mqo.objective(X, dg, kind, 1e-3)
+    w = torch.linspace(-1, 1, f.numel(), dtype=torch.float64, device=DEV)
+    (f * w).sum().backward()
+    _, gr = pga.objective_and_grad(g, kind, 1e-3, X0.astype(np.float64), w.cpu().numpy())
+    got = X.grad.cpu().numpy()
+    assert np.abs(got - gr).max() / max(1.0, np.abs(gr).max()) <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["er300", "reg3", "torus"])
+def test_unrolled_forward_bit_exact_and_adjoint(mqo, name):
+    kind, g = CASES[name]
+    dg = mqo.DeviceGraph(g, DEV)
+    param = 2.0 if kind == "mis" else 1e-3
+    B, K, c, alpha = 6, 20, 5, 0.01
+    X0 = _x(kind, g.n, B, 121)
+    XK, ckpt = mqo.unrolled_forward(kind, dg, torch.from_numpy(X0).to(DEV), alpha, K, c, param)
+    xs = pga.unrolled_forward(g, kind, param, alpha, K, X0, precision="fp32")
+    assert np.array_equal(XK.cpu().numpy(), xs[K])
+    for j in range(K // c):
+        assert np.array_equal(ckpt[j].cpu().numpy(), xs[j * c])
+    dL = obj.gradient(kind, xs[K].astype(np.float64), obj.adjacency(g), param)
+    dX0, da = mqo.unrolled_backward(kind, dg, ckpt, torch.from_numpy(dL.astype(np.float32)).to(DEV), alpha, K, c,
+                                    param)
+    rX0, ra = pga.unrolled_backward(g, kind, param, alpha, K, X0, dL.astype(np.float32).astype(np.float64),
+                                    precision="fp32")
+    got = dX0.cpu().numpy()
+    # float32 adjoint recursion over K steps against float64: relative 1e-4
+    assert np.abs(got - rX0).max() / max(1.0, np.abs(rX0).max()) <= 1e-4
+    assert np.allclose(da.cpu().numpy(), ra, rtol=1e-4, atol=1e-4 * np.abs(ra).max())
+
+
+def test_unrolled_autograd_function(mqo):
+    kind, g = CASES["reg3"]
+    dg = mqo.DeviceGraph(g, DEV)
+    X0 = torch.from_numpy(_x(kind, g.n, 4, 131)).to(DEV).requires_grad_(True)
+    alpha = torch.tensor(0.01, dtype=torch.float64, device=DEV, requires_grad=True)
+    XK = mqo.unrolled_pga(X0, alpha, dg, kind, 1e-3, K=10, ckpt_every=5)
+    loss = mqo.objective(XK, dg, kind, 1e-3).sum()
+    loss.backward()
+    x0 = X0.detach().cpu().numpy()
+    xs = pga.unrolled_forward(g, kind, 1e-3, 0.01, 10, x0, precision="fp32")
+    dL = obj.gradient(kind, xs[10].astype(np.float64), obj.adjacency(g), 1e-3)
+    rX0, ra = pga.unrolled_backward(g, kind, 1e-3, 0.01, 10, x0, dL, precision="fp32")
+    assert np.abs(X0.grad.cpu().numpy() - rX0).max() / max(1.0, np.abs(rX0).max()) <= 1e-4
+    assert abs(float(alpha.grad) - ra.sum()) <= 1e-4 * max(1.0, abs(ra.sum()))
