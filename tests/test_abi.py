@@ -1,0 +1,146 @@
+"""CPU checks of the C-ABI library: it loads, exports every function the
+header declares, and rejects invalid graphs and parameters on the host
+before any GPU call.  No compute is launched."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from synth import graphs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mqo.h")
+
+
+@pytest.fixture(scope="module")
+def m():
+    from paper_2605_06921_amd import mqo
+    return mqo
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mqo_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(m):
+    names = _declared()
+    assert len(names) >= 20
+    lib = ctypes.CDLL(m.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    # the binding declares a signature for each of them
+    assert set(names) == set(m.SIGNATURES)
+
+
+def test_version_status_and_params(m):
+    assert m.version() == 100
+    L = m.lib()
+    assert L.mqo_status_string(0) == b"ok"
+    assert L.mqo_status_string(-2) == b"invalid graph"
+    p = m.make_params(batch=7, rho=0.3)
+    assert p.struct_size == ctypes.sizeof(m._Params)
+    assert p.batch == 7 and abs(p.rho - 0.3) < 1e-15 and p.local_search == 1
+
+
+def _valid():
+    g = graphs.with_weights(graphs.erdos_renyi(40, 0.2, 3), 4)
+    return g
+
+
+def test_validate_graph_host_accepts_canonical(m):
+    g = _valid()
+    assert m.validate_graph_host(g.n, g.row_ptr, g.col_idx, g.weight) == 0
+    assert m.validate_graph_host(5, np.zeros(6, np.int32), np.zeros(0, np.int32)) == 0
+
+
+@pytest.mark.parametrize("breakage", ["asym", "self", "unsorted", "dup", "range", "rowptr", "weight"])
+def test_validate_graph_host_rejects(m, breakage):
+    g = _valid()
+    rp, ci, w = g.row_ptr.copy(), g.col_idx.copy(), g.weight.copy()
+    v = int(np.argmax(np.diff(rp) >= 2))  # a row with at least two entries
+    a = rp[v]
+    if breakage == "asym":
+        ci[a] = [c for c in range(g.n) if c != v and c not in ci[rp[v]:rp[v + 1]]][0]
+        ci[rp[v]:rp[v + 1]] = np.sort(ci[rp[v]:rp[v + 1]])
+    elif breakage == "self":
+        ci[a] = v
+        ci[rp[v]:rp[v + 1]] = np.sort(ci[rp[v]:rp[v + 1]])
+    elif breakage == "unsorted":
+        ci[a], ci[a + 1] = ci[a + 1], ci[a]
+    elif breakage == "dup":
+        ci[a + 1] = ci[a]
+    elif breakage == "range":
+        ci[a] = g.n + 3
+    elif breakage == "rowptr":
+        rp[v + 1] = rp[v] - 1
+    elif breakage == "weight":
+        w[a] = w[a] + 7
+    assert m.validate_graph_host(g.n, rp, ci, w) == -2
+    assert m.last_error()
+
+
+def _struct(m, n=10, G=1, offsets=None, weight=False):
+    off = np.array(offsets if offsets is not None else [0, n], dtype=np.int64)
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    s = m._Graph(G, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(off[-1]), 4, dummy, dummy,
+                 dummy if weight else None)
+    return s, off
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("batch", 0, -1), ("rounds", 0, -1), ("alpha", -0.1, -1), ("gamma", 1.0, -1), ("rho", 1.0, -1),
+    ("momentum", 1.0, -1), ("check_every", 5, -5), ("plan", 9, -1), ("tile_cols", 3, -1),
+    ("tile_threads", 100, -1), ("steps_per_round", -1, -1), ("init_mode", 4, -1),
+])
+def test_solve_rejects_parameters_on_host(m, field, value, status):
+    s, off = _struct(m)
+    p = m.make_params(batch=2)
+    setattr(p, field, value)
+    r = m._Result()
+    st = m.lib().mqo_solve_mis(ctypes.byref(s), ctypes.byref(p), None, ctypes.byref(r), None, 0, None)
+    assert st == status, m.last_error()
+
+
+def test_solve_rejects_graph_arguments_on_host(m):
+    L = m.lib()
+    p = m.make_params(batch=2, lam=1e-3)
+    r = m._Result()
+    s, off = _struct(m, weight=True)
+    assert L.mqo_solve_mis(ctypes.byref(s), ctypes.byref(p), None, ctypes.byref(r), None, 0, None) == -1
+    p2 = m.make_params(batch=2, lam=2.0)
+    s, off = _struct(m)
+    assert L.mqo_solve_maxcut(ctypes.byref(s), ctypes.byref(p2), None, ctypes.byref(r), None, 0, None) == -1
+    s, off = _struct(m, G=2, offsets=[0, 5, 5])  # an empty graph in the batch
+    assert L.mqo_solve_maxcut(ctypes.byref(s), ctypes.byref(p), None, ctypes.byref(r), None, 0, None) == -2
+    s, off = _struct(m, G=1, offsets=[1, 5])
+    assert L.mqo_solve_maxcut(ctypes.byref(s), ctypes.byref(p), None, ctypes.byref(r), None, 0, None) == -2
+    # missing outputs
+    s, off = _struct(m)
+    assert L.mqo_solve_maxcut(ctypes.byref(s), ctypes.byref(p), None, ctypes.byref(r), None, 0, None) == -1
+
+
+def test_workspace_sizes(m):
+    L = m.lib()
+    s, off = _struct(m, n=1000)
+    p = m.make_params(batch=64)
+    ws = L.mqo_workspace_size(ctypes.byref(s), ctypes.byref(p), 1)
+    assert ws >= 1000 * 64 * (4 * 5 + 3)
+    p.batch = 0
+    assert L.mqo_workspace_size(ctypes.byref(s), ctypes.byref(p), 1) == 0
+    assert L.mqo_unrolled_workspace_size(ctypes.byref(s), 64, 5) >= 8 * 1000 * 64 * 4
+    assert L.mqo_objective_workspace_size(ctypes.byref(s), 64) > 0
+
+
+def test_async_entry_points_reject_bad_arguments(m):
+    L = m.lib()
+    s, off = _struct(m)
+    assert L.mqo_objective_grad(ctypes.byref(s), 0, 0.5, ctypes.c_void_p(0x1000), 4, None, None, None, None, 0,
+                                None) == -1  # gamma <= 1
+    assert L.mqo_pga_unrolled_forward(ctypes.byref(s), 1, 1e-3, 0.01, 7, 5, ctypes.c_void_p(0x1000),
+                                      ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 4, None, 0, None) == -1
+    assert L.mqo_reset(ctypes.byref(s), 0, 4, 0, 1, 1.5, 0, ctypes.c_void_p(0x1000), None, ctypes.c_void_p(0x1000),
+                       None, 0, None) == -1
