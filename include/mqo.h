@@ -93,6 +93,13 @@ typedef struct {
   int32_t tile_cols;       /* persistent plan: trajectories per workgroup, a
                               power of two <= 64, or 0 = autotune             */
   int32_t tile_threads;    /* persistent plan: 256, 512 or 1024, 0 = autotune   */
+  int32_t tile_vec;        /* persistent plan: trajectories per lane in the
+                              step loop, 1, 2 or 4, 0 = autotune             */
+  int32_t tile_csr;        /* persistent plan: 1 = column indices from global
+                              memory, 2 = staged in LDS, 0 = autotune        */
+  int32_t tile_reg;        /* persistent plan, unweighted graphs of degree
+                              <= 16: 2 = neighbour offsets in registers,
+                              1 = never, 0 = autotune                        */
   uint64_t seed;
   double time_budget_s;    /* 0 = none; otherwise no round starts after it      */
 } mqo_params;
@@ -109,6 +116,10 @@ typedef struct {
   int32_t plan_used;           /* (host) MQO_PLAN_PLAIN/BATCHED/PERSISTENT     */
   int32_t tile_cols_used;      /* (host) persistent plan choice, else 0        */
   int32_t tile_threads_used;   /* (host)                                       */
+  int32_t tile_vec_used;       /* (host) trajectories per lane in the steps    */
+  int32_t tile_csr_lds_used;   /* (host) 1 = column indices staged in LDS      */
+  int32_t tile_reg_degree_used;/* (host) padded degree of the register
+                                  adjacency, 0 = not used                    */
   int64_t ls_iterations;       /* (host) local-search iterations summed over
                                   rounds (per round: the largest count of any
                                   graph / trajectory tile)                   */

@@ -56,6 +56,12 @@ inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 // process-wide resources: a private stream (default priority) for blocking
 // entry points, pinned readback memory, and plan caches
 // ---------------------------------------------------------------------------
+// persistent-plan shape: trajectories per workgroup, threads, trajectories
+// per lane in the step loop, column indices staged in LDS
+struct TileCfg {
+  int T, threads, vec, csr, dreg, ipt;
+};
+
 struct Resources {
   std::mutex mu;
   hipStream_t stream = nullptr;
@@ -63,7 +69,7 @@ struct Resources {
   int32_t *small = nullptr;   // 64 device ints of scratch for entry points without a workspace
   int device = -1;
   int lds_limit = 0;
-  std::map<std::string, std::pair<int, int>> tile_tuning;  // key -> (T, threads)
+  std::map<std::string, TileCfg> tile_tuning;  // shape key -> tuned tile shape
 };
 
 Resources &res() {
@@ -139,6 +145,10 @@ int check_params(const mqo_params *p, mqo_objective obj) {
     return fail(MQO_ERR_INVALID_ARG, "tile_cols must be 0 or a power of two <= 64");
   if (p->tile_threads != 0 && p->tile_threads != 256 && p->tile_threads != 512 && p->tile_threads != 1024)
     return fail(MQO_ERR_INVALID_ARG, "tile_threads must be 0, 256, 512 or 1024");
+  if (p->tile_vec != 0 && p->tile_vec != 1 && p->tile_vec != 2 && p->tile_vec != 4)
+    return fail(MQO_ERR_INVALID_ARG, "tile_vec must be 0, 1, 2 or 4");
+  if (p->tile_csr < 0 || p->tile_csr > 2) return fail(MQO_ERR_INVALID_ARG, "tile_csr must be 0, 1 or 2");
+  if (p->tile_reg < 0 || p->tile_reg > 2) return fail(MQO_ERR_INVALID_ARG, "tile_reg must be 0, 1 or 2");
   if (p->time_budget_s < 0.0) return fail(MQO_ERR_INVALID_ARG, "time_budget_s must be >= 0");
   return MQO_OK;
 }
@@ -258,6 +268,7 @@ struct Solve {
   int32_t B, G;
   int64_t n_max;
   std::vector<int64_t> nnz_g;
+  int32_t max_deg = 0;  // largest degree of any vertex in the batch
   void *ws;
   Layout L;
   hipStream_t s;
@@ -505,15 +516,30 @@ int solve_plain(Solve &S, int32_t *rounds_done) {
 // persistent tile plan + autotuner
 // ---------------------------------------------------------------------------
 int tile_lds_budget() {
-  const int static_lds = 4 * 64 * 4 + 3 * 64 * 8 + 64 * 4 + 2 * 4 + 256;
+  const int static_lds = 4 * 64 * 4 + 2 * 64 * 8 + 64 * 4 + 2 * 4 + 256;
   return std::min(res().lds_limit, 160 * 1024) - static_lds;
 }
 
-bool tile_feasible(int64_t n_max, int T, int threads) {
-  return tile_shape_ok(n_max, T, threads) && (int64_t)tile_lds_bytes(n_max, T) <= tile_lds_budget();
+int64_t nnz_max_of(const Solve &S) {
+  int64_t m = 0;
+  for (int64_t x : S.nnz_g) m = std::max(m, x);
+  return m;
 }
 
-TileArgs tile_args(Solve &S, int T, const float *x0) {
+bool tile_feasible(const Solve &S, const TileCfg &c) {
+  return tile_shape_ok(S.n_max, c.T, c.threads, c.vec, c.csr != 0, c.dreg, c.ipt) &&
+         (int64_t)tile_lds_bytes(S.n_max, c.T, nnz_max_of(S), c.csr != 0) <= tile_lds_budget();
+}
+
+// any shape at all fits (plan selection)
+bool tile_possible(const Solve &S) {
+  for (int T = 1; T <= 64; T <<= 1)
+    for (int th : {256, 512, 1024})
+      if (tile_feasible(S, TileCfg{T, th, 1, 0, 0, 0})) return true;
+  return false;
+}
+
+TileArgs tile_args(Solve &S, const TileCfg &c, const float *x0) {
   TileArgs a{};
   a.row_ptr = S.g->row_ptr;
   a.col_idx = S.g->col_idx;
@@ -521,11 +547,16 @@ TileArgs tile_args(Solve &S, int T, const float *x0) {
   a.vtx_off = at<int64_t>(S.ws, S.L.voff);
   a.G = S.G;
   a.B = S.B;
-  a.T = T;
+  a.T = c.T;
   a.log2T = 0;
-  while ((1 << a.log2T) < T) ++a.log2T;
-  a.tiles = (S.B + T - 1) / T;
+  while ((1 << a.log2T) < c.T) ++a.log2T;
+  a.tiles = (S.B + c.T - 1) / c.T;
   a.n_max = (int32_t)S.n_max;
+  a.nnz_max = (int32_t)nnz_max_of(S);
+  a.vec = c.vec;
+  a.csr_lds = c.csr;
+  a.dreg = c.dreg;
+  a.ipt = c.ipt;
   a.steps = S.p->steps_per_round;
   a.reset_mode = S.p->reset_mode;
   a.ls = S.p->local_search == MQO_LS_ONE_FLIP;
@@ -556,117 +587,129 @@ std::string tile_key(const Solve &S) {
   return buf;
 }
 
-int tune_tile(Solve &S, const float *x0, int *T_out, int *threads_out) {
+// Candidate shapes, honouring tile_cols / tile_threads when the caller fixed them.
+std::vector<TileCfg> tile_candidates(const Solve &S) {
+  int Tmax = 1;
+  while (Tmax < S.B && Tmax < 64) Tmax <<= 1;
+  std::vector<TileCfg> out;
+  for (int T = 1; T <= Tmax; T <<= 1) {
+    if (S.p->tile_cols && T != S.p->tile_cols) continue;
+    for (int th : {256, 512, 1024}) {
+      if (S.p->tile_threads && th != S.p->tile_threads) continue;
+      if (S.p->tile_reg != 1 && S.g->weight == nullptr && S.max_deg <= 16) {
+        // register adjacency: degree padded to 4, 8 or 16, 1, 2 or 4 rows per lane
+        const int dreg = S.max_deg <= 4 ? 4 : S.max_deg <= 8 ? 8 : 16;
+        const int64_t need = (S.n_max * T + th - 1) / th;
+        const int ipt = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 0;
+        const TileCfg c{T, th, 1, 0, dreg, ipt};
+        if (ipt && (!S.p->tile_vec || S.p->tile_vec == 1) && S.p->tile_csr != 2 && tile_feasible(S, c))
+          out.push_back(c);
+      }
+      if (S.p->tile_reg == 2) continue;
+      for (int vec : {1, 2, 4})
+        for (int csr : {1, 0}) {
+          if (S.p->tile_vec && vec != S.p->tile_vec) continue;
+          if (S.p->tile_csr && csr != S.p->tile_csr - 1) continue;
+          const TileCfg c{T, th, vec, csr, 0, 0};
+          if (tile_feasible(S, c)) out.push_back(c);
+        }
+    }
+  }
+  return out;
+}
+
+// Time one round of up to 32 steps per candidate; keep the fastest.  Every
+// candidate computes bit-identical results, so this only affects speed.
+int tune_tile(Solve &S, const float *x0, TileCfg *out) {
   Resources &R = res();
-  const std::string key = tile_key(S);
+  char fixed[64];
+  snprintf(fixed, sizeof(fixed), "|%d|%d|%d|%d|%d|%d", S.p->tile_cols, S.p->tile_threads, S.p->tile_vec,
+           S.p->tile_csr, S.p->tile_reg, S.max_deg);
+  const std::string key = tile_key(S) + fixed;
   {
     std::lock_guard<std::mutex> lk(R.mu);
     auto it = R.tile_tuning.find(key);
     if (it != R.tile_tuning.end()) {
-      *T_out = it->second.first;
-      *threads_out = it->second.second;
+      *out = it->second;
       return MQO_OK;
     }
   }
-  int Tmax = 1;
-  while (Tmax < S.B && Tmax < 64) Tmax <<= 1;
-  std::vector<std::pair<int, int>> cands;
-  for (int T = 1; T <= Tmax; T <<= 1)
-    for (int th : {256, 512, 1024})
-      if (tile_feasible(S.n_max, T, th)) cands.push_back({T, th});
-  if (cands.empty()) return fail(MQO_ERR_UNSUPPORTED, "graphs too large for the persistent plan");
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  double best_t = 1e30;
-  std::pair<int, int> best_c = cands[0];
-  const bool mc = S.maxcut, w = S.g->weight != nullptr, m = S.p->momentum != 0.0f;
-  for (auto c : cands) {
-    TileArgs a = tile_args(S, c.first, x0);
-    a.r0 = 0;
-    a.r1 = 1;
-    a.steps = std::min(S.p->steps_per_round, 32);
-    float ms = 0.f;
-    hipError_t e = launch_tile_round(mc, w, m, a, c.second, S.s);  // warm-up
-    if (e != hipSuccess) continue;
-    HIP_TRY(hipEventRecord(e0, S.s));
-    for (int rep = 0; rep < 2; ++rep) (void)launch_tile_round(mc, w, m, a, c.second, S.s);
-    HIP_TRY(hipEventRecord(e1, S.s));
-    HIP_TRY(hipEventSynchronize(e1));
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best_t) {
-      best_t = ms;
-      best_c = c;
+  const std::vector<TileCfg> cands = tile_candidates(S);
+  if (cands.empty()) return fail(MQO_ERR_UNSUPPORTED, "no persistent tile shape fits these graphs");
+  TileCfg best_c = cands[0];
+  if (cands.size() > 1) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    double best_t = 1e30;
+    const bool mc = S.maxcut, w = S.g->weight != nullptr;
+    for (const TileCfg &c : cands) {
+      // the shapes differ only in the step loop: time one round of up to 64
+      // steps without the local search (which depends on the start point)
+      TileArgs a = tile_args(S, c, x0);
+      a.r0 = 0;
+      a.r1 = 1;
+      a.steps = std::min(S.p->steps_per_round, 64);
+      a.ls = 0;
+      float ms = 0.f;
+      if (launch_tile_round(mc, w, a, c.threads, S.s) != hipSuccess) continue;  // warm-up
+      HIP_TRY(hipEventRecord(e0, S.s));
+      for (int rep = 0; rep < 2; ++rep) (void)launch_tile_round(mc, w, a, c.threads, S.s);
+      HIP_TRY(hipEventRecord(e1, S.s));
+      HIP_TRY(hipEventSynchronize(e1));
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_t) {
+        best_t = ms;
+        best_c = c;
+      }
     }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   {
     std::lock_guard<std::mutex> lk(R.mu);
     R.tile_tuning[key] = best_c;
   }
-  *T_out = best_c.first;
-  *threads_out = best_c.second;
+  *out = best_c;
   return MQO_OK;
 }
 
-int solve_tile(Solve &S, int32_t *rounds_done, int *T_used, int *th_used) {
+int solve_tile(Solve &S, int32_t *rounds_done, TileCfg *used) {
   const float *x0 = S.x0;
   if (!x0) {
     float *X = at<float>(S.ws, S.L.X);
     TRY(init_x(S, X));
     x0 = X;
   }
-  int T = S.p->tile_cols, th = S.p->tile_threads;
-  if (T == 0 || th == 0) {
-    int Tt = 0, tht = 0;
-    TRY(tune_tile(S, x0, &Tt, &tht));
-    if (T == 0) T = Tt;
-    if (th == 0) th = tht;
-  }
-  if (!tile_feasible(S.n_max, T, th))
-    return fail(MQO_ERR_UNSUPPORTED, "tile_cols=%d, tile_threads=%d do not fit graphs of %lld vertices", T, th,
-                (long long)S.n_max);
-  *T_used = T;
-  *th_used = th;
+  TileCfg cfg{};
+  TRY(tune_tile(S, x0, &cfg));
+  *used = cfg;
   launch_fill_i32(at<int32_t>(S.ws, S.L.err), 1, 0, S.s);
-  TileArgs a = tile_args(S, T, x0);
-  const bool mc = S.maxcut, w = S.g->weight != nullptr, m = S.p->momentum != 0.0f;
+  TileArgs a = tile_args(S, cfg, x0);
+  const bool mc = S.maxcut, w = S.g->weight != nullptr;
   const int nwg = S.G * a.tiles;
   std::vector<int32_t> lsi;
   int32_t r = 0;
-  if (S.p->time_budget_s <= 0.0) {
-    a.r0 = 0;
-    a.r1 = S.p->rounds;
+  const bool budget = S.p->time_budget_s > 0.0;
+  const double t0 = now_s();
+  // without a time budget the whole solve is one launch; with one, a launch per round
+  for (r = 0; r < S.p->rounds;) {
+    if (r > 0) {
+      HIP_TRY(hipStreamSynchronize(S.s));
+      if (now_s() - t0 >= S.p->time_budget_s) break;
+    }
+    a.r0 = r;
+    a.r1 = budget ? r + 1 : S.p->rounds;
     hipEvent_t e0;
     TRY(S.begin_timed(&e0));
-    hipError_t e = launch_tile_round(mc, w, m, a, th, S.s);
+    hipError_t e = launch_tile_round(mc, w, a, cfg.threads, S.s);
     if (e != hipSuccess) return fail(MQO_ERR_HIP, "tile launch: %s", hipGetErrorString(e));
     TRY(S.end_timed(e0));
-    r = S.p->rounds;
     TRY(read_back_i32(a.ls_iters, nwg, lsi, S.s));
     int64_t mx = 0;
     for (int32_t x : lsi) mx = std::max<int64_t>(mx, x);
     S.ls_iters += mx;
-  } else {
-    const double t0 = now_s();
-    for (r = 0; r < S.p->rounds; ++r) {
-      if (r > 0) {
-        HIP_TRY(hipStreamSynchronize(S.s));
-        if (now_s() - t0 >= S.p->time_budget_s) break;
-      }
-      a.r0 = r;
-      a.r1 = r + 1;
-      hipEvent_t e0;
-      TRY(S.begin_timed(&e0));
-      hipError_t e = launch_tile_round(mc, w, m, a, th, S.s);
-      if (e != hipSuccess) return fail(MQO_ERR_HIP, "tile launch: %s", hipGetErrorString(e));
-      TRY(S.end_timed(e0));
-      TRY(read_back_i32(a.ls_iters, nwg, lsi, S.s));
-      int64_t mx = 0;
-      for (int32_t x : lsi) mx = std::max<int64_t>(mx, x);
-      S.ls_iters += mx;
-    }
+    r = a.r1;
   }
   std::vector<int32_t> err;
   TRY(read_back_i32(at<int32_t>(S.ws, S.L.err), 1, err, S.s));
@@ -709,18 +752,20 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
   TRY(read_back_i32(at<int32_t>(ws, L.rpat), S.G + 1, rp, s));
   S.nnz_g.resize(S.G);
   for (int32_t i = 0; i < S.G; ++i) S.nnz_g[i] = rp[i + 1] - rp[i];
+  {
+    int32_t *dm = at<int32_t>(ws, L.dmax);
+    launch_degree_max(g->row_ptr, g->n_total, dm, s);
+    std::vector<int32_t> d;
+    TRY(read_back_i32(dm, 1, d, s));
+    S.max_deg = d[0];
+  }
 
   int plan = p->plan;
-  if (plan == MQO_PLAN_AUTO) {
-    bool fits = false;
-    for (int T = 1; T <= 64 && !fits; T <<= 1)
-      for (int th : {256, 512, 1024}) fits = fits || tile_feasible(S.n_max, T, th);
-    plan = fits ? MQO_PLAN_PERSISTENT : MQO_PLAN_BATCHED;
-  }
+  if (plan == MQO_PLAN_AUTO) plan = tile_possible(S) ? MQO_PLAN_PERSISTENT : MQO_PLAN_BATCHED;
   int32_t rounds_done = 0;
-  int T_used = 0, th_used = 0;
+  TileCfg used{0, 0, 0, 0, 0, 0};
   if (plan == MQO_PLAN_PERSISTENT)
-    TRY(solve_tile(S, &rounds_done, &T_used, &th_used));
+    TRY(solve_tile(S, &rounds_done, &used));
   else if (plan == MQO_PLAN_BATCHED)
     TRY(solve_batched(S, &rounds_done));
   else
@@ -742,8 +787,11 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
   r->steps_executed = (int64_t)rounds_done * p->steps_per_round;
   r->edge_updates = nnz_sum * S.B * r->steps_executed;
   r->plan_used = plan;
-  r->tile_cols_used = T_used;
-  r->tile_threads_used = th_used;
+  r->tile_cols_used = used.T;
+  r->tile_threads_used = used.threads;
+  r->tile_vec_used = used.vec;
+  r->tile_csr_lds_used = used.csr;
+  r->tile_reg_degree_used = used.dreg;
   r->ls_iterations = S.ls_iters;
   r->step_kernel_ms = S.timed_ms();
   r->step_kernel_launches = (int64_t)S.timed.size();

@@ -116,6 +116,42 @@ __device__ __forceinline__ bool key_beats(int32_t k1a, uint32_t pa, int64_t va, 
   return va < vb;
 }
 
+// Executed by one whole wavefront (64 lanes, threadIdx.x & 63 = lane):
+// hist[0..255] counts keys per digit; finds the digit bin holding the
+// krem-th smallest key (1-based, krem <= total), the count of keys in the
+// bins before it and the count in it.  Lane l owns bins 4l .. 4l+3.
+__device__ __forceinline__ void wave_select_digit(const uint32_t *hist, uint32_t krem, uint32_t &digit,
+                                                  uint32_t &before, uint32_t &at) {
+  const int lane = threadIdx.x & 63;
+  uint32_t h[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) h[i] = hist[lane * 4 + i];
+  const uint32_t own = h[0] + h[1] + h[2] + h[3];
+  uint32_t incl = own;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += t;
+  }
+  const uint32_t excl = incl - own;
+  const unsigned long long mask = __ballot(excl < krem && krem <= incl);
+  const int src = mask ? __builtin_ctzll(mask) : 63;
+  // inside the lane: the one bin where the running count first reaches krem
+  uint32_t d = lane * 4 + 3, b = excl, a = h[3], run = excl;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (run < krem && krem <= run + h[i]) {
+      d = lane * 4 + i;
+      b = run;
+      a = h[i];
+    }
+    run += h[i];
+  }
+  digit = __shfl(d, src, 64);
+  before = __shfl(b, src, 64);
+  at = __shfl(a, src, 64);
+}
+
 // One graph of a batch as the kernels see it.
 struct GraphView {
   const int32_t *row_ptr;

@@ -409,44 +409,54 @@ __device__ __forceinline__ uint32_t reset_key(const uint32_t *keys, int64_t lo, 
   return philox_vertex(seed, PURPOSE_RESET, traj, round, (uint64_t)v);
 }
 
+// One block per (chunk of RESET_CHUNK rows, column): a 256-bin histogram of
+// the current digit in LDS, merged into the column's global histogram with
+// one atomic per non-empty bin.
+constexpr int64_t RESET_CHUNK = 16384;
+
 __global__ __launch_bounds__(256) void k_reset_hist(const SelState *__restrict__ st, uint32_t *__restrict__ hist,
                                                     const uint32_t *__restrict__ keys, int64_t lo, int64_t n,
-                                                    int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0,
-                                                    uint64_t round, int32_t pass) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nvb = (n + 7) >> 3;
-  if (idx >= nvb * ncols) return;
-  const int32_t c = (int32_t)(idx % ncols);
-  const int64_t vb = idx / ncols;
-  uint32_t r[8];
-  if (!keys) philox_block8(r, seed, PURPOSE_RESET, traj0 + c, round, (uint64_t)vb);
+                                                    int32_t ld, uint64_t seed, uint64_t traj0, uint64_t round,
+                                                    int32_t pass) {
+  __shared__ uint32_t sh[256];
+  const int32_t c = blockIdx.y;
+  sh[threadIdx.x] = 0u;
+  __syncthreads();
   const uint32_t prefix = st[c].prefix;
   const int hs = 32 - 8 * pass, ds = 24 - 8 * pass;
+  const int64_t v0 = (int64_t)blockIdx.x * RESET_CHUNK;
+  const int64_t v1 = min(n, v0 + RESET_CHUNK);
+  for (int64_t vb = (v0 >> 3) + threadIdx.x; vb * 8 < v1; vb += blockDim.x) {
+    uint32_t r[8];
+    if (!keys) philox_block8(r, seed, PURPOSE_RESET, traj0 + c, round, (uint64_t)vb);
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int64_t v = vb * 8 + i;
-    if (v >= n) break;
-    const uint32_t key = keys ? keys[(lo + v) * ld + c] : r[i];
-    if (pass == 0 || (key >> hs) == prefix) atomicAdd(&hist[c * 256 + ((key >> ds) & 255u)], 1u);
+    for (int i = 0; i < 8; ++i) {
+      const int64_t v = vb * 8 + i;
+      if (v >= v1) break;
+      const uint32_t key = keys ? keys[(lo + v) * ld + c] : r[i];
+      if (pass == 0 || (key >> hs) == prefix) atomicAdd(&sh[(key >> ds) & 255u], 1u);
+    }
   }
+  __syncthreads();
+  const uint32_t h = sh[threadIdx.x];
+  if (h) atomicAdd(&hist[c * 256 + threadIdx.x], h);
 }
 
-__global__ void k_reset_digit(SelState *st, uint32_t *hist, int32_t ncols) {
-  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
+// one wavefront per column: pick the digit bin holding the krem-th smallest
+// key, then clear the column's histogram for the next pass
+__global__ __launch_bounds__(64) void k_reset_digit(SelState *st, uint32_t *hist) {
+  const int32_t c = blockIdx.x;
   SelState s = st[c];
-  uint32_t cum = 0, d = 0, h = 0;
-  for (d = 0; d < 256; ++d) {
-    h = hist[c * 256 + d];
-    if (cum + h >= s.krem) break;
-    cum += h;
+  uint32_t d, before, at;
+  wave_select_digit(hist + c * 256, s.krem, d, before, at);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) hist[c * 256 + threadIdx.x * 4 + i] = 0u;
+  if (threadIdx.x == 0) {
+    s.prefix = (s.prefix << 8) | d;
+    s.krem -= before;
+    s.cnteq = at;
+    st[c] = s;
   }
-  if (d > 255) d = 255;  // unreachable when krem <= count
-  s.prefix = (s.prefix << 8) | d;
-  s.krem -= cum;
-  s.cnteq = h;
-  st[c] = s;
-  for (int i = 0; i < 256; ++i) hist[c * 256 + i] = 0u;
 }
 
 // Columns whose threshold key is shared by more vertices than remain to be
@@ -762,6 +772,11 @@ void launch_init_uniform(bool maxcut, float *X, int64_t lo, int64_t n, int32_t n
     MQO_LAUNCH(k_init_uniform<false>, dim3(blocks_for(count)), dim3(256), 0, s, X, lo, n, ncols, ld, seed, traj0);
 }
 
+void launch_degree_max(const int32_t *row_ptr, int64_t n, int32_t *out, hipStream_t s) {
+  MQO_LAUNCH(k_fill_i32, dim3(1), dim3(64), 0, s, out, (int64_t)1, 0);
+  MQO_LAUNCH(k_degree_max, dim3(blocks_for(n < 262144 ? n : 262144)), dim3(256), 0, s, row_ptr, (int64_t)0, n, out);
+}
+
 void launch_init_degree(bool maxcut, float *X, const int32_t *row_ptr, int32_t *dmax_scratch, int64_t lo, int64_t n,
                         int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0, float sigma, hipStream_t s) {
   MQO_LAUNCH(k_fill_i32, dim3(1), dim3(64), 0, s, dmax_scratch, (int64_t)1, 0);
@@ -924,10 +939,10 @@ void launch_reset(bool maxcut, const int8_t *Zb, int32_t ldb, const uint32_t *ke
   if (k > 0) {
     MQO_LAUNCH(k_reset_init, dim3(blocks_for((int64_t)ncols * 256)), dim3(256), 0, s, st, hist, ncols, (uint32_t)k,
                (uint32_t)n);
+    const dim3 hgrid((unsigned)((n + RESET_CHUNK - 1) / RESET_CHUNK), (unsigned)ncols);
     for (int pass = 0; pass < 4; ++pass) {
-      MQO_LAUNCH(k_reset_hist, dim3(blocks_for(cnt)), dim3(256), 0, s, st, hist, keys, lo, n, ncols, ld, seed, traj0,
-                 round, pass);
-      MQO_LAUNCH(k_reset_digit, dim3(blocks_for(ncols)), dim3(256), 0, s, st, hist, ncols);
+      MQO_LAUNCH(k_reset_hist, hgrid, dim3(256), 0, s, st, hist, keys, lo, n, ld, seed, traj0, round, pass);
+      MQO_LAUNCH(k_reset_digit, dim3(ncols), dim3(64), 0, s, st, hist);
     }
     MQO_LAUNCH(k_reset_ties, dim3(ncols), dim3(256), 0, s, st, keys, lo, n, ld, seed, traj0, round);
   }

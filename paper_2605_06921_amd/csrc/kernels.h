@@ -22,6 +22,7 @@ void launch_init_uniform(bool maxcut, float *X, int64_t lo, int64_t n, int32_t n
                          uint64_t traj0, hipStream_t s);
 void launch_init_degree(bool maxcut, float *X, const int32_t *row_ptr, int32_t *dmax_scratch, int64_t lo, int64_t n,
                         int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0, float sigma, hipStream_t s);
+void launch_degree_max(const int32_t *row_ptr, int64_t n, int32_t *out, hipStream_t s);
 void launch_pga_step(bool maxcut, const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols, int32_t ld,
                      StepCfg cfg, float alpha, float mu, float param, hipStream_t s);
 void launch_copy_f32(const float *a, float *b, int64_t count, hipStream_t s);
@@ -70,7 +71,12 @@ struct TileArgs {
   const int32_t *weight;
   const int64_t *vtx_off;  // device [G+1]
   int32_t G, B, T, log2T, tiles;
-  int32_t n_max;  // scratch stride (rows)
+  int32_t n_max;    // scratch stride (rows)
+  int32_t nnz_max;  // largest graph's stored entries
+  int32_t vec;      // trajectories per lane in the step loop (1, 2, 4)
+  int32_t csr_lds;  // stage the graph's columns in LDS (16-bit local ids)
+  int32_t dreg;     // > 0: neighbour offsets held in registers, padded to dreg
+  int32_t ipt;      // lane items per thread in the register-adjacency path
   int32_t steps, r0, r1, reset_mode, ls;
   float alpha, mu, param;
   double rho;
@@ -87,9 +93,8 @@ struct TileArgs {
   int32_t *err;
 };
 
-bool tile_shape_ok(int64_t n_max, int T, int threads);
-size_t tile_lds_bytes(int64_t n_max, int T);
-hipError_t launch_tile_round(bool maxcut, bool weighted, bool momentum, const TileArgs &a, int threads,
-                             hipStream_t s);
+bool tile_shape_ok(int64_t n_max, int T, int threads, int vec, bool csr_lds, int dreg, int ipt);
+size_t tile_lds_bytes(int64_t n_max, int T, int64_t nnz_max, bool csr_lds);
+hipError_t launch_tile_round(bool maxcut, bool weighted, const TileArgs &a, int threads, hipStream_t s);
 
 }  // namespace mqo

@@ -7,6 +7,11 @@
 // arrays and the momentum live in a private global scratch region of the
 // workgroup (L1/L2 resident).
 //
+// Step-loop shape (chosen by the autotuner): each lane owns VEC consecutive
+// trajectories of one row (LDS reads of 4*VEC bytes); with CSR_LDS the
+// graph's column indices are staged in LDS as 16-bit local ids so that a
+// step touches no global memory at all.
+//
 // Arithmetic per element is identical to the grid kernels (same operation
 // order), so every plan gives bit-identical trajectories.
 #include "common.h"
@@ -16,8 +21,38 @@ namespace mqo {
 
 constexpr int TILE_MAX_T = 64;
 
-template <bool MAXCUT, bool WEIGHTED, bool MOMENTUM>
-__global__ __launch_bounds__(1024) void k_tile_round(TileArgs a) {
+template <int VEC>
+__device__ __forceinline__ void lds_load(const float *p, float (&o)[VEC]) {
+  if constexpr (VEC == 1) {
+    o[0] = *p;
+  } else if constexpr (VEC == 2) {
+    const float2 t = *reinterpret_cast<const float2 *>(p);
+    o[0] = t.x;
+    o[1] = t.y;
+  } else {
+    const float4 t = *reinterpret_cast<const float4 *>(p);
+    o[0] = t.x;
+    o[1] = t.y;
+    o[2] = t.z;
+    o[3] = t.w;
+  }
+}
+
+template <int VEC>
+__device__ __forceinline__ void lds_store(float *p, const float (&o)[VEC]) {
+  if constexpr (VEC == 1) {
+    *p = o[0];
+  } else if constexpr (VEC == 2) {
+    *reinterpret_cast<float2 *>(p) = make_float2(o[0], o[1]);
+  } else {
+    *reinterpret_cast<float4 *>(p) = make_float4(o[0], o[1], o[2], o[3]);
+  }
+}
+
+template <bool MAXCUT, bool WEIGHTED, int VEC, bool CSR_LDS, int DREG, int IPT>
+// Four register rows per lane need more than the 128 VGPRs a 1024-thread
+// workgroup leaves, so that variant is built for at most 512 threads.
+__global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a) {
   extern __shared__ float smem[];
   __shared__ uint32_t s_prefix[TILE_MAX_T], s_krem[TILE_MAX_T], s_cnteq[TILE_MAX_T], s_tie[TILE_MAX_T];
   __shared__ unsigned long long s_acc[2][TILE_MAX_T];
@@ -25,6 +60,7 @@ __global__ __launch_bounds__(1024) void k_tile_round(TileArgs a) {
   __shared__ int32_t s_active[2];
 
   const int nthr = blockDim.x, tid = threadIdx.x;
+  const int wave = tid >> 6, nwaves = nthr >> 6;
   // XCD-aware placement: the dispatch slots of one XCD (blockIdx % 8) take
   // consecutive (graph, tile) pairs, so a graph's CSR stays in one L2.
   const int32_t nwg = a.G * a.tiles;
@@ -40,25 +76,57 @@ __global__ __launch_bounds__(1024) void k_tile_round(TileArgs a) {
   const int64_t traj0 = (int64_t)g * a.B + b0;
   const int64_t ldz = a.B;
   const int32_t ilo = (int32_t)lo;
+  const bool momentum = a.mu != 0.0f;
 
-  const int32_t rowsA = max(a.n_max, 256);
-  float *xa = smem;                                                       // [rowsA][T], also the reset histogram
-  float *xb = smem + (size_t)rowsA * T;                                   // [n_max][T]
-  int32_t *rps = reinterpret_cast<int32_t *>(xb + (size_t)a.n_max * T);  // [n+1] row_ptr of the graph
+  // both iterate buffers have rowsX rows; the last row stays 0 (padding
+  // target of the register adjacency), rows 0..255 of xa also hold the reset
+  // histogram
+  const int32_t rowsX = max(a.n_max, 256) + 1;
+  const int32_t zrow = rowsX - 1;
+  float *xa = smem;                                                     // [rowsX][T]
+  float *xb = smem + (size_t)rowsX * T;                                 // [rowsX][T]
+  int32_t *rps = reinterpret_cast<int32_t *>(xb + (size_t)rowsX * T);  // [n_max+1] row_ptr of the graph
+  uint16_t *cls = reinterpret_cast<uint16_t *>(rps + a.n_max + 1);      // [nnz_max] local columns (CSR_LDS)
   const int64_t sbase = (int64_t)wid * a.n_max * T;
   int8_t *zs = a.zs + sbase;
   int32_t *nb = a.nb + sbase;
   uint32_t *prio = a.prio + sbase;  // also the reset keys
   int8_t *fl = a.fl + sbase;
-  float *vm = MOMENTUM ? a.vm + sbase : nullptr;
+  float *vm = a.vm + sbase;
   const int32_t *ci = a.col_idx;
   const int32_t *wt = a.weight;
 
-  for (int32_t v = tid; v <= n; v += nthr) rps[v] = a.row_ptr[lo + v];
-  const int32_t nnz_g = a.row_ptr[lo + n] - a.row_ptr[lo];
+  const int32_t e0 = a.row_ptr[lo];
+  for (int32_t v = tid; v <= n; v += nthr) rps[v] = a.row_ptr[lo + v] - e0;
+  const int32_t nnz_g = a.row_ptr[lo + n] - e0;
+  const int32_t *cig = ci + e0;  // the graph's columns, global ids
+  const int32_t *wtg = WEIGHTED ? wt + e0 : nullptr;
+  if (CSR_LDS)
+    for (int32_t j = tid; j < nnz_g; j += nthr) cls[j] = (uint16_t)(cig[j] - ilo);
   const int32_t k = (int32_t)floor(a.rho * (double)n);
   const int32_t ls_cap = 4 * (n + nnz_g) + 64;
   int32_t ls_total = 0;
+  for (int32_t c = tid; c < T; c += nthr) {
+    xa[zrow * T + c] = 0.0f;
+    xb[zrow * T + c] = 0.0f;
+  }
+  // register adjacency (DREG > 0, unweighted graphs of degree <= DREG): lane
+  // item i = row v, trajectory c keeps the LDS offsets of its neighbours in
+  // ascending CSR order, padded with the zero row; adding the padding zeros
+  // at the end of the sum leaves every result bit-identical
+  int32_t off[DREG > 0 ? IPT : 1][DREG > 0 ? DREG : 1];
+  float xr[DREG > 0 ? IPT : 1];  // the lane's own iterate entries, kept across steps
+  if constexpr (DREG > 0) {
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      const int32_t L = tid + i * nthr;
+      const int32_t v = L < nT ? L >> lt : 0, c = L & (T - 1);
+      const int32_t beg = L < nT ? a.row_ptr[lo + v] - e0 : 0, end = L < nT ? a.row_ptr[lo + v + 1] - e0 : 0;
+#pragma unroll
+      for (int kk = 0; kk < DREG; ++kk)
+        off[i][kk] = beg + kk < end ? ((cig[beg + kk] - ilo) << lt) | c : (zrow << lt) | c;
+    }
+  }
   __syncthreads();
 
   for (int32_t r = a.r0; r < a.r1; ++r) {
@@ -94,18 +162,14 @@ __global__ __launch_bounds__(1024) void k_tile_round(TileArgs a) {
             }
           }
           __syncthreads();
-          if (tid < cols) {
-            uint32_t cum = 0, d = 0, hv = 0;
-            const uint32_t kr = s_krem[tid];
-            for (d = 0; d < 256; ++d) {
-              hv = hist[tid * 256 + d];
-              if (cum + hv >= kr) break;
-              cum += hv;
+          for (int32_t c = wave; c < cols; c += nwaves) {  // one wavefront per column
+            uint32_t d, before, at;
+            wave_select_digit(hist + c * 256, s_krem[c], d, before, at);
+            if ((tid & 63) == 0) {
+              s_prefix[c] = (s_prefix[c] << 8) | d;
+              s_krem[c] -= before;
+              s_cnteq[c] = at;
             }
-            if (d > 255) d = 255;
-            s_prefix[tid] = (s_prefix[tid] << 8) | d;
-            s_krem[tid] = kr - cum;
-            s_cnteq[tid] = hv;
           }
           __syncthreads();
         }
@@ -139,39 +203,89 @@ __global__ __launch_bounds__(1024) void k_tile_round(TileArgs a) {
         xa[L] = x;
       }
     }
-    if (MOMENTUM)
+    if (momentum)
       for (int32_t L = tid; L < nT; L += nthr) vm[L] = 0.0f;
     __syncthreads();
 
     // ------------------------------------------------------------ PGA steps
+    const int32_t nI = nT / VEC;  // lane items: VEC consecutive trajectories of one row
     for (int32_t st = 0; st < a.steps; ++st) {
       const float *src = (st & 1) ? xb : xa;
       float *dst = (st & 1) ? xa : xb;
-      for (int32_t L = tid; L < nT; L += nthr) {
-        const int32_t v = L >> lt, c = L & (T - 1);
-        const int32_t beg = rps[v], end = rps[v + 1];
-        float acc = 0.0f;
-#pragma unroll 4
-        for (int32_t j = beg; j < end; ++j) {
-          const int32_t u = ci[j] - ilo;
-          const float xu = src[(u << lt) | c];
-          if (WEIGHTED) {
-            const float p = (float)wt[j] * xu;
-            acc = acc + p;
-          } else {
-            acc = acc + xu;
+      if constexpr (DREG > 0) {
+        // all neighbour reads of all the lane's rows are independent LDS loads
+        if (st == 0) {
+#pragma unroll
+          for (int i = 0; i < IPT; ++i) {
+            const int32_t L = tid + i * nthr;
+            xr[i] = L < nT ? src[L] : 0.0f;
           }
         }
-        const float gr = grad_from_sum<MAXCUT>(acc, a.param);
-        float d = gr;
-        if (MOMENTUM) {
-          const float t = a.mu * vm[L];
-          d = t + gr;
-          vm[L] = d;
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+          const int32_t L = tid + i * nthr;
+          if (L < nT) {
+            float acc = 0.0f;
+            // unconditional reads (padding hits the zero row as a broadcast)
+            // so that all of them issue back to back
+#pragma unroll
+            for (int kk = 0; kk < DREG; ++kk) acc = acc + src[off[i][kk]];
+            const float gr = grad_from_sum<MAXCUT>(acc, a.param);
+            float d = gr;
+            if (momentum) {
+              const float t = a.mu * vm[L];
+              d = t + gr;
+              vm[L] = d;
+            }
+            const float s = a.alpha * d;
+            const float y = xr[i] + s;
+            xr[i] = clip_box<MAXCUT>(y);
+            dst[L] = xr[i];
+          }
         }
-        const float s = a.alpha * d;
-        const float y = src[L] + s;
-        dst[L] = clip_box<MAXCUT>(y);
+        __syncthreads();
+        continue;
+      }
+      for (int32_t I = tid; I < nI; I += nthr) {
+        const int32_t L0 = I * VEC;
+        const int32_t v = L0 >> lt, c0 = L0 & (T - 1);
+        const int32_t beg = rps[v], end = rps[v + 1];
+        float acc[VEC];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
+#pragma unroll 4
+        for (int32_t j = beg; j < end; ++j) {
+          const int32_t u = CSR_LDS ? (int32_t)cls[j] : cig[j] - ilo;
+          float xu[VEC];
+          lds_load<VEC>(src + ((u << lt) | c0), xu);
+          if (WEIGHTED) {
+            const float w = (float)wtg[j];
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) {
+              const float p = w * xu[i];
+              acc[i] = acc[i] + p;
+            }
+          } else {
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + xu[i];
+          }
+        }
+        float x[VEC];
+        lds_load<VEC>(src + L0, x);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+          const float gr = grad_from_sum<MAXCUT>(acc[i], a.param);
+          float d = gr;
+          if (momentum) {
+            const float t = a.mu * vm[L0 + i];
+            d = t + gr;
+            vm[L0 + i] = d;
+          }
+          const float s = a.alpha * d;
+          const float y = x[i] + s;
+          x[i] = clip_box<MAXCUT>(y);
+        }
+        lds_store<VEC>(dst + L0, x);
       }
       __syncthreads();
     }
@@ -184,9 +298,9 @@ __global__ __launch_bounds__(1024) void k_tile_round(TileArgs a) {
       const int32_t v = L >> lt, c = L & (T - 1);
       int32_t s = 0;
       for (int32_t j = rps[v]; j < rps[v + 1]; ++j) {
-        const int32_t u = ci[j] - ilo;
+        const int32_t u = CSR_LDS ? (int32_t)cls[j] : cig[j] - ilo;
         const int32_t zu = zs[(u << lt) | c];
-        s += WEIGHTED ? wt[j] * zu : zu;
+        s += WEIGHTED ? wtg[j] * zu : zu;
       }
       nb[L] = s;
     }
@@ -210,7 +324,7 @@ __global__ __launch_bounds__(1024) void k_tile_round(TileArgs a) {
             const uint32_t pv = prio[L];
             f = 1;
             for (int32_t j = rps[v]; j < rps[v + 1]; ++j) {
-              const int32_t u = ci[j] - ilo;
+              const int32_t u = CSR_LDS ? (int32_t)cls[j] : cig[j] - ilo;
               const int32_t Lu = (u << lt) | c;
               int32_t k1u;
               if (ls_candidate_t<MAXCUT>(zs[Lu], nb[Lu], k1u) && key_beats(k1u, prio[Lu], u, k1, pv, v)) {
@@ -236,8 +350,8 @@ __global__ __launch_bounds__(1024) void k_tile_round(TileArgs a) {
             zs[L] = (int8_t)zn;
             const int32_t dz = zn - z;
             for (int32_t j = rps[v]; j < rps[v + 1]; ++j) {
-              const int32_t u = ci[j] - ilo;
-              atomicAdd(&nb[(u << lt) | c], WEIGHTED ? dz * wt[j] : dz);
+              const int32_t u = CSR_LDS ? (int32_t)cls[j] : cig[j] - ilo;
+              atomicAdd(&nb[(u << lt) | c], WEIGHTED ? dz * wtg[j] : dz);
             }
           }
         }
@@ -258,7 +372,7 @@ __global__ __launch_bounds__(1024) void k_tile_round(TileArgs a) {
           int32_t wsum = rps[v + 1] - rps[v];
           if (WEIGHTED) {
             wsum = 0;
-            for (int32_t j = rps[v]; j < rps[v + 1]; ++j) wsum += wt[j];
+            for (int32_t j = rps[v]; j < rps[v + 1]; ++j) wsum += wtg[j];
           }
           const long long a0 = (long long)wsum - (long long)z * s;
           if (a0) atomicAdd(&s_acc[0][c], (unsigned long long)a0);
@@ -290,20 +404,32 @@ __global__ __launch_bounds__(1024) void k_tile_round(TileArgs a) {
   if (tid == 0) a.ls_iters[wid] = ls_total;
 }
 
-bool tile_shape_ok(int64_t n_max, int T, int threads) {
-  return T >= 1 && T <= TILE_MAX_T && (T & (T - 1)) == 0 && (threads == 256 || threads == 512 || threads == 1024) &&
-         n_max >= 1 && n_max * T < (1LL << 30);
+bool tile_shape_ok(int64_t n_max, int T, int threads, int vec, bool csr_lds, int dreg, int ipt) {
+  if (!(T >= 1 && T <= TILE_MAX_T && (T & (T - 1)) == 0 && (threads == 256 || threads == 512 || threads == 1024) &&
+        n_max >= 1 && n_max * T < (1LL << 30) && (vec == 1 || vec == 2 || vec == 4) && vec <= T &&
+        (!csr_lds || n_max <= 65536)))
+    return false;
+  if (dreg == 0) return true;
+  // register adjacency: one trajectory per lane item, at most ipt items per
+  // lane; the shapes below fit the 128-VGPR budget of 1024-thread workgroups
+  // without spilling
+  const bool fits_regs = (dreg == 4 && ipt <= 2) || (dreg == 8 && ipt <= 2) || (dreg == 16 && ipt == 1) ||
+                         (dreg <= 8 && ipt == 4 && threads <= 512);
+  return fits_regs && (ipt == 1 || ipt == 2 || ipt == 4) && vec == 1 && !csr_lds &&
+         n_max * T <= (int64_t)ipt * threads;
 }
 
-size_t tile_lds_bytes(int64_t n_max, int T) {
-  const int64_t rowsA = n_max > 256 ? n_max : 256;
-  return (size_t)(rowsA + n_max) * T * sizeof(float) + (size_t)(n_max + 1) * sizeof(int32_t);
+size_t tile_lds_bytes(int64_t n_max, int T, int64_t nnz_max, bool csr_lds) {
+  const int64_t rowsX = (n_max > 256 ? n_max : 256) + 1;
+  size_t b = (size_t)(2 * rowsX) * T * sizeof(float) + (size_t)(n_max + 1) * sizeof(int32_t);
+  if (csr_lds) b += (size_t)nnz_max * sizeof(uint16_t);
+  return (b + 15) & ~(size_t)15;
 }
 
-template <bool MC, bool W, bool M>
+template <bool MC, bool W, int VEC, bool CL, int DREG, int IPT>
 static hipError_t tile_launch_t(const TileArgs &a, int threads, hipStream_t s) {
-  const size_t lds = tile_lds_bytes(a.n_max, a.T);
-  auto kern = k_tile_round<MC, W, M>;
+  const size_t lds = tile_lds_bytes(a.n_max, a.T, a.nnz_max, CL);
+  auto kern = k_tile_round<MC, W, VEC, CL, DREG, IPT>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -311,15 +437,41 @@ static hipError_t tile_launch_t(const TileArgs &a, int threads, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_tile_round(bool maxcut, bool weighted, bool momentum, const TileArgs &a, int threads,
-                             hipStream_t s) {
-  if (!tile_shape_ok(a.n_max, a.T, threads)) return hipErrorInvalidValue;
-  if (maxcut) {
-    if (weighted)
-      return momentum ? tile_launch_t<true, true, true>(a, threads, s) : tile_launch_t<true, true, false>(a, threads, s);
-    return momentum ? tile_launch_t<true, false, true>(a, threads, s) : tile_launch_t<true, false, false>(a, threads, s);
+template <bool MC, int DREG>
+static hipError_t tile_launch_reg(const TileArgs &a, int threads, hipStream_t s) {
+  if (DREG == 16 || a.ipt == 1) return tile_launch_t<MC, false, 1, false, DREG, 1>(a, threads, s);
+  if (a.ipt == 2) return tile_launch_t<MC, false, 1, false, DREG, DREG == 16 ? 1 : 2>(a, threads, s);
+  return tile_launch_t<MC, false, 1, false, DREG, DREG == 16 ? 1 : 4>(a, threads, s);
+}
+
+template <bool MC, bool W>
+static hipError_t tile_launch_mw(const TileArgs &a, int threads, hipStream_t s) {
+  if (!W && a.dreg > 0) {
+    switch (a.dreg) {
+      case 4: return tile_launch_reg<MC, 4>(a, threads, s);
+      case 8: return tile_launch_reg<MC, 8>(a, threads, s);
+      default: return tile_launch_reg<MC, 16>(a, threads, s);
+    }
   }
-  return momentum ? tile_launch_t<false, false, true>(a, threads, s) : tile_launch_t<false, false, false>(a, threads, s);
+  if (a.csr_lds) {
+    switch (a.vec) {
+      case 4: return tile_launch_t<MC, W, 4, true, 0, 1>(a, threads, s);
+      case 2: return tile_launch_t<MC, W, 2, true, 0, 1>(a, threads, s);
+      default: return tile_launch_t<MC, W, 1, true, 0, 1>(a, threads, s);
+    }
+  }
+  switch (a.vec) {
+    case 4: return tile_launch_t<MC, W, 4, false, 0, 1>(a, threads, s);
+    case 2: return tile_launch_t<MC, W, 2, false, 0, 1>(a, threads, s);
+    default: return tile_launch_t<MC, W, 1, false, 0, 1>(a, threads, s);
+  }
+}
+
+hipError_t launch_tile_round(bool maxcut, bool weighted, const TileArgs &a, int threads, hipStream_t s) {
+  if (!tile_shape_ok(a.n_max, a.T, threads, a.vec, a.csr_lds != 0, a.dreg, a.ipt)) return hipErrorInvalidValue;
+  if (weighted && a.dreg > 0) return hipErrorInvalidValue;
+  if (maxcut) return weighted ? tile_launch_mw<true, true>(a, threads, s) : tile_launch_mw<true, false>(a, threads, s);
+  return tile_launch_mw<false, false>(a, threads, s);
 }
 
 }  // namespace mqo

@@ -42,7 +42,8 @@ class _Params(ctypes.Structure):
                 ("momentum", ctypes.c_float), ("gamma", ctypes.c_float), ("lam", ctypes.c_float),
                 ("rho", ctypes.c_double), ("init_sigma", ctypes.c_float), ("init_mode", ctypes.c_int32),
                 ("reset_mode", ctypes.c_int32), ("local_search", ctypes.c_int32), ("plan", ctypes.c_int32),
-                ("tile_cols", ctypes.c_int32), ("tile_threads", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("tile_cols", ctypes.c_int32), ("tile_threads", ctypes.c_int32), ("tile_vec", ctypes.c_int32),
+                ("tile_csr", ctypes.c_int32), ("tile_reg", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("time_budget_s", ctypes.c_double)]
 
 
@@ -51,7 +52,9 @@ class _Result(ctypes.Structure):
                 ("traj_best_x", ctypes.c_void_p), ("edge_updates", ctypes.c_int64),
                 ("steps_executed", ctypes.c_int64), ("rounds_executed", ctypes.c_int32),
                 ("plan_used", ctypes.c_int32), ("tile_cols_used", ctypes.c_int32),
-                ("tile_threads_used", ctypes.c_int32), ("ls_iterations", ctypes.c_int64),
+                ("tile_threads_used", ctypes.c_int32), ("tile_vec_used", ctypes.c_int32),
+                ("tile_csr_lds_used", ctypes.c_int32), ("tile_reg_degree_used", ctypes.c_int32),
+                ("ls_iterations", ctypes.c_int64),
                 ("step_kernel_ms", ctypes.c_double), ("step_kernel_launches", ctypes.c_int64)]
 
 
@@ -174,7 +177,8 @@ def last_error() -> str:
 
 def make_params(batch=1, steps_per_round=200, rounds=1, alpha=0.01, momentum=0.0, gamma=2.0, lam=1e-3,
                 rho=0.05, init_sigma=0.0, init_mode="uniform", reset_mode="zero", local_search=True,
-                plan="auto", seed=0, time_budget_s=0.0, tile_cols=0, tile_threads=0, check_every=0) -> _Params:
+                plan="auto", seed=0, time_budget_s=0.0, tile_cols=0, tile_threads=0, tile_vec=0, tile_csr=0,
+                tile_reg=0, check_every=0) -> _Params:
     p = _Params()
     _lib.mqo_params_default(ctypes.byref(p))
     p.batch, p.steps_per_round, p.rounds, p.check_every = batch, steps_per_round, rounds, check_every
@@ -183,7 +187,8 @@ def make_params(batch=1, steps_per_round=200, rounds=1, alpha=0.01, momentum=0.0
     p.init_mode, p.reset_mode = INIT[init_mode], RESET[reset_mode]
     p.local_search = 1 if local_search else 0
     p.plan = PLANS[plan]
-    p.tile_cols, p.tile_threads = tile_cols, tile_threads
+    p.tile_cols, p.tile_threads, p.tile_vec, p.tile_csr = tile_cols, tile_threads, tile_vec, tile_csr
+    p.tile_reg = tile_reg
     p.seed, p.time_budget_s = seed, time_budget_s
     return p
 
@@ -238,13 +243,15 @@ def solve(kind, dg: DeviceGraph, x0: Optional[torch.Tensor] = None, workspace: O
             raise ValueError("x0 must be a float32 [n_total * B] tensor on the graph's device")
         x0 = x0.contiguous()
     r = _Result(best_x.data_ptr(), best_value.data_ptr(), None if traj_v is None else traj_v.data_ptr(),
-                None if traj_x is None else traj_x.data_ptr(), 0, 0, 0, 0, 0, 0, 0, 0.0, 0)
+                None if traj_x is None else traj_x.data_ptr())
     fn = _lib.mqo_solve_mis if k == MIS else _lib.mqo_solve_maxcut
     _check(fn(dg.struct, ctypes.byref(p), _ptr(x0), ctypes.byref(r), ctypes.c_void_p(ws.data_ptr()), nbytes,
               _stream(dev)), "mqo_solve")
     out = dict(best_x=best_x, best_value=best_value, edge_updates=r.edge_updates, steps_executed=r.steps_executed,
                rounds_executed=r.rounds_executed, plan=PLAN_NAMES[r.plan_used], tile_cols=r.tile_cols_used,
-               tile_threads=r.tile_threads_used, ls_iterations=r.ls_iterations,
+               tile_threads=r.tile_threads_used, tile_vec=r.tile_vec_used, tile_csr_lds=r.tile_csr_lds_used,
+               tile_reg_degree=r.tile_reg_degree_used,
+               ls_iterations=r.ls_iterations,
                step_kernel_ms=r.step_kernel_ms, step_kernel_launches=r.step_kernel_launches)
     if want_traj:
         out["traj_best_value"] = traj_v

@@ -236,13 +236,18 @@ def test_solve_bit_exact_every_plan(mqo, ci, plan):
 
 @pytest.mark.parametrize("T", [1, 2, 4, 8, 16, 32, 64])
 @pytest.mark.parametrize("threads", [256, 1024])
-def test_persistent_tile_shapes_agree(mqo, T, threads):
-    kind, g = CASES["reg3"]
-    kw = dict(batch=37, steps_per_round=30, rounds=3, alpha=0.01, rho=0.05, seed=3)
+@pytest.mark.parametrize("vec", [1, 2, 4])
+@pytest.mark.parametrize("csr", [1, 2])
+@pytest.mark.parametrize("name", ["reg3", "torus"])
+def test_persistent_tile_shapes_agree(mqo, name, T, threads, vec, csr):
+    if vec > T:
+        pytest.skip("a lane cannot own more trajectories than the tile has")
+    kind, g = CASES[name]
+    kw = dict(batch=37, steps_per_round=30, rounds=3, alpha=0.01, rho=0.05, seed=3, momentum=0.3)
     dg = mqo.DeviceGraph(g, DEV)
     ref = mqo.solve(kind, dg, plan="batched", **kw)
-    out = mqo.solve(kind, dg, plan="persistent", tile_cols=T, tile_threads=threads, **kw)
-    assert out["tile_cols"] == T and out["tile_threads"] == threads
+    out = mqo.solve(kind, dg, plan="persistent", tile_cols=T, tile_threads=threads, tile_vec=vec, tile_csr=csr, **kw)
+    assert (out["tile_cols"], out["tile_threads"], out["tile_vec"], out["tile_csr_lds"]) == (T, threads, vec, csr - 1)
     assert torch.equal(out["traj_best_value"], ref["traj_best_value"])
     assert torch.equal(out["traj_best_x"], ref["traj_best_x"])
 

@@ -1,0 +1,200 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times: whole solves compared with the oracle on sampled
+trajectories (trajectories are independent chains), single steps compared
+on sampled rows, discrete work compared on whole arrays or sampled
+columns."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from synth import graphs, arrays  # noqa: E402
+from synth.workloads import WORKLOADS  # noqa: E402
+from oracle import objectives as obj, pga, discrete, solver  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def mqo():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_06921_amd import mqo as m
+    return m
+
+
+_cache = {}
+
+
+def _graph(name):
+    if name not in _cache:
+        _cache[name] = WORKLOADS[name].make_graph()
+    return _cache[name]
+
+
+def _params(wl, cols=None):
+    return solver.Params(batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=wl.rounds, alpha=wl.alpha,
+                         seed=wl.seed, gamma=wl.gamma, lam=wl.lam, rho=wl.rho, reset_mode=wl.reset_mode,
+                         local_search=wl.local_search)
+
+
+def _solve_gpu(mqo, wl, g):
+    dg = mqo.DeviceGraph(g, DEV)
+    return mqo.solve(wl.problem, dg, batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=wl.rounds,
+                     alpha=wl.alpha, gamma=wl.gamma, lam=wl.lam, rho=wl.rho, reset_mode=wl.reset_mode,
+                     local_search=wl.local_search, seed=wl.seed)
+
+
+# --------------------------------------------------------------------------
+# reset over several 16384-row chunks
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("rho", [0.05, 0.3])
+def test_reset_multi_chunk(mqo, rho):
+    g = graphs.erdos_renyi(40000, 2e-4, 501)
+    dg = mqo.DeviceGraph(g, DEV)
+    Zb = arrays.binary01((g.n, 3), 502)
+    X = mqo.reset("mis", dg, torch.from_numpy(Zb).to(DEV), seed=9, rnd=6, rho=rho).cpu().numpy()
+    mask = discrete.reset_set(g.n, discrete.reset_count(rho, g.n), 9, np.arange(3), 6)
+    assert np.array_equal(X, discrete.reset_apply("mis", Zb, mask))
+
+
+def test_reset_multi_chunk_ties(mqo):
+    g = graphs.erdos_renyi(40000, 2e-4, 503)
+    dg = mqo.DeviceGraph(g, DEV)
+    keys = arrays.integers((g.n, 2), 0, 4, 504)
+    Zb = arrays.spins((g.n, 2), 505)
+    X = mqo.reset("maxcut", dg, torch.from_numpy(Zb).to(DEV), seed=0, rnd=2, rho=0.3, mode="flip",
+                  keys=torch.from_numpy(keys.astype(np.int32)).to(DEV)).cpu().numpy()
+    mask = discrete.reset_set(g.n, 12000, 0, np.arange(2), 2, keys=keys)
+    assert np.array_equal(X, discrete.reset_apply("maxcut", Zb, mask, "flip"))
+
+
+# --------------------------------------------------------------------------
+# whole solves at full size, sampled trajectories
+# --------------------------------------------------------------------------
+
+def test_reg3_maxcut_full_solve_sampled(mqo):
+    wl = WORKLOADS["reg3_maxcut"]
+    g = _graph("reg3_maxcut")
+    out = _solve_gpu(mqo, wl, g)
+    cols = [0, 101, 255]
+    vals, zb = solver.solve_graph(wl.problem, g, _params(wl), 0, cols=cols)
+    assert np.array_equal(out["traj_best_value"].cpu().numpy()[cols], vals)
+    assert np.array_equal(out["traj_best_x"].cpu().numpy()[:, cols], zb)
+    tv = out["traj_best_value"].cpu().numpy()
+    assert out["best_value"].item() == tv.max()
+    assert discrete.evaluate_cut(g, out["best_x"].cpu().numpy()[:, None])[0] == tv.max()
+
+
+def test_er_batch_full_solve_sampled(mqo):
+    wl = WORKLOADS["er_batch_mis"]
+    g = _graph("er_batch_mis")
+    out = _solve_gpu(mqo, wl, g)
+    tv = out["traj_best_value"].cpu().numpy()
+    tx = out["traj_best_x"].cpu().numpy()
+    for gi, cols in ((0, [0, 511]), (127, [300])):
+        sub = g.subgraph(gi)
+        lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+        vals, zb = solver.solve_graph(wl.problem, sub, _params(wl), gi, cols=cols)
+        assert np.array_equal(tv[gi * wl.batch + np.array(cols)], vals)
+        assert np.array_equal(tx[lo:hi][:, cols], zb)
+    # every incumbent is a maximal independent set of its graph
+    bx = out["best_x"].cpu().numpy()
+    for gi in range(0, 128, 17):
+        sub = g.subgraph(gi)
+        lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+        assert discrete.is_maximal_independent(sub, bx[lo:hi, None])[0]
+
+
+# --------------------------------------------------------------------------
+# million-vertex graphs: one step on sampled rows, evaluation, search, reset
+# --------------------------------------------------------------------------
+
+def _rows_step32(g, X, rows, kind, alpha, param):
+    """float32 replay of one step restricted to the given rows."""
+    out = np.empty((len(rows), X.shape[1]), dtype=np.float32)
+    for i, v in enumerate(rows):
+        acc = np.zeros(X.shape[1], dtype=np.float32)
+        for j in range(g.row_ptr[v], g.row_ptr[v + 1]):
+            u = g.col_idx[j]
+            if g.weight is None:
+                acc = acc + X[u]
+            else:
+                acc = acc + np.float32(g.weight[j]) * X[u]
+        gr = (np.float32(1.0) - np.float32(param) * acc) if kind == "mis" else \
+            (np.float32(-np.float32(param)) - np.float32(2.0) * acc)
+        y = X[v] + np.float32(alpha) * gr
+        lo, hi = obj.box(kind)
+        out[i] = np.minimum(np.maximum(y, np.float32(lo)), np.float32(hi))
+    return out
+
+
+@pytest.mark.parametrize("name", ["er1m_mis", "torus1m_maxcut"])
+def test_million_vertex_round_pieces(mqo, name):
+    wl = WORKLOADS[name]
+    g = _graph(name)
+    dg = mqo.DeviceGraph(g, DEV)
+    B = wl.batch
+    param = wl.gamma if wl.problem == "mis" else wl.lam
+    X0 = mqo.init_iterate(wl.problem, dg, B, seed=wl.seed)
+    x0 = X0.cpu().numpy()
+    rows = np.concatenate([np.arange(5), np.random.default_rng(1).integers(0, g.n, 300), [g.n - 1]])
+    assert np.array_equal(x0[rows], pga.init_uniform(wl.problem, g.n, np.arange(B), wl.seed)[rows])
+    X = X0.clone()
+    mqo.pga_steps(wl.problem, dg, X, 1, alpha=wl.alpha, gamma=wl.gamma, lam=wl.lam)
+    x1 = X.cpu().numpy()
+    assert np.array_equal(x1[rows], _rows_step32(g, x0, rows, wl.problem, wl.alpha, param))
+    # rounding and exact evaluation on the whole arrays
+    Z, value, conf, fixed = mqo.round_evaluate(wl.problem, dg, X)
+    Zr = discrete.round_x(wl.problem, x1)
+    assert np.array_equal(Z.cpu().numpy(), Zr)
+    assert np.array_equal(value.cpu().numpy(), discrete.value(wl.problem, g, Zr))
+    # local search on a sampled column (columns are independent)
+    cols = [17]
+    Zc = Z.clone()
+    mqo.local_search(wl.problem, dg, Zc, seed=wl.seed, rnd=3)
+    ref, _ = discrete.local_search(wl.problem, g, Zr[:, cols], wl.seed, np.array(cols), 3)
+    assert np.array_equal(Zc.cpu().numpy()[:, cols], ref)
+    # reset of the searched incumbents, sampled columns
+    Xr = mqo.reset(wl.problem, dg, Zc, seed=wl.seed, rnd=4, rho=wl.rho).cpu().numpy()
+    k = discrete.reset_count(wl.rho, g.n)
+    mask = discrete.reset_set(g.n, k, wl.seed, np.array(cols), 4)
+    assert np.array_equal(Xr[:, cols], discrete.reset_apply(wl.problem, Zc.cpu().numpy()[:, cols], mask))
+    assert np.all((Xr == 0).sum(0) >= k) if wl.problem == "mis" else np.all((Xr == 0).sum(0) == k)
+
+
+# --------------------------------------------------------------------------
+# differentiation at the 1e5-vertex shapes, batch 64
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["ba100k_mis", "reg5_100k_maxcut"])
+def test_differentiation_full_size(mqo, name):
+    wl = WORKLOADS[name]
+    g = _graph(name)
+    dg = mqo.DeviceGraph(g, DEV)
+    B = wl.batch
+    param = wl.gamma if wl.problem == "mis" else wl.lam
+    lo_b, hi_b = obj.box(wl.problem)
+    X0 = arrays.uniform((g.n, B), lo_b, hi_b, 601)
+    Xt = torch.from_numpy(X0).to(DEV)
+    f, grad = mqo.objective_grad(wl.problem, dg, Xt, param)
+    fr, gr = pga.objective_and_grad(g, wl.problem, param, X0.astype(np.float64))
+    assert np.abs(grad.cpu().numpy() - gr).max() / max(1.0, np.abs(gr).max()) <= 1e-5
+    assert np.allclose(f.cpu().numpy(), fr, rtol=1e-5)
+    # K = 20 unrolled steps, checkpoints every 5: forward bit-exact, adjoint on sampled columns
+    K, c = 20, 5
+    XK, ckpt = mqo.unrolled_forward(wl.problem, dg, Xt, wl.alpha, K, c, param)
+    cols = [0, 63]
+    xs = pga.unrolled_forward(g, wl.problem, param, wl.alpha, K, X0[:, cols], precision="fp32")
+    assert np.array_equal(XK.cpu().numpy()[:, cols], xs[K])
+    dL = obj.gradient(wl.problem, XK.cpu().numpy().astype(np.float64), obj.adjacency(g), param)
+    dX0, da = mqo.unrolled_backward(wl.problem, dg, ckpt, torch.from_numpy(dL.astype(np.float32)).to(DEV),
+                                    wl.alpha, K, c, param)
+    rX0, ra = pga.unrolled_backward(g, wl.problem, param, wl.alpha, K, X0[:, cols],
+                                    dL[:, cols].astype(np.float32).astype(np.float64), precision="fp32")
+    got = dX0.cpu().numpy()[:, cols]
+    assert np.abs(got - rX0).max() / max(1.0, np.abs(rX0).max()) <= 1e-4
+    assert np.allclose(da.cpu().numpy()[cols], ra, rtol=1e-4, atol=1e-4 * np.abs(ra).max())

@@ -1,0 +1,67 @@
+"""The persistent plan's register-adjacency step loop (unweighted graphs of
+degree <= 16) against the batched plan and the oracle, for every tile
+shape it supports."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from synth import graphs  # noqa: E402
+from oracle import solver  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def mqo():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_06921_amd import mqo as m
+    return m
+
+
+CASES = {
+    # degree 3 -> padded 4; degree <= 8; degree <= 16 over a ragged batch
+    "reg3": ("maxcut", graphs.random_regular(300, 3, 21)),
+    "reg7_mis": ("mis", graphs.random_regular(200, 7, 22)),
+    "er_batch": ("mis", graphs.concat([graphs.erdos_renyi(150, 0.05, 23), graphs.cycle(17),
+                                       graphs.erdos_renyi(90, 0.1, 24)])),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("T", [1, 2, 8, 64])
+@pytest.mark.parametrize("threads", [256, 1024])
+@pytest.mark.parametrize("momentum", [0.0, 0.4])
+def test_register_adjacency_agrees(mqo, name, T, threads, momentum):
+    kind, g = CASES[name]
+    if g.degrees().max() > 16:
+        pytest.skip("degree above the register path's limit")
+    B = 23
+    kw = dict(batch=B, steps_per_round=25, rounds=3, alpha=0.02, rho=0.1, seed=5, momentum=momentum)
+    dg = mqo.DeviceGraph(g, DEV)
+    dmax = g.degrees().max()
+    rows_per_lane = 1 if dmax > 8 else (4 if threads <= 512 else 2)
+    if max(np.diff(g.vtx_offset)) * T > rows_per_lane * threads:  # no register shape
+        with pytest.raises(mqo.MqoError):
+            mqo.solve(kind, dg, plan="persistent", tile_cols=T, tile_threads=threads, tile_reg=2, **kw)
+        return
+    out = mqo.solve(kind, dg, plan="persistent", tile_cols=T, tile_threads=threads, tile_reg=2, **kw)
+    assert out["tile_reg_degree"] in (4, 8, 16)
+    ref = mqo.solve(kind, dg, plan="batched", **kw)
+    assert torch.equal(out["traj_best_value"], ref["traj_best_value"])
+    assert torch.equal(out["traj_best_x"], ref["traj_best_x"])
+    if T == 8 and threads == 256:
+        o = solver.solve(kind, g, solver.Params(batch=B, steps_per_round=25, rounds=3, alpha=0.02, rho=0.1, seed=5,
+                                                mu=momentum))
+        assert np.array_equal(out["traj_best_value"].cpu().numpy(), o["traj_best_value"])
+        assert np.array_equal(out["traj_best_x"].cpu().numpy(), o["traj_best_x"])
+
+
+def test_register_adjacency_rejected_when_degree_too_high(mqo):
+    g = graphs.star(40)
+    dg = mqo.DeviceGraph(g, DEV)
+    with pytest.raises(mqo.MqoError):
+        mqo.solve("mis", dg, batch=4, steps_per_round=5, rounds=1, plan="persistent", tile_reg=2)
