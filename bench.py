@@ -28,6 +28,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12  # bytes/s, MI355X
+# LDS: 256 CUs x 128 bytes/clock x 2.4 GHz
+LDS_PEAK = 256 * 128 * 2.4e9
+KERNEL_SOURCES = {"k_tile_round": "paper_2605_06921_amd/csrc/tile_kernel.hip",
+                  "k_pga_step": "paper_2605_06921_amd/csrc/grid_kernels.hip"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def source_sha256(path):
+    import hashlib
+    with open(os.path.join(ROOT, path), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    calibrated FETCH_SIZE / WRITE_SIZE counter runs, or None when there is
+    no record or the kernel source changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = json.load(open(TRAFFIC_FILE)).get(workload, {}).get(kernel)
+    if not rec or rec.get("source_sha256") != source_sha256(KERNEL_SOURCES[kernel]):
+        return None
+    return rec["hbm_bytes_per_launch"]
 
 
 def log(msg):
@@ -83,6 +106,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (scale for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); trajectories are independent, "
@@ -94,6 +119,13 @@ def main():
     from paper_2605_06921_amd import mqo
 
     wl = WORKLOADS[args.workload]
+    if args.copy_calibration_mb:
+        a = torch.empty(args.copy_calibration_mb << 18, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.copy_calibration_mb} MiB done")
+        del a, b
     log(f"[bench] building graph {wl.name}")
     g = wl.make_graph()
     dev = torch.device("cuda:0")
@@ -135,10 +167,20 @@ def main():
     per_launch_bytes = step_bytes(g, wl.batch) * steps_per_launch
     avg_launch_s = kms / 1e3 / max(1, klaunch)
     achieved = per_launch_bytes / avg_launch_s
+    kernel = "k_tile_round" if out["plan"] == "persistent" else "k_pga_step"
+    traffic = measured_traffic(wl.name, kernel)
     res["roofline"] = dict(bound="hbm", achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
-                           frac=achieved / HBM_PEAK, traffic=None,
-                           kernel="k_tile_round" if out["plan"] == "persistent" else "k_pga_step",
-                           avg_launch_ms=avg_launch_s * 1e3, algorithmic_bytes_per_launch=per_launch_bytes)
+                           frac=achieved / HBM_PEAK, traffic=traffic, kernel=kernel,
+                           avg_launch_ms=avg_launch_s * 1e3, algorithmic_bytes_per_launch=per_launch_bytes,
+                           steps_per_launch=steps_per_launch)
+    if out["plan"] == "persistent":
+        # the iterate lives in LDS: per step every edge update gathers 4 bytes
+        # and every element is read and written once
+        lds_bytes = (4 * g.nnz * wl.batch + 8 * g.n * wl.batch) * steps_per_launch
+        res["roofline"]["note"] = ("HBM-equivalent: the persistent kernel keeps the iterate in LDS, so the "
+                                   "algorithmic bytes are what a streaming step would move, not its HBM traffic")
+        res["lds_roofline"] = dict(achieved=lds_bytes / avg_launch_s / 1e9, peak=LDS_PEAK / 1e9, unit="GB/s",
+                                   frac=lds_bytes / avg_launch_s / LDS_PEAK, bytes_per_launch=lds_bytes)
 
     if not args.no_plain:
         log("[bench] plain per-trajectory solve")

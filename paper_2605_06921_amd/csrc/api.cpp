@@ -816,7 +816,7 @@ int check_param(mqo_objective obj, float param) {
 
 size_t partial_count(const mqo_graph *g, int32_t B) {
   const StepCfg cfg = default_step_cfg(B, B);
-  return (size_t)grid_blocks_x(max_graph_rows(g), cfg) * B;
+  return (size_t)(grid_blocks_x(max_graph_rows(g), cfg) + REDUCE_SLICES) * B;
 }
 
 }  // namespace

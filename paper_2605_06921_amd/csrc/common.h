@@ -152,6 +152,14 @@ __device__ __forceinline__ void wave_select_digit(const uint32_t *hist, uint32_t
   at = __shfl(a, src, 64);
 }
 
+// Sum of v over the lanes of the wavefront that share lane % width (width a
+// power of two <= 64); the result is valid in lanes 0 .. width-1.  Every
+// lane must call it.
+__device__ __forceinline__ long long wave_sum_stride(long long v, int width) {
+  for (int off = 32; off >= width; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
 // One graph of a batch as the kernels see it.
 struct GraphView {
   const int32_t *row_ptr;
@@ -169,12 +177,22 @@ struct RowMap {
   bool active;
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8).  Renumber them so that each XCD gets one contiguous range of
+// logical blocks: neighbouring rows then share an XCD's L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t x = b & 7;
+  int64_t start = 0;
+  for (int64_t y = 0; y < x; ++y) start += (nb + 7 - y) >> 3;  // blocks of XCD y
+  return start + (b >> 3);
+}
+
 template <int VEC>
 __device__ __forceinline__ RowMap map_rows(int64_t nrows, int32_t ncols, int32_t lanes_log2) {
   RowMap m;
   const int32_t lanes = 1 << lanes_log2;
   const int32_t rows_per_block = blockDim.x >> lanes_log2;
-  m.row = (int64_t)blockIdx.x * rows_per_block + (threadIdx.x >> lanes_log2);
+  m.row = xcd_block(blockIdx.x, gridDim.x) * rows_per_block + (threadIdx.x >> lanes_log2);
   m.col = (int32_t)(blockIdx.y * lanes + (threadIdx.x & (lanes - 1))) * VEC;
   m.active = m.row < nrows && m.col < ncols;
   return m;

@@ -132,13 +132,50 @@ __device__ __forceinline__ void store_vec(float *p, const float (&o)[VEC]) {
   }
 }
 
-// acc[i] = sum over the row's neighbours, ascending CSR order, one rounding per add
+// acc[i] = sum over the row's neighbours, ascending CSR order, one rounding per add.
+// With 4 or more lanes per row the lanes load up to `lanes` column indices
+// (and weights) of the row in one coalesced load and pass them round with
+// shuffles, so the gathers do not wait on one index load each.
+// Every lane of a valid row must call it (the shuffles read the row's other
+// lanes); lanes whose column is past the batch pass colok = false and only
+// help with the index loads.
 template <int VEC, bool WEIGHTED>
 __device__ __forceinline__ void row_gather(const GraphView &g, const float *__restrict__ X, int64_t v, int32_t col,
-                                           int32_t ld, float (&acc)[VEC]) {
+                                           int32_t ld, int32_t lanes_log2, bool colok, float (&acc)[VEC]) {
 #pragma unroll
   for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
   const int32_t beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+  if (lanes_log2 >= 2) {
+    const int32_t lanes = 1 << lanes_log2;
+    const int32_t lane = threadIdx.x & (lanes - 1);
+    for (int32_t j0 = beg; j0 < end; j0 += lanes) {
+      const bool have = j0 + lane < end;
+      const int32_t myu = have ? g.col_idx[j0 + lane] : 0;
+      const int32_t myw = WEIGHTED ? (have ? g.weight[j0 + lane] : 0) : 1;
+      const int32_t cnt = min(lanes, end - j0);
+#pragma unroll 4
+      for (int32_t k = 0; k < cnt; ++k) {
+        const int64_t u = __shfl(myu, k, lanes);
+        const int32_t wk = WEIGHTED ? __shfl(myw, k, lanes) : 1;
+        if (!colok) continue;
+        float x[VEC];
+        load_vec<VEC>(X + u * ld + col, x);
+        if (WEIGHTED) {
+          const float w = (float)wk;
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) {
+            const float p = w * x[i];
+            acc[i] = acc[i] + p;
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + x[i];
+        }
+      }
+    }
+    return;
+  }
+  if (!colok) return;
 #pragma unroll 4
   for (int32_t j = beg; j < end; ++j) {
     const int64_t u = g.col_idx[j];
@@ -158,15 +195,92 @@ __device__ __forceinline__ void row_gather(const GraphView &g, const float *__re
   }
 }
 
+// Block-wide neighbour sums for the rows of this block; every thread of the
+// block must call it.  Rows of degree above max(32, 2 * lanes) (hubs, e.g. in
+// preferential-attachment graphs) would keep one lane group busy long after
+// the rest of the block: they are deferred, and for each of them the whole
+// block stages chunks of its neighbours' slices [col0, col0 + lanes*VEC) into
+// LDS, from which the row's own lane group adds them in ascending CSR order
+// -- the same operations in the same order as row_gather.
+constexpr int HUB_STAGE = 2048;  // floats of staging
+
+template <int VEC, bool WEIGHTED>
+__device__ __forceinline__ void block_gather(const GraphView &g, const float *__restrict__ X, const RowMap &m,
+                                             int32_t ncols, int32_t ld, int32_t lanes_log2, float (&acc)[VEC]) {
+  __shared__ float stage[HUB_STAGE];
+  __shared__ float wstage[WEIGHTED ? HUB_STAGE : 1];
+  __shared__ int32_t hubs[256];
+  __shared__ int32_t nhub;
+  const int32_t lanes = 1 << lanes_log2;
+  const int32_t grp = threadIdx.x >> lanes_log2, lane = threadIdx.x & (lanes - 1);
+  const int32_t hub_deg = max(32, 2 * lanes);
+  if (threadIdx.x == 0) nhub = 0;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
+  if (m.row < g.n) {
+    const int64_t v = g.lo + m.row;
+    if (g.row_ptr[v + 1] - g.row_ptr[v] > hub_deg) {
+      if (lane == 0) hubs[atomicAdd(&nhub, 1)] = grp;
+    } else {
+      row_gather<VEC, WEIGHTED>(g, X, v, m.col, ld, lanes_log2, m.active, acc);
+    }
+  }
+  __syncthreads();
+  const int32_t nh = nhub;
+  if (nh == 0) return;  // uniform over the block
+  const int32_t cols_blk = lanes * VEC;
+  const int32_t col0 = blockIdx.y * cols_blk;
+  const int32_t CH = HUB_STAGE / cols_blk;  // neighbours per staged chunk
+  const int64_t row0 = m.row - grp;         // first row of the block
+  for (int32_t h = 0; h < nh; ++h) {
+    const int32_t og = hubs[h];
+    const int64_t hv = g.lo + row0 + og;
+    const int32_t hb = g.row_ptr[hv], he = g.row_ptr[hv + 1];
+    for (int32_t j0 = hb; j0 < he; j0 += CH) {
+      const int32_t cnt = min(CH, he - j0);
+      for (int32_t e = threadIdx.x; e < cnt * lanes; e += blockDim.x) {
+        const int32_t k = e >> lanes_log2, p = e & (lanes - 1);
+        const int32_t c = col0 + p * VEC;
+        if (c < ncols) {
+          const int64_t u = g.col_idx[j0 + k];
+          float x[VEC];
+          load_vec<VEC>(X + u * ld + c, x);
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) stage[k * cols_blk + p * VEC + i] = x[i];
+        }
+        if (WEIGHTED && p == 0) wstage[k] = (float)g.weight[j0 + k];
+      }
+      __syncthreads();
+      if (grp == og && m.active) {
+        for (int32_t k = 0; k < cnt; ++k) {
+          if (WEIGHTED) {
+            const float w = wstage[k];
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) {
+              const float p = w * stage[k * cols_blk + lane * VEC + i];
+              acc[i] = acc[i] + p;
+            }
+          } else {
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + stage[k * cols_blk + lane * VEC + i];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 template <int VEC, bool MAXCUT, bool WEIGHTED, bool MOMENTUM>
 __global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__restrict__ X, float *__restrict__ Xn,
                                                   float *__restrict__ V, int32_t ncols, int32_t ld,
                                                   int32_t lanes_log2, float alpha, float mu, float param) {
   const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2);
+  float acc[VEC];
+  block_gather<VEC, WEIGHTED>(g, X, m, ncols, ld, lanes_log2, acc);
   if (!m.active) return;
   const int64_t v = g.lo + m.row;
-  float acc[VEC];
-  row_gather<VEC, WEIGHTED>(g, X, v, m.col, ld, acc);
   float x[VEC], vv[VEC];
   load_vec<VEC>(X + v * ld + m.col, x);
   if (MOMENTUM) load_vec<VEC>(V + v * ld + m.col, vv);
@@ -233,11 +347,15 @@ template <bool MAXCUT, bool WEIGHTED>
 __global__ __launch_bounds__(256) void k_nbr_eval(GraphView g, const int8_t *__restrict__ Z, int32_t *__restrict__ NB,
                                                   unsigned long long *__restrict__ acc, int32_t ncols, int32_t ld,
                                                   int32_t lanes_log2) {
-  __shared__ unsigned long long sacc[3][64];
+  // per-column sums: wavefront shuffle reduction over the lanes of one column,
+  // then one LDS add per (wavefront, column) and one global atomic per
+  // (block, column)
+  __shared__ long long sacc[3][64];
   const int lanes = 1 << lanes_log2;
-  if (threadIdx.x < 3 * 64) sacc[threadIdx.x / 64][threadIdx.x % 64] = 0ull;
+  if (threadIdx.x < 3 * 64) sacc[threadIdx.x / 64][threadIdx.x % 64] = 0;
   __syncthreads();
   const RowMap m = map_rows<1>(g.n, ncols, lanes_log2);
+  long long a[3] = {0, 0, 0};
   if (m.active) {
     const int64_t v = g.lo + m.row;
     const int32_t beg = g.row_ptr[v], end = g.row_ptr[v + 1];
@@ -256,25 +374,27 @@ __global__ __launch_bounds__(256) void k_nbr_eval(GraphView g, const int8_t *__r
     if (!WEIGHTED) wsum = end - beg;
     if (NB) NB[v * ld + m.col] = s;
     const int32_t zv = Z[v * ld + m.col];
-    const int lane = threadIdx.x & (lanes - 1);
     if (MAXCUT) {
-      const long long a0 = (long long)wsum - (long long)zv * s;
-      if (a0) atomicAdd(&sacc[0][lane], (unsigned long long)a0);
+      a[0] = (long long)wsum - (long long)zv * s;
     } else {
-      if (zv) {
-        atomicAdd(&sacc[0][lane], 1ull);
-        if (s) atomicAdd(&sacc[1][lane], (unsigned long long)s);
-      } else if (s == 0) {
-        atomicAdd(&sacc[2][lane], 1ull);
-      }
+      a[0] = zv;
+      a[1] = zv ? s : 0;
+      a[2] = (zv == 0 && s == 0) ? 1 : 0;
     }
+  }
+  const int width = lanes < 64 ? lanes : 64;
+  const int wl = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < (MAXCUT ? 1 : 3); ++k) {
+    const long long t = wave_sum_stride(a[k], width);
+    if (wl < width && t) atomicAdd(reinterpret_cast<unsigned long long *>(&sacc[k][wl]), (unsigned long long)t);
   }
   __syncthreads();
   if ((int)threadIdx.x < lanes) {
     const int32_t c = blockIdx.y * lanes + threadIdx.x;
     if (c < ncols) {
       for (int k = 0; k < (MAXCUT ? 1 : 3); ++k)
-        if (sacc[k][threadIdx.x]) atomicAdd(&acc[k * ncols + c], sacc[k][threadIdx.x]);
+        if (sacc[k][threadIdx.x]) atomicAdd(&acc[k * ncols + c], (unsigned long long)sacc[k][threadIdx.x]);
     }
   }
 }
@@ -662,10 +782,10 @@ __global__ __launch_bounds__(256) void k_objective_grad(GraphView g, const float
   double fv[VEC];
 #pragma unroll
   for (int i = 0; i < VEC; ++i) fv[i] = 0.0;
+  float acc[VEC];
+  block_gather<VEC, WEIGHTED>(g, X, m, ncols, ld, lanes_log2, acc);
   if (m.active) {
     const int64_t v = g.lo + m.row;
-    float acc[VEC];
-    row_gather<VEC, WEIGHTED>(g, X, v, m.col, ld, acc);
     float x[VEC];
     load_vec<VEC>(X + v * ld + m.col, x);
     const double c = MAXCUT ? -(double)param : 1.0;
@@ -682,20 +802,36 @@ __global__ __launch_bounds__(256) void k_objective_grad(GraphView g, const float
   if (part) block_column_partials<VEC>(fv, m.active, m.col, ncols, lanes_log2, part);
 }
 
-// out[c] (+)= sum over nblk partials, fixed tree order (one block per column)
+// Column sums of per-block partials part[nblk][ncols] in a fixed order.
+// Block (x, y) sums, for W = 2^wlog2 consecutive columns, the partial rows
+// [y * per_slice, (y + 1) * per_slice): lane group r of the block takes rows
+// r, r + R, ... (R = 256 / W; coalesced over the columns), then a fixed tree
+// over r.  With gridDim.y > 1 it writes dst[y][ncols] (the next level);
+// with one slice it writes (or adds to) the final dst[ncols].
 __global__ __launch_bounds__(256) void k_reduce_partials(const double *__restrict__ part, int64_t nblk, int32_t ncols,
-                                                         double *__restrict__ out, int32_t accumulate) {
+                                                         int32_t wlog2, int64_t per_slice, double *__restrict__ dst,
+                                                         int32_t accumulate) {
   __shared__ double s[256];
-  const int32_t c = blockIdx.x;
+  const int32_t W = 1 << wlog2, R = 256 >> wlog2;
+  const int32_t c = blockIdx.x * W + (threadIdx.x & (W - 1));
+  const int32_t r = threadIdx.x >> wlog2;
+  const int64_t b0 = (int64_t)blockIdx.y * per_slice;
+  const int64_t b1 = min(nblk, b0 + per_slice);
   double t = 0.0;
-  for (int64_t b = threadIdx.x; b < nblk; b += blockDim.x) t += part[b * ncols + c];
+  if (c < ncols)
+    for (int64_t b = b0 + r; b < b1; b += R) t += part[b * ncols + c];
   s[threadIdx.x] = t;
   __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+  for (int32_t off = R >> 1; off > 0; off >>= 1) {
+    if (r < off) s[threadIdx.x] += s[threadIdx.x + (off << wlog2)];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[c] = accumulate ? out[c] + s[0] : s[0];
+  if (r == 0 && c < ncols) {
+    if (gridDim.y > 1)
+      dst[(int64_t)blockIdx.y * ncols + c] = s[threadIdx.x];
+    else
+      dst[c] = accumulate ? dst[c] + s[threadIdx.x] : s[threadIdx.x];
+  }
 }
 
 // adjoint, part 1: recompute g(x_k), the clip mask, mu = mask * lam_next,
@@ -709,10 +845,10 @@ __global__ __launch_bounds__(256) void k_adj_mu(GraphView g, const float *__rest
   double dv[VEC];
 #pragma unroll
   for (int i = 0; i < VEC; ++i) dv[i] = 0.0;
+  float acc[VEC];
+  block_gather<VEC, WEIGHTED>(g, Xk, m, ncols, ld, lanes_log2, acc);
   if (m.active) {
     const int64_t v = g.lo + m.row;
-    float acc[VEC];
-    row_gather<VEC, WEIGHTED>(g, Xk, v, m.col, ld, acc);
     float x[VEC], ln[VEC], mu[VEC];
     load_vec<VEC>(Xk + v * ld + m.col, x);
     load_vec<VEC>(lam_next + v * ld + m.col, ln);
@@ -736,10 +872,10 @@ __global__ __launch_bounds__(256) void k_adj_lambda(GraphView g, const float *__
                                                     int32_t ncols, int32_t ld, int32_t lanes_log2, float alpha,
                                                     float eta) {
   const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2);
+  float acc[VEC], mv[VEC], out[VEC];
+  block_gather<VEC, WEIGHTED>(g, mu, m, ncols, ld, lanes_log2, acc);
   if (!m.active) return;
   const int64_t v = g.lo + m.row;
-  float acc[VEC], mv[VEC], out[VEC];
-  row_gather<VEC, WEIGHTED>(g, mu, v, m.col, ld, acc);
   load_vec<VEC>(mu + v * ld + m.col, mv);
 #pragma unroll
   for (int i = 0; i < VEC; ++i) {
@@ -1009,9 +1145,25 @@ void launch_objective_grad(bool maxcut, const GraphView &g, const float *X, cons
 #undef MQO_OBJ
 }
 
-void launch_reduce_partials(const double *part, int64_t nblk, int32_t ncols, double *out, bool accumulate,
-                            hipStream_t s) {
-  MQO_LAUNCH(k_reduce_partials, dim3(ncols), dim3(256), 0, s, part, nblk, ncols, out, (int32_t)accumulate);
+void launch_reduce_partials(double *part, int64_t nblk, int32_t ncols, double *out, bool accumulate, hipStream_t s) {
+  int32_t wlog2 = 0;
+  while ((1 << wlog2) < ncols && wlog2 < 6) ++wlog2;
+  const unsigned cx = (unsigned)((ncols + (1 << wlog2) - 1) >> wlog2);
+  // first level: up to REDUCE_SLICES slices of at least 64 partial rows each,
+  // written after the partials; second level: one slice
+  int64_t slices = (nblk + 63) / 64;
+  if (slices > REDUCE_SLICES) slices = REDUCE_SLICES;
+  if (slices > 1) {
+    const int64_t per = (nblk + slices - 1) / slices;
+    slices = (nblk + per - 1) / per;
+    double *lvl = part + nblk * ncols;
+    MQO_LAUNCH(k_reduce_partials, dim3(cx, (unsigned)slices), dim3(256), 0, s, part, nblk, ncols, wlog2, per, lvl, 0);
+    MQO_LAUNCH(k_reduce_partials, dim3(cx, 1), dim3(256), 0, s, lvl, slices, ncols, wlog2, slices, out,
+               (int32_t)accumulate);
+  } else {
+    MQO_LAUNCH(k_reduce_partials, dim3(cx, 1), dim3(256), 0, s, part, nblk, ncols, wlog2, nblk, out,
+               (int32_t)accumulate);
+  }
 }
 
 template <int VEC, bool MC, bool W>

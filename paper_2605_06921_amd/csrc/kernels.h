@@ -55,8 +55,9 @@ void launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, const 
                           int32_t G, int64_t n, int32_t *err, hipStream_t s);
 void launch_objective_grad(bool maxcut, const GraphView &g, const float *X, const float *scale, float *grad,
                            double *part, int32_t ncols, int32_t ld, StepCfg cfg, float param, hipStream_t s);
-void launch_reduce_partials(const double *part, int64_t nblk, int32_t ncols, double *out, bool accumulate,
-                            hipStream_t s);
+// partial rows [nblk][ncols] followed by room for REDUCE_SLICES more rows
+constexpr int64_t REDUCE_SLICES = 128;
+void launch_reduce_partials(double *part, int64_t nblk, int32_t ncols, double *out, bool accumulate, hipStream_t s);
 void launch_adjoint_step(bool maxcut, const GraphView &g, const float *Xk, const float *lam_next, float *mu,
                          float *lam, double *part, int32_t ncols, int32_t ld, StepCfg cfg, float alpha, float param,
                          hipStream_t s);

@@ -53,7 +53,7 @@ template <bool MAXCUT, bool WEIGHTED, int VEC, bool CSR_LDS, int DREG, int IPT>
 // Four register rows per lane need more than the 128 VGPRs a 1024-thread
 // workgroup leaves, so that variant is built for at most 512 threads.
 __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a) {
-  extern __shared__ float smem[];
+  extern __shared__ __align__(16) float smem[];
   __shared__ uint32_t s_prefix[TILE_MAX_T], s_krem[TILE_MAX_T], s_cnteq[TILE_MAX_T], s_tie[TILE_MAX_T];
   __shared__ unsigned long long s_acc[2][TILE_MAX_T];
   __shared__ int32_t s_take[TILE_MAX_T];
@@ -86,7 +86,10 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
   float *xa = smem;                                                     // [rowsX][T]
   float *xb = smem + (size_t)rowsX * T;                                 // [rowsX][T]
   int32_t *rps = reinterpret_cast<int32_t *>(xb + (size_t)rowsX * T);  // [n_max+1] row_ptr of the graph
-  uint16_t *cls = reinterpret_cast<uint16_t *>(rps + a.n_max + 1);      // [nnz_max] local columns (CSR_LDS)
+  // [nnz_max + 8] local columns (CSR_LDS), 16-byte aligned for 8-wide reads
+  const size_t cls_off = ((size_t)(2 * rowsX) * T * sizeof(float) + (size_t)(a.n_max + 1) * sizeof(int32_t) + 15) &
+                         ~(size_t)15;
+  uint16_t *cls = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(smem) + cls_off);
   const int64_t sbase = (int64_t)wid * a.n_max * T;
   int8_t *zs = a.zs + sbase;
   int32_t *nb = a.nb + sbase;
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
   const int32_t *cig = ci + e0;  // the graph's columns, global ids
   const int32_t *wtg = WEIGHTED ? wt + e0 : nullptr;
   if (CSR_LDS)
-    for (int32_t j = tid; j < nnz_g; j += nthr) cls[j] = (uint16_t)(cig[j] - ilo);
+    for (int32_t j = tid; j < nnz_g + 8; j += nthr) cls[j] = j < nnz_g ? (uint16_t)(cig[j] - ilo) : (uint16_t)0;
   const int32_t k = (int32_t)floor(a.rho * (double)n);
   const int32_t ls_cap = 4 * (n + nnz_g) + 64;
   int32_t ls_total = 0;
@@ -253,21 +256,49 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
         float acc[VEC];
 #pragma unroll
         for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
-#pragma unroll 4
-        for (int32_t j = beg; j < end; ++j) {
-          const int32_t u = CSR_LDS ? (int32_t)cls[j] : cig[j] - ilo;
-          float xu[VEC];
-          lds_load<VEC>(src + ((u << lt) | c0), xu);
-          if (WEIGHTED) {
-            const float w = (float)wtg[j];
+        if constexpr (CSR_LDS) {
+          // eight local ids per 16-byte LDS read; neighbours still added in
+          // ascending CSR order
+          for (int32_t j0 = beg & ~7; j0 < end; j0 += 8) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(cls + j0);
+            const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) {
-              const float p = w * xu[i];
-              acc[i] = acc[i] + p;
+            for (int kk = 0; kk < 8; ++kk) {
+              const int32_t j = j0 + kk;
+              if (j < beg || j >= end) continue;
+              const int32_t u = (int32_t)((qw[kk >> 1] >> (16 * (kk & 1))) & 0xffffu);
+              float xu[VEC];
+              lds_load<VEC>(src + ((u << lt) | c0), xu);
+              if (WEIGHTED) {
+                const float w = (float)wtg[j];
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) {
+                  const float p = w * xu[i];
+                  acc[i] = acc[i] + p;
+                }
+              } else {
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + xu[i];
+              }
             }
-          } else {
+          }
+        } else {
+#pragma unroll 4
+          for (int32_t j = beg; j < end; ++j) {
+            const int32_t u = cig[j] - ilo;
+            float xu[VEC];
+            lds_load<VEC>(src + ((u << lt) | c0), xu);
+            if (WEIGHTED) {
+              const float w = (float)wtg[j];
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + xu[i];
+              for (int i = 0; i < VEC; ++i) {
+                const float p = w * xu[i];
+                acc[i] = acc[i] + p;
+              }
+            } else {
+#pragma unroll
+              for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + xu[i];
+            }
           }
         }
         float x[VEC];
@@ -362,24 +393,37 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
     }
 
     // ------------------------------------------------ evaluation, acceptance
+    // every item of a thread belongs to trajectory tid % T: sum them in
+    // registers, reduce over the wavefront's lanes of that trajectory, then
+    // one LDS add per (wavefront, trajectory)
     if (tid < 2 * TILE_MAX_T) s_acc[tid / TILE_MAX_T][tid % TILE_MAX_T] = 0ull;
     __syncthreads();
-    for (int32_t L = tid; L < nT; L += nthr) {
-      const int32_t v = L >> lt, c = L & (T - 1);
-      if (c < cols) {
-        const int32_t z = zs[L], s = nb[L];
-        if (MAXCUT) {
-          int32_t wsum = rps[v + 1] - rps[v];
-          if (WEIGHTED) {
-            wsum = 0;
-            for (int32_t j = rps[v]; j < rps[v + 1]; ++j) wsum += wtg[j];
+    {
+      long long a0 = 0, a1 = 0;
+      for (int32_t L = tid; L < nT; L += nthr) {
+        const int32_t v = L >> lt, c = L & (T - 1);
+        if (c < cols) {
+          const int32_t z = zs[L], s = nb[L];
+          if (MAXCUT) {
+            int32_t wsum = rps[v + 1] - rps[v];
+            if (WEIGHTED) {
+              wsum = 0;
+              for (int32_t j = rps[v]; j < rps[v + 1]; ++j) wsum += wtg[j];
+            }
+            a0 += (long long)wsum - (long long)z * s;
+          } else if (z) {
+            a0 += 1;
+            a1 += s;
           }
-          const long long a0 = (long long)wsum - (long long)z * s;
-          if (a0) atomicAdd(&s_acc[0][c], (unsigned long long)a0);
-        } else if (z) {
-          atomicAdd(&s_acc[0][c], 1ull);
-          if (s) atomicAdd(&s_acc[1][c], (unsigned long long)s);
         }
+      }
+      const int width = T;  // T <= 64 divides the wavefront
+      a0 = wave_sum_stride(a0, width);
+      a1 = wave_sum_stride(a1, width);
+      const int wl = tid & 63;
+      if (wl < width) {
+        if (a0) atomicAdd(&s_acc[0][wl], (unsigned long long)a0);
+        if (!MAXCUT && a1) atomicAdd(&s_acc[1][wl], (unsigned long long)a1);
       }
     }
     __syncthreads();
@@ -422,7 +466,7 @@ bool tile_shape_ok(int64_t n_max, int T, int threads, int vec, bool csr_lds, int
 size_t tile_lds_bytes(int64_t n_max, int T, int64_t nnz_max, bool csr_lds) {
   const int64_t rowsX = (n_max > 256 ? n_max : 256) + 1;
   size_t b = (size_t)(2 * rowsX) * T * sizeof(float) + (size_t)(n_max + 1) * sizeof(int32_t);
-  if (csr_lds) b += (size_t)nnz_max * sizeof(uint16_t);
+  if (csr_lds) b = ((b + 15) & ~(size_t)15) + (size_t)(nnz_max + 8) * sizeof(uint16_t);
   return (b + 15) & ~(size_t)15;
 }
 

@@ -1,6 +1,8 @@
 """Python binding of libmqo (ctypes).  Argument marshalling only: every step
 of the path runs in the HIP library; torch provides device memory and the
 current stream.  Importing this module raises if libmqo.so is missing.
+The environment variable MQO_LIBRARY, when set, names another build of the
+same library to load instead (for comparing kernel variants).
 """
 from __future__ import annotations
 
@@ -12,7 +14,7 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmqo.so")
+LIB_PATH = os.environ.get("MQO_LIBRARY") or os.path.join(_HERE, "libmqo.so")
 
 MIS = 0
 MAXCUT = 1

@@ -72,9 +72,9 @@ WORKLOADS: Dict[str, Workload] = {
                     "1000 steps of 0.01, round at 0.5, repair + 1-flip search"),
     "reg3_maxcut": Workload(
         "reg3_maxcut", "maxcut", _c2, batch=256, steps_per_round=200, rounds=10,
-        alpha=0.01, seed=2000 + 10**6,
+        alpha=0.01, seed=2000 + 10**6, reset_mode="flip",
         description="random 3-regular n=2000, MaxCut f_B (lambda=1e-3), 256 restarts, "
-                    "2000 steps in 10 rounds of 200, reset 5% of the incumbent, "
+                    "2000 steps in 10 rounds of 200, flip 5% of the incumbent's spins, "
                     "1-flip search, int64 cuts"),
     "er_batch_mis": Workload(
         "er_batch_mis", "mis", _c3, batch=512, steps_per_round=200, rounds=10,

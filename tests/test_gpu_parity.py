@@ -375,3 +375,59 @@ def test_unrolled_autograd_function(mqo):
     rX0, ra = pga.unrolled_backward(g, kind, 1e-3, 0.01, 10, x0, dL, precision="fp32")
     assert np.abs(X0.grad.cpu().numpy() - rX0).max() / max(1.0, np.abs(rX0).max()) <= 1e-4
     assert abs(float(alpha.grad) - ra.sum()) <= 1e-4 * max(1.0, abs(ra.sum()))
+
+
+# --------------------------------------------------------------------------
+# rows of very high degree (hubs) in the streaming kernels
+# --------------------------------------------------------------------------
+
+HUB_CASES = {
+    "ba_star": ("mis", graphs.concat([graphs.barabasi_albert(1500, 3, 131), graphs.star(700)])),
+    "ba_weighted": ("maxcut", graphs.with_weights(graphs.barabasi_albert(3000, 5, 132), 133)),
+}
+
+
+@pytest.mark.parametrize("name", list(HUB_CASES))
+@pytest.mark.parametrize("B", [1, 3, 16, 64, 130])
+def test_hub_rows_steps_objective_adjoint(mqo, name, B):
+    kind, g = HUB_CASES[name]
+    assert g.degrees().max() > 128  # every lane count defers such rows
+    dg = mqo.DeviceGraph(g, DEV)
+    param = 2.0 if kind == "mis" else 1e-3
+    X0 = _x(kind, g.n, B, 141 + B)
+    X = torch.from_numpy(X0).to(DEV)
+    mqo.pga_steps(kind, dg, X, 3, alpha=0.02, gamma=2.0, lam=1e-3)
+    ref = X0
+    for _ in range(3):
+        ref, _ = pga.step32(g, ref, kind, 0.02, param)
+    assert np.array_equal(X.cpu().numpy(), ref)
+
+    f, grad = mqo.objective_grad(kind, dg, torch.from_numpy(X0).to(DEV), param)
+    for gi in range(g.num_graphs):
+        sub = g.subgraph(gi)
+        lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+        fr, gr = pga.objective_and_grad(sub, kind, param, X0[lo:hi].astype(np.float64), np.ones(B))
+        assert np.allclose(f.cpu().numpy()[gi * B:(gi + 1) * B], fr, rtol=1e-5,
+                           atol=1e-5 * np.abs(X0[lo:hi]).sum())
+        assert np.abs(grad.cpu().numpy()[lo:hi] - gr).max() / max(1.0, np.abs(gr).max()) <= 1e-5
+
+    if g.num_graphs == 1 and B in (3, 64):
+        K, c, alpha = 10, 5, 0.01
+        XK, ckpt = mqo.unrolled_forward(kind, dg, torch.from_numpy(X0).to(DEV), alpha, K, c, param)
+        xs = pga.unrolled_forward(g, kind, param, alpha, K, X0, precision="fp32")
+        assert np.array_equal(XK.cpu().numpy(), xs[K])
+        dL = obj.gradient(kind, xs[K].astype(np.float64), obj.adjacency(g), param).astype(np.float32)
+        dX0, da = mqo.unrolled_backward(kind, dg, ckpt, torch.from_numpy(dL).to(DEV), alpha, K, c, param)
+        rX0, ra = pga.unrolled_backward(g, kind, param, alpha, K, X0, dL.astype(np.float64), precision="fp32")
+        assert np.abs(dX0.cpu().numpy() - rX0).max() / max(1.0, np.abs(rX0).max()) <= 1e-4
+        assert np.allclose(da.cpu().numpy(), ra, rtol=1e-4, atol=1e-4 * np.abs(ra).max())
+
+
+@pytest.mark.parametrize("plan", ["batched", "plain"])
+def test_hub_rows_solve_bit_exact(mqo, plan):
+    kind, g = HUB_CASES["ba_star"]
+    kw = dict(batch=5, steps_per_round=20, rounds=2, alpha=0.02, rho=0.1, seed=17)
+    out = mqo.solve(kind, mqo.DeviceGraph(g, DEV), plan=plan, **kw)
+    ref = _oracle_solve(kind, g, kw)
+    assert np.array_equal(out["traj_best_value"].cpu().numpy(), ref["traj_best_value"])
+    assert np.array_equal(out["traj_best_x"].cpu().numpy(), ref["traj_best_x"])
