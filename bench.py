@@ -70,30 +70,37 @@ def step_bytes(g, B, momentum=False):
 
 
 def cpu_baseline(wl, g, budget_s=15.0):
-    """The oracle (float32 replay, as used for parity) on a bounded sample:
-    the first graph, a few trajectories, whole rounds until ~budget_s."""
+    """The oracle (float32 replay, as used for parity) on a bounded sample of
+    the workload: the first graph, whole rounds of the first trajectories,
+    sized from a one-round probe to take about budget_s."""
     from oracle import solver as osolver
+
+    def params(rounds):
+        return osolver.Params(batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=rounds, alpha=wl.alpha,
+                              seed=wl.seed, gamma=wl.gamma, lam=wl.lam, rho=wl.rho, reset_mode=wl.reset_mode,
+                              local_search=wl.local_search)
+
     sub = g.subgraph(0)
-    cols = np.arange(min(wl.batch, 8))
-    p = osolver.Params(batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=1, alpha=wl.alpha, seed=wl.seed,
-                       gamma=wl.gamma, lam=wl.lam, rho=wl.rho, reset_mode=wl.reset_mode,
-                       local_search=wl.local_search)
     t0 = time.perf_counter()
-    rounds = 0
+    osolver.solve_graph(wl.problem, sub, params(1), 0, cols=np.arange(1))
+    probe = time.perf_counter() - t0
+    rounds = int(min(wl.rounds, max(1, budget_s // probe)))
+    ncols = 1
     while True:
-        p.rounds = rounds + 1
-        osolver.solve_graph(wl.problem, sub, p, 0, cols=cols)
-        rounds += 1
+        t0 = time.perf_counter()
+        osolver.solve_graph(wl.problem, sub, params(rounds), 0, cols=np.arange(ncols))
         el = time.perf_counter() - t0
-        if el >= budget_s or rounds >= wl.rounds:
+        # the oracle is vectorised over trajectories: grow the sample until
+        # it fills about half the budget
+        if rounds < wl.rounds or ncols == wl.batch or el >= budget_s / 2:
             break
-    # solve_graph recomputes all rounds each call: count the work of every call
-    total_rounds = rounds * (rounds + 1) // 2
-    eu = sub.nnz * len(cols) * wl.steps_per_round * total_rounds
+        ncols = int(min(wl.batch, max(2 * ncols, ncols * budget_s / max(el, 1e-3))))
+    eu = sub.nnz * ncols * wl.steps_per_round * rounds
     return dict(value=eu / el, unit="edge-updates/s", cores=1, kind="oracle",
-                sample=f"graph 0 of {g.num_graphs} (n={sub.n}, nnz={sub.nnz}), trajectories 0..{len(cols) - 1} "
-                       f"of {wl.batch}, rounds 1..{rounds} of {wl.rounds} ({wl.steps_per_round} steps each), "
-                       f"float32 replay, single-threaded numpy, {el:.1f} s")
+                sample=f"graph 0 of {g.num_graphs} (n={sub.n}, nnz={sub.nnz}), trajectories 0..{ncols - 1} "
+                       f"of {wl.batch}, rounds 1..{rounds} of {wl.rounds} ({wl.steps_per_round} steps each, "
+                       f"reset, 1-flip search and evaluation included), float32 replay, single-threaded "
+                       f"numpy/scipy, {el:.1f} s")
 
 
 def main():

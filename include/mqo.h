@@ -70,6 +70,19 @@ typedef struct {
   const int32_t *row_ptr;     /* [n_total + 1]                                */
   const int32_t *col_idx;     /* [nnz_total]                                  */
   const int32_t *weight;      /* [nnz_total] or NULL (unit weights)           */
+  /* Optional list of high-degree rows ("hubs"); hub_offset = NULL for none.
+   * The sparse-product kernels (PGA step, objective gradient, adjoint) give
+   * every listed row column slices of their own workgroups instead of one
+   * lane group, so that a row of very high degree (preferential-attachment
+   * graphs) does not hold up a whole step.  Results are bit-identical with
+   * and without the list.  hub_rows holds, graph after graph, the global
+   * ids of EXACTLY the rows of degree > hub_min_degree, ascending;
+   * hub_offset[i] .. hub_offset[i+1] delimits graph i's part.  The solves
+   * check the list on the device (MQO_ERR_INVALID_GRAPH); the asynchronous
+   * entry points trust it. */
+  int32_t hub_min_degree;     /* >= 0                                         */
+  const int64_t *hub_offset;  /* (host) [G+1], hub_offset[0] = 0, or NULL     */
+  const int32_t *hub_rows;    /* [hub_offset[G]]                              */
 } mqo_graph;
 
 /* Search parameters.  Fill with mqo_params_default() first. */

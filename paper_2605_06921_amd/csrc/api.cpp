@@ -115,6 +115,16 @@ int check_graph_args(const mqo_graph *g, bool need_weight_free) {
   if (!g->row_ptr) return fail(MQO_ERR_INVALID_ARG, "row_ptr is NULL");
   if (g->nnz_total > 0 && !g->col_idx) return fail(MQO_ERR_INVALID_ARG, "col_idx is NULL");
   if (need_weight_free && g->weight) return fail(MQO_ERR_INVALID_ARG, "the MIS objective takes an unweighted graph");
+  if (g->hub_offset) {
+    if (g->hub_min_degree < 0) return fail(MQO_ERR_INVALID_ARG, "hub_min_degree must be >= 0");
+    if (g->hub_offset[0] != 0) return fail(MQO_ERR_INVALID_GRAPH, "hub_offset[0] must be 0");
+    for (int32_t i = 0; i < g->num_graphs; ++i) {
+      const int64_t c = g->hub_offset[i + 1] - g->hub_offset[i];
+      if (c < 0 || c > g->vtx_offset[i + 1] - g->vtx_offset[i])
+        return fail(MQO_ERR_INVALID_GRAPH, "hub_offset of graph %d out of range", i);
+    }
+    if (g->hub_offset[g->num_graphs] > 0 && !g->hub_rows) return fail(MQO_ERR_INVALID_ARG, "hub_rows is NULL");
+  }
   return MQO_OK;
 }
 
@@ -220,6 +230,14 @@ GraphView view_of(const mqo_graph *g, int32_t i) {
   v.weight = g->weight;
   v.lo = g->vtx_offset[i];
   v.n = g->vtx_offset[i + 1] - g->vtx_offset[i];
+  v.hubs = nullptr;
+  v.nhub = 0;
+  v.hub_deg = 0x7fffffff;
+  if (g->hub_offset && g->hub_offset[i + 1] > g->hub_offset[i]) {
+    v.hubs = g->hub_rows + g->hub_offset[i];
+    v.nhub = (int32_t)(g->hub_offset[i + 1] - g->hub_offset[i]);
+    v.hub_deg = g->hub_min_degree;
+  }
   return v;
 }
 
@@ -252,6 +270,25 @@ int validate_on_device(const mqo_graph *g, int64_t *voff_dev, int32_t *err_dev, 
     if (e[0] & 8) return fail(MQO_ERR_INVALID_GRAPH, "columns not strictly ascending within a row");
     if (e[0] & 16) return fail(MQO_ERR_INVALID_GRAPH, "adjacency not symmetric");
     if (e[0] & 32) return fail(MQO_ERR_INVALID_GRAPH, "weights not symmetric");
+  }
+  if (g->hub_offset) {
+    launch_fill_i32(err_dev, 1, 0, s);
+    for (int32_t i = 0; i < g->num_graphs; ++i) {
+      const int64_t c = g->hub_offset[i + 1] - g->hub_offset[i];
+      if (c > 0)
+        launch_validate_hubs(g->row_ptr, g->hub_rows + g->hub_offset[i], c, g->vtx_offset[i],
+                             g->vtx_offset[i + 1] - g->vtx_offset[i], g->hub_min_degree, err_dev, s);
+    }
+    HIP_TRY(hipGetLastError());
+    TRY(read_back_i32(err_dev, 1, e, s));
+    if (e[0]) return fail(MQO_ERR_INVALID_GRAPH, "a hub_rows entry is out of its graph, not ascending or not a hub");
+    launch_fill_i32(err_dev, 1, 0, s);
+    launch_count_hubs(g->row_ptr, g->n_total, g->hub_min_degree, err_dev, s);
+    HIP_TRY(hipGetLastError());
+    TRY(read_back_i32(err_dev, 1, e, s));
+    if (e[0] != g->hub_offset[g->num_graphs])
+      return fail(MQO_ERR_INVALID_GRAPH, "hub_rows lists %lld rows, the graph has %d of degree > %d",
+                  (long long)g->hub_offset[g->num_graphs], e[0], g->hub_min_degree);
   }
   return MQO_OK;
 }
@@ -814,9 +851,19 @@ int check_param(mqo_objective obj, float param) {
   return MQO_OK;
 }
 
+int64_t max_graph_hubs(const mqo_graph *g) {
+  int64_t m = 0;
+  if (g->hub_offset)
+    for (int32_t i = 0; i < g->num_graphs; ++i) m = std::max(m, g->hub_offset[i + 1] - g->hub_offset[i]);
+  return m;
+}
+
+// float64 partial rows of the objective / adjoint kernels of one graph: one
+// per row workgroup, one per hub row, then room for the reduction's slices
 size_t partial_count(const mqo_graph *g, int32_t B) {
   const StepCfg cfg = default_step_cfg(B, B);
-  return (size_t)(grid_blocks_x(max_graph_rows(g), cfg) + REDUCE_SLICES) * B;
+  const int64_t nblk = grid_blocks_x(max_graph_rows(g), cfg) + max_graph_hubs(g);
+  return (size_t)(nblk + reduce_rows(nblk)) * B;
 }
 
 }  // namespace
@@ -891,7 +938,7 @@ int mqo_objective_grad(const mqo_graph *g, mqo_objective obj, float param, const
     const float *sc = scale ? scale + (int64_t)gi * B : nullptr;
     double *part = f_out ? reinterpret_cast<double *>(ws) : nullptr;
     launch_objective_grad(mc, gv, X, sc, grad_out, part, B, B, cfg, param, s);
-    if (f_out) launch_reduce_partials(part, grid_blocks_x(gv.n, cfg), B, f_out + (int64_t)gi * B, false, s);
+    if (f_out) launch_reduce_partials(part, grid_blocks_x(gv.n, cfg) + gv.nhub, B, f_out + (int64_t)gi * B, false, s);
   }
   HIP_TRY(hipGetLastError());
   return MQO_OK;
@@ -965,7 +1012,7 @@ int mqo_pga_unrolled_backward(const mqo_graph *g, mqo_objective obj, float param
   const int32_t nseg = K / ckpt_every;
   for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
     const GraphView gv = view_of(g, gi);
-    const int64_t nblk = grid_blocks_x(gv.n, cfg);
+    const int64_t nblk = grid_blocks_x(gv.n, cfg) + gv.nhub;
     launch_copy_f32(dL_dXK + gv.lo * B, lamA + gv.lo * B, gv.n * B, s);
     launch_fill_i64(reinterpret_cast<int64_t *>(dL_dalpha + (int64_t)gi * B), B, 0, s);  // +0.0
     float *cur = lamA, *nxt = lamB;

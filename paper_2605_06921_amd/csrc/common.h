@@ -167,6 +167,9 @@ struct GraphView {
   const int32_t *weight;  // nullptr = unit
   int64_t lo;             // first global row of the graph
   int64_t n;              // rows of the graph
+  const int32_t *hubs;    // global ids of the rows of degree > hub_deg, ascending
+  int32_t nhub;           // 0 = no hub list
+  int32_t hub_deg;
 };
 
 // Row x column mapping: W lanes per row (power of two <= 64), each lane
@@ -177,25 +180,22 @@ struct RowMap {
   bool active;
 };
 
-// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
-// b % 8).  Renumber them so that each XCD gets one contiguous range of
-// logical blocks: neighbouring rows then share an XCD's L2.
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
-  const int64_t x = b & 7;
-  int64_t start = 0;
-  for (int64_t y = 0; y < x; ++y) start += (nb + 7 - y) >> 3;  // blocks of XCD y
-  return start + (b >> 3);
+// Lane group of 2^lanes_log2 lanes per row; bx is the workgroup's index
+// among the row workgroups of the launch.
+template <int VEC>
+__device__ __forceinline__ RowMap map_rows(int64_t nrows, int32_t ncols, int32_t lanes_log2, int64_t bx) {
+  RowMap m;
+  const int32_t lanes = 1 << lanes_log2;
+  const int32_t rows_per_block = blockDim.x >> lanes_log2;
+  m.row = bx * rows_per_block + (threadIdx.x >> lanes_log2);
+  m.col = (int32_t)(blockIdx.y * lanes + (threadIdx.x & (lanes - 1))) * VEC;
+  m.active = m.row < nrows && m.col < ncols;
+  return m;
 }
 
 template <int VEC>
 __device__ __forceinline__ RowMap map_rows(int64_t nrows, int32_t ncols, int32_t lanes_log2) {
-  RowMap m;
-  const int32_t lanes = 1 << lanes_log2;
-  const int32_t rows_per_block = blockDim.x >> lanes_log2;
-  m.row = xcd_block(blockIdx.x, gridDim.x) * rows_per_block + (threadIdx.x >> lanes_log2);
-  m.col = (int32_t)(blockIdx.y * lanes + (threadIdx.x & (lanes - 1))) * VEC;
-  m.active = m.row < nrows && m.col < ncols;
-  return m;
+  return map_rows<VEC>(nrows, ncols, lanes_log2, (int64_t)blockIdx.x);
 }
 
 }  // namespace mqo

@@ -5,6 +5,8 @@
 // Element (v, c) of an [n][ld] array lives at v * ld + c with v the GLOBAL
 // row; random draws use the local index v - lo and the trajectory id
 // traj0 + c.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -133,12 +135,28 @@ __device__ __forceinline__ void store_vec(float *p, const float (&o)[VEC]) {
 }
 
 // acc[i] = sum over the row's neighbours, ascending CSR order, one rounding per add.
-// With 4 or more lanes per row the lanes load up to `lanes` column indices
-// (and weights) of the row in one coalesced load and pass them round with
-// shuffles, so the gathers do not wait on one index load each.
-// Every lane of a valid row must call it (the shuffles read the row's other
-// lanes); lanes whose column is past the batch pass colok = false and only
-// help with the index loads.
+// Column indices (and weights) are streamed with non-temporal loads so that
+// they do not evict iterate lines.  With 4 or more lanes per row the lanes
+// load up to `lanes` indices of the row in one coalesced load and pass them
+// round with wave shuffles; then every lane of the row's group must call it
+// (lanes whose columns are past the batch pass colok = false and only help
+// with the index loads).  With 1 or 2 lanes per row each lane loads eight
+// indices at a time and issues the eight gathers back to back.
+template <int VEC, bool WEIGHTED>
+__device__ __forceinline__ void add_neighbour(float (&acc)[VEC], const float (&x)[VEC], int32_t w) {
+  if (WEIGHTED) {
+    const float wf = (float)w;
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      const float p = wf * x[i];
+      acc[i] = acc[i] + p;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + x[i];
+  }
+}
+
 template <int VEC, bool WEIGHTED>
 __device__ __forceinline__ void row_gather(const GraphView &g, const float *__restrict__ X, int64_t v, int32_t col,
                                            int32_t ld, int32_t lanes_log2, bool colok, float (&acc)[VEC]) {
@@ -150,8 +168,8 @@ __device__ __forceinline__ void row_gather(const GraphView &g, const float *__re
     const int32_t lane = threadIdx.x & (lanes - 1);
     for (int32_t j0 = beg; j0 < end; j0 += lanes) {
       const bool have = j0 + lane < end;
-      const int32_t myu = have ? g.col_idx[j0 + lane] : 0;
-      const int32_t myw = WEIGHTED ? (have ? g.weight[j0 + lane] : 0) : 1;
+      const int32_t myu = have ? __builtin_nontemporal_load(g.col_idx + j0 + lane) : 0;
+      const int32_t myw = WEIGHTED && have ? __builtin_nontemporal_load(g.weight + j0 + lane) : 1;
       const int32_t cnt = min(lanes, end - j0);
 #pragma unroll 4
       for (int32_t k = 0; k < cnt; ++k) {
@@ -160,143 +178,161 @@ __device__ __forceinline__ void row_gather(const GraphView &g, const float *__re
         if (!colok) continue;
         float x[VEC];
         load_vec<VEC>(X + u * ld + col, x);
-        if (WEIGHTED) {
-          const float w = (float)wk;
-#pragma unroll
-          for (int i = 0; i < VEC; ++i) {
-            const float p = w * x[i];
-            acc[i] = acc[i] + p;
-          }
-        } else {
-#pragma unroll
-          for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + x[i];
-        }
+        add_neighbour<VEC, WEIGHTED>(acc, x, wk);
       }
     }
     return;
   }
   if (!colok) return;
-#pragma unroll 4
-  for (int32_t j = beg; j < end; ++j) {
-    const int64_t u = g.col_idx[j];
-    float x[VEC];
-    load_vec<VEC>(X + u * ld + col, x);
-    if (WEIGHTED) {
-      const float w = (float)g.weight[j];
+  for (int32_t j0 = beg; j0 < end; j0 += 8) {
+    int32_t u[8], w[8];
 #pragma unroll
-      for (int i = 0; i < VEC; ++i) {
-        const float p = w * x[i];
-        acc[i] = acc[i] + p;
-      }
-    } else {
+    for (int k = 0; k < 8; ++k) {
+      const bool ok = j0 + k < end;
+      u[k] = ok ? __builtin_nontemporal_load(g.col_idx + j0 + k) : 0;
+      w[k] = WEIGHTED && ok ? __builtin_nontemporal_load(g.weight + j0 + k) : 1;
+    }
 #pragma unroll
-      for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + x[i];
+    for (int k = 0; k < 8; ++k) {
+      if (j0 + k >= end) break;
+      float x[VEC];
+      load_vec<VEC>(X + (int64_t)u[k] * ld + col, x);
+      add_neighbour<VEC, WEIGHTED>(acc, x, w[k]);
     }
   }
 }
 
-// Block-wide neighbour sums for the rows of this block; every thread of the
-// block must call it.  Rows of degree above max(32, 2 * lanes) (hubs, e.g. in
-// preferential-attachment graphs) would keep one lane group busy long after
-// the rest of the block: they are deferred, and for each of them the whole
-// block stages chunks of its neighbours' slices [col0, col0 + lanes*VEC) into
-// LDS, from which the row's own lane group adds them in ascending CSR order
-// -- the same operations in the same order as row_gather.
-constexpr int HUB_STAGE = 2048;  // floats of staging
+// ---------------------------------------------------------------------------
+// Hub rows.  A row of degree above g.hub_deg (listed in g.hubs) is not
+// handled by a lane group: the first hub_blocks(g, ncols) workgroups of a
+// launch each take one (hub, slice of HUB_SW columns).  The whole workgroup
+// stages the slice of up to HUB_CHUNK neighbours at a time into LDS, then
+// lane c of the first wavefront adds column c0 + c in ascending CSR order,
+// so the result is the same as row_gather's.
+// ---------------------------------------------------------------------------
+constexpr int HUB_SW = 4;
+constexpr int HUB_CHUNK = 1024;
+// dynamic LDS of a hub workgroup
+static inline size_t hub_lds(bool weighted) { return HUB_CHUNK * (16 + (weighted ? 4 : 0)); }
 
-template <int VEC, bool WEIGHTED>
-__device__ __forceinline__ void block_gather(const GraphView &g, const float *__restrict__ X, const RowMap &m,
-                                             int32_t ncols, int32_t ld, int32_t lanes_log2, float (&acc)[VEC]) {
-  __shared__ float stage[HUB_STAGE];
-  __shared__ float wstage[WEIGHTED ? HUB_STAGE : 1];
-  __shared__ int32_t hubs[256];
-  __shared__ int32_t nhub;
-  const int32_t lanes = 1 << lanes_log2;
-  const int32_t grp = threadIdx.x >> lanes_log2, lane = threadIdx.x & (lanes - 1);
-  const int32_t hub_deg = max(32, 2 * lanes);
-  if (threadIdx.x == 0) nhub = 0;
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
-  if (m.row < g.n) {
-    const int64_t v = g.lo + m.row;
-    if (g.row_ptr[v + 1] - g.row_ptr[v] > hub_deg) {
-      if (lane == 0) hubs[atomicAdd(&nhub, 1)] = grp;
-    } else {
-      row_gather<VEC, WEIGHTED>(g, X, v, m.col, ld, lanes_log2, m.active, acc);
-    }
-  }
-  __syncthreads();
-  const int32_t nh = nhub;
-  if (nh == 0) return;  // uniform over the block
-  const int32_t cols_blk = lanes * VEC;
-  const int32_t col0 = blockIdx.y * cols_blk;
-  const int32_t CH = HUB_STAGE / cols_blk;  // neighbours per staged chunk
-  const int64_t row0 = m.row - grp;         // first row of the block
-  for (int32_t h = 0; h < nh; ++h) {
-    const int32_t og = hubs[h];
-    const int64_t hv = g.lo + row0 + og;
-    const int32_t hb = g.row_ptr[hv], he = g.row_ptr[hv + 1];
-    for (int32_t j0 = hb; j0 < he; j0 += CH) {
-      const int32_t cnt = min(CH, he - j0);
-      for (int32_t e = threadIdx.x; e < cnt * lanes; e += blockDim.x) {
-        const int32_t k = e >> lanes_log2, p = e & (lanes - 1);
-        const int32_t c = col0 + p * VEC;
-        if (c < ncols) {
-          const int64_t u = g.col_idx[j0 + k];
-          float x[VEC];
-          load_vec<VEC>(X + u * ld + c, x);
-#pragma unroll
-          for (int i = 0; i < VEC; ++i) stage[k * cols_blk + p * VEC + i] = x[i];
-        }
-        if (WEIGHTED && p == 0) wstage[k] = (float)g.weight[j0 + k];
+__host__ __device__ inline int32_t hub_slices(int32_t ncols) { return (ncols + HUB_SW - 1) / HUB_SW; }
+__host__ __device__ inline int64_t hub_blocks(const GraphView &g, int32_t ncols) {
+  return (int64_t)g.nhub * hub_slices(ncols);
+}
+
+struct HubItem {
+  int64_t v;   // global row
+  int32_t h;   // index in the graph's hub list
+  int32_t c0;  // first column of the slice
+  int32_t cw;  // columns in the slice
+};
+
+__device__ __forceinline__ HubItem hub_item(const GraphView &g, int32_t ncols) {
+  HubItem it;
+  const int32_t ns = hub_slices(ncols);
+  it.h = (int32_t)(blockIdx.x / ns);
+  it.c0 = (int32_t)(blockIdx.x % ns) * HUB_SW;
+  it.cw = min(HUB_SW, ncols - it.c0);
+  it.v = g.hubs[it.h];
+  return it;
+}
+
+// Every thread of the workgroup calls it; the sum is valid in threads 0 .. cw-1.
+template <bool WEIGHTED>
+__device__ __forceinline__ float hub_gather(const GraphView &g, const float *__restrict__ X, const HubItem &it,
+                                            int32_t ld) {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  float4 *st = reinterpret_cast<float4 *>(dyn_lds);          // [HUB_CHUNK]
+  float *wst = reinterpret_cast<float *>(st + HUB_CHUNK);  // [HUB_CHUNK] when weighted
+  const int32_t beg = g.row_ptr[it.v], end = g.row_ptr[it.v + 1];
+  const bool v4 = it.cw == 4 && (ld & 3) == 0 && ((uintptr_t)X & 15) == 0;
+  const float *sf = reinterpret_cast<const float *>(st);
+  float acc = 0.0f;
+  for (int32_t j0 = beg; j0 < end; j0 += HUB_CHUNK) {
+    const int32_t cnt = min(HUB_CHUNK, end - j0);
+    for (int32_t k = threadIdx.x; k < cnt; k += blockDim.x) {
+      const int64_t u = __builtin_nontemporal_load(g.col_idx + j0 + k);
+      const float *p = X + u * ld + it.c0;
+      float4 x;
+      if (v4) {
+        x = *reinterpret_cast<const float4 *>(p);
+      } else {
+        x.x = p[0];
+        x.y = it.cw > 1 ? p[1] : 0.0f;
+        x.z = it.cw > 2 ? p[2] : 0.0f;
+        x.w = it.cw > 3 ? p[3] : 0.0f;
       }
-      __syncthreads();
-      if (grp == og && m.active) {
-        for (int32_t k = 0; k < cnt; ++k) {
-          if (WEIGHTED) {
-            const float w = wstage[k];
-#pragma unroll
-            for (int i = 0; i < VEC; ++i) {
-              const float p = w * stage[k * cols_blk + lane * VEC + i];
-              acc[i] = acc[i] + p;
-            }
-          } else {
-#pragma unroll
-            for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + stage[k * cols_blk + lane * VEC + i];
-          }
+      st[k] = x;
+      if (WEIGHTED) wst[k] = (float)g.weight[j0 + k];
+    }
+    __syncthreads();
+    if ((int32_t)threadIdx.x < it.cw) {
+#pragma unroll 8
+      for (int32_t k = 0; k < cnt; ++k) {
+        const float x = sf[k * 4 + threadIdx.x];
+        if (WEIGHTED) {
+          const float p = wst[k] * x;
+          acc = acc + p;
+        } else {
+          acc = acc + x;
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
+  return acc;
+}
+
+// The rows a lane group skips because a hub workgroup owns them.
+__device__ __forceinline__ bool is_hub_row(const GraphView &g, int64_t v) {
+  return g.nhub > 0 && g.row_ptr[v + 1] - g.row_ptr[v] > g.hub_deg;
+}
+
+// One PGA step of Sec. 3 (with optional heavy-ball momentum) for a single column.
+template <bool MAXCUT, bool MOMENTUM>
+__device__ __forceinline__ void step_update(float &x, float &vv, float acc, float alpha, float mu, float param) {
+  const float gr = grad_from_sum<MAXCUT>(acc, param);
+  float d = gr;
+  if (MOMENTUM) {
+    const float t = mu * vv;
+    vv = t + gr;
+    d = vv;
+  }
+  const float s = alpha * d;
+  const float y = x + s;
+  x = clip_box<MAXCUT>(y);
 }
 
 template <int VEC, bool MAXCUT, bool WEIGHTED, bool MOMENTUM>
 __global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__restrict__ X, float *__restrict__ Xn,
                                                   float *__restrict__ V, int32_t ncols, int32_t ld,
                                                   int32_t lanes_log2, float alpha, float mu, float param) {
-  const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2);
-  float acc[VEC];
-  block_gather<VEC, WEIGHTED>(g, X, m, ncols, ld, lanes_log2, acc);
-  if (!m.active) return;
+  const int64_t nhb = hub_blocks(g, ncols);
+  if (blockIdx.x < nhb) {
+    if (blockIdx.y != 0) return;
+    const HubItem it = hub_item(g, ncols);
+    const float acc = hub_gather<WEIGHTED>(g, X, it, ld);
+    if ((int32_t)threadIdx.x < it.cw) {
+      const int64_t e = it.v * ld + it.c0 + threadIdx.x;
+      float x = X[e], vv = MOMENTUM ? V[e] : 0.0f;
+      step_update<MAXCUT, MOMENTUM>(x, vv, acc, alpha, mu, param);
+      Xn[e] = x;
+      if (MOMENTUM) V[e] = vv;
+    }
+    return;
+  }
+  const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2, blockIdx.x - nhb);
+  if (m.row >= g.n) return;  // the whole lane group of the row
   const int64_t v = g.lo + m.row;
+  if (is_hub_row(g, v)) return;
+  float acc[VEC];
+  row_gather<VEC, WEIGHTED>(g, X, v, m.col, ld, lanes_log2, m.active, acc);
+  if (!m.active) return;
   float x[VEC], vv[VEC];
   load_vec<VEC>(X + v * ld + m.col, x);
   if (MOMENTUM) load_vec<VEC>(V + v * ld + m.col, vv);
 #pragma unroll
-  for (int i = 0; i < VEC; ++i) {
-    const float gr = grad_from_sum<MAXCUT>(acc[i], param);
-    float d = gr;
-    if (MOMENTUM) {
-      const float t = mu * vv[i];
-      vv[i] = t + gr;
-      d = vv[i];
-    }
-    const float s = alpha * d;
-    const float y = x[i] + s;
-    x[i] = clip_box<MAXCUT>(y);
-  }
+  for (int i = 0; i < VEC; ++i) step_update<MAXCUT, MOMENTUM>(x[i], vv[i], acc[i], alpha, mu, param);
   store_vec<VEC>(Xn + v * ld + m.col, x);
   if (MOMENTUM) store_vec<VEC>(V + v * ld + m.col, vv);
 }
@@ -751,26 +787,49 @@ __global__ void k_validate_cols(const int32_t *__restrict__ row_ptr, const int32
 // ---------------------------------------------------------------------------
 // differentiation
 // ---------------------------------------------------------------------------
-// Deterministic per-block column partial sums: vals[threadIdx] summed over
-// the block's rows in fixed order into part[blockIdx.x][col].
+// Deterministic per-block column partial sums: val summed over the block's
+// rows into part[prow][col .. col+VEC).  Each wavefront first adds its rows
+// with a fixed shuffle tree (lanes with equal lane % lanes), then the first
+// wavefront adds the per-wave sums in wave order.  Every thread of the block
+// must call it; it uses PARTIAL_LDS(VEC) bytes of the dynamic LDS.
+#define PARTIAL_LDS(VEC) ((size_t)(256 / 64) * 64 * (VEC) * sizeof(double))
+
 template <int VEC>
 __device__ __forceinline__ void block_column_partials(const double (&val)[VEC], bool active, int32_t col,
-                                                      int32_t ncols, int32_t lanes_log2, double *part) {
-  __shared__ double s[256 * 4];
+                                                      int32_t ncols, int32_t lanes_log2, double *part,
+                                                      int64_t prow) {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  double *s = reinterpret_cast<double *>(dyn_lds);  // [waves][64][VEC]
   const int lanes = 1 << lanes_log2;
-  const int rpb = blockDim.x >> lanes_log2;
-  const int r = threadIdx.x >> lanes_log2, l = threadIdx.x & (lanes - 1);
+  const int wave = threadIdx.x >> 6, wl = threadIdx.x & 63;
+  const int nwaves = blockDim.x >> 6;
 #pragma unroll
-  for (int i = 0; i < VEC; ++i) s[(r * lanes + l) * VEC + i] = active ? val[i] : 0.0;
+  for (int i = 0; i < VEC; ++i) {
+    double t = active ? val[i] : 0.0;
+    for (int off = 32; off >= lanes; off >>= 1) t += __shfl_down(t, off, 64);
+    if (wl < lanes) s[(wave * 64 + wl) * VEC + i] = t;
+  }
   __syncthreads();
-  if (r == 0 && col < ncols) {
+  if (wave == 0 && wl < lanes && col < ncols) {
 #pragma unroll
     for (int i = 0; i < VEC; ++i) {
       double t = 0.0;
-      for (int rr = 0; rr < rpb; ++rr) t += s[(rr * lanes + l) * VEC + i];
-      part[(int64_t)blockIdx.x * ncols + col + i] = t;
+      for (int w = 0; w < nwaves; ++w) t += s[(w * 64 + wl) * VEC + i];
+      part[prow * ncols + col + i] = t;
     }
   }
+}
+
+// Partials of the objective and gradient of Eq. (3) / (7):
+// f_b = sum_v x_v (c + eta/2 (A x)_v), grad = scale_b (c + eta A x).
+// Partial rows: one per row workgroup, then one per hub row.
+template <bool MAXCUT>
+__device__ __forceinline__ void objective_terms(float x, float acc, float param, float sc, float &gr, double &fv) {
+  const double c = MAXCUT ? -(double)param : 1.0;
+  const double eta = MAXCUT ? -2.0 : -(double)param;
+  const float gg = grad_from_sum<MAXCUT>(acc, param);
+  gr = sc * gg;
+  fv = (double)x * (c + 0.5 * eta * (double)acc);
 }
 
 template <int VEC, bool MAXCUT, bool WEIGHTED>
@@ -778,28 +837,41 @@ __global__ __launch_bounds__(256) void k_objective_grad(GraphView g, const float
                                                         const float *__restrict__ scale, float *__restrict__ grad,
                                                         double *__restrict__ part, int32_t ncols, int32_t ld,
                                                         int32_t lanes_log2, float param) {
-  const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2);
+  const int64_t nhb = hub_blocks(g, ncols);
+  const int64_t nrb = gridDim.x - nhb;  // row workgroups
+  if (blockIdx.x < nhb) {
+    if (blockIdx.y != 0) return;
+    const HubItem it = hub_item(g, ncols);
+    const float acc = hub_gather<WEIGHTED>(g, X, it, ld);
+    if ((int32_t)threadIdx.x < it.cw) {
+      const int32_t c = it.c0 + threadIdx.x;
+      const int64_t e = it.v * ld + c;
+      float gr;
+      double fv;
+      objective_terms<MAXCUT>(X[e], acc, param, scale ? scale[c] : 1.0f, gr, fv);
+      if (grad) grad[e] = gr;
+      if (part) part[(nrb + it.h) * ncols + c] = fv;
+    }
+    return;
+  }
+  const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2, blockIdx.x - nhb);
+  const bool row_mine = m.row < g.n && !is_hub_row(g, g.lo + m.row);  // uniform over the lane group
+  const bool mine = row_mine && m.active;
   double fv[VEC];
 #pragma unroll
   for (int i = 0; i < VEC; ++i) fv[i] = 0.0;
   float acc[VEC];
-  block_gather<VEC, WEIGHTED>(g, X, m, ncols, ld, lanes_log2, acc);
-  if (m.active) {
+  if (row_mine) row_gather<VEC, WEIGHTED>(g, X, g.lo + m.row, m.col, ld, lanes_log2, m.active, acc);
+  if (mine) {
     const int64_t v = g.lo + m.row;
-    float x[VEC];
+    float x[VEC], gr[VEC];
     load_vec<VEC>(X + v * ld + m.col, x);
-    const double c = MAXCUT ? -(double)param : 1.0;
-    const double eta = MAXCUT ? -2.0 : -(double)param;
-    float gr[VEC];
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) {
-      const float gg = grad_from_sum<MAXCUT>(acc[i], param);
-      gr[i] = scale ? scale[m.col + i] * gg : gg;
-      fv[i] = (double)x[i] * (c + 0.5 * eta * (double)acc[i]);
-    }
+    for (int i = 0; i < VEC; ++i)
+      objective_terms<MAXCUT>(x[i], acc[i], param, scale ? scale[m.col + i] : 1.0f, gr[i], fv[i]);
     if (grad) store_vec<VEC>(grad + v * ld + m.col, gr);
   }
-  if (part) block_column_partials<VEC>(fv, m.active, m.col, ncols, lanes_log2, part);
+  if (part) block_column_partials<VEC>(fv, mine, m.col, ncols, lanes_log2, part, blockIdx.x - nhb);
 }
 
 // Column sums of per-block partials part[nblk][ncols] in a fixed order.
@@ -818,8 +890,10 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double *__restric
   const int64_t b0 = (int64_t)blockIdx.y * per_slice;
   const int64_t b1 = min(nblk, b0 + per_slice);
   double t = 0.0;
-  if (c < ncols)
+  if (c < ncols) {
+#pragma unroll 8
     for (int64_t b = b0 + r; b < b1; b += R) t += part[b * ncols + c];
+  }
   s[threadIdx.x] = t;
   __syncthreads();
   for (int32_t off = R >> 1; off > 0; off >>= 1) {
@@ -835,54 +909,92 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double *__restric
 }
 
 // adjoint, part 1: recompute g(x_k), the clip mask, mu = mask * lam_next,
-// and per-block partials of <mu, g> for dL/dalpha
+// and partials of <mu, g> for dL/dalpha (rows as in k_objective_grad)
+template <bool MAXCUT>
+__device__ __forceinline__ void adjoint_mu(float x, float ln, float acc, float alpha, float param, float &mu,
+                                           double &dv) {
+  const float gr = grad_from_sum<MAXCUT>(acc, param);
+  const float s = alpha * gr;
+  const float z = x + s;
+  const bool mask = z >= box_lo<MAXCUT>() && z <= box_hi();
+  mu = mask ? ln : 0.0f;
+  dv = (double)mu * (double)gr;
+}
+
 template <int VEC, bool MAXCUT, bool WEIGHTED>
 __global__ __launch_bounds__(256) void k_adj_mu(GraphView g, const float *__restrict__ Xk,
                                                 const float *__restrict__ lam_next, float *__restrict__ mu_out,
                                                 double *__restrict__ part, int32_t ncols, int32_t ld,
                                                 int32_t lanes_log2, float alpha, float param) {
-  const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2);
+  const int64_t nhb = hub_blocks(g, ncols);
+  const int64_t nrb = gridDim.x - nhb;
+  if (blockIdx.x < nhb) {
+    if (blockIdx.y != 0) return;
+    const HubItem it = hub_item(g, ncols);
+    const float acc = hub_gather<WEIGHTED>(g, Xk, it, ld);
+    if ((int32_t)threadIdx.x < it.cw) {
+      const int32_t c = it.c0 + threadIdx.x;
+      const int64_t e = it.v * ld + c;
+      float mu;
+      double dv;
+      adjoint_mu<MAXCUT>(Xk[e], lam_next[e], acc, alpha, param, mu, dv);
+      mu_out[e] = mu;
+      part[(nrb + it.h) * ncols + c] = dv;
+    }
+    return;
+  }
+  const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2, blockIdx.x - nhb);
+  const bool row_mine = m.row < g.n && !is_hub_row(g, g.lo + m.row);  // uniform over the lane group
+  const bool mine = row_mine && m.active;
   double dv[VEC];
 #pragma unroll
   for (int i = 0; i < VEC; ++i) dv[i] = 0.0;
   float acc[VEC];
-  block_gather<VEC, WEIGHTED>(g, Xk, m, ncols, ld, lanes_log2, acc);
-  if (m.active) {
+  if (row_mine) row_gather<VEC, WEIGHTED>(g, Xk, g.lo + m.row, m.col, ld, lanes_log2, m.active, acc);
+  if (mine) {
     const int64_t v = g.lo + m.row;
     float x[VEC], ln[VEC], mu[VEC];
     load_vec<VEC>(Xk + v * ld + m.col, x);
     load_vec<VEC>(lam_next + v * ld + m.col, ln);
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) {
-      const float gr = grad_from_sum<MAXCUT>(acc[i], param);
-      const float s = alpha * gr;
-      const float z = x[i] + s;
-      const bool mask = z >= box_lo<MAXCUT>() && z <= box_hi();
-      mu[i] = mask ? ln[i] : 0.0f;
-      dv[i] = (double)mu[i] * (double)gr;
-    }
+    for (int i = 0; i < VEC; ++i) adjoint_mu<MAXCUT>(x[i], ln[i], acc[i], alpha, param, mu[i], dv[i]);
     store_vec<VEC>(mu_out + v * ld + m.col, mu);
   }
-  block_column_partials<VEC>(dv, m.active, m.col, ncols, lanes_log2, part);
+  block_column_partials<VEC>(dv, mine, m.col, ncols, lanes_log2, part, blockIdx.x - nhb);
 }
 
 // adjoint, part 2: lam_k = mu + alpha * (eta * (A mu))
+__device__ __forceinline__ float adjoint_lambda(float mv, float acc, float alpha, float eta) {
+  const float t1 = eta * acc;
+  const float t2 = alpha * t1;
+  return mv + t2;
+}
+
 template <int VEC, bool WEIGHTED>
 __global__ __launch_bounds__(256) void k_adj_lambda(GraphView g, const float *__restrict__ mu, float *__restrict__ lam,
                                                     int32_t ncols, int32_t ld, int32_t lanes_log2, float alpha,
                                                     float eta) {
-  const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2);
-  float acc[VEC], mv[VEC], out[VEC];
-  block_gather<VEC, WEIGHTED>(g, mu, m, ncols, ld, lanes_log2, acc);
-  if (!m.active) return;
+  const int64_t nhb = hub_blocks(g, ncols);
+  if (blockIdx.x < nhb) {
+    if (blockIdx.y != 0) return;
+    const HubItem it = hub_item(g, ncols);
+    const float acc = hub_gather<WEIGHTED>(g, mu, it, ld);
+    if ((int32_t)threadIdx.x < it.cw) {
+      const int64_t e = it.v * ld + it.c0 + threadIdx.x;
+      lam[e] = adjoint_lambda(mu[e], acc, alpha, eta);
+    }
+    return;
+  }
+  const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2, blockIdx.x - nhb);
+  if (m.row >= g.n) return;  // the whole lane group of the row
   const int64_t v = g.lo + m.row;
+  if (is_hub_row(g, v)) return;
+  float acc[VEC], mv[VEC], out[VEC];
+  row_gather<VEC, WEIGHTED>(g, mu, v, m.col, ld, lanes_log2, m.active, acc);
+  if (!m.active) return;
   load_vec<VEC>(mu + v * ld + m.col, mv);
 #pragma unroll
-  for (int i = 0; i < VEC; ++i) {
-    const float t1 = eta * acc[i];
-    const float t2 = alpha * t1;
-    out[i] = mv[i] + t2;
-  }
+  for (int i = 0; i < VEC; ++i) out[i] = adjoint_lambda(mv[i], acc[i], alpha, eta);
   store_vec<VEC>(lam + v * ld + m.col, out);
 }
 
@@ -937,10 +1049,18 @@ StepCfg default_step_cfg(int32_t ncols, int32_t ld) {
   return c;
 }
 
+// Row workgroups of a sparse-product kernel plus, in front, one workgroup per
+// (hub row, column slice).
+static inline dim3 spmm_grid(const GraphView &g, int32_t ncols, int ll, int vec) {
+  dim3 grid = grid_rows(g.n, ncols, ll, vec, 256);
+  grid.x = (unsigned)(grid.x + hub_blocks(g, ncols));
+  return grid;
+}
+
 template <int VEC, bool MC, bool W, bool M>
 static void step_t(const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols, int32_t ld, int ll,
                    float alpha, float mu, float param, hipStream_t s) {
-  MQO_LAUNCH((k_pga_step<VEC, MC, W, M>), grid_rows(g.n, ncols, ll, VEC, 256), dim3(256), 0, s, g, X, Xn, V, ncols,
+  MQO_LAUNCH((k_pga_step<VEC, MC, W, M>), spmm_grid(g, ncols, ll, VEC), dim3(256), g.nhub ? hub_lds(W) : 0, s, g, X, Xn, V, ncols,
              ld, ll, alpha, mu, param);
 }
 
@@ -1108,6 +1228,34 @@ void launch_validate_rows(const int32_t *row_ptr, int64_t n, int64_t nnz, int32_
   MQO_LAUNCH(k_validate_rows, dim3(blocks_for(n)), dim3(256), 0, s, row_ptr, n, nnz, err);
 }
 
+// hub list of one graph: each entry a row of [lo, lo + n) with degree >
+// min_deg, strictly ascending (err |= 64 otherwise)
+__global__ void k_validate_hubs(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ hubs, int64_t count,
+                                int64_t lo, int64_t n, int32_t min_deg, int32_t *err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int64_t r = hubs[i];
+  if (r < lo || r >= lo + n || (i > 0 && hubs[i - 1] >= r) || row_ptr[r + 1] - row_ptr[r] <= min_deg)
+    atomicOr(err, 64);
+}
+
+// number of rows of degree > min_deg
+__global__ void k_count_hubs(const int32_t *__restrict__ row_ptr, int64_t n, int32_t min_deg, int32_t *count) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool hub = v < n && row_ptr[v + 1] - row_ptr[v] > min_deg;
+  const unsigned long long b = __ballot(hub);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (int32_t)__popcll(b));
+}
+
+void launch_validate_hubs(const int32_t *row_ptr, const int32_t *hubs, int64_t count, int64_t lo, int64_t n,
+                          int32_t min_deg, int32_t *err, hipStream_t s) {
+  MQO_LAUNCH(k_validate_hubs, dim3(blocks_for(count)), dim3(256), 0, s, row_ptr, hubs, count, lo, n, min_deg, err);
+}
+
+void launch_count_hubs(const int32_t *row_ptr, int64_t n, int32_t min_deg, int32_t *count, hipStream_t s) {
+  MQO_LAUNCH(k_count_hubs, dim3(blocks_for(n)), dim3(256), 0, s, row_ptr, n, min_deg, count);
+}
+
 void launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, const int32_t *weight, const int64_t *voff,
                           int32_t G, int64_t n, int32_t *err, hipStream_t s) {
   MQO_LAUNCH(k_validate_cols, dim3(blocks_for(n)), dim3(256), 0, s, row_ptr, col_idx, weight, voff, G, n, err);
@@ -1118,7 +1266,8 @@ int64_t grid_blocks_x(int64_t nrows, StepCfg cfg) { return grid_rows(nrows, 1, c
 template <int VEC, bool MC, bool W>
 static void obj_t(const GraphView &g, const float *X, const float *scale, float *grad, double *part, int32_t ncols,
                   int32_t ld, int ll, float param, hipStream_t s) {
-  MQO_LAUNCH((k_objective_grad<VEC, MC, W>), grid_rows(g.n, ncols, ll, VEC, 256), dim3(256), 0, s, g, X, scale, grad,
+  MQO_LAUNCH((k_objective_grad<VEC, MC, W>), spmm_grid(g, ncols, ll, VEC), dim3(256),
+             std::max(g.nhub ? hub_lds(W) : 0, part ? PARTIAL_LDS(VEC) : 0), s, g, X, scale, grad,
              part, ncols, ld, ll, param);
 }
 
@@ -1149,30 +1298,31 @@ void launch_reduce_partials(double *part, int64_t nblk, int32_t ncols, double *o
   int32_t wlog2 = 0;
   while ((1 << wlog2) < ncols && wlog2 < 6) ++wlog2;
   const unsigned cx = (unsigned)((ncols + (1 << wlog2) - 1) >> wlog2);
-  // first level: up to REDUCE_SLICES slices of at least 64 partial rows each,
-  // written after the partials; second level: one slice
-  int64_t slices = (nblk + 63) / 64;
-  if (slices > REDUCE_SLICES) slices = REDUCE_SLICES;
-  if (slices > 1) {
-    const int64_t per = (nblk + slices - 1) / slices;
-    slices = (nblk + per - 1) / per;
-    double *lvl = part + nblk * ncols;
-    MQO_LAUNCH(k_reduce_partials, dim3(cx, (unsigned)slices), dim3(256), 0, s, part, nblk, ncols, wlog2, per, lvl, 0);
-    MQO_LAUNCH(k_reduce_partials, dim3(cx, 1), dim3(256), 0, s, lvl, slices, ncols, wlog2, slices, out,
-               (int32_t)accumulate);
-  } else {
-    MQO_LAUNCH(k_reduce_partials, dim3(cx, 1), dim3(256), 0, s, part, nblk, ncols, wlog2, nblk, out,
-               (int32_t)accumulate);
+  // levels of slices of 8 R partial rows (8 loads per thread), written after
+  // the partials, until one workgroup per column chunk finishes
+  const int64_t per = 8 * (int64_t)(256 >> wlog2);
+  const double *src = part;
+  double *next = part + nblk * ncols;
+  int64_t rows = nblk;
+  while (rows > per) {
+    int64_t p = per;
+    while ((rows + p - 1) / p > 65535) p *= 2;
+    const int64_t slices = (rows + p - 1) / p;
+    MQO_LAUNCH(k_reduce_partials, dim3(cx, (unsigned)slices), dim3(256), 0, s, src, rows, ncols, wlog2, p, next, 0);
+    src = next;
+    next += slices * ncols;
+    rows = slices;
   }
+  MQO_LAUNCH(k_reduce_partials, dim3(cx, 1), dim3(256), 0, s, src, rows, ncols, wlog2, rows, out, (int32_t)accumulate);
 }
 
 template <int VEC, bool MC, bool W>
 static void adj_t(const GraphView &g, const float *Xk, const float *lam_next, float *mu, float *lam, double *part,
                   int32_t ncols, int32_t ld, int ll, float alpha, float param, hipStream_t s) {
-  const dim3 grid = grid_rows(g.n, ncols, ll, VEC, 256);
-  MQO_LAUNCH((k_adj_mu<VEC, MC, W>), grid, dim3(256), 0, s, g, Xk, lam_next, mu, part, ncols, ld, ll, alpha, param);
+  const dim3 grid = spmm_grid(g, ncols, ll, VEC);
+  MQO_LAUNCH((k_adj_mu<VEC, MC, W>), grid, dim3(256), std::max(g.nhub ? hub_lds(W) : 0, PARTIAL_LDS(VEC)), s, g, Xk, lam_next, mu, part, ncols, ld, ll, alpha, param);
   const float eta = MC ? -2.0f : -param;
-  MQO_LAUNCH((k_adj_lambda<VEC, W>), grid, dim3(256), 0, s, g, mu, lam, ncols, ld, ll, alpha, eta);
+  MQO_LAUNCH((k_adj_lambda<VEC, W>), grid, dim3(256), g.nhub ? hub_lds(W) : 0, s, g, mu, lam, ncols, ld, ll, alpha, eta);
 }
 
 void launch_adjoint_step(bool maxcut, const GraphView &g, const float *Xk, const float *lam_next, float *mu,

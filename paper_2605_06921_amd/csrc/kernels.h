@@ -51,12 +51,16 @@ void launch_copy_best_x(const int8_t *Zb, int32_t B, const int64_t *voff, int32_
                         int8_t *out, int64_t n_total, hipStream_t s);
 void launch_gather_rowptr(const int32_t *row_ptr, const int64_t *voff, int32_t G, int32_t *out, hipStream_t s);
 void launch_validate_rows(const int32_t *row_ptr, int64_t n, int64_t nnz, int32_t *err, hipStream_t s);
+void launch_validate_hubs(const int32_t *row_ptr, const int32_t *hubs, int64_t count, int64_t lo, int64_t n,
+                          int32_t min_deg, int32_t *err, hipStream_t s);
+void launch_count_hubs(const int32_t *row_ptr, int64_t n, int32_t min_deg, int32_t *count, hipStream_t s);
 void launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, const int32_t *weight, const int64_t *voff,
                           int32_t G, int64_t n, int32_t *err, hipStream_t s);
 void launch_objective_grad(bool maxcut, const GraphView &g, const float *X, const float *scale, float *grad,
                            double *part, int32_t ncols, int32_t ld, StepCfg cfg, float param, hipStream_t s);
-// partial rows [nblk][ncols] followed by room for REDUCE_SLICES more rows
-constexpr int64_t REDUCE_SLICES = 128;
+// partial rows [nblk][ncols] followed by room for reduce_rows(nblk) more
+// rows (the reduction's intermediate levels)
+inline int64_t reduce_rows(int64_t nblk) { return nblk / 7 + 64; }
 void launch_reduce_partials(double *part, int64_t nblk, int32_t ncols, double *out, bool accumulate, hipStream_t s);
 void launch_adjoint_step(bool maxcut, const GraphView &g, const float *Xk, const float *lam_next, float *mu,
                          float *lam, double *part, int32_t ncols, int32_t ld, StepCfg cfg, float alpha, float param,

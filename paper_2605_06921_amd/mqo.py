@@ -35,7 +35,8 @@ class MqoError(RuntimeError):
 class _Graph(ctypes.Structure):
     _fields_ = [("num_graphs", ctypes.c_int32), ("vtx_offset", ctypes.POINTER(ctypes.c_int64)),
                 ("n_total", ctypes.c_int64), ("nnz_total", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
-                ("col_idx", ctypes.c_void_p), ("weight", ctypes.c_void_p)]
+                ("col_idx", ctypes.c_void_p), ("weight", ctypes.c_void_p), ("hub_min_degree", ctypes.c_int32),
+                ("hub_offset", ctypes.POINTER(ctypes.c_int64)), ("hub_rows", ctypes.c_void_p)]
 
 
 class _Params(ctypes.Structure):
@@ -132,9 +133,12 @@ class DeviceGraph:
     """A canonical CSR (or a block-diagonal batch) resident on the GPU.
 
     ``graph`` needs attributes n, row_ptr, col_idx, weight (or None) and
-    vtx_offset (int64[G+1]) as numpy arrays."""
+    vtx_offset (int64[G+1]) as numpy arrays.  Rows of degree above
+    ``hub_min_degree`` are listed as hubs (their sparse products get
+    workgroups of their own); "auto" takes max(128, 8 x mean degree), None
+    lists none.  Results do not depend on it."""
 
-    def __init__(self, graph, device="cuda"):
+    def __init__(self, graph, device="cuda", hub_min_degree="auto"):
         self.device = torch.device(device)
         self.n = int(graph.n)
         self.vtx_offset = np.ascontiguousarray(graph.vtx_offset, dtype=np.int64)
@@ -146,10 +150,30 @@ class DeviceGraph:
         self.weight = None
         if graph.weight is not None:
             self.weight = torch.from_numpy(np.ascontiguousarray(graph.weight, dtype=np.int32)).to(self.device)
+        self.hub_min_degree = hub_min_degree
+        self.hub_offset = None
+        self.hub_rows = None
+        if hub_min_degree is not None:
+            deg = np.diff(np.asarray(graph.row_ptr, dtype=np.int64))
+            if hub_min_degree == "auto":
+                hub_min_degree = max(128, 8 * int(np.ceil(deg.mean()))) if len(deg) else 128
+            self.hub_min_degree = hub_min_degree
+            hubs = np.nonzero(deg > hub_min_degree)[0]
+            if len(hubs):
+                self.hub_offset = np.searchsorted(hubs, self.vtx_offset).astype(np.int64)
+                self.hub_rows = torch.from_numpy(hubs.astype(np.int32)).to(self.device)
         self._struct = _Graph(self.num_graphs,
                               self.vtx_offset.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                               self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
-                              None if self.weight is None else self.weight.data_ptr())
+                              None if self.weight is None else self.weight.data_ptr(),
+                              0 if self.hub_offset is None else int(hub_min_degree),
+                              None if self.hub_offset is None else
+                              self.hub_offset.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                              None if self.hub_rows is None else self.hub_rows.data_ptr())
+
+    @property
+    def num_hubs(self):
+        return 0 if self.hub_offset is None else int(self.hub_offset[-1])
 
     @property
     def struct(self):

@@ -123,6 +123,28 @@ def test_solve_rejects_graph_arguments_on_host(m):
     assert L.mqo_solve_maxcut(ctypes.byref(s), ctypes.byref(p), None, ctypes.byref(r), None, 0, None) == -1
 
 
+def test_hub_list_rejected_on_host(m):
+    L = m.lib()
+    p = m.make_params(batch=2)
+    r = m._Result()
+    for hoff, mindeg, rows, status in [([1, 1], 8, True, -2), ([0, 11], 8, True, -2), ([0, 2], 8, False, -1),
+                                       ([0, 2], -1, True, -1)]:
+        s, off = _struct(m)
+        ho = np.array(hoff, dtype=np.int64)
+        s.hub_offset = ho.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        s.hub_min_degree = mindeg
+        s.hub_rows = 0x1000 if rows else None
+        assert L.mqo_solve_mis(ctypes.byref(s), ctypes.byref(p), None, ctypes.byref(r), None, 0, None) == status
+    # the objective's partial rows grow by one per hub of the largest graph
+    s, off = _struct(m, n=1000)
+    base = L.mqo_objective_workspace_size(ctypes.byref(s), 64)
+    ho = np.array([0, 40], dtype=np.int64)
+    s.hub_offset = ho.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    s.hub_min_degree = 8
+    s.hub_rows = 0x1000
+    assert L.mqo_objective_workspace_size(ctypes.byref(s), 64) >= base + 40 * 64 * 8
+
+
 def test_workspace_sizes(m):
     L = m.lib()
     s, off = _struct(m, n=1000)

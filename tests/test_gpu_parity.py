@@ -389,10 +389,12 @@ HUB_CASES = {
 
 @pytest.mark.parametrize("name", list(HUB_CASES))
 @pytest.mark.parametrize("B", [1, 3, 16, 64, 130])
-def test_hub_rows_steps_objective_adjoint(mqo, name, B):
+@pytest.mark.parametrize("hub_min_degree", [None, 8, 128])
+def test_hub_rows_steps_objective_adjoint(mqo, name, B, hub_min_degree):
     kind, g = HUB_CASES[name]
-    assert g.degrees().max() > 128  # every lane count defers such rows
-    dg = mqo.DeviceGraph(g, DEV)
+    assert g.degrees().max() > 128
+    dg = mqo.DeviceGraph(g, DEV, hub_min_degree=hub_min_degree)
+    assert (dg.num_hubs > 0) == (hub_min_degree is not None)
     param = 2.0 if kind == "mis" else 1e-3
     X0 = _x(kind, g.n, B, 141 + B)
     X = torch.from_numpy(X0).to(DEV)
@@ -424,10 +426,32 @@ def test_hub_rows_steps_objective_adjoint(mqo, name, B):
 
 
 @pytest.mark.parametrize("plan", ["batched", "plain"])
-def test_hub_rows_solve_bit_exact(mqo, plan):
+@pytest.mark.parametrize("hub_min_degree", [8, 128])
+def test_hub_rows_solve_bit_exact(mqo, plan, hub_min_degree):
     kind, g = HUB_CASES["ba_star"]
     kw = dict(batch=5, steps_per_round=20, rounds=2, alpha=0.02, rho=0.1, seed=17)
-    out = mqo.solve(kind, mqo.DeviceGraph(g, DEV), plan=plan, **kw)
+    out = mqo.solve(kind, mqo.DeviceGraph(g, DEV, hub_min_degree=hub_min_degree), plan=plan, **kw)
     ref = _oracle_solve(kind, g, kw)
     assert np.array_equal(out["traj_best_value"].cpu().numpy(), ref["traj_best_value"])
     assert np.array_equal(out["traj_best_x"].cpu().numpy(), ref["traj_best_x"])
+
+
+def test_hub_list_checked_on_device(mqo):
+    kind, g = HUB_CASES["ba_star"]
+    dg = mqo.DeviceGraph(g, DEV, hub_min_degree=8)
+    dg.validate()
+    kw = dict(batch=2, steps_per_round=2, rounds=1)
+    # drop one hub from the list: the count no longer matches
+    rows = dg.hub_rows.clone()
+    dg.hub_rows[-1] = rows[-2]
+    with pytest.raises(mqo.MqoError) as e:
+        mqo.solve(kind, dg, **kw)
+    assert e.value.status == -2
+    dg.hub_rows.copy_(rows)
+    # a listed row below the threshold
+    light = int(np.nonzero(g.degrees() <= 8)[0][0])
+    dg.hub_rows[0] = light
+    with pytest.raises(mqo.MqoError):
+        dg.validate()
+    dg.hub_rows.copy_(rows)
+    mqo.solve(kind, dg, **kw)
