@@ -390,17 +390,22 @@ __global__ __launch_bounds__(256) void k_nbr_eval(GraphView g, const int8_t *__r
   const int lanes = 1 << lanes_log2;
   if (threadIdx.x < 3 * 64) sacc[threadIdx.x / 64][threadIdx.x % 64] = 0;
   __syncthreads();
-  const RowMap m = map_rows<1>(g.n, ncols, lanes_log2);
+  // grid-stride over the row workgroups, so that the per-column global
+  // atomics are paid once per resident workgroup, not once per 256 rows
+  const int64_t nrb = (g.n + (blockDim.x >> lanes_log2) - 1) / (blockDim.x >> lanes_log2);
   long long a[3] = {0, 0, 0};
-  if (m.active) {
+  for (int64_t bx = blockIdx.x; bx < nrb; bx += gridDim.x) {
+    const RowMap m = map_rows<1>(g.n, ncols, lanes_log2, bx);
+    if (!m.active) continue;
     const int64_t v = g.lo + m.row;
     const int32_t beg = g.row_ptr[v], end = g.row_ptr[v + 1];
     int32_t s = 0, wsum = 0;
+#pragma unroll 4
     for (int32_t j = beg; j < end; ++j) {
-      const int64_t u = g.col_idx[j];
+      const int64_t u = __builtin_nontemporal_load(g.col_idx + j);
       const int32_t zu = Z[u * ld + m.col];
       if (WEIGHTED) {
-        const int32_t w = g.weight[j];
+        const int32_t w = __builtin_nontemporal_load(g.weight + j);
         s += w * zu;
         wsum += w;
       } else {
@@ -411,11 +416,11 @@ __global__ __launch_bounds__(256) void k_nbr_eval(GraphView g, const int8_t *__r
     if (NB) NB[v * ld + m.col] = s;
     const int32_t zv = Z[v * ld + m.col];
     if (MAXCUT) {
-      a[0] = (long long)wsum - (long long)zv * s;
+      a[0] += (long long)wsum - (long long)zv * s;
     } else {
-      a[0] = zv;
-      a[1] = zv ? s : 0;
-      a[2] = (zv == 0 && s == 0) ? 1 : 0;
+      a[0] += zv;
+      a[1] += zv ? s : 0;
+      a[2] += (zv == 0 && s == 0) ? 1 : 0;
     }
   }
   const int width = lanes < 64 ? lanes : 64;
@@ -486,8 +491,10 @@ __global__ __launch_bounds__(256) void k_ls_select(GraphView g, const int8_t *__
   int32_t k1;
   const bool p = ls_candidate_t<MAXCUT>(Z[e], NB[e], k1);
   int8_t f = 0;
+  // one store of the "still searching" flag per wavefront
+  const unsigned long long bal = __ballot(p);
+  if (p && (int)(threadIdx.x & 63) == __builtin_ctzll(bal)) *active = 1;
   if (p) {
-    *active = 1;
     const uint32_t pv = PRIO[e];
     f = 1;
     const int32_t beg = g.row_ptr[v], end = g.row_ptr[v + 1];
@@ -532,11 +539,31 @@ __global__ __launch_bounds__(256) void k_accept_copy(const int8_t *__restrict__ 
                                                      const int64_t *__restrict__ value,
                                                      const int64_t *__restrict__ best, int64_t lo, int64_t n,
                                                      int32_t ncols, int32_t ld, int32_t ldb, int32_t first) {
+  // one row per lane group of up to 64 lanes, 4 columns per lane when the
+  // layout allows 4-byte accesses
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n * ncols) return;
-  const int32_t c = (int32_t)(idx % ncols);
-  const int64_t v = lo + idx / ncols;
-  if (first || value[c] > best[c]) Zb[v * ldb + c] = Z[v * ld + c];
+  const bool quad = (ncols & 3) == 0 && (ld & 3) == 0 && (ldb & 3) == 0 && (((uintptr_t)Z | (uintptr_t)Zb) & 3) == 0;
+  const int32_t per_row = quad ? ncols >> 2 : ncols;
+  if (idx >= n * per_row) return;
+  const int64_t v = lo + idx / per_row;
+  const int32_t q = (int32_t)(idx % per_row);
+  if (quad) {
+    const int32_t c = q << 2;
+    const uint32_t zq = *reinterpret_cast<const uint32_t *>(Z + v * ld + c);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(Zb + v * ldb + c);
+    bool take[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) take[i] = first || value[c + i] > best[c + i];
+    if (take[0] && take[1] && take[2] && take[3]) {
+      *dst = zq;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (take[i]) Zb[v * ldb + c + i] = (int8_t)(zq >> (8 * i));
+    }
+  } else if (first || value[q] > best[q]) {
+    Zb[v * ldb + q] = Z[v * ld + q];
+  }
 }
 
 __global__ void k_accept_best(const int64_t *__restrict__ value, int64_t *__restrict__ best, int32_t ncols,
@@ -1137,7 +1164,8 @@ void launch_evaluate(bool maxcut, const GraphView &g, const int8_t *Z, int32_t *
                      int64_t *conflicts, int8_t *fixed, int32_t ncols, int32_t ld, hipStream_t s) {
   launch_fill_i64(reinterpret_cast<int64_t *>(acc), 3LL * ncols, 0, s);
   const int ll = lanes_log2_for(ncols);
-  const dim3 grid = grid_rows(g.n, ncols, ll, 1, 256);
+  dim3 grid = grid_rows(g.n, ncols, ll, 1, 256);
+  if (grid.x > 2048) grid.x = 2048;  // workgroups stride over the rows
   unsigned long long *a = reinterpret_cast<unsigned long long *>(acc);
   const bool w = g.weight != nullptr;
   if (maxcut) {
@@ -1179,8 +1207,9 @@ void launch_ls_iteration(bool maxcut, const GraphView &g, int8_t *Z, int32_t *NB
 
 void launch_accept(const int8_t *Z, int8_t *Zb, const int64_t *value, int64_t *best, int64_t lo, int64_t n,
                    int32_t ncols, int32_t ld, int32_t ldb, bool first, hipStream_t s) {
-  MQO_LAUNCH(k_accept_copy, dim3(blocks_for(n * ncols)), dim3(256), 0, s, Z, Zb, value, best, lo, n, ncols, ld, ldb,
-             (int32_t)first);
+  const bool quad = (ncols & 3) == 0 && (ld & 3) == 0 && (ldb & 3) == 0 && (((uintptr_t)Z | (uintptr_t)Zb) & 3) == 0;
+  MQO_LAUNCH(k_accept_copy, dim3(blocks_for(n * (quad ? ncols >> 2 : ncols))), dim3(256), 0, s, Z, Zb, value, best, lo,
+             n, ncols, ld, ldb, (int32_t)first);
   MQO_LAUNCH(k_accept_best, dim3(blocks_for(ncols)), dim3(256), 0, s, value, best, ncols, (int32_t)first);
 }
 
