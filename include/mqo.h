@@ -83,6 +83,10 @@ typedef struct {
   int32_t hub_min_degree;     /* >= 0                                         */
   const int64_t *hub_offset;  /* (host) [G+1], hub_offset[0] = 0, or NULL     */
   const int32_t *hub_rows;    /* [hub_offset[G]]                              */
+  /* Optional hint: the largest row degree, or 0 if unknown.  It only picks
+   * kernel shapes (near-regular graphs take rows in pairs); results do not
+   * depend on it, and the solves measure the degree themselves. */
+  int32_t max_degree;
 } mqo_graph;
 
 /* Search parameters.  Fill with mqo_params_default() first. */

@@ -125,6 +125,7 @@ int check_graph_args(const mqo_graph *g, bool need_weight_free) {
     }
     if (g->hub_offset[g->num_graphs] > 0 && !g->hub_rows) return fail(MQO_ERR_INVALID_ARG, "hub_rows is NULL");
   }
+  if (g->max_degree < 0) return fail(MQO_ERR_INVALID_ARG, "max_degree must be >= 0 (0 = unknown)");
   return MQO_OK;
 }
 
@@ -223,7 +224,9 @@ T *at(void *ws, size_t off) {
   return reinterpret_cast<T *>(reinterpret_cast<char *>(ws) + off);
 }
 
-GraphView view_of(const mqo_graph *g, int32_t i) {
+// max_deg: the largest degree if known (a solve measures it), else -1 for
+// the caller's hint g->max_degree (0 = unknown)
+GraphView view_of(const mqo_graph *g, int32_t i, int32_t max_deg = -1) {
   GraphView v;
   v.row_ptr = g->row_ptr;
   v.col_idx = g->col_idx;
@@ -238,6 +241,10 @@ GraphView view_of(const mqo_graph *g, int32_t i) {
     v.nhub = (int32_t)(g->hub_offset[i + 1] - g->hub_offset[i]);
     v.hub_deg = g->hub_min_degree;
   }
+  // near-regular (mean degree >= 0.9 x max): row pairs of equal degree are
+  // the common case
+  const int64_t md = max_deg >= 0 ? max_deg : g->max_degree;
+  v.pairs = md > 0 && 10 * g->nnz_total >= 9 * g->n_total * md ? 1 : 0;
   return v;
 }
 
@@ -347,7 +354,7 @@ int k_of(const Solve &S, int64_t n) { return (int)std::floor(S.p->rho * (double)
 // initial iterate of every graph into X ([n][B]) unless x0 is given
 int init_x(Solve &S, float *X) {
   for (int32_t gi = 0; gi < S.G; ++gi) {
-    const GraphView gv = view_of(S.g, gi);
+    const GraphView gv = view_of(S.g, gi, S.max_deg);
     if (S.p->init_mode == MQO_INIT_UNIFORM)
       launch_init_uniform(S.maxcut, X, gv.lo, gv.n, S.B, S.B, S.p->seed, (uint64_t)gi * S.B, S.s);
     else
@@ -496,7 +503,7 @@ int solve_batched(Solve &S, int32_t *rounds_done) {
       if (now_s() - t0 >= S.p->time_budget_s) break;
     }
     for (int32_t gi = 0; gi < S.G; ++gi) {
-      const GraphView gv = view_of(S.g, gi);
+      const GraphView gv = view_of(S.g, gi, S.max_deg);
       const int64_t t = (int64_t)gi * B;
       TRY(grid_round(S, loops[gi], use_graph, gv, r, X, Xt, V, Z, Zb, B, NB, PRIO, F, value + t, best + t, B, B,
                      (uint64_t)t));
@@ -525,7 +532,7 @@ int solve_plain(Solve &S, int32_t *rounds_done) {
   int32_t rmax = 0;
   bool out_of_time = false;
   for (int32_t gi = 0; gi < S.G && !out_of_time; ++gi) {
-    const GraphView gv = view_of(S.g, gi);
+    const GraphView gv = view_of(S.g, gi, S.max_deg);
     StepLoop loop;  // the captured step loop serves every trajectory of the graph
     for (int32_t b = 0; b < B && !out_of_time; ++b) {
       const int64_t t = (int64_t)gi * B + b;
@@ -938,7 +945,7 @@ int mqo_objective_grad(const mqo_graph *g, mqo_objective obj, float param, const
     const float *sc = scale ? scale + (int64_t)gi * B : nullptr;
     double *part = f_out ? reinterpret_cast<double *>(ws) : nullptr;
     launch_objective_grad(mc, gv, X, sc, grad_out, part, B, B, cfg, param, s);
-    if (f_out) launch_reduce_partials(part, grid_blocks_x(gv.n, cfg) + gv.nhub, B, f_out + (int64_t)gi * B, false, s);
+    if (f_out) launch_reduce_partials(part, spmm_row_blocks(gv, cfg) + gv.nhub, B, f_out + (int64_t)gi * B, false, s);
   }
   HIP_TRY(hipGetLastError());
   return MQO_OK;
@@ -1012,7 +1019,7 @@ int mqo_pga_unrolled_backward(const mqo_graph *g, mqo_objective obj, float param
   const int32_t nseg = K / ckpt_every;
   for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
     const GraphView gv = view_of(g, gi);
-    const int64_t nblk = grid_blocks_x(gv.n, cfg) + gv.nhub;
+    const int64_t nblk = spmm_row_blocks(gv, cfg) + gv.nhub;
     launch_copy_f32(dL_dXK + gv.lo * B, lamA + gv.lo * B, gv.n * B, s);
     launch_fill_i64(reinterpret_cast<int64_t *>(dL_dalpha + (int64_t)gi * B), B, 0, s);  // +0.0
     float *cur = lamA, *nxt = lamB;

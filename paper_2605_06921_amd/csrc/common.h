@@ -170,6 +170,7 @@ struct GraphView {
   const int32_t *hubs;    // global ids of the rows of degree > hub_deg, ascending
   int32_t nhub;           // 0 = no hub list
   int32_t hub_deg;
+  int32_t pairs;          // 1: near-regular graph, lane groups take rows in pairs
 };
 
 // Row x column mapping: W lanes per row (power of two <= 64), each lane

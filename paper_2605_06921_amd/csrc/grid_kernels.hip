@@ -202,6 +202,43 @@ __device__ __forceinline__ void row_gather(const GraphView &g, const float *__re
   }
 }
 
+// Two rows of equal degree summed in lockstep by one lane group (4 or more
+// lanes per row): twice the independent gathers in flight per lane.  Each
+// row's sum keeps its own ascending CSR order.
+template <int VEC, bool WEIGHTED>
+__device__ __forceinline__ void row_gather2(const GraphView &g, const float *__restrict__ X, int64_t v0, int64_t v1,
+                                            int32_t col, int32_t ld, int32_t lanes_log2, bool colok,
+                                            float (&a0)[VEC], float (&a1)[VEC]) {
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) {
+    a0[i] = 0.0f;
+    a1[i] = 0.0f;
+  }
+  const int32_t b0 = g.row_ptr[v0], e0 = g.row_ptr[v0 + 1];
+  const int32_t b1 = g.row_ptr[v1];
+  const int32_t lanes = 1 << lanes_log2;
+  const int32_t lane = threadIdx.x & (lanes - 1);
+  for (int32_t j = 0; j < e0 - b0; j += lanes) {
+    const int32_t cnt = min(lanes, e0 - b0 - j);
+    const bool have = lane < cnt;
+    const int32_t u0l = have ? __builtin_nontemporal_load(g.col_idx + b0 + j + lane) : 0;
+    const int32_t u1l = have ? __builtin_nontemporal_load(g.col_idx + b1 + j + lane) : 0;
+    const int32_t w0l = WEIGHTED && have ? __builtin_nontemporal_load(g.weight + b0 + j + lane) : 1;
+    const int32_t w1l = WEIGHTED && have ? __builtin_nontemporal_load(g.weight + b1 + j + lane) : 1;
+#pragma unroll 4
+    for (int32_t k = 0; k < cnt; ++k) {
+      const int64_t u0 = __shfl(u0l, k, lanes), u1 = __shfl(u1l, k, lanes);
+      const int32_t w0 = WEIGHTED ? __shfl(w0l, k, lanes) : 1, w1 = WEIGHTED ? __shfl(w1l, k, lanes) : 1;
+      if (!colok) continue;
+      float x0[VEC], x1[VEC];
+      load_vec<VEC>(X + u0 * ld + col, x0);
+      load_vec<VEC>(X + u1 * ld + col, x1);
+      add_neighbour<VEC, WEIGHTED>(a0, x0, w0);
+      add_neighbour<VEC, WEIGHTED>(a1, x1, w1);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Hub rows.  A row of degree above g.hub_deg (listed in g.hubs) is not
 // handled by a lane group: the first hub_blocks(g, ncols) workgroups of a
@@ -288,6 +325,39 @@ __device__ __forceinline__ bool is_hub_row(const GraphView &g, int64_t v) {
   return g.nhub > 0 && g.row_ptr[v + 1] - g.row_ptr[v] > g.hub_deg;
 }
 
+// The ROWS rows of a lane group in row workgroup bx (rows grp and grp + rpb
+// of a ROWS * rpb-row block; rpb = lane groups per workgroup), whether the
+// group owns each (in range, not a hub; uniform over the group), and their
+// neighbour sums.  Every lane of the group must call it.  ROWS = 2 is
+// launched for near-regular graphs only: two rows of equal degree go in
+// lockstep, otherwise one after the other.
+template <int VEC, bool WEIGHTED, int ROWS>
+__device__ __forceinline__ void group_gather(const GraphView &g, const float *__restrict__ X, int64_t bx,
+                                             int32_t ncols, int32_t ld, int32_t lanes_log2, int64_t (&v)[ROWS],
+                                             bool (&own)[ROWS], int32_t &col, float (&acc)[ROWS][VEC]) {
+  const int32_t lanes = 1 << lanes_log2;
+  const int32_t rpb = blockDim.x >> lanes_log2;
+  const int64_t r0 = bx * ROWS * rpb + (threadIdx.x >> lanes_log2);
+  col = (int32_t)(blockIdx.y * lanes + (threadIdx.x & (lanes - 1))) * VEC;
+  const bool colok = col < ncols;
+#pragma unroll
+  for (int k = 0; k < ROWS; ++k) {
+    const int64_t r = r0 + (int64_t)k * rpb;
+    v[k] = g.lo + r;
+    own[k] = r < g.n && !is_hub_row(g, v[k]);
+  }
+  if constexpr (ROWS == 2) {
+    if (own[0] && own[1] &&
+        g.row_ptr[v[0] + 1] - g.row_ptr[v[0]] == g.row_ptr[v[1] + 1] - g.row_ptr[v[1]]) {
+      row_gather2<VEC, WEIGHTED>(g, X, v[0], v[1], col, ld, lanes_log2, colok, acc[0], acc[1]);
+      return;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < ROWS; ++k)
+    if (own[k]) row_gather<VEC, WEIGHTED>(g, X, v[k], col, ld, lanes_log2, colok, acc[k]);
+}
+
 // One PGA step of Sec. 3 (with optional heavy-ball momentum) for a single column.
 template <bool MAXCUT, bool MOMENTUM>
 __device__ __forceinline__ void step_update(float &x, float &vv, float acc, float alpha, float mu, float param) {
@@ -303,7 +373,7 @@ __device__ __forceinline__ void step_update(float &x, float &vv, float acc, floa
   x = clip_box<MAXCUT>(y);
 }
 
-template <int VEC, bool MAXCUT, bool WEIGHTED, bool MOMENTUM>
+template <int VEC, bool MAXCUT, bool WEIGHTED, bool MOMENTUM, int ROWS>
 __global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__restrict__ X, float *__restrict__ Xn,
                                                   float *__restrict__ V, int32_t ncols, int32_t ld,
                                                   int32_t lanes_log2, float alpha, float mu, float param) {
@@ -321,20 +391,23 @@ __global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__re
     }
     return;
   }
-  const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2, blockIdx.x - nhb);
-  if (m.row >= g.n) return;  // the whole lane group of the row
-  const int64_t v = g.lo + m.row;
-  if (is_hub_row(g, v)) return;
-  float acc[VEC];
-  row_gather<VEC, WEIGHTED>(g, X, v, m.col, ld, lanes_log2, m.active, acc);
-  if (!m.active) return;
-  float x[VEC], vv[VEC];
-  load_vec<VEC>(X + v * ld + m.col, x);
-  if (MOMENTUM) load_vec<VEC>(V + v * ld + m.col, vv);
+  int64_t v[ROWS];
+  bool own[ROWS];
+  int32_t col;
+  float acc[ROWS][VEC];
+  group_gather<VEC, WEIGHTED, ROWS>(g, X, blockIdx.x - nhb, ncols, ld, lanes_log2, v, own, col, acc);
+  if (col >= ncols) return;
 #pragma unroll
-  for (int i = 0; i < VEC; ++i) step_update<MAXCUT, MOMENTUM>(x[i], vv[i], acc[i], alpha, mu, param);
-  store_vec<VEC>(Xn + v * ld + m.col, x);
-  if (MOMENTUM) store_vec<VEC>(V + v * ld + m.col, vv);
+  for (int k = 0; k < ROWS; ++k) {
+    if (!own[k]) continue;
+    float x[VEC], vv[VEC];
+    load_vec<VEC>(X + v[k] * ld + col, x);
+    if (MOMENTUM) load_vec<VEC>(V + v[k] * ld + col, vv);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) step_update<MAXCUT, MOMENTUM>(x[i], vv[i], acc[k][i], alpha, mu, param);
+    store_vec<VEC>(Xn + v[k] * ld + col, x);
+    if (MOMENTUM) store_vec<VEC>(V + v[k] * ld + col, vv);
+  }
 }
 
 __global__ void k_copy_f32(const float *__restrict__ a, float *__restrict__ b, int64_t count) {
@@ -859,7 +932,7 @@ __device__ __forceinline__ void objective_terms(float x, float acc, float param,
   fv = (double)x * (c + 0.5 * eta * (double)acc);
 }
 
-template <int VEC, bool MAXCUT, bool WEIGHTED>
+template <int VEC, bool MAXCUT, bool WEIGHTED, int ROWS>
 __global__ __launch_bounds__(256) void k_objective_grad(GraphView g, const float *__restrict__ X,
                                                         const float *__restrict__ scale, float *__restrict__ grad,
                                                         double *__restrict__ part, int32_t ncols, int32_t ld,
@@ -881,24 +954,30 @@ __global__ __launch_bounds__(256) void k_objective_grad(GraphView g, const float
     }
     return;
   }
-  const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2, blockIdx.x - nhb);
-  const bool row_mine = m.row < g.n && !is_hub_row(g, g.lo + m.row);  // uniform over the lane group
-  const bool mine = row_mine && m.active;
+  int64_t v[ROWS];
+  bool own[ROWS];
+  int32_t col;
+  float acc[ROWS][VEC];
+  group_gather<VEC, WEIGHTED, ROWS>(g, X, blockIdx.x - nhb, ncols, ld, lanes_log2, v, own, col, acc);
   double fv[VEC];
 #pragma unroll
   for (int i = 0; i < VEC; ++i) fv[i] = 0.0;
-  float acc[VEC];
-  if (row_mine) row_gather<VEC, WEIGHTED>(g, X, g.lo + m.row, m.col, ld, lanes_log2, m.active, acc);
-  if (mine) {
-    const int64_t v = g.lo + m.row;
-    float x[VEC], gr[VEC];
-    load_vec<VEC>(X + v * ld + m.col, x);
+  bool any = false;
 #pragma unroll
-    for (int i = 0; i < VEC; ++i)
-      objective_terms<MAXCUT>(x[i], acc[i], param, scale ? scale[m.col + i] : 1.0f, gr[i], fv[i]);
-    if (grad) store_vec<VEC>(grad + v * ld + m.col, gr);
+  for (int k = 0; k < ROWS; ++k) {
+    if (!own[k] || col >= ncols) continue;
+    any = true;
+    float x[VEC], gr[VEC];
+    load_vec<VEC>(X + v[k] * ld + col, x);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      double f;
+      objective_terms<MAXCUT>(x[i], acc[k][i], param, scale ? scale[col + i] : 1.0f, gr[i], f);
+      fv[i] += f;
+    }
+    if (grad) store_vec<VEC>(grad + v[k] * ld + col, gr);
   }
-  if (part) block_column_partials<VEC>(fv, mine, m.col, ncols, lanes_log2, part, blockIdx.x - nhb);
+  if (part) block_column_partials<VEC>(fv, any, col, ncols, lanes_log2, part, blockIdx.x - nhb);
 }
 
 // Column sums of per-block partials part[nblk][ncols] in a fixed order.
@@ -948,7 +1027,7 @@ __device__ __forceinline__ void adjoint_mu(float x, float ln, float acc, float a
   dv = (double)mu * (double)gr;
 }
 
-template <int VEC, bool MAXCUT, bool WEIGHTED>
+template <int VEC, bool MAXCUT, bool WEIGHTED, int ROWS>
 __global__ __launch_bounds__(256) void k_adj_mu(GraphView g, const float *__restrict__ Xk,
                                                 const float *__restrict__ lam_next, float *__restrict__ mu_out,
                                                 double *__restrict__ part, int32_t ncols, int32_t ld,
@@ -970,24 +1049,31 @@ __global__ __launch_bounds__(256) void k_adj_mu(GraphView g, const float *__rest
     }
     return;
   }
-  const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2, blockIdx.x - nhb);
-  const bool row_mine = m.row < g.n && !is_hub_row(g, g.lo + m.row);  // uniform over the lane group
-  const bool mine = row_mine && m.active;
+  int64_t v[ROWS];
+  bool own[ROWS];
+  int32_t col;
+  float acc[ROWS][VEC];
+  group_gather<VEC, WEIGHTED, ROWS>(g, Xk, blockIdx.x - nhb, ncols, ld, lanes_log2, v, own, col, acc);
   double dv[VEC];
 #pragma unroll
   for (int i = 0; i < VEC; ++i) dv[i] = 0.0;
-  float acc[VEC];
-  if (row_mine) row_gather<VEC, WEIGHTED>(g, Xk, g.lo + m.row, m.col, ld, lanes_log2, m.active, acc);
-  if (mine) {
-    const int64_t v = g.lo + m.row;
-    float x[VEC], ln[VEC], mu[VEC];
-    load_vec<VEC>(Xk + v * ld + m.col, x);
-    load_vec<VEC>(lam_next + v * ld + m.col, ln);
+  bool any = false;
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) adjoint_mu<MAXCUT>(x[i], ln[i], acc[i], alpha, param, mu[i], dv[i]);
-    store_vec<VEC>(mu_out + v * ld + m.col, mu);
+  for (int k = 0; k < ROWS; ++k) {
+    if (!own[k] || col >= ncols) continue;
+    any = true;
+    float x[VEC], ln[VEC], mu[VEC];
+    load_vec<VEC>(Xk + v[k] * ld + col, x);
+    load_vec<VEC>(lam_next + v[k] * ld + col, ln);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      double d;
+      adjoint_mu<MAXCUT>(x[i], ln[i], acc[k][i], alpha, param, mu[i], d);
+      dv[i] += d;
+    }
+    store_vec<VEC>(mu_out + v[k] * ld + col, mu);
   }
-  block_column_partials<VEC>(dv, mine, m.col, ncols, lanes_log2, part, blockIdx.x - nhb);
+  block_column_partials<VEC>(dv, any, col, ncols, lanes_log2, part, blockIdx.x - nhb);
 }
 
 // adjoint, part 2: lam_k = mu + alpha * (eta * (A mu))
@@ -997,7 +1083,7 @@ __device__ __forceinline__ float adjoint_lambda(float mv, float acc, float alpha
   return mv + t2;
 }
 
-template <int VEC, bool WEIGHTED>
+template <int VEC, bool WEIGHTED, int ROWS>
 __global__ __launch_bounds__(256) void k_adj_lambda(GraphView g, const float *__restrict__ mu, float *__restrict__ lam,
                                                     int32_t ncols, int32_t ld, int32_t lanes_log2, float alpha,
                                                     float eta) {
@@ -1012,17 +1098,21 @@ __global__ __launch_bounds__(256) void k_adj_lambda(GraphView g, const float *__
     }
     return;
   }
-  const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2, blockIdx.x - nhb);
-  if (m.row >= g.n) return;  // the whole lane group of the row
-  const int64_t v = g.lo + m.row;
-  if (is_hub_row(g, v)) return;
-  float acc[VEC], mv[VEC], out[VEC];
-  row_gather<VEC, WEIGHTED>(g, mu, v, m.col, ld, lanes_log2, m.active, acc);
-  if (!m.active) return;
-  load_vec<VEC>(mu + v * ld + m.col, mv);
+  int64_t v[ROWS];
+  bool own[ROWS];
+  int32_t col;
+  float acc[ROWS][VEC];
+  group_gather<VEC, WEIGHTED, ROWS>(g, mu, blockIdx.x - nhb, ncols, ld, lanes_log2, v, own, col, acc);
+  if (col >= ncols) return;
 #pragma unroll
-  for (int i = 0; i < VEC; ++i) out[i] = adjoint_lambda(mv[i], acc[i], alpha, eta);
-  store_vec<VEC>(lam + v * ld + m.col, out);
+  for (int k = 0; k < ROWS; ++k) {
+    if (!own[k]) continue;
+    float mv[VEC], out[VEC];
+    load_vec<VEC>(mu + v[k] * ld + col, mv);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) out[i] = adjoint_lambda(mv[i], acc[k][i], alpha, eta);
+    store_vec<VEC>(lam + v[k] * ld + col, out);
+  }
 }
 
 // ===========================================================================
@@ -1078,8 +1168,13 @@ StepCfg default_step_cfg(int32_t ncols, int32_t ld) {
 
 // Row workgroups of a sparse-product kernel plus, in front, one workgroup per
 // (hub row, column slice).
+// rows per lane group of the sparse-product kernels: pairs on near-regular
+// graphs when a row has 4 or more lanes (the lockstep gather shuffles indices)
+static inline int spmm_rows(const GraphView &g, int ll) { return g.pairs && ll >= 2 ? 2 : 1; }
+
 static inline dim3 spmm_grid(const GraphView &g, int32_t ncols, int ll, int vec) {
-  dim3 grid = grid_rows(g.n, ncols, ll, vec, 256);
+  const int rows = spmm_rows(g, ll);
+  dim3 grid = grid_rows((g.n + rows - 1) / rows, ncols, ll, vec, 256);
   grid.x = (unsigned)(grid.x + hub_blocks(g, ncols));
   return grid;
 }
@@ -1087,8 +1182,13 @@ static inline dim3 spmm_grid(const GraphView &g, int32_t ncols, int ll, int vec)
 template <int VEC, bool MC, bool W, bool M>
 static void step_t(const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols, int32_t ld, int ll,
                    float alpha, float mu, float param, hipStream_t s) {
-  MQO_LAUNCH((k_pga_step<VEC, MC, W, M>), spmm_grid(g, ncols, ll, VEC), dim3(256), g.nhub ? hub_lds(W) : 0, s, g, X, Xn, V, ncols,
-             ld, ll, alpha, mu, param);
+  const size_t lds = g.nhub ? hub_lds(W) : 0;
+  if (spmm_rows(g, ll) == 2)
+    MQO_LAUNCH((k_pga_step<VEC, MC, W, M, 2>), spmm_grid(g, ncols, ll, VEC), dim3(256), lds, s, g, X, Xn, V, ncols,
+               ld, ll, alpha, mu, param);
+  else
+    MQO_LAUNCH((k_pga_step<VEC, MC, W, M, 1>), spmm_grid(g, ncols, ll, VEC), dim3(256), lds, s, g, X, Xn, V, ncols,
+               ld, ll, alpha, mu, param);
 }
 
 template <int VEC>
@@ -1292,12 +1392,21 @@ void launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, const 
 
 int64_t grid_blocks_x(int64_t nrows, StepCfg cfg) { return grid_rows(nrows, 1, cfg.lanes_log2, 1, 256).x; }
 
+int64_t spmm_row_blocks(const GraphView &g, StepCfg cfg) {
+  const int rows = spmm_rows(g, cfg.lanes_log2);
+  return grid_rows((g.n + rows - 1) / rows, 1, cfg.lanes_log2, 1, 256).x;
+}
+
 template <int VEC, bool MC, bool W>
 static void obj_t(const GraphView &g, const float *X, const float *scale, float *grad, double *part, int32_t ncols,
                   int32_t ld, int ll, float param, hipStream_t s) {
-  MQO_LAUNCH((k_objective_grad<VEC, MC, W>), spmm_grid(g, ncols, ll, VEC), dim3(256),
-             std::max(g.nhub ? hub_lds(W) : 0, part ? PARTIAL_LDS(VEC) : 0), s, g, X, scale, grad,
-             part, ncols, ld, ll, param);
+  const size_t lds = std::max(g.nhub ? hub_lds(W) : 0, part ? PARTIAL_LDS(VEC) : 0);
+  if (spmm_rows(g, ll) == 2)
+    MQO_LAUNCH((k_objective_grad<VEC, MC, W, 2>), spmm_grid(g, ncols, ll, VEC), dim3(256), lds, s, g, X, scale, grad,
+               part, ncols, ld, ll, param);
+  else
+    MQO_LAUNCH((k_objective_grad<VEC, MC, W, 1>), spmm_grid(g, ncols, ll, VEC), dim3(256), lds, s, g, X, scale, grad,
+               part, ncols, ld, ll, param);
 }
 
 void launch_objective_grad(bool maxcut, const GraphView &g, const float *X, const float *scale, float *grad,
@@ -1349,9 +1458,17 @@ template <int VEC, bool MC, bool W>
 static void adj_t(const GraphView &g, const float *Xk, const float *lam_next, float *mu, float *lam, double *part,
                   int32_t ncols, int32_t ld, int ll, float alpha, float param, hipStream_t s) {
   const dim3 grid = spmm_grid(g, ncols, ll, VEC);
-  MQO_LAUNCH((k_adj_mu<VEC, MC, W>), grid, dim3(256), std::max(g.nhub ? hub_lds(W) : 0, PARTIAL_LDS(VEC)), s, g, Xk, lam_next, mu, part, ncols, ld, ll, alpha, param);
+  const size_t lds_mu = std::max(g.nhub ? hub_lds(W) : 0, PARTIAL_LDS(VEC)), lds_lam = g.nhub ? hub_lds(W) : 0;
   const float eta = MC ? -2.0f : -param;
-  MQO_LAUNCH((k_adj_lambda<VEC, W>), grid, dim3(256), g.nhub ? hub_lds(W) : 0, s, g, mu, lam, ncols, ld, ll, alpha, eta);
+  if (spmm_rows(g, ll) == 2) {
+    MQO_LAUNCH((k_adj_mu<VEC, MC, W, 2>), grid, dim3(256), lds_mu, s, g, Xk, lam_next, mu, part, ncols, ld, ll, alpha,
+               param);
+    MQO_LAUNCH((k_adj_lambda<VEC, W, 2>), grid, dim3(256), lds_lam, s, g, mu, lam, ncols, ld, ll, alpha, eta);
+  } else {
+    MQO_LAUNCH((k_adj_mu<VEC, MC, W, 1>), grid, dim3(256), lds_mu, s, g, Xk, lam_next, mu, part, ncols, ld, ll, alpha,
+               param);
+    MQO_LAUNCH((k_adj_lambda<VEC, W, 1>), grid, dim3(256), lds_lam, s, g, mu, lam, ncols, ld, ll, alpha, eta);
+  }
 }
 
 void launch_adjoint_step(bool maxcut, const GraphView &g, const float *Xk, const float *lam_next, float *mu,

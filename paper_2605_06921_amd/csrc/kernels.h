@@ -17,6 +17,8 @@ struct StepCfg {
 
 StepCfg default_step_cfg(int32_t ncols, int32_t ld);
 int64_t grid_blocks_x(int64_t nrows, StepCfg cfg);
+// row workgroups of a sparse-product launch over graph g (without hub workgroups)
+int64_t spmm_row_blocks(const GraphView &g, StepCfg cfg);
 
 void launch_init_uniform(bool maxcut, float *X, int64_t lo, int64_t n, int32_t ncols, int32_t ld, uint64_t seed,
                          uint64_t traj0, hipStream_t s);

@@ -36,7 +36,8 @@ class _Graph(ctypes.Structure):
     _fields_ = [("num_graphs", ctypes.c_int32), ("vtx_offset", ctypes.POINTER(ctypes.c_int64)),
                 ("n_total", ctypes.c_int64), ("nnz_total", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
                 ("col_idx", ctypes.c_void_p), ("weight", ctypes.c_void_p), ("hub_min_degree", ctypes.c_int32),
-                ("hub_offset", ctypes.POINTER(ctypes.c_int64)), ("hub_rows", ctypes.c_void_p)]
+                ("hub_offset", ctypes.POINTER(ctypes.c_int64)), ("hub_rows", ctypes.c_void_p),
+                ("max_degree", ctypes.c_int32)]
 
 
 class _Params(ctypes.Structure):
@@ -153,8 +154,9 @@ class DeviceGraph:
         self.hub_min_degree = hub_min_degree
         self.hub_offset = None
         self.hub_rows = None
+        deg = np.diff(np.asarray(graph.row_ptr, dtype=np.int64))
+        self.max_degree = int(deg.max()) if len(deg) else 0
         if hub_min_degree is not None:
-            deg = np.diff(np.asarray(graph.row_ptr, dtype=np.int64))
             if hub_min_degree == "auto":
                 hub_min_degree = max(128, 8 * int(np.ceil(deg.mean()))) if len(deg) else 128
             self.hub_min_degree = hub_min_degree
@@ -169,7 +171,7 @@ class DeviceGraph:
                               0 if self.hub_offset is None else int(hub_min_degree),
                               None if self.hub_offset is None else
                               self.hub_offset.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                              None if self.hub_rows is None else self.hub_rows.data_ptr())
+                              None if self.hub_rows is None else self.hub_rows.data_ptr(), self.max_degree)
 
     @property
     def num_hubs(self):

@@ -145,6 +145,14 @@ def test_hub_list_rejected_on_host(m):
     assert L.mqo_objective_workspace_size(ctypes.byref(s), 64) >= base + 40 * 64 * 8
 
 
+def test_negative_degree_hint_rejected(m):
+    s, off = _struct(m)
+    s.max_degree = -1
+    p = m.make_params(batch=2)
+    r = m._Result()
+    assert m.lib().mqo_solve_mis(ctypes.byref(s), ctypes.byref(p), None, ctypes.byref(r), None, 0, None) == -1
+
+
 def test_workspace_sizes(m):
     L = m.lib()
     s, off = _struct(m, n=1000)

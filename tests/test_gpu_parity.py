@@ -455,3 +455,43 @@ def test_hub_list_checked_on_device(mqo):
         dg.validate()
     dg.hub_rows.copy_(rows)
     mqo.solve(kind, dg, **kw)
+
+
+# --------------------------------------------------------------------------
+# lane groups taking rows in pairs (chosen for near-regular graphs); forced
+# here through the max_degree hint on irregular graphs so that both the
+# lockstep and the one-after-the-other paths run
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["er300", "cut_batch", "ba_star"])
+@pytest.mark.parametrize("B", [16, 64, 100])
+def test_row_pairs_forced(mqo, name, B):
+    kind, g = HUB_CASES[name] if name in HUB_CASES else CASES[name]
+    dg = mqo.DeviceGraph(g, DEV, hub_min_degree=8 if name == "ba_star" else "auto")
+    dg._struct.max_degree = 1  # hint: "near-regular" -> pairs
+    param = 2.0 if kind == "mis" else 1e-3
+    X0 = _x(kind, g.n, B, 161 + B)
+    X = torch.from_numpy(X0).to(DEV)
+    mqo.pga_steps(kind, dg, X, 3, alpha=0.02, gamma=2.0, lam=1e-3)
+    ref = X0
+    for _ in range(3):
+        ref, _ = pga.step32(g, ref, kind, 0.02, param)
+    assert np.array_equal(X.cpu().numpy(), ref)
+    f, grad = mqo.objective_grad(kind, dg, torch.from_numpy(X0).to(DEV), param)
+    for gi in range(g.num_graphs):
+        sub = g.subgraph(gi)
+        lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+        fr, gr = pga.objective_and_grad(sub, kind, param, X0[lo:hi].astype(np.float64), np.ones(B))
+        assert np.allclose(f.cpu().numpy()[gi * B:(gi + 1) * B], fr, rtol=1e-5,
+                           atol=1e-5 * np.abs(X0[lo:hi]).sum())
+        assert np.abs(grad.cpu().numpy()[lo:hi] - gr).max() / max(1.0, np.abs(gr).max()) <= 1e-5
+    if g.num_graphs == 1:
+        K, c, alpha = 10, 5, 0.01
+        XK, ckpt = mqo.unrolled_forward(kind, dg, torch.from_numpy(X0).to(DEV), alpha, K, c, param)
+        xs = pga.unrolled_forward(g, kind, param, alpha, K, X0, precision="fp32")
+        assert np.array_equal(XK.cpu().numpy(), xs[K])
+        dL = obj.gradient(kind, xs[K].astype(np.float64), obj.adjacency(g), param).astype(np.float32)
+        dX0, da = mqo.unrolled_backward(kind, dg, ckpt, torch.from_numpy(dL).to(DEV), alpha, K, c, param)
+        rX0, ra = pga.unrolled_backward(g, kind, param, alpha, K, X0, dL.astype(np.float64), precision="fp32")
+        assert np.abs(dX0.cpu().numpy() - rX0).max() / max(1.0, np.abs(rX0).max()) <= 1e-4
+        assert np.allclose(da.cpu().numpy(), ra, rtol=1e-4, atol=1e-4 * np.abs(ra).max())
