@@ -166,19 +166,31 @@ __device__ __forceinline__ void row_gather(const GraphView &g, const float *__re
   if (lanes_log2 >= 2) {
     const int32_t lanes = 1 << lanes_log2;
     const int32_t lane = threadIdx.x & (lanes - 1);
+    // batches of KB indices: shuffled out first, then KB gathers issued back
+    // to back, then added in order (the shuffles keep a plain loop from
+    // being unrolled, which would leave one gather in flight per lane)
+    constexpr int KB = 4;
     for (int32_t j0 = beg; j0 < end; j0 += lanes) {
       const bool have = j0 + lane < end;
       const int32_t myu = have ? __builtin_nontemporal_load(g.col_idx + j0 + lane) : 0;
       const int32_t myw = WEIGHTED && have ? __builtin_nontemporal_load(g.weight + j0 + lane) : 1;
       const int32_t cnt = min(lanes, end - j0);
-#pragma unroll 4
-      for (int32_t k = 0; k < cnt; ++k) {
-        const int64_t u = __shfl(myu, k, lanes);
-        const int32_t wk = WEIGHTED ? __shfl(myw, k, lanes) : 1;
-        if (!colok) continue;
-        float x[VEC];
-        load_vec<VEC>(X + u * ld + col, x);
-        add_neighbour<VEC, WEIGHTED>(acc, x, wk);
+      for (int32_t k0 = 0; k0 < cnt; k0 += KB) {
+        int64_t u[KB];
+        int32_t w[KB];
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) {
+          const int32_t src = min(k0 + kk, lanes - 1);
+          u[kk] = __shfl(myu, src, lanes);
+          w[kk] = WEIGHTED ? __shfl(myw, src, lanes) : 1;
+        }
+        float x[KB][VEC];
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk)
+          if (colok && k0 + kk < cnt) load_vec<VEC>(X + u[kk] * ld + col, x[kk]);
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk)
+          if (colok && k0 + kk < cnt) add_neighbour<VEC, WEIGHTED>(acc, x[kk], w[kk]);
       }
     }
     return;
