@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--tile", default="",
+                    help="persistent plan shape T,threads,vec,csr,reg (mqo_params tile_* fields; 0 = autotune)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (scale for HBM counters)")
     args = ap.parse_args()
@@ -139,6 +141,9 @@ def main():
     dg = mqo.DeviceGraph(g, dev)
     kw = dict(batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=wl.rounds, alpha=wl.alpha, gamma=wl.gamma,
               lam=wl.lam, rho=wl.rho, reset_mode=wl.reset_mode, local_search=wl.local_search, seed=wl.seed)
+    if args.tile:
+        t = [int(v) for v in args.tile.split(",")]
+        kw.update(tile_cols=t[0], tile_threads=t[1], tile_vec=t[2], tile_csr=t[3], tile_reg=t[4])
     ws = mqo.Workspace(dev)
     for i in range(args.warmup):
         out = mqo.solve(wl.problem, dg, plan=args.plan, workspace=ws, **kw)
@@ -166,8 +171,10 @@ def main():
                data="synthetic",
                config=dict(workload=wl.name, description=wl.description, graphs=g.num_graphs, n=g.n, nnz=g.nnz,
                            batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=wl.rounds, alpha=wl.alpha,
-                           rho=wl.rho, plan=out["plan"], tile_cols=out["tile_cols"],
-                           tile_threads=out["tile_threads"], parallelism="dp1"))
+                           rho=wl.rho, reset_mode=wl.reset_mode, plan=out["plan"], tile_cols=out["tile_cols"],
+                           tile_threads=out["tile_threads"], tile_vec=out["tile_vec"],
+                           tile_csr_lds=out["tile_csr_lds"], tile_reg_degree=out["tile_reg_degree"],
+                           parallelism="dp1"))
 
     # dominant kernel: the launches that run the PGA steps
     steps_per_launch = wl.steps_per_round * wl.rounds / max(1, out["step_kernel_launches"])

@@ -641,8 +641,8 @@ std::vector<TileCfg> tile_candidates(const Solve &S) {
     for (int th : {256, 512, 1024}) {
       if (S.p->tile_threads && th != S.p->tile_threads) continue;
       if (S.p->tile_reg != 1 && S.g->weight == nullptr && S.max_deg <= 16) {
-        // register adjacency: degree padded to 4, 8 or 16, 1, 2 or 4 rows per lane
-        const int dreg = S.max_deg <= 4 ? 4 : S.max_deg <= 8 ? 8 : 16;
+        // register adjacency: degree padded to 3, 4, 8 or 16, 1, 2 or 4 rows per lane
+        const int dreg = S.max_deg <= 3 ? 3 : S.max_deg <= 4 ? 4 : S.max_deg <= 8 ? 8 : 16;
         const int64_t need = (S.n_max * T + th - 1) / th;
         const int ipt = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 0;
         const TileCfg c{T, th, 1, 0, dreg, ipt};

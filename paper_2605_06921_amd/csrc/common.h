@@ -67,8 +67,9 @@ __device__ __forceinline__ float unit_f32(uint32_t u) { return (float)(u >> 8) *
 template <bool MAXCUT>
 __device__ __forceinline__ float grad_from_sum(float acc, float param) {
   if (MAXCUT) {
-    const float t = 2.0f * acc;
-    return (-param) - t;
+    // 2 * acc is exact, so the fused form rounds (-lambda) - 2 * acc once,
+    // exactly as the two-operation form does
+    return fmaf(-2.0f, acc, -param);
   } else {
     const float t = param * acc;
     return 1.0f - t;

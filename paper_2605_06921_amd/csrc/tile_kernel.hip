@@ -117,8 +117,12 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
   // item i = row v, trajectory c keeps the LDS offsets of its neighbours in
   // ascending CSR order, padded with the zero row; adding the padding zeros
   // at the end of the sum leaves every result bit-identical
-  int32_t off[DREG > 0 ? IPT : 1][DREG > 0 ? DREG : 1];
-  float xr[DREG > 0 ? IPT : 1];  // the lane's own iterate entries, kept across steps
+  // The LDS addresses of the neighbours in both iterate buffers are kept, so
+  // that a step issues its DREG reads without address arithmetic.
+  constexpr int RI = DREG > 0 ? IPT : 1, RD = DREG > 0 ? DREG : 1;
+  const float *pa[RI][RD];
+  const float *pb[RI][RD];
+  float xr[RI];  // the lane's own iterate entries, kept across steps
   if constexpr (DREG > 0) {
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
@@ -126,8 +130,11 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
       const int32_t v = L < nT ? L >> lt : 0, c = L & (T - 1);
       const int32_t beg = L < nT ? a.row_ptr[lo + v] - e0 : 0, end = L < nT ? a.row_ptr[lo + v + 1] - e0 : 0;
 #pragma unroll
-      for (int kk = 0; kk < DREG; ++kk)
-        off[i][kk] = beg + kk < end ? ((cig[beg + kk] - ilo) << lt) | c : (zrow << lt) | c;
+      for (int kk = 0; kk < DREG; ++kk) {
+        const int32_t off = beg + kk < end ? ((cig[beg + kk] - ilo) << lt) | c : (zrow << lt) | c;
+        pa[i][kk] = xa + off;
+        pb[i][kk] = xb + off;
+      }
     }
   }
   __syncthreads();
@@ -212,27 +219,24 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
 
     // ------------------------------------------------------------ PGA steps
     const int32_t nI = nT / VEC;  // lane items: VEC consecutive trajectories of one row
-    for (int32_t st = 0; st < a.steps; ++st) {
-      const float *src = (st & 1) ? xb : xa;
-      float *dst = (st & 1) ? xa : xb;
-      if constexpr (DREG > 0) {
-        // all neighbour reads of all the lane's rows are independent LDS loads
-        if (st == 0) {
+    if constexpr (DREG > 0) {
+      // Step st reads buffer (st & 1 ? xb : xa) and writes the other; all
+      // neighbour reads of the lane's rows are independent LDS loads,
+      // unconditional (padding reads the zero row) so that they issue back to
+      // back.
 #pragma unroll
-          for (int i = 0; i < IPT; ++i) {
-            const int32_t L = tid + i * nthr;
-            xr[i] = L < nT ? src[L] : 0.0f;
-          }
-        }
+      for (int i = 0; i < IPT; ++i) {
+        const int32_t L = tid + i * nthr;
+        xr[i] = L < nT ? xa[L] : 0.0f;
+      }
+      auto reg_step = [&](const float *const(&p)[RI][RD], float *dst) {
 #pragma unroll
         for (int i = 0; i < IPT; ++i) {
           const int32_t L = tid + i * nthr;
           if (L < nT) {
             float acc = 0.0f;
-            // unconditional reads (padding hits the zero row as a broadcast)
-            // so that all of them issue back to back
 #pragma unroll
-            for (int kk = 0; kk < DREG; ++kk) acc = acc + src[off[i][kk]];
+            for (int kk = 0; kk < DREG; ++kk) acc = acc + *p[i][kk];
             const float gr = grad_from_sum<MAXCUT>(acc, a.param);
             float d = gr;
             if (momentum) {
@@ -247,8 +251,15 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
           }
         }
         __syncthreads();
-        continue;
+      };
+      for (int32_t st = 0; st < a.steps; st += 2) {
+        reg_step(pa, xb);
+        if (st + 1 < a.steps) reg_step(pb, xa);
       }
+    }
+    for (int32_t st = 0; DREG == 0 && st < a.steps; ++st) {
+      const float *src = (st & 1) ? xb : xa;
+      float *dst = (st & 1) ? xa : xb;
       for (int32_t I = tid; I < nI; I += nthr) {
         const int32_t L0 = I * VEC;
         const int32_t v = L0 >> lt, c0 = L0 & (T - 1);
@@ -457,7 +468,8 @@ bool tile_shape_ok(int64_t n_max, int T, int threads, int vec, bool csr_lds, int
   // register adjacency: one trajectory per lane item, at most ipt items per
   // lane; the shapes below fit the 128-VGPR budget of 1024-thread workgroups
   // without spilling
-  const bool fits_regs = (dreg == 4 && ipt <= 2) || (dreg == 8 && ipt <= 2) || (dreg == 16 && ipt == 1) ||
+  const bool fits_regs = (dreg == 3 && ipt <= 2) || (dreg == 4 && ipt <= 2) || (dreg == 8 && ipt <= 2) ||
+                         (dreg == 16 && ipt == 1) ||
                          (dreg <= 8 && ipt == 4 && threads <= 512);
   return fits_regs && (ipt == 1 || ipt == 2 || ipt == 4) && vec == 1 && !csr_lds &&
          n_max * T <= (int64_t)ipt * threads;
@@ -492,6 +504,7 @@ template <bool MC, bool W>
 static hipError_t tile_launch_mw(const TileArgs &a, int threads, hipStream_t s) {
   if (!W && a.dreg > 0) {
     switch (a.dreg) {
+      case 3: return tile_launch_reg<MC, 3>(a, threads, s);
       case 4: return tile_launch_reg<MC, 4>(a, threads, s);
       case 8: return tile_launch_reg<MC, 8>(a, threads, s);
       default: return tile_launch_reg<MC, 16>(a, threads, s);

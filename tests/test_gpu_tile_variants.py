@@ -49,7 +49,7 @@ def test_register_adjacency_agrees(mqo, name, T, threads, momentum):
             mqo.solve(kind, dg, plan="persistent", tile_cols=T, tile_threads=threads, tile_reg=2, **kw)
         return
     out = mqo.solve(kind, dg, plan="persistent", tile_cols=T, tile_threads=threads, tile_reg=2, **kw)
-    assert out["tile_reg_degree"] in (4, 8, 16)
+    assert out["tile_reg_degree"] in (3, 4, 8, 16)
     ref = mqo.solve(kind, dg, plan="batched", **kw)
     assert torch.equal(out["traj_best_value"], ref["traj_best_value"])
     assert torch.equal(out["traj_best_x"], ref["traj_best_x"])
