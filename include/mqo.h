@@ -20,7 +20,14 @@
  *     not depend on the launch plan or on the graph's position in a batch.
  *   - Float32 steps follow one fixed operation order (per row, neighbours
  *     summed in ascending CSR order with one rounding per add, no fused
- *     multiply-add), so every launch plan gives bit-identical iterates.
+ *     multiply-add except -lambda - 2 * acc, whose product is exact so that
+ *     one rounding gives the same result), so every launch plan gives
+ *     bit-identical iterates.
+ *   - The blocking entry points (the solves, mqo_local_search,
+ *     mqo_validate_graph) share the library's pinned read-back buffer and
+ *     internal stream and run one at a time per process (an internal lock);
+ *     the asynchronous ones may be called concurrently on different
+ *     streams with different workspaces.
  */
 #ifndef MQO_H
 #define MQO_H

@@ -64,8 +64,12 @@ struct TileCfg {
 
 struct Resources {
   std::mutex mu;
+  std::mutex host_mu;  // held by the blocking entry points (pinned buffer, internal stream)
   hipStream_t stream = nullptr;
   int32_t *pinned = nullptr;  // 1024 ints
+  int64_t *pinned_voff = nullptr;  // staging of vtx_offset for its upload
+  size_t pinned_voff_n = 0;
+  hipEvent_t input_ready = nullptr;  // caller's stream -> internal stream
   int32_t *small = nullptr;   // 64 device ints of scratch for entry points without a workspace
   int device = -1;
   int lds_limit = 0;
@@ -87,6 +91,7 @@ int ensure_resources() {
     r.stream = nullptr;
   }
   if (!r.pinned) HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&r.pinned), 1024 * sizeof(int32_t), 0));
+  if (!r.input_ready) HIP_TRY(hipEventCreateWithFlags(&r.input_ready, hipEventDisableTiming));
   HIP_TRY(hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking));
   if (r.small) (void)hipFree(r.small);
   HIP_TRY(hipMalloc(reinterpret_cast<void **>(&r.small), 64 * sizeof(int32_t)));
@@ -260,43 +265,81 @@ int read_back_i32(const int32_t *dev, int count, std::vector<int32_t> &out, hipS
   return MQO_OK;
 }
 
-// device-side canonical-form check; voff_dev must already hold vtx_offset
-int validate_on_device(const mqo_graph *g, int64_t *voff_dev, int32_t *err_dev, hipStream_t s) {
-  launch_fill_i32(err_dev, 1, 0, s);
-  launch_validate_rows(g->row_ptr, g->n_total, g->nnz_total, err_dev, s);
-  HIP_TRY(hipGetLastError());
-  std::vector<int32_t> e;
-  TRY(read_back_i32(err_dev, 1, e, s));
-  if (e[0]) return fail(MQO_ERR_INVALID_GRAPH, "row_ptr is not monotone within [0, nnz]");
-  if (g->nnz_total > 0) {
-    launch_validate_cols(g->row_ptr, g->col_idx, g->weight, voff_dev, g->num_graphs, g->n_total, err_dev, s);
-    HIP_TRY(hipGetLastError());
-    TRY(read_back_i32(err_dev, 1, e, s));
-    if (e[0] & 2) return fail(MQO_ERR_INVALID_GRAPH, "a column index leaves its graph's vertex range");
-    if (e[0] & 4) return fail(MQO_ERR_INVALID_GRAPH, "self loop");
-    if (e[0] & 8) return fail(MQO_ERR_INVALID_GRAPH, "columns not strictly ascending within a row");
-    if (e[0] & 16) return fail(MQO_ERR_INVALID_GRAPH, "adjacency not symmetric");
-    if (e[0] & 32) return fail(MQO_ERR_INVALID_GRAPH, "weights not symmetric");
+// Several device int32 ranges read back with one synchronisation.
+int read_back_many(const std::vector<std::pair<const int32_t *, int>> &parts, std::vector<int32_t> &out,
+                   hipStream_t s) {
+  Resources &r = res();
+  int total = 0;
+  for (const auto &pt : parts) total += pt.second;
+  if (total > 1024) {  // larger than the pinned buffer: one at a time
+    out.clear();
+    for (const auto &pt : parts) {
+      std::vector<int32_t> o;
+      TRY(read_back_i32(pt.first, pt.second, o, s));
+      out.insert(out.end(), o.begin(), o.end());
+    }
+    return MQO_OK;
   }
-  if (g->hub_offset) {
-    launch_fill_i32(err_dev, 1, 0, s);
+  int off = 0;
+  for (const auto &pt : parts) {
+    HIP_TRY(hipMemcpyAsync(r.pinned + off, pt.first, pt.second * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    off += pt.second;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  out.assign(r.pinned, r.pinned + total);
+  return MQO_OK;
+}
+
+// Device-side canonical-form check with one synchronisation: the column
+// and hub checks guard their own reads, so they run in the same pass as the
+// row_ptr check.  voff_dev must already hold vtx_offset; err_dev has room
+// for 4 ints.  When rpat_dev / dmax_dev are given, it also returns the
+// row_ptr entries at the graph boundaries (rp, G+1 values) and the largest
+// degree (max_deg).
+int validate_on_device(const mqo_graph *g, int64_t *voff_dev, int32_t *err_dev, hipStream_t s,
+                       int32_t *rpat_dev = nullptr, int32_t *dmax_dev = nullptr, std::vector<int32_t> *rp = nullptr,
+                       int32_t *max_deg = nullptr) {
+  launch_fill_i32(err_dev, 4, 0, s);
+  launch_validate_rows(g->row_ptr, g->n_total, g->nnz_total, err_dev, s);
+  if (g->nnz_total > 0)
+    launch_validate_cols(g->row_ptr, g->col_idx, g->weight, voff_dev, g->num_graphs, g->n_total, g->nnz_total,
+                         err_dev + 1, s);
+  const bool hubs = g->hub_offset != nullptr;
+  if (hubs) {
     for (int32_t i = 0; i < g->num_graphs; ++i) {
       const int64_t c = g->hub_offset[i + 1] - g->hub_offset[i];
       if (c > 0)
         launch_validate_hubs(g->row_ptr, g->hub_rows + g->hub_offset[i], c, g->vtx_offset[i],
-                             g->vtx_offset[i + 1] - g->vtx_offset[i], g->hub_min_degree, err_dev, s);
+                             g->vtx_offset[i + 1] - g->vtx_offset[i], g->hub_min_degree, err_dev + 2, s);
     }
-    HIP_TRY(hipGetLastError());
-    TRY(read_back_i32(err_dev, 1, e, s));
-    if (e[0]) return fail(MQO_ERR_INVALID_GRAPH, "a hub_rows entry is out of its graph, not ascending or not a hub");
-    launch_fill_i32(err_dev, 1, 0, s);
-    launch_count_hubs(g->row_ptr, g->n_total, g->hub_min_degree, err_dev, s);
-    HIP_TRY(hipGetLastError());
-    TRY(read_back_i32(err_dev, 1, e, s));
-    if (e[0] != g->hub_offset[g->num_graphs])
-      return fail(MQO_ERR_INVALID_GRAPH, "hub_rows lists %lld rows, the graph has %d of degree > %d",
-                  (long long)g->hub_offset[g->num_graphs], e[0], g->hub_min_degree);
+    launch_count_hubs(g->row_ptr, g->n_total, g->hub_min_degree, err_dev + 3, s);
   }
+  std::vector<std::pair<const int32_t *, int>> parts{{err_dev, 4}};
+  if (rpat_dev) {
+    launch_gather_rowptr(g->row_ptr, voff_dev, g->num_graphs, rpat_dev, s);
+    parts.push_back({rpat_dev, g->num_graphs + 1});
+  }
+  if (dmax_dev) {
+    launch_degree_max(g->row_ptr, g->n_total, dmax_dev, s);
+    parts.push_back({dmax_dev, 1});
+  }
+  HIP_TRY(hipGetLastError());
+  std::vector<int32_t> e;
+  TRY(read_back_many(parts, e, s));
+  if (e[0]) return fail(MQO_ERR_INVALID_GRAPH, "row_ptr is not monotone within [0, nnz]");
+  if (e[1] & 2) return fail(MQO_ERR_INVALID_GRAPH, "a column index leaves its graph's vertex range");
+  if (e[1] & 4) return fail(MQO_ERR_INVALID_GRAPH, "self loop");
+  if (e[1] & 8) return fail(MQO_ERR_INVALID_GRAPH, "columns not strictly ascending within a row");
+  if (e[1] & 16) return fail(MQO_ERR_INVALID_GRAPH, "adjacency not symmetric");
+  if (e[1] & 32) return fail(MQO_ERR_INVALID_GRAPH, "weights not symmetric");
+  if (hubs) {
+    if (e[2]) return fail(MQO_ERR_INVALID_GRAPH, "a hub_rows entry is out of its graph, not ascending or not a hub");
+    if (e[3] != g->hub_offset[g->num_graphs])
+      return fail(MQO_ERR_INVALID_GRAPH, "hub_rows lists %lld rows, the graph has %d of degree > %d",
+                  (long long)g->hub_offset[g->num_graphs], e[3], g->hub_min_degree);
+  }
+  if (rp) rp->assign(e.begin() + 4, e.begin() + 5 + g->num_graphs);
+  if (max_deg) *max_deg = e.back();
   return MQO_OK;
 }
 
@@ -318,6 +361,7 @@ struct Solve {
   hipStream_t s;
   const float *x0;
   int64_t ls_iters = 0;
+  int32_t deferred_tile_wg = 0;  // > 0: the tile counters sit in the pinned buffer after the final sync
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;  // around the step launches
 
   int begin_timed(hipEvent_t *e0) {
@@ -572,7 +616,7 @@ int64_t nnz_max_of(const Solve &S) {
 
 bool tile_feasible(const Solve &S, const TileCfg &c) {
   return tile_shape_ok(S.n_max, c.T, c.threads, c.vec, c.csr != 0, c.dreg, c.ipt) &&
-         (int64_t)tile_lds_bytes(S.n_max, c.T, nnz_max_of(S), c.csr != 0) <= tile_lds_budget();
+         (int64_t)tile_lds_bytes(S.n_max, c.T, nnz_max_of(S), c.csr != 0, c.dreg > 0) <= tile_lds_budget();
 }
 
 // any shape at all fits (plan selection)
@@ -749,15 +793,26 @@ int solve_tile(Solve &S, int32_t *rounds_done, TileCfg *used) {
     hipError_t e = launch_tile_round(mc, w, a, cfg.threads, S.s);
     if (e != hipSuccess) return fail(MQO_ERR_HIP, "tile launch: %s", hipGetErrorString(e));
     TRY(S.end_timed(e0));
+    r = a.r1;
+    if (!budget && nwg < 1024) {
+      // read back with the solve's final synchronisation
+      Resources &R = res();
+      HIP_TRY(hipMemcpyAsync(R.pinned, a.ls_iters, nwg * sizeof(int32_t), hipMemcpyDeviceToHost, S.s));
+      HIP_TRY(hipMemcpyAsync(R.pinned + nwg, at<int32_t>(S.ws, S.L.err), sizeof(int32_t), hipMemcpyDeviceToHost,
+                             S.s));
+      S.deferred_tile_wg = nwg;
+      break;
+    }
     TRY(read_back_i32(a.ls_iters, nwg, lsi, S.s));
     int64_t mx = 0;
     for (int32_t x : lsi) mx = std::max<int64_t>(mx, x);
     S.ls_iters += mx;
-    r = a.r1;
   }
-  std::vector<int32_t> err;
-  TRY(read_back_i32(at<int32_t>(S.ws, S.L.err), 1, err, S.s));
-  if (err[0]) return fail(MQO_ERR_INTERNAL, "local search did not terminate");
+  if (!S.deferred_tile_wg) {
+    std::vector<int32_t> err;
+    TRY(read_back_i32(at<int32_t>(S.ws, S.L.err), 1, err, S.s));
+    if (err[0]) return fail(MQO_ERR_INTERNAL, "local search did not terminate");
+  }
   *rounds_done = r;
   return MQO_OK;
 }
@@ -770,9 +825,12 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
   const Layout L = make_layout(g, p->batch);
   if (!ws || ws_bytes < L.total) return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", L.total);
   TRY(ensure_resources());
-  hipStream_t s = res().stream;
-  if (stream) HIP_TRY(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
-  else HIP_TRY(hipDeviceSynchronize());
+  std::lock_guard<std::mutex> host_lock(res().host_mu);
+  Resources &R = res();
+  hipStream_t s = R.stream;
+  // the internal stream waits for the work the caller has queued on `stream`
+  HIP_TRY(hipEventRecord(R.input_ready, reinterpret_cast<hipStream_t>(stream)));
+  HIP_TRY(hipStreamWaitEvent(s, R.input_ready, 0));
 
   Solve S;
   S.g = g;
@@ -789,20 +847,21 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
   S.x0 = x0;
 
   int64_t *voff = at<int64_t>(ws, L.voff);
-  HIP_TRY(hipMemcpyAsync(voff, g->vtx_offset, (g->num_graphs + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-  TRY(validate_on_device(g, voff, at<int32_t>(ws, L.err), s));
-  launch_gather_rowptr(g->row_ptr, voff, S.G, at<int32_t>(ws, L.rpat), s);
+  const size_t nvo = (size_t)g->num_graphs + 1;
+  if (R.pinned_voff_n < nvo) {
+    if (R.pinned_voff) (void)hipHostFree(R.pinned_voff);
+    R.pinned_voff = nullptr;
+    R.pinned_voff_n = 0;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&R.pinned_voff), nvo * sizeof(int64_t), 0));
+    R.pinned_voff_n = nvo;
+  }
+  std::memcpy(R.pinned_voff, g->vtx_offset, nvo * sizeof(int64_t));
+  HIP_TRY(hipMemcpyAsync(voff, R.pinned_voff, nvo * sizeof(int64_t), hipMemcpyHostToDevice, s));
   std::vector<int32_t> rp;
-  TRY(read_back_i32(at<int32_t>(ws, L.rpat), S.G + 1, rp, s));
+  TRY(validate_on_device(g, voff, at<int32_t>(ws, L.err), s, at<int32_t>(ws, L.rpat), at<int32_t>(ws, L.dmax), &rp,
+                         &S.max_deg));
   S.nnz_g.resize(S.G);
   for (int32_t i = 0; i < S.G; ++i) S.nnz_g[i] = rp[i + 1] - rp[i];
-  {
-    int32_t *dm = at<int32_t>(ws, L.dmax);
-    launch_degree_max(g->row_ptr, g->n_total, dm, s);
-    std::vector<int32_t> d;
-    TRY(read_back_i32(dm, 1, d, s));
-    S.max_deg = d[0];
-  }
 
   int plan = p->plan;
   if (plan == MQO_PLAN_AUTO) plan = tile_possible(S) ? MQO_PLAN_PERSISTENT : MQO_PLAN_BATCHED;
@@ -825,6 +884,13 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
     HIP_TRY(hipMemcpyAsync(r->traj_best_x, at<int8_t>(ws, L.Zb), (size_t)g->n_total * S.B, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
+  if (S.deferred_tile_wg) {
+    const int32_t *pin = res().pinned;
+    int64_t mx = 0;
+    for (int32_t i = 0; i < S.deferred_tile_wg; ++i) mx = std::max<int64_t>(mx, pin[i]);
+    S.ls_iters += mx;
+    if (pin[S.deferred_tile_wg]) return fail(MQO_ERR_INTERNAL, "local search did not terminate");
+  }
   int64_t nnz_sum = 0;
   for (int64_t x : S.nnz_g) nnz_sum += x;
   r->rounds_executed = rounds_done;
@@ -1111,6 +1177,7 @@ int mqo_local_search(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t 
   const Layout L = make_layout(g, B);
   if (!ws || ws_bytes < L.total) return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", L.total);
   TRY(ensure_resources());
+  std::lock_guard<std::mutex> host_lock(res().host_mu);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const bool mc = obj == MQO_OBJ_MAXCUT_FB;
   int64_t total = 0;
@@ -1182,6 +1249,7 @@ int mqo_validate_graph_host(int64_t n, int64_t nnz, const int32_t *row_ptr, cons
 int mqo_validate_graph(const mqo_graph *g, void *stream) {
   TRY(check_graph_args(g, false));
   TRY(ensure_resources());
+  std::lock_guard<std::mutex> host_lock(res().host_mu);
   hipStream_t s = res().stream;
   if (stream) HIP_TRY(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
   void *buf = nullptr;

@@ -6,6 +6,7 @@
 // row; random draws use the local index v - lo and the trajectory id
 // traj0 + c.
 #include <algorithm>
+#include <climits>
 
 #include "common.h"
 #include "kernels.h"
@@ -801,21 +802,45 @@ __global__ __launch_bounds__(256) void k_reset_apply(const SelState *__restrict_
 // ---------------------------------------------------------------------------
 // answer per graph: best incumbent, ties to the lowest trajectory
 // ---------------------------------------------------------------------------
-__global__ void k_pick_best(const int64_t *__restrict__ best, int32_t G, int32_t B, int64_t *__restrict__ best_value,
-                            int32_t *__restrict__ best_b) {
-  const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= G) return;
-  int64_t bv = best[(int64_t)g * B];
-  int32_t bb = 0;
-  for (int32_t b = 1; b < B; ++b) {
+// one workgroup per graph: (value, -b) maximised over the trajectories by
+// lane strides, a wavefront shuffle tree and the first wavefront
+__global__ __launch_bounds__(256) void k_pick_best(const int64_t *__restrict__ best, int32_t G, int32_t B,
+                                                   int64_t *__restrict__ best_value, int32_t *__restrict__ best_b) {
+  __shared__ int64_t sv[4];
+  __shared__ int32_t sb[4];
+  const int32_t g = blockIdx.x;
+  int64_t bv = INT64_MIN;
+  int32_t bb = 0x7fffffff;
+  for (int32_t b = threadIdx.x; b < B; b += blockDim.x) {
     const int64_t x = best[(int64_t)g * B + b];
-    if (x > bv) {
+    if (x > bv) {  // b ascends within the thread: ties keep the lower
       bv = x;
       bb = b;
     }
   }
-  best_value[g] = bv;
-  best_b[g] = bb;
+  for (int off = 32; off > 0; off >>= 1) {
+    const int64_t ov = __shfl_down(bv, off, 64);
+    const int32_t ob = __shfl_down(bb, off, 64);
+    if (ov > bv || (ov == bv && ob < bb)) {
+      bv = ov;
+      bb = ob;
+    }
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sv[wave] = bv;
+    sb[wave] = bb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+      if (sv[w] > bv || (sv[w] == bv && sb[w] < bb)) {
+        bv = sv[w];
+        bb = sb[w];
+      }
+    best_value[g] = bv;
+    best_b[g] = bb;
+  }
 }
 
 __global__ void k_copy_best_x(const int8_t *__restrict__ Zb, int32_t B, const int64_t *__restrict__ voff, int32_t G,
@@ -851,9 +876,12 @@ __global__ void k_validate_rows(const int32_t *__restrict__ row_ptr, int64_t n, 
   }
 }
 
+// Runs in the same pass as k_validate_rows: rows whose row_ptr range is not
+// inside [0, nnz] are skipped here (k_validate_rows flags them), so no read
+// leaves col_idx.
 __global__ void k_validate_cols(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
                                 const int32_t *__restrict__ weight, const int64_t *__restrict__ voff, int32_t G,
-                                int64_t n, int32_t *err) {
+                                int64_t n, int64_t nnz, int32_t *err) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   int32_t glo = 0, ghi = G;
@@ -866,6 +894,7 @@ __global__ void k_validate_cols(const int32_t *__restrict__ row_ptr, const int32
   }
   const int64_t lo = voff[glo], hi = voff[glo + 1];
   const int32_t beg = row_ptr[v], end = row_ptr[v + 1];
+  if (beg < 0 || beg > end || (int64_t)end > nnz) return;
   int64_t prev = -1;
   for (int32_t j = beg; j < end; ++j) {
     const int64_t c = col_idx[j];
@@ -878,6 +907,7 @@ __global__ void k_validate_cols(const int32_t *__restrict__ row_ptr, const int32
     prev = c;
     // symmetry: v must appear in row c (binary search; rows are checked sorted)
     int32_t a = row_ptr[c], b = row_ptr[c + 1] - 1;
+    if (a < 0 || a > b + 1 || (int64_t)b >= nnz) continue;  // row c is flagged by the row check
     bool found = false;
     while (a <= b) {
       const int32_t mid = (a + b) >> 1;
@@ -1353,7 +1383,7 @@ void launch_reset(bool maxcut, const int8_t *Zb, int32_t ldb, const uint32_t *ke
 
 void launch_pick_best(const int64_t *best, int32_t G, int32_t B, int64_t *best_value, int32_t *best_b,
                       hipStream_t s) {
-  MQO_LAUNCH(k_pick_best, dim3(blocks_for(G)), dim3(256), 0, s, best, G, B, best_value, best_b);
+  MQO_LAUNCH(k_pick_best, dim3((unsigned)G), dim3(256), 0, s, best, G, B, best_value, best_b);
 }
 
 void launch_copy_best_x(const int8_t *Zb, int32_t B, const int64_t *voff, int32_t G, const int32_t *best_b,
@@ -1398,8 +1428,8 @@ void launch_count_hubs(const int32_t *row_ptr, int64_t n, int32_t min_deg, int32
 }
 
 void launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, const int32_t *weight, const int64_t *voff,
-                          int32_t G, int64_t n, int32_t *err, hipStream_t s) {
-  MQO_LAUNCH(k_validate_cols, dim3(blocks_for(n)), dim3(256), 0, s, row_ptr, col_idx, weight, voff, G, n, err);
+                          int32_t G, int64_t n, int64_t nnz, int32_t *err, hipStream_t s) {
+  MQO_LAUNCH(k_validate_cols, dim3(blocks_for(n)), dim3(256), 0, s, row_ptr, col_idx, weight, voff, G, n, nnz, err);
 }
 
 int64_t grid_blocks_x(int64_t nrows, StepCfg cfg) { return grid_rows(nrows, 1, cfg.lanes_log2, 1, 256).x; }

@@ -56,8 +56,9 @@ void launch_validate_rows(const int32_t *row_ptr, int64_t n, int64_t nnz, int32_
 void launch_validate_hubs(const int32_t *row_ptr, const int32_t *hubs, int64_t count, int64_t lo, int64_t n,
                           int32_t min_deg, int32_t *err, hipStream_t s);
 void launch_count_hubs(const int32_t *row_ptr, int64_t n, int32_t min_deg, int32_t *count, hipStream_t s);
+// safe to run in the same pass as the row check (skips rows with a bad range)
 void launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, const int32_t *weight, const int64_t *voff,
-                          int32_t G, int64_t n, int32_t *err, hipStream_t s);
+                          int32_t G, int64_t n, int64_t nnz, int32_t *err, hipStream_t s);
 void launch_objective_grad(bool maxcut, const GraphView &g, const float *X, const float *scale, float *grad,
                            double *part, int32_t ncols, int32_t ld, StepCfg cfg, float param, hipStream_t s);
 // partial rows [nblk][ncols] followed by room for reduce_rows(nblk) more
@@ -101,7 +102,7 @@ struct TileArgs {
 };
 
 bool tile_shape_ok(int64_t n_max, int T, int threads, int vec, bool csr_lds, int dreg, int ipt);
-size_t tile_lds_bytes(int64_t n_max, int T, int64_t nnz_max, bool csr_lds);
+size_t tile_lds_bytes(int64_t n_max, int T, int64_t nnz_max, bool csr_lds, bool state_lds);
 hipError_t launch_tile_round(bool maxcut, bool weighted, const TileArgs &a, int threads, hipStream_t s);
 
 }  // namespace mqo

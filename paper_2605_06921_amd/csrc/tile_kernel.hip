@@ -49,6 +49,15 @@ __device__ __forceinline__ void lds_store(float *p, const float (&o)[VEC]) {
   }
 }
 
+// Byte offset, in the dynamic LDS, of the end of the iterate buffers, the
+// graph's row_ptr and (CSR_LDS) its local column ids.
+__host__ __device__ inline size_t tile_state_offset(int64_t n_max, int T, int64_t nnz_max, bool csr_lds) {
+  const int64_t rowsX = (n_max > 256 ? n_max : 256) + 1;
+  size_t b = (size_t)(2 * rowsX) * T * sizeof(float) + (size_t)(n_max + 1) * sizeof(int32_t);
+  if (csr_lds) b = ((b + 15) & ~(size_t)15) + (size_t)(nnz_max + 8) * sizeof(uint16_t);
+  return (b + 15) & ~(size_t)15;
+}
+
 template <bool MAXCUT, bool WEIGHTED, int VEC, bool CSR_LDS, int DREG, int IPT>
 // Four register rows per lane need more than the 128 VGPRs a 1024-thread
 // workgroup leaves, so that variant is built for at most 512 threads.
@@ -90,11 +99,17 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
   const size_t cls_off = ((size_t)(2 * rowsX) * T * sizeof(float) + (size_t)(a.n_max + 1) * sizeof(int32_t) + 15) &
                          ~(size_t)15;
   uint16_t *cls = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(smem) + cls_off);
+  // discrete state per (row, trajectory): in LDS after the CSR for the
+  // register-adjacency shapes (small tiles), else in the workgroup's region
+  // of the global scratch (L2-resident)
   const int64_t sbase = (int64_t)wid * a.n_max * T;
-  int8_t *zs = a.zs + sbase;
-  int32_t *nb = a.nb + sbase;
-  uint32_t *prio = a.prio + sbase;  // also the reset keys
-  int8_t *fl = a.fl + sbase;
+  const int64_t nTmax = (int64_t)a.n_max * T;
+  char *sl = reinterpret_cast<char *>(smem) + tile_state_offset(a.n_max, T, a.nnz_max, CSR_LDS);
+  constexpr bool SLDS = DREG > 0;
+  int8_t *zs = SLDS ? reinterpret_cast<int8_t *>(sl + 8 * nTmax) : a.zs + sbase;
+  int32_t *nb = SLDS ? reinterpret_cast<int32_t *>(sl + 4 * nTmax) : a.nb + sbase;
+  uint32_t *prio = SLDS ? reinterpret_cast<uint32_t *>(sl) : a.prio + sbase;  // also the reset keys
+  int8_t *fl = SLDS ? reinterpret_cast<int8_t *>(sl + 9 * nTmax) : a.fl + sbase;
   float *vm = a.vm + sbase;
   const int32_t *ci = a.col_idx;
   const int32_t *wt = a.weight;
@@ -475,16 +490,16 @@ bool tile_shape_ok(int64_t n_max, int T, int threads, int vec, bool csr_lds, int
          n_max * T <= (int64_t)ipt * threads;
 }
 
-size_t tile_lds_bytes(int64_t n_max, int T, int64_t nnz_max, bool csr_lds) {
-  const int64_t rowsX = (n_max > 256 ? n_max : 256) + 1;
-  size_t b = (size_t)(2 * rowsX) * T * sizeof(float) + (size_t)(n_max + 1) * sizeof(int32_t);
-  if (csr_lds) b = ((b + 15) & ~(size_t)15) + (size_t)(nnz_max + 8) * sizeof(uint16_t);
+size_t tile_lds_bytes(int64_t n_max, int T, int64_t nnz_max, bool csr_lds, bool state_lds) {
+  size_t b = tile_state_offset(n_max, T, nnz_max, csr_lds);
+  // prio, nb (4 bytes), z, flag (1 byte) per (row, trajectory)
+  if (state_lds) b += (size_t)n_max * T * 10;
   return (b + 15) & ~(size_t)15;
 }
 
 template <bool MC, bool W, int VEC, bool CL, int DREG, int IPT>
 static hipError_t tile_launch_t(const TileArgs &a, int threads, hipStream_t s) {
-  const size_t lds = tile_lds_bytes(a.n_max, a.T, a.nnz_max, CL);
+  const size_t lds = tile_lds_bytes(a.n_max, a.T, a.nnz_max, CL, DREG > 0);
   auto kern = k_tile_round<MC, W, VEC, CL, DREG, IPT>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
