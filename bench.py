@@ -31,7 +31,8 @@ HBM_PEAK = 8.0e12  # bytes/s, MI355X
 # LDS: 256 CUs x 128 bytes/clock x 2.4 GHz
 LDS_PEAK = 256 * 128 * 2.4e9
 KERNEL_SOURCES = {"k_tile_round": "paper_2605_06921_amd/csrc/tile_kernel.hip",
-                  "k_pga_step": "paper_2605_06921_amd/csrc/grid_kernels.hip"}
+                  "k_pga_step": "paper_2605_06921_amd/csrc/grid_kernels.hip",
+                  "k_objective_grad": "paper_2605_06921_amd/csrc/grid_kernels.hip"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
@@ -103,6 +104,75 @@ def cpu_baseline(wl, g, budget_s=15.0):
                        f"numpy/scipy, {el:.1f} s")
 
 
+def bench_differentiation(args, wl):
+    """Objective + gradient (grad) or the unrolled adjoint (unrolled) over the
+    workload's batch.  EU = one stored CSR entry x one trajectory in one
+    sparse-product pass; an unrolled forward + backward of K = 20 steps with
+    checkpoints every 5 is 20 + 4 x (4 + 2 x 5) = 76 passes."""
+    import torch
+    from synth import arrays
+    from paper_2605_06921_amd import mqo
+
+    if args.copy_calibration_mb:
+        a = torch.empty(args.copy_calibration_mb << 18, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    g = wl.make_graph()
+    dev = torch.device("cuda:0")
+    dg = mqo.DeviceGraph(g, dev)
+    B = wl.batch
+    param = wl.gamma if wl.problem == "mis" else wl.lam
+    lo = 0.0 if wl.problem == "mis" else -1.0
+    X = torch.from_numpy(arrays.uniform((g.n, B), lo, 1.0, wl.seed)).to(dev)
+    K, c = 20, 5
+    if args.mode == "grad":
+        passes = 1
+        kernel = "k_objective_grad"
+
+        def run():
+            return mqo.objective_grad(wl.problem, dg, X, param)
+    else:
+        passes = K + (K // c) * ((c - 1) + 2 * c)
+        kernel = "k_adj_mu"
+        dL = torch.ones_like(X)
+
+        def run():
+            XK, ckpt = mqo.unrolled_forward(wl.problem, dg, X, wl.alpha, K, c, param)
+            return mqo.unrolled_backward(wl.problem, dg, ckpt, dL, wl.alpha, K, c, param)
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gpu_s = e0.elapsed_time(e1) / 1e3  # the library's launches run on the current stream
+    eu = g.nnz * B * passes * args.steps
+    res = dict(metric="edge-updates/s of the differentiation path; HBM GB/s", value=eu / el, unit="edge-updates/s",
+               n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=1e3 * el / args.steps,
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload=wl.name, mode=args.mode, description=wl.description, n=g.n, nnz=g.nnz, batch=B,
+                           sparse_product_passes=passes, hubs=dg.num_hubs, parallelism="dp1"))
+    # algorithmic bytes per pass: CSR once, X read, output written (float64
+    # objective partials are small); average over the timed region
+    per_pass = step_bytes(g, B)
+    achieved = per_pass * passes * args.steps / gpu_s
+    res["roofline"] = dict(bound="hbm", achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
+                           frac=achieved / HBM_PEAK,
+                           traffic=measured_traffic(wl.name, kernel) if args.mode == "grad" else None,
+                           kernel=kernel, algorithmic_bytes_per_pass=per_pass,
+                           gpu_ms_per_step=1e3 * gpu_s / args.steps,
+                           note="HIP-event time of whole calls (every launch of the call, including the "
+                                "float64 reductions), so a lower bound on the sparse-product kernels' rate")
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +183,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--mode", default="solve", choices=["solve", "grad", "unrolled"],
+                    help="solve: whole batched solves; grad: objective + SpMM gradient over the batch; "
+                         "unrolled: K = 20 unrolled PGA steps forward and their adjoint (checkpoints every 5)")
     ap.add_argument("--tile", default="",
                     help="persistent plan shape T,threads,vec,csr,reg (mqo_params tile_* fields; 0 = autotune)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -128,6 +201,8 @@ def main():
     from paper_2605_06921_amd import mqo
 
     wl = WORKLOADS[args.workload]
+    if args.mode != "solve":
+        return bench_differentiation(args, wl)
     if args.copy_calibration_mb:
         a = torch.empty(args.copy_calibration_mb << 18, dtype=torch.float32, device="cuda:0").fill_(1.0)
         b = torch.empty_like(a)
