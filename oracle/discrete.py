@@ -78,6 +78,25 @@ def is_pga_fixed_mis(graph, Z, gamma, alpha=1.0):
     return np.all(Y == X, axis=0)
 
 
+def is_pga_fixed_cut(graph, S, lam, alpha=1.0):
+    """A binary s in {-1,+1}^n is a fixed point of the projected step on
+    f_B (Eq. (7), Sec. 3): 1{s = Pi_[-1,1](s + alpha grad f_B(s))}, evaluated
+    literally in float64, per column."""
+    A = obj.adjacency(graph)
+    X = np.asarray(S, dtype=np.float64)
+    Y = np.clip(X + alpha * obj.grad_f_B(X, A, lam), -1.0, 1.0)
+    return np.all(Y == X, axis=0)
+
+
+def is_pga_fixed(kind, graph, Z, param, alpha=1.0):
+    """The early-exit test of the schedule: the rounded point is a fixed point
+    of the projected gradient step (Eq. (8) for MIS, its f_B analogue for
+    MaxCut)."""
+    if kind == obj.MIS:
+        return is_pga_fixed_mis(graph, Z, param, alpha)
+    return is_pga_fixed_cut(graph, Z, param, alpha)
+
+
 def is_maximal_independent(graph, Z):
     """Brute definition: no edge inside I, and every v outside I has a
     neighbour in I."""

@@ -5,7 +5,12 @@ Round r = 0 .. rounds-1 of trajectory t = g*B + b:
   * r = 0 starts from x0 (given, or drawn by the initialisation rule);
     r > 0 starts from the incumbent with the reset set R zeroed (Sec. 4;
     Alg. 1 / Alg. 2 reset loop), momentum cleared;
-  * ``steps_per_round`` PGA steps (float32 replay, or float64);
+  * ``steps_per_round`` PGA steps (float32 replay, or float64); with
+    ``check_every`` = c > 0, after every c steps of a round (before its
+    end) a trajectory whose rounded point is a fixed point of the projected
+    step (the checker of Eq. (8) for MIS, its f_B analogue for MaxCut)
+    stops stepping for the rest of the round (Alg. 1 / Alg. 2 run PGA
+    until a MIS is detected / until convergence);
   * threshold rounding (Sec. 3);
   * optional 1-flip local search (parallel rule, ``discrete.local_search``);
   * exact evaluation; accept iff strictly better than the incumbent
@@ -40,13 +45,17 @@ class Params:
     local_search: bool = True
     init_mode: str = "uniform"
     init_sigma: float = 0.0
+    check_every: int = 0
 
 
-def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32", trace=None, cols=None):
+def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32", trace=None, cols=None,
+                stats=None):
     """Run the search on one graph (local indices).  Returns
     (traj_best_value int64[B], traj_best_z int8[n][B]).  Trajectories are
     independent, so ``cols`` may select a subset b of them (x0 then holds
-    only those columns); the outputs hold the selected columns in order."""
+    only those columns); the outputs hold the selected columns in order.
+    ``stats`` (a dict) receives steps[B], the PGA steps each trajectory
+    executed."""
     n = graph.n
     cols = np.arange(p.batch, dtype=np.int64) if cols is None else np.asarray(cols, dtype=np.int64)
     B = len(cols)
@@ -56,6 +65,7 @@ def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32"
     k = discrete.reset_count(p.rho, n)
     best = np.full(B, np.iinfo(np.int64).min, dtype=np.int64)
     zbest = np.zeros((n, B), dtype=np.int8)
+    steps = np.zeros(B, dtype=np.int64)
     for r in range(p.rounds):
         if r == 0:
             if x0 is not None:
@@ -68,11 +78,22 @@ def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32"
             mask = discrete.reset_set(n, k, p.seed, traj, r)
             X = discrete.reset_apply(kind, zbest, mask, p.reset_mode)
         V = None
-        for _ in range(p.steps_per_round):
+        active = np.ones(B, dtype=bool)
+        for st in range(p.steps_per_round):
+            if not active.any():
+                break
             if precision == "fp32":
-                X, V = pga.step32(graph, X, kind, p.alpha, param, p.mu, V)
+                Xn, Vn = pga.step32(graph, X, kind, p.alpha, param, p.mu, V)
             else:
-                X, V = pga.step64(X, A, kind, p.alpha, param, p.mu, V)
+                Xn, Vn = pga.step64(X, A, kind, p.alpha, param, p.mu, V)
+            # stopped trajectories keep their iterate (and momentum)
+            X = np.where(active[None, :], Xn, X)
+            V = Vn if V is None or Vn is None else np.where(active[None, :], Vn, V)
+            steps += active
+            done = st + 1
+            if p.check_every > 0 and done % p.check_every == 0 and done < p.steps_per_round:
+                fixed = discrete.is_pga_fixed(kind, graph, discrete.round_x(kind, X), param, p.alpha)
+                active &= ~fixed
         Z = discrete.round_x(kind, X)
         if p.local_search:
             Z, _ = discrete.local_search(kind, graph, Z, p.seed, traj, r)
@@ -82,26 +103,33 @@ def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32"
         zbest[:, take] = Z[:, take]
         if trace is not None:
             trace.append(dict(round=r, value=val.copy(), best=best.copy()))
+    if stats is not None:
+        stats["steps"] = steps
     return best, zbest
 
 
 def solve(kind, graph, p: Params, x0=None, precision="fp32"):
     """All graphs of a batch.  Returns a dict with best_value[G],
-    best_x int8[n_total], traj_best_value[G*B], traj_best_x int8[n_total][B]."""
+    best_x int8[n_total], traj_best_value[G*B], traj_best_x int8[n_total][B],
+    traj_steps[G*B] (PGA steps executed)."""
     G = graph.num_graphs
     offs = graph.vtx_offset
     out_vals = np.zeros(G * p.batch, dtype=np.int64)
     out_z = np.zeros((graph.n, p.batch), dtype=np.int8)
     best_value = np.zeros(G, dtype=np.int64)
     best_x = np.zeros(graph.n, dtype=np.int8)
+    out_steps = np.zeros(G * p.batch, dtype=np.int64)
     for g in range(G):
         sub = graph.subgraph(g)
         lo, hi = int(offs[g]), int(offs[g + 1])
         x0g = None if x0 is None else np.asarray(x0)[lo:hi]
-        vals, zb = solve_graph(kind, sub, p, g, x0g, precision)
+        st = {}
+        vals, zb = solve_graph(kind, sub, p, g, x0g, precision, stats=st)
+        out_steps[g * p.batch:(g + 1) * p.batch] = st["steps"]
         out_vals[g * p.batch:(g + 1) * p.batch] = vals
         out_z[lo:hi] = zb
         b = int(np.argmax(vals))  # first index of the maximum
         best_value[g] = vals[b]
         best_x[lo:hi] = zb[:, b]
-    return dict(best_value=best_value, best_x=best_x, traj_best_value=out_vals, traj_best_x=out_z)
+    return dict(best_value=best_value, best_x=best_x, traj_best_value=out_vals, traj_best_x=out_z,
+                traj_steps=out_steps)
