@@ -103,7 +103,13 @@ typedef struct {
   int32_t steps_per_round; /* PGA steps per round, >= 0                         */
   int32_t rounds;          /* >= 1; round 0 starts from x0, later rounds from
                               the incumbent after the reset of Sec. 4         */
-  int32_t check_every;     /* 0 (early exit on the checker is not offered)      */
+  int32_t check_every;     /* 0 = off; c > 0: after every c PGA steps of a
+                              round (before its end) a trajectory whose rounded
+                              point is a fixed point of the projected step
+                              (the checker of Eq. (8) for MIS, s_v t_v < 0 or
+                              s_v t_v = 0 with s_v = -1 for f_B) stops
+                              stepping for the rest of the round; edge_updates
+                              then counts the steps actually executed       */
   float alpha;             /* step size, > 0                                    */
   float momentum;          /* heavy-ball coefficient in [0, 1); 0 = plain PGA   */
   float gamma;             /* MIS edge penalty, > 1                             */
@@ -134,7 +140,8 @@ typedef struct {
   int64_t *best_value;         /* [G]: MIS size / cut weight (-1 = none)       */
   int64_t *traj_best_value;    /* [G*B] incumbent values, or NULL             */
   int8_t *traj_best_x;         /* [n_total*B] incumbents, or NULL             */
-  int64_t edge_updates;        /* (host) sum_g nnz_g * B * steps executed      */
+  int64_t edge_updates;        /* (host) sum over trajectories of the steps
+                                  each executed x nnz of its graph            */
   int64_t steps_executed;      /* (host) PGA steps per trajectory              */
   int32_t rounds_executed;     /* (host)                                       */
   int32_t plan_used;           /* (host) MQO_PLAN_PLAIN/BATCHED/PERSISTENT     */

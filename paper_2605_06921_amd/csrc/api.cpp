@@ -140,7 +140,7 @@ int check_params(const mqo_params *p, mqo_objective obj) {
   if (p->batch < 1) return fail(MQO_ERR_INVALID_ARG, "batch must be >= 1");
   if (p->steps_per_round < 0) return fail(MQO_ERR_INVALID_ARG, "steps_per_round must be >= 0");
   if (p->rounds < 1) return fail(MQO_ERR_INVALID_ARG, "rounds must be >= 1");
-  if (p->check_every != 0) return fail(MQO_ERR_UNSUPPORTED, "check_every must be 0");
+  if (p->check_every < 0) return fail(MQO_ERR_INVALID_ARG, "check_every must be >= 0");
   if (!(p->alpha > 0.0f) || !std::isfinite(p->alpha)) return fail(MQO_ERR_INVALID_ARG, "alpha must be > 0");
   if (!(p->momentum >= 0.0f && p->momentum < 1.0f)) return fail(MQO_ERR_INVALID_ARG, "momentum must be in [0,1)");
   if (obj == MQO_OBJ_MIS_H && !(p->gamma > 1.0f && std::isfinite(p->gamma)))
@@ -180,7 +180,7 @@ int64_t max_graph_rows(const mqo_graph *g) {
 // ---------------------------------------------------------------------------
 struct Layout {
   size_t X, Xt, V, Z, Zb, NB, PRIO, F, value, best, acc, act, voff, rpat, bestb, dmax, err, reset, tzs, tnb, tprio,
-      tfl, tvm, tls, pX, pXt, pV, total;
+      tfl, tvm, tls, pX, pXt, pV, colact, fixedc, steps, total;
 };
 
 Layout make_layout(const mqo_graph *g, int32_t B) {
@@ -220,6 +220,9 @@ Layout make_layout(const mqo_graph *g, int32_t B) {
   L.pX = take(n * 4);  // plain plan: one trajectory as contiguous vectors
   L.pXt = take(n * 4);
   L.pV = take(n * 4);
+  L.colact = take(G * B);  // early exit: trajectory still stepping in this round
+  L.fixedc = take(B);      // early exit: rounded point fixed (per column of one graph)
+  L.steps = take(G * B * 8);  // PGA steps each trajectory executed
   L.total = o;
   return L;
 }
@@ -453,42 +456,74 @@ int run_local_search(Solve &S, const GraphView &gv, int8_t *Z, int32_t *NB, uint
 
 // steps on one graph, ping-pong X <-> Xt, result back in X
 struct StepLoop {
-  hipGraphExec_t exec = nullptr;
-  hipGraph_t graph = nullptr;
+  // captured step chunks: [0] = the chunk between checks (or the whole
+  // round), [1] = the shorter last chunk of a round
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  hipGraph_t graph[2] = {nullptr, nullptr};
   ~StepLoop() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    for (int i = 0; i < 2; ++i) {
+      if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
+      if (graph[i]) (void)hipGraphDestroy(graph[i]);
+    }
   }
 };
 
 void enqueue_steps(Solve &S, const GraphView &gv, float *X, float *Xt, float *V, int32_t ncols, int32_t ld,
-                   int32_t steps) {
+                   int32_t steps, const int8_t *colact) {
   const StepCfg cfg = default_step_cfg(ncols, ld);
   float *a = X, *b = Xt;
   for (int32_t st = 0; st < steps; ++st) {
-    launch_pga_step(S.maxcut, gv, a, b, V, ncols, ld, cfg, S.p->alpha, S.p->momentum, S.param, S.s);
+    launch_pga_step(S.maxcut, gv, a, b, V, ncols, ld, cfg, S.p->alpha, S.p->momentum, S.param, S.s, colact);
     std::swap(a, b);
   }
   if (a != X) launch_copy_f32(a + gv.lo * ld, X + gv.lo * ld, gv.n * ld, S.s);
 }
 
-int run_steps(Solve &S, StepLoop &loop, bool use_graph, const GraphView &gv, float *X, float *Xt, float *V,
-              int32_t ncols, int32_t ld) {
-  const int32_t steps = S.p->steps_per_round;
-  if (steps == 0) return MQO_OK;
+int run_chunk(Solve &S, StepLoop &loop, int slot, bool use_graph, const GraphView &gv, float *X, float *Xt,
+              float *V, int32_t ncols, int32_t ld, int32_t steps, const int8_t *colact) {
   if (!use_graph) {
-    enqueue_steps(S, gv, X, Xt, V, ncols, ld, steps);
+    enqueue_steps(S, gv, X, Xt, V, ncols, ld, steps, colact);
     HIP_TRY(hipGetLastError());
     return MQO_OK;
   }
-  if (!loop.exec) {
+  if (!loop.exec[slot]) {
     HIP_TRY(hipStreamBeginCapture(S.s, hipStreamCaptureModeThreadLocal));
-    enqueue_steps(S, gv, X, Xt, V, ncols, ld, steps);
-    hipError_t e = hipStreamEndCapture(S.s, &loop.graph);
+    enqueue_steps(S, gv, X, Xt, V, ncols, ld, steps, colact);
+    hipError_t e = hipStreamEndCapture(S.s, &loop.graph[slot]);
     if (e != hipSuccess) return fail(MQO_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    HIP_TRY(hipGraphInstantiate(&loop.exec, loop.graph, nullptr, nullptr, 0));
+    HIP_TRY(hipGraphInstantiate(&loop.exec[slot], loop.graph[slot], nullptr, nullptr, 0));
   }
-  HIP_TRY(hipGraphLaunch(loop.exec, S.s));
+  HIP_TRY(hipGraphLaunch(loop.exec[slot], S.s));
+  return MQO_OK;
+}
+
+// The round's PGA steps.  With check_every = c > 0: chunks of c steps, and
+// after every chunk but the last the rounded point of every still-active
+// trajectory is tested (fixed point of the projected step); fixed ones stop
+// stepping for the rest of the round.  colact / steps_ctr: the columns'
+// active flags and executed-step counters.
+int run_steps(Solve &S, StepLoop &loop, bool use_graph, const GraphView &gv, float *X, float *Xt, float *V,
+              int32_t ncols, int32_t ld, int8_t *colact, int64_t *steps_ctr, int8_t *Z, int32_t *NB,
+              int64_t *value_scratch) {
+  const int32_t steps = S.p->steps_per_round;
+  if (steps == 0) return MQO_OK;
+  const int32_t c = S.p->check_every;
+  if (c <= 0) return run_chunk(S, loop, 0, use_graph, gv, X, Xt, V, ncols, ld, steps, nullptr);
+  launch_fill_i8(colact, ncols, 1, S.s);
+  for (int32_t done = 0; done < steps;) {
+    const int32_t len = std::min(c, steps - done);
+    launch_count_steps(colact, steps_ctr, ncols, len, S.s);
+    TRY(run_chunk(S, loop, len == c ? 0 : 1, use_graph, gv, X, Xt, V, ncols, ld, len, colact));
+    done += len;
+    if (done < steps) {
+      int8_t *fixed = at<int8_t>(S.ws, S.L.fixedc);
+      launch_round(S.maxcut, X, Z, gv.lo, gv.n, ncols, ld, S.s);
+      launch_evaluate(S.maxcut, gv, Z, NB, at<long long>(S.ws, S.L.acc), value_scratch, nullptr, fixed, ncols, ld,
+                      S.s);
+      launch_active_update(colact, fixed, ncols, S.s);
+    }
+  }
+  HIP_TRY(hipGetLastError());
   return MQO_OK;
 }
 
@@ -498,9 +533,13 @@ double now_s() {
 
 // one round of one graph on columns [traj0, traj0+ncols); arrays at ld,
 // incumbents at Zb (ldb) / best / value (offset to traj0 already)
+// colact: the columns' early-exit flags; its address is recorded in the
+// captured step loops, so a loop shared by several trajectories (plain
+// plan) gets one fixed slot
 int grid_round(Solve &S, StepLoop &loop, bool use_graph, const GraphView &gv, int32_t r, float *X, float *Xt,
                float *V, int8_t *Z, int8_t *Zb, int32_t ldb, int32_t *NB, uint32_t *PRIO, int8_t *F, int64_t *value,
-               int64_t *best, int32_t ncols, int32_t ld, uint64_t traj0) {
+               int64_t *best, int32_t ncols, int32_t ld, uint64_t traj0, int8_t *colact) {
+  int64_t *steps_ctr = at<int64_t>(S.ws, S.L.steps) + traj0;
   const bool mom = S.p->momentum != 0.0f;
   if (r > 0) {
     launch_reset(S.maxcut, Zb, ldb, nullptr, X, mom ? V : nullptr, gv.lo, gv.n, ncols, ld, S.p->seed, traj0,
@@ -511,7 +550,8 @@ int grid_round(Solve &S, StepLoop &loop, bool use_graph, const GraphView &gv, in
   if (S.p->steps_per_round > 0) {
     hipEvent_t e0;
     TRY(S.begin_timed(&e0));
-    TRY(run_steps(S, loop, use_graph, gv, X, Xt, mom ? V : nullptr, ncols, ld));
+    TRY(run_steps(S, loop, use_graph, gv, X, Xt, mom ? V : nullptr, ncols, ld, colact, steps_ctr, Z, NB, value));
+    if (S.p->check_every <= 0) launch_add_i64(steps_ctr, ncols, S.p->steps_per_round, S.s);
     TRY(S.end_timed(e0));
   }
   launch_round(S.maxcut, X, Z, gv.lo, gv.n, ncols, ld, S.s);
@@ -550,7 +590,7 @@ int solve_batched(Solve &S, int32_t *rounds_done) {
       const GraphView gv = view_of(S.g, gi, S.max_deg);
       const int64_t t = (int64_t)gi * B;
       TRY(grid_round(S, loops[gi], use_graph, gv, r, X, Xt, V, Z, Zb, B, NB, PRIO, F, value + t, best + t, B, B,
-                     (uint64_t)t));
+                     (uint64_t)t, at<int8_t>(S.ws, S.L.colact) + t));
     }
   }
   *rounds_done = r;
@@ -591,7 +631,7 @@ int solve_plain(Solve &S, int32_t *rounds_done) {
           }
         }
         TRY(grid_round(S, loop, use_graph, gv, r, X, Xt, V, Z, Zb + b, B, NB, PRIO, F, value + t, best + t, 1, 1,
-                       (uint64_t)t));
+                       (uint64_t)t, at<int8_t>(S.ws, S.L.colact)));
       }
       rmax = std::max(rmax, r);
     }
@@ -663,6 +703,8 @@ TileArgs tile_args(Solve &S, const TileCfg &c, const float *x0) {
   a.vm = at<float>(S.ws, S.L.tvm);
   a.ls_iters = at<int32_t>(S.ws, S.L.tls);
   a.err = at<int32_t>(S.ws, S.L.err);
+  a.check_every = S.p->check_every;
+  a.steps_done = at<int64_t>(S.ws, S.L.steps);
   return a;
 }
 
@@ -772,6 +814,7 @@ int solve_tile(Solve &S, int32_t *rounds_done, TileCfg *used) {
   TileCfg cfg{};
   TRY(tune_tile(S, x0, &cfg));
   *used = cfg;
+  launch_fill_i64(at<int64_t>(S.ws, S.L.steps), (int64_t)S.G * S.B, 0, S.s);  // the tuner's trials counted too
   launch_fill_i32(at<int32_t>(S.ws, S.L.err), 1, 0, S.s);
   TileArgs a = tile_args(S, cfg, x0);
   const bool mc = S.maxcut, w = S.g->weight != nullptr;
@@ -794,7 +837,7 @@ int solve_tile(Solve &S, int32_t *rounds_done, TileCfg *used) {
     if (e != hipSuccess) return fail(MQO_ERR_HIP, "tile launch: %s", hipGetErrorString(e));
     TRY(S.end_timed(e0));
     r = a.r1;
-    if (!budget && nwg < 1024) {
+    if (!budget && nwg < 1019) {
       // read back with the solve's final synchronisation
       Resources &R = res();
       HIP_TRY(hipMemcpyAsync(R.pinned, a.ls_iters, nwg * sizeof(int32_t), hipMemcpyDeviceToHost, S.s));
@@ -863,6 +906,7 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
   S.nnz_g.resize(S.G);
   for (int32_t i = 0; i < S.G; ++i) S.nnz_g[i] = rp[i + 1] - rp[i];
 
+  launch_fill_i64(at<int64_t>(ws, L.steps), (int64_t)S.G * S.B, 0, s);
   int plan = p->plan;
   if (plan == MQO_PLAN_AUTO) plan = tile_possible(S) ? MQO_PLAN_PERSISTENT : MQO_PLAN_BATCHED;
   int32_t rounds_done = 0;
@@ -882,6 +926,11 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
     HIP_TRY(hipMemcpyAsync(r->traj_best_value, best, (size_t)S.G * S.B * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
   if (r->traj_best_x)
     HIP_TRY(hipMemcpyAsync(r->traj_best_x, at<int8_t>(ws, L.Zb), (size_t)g->n_total * S.B, hipMemcpyDeviceToDevice, s));
+  // exact edge updates: sum over trajectories of executed steps x nnz of the graph
+  int64_t *eu_dev = at<int64_t>(ws, L.dmax);  // max degree is on the host already
+  launch_edge_updates(at<int64_t>(ws, L.steps), at<int32_t>(ws, L.rpat), S.G, S.B, eu_dev, s);
+  int64_t *eu_host = reinterpret_cast<int64_t *>(res().pinned + 1020);  // 8-byte aligned, after the tile counters
+  HIP_TRY(hipMemcpyAsync(eu_host, eu_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   if (S.deferred_tile_wg) {
@@ -891,11 +940,9 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
     S.ls_iters += mx;
     if (pin[S.deferred_tile_wg]) return fail(MQO_ERR_INTERNAL, "local search did not terminate");
   }
-  int64_t nnz_sum = 0;
-  for (int64_t x : S.nnz_g) nnz_sum += x;
   r->rounds_executed = rounds_done;
   r->steps_executed = (int64_t)rounds_done * p->steps_per_round;
-  r->edge_updates = nnz_sum * S.B * r->steps_executed;
+  r->edge_updates = *eu_host;
   r->plan_used = plan;
   r->tile_cols_used = used.T;
   r->tile_threads_used = used.threads;

@@ -386,10 +386,14 @@ __device__ __forceinline__ void step_update(float &x, float &vv, float acc, floa
   x = clip_box<MAXCUT>(y);
 }
 
+// colact[c] = 0 marks a trajectory that stopped stepping for the rest of
+// the round (early exit): its iterate and momentum are copied through.
+// nullptr = all active.
 template <int VEC, bool MAXCUT, bool WEIGHTED, bool MOMENTUM, int ROWS>
 __global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__restrict__ X, float *__restrict__ Xn,
                                                   float *__restrict__ V, int32_t ncols, int32_t ld,
-                                                  int32_t lanes_log2, float alpha, float mu, float param) {
+                                                  int32_t lanes_log2, float alpha, float mu, float param,
+                                                  const int8_t *__restrict__ colact) {
   const int64_t nhb = hub_blocks(g, ncols);
   if (blockIdx.x < nhb) {
     if (blockIdx.y != 0) return;
@@ -398,7 +402,7 @@ __global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__re
     if ((int32_t)threadIdx.x < it.cw) {
       const int64_t e = it.v * ld + it.c0 + threadIdx.x;
       float x = X[e], vv = MOMENTUM ? V[e] : 0.0f;
-      step_update<MAXCUT, MOMENTUM>(x, vv, acc, alpha, mu, param);
+      if (!colact || colact[it.c0 + threadIdx.x]) step_update<MAXCUT, MOMENTUM>(x, vv, acc, alpha, mu, param);
       Xn[e] = x;
       if (MOMENTUM) V[e] = vv;
     }
@@ -417,7 +421,8 @@ __global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__re
     load_vec<VEC>(X + v[k] * ld + col, x);
     if (MOMENTUM) load_vec<VEC>(V + v[k] * ld + col, vv);
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) step_update<MAXCUT, MOMENTUM>(x[i], vv[i], acc[k][i], alpha, mu, param);
+    for (int i = 0; i < VEC; ++i)
+      if (!colact || colact[col + i]) step_update<MAXCUT, MOMENTUM>(x[i], vv[i], acc[k][i], alpha, mu, param);
     store_vec<VEC>(Xn + v[k] * ld + col, x);
     if (MOMENTUM) store_vec<VEC>(V + v[k] * ld + col, vv);
   }
@@ -464,7 +469,8 @@ __global__ __launch_bounds__(256) void k_round(const float *__restrict__ X, int8
 
 // NB = A Z (int32) and per-column accumulators acc[3][ncols] (int64):
 // MIS  : acc0 = |I|, acc1 = sum z m = 2 * edges inside I, acc2 = #{v: z=0, m=0}
-// MaxCut: acc0 = sum_v (W_v - s_v t_v) = 4 Cut(S)   (W_v = sum of row weights)
+// MaxCut: acc0 = sum_v (W_v - s_v t_v) = 4 Cut(S)   (W_v = sum of row weights),
+//         acc1 = #{v: the projected step would move s_v}
 template <bool MAXCUT, bool WEIGHTED>
 __global__ __launch_bounds__(256) void k_nbr_eval(GraphView g, const int8_t *__restrict__ Z, int32_t *__restrict__ NB,
                                                   unsigned long long *__restrict__ acc, int32_t ncols, int32_t ld,
@@ -503,6 +509,10 @@ __global__ __launch_bounds__(256) void k_nbr_eval(GraphView g, const int8_t *__r
     const int32_t zv = Z[v * ld + m.col];
     if (MAXCUT) {
       a[0] += (long long)wsum - (long long)zv * s;
+      // the projected f_B step moves s_v off the vertex unless s_v t_v < 0,
+      // or s_v t_v = 0 and s_v = -1 (gradient -lambda - 2 t_v, 0 < lambda < 2)
+      const int32_t st = zv * s;
+      a[1] += (st > 0 || (st == 0 && zv == 1)) ? 1 : 0;
     } else {
       a[0] += zv;
       a[1] += zv ? s : 0;
@@ -512,7 +522,7 @@ __global__ __launch_bounds__(256) void k_nbr_eval(GraphView g, const int8_t *__r
   const int width = lanes < 64 ? lanes : 64;
   const int wl = threadIdx.x & 63;
 #pragma unroll
-  for (int k = 0; k < (MAXCUT ? 1 : 3); ++k) {
+  for (int k = 0; k < (MAXCUT ? 2 : 3); ++k) {
     const long long t = wave_sum_stride(a[k], width);
     if (wl < width && t) atomicAdd(reinterpret_cast<unsigned long long *>(&sacc[k][wl]), (unsigned long long)t);
   }
@@ -520,7 +530,7 @@ __global__ __launch_bounds__(256) void k_nbr_eval(GraphView g, const int8_t *__r
   if ((int)threadIdx.x < lanes) {
     const int32_t c = blockIdx.y * lanes + threadIdx.x;
     if (c < ncols) {
-      for (int k = 0; k < (MAXCUT ? 1 : 3); ++k)
+      for (int k = 0; k < (MAXCUT ? 2 : 3); ++k)
         if (sacc[k][threadIdx.x]) atomicAdd(&acc[k * ncols + c], (unsigned long long)sacc[k][threadIdx.x]);
     }
   }
@@ -533,6 +543,7 @@ __global__ void k_value_finalize(const long long *__restrict__ acc, int32_t ncol
   if (c >= ncols) return;
   if (MAXCUT) {
     value[c] = acc[c] / 4;
+    if (fixed) fixed[c] = acc[ncols + c] == 0 ? 1 : 0;
   } else {
     const long long size = acc[c], conf = acc[ncols + c] / 2, freev = acc[2 * ncols + c];
     value[c] = conf == 0 ? size : -1;
@@ -1223,51 +1234,51 @@ static inline dim3 spmm_grid(const GraphView &g, int32_t ncols, int ll, int vec)
 
 template <int VEC, bool MC, bool W, bool M>
 static void step_t(const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols, int32_t ld, int ll,
-                   float alpha, float mu, float param, hipStream_t s) {
+                   float alpha, float mu, float param, const int8_t *colact, hipStream_t s) {
   const size_t lds = g.nhub ? hub_lds(W) : 0;
   if (spmm_rows(g, ll) == 2)
     MQO_LAUNCH((k_pga_step<VEC, MC, W, M, 2>), spmm_grid(g, ncols, ll, VEC), dim3(256), lds, s, g, X, Xn, V, ncols,
-               ld, ll, alpha, mu, param);
+               ld, ll, alpha, mu, param, colact);
   else
     MQO_LAUNCH((k_pga_step<VEC, MC, W, M, 1>), spmm_grid(g, ncols, ll, VEC), dim3(256), lds, s, g, X, Xn, V, ncols,
-               ld, ll, alpha, mu, param);
+               ld, ll, alpha, mu, param, colact);
 }
 
 template <int VEC>
 static void step_v(bool mc, bool w, bool m, const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols,
-                   int32_t ld, int ll, float alpha, float mu, float param, hipStream_t s) {
+                   int32_t ld, int ll, float alpha, float mu, float param, const int8_t *colact, hipStream_t s) {
   if (mc) {
     if (w) {
       if (m)
-        step_t<VEC, true, true, true>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, s);
+        step_t<VEC, true, true, true>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, colact, s);
       else
-        step_t<VEC, true, true, false>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, s);
+        step_t<VEC, true, true, false>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, colact, s);
     } else {
       if (m)
-        step_t<VEC, true, false, true>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, s);
+        step_t<VEC, true, false, true>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, colact, s);
       else
-        step_t<VEC, true, false, false>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, s);
+        step_t<VEC, true, false, false>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, colact, s);
     }
   } else {
     if (m)
-      step_t<VEC, false, false, true>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, s);
+      step_t<VEC, false, false, true>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, colact, s);
     else
-      step_t<VEC, false, false, false>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, s);
+      step_t<VEC, false, false, false>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, colact, s);
   }
 }
 
 void launch_pga_step(bool maxcut, const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols, int32_t ld,
-                     StepCfg cfg, float alpha, float mu, float param, hipStream_t s) {
+                     StepCfg cfg, float alpha, float mu, float param, hipStream_t s, const int8_t *colact) {
   const bool w = g.weight != nullptr, m = mu != 0.0f;
   switch (cfg.vec) {
     case 4:
-      step_v<4>(maxcut, w, m, g, X, Xn, V, ncols, ld, cfg.lanes_log2, alpha, mu, param, s);
+      step_v<4>(maxcut, w, m, g, X, Xn, V, ncols, ld, cfg.lanes_log2, alpha, mu, param, colact, s);
       break;
     case 2:
-      step_v<2>(maxcut, w, m, g, X, Xn, V, ncols, ld, cfg.lanes_log2, alpha, mu, param, s);
+      step_v<2>(maxcut, w, m, g, X, Xn, V, ncols, ld, cfg.lanes_log2, alpha, mu, param, colact, s);
       break;
     default:
-      step_v<1>(maxcut, w, m, g, X, Xn, V, ncols, ld, cfg.lanes_log2, alpha, mu, param, s);
+      step_v<1>(maxcut, w, m, g, X, Xn, V, ncols, ld, cfg.lanes_log2, alpha, mu, param, colact, s);
       break;
   }
 }
@@ -1279,6 +1290,66 @@ void launch_copy_f32(const float *a, float *b, int64_t count, hipStream_t s) {
 void launch_strided_copy_f32(const float *src, int32_t lds, int32_t cs, float *dst, int32_t ldd, int32_t cd,
                              int64_t lo, int64_t n, hipStream_t s) {
   MQO_LAUNCH(k_strided_copy_f32, dim3(blocks_for(n)), dim3(256), 0, s, src, lds, cs, dst, ldd, cd, lo, n);
+}
+
+// early exit: trajectories whose rounded point is fixed stop stepping
+__global__ void k_active_update(int8_t *__restrict__ colact, const int8_t *__restrict__ fixed, int32_t ncols) {
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncols && fixed[c]) colact[c] = 0;
+}
+
+// executed-step counters: + len for every active trajectory
+__global__ void k_count_steps(const int8_t *__restrict__ colact, int64_t *__restrict__ steps, int32_t ncols,
+                              int32_t len) {
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncols && colact[c]) steps[c] += len;
+}
+
+__global__ void k_fill_i8(int8_t *p, int64_t count, int8_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_add_i64(int64_t *p, int64_t count, int64_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] += v;
+}
+
+// out += sum over trajectories t = g*B + b of steps[t] * nnz_g, nnz_g from
+// the row_ptr entries at the graph boundaries (rpat[G+1]); out zeroed first
+__global__ void k_edge_updates(const int64_t *__restrict__ steps, const int32_t *__restrict__ rpat, int32_t G,
+                               int32_t B, unsigned long long *out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long v = 0;
+  if (t < (int64_t)G * B) {
+    const int32_t g = (int32_t)(t / B);
+    v = (unsigned long long)steps[t] * (unsigned long long)(rpat[g + 1] - rpat[g]);
+  }
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(out, v);
+}
+
+void launch_fill_i8(int8_t *p, int64_t count, int8_t v, hipStream_t s) {
+  MQO_LAUNCH(k_fill_i8, dim3(blocks_for(count < 262144 ? count : 262144)), dim3(256), 0, s, p, count, v);
+}
+
+void launch_add_i64(int64_t *p, int64_t count, int64_t v, hipStream_t s) {
+  MQO_LAUNCH(k_add_i64, dim3(blocks_for(count < 262144 ? count : 262144)), dim3(256), 0, s, p, count, v);
+}
+
+void launch_edge_updates(const int64_t *steps, const int32_t *rpat, int32_t G, int32_t B, int64_t *out,
+                         hipStream_t s) {
+  launch_fill_i64(out, 1, 0, s);
+  MQO_LAUNCH(k_edge_updates, dim3(blocks_for((int64_t)G * B)), dim3(256), 0, s, steps, rpat, G, B,
+             reinterpret_cast<unsigned long long *>(out));
+}
+
+void launch_active_update(int8_t *colact, const int8_t *fixed, int32_t ncols, hipStream_t s) {
+  MQO_LAUNCH(k_active_update, dim3(blocks_for(ncols)), dim3(256), 0, s, colact, fixed, ncols);
+}
+
+void launch_count_steps(const int8_t *colact, int64_t *steps, int32_t ncols, int32_t len, hipStream_t s) {
+  MQO_LAUNCH(k_count_steps, dim3(blocks_for(ncols)), dim3(256), 0, s, colact, steps, ncols, len);
 }
 
 void launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s) {

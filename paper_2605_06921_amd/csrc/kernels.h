@@ -25,8 +25,17 @@ void launch_init_uniform(bool maxcut, float *X, int64_t lo, int64_t n, int32_t n
 void launch_init_degree(bool maxcut, float *X, const int32_t *row_ptr, int32_t *dmax_scratch, int64_t lo, int64_t n,
                         int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0, float sigma, hipStream_t s);
 void launch_degree_max(const int32_t *row_ptr, int64_t n, int32_t *out, hipStream_t s);
+// colact: per-column active flags (0 = stopped for the round: copied
+// through), or nullptr for all active
 void launch_pga_step(bool maxcut, const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols, int32_t ld,
-                     StepCfg cfg, float alpha, float mu, float param, hipStream_t s);
+                     StepCfg cfg, float alpha, float mu, float param, hipStream_t s, const int8_t *colact = nullptr);
+void launch_active_update(int8_t *colact, const int8_t *fixed, int32_t ncols, hipStream_t s);
+void launch_fill_i8(int8_t *p, int64_t count, int8_t v, hipStream_t s);
+void launch_add_i64(int64_t *p, int64_t count, int64_t v, hipStream_t s);
+// *out = sum_t steps[t] * nnz of t's graph (rpat: row_ptr at the G+1 graph boundaries)
+void launch_edge_updates(const int64_t *steps, const int32_t *rpat, int32_t G, int32_t B, int64_t *out,
+                         hipStream_t s);
+void launch_count_steps(const int8_t *colact, int64_t *steps, int32_t ncols, int32_t len, hipStream_t s);
 void launch_copy_f32(const float *a, float *b, int64_t count, hipStream_t s);
 void launch_strided_copy_f32(const float *src, int32_t lds, int32_t cs, float *dst, int32_t ldd, int32_t cd,
                              int64_t lo, int64_t n, hipStream_t s);
@@ -86,6 +95,7 @@ struct TileArgs {
   int32_t dreg;     // > 0: neighbour offsets held in registers, padded to dreg
   int32_t ipt;      // lane items per thread in the register-adjacency path
   int32_t steps, r0, r1, reset_mode, ls;
+  int32_t check_every;  // > 0: early-exit test after every check_every steps of a round
   float alpha, mu, param;
   double rho;
   uint64_t seed;
@@ -98,6 +108,7 @@ struct TileArgs {
   int8_t *fl;
   float *vm;          // momentum, same layout (used when mu != 0)
   int32_t *ls_iters;  // [workgroups]
+  int64_t *steps_done;  // [G*B] PGA steps executed, accumulated
   int32_t *err;
 };
 

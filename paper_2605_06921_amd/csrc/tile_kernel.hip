@@ -14,6 +14,8 @@
 //
 // Arithmetic per element is identical to the grid kernels (same operation
 // order), so every plan gives bit-identical trajectories.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -67,6 +69,10 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
   __shared__ unsigned long long s_acc[2][TILE_MAX_T];
   __shared__ int32_t s_take[TILE_MAX_T];
   __shared__ int32_t s_active[2];
+  // early exit: column still stepping in this round, its rounded point
+  // failed the fixed-point test, PGA steps it executed (all rounds)
+  __shared__ int32_t s_act[TILE_MAX_T], s_viol[TILE_MAX_T];
+  __shared__ long long s_cnt[TILE_MAX_T];
 
   const int nthr = blockDim.x, tid = threadIdx.x;
   const int wave = tid >> 6, nwaves = nthr >> 6;
@@ -114,6 +120,8 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
   const int32_t *ci = a.col_idx;
   const int32_t *wt = a.weight;
 
+  if (tid < TILE_MAX_T) s_cnt[tid] = 0;
+  const bool chk = a.check_every > 0;
   const int32_t e0 = a.row_ptr[lo];
   for (int32_t v = tid; v <= n; v += nthr) rps[v] = a.row_ptr[lo + v] - e0;
   const int32_t nnz_g = a.row_ptr[lo + n] - e0;
@@ -235,118 +243,192 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
     // ------------------------------------------------------------ PGA steps
     const int32_t nI = nT / VEC;  // lane items: VEC consecutive trajectories of one row
     if constexpr (DREG > 0) {
-      // Step st reads buffer (st & 1 ? xb : xa) and writes the other; all
-      // neighbour reads of the lane's rows are independent LDS loads,
-      // unconditional (padding reads the zero row) so that they issue back to
-      // back.
 #pragma unroll
       for (int i = 0; i < IPT; ++i) {
         const int32_t L = tid + i * nthr;
         xr[i] = L < nT ? xa[L] : 0.0f;
       }
-      auto reg_step = [&](const float *const(&p)[RI][RD], float *dst) {
-#pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-          const int32_t L = tid + i * nthr;
-          if (L < nT) {
-            float acc = 0.0f;
-#pragma unroll
-            for (int kk = 0; kk < DREG; ++kk) acc = acc + *p[i][kk];
-            const float gr = grad_from_sum<MAXCUT>(acc, a.param);
-            float d = gr;
-            if (momentum) {
-              const float t = a.mu * vm[L];
-              d = t + gr;
-              vm[L] = d;
-            }
-            const float s = a.alpha * d;
-            const float y = xr[i] + s;
-            xr[i] = clip_box<MAXCUT>(y);
-            dst[L] = xr[i];
-          }
-        }
-        __syncthreads();
-      };
-      for (int32_t st = 0; st < a.steps; st += 2) {
-        reg_step(pa, xb);
-        if (st + 1 < a.steps) reg_step(pb, xa);
-      }
     }
-    for (int32_t st = 0; DREG == 0 && st < a.steps; ++st) {
-      const float *src = (st & 1) ? xb : xa;
-      float *dst = (st & 1) ? xa : xb;
-      for (int32_t I = tid; I < nI; I += nthr) {
-        const int32_t L0 = I * VEC;
-        const int32_t v = L0 >> lt, c0 = L0 & (T - 1);
-        const int32_t beg = rps[v], end = rps[v + 1];
-        float acc[VEC];
+    // Step st reads buffer (st & 1 ? xb : xa) and writes the other.  With
+    // check_every = c > 0 the steps run in chunks of c; after every chunk but
+    // the last, columns whose rounded point is a fixed point of the projected
+    // step stop for the rest of the round (their entries are copied through).
+    if (tid < T) {
+      s_act[tid] = tid < cols ? 1 : 0;
+      s_viol[tid] = 0;
+    }
+    __syncthreads();
+    int32_t done = 0;
+    while (done < a.steps) {
+      const int32_t len = chk ? min(a.check_every, a.steps - done) : a.steps - done;
+      if (T == 1 && !s_act[0]) break;  // uniform: the workgroup's only trajectory stopped
+      __syncthreads();
+      if (tid < cols && s_act[tid]) s_cnt[tid] += len;
+      if constexpr (DREG > 0) {
+        // all neighbour reads of the lane's rows are independent LDS loads,
+        // unconditional (padding reads the zero row) so that they issue back
+        // to back
+        // CHK (compile-time): stopped columns are copied through
+        auto reg_step = [&](auto chk_tag, const float *const(&p)[RI][RD], float *dst) {
+          constexpr bool CHK = decltype(chk_tag)::value;
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
-        if constexpr (CSR_LDS) {
-          // eight local ids per 16-byte LDS read; neighbours still added in
-          // ascending CSR order
-          for (int32_t j0 = beg & ~7; j0 < end; j0 += 8) {
-            const uint4 q = *reinterpret_cast<const uint4 *>(cls + j0);
-            const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-            for (int kk = 0; kk < 8; ++kk) {
-              const int32_t j = j0 + kk;
-              if (j < beg || j >= end) continue;
-              const int32_t u = (int32_t)((qw[kk >> 1] >> (16 * (kk & 1))) & 0xffffu);
-              float xu[VEC];
-              lds_load<VEC>(src + ((u << lt) | c0), xu);
-              if (WEIGHTED) {
-                const float w = (float)wtg[j];
-#pragma unroll
-                for (int i = 0; i < VEC; ++i) {
-                  const float p = w * xu[i];
-                  acc[i] = acc[i] + p;
-                }
-              } else {
-#pragma unroll
-                for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + xu[i];
+          for (int i = 0; i < IPT; ++i) {
+            const int32_t L = tid + i * nthr;
+            if (L < nT) {
+              if (CHK && T > 1 && !s_act[L & (T - 1)]) {
+                dst[L] = xr[i];
+                continue;
               }
+              float acc = 0.0f;
+#pragma unroll
+              for (int kk = 0; kk < DREG; ++kk) acc = acc + *p[i][kk];
+              const float gr = grad_from_sum<MAXCUT>(acc, a.param);
+              float d = gr;
+              if (momentum) {
+                const float t = a.mu * vm[L];
+                d = t + gr;
+                vm[L] = d;
+              }
+              const float s = a.alpha * d;
+              const float y = xr[i] + s;
+              xr[i] = clip_box<MAXCUT>(y);
+              dst[L] = xr[i];
             }
+          }
+          __syncthreads();
+        };
+        if (!chk) {
+          for (int32_t st = done; st < done + len; st += 2) {
+            reg_step(std::false_type{}, pa, xb);
+            if (st + 1 < done + len) reg_step(std::false_type{}, pb, xa);
           }
         } else {
-#pragma unroll 4
-          for (int32_t j = beg; j < end; ++j) {
-            const int32_t u = cig[j] - ilo;
-            float xu[VEC];
-            lds_load<VEC>(src + ((u << lt) | c0), xu);
-            if (WEIGHTED) {
-              const float w = (float)wtg[j];
+          for (int32_t st = done; st < done + len; ++st) {
+            if (st & 1)
+              reg_step(std::true_type{}, pb, xa);
+            else
+              reg_step(std::true_type{}, pa, xb);
+          }
+        }
+      }
+      if constexpr (DREG == 0) {
+        // CHK (compile-time): stopped columns are copied through
+        auto gen_step = [&](auto chk_tag, int32_t st) {
+          constexpr bool CHK = decltype(chk_tag)::value;
+          const float *src = (st & 1) ? xb : xa;
+          float *dst = (st & 1) ? xa : xb;
+          for (int32_t I = tid; I < nI; I += nthr) {
+            const int32_t L0 = I * VEC;
+            const int32_t v = L0 >> lt, c0 = L0 & (T - 1);
+            const int32_t beg = rps[v], end = rps[v + 1];
+            float acc[VEC];
 #pragma unroll
-              for (int i = 0; i < VEC; ++i) {
-                const float p = w * xu[i];
-                acc[i] = acc[i] + p;
+            for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
+            if constexpr (CSR_LDS) {
+              // eight local ids per 16-byte LDS read; neighbours still added in
+              // ascending CSR order
+              for (int32_t j0 = beg & ~7; j0 < end; j0 += 8) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(cls + j0);
+                const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) {
+                  const int32_t j = j0 + kk;
+                  if (j < beg || j >= end) continue;
+                  const int32_t u = (int32_t)((qw[kk >> 1] >> (16 * (kk & 1))) & 0xffffu);
+                  float xu[VEC];
+                  lds_load<VEC>(src + ((u << lt) | c0), xu);
+                  if (WEIGHTED) {
+                    const float w = (float)wtg[j];
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) {
+                      const float p = w * xu[i];
+                      acc[i] = acc[i] + p;
+                    }
+                  } else {
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + xu[i];
+                  }
+                }
               }
             } else {
+#pragma unroll 4
+              for (int32_t j = beg; j < end; ++j) {
+                const int32_t u = cig[j] - ilo;
+                float xu[VEC];
+                lds_load<VEC>(src + ((u << lt) | c0), xu);
+                if (WEIGHTED) {
+                  const float w = (float)wtg[j];
 #pragma unroll
-              for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + xu[i];
+                  for (int i = 0; i < VEC; ++i) {
+                    const float p = w * xu[i];
+                    acc[i] = acc[i] + p;
+                  }
+                } else {
+#pragma unroll
+                  for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + xu[i];
+                }
+              }
             }
-          }
-        }
-        float x[VEC];
-        lds_load<VEC>(src + L0, x);
+            float x[VEC];
+            lds_load<VEC>(src + L0, x);
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) {
-          const float gr = grad_from_sum<MAXCUT>(acc[i], a.param);
-          float d = gr;
-          if (momentum) {
-            const float t = a.mu * vm[L0 + i];
-            d = t + gr;
-            vm[L0 + i] = d;
+            for (int i = 0; i < VEC; ++i) {
+              const float gr = grad_from_sum<MAXCUT>(acc[i], a.param);
+              float d = gr;
+              if (momentum) {
+                const float t = a.mu * vm[L0 + i];
+                d = t + gr;
+                if (!CHK || s_act[c0 + i]) vm[L0 + i] = d;
+              }
+              const float s = a.alpha * d;
+              const float y = x[i] + s;
+              if (!CHK || s_act[c0 + i]) x[i] = clip_box<MAXCUT>(y);  // else copied through
+            }
+            lds_store<VEC>(dst + L0, x);
           }
-          const float s = a.alpha * d;
-          const float y = x[i] + s;
-          x[i] = clip_box<MAXCUT>(y);
+          __syncthreads();
+        };
+        for (int32_t st = done; st < done + len; ++st) {
+          if (chk)
+            gen_step(std::true_type{}, st);
+          else
+            gen_step(std::false_type{}, st);
         }
-        lds_store<VEC>(dst + L0, x);
       }
-      __syncthreads();
+      done += len;
+      if (done < a.steps) {
+        // the early-exit test on the current iterate
+        const float *xc = (done & 1) ? xb : xa;
+        for (int32_t L = tid; L < nT; L += nthr) zs[L] = round_x<MAXCUT>(xc[L]);
+        __syncthreads();
+        for (int32_t L = tid; L < nT; L += nthr) {
+          const int32_t v = L >> lt, c = L & (T - 1);
+          if (c >= cols || !s_act[c]) continue;
+          int32_t sum = 0;
+          for (int32_t j = rps[v]; j < rps[v + 1]; ++j) {
+            const int32_t u = CSR_LDS ? (int32_t)cls[j] : cig[j] - ilo;
+            const int32_t zu = zs[(u << lt) | c];
+            sum += WEIGHTED ? wtg[j] * zu : zu;
+          }
+          const int32_t z = zs[L];
+          bool moves;
+          if (MAXCUT) {
+            const int32_t st = z * sum;  // gradient -lambda - 2 t_v, 0 < lambda < 2
+            moves = st > 0 || (st == 0 && z == 1);
+          } else {
+            moves = z ? sum != 0 : sum == 0;  // checker of Eq. (8), gamma > 1
+          }
+          if (moves) s_viol[c] = 1;
+        }
+        __syncthreads();
+        if (tid < T) {
+          if (!s_viol[tid]) s_act[tid] = 0;
+          s_viol[tid] = 0;
+        }
+        __syncthreads();
+      }
     }
-    const float *xf = (a.steps & 1) ? xb : xa;
+    const float *xf = (done & 1) ? xb : xa;
 
     // ------------------------------------------- rounding and neighbour counts
     for (int32_t L = tid; L < nT; L += nthr) zs[L] = round_x<MAXCUT>(xf[L]);
@@ -472,6 +554,7 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
     __syncthreads();
   }
   if (tid == 0) a.ls_iters[wid] = ls_total;
+  if (tid < cols) a.steps_done[traj0 + tid] += s_cnt[tid];
 }
 
 bool tile_shape_ok(int64_t n_max, int T, int threads, int vec, bool csr_lds, int dreg, int ipt) {

@@ -93,7 +93,7 @@ def _struct(m, n=10, G=1, offsets=None, weight=False):
 
 @pytest.mark.parametrize("field,value,status", [
     ("batch", 0, -1), ("rounds", 0, -1), ("alpha", -0.1, -1), ("gamma", 1.0, -1), ("rho", 1.0, -1),
-    ("momentum", 1.0, -1), ("check_every", 5, -5), ("plan", 9, -1), ("tile_cols", 3, -1),
+    ("momentum", 1.0, -1), ("check_every", -1, -1), ("plan", 9, -1), ("tile_cols", 3, -1),
     ("tile_threads", 100, -1), ("steps_per_round", -1, -1), ("init_mode", 4, -1),
 ])
 def test_solve_rejects_parameters_on_host(m, field, value, status):

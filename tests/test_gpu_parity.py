@@ -495,3 +495,36 @@ def test_row_pairs_forced(mqo, name, B):
         rX0, ra = pga.unrolled_backward(g, kind, param, alpha, K, X0, dL.astype(np.float64), precision="fp32")
         assert np.abs(dX0.cpu().numpy() - rX0).max() / max(1.0, np.abs(rX0).max()) <= 1e-4
         assert np.allclose(da.cpu().numpy(), ra, rtol=1e-4, atol=1e-4 * np.abs(ra).max())
+
+
+# --------------------------------------------------------------------------
+# a11: optional early exit of a round at fixed points of the projected step
+# --------------------------------------------------------------------------
+
+EXIT_CASES = [
+    ("mis", "er300", dict(batch=6, steps_per_round=60, rounds=3, alpha=0.05, rho=0.1)),
+    ("mis", "er_batch", dict(batch=5, steps_per_round=45, rounds=2, alpha=0.05, rho=0.1)),
+    ("maxcut", "reg3", dict(batch=10, steps_per_round=80, rounds=3, alpha=0.2, rho=0.05)),
+    ("maxcut", "torus", dict(batch=4, steps_per_round=50, rounds=2, alpha=0.2, rho=0.2, reset_mode="flip")),
+    ("maxcut", "cut_batch", dict(batch=3, steps_per_round=40, rounds=2, alpha=0.2, rho=0.3, momentum=0.5)),
+]
+
+
+@pytest.mark.parametrize("ci", range(len(EXIT_CASES)))
+@pytest.mark.parametrize("check", [1, 7, 200])
+@pytest.mark.parametrize("plan,tile", [("persistent", {}), ("persistent", dict(tile_cols=4, tile_reg=1)),
+                                       ("batched", {}), ("plain", {})])
+def test_early_exit_bit_exact(mqo, ci, check, plan, tile):
+    kind, name, kw = EXIT_CASES[ci]
+    g = CASES[name][1]
+    kw = dict(kw, seed=23, check_every=check)
+    out = mqo.solve(kind, mqo.DeviceGraph(g, DEV), plan=plan, **tile, **kw)
+    p = solver.Params(batch=kw["batch"], steps_per_round=kw["steps_per_round"], rounds=kw["rounds"],
+                      alpha=kw["alpha"], seed=23, mu=kw.get("momentum", 0.0), rho=kw["rho"],
+                      reset_mode=kw.get("reset_mode", "zero"), check_every=check)
+    ref = solver.solve(kind, g, p)
+    assert np.array_equal(out["traj_best_value"].cpu().numpy(), ref["traj_best_value"])
+    assert np.array_equal(out["traj_best_x"].cpu().numpy(), ref["traj_best_x"])
+    nnz_g = np.diff(g.row_ptr[g.vtx_offset])
+    eu = int((ref["traj_steps"].reshape(g.num_graphs, -1) * nnz_g[:, None]).sum())
+    assert out["edge_updates"] == eu
