@@ -20,7 +20,11 @@ import numpy as np
 import scipy.sparse as sp
 
 MIS = "mis"
-MAXCUT = "maxcut"
+MAXCUT = "maxcut"        # perturbed bias f_B, Eq. (7): the formulation the algorithms use
+MAXCUT_L = "maxcut_fl"   # Laplacian f_L, Eq. (4)
+MAXCUT_P = "maxcut_fp"   # perturbed Laplacian f_P, Eq. (5)
+MAXCUT_A = "maxcut_fa"   # adjacency f_A, Eq. (6)
+CUT_KINDS = (MAXCUT, MAXCUT_L, MAXCUT_P, MAXCUT_A)
 
 
 def adjacency(graph, dtype=np.float64) -> sp.csr_matrix:
@@ -75,13 +79,63 @@ def f_P(X, A, lam):
     return np.einsum("vb,vb->b", X, laplacian(A) @ X) + lam * np.einsum("vb,vb->b", X, X)
 
 
+def grad_f_L(X, A):
+    """Gradient of Eq. (4): (1/2) L x.  (The text's proof of Prop. 3.5 writes
+    L x; differentiating (1/4) x^T L x with L symmetric gives L x / 2.)"""
+    X = np.asarray(X, dtype=np.float64)
+    return 0.5 * (laplacian(A) @ X)
+
+
+def grad_f_P(X, A, lam):
+    """Gradient of Eq. (5): 2 (L + lambda I) x.  (The proof of Thm. 3.3 steps
+    by alpha/2 (L + lambda I) x, which changes alpha only; both fix every
+    binary point.)"""
+    X = np.asarray(X, dtype=np.float64)
+    return 2.0 * (laplacian(A) @ X + lam * X)
+
+
+def grad_f_A(X, A):
+    """Gradient of Eq. (6): -2 A x."""
+    return -2.0 * (A @ np.asarray(X, dtype=np.float64))
+
+
 def objective(kind, X, A, param):
-    """The objective the path ascends: h for MIS, f_B for MaxCut."""
-    return h(X, A, param) if kind == MIS else f_B(X, A, param)
+    """The objective the path ascends: h for MIS, f_B (or the formulation
+    named by ``kind``) for MaxCut."""
+    if kind == MIS:
+        return h(X, A, param)
+    if kind == MAXCUT_L:
+        return f_L(X, A)
+    if kind == MAXCUT_P:
+        return f_P(X, A, param)
+    if kind == MAXCUT_A:
+        return f_A(X, A)
+    return f_B(X, A, param)
 
 
 def gradient(kind, X, A, param):
-    return grad_h(X, A, param) if kind == MIS else grad_f_B(X, A, param)
+    if kind == MIS:
+        return grad_h(X, A, param)
+    if kind == MAXCUT_L:
+        return grad_f_L(X, A)
+    if kind == MAXCUT_P:
+        return grad_f_P(X, A, param)
+    if kind == MAXCUT_A:
+        return grad_f_A(X, A)
+    return grad_f_B(X, A, param)
+
+
+def hessian_vec(kind, A, param, M):
+    """H m for the (quadratic) objective of ``kind``: its gradient is
+    grad(0) + H x."""
+    M = np.asarray(M, dtype=np.float64)
+    if kind == MIS:
+        return -param * (A @ M)
+    if kind == MAXCUT_L:
+        return 0.5 * (laplacian(A) @ M)
+    if kind == MAXCUT_P:
+        return 2.0 * (laplacian(A) @ M + param * M)
+    return -2.0 * (A @ M)
 
 
 def box(kind):

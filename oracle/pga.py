@@ -60,10 +60,31 @@ def neighbour_sum32(graph, X):
     return acc
 
 
+def weighted_degree32(graph):
+    """W_v = sum of the row's weights (the degree when unweighted), exact in float32."""
+    deg = np.diff(graph.row_ptr.astype(np.int64))
+    if graph.weight is None:
+        return deg.astype(F32)
+    rows = np.repeat(np.arange(graph.n), deg)
+    return np.bincount(rows, weights=graph.weight.astype(np.float64), minlength=graph.n).astype(F32)
+
+
 def gradient32(graph, X, kind, param):
+    """float32 gradient, one rounding per operation in the order written:
+    MIS 1 - gamma acc; f_B -lambda - 2 acc; f_L 0.5 (W x - acc);
+    f_P 2 ((W x - acc) + lambda x); f_A -2 acc (acc = A x summed in CSR order)."""
+    X = np.asarray(X, dtype=F32)
     acc = neighbour_sum32(graph, X)
     if kind == obj.MIS:
         return F32(1.0) - F32(param) * acc
+    if kind in (obj.MAXCUT_L, obj.MAXCUT_P):
+        W = weighted_degree32(graph)[:, None]
+        t = W * X - acc
+        if kind == obj.MAXCUT_L:
+            return F32(0.5) * t
+        return F32(2.0) * (t + F32(param) * X)
+    if kind == obj.MAXCUT_A:
+        return F32(-2.0) * acc
     return F32(-F32(param)) - F32(2.0) * acc
 
 
@@ -151,30 +172,29 @@ def unrolled_backward(graph, kind, param, alpha, K, X0, dL_dXK, precision="fp64"
     """Adjoint of the K-step map (float64 arithmetic).
 
     With z_k = x_k + alpha g(x_k), x_{k+1} = Pi(z_k), mask_k = [lo <= z_k <= hi]
-    and g(x) = c + eta A x:
+    and g(x) = g(0) + H x (every objective here is quadratic):
         mu_k   = mask_k * lam_{k+1}
         dL/dalpha += <mu_k, g(x_k)>
-        lam_k  = mu_k + alpha * eta * A mu_k
+        lam_k  = mu_k + alpha * H mu_k
     starting from lam_K = dL/dx_K.  ``precision`` selects the forward pass
     that decides the masks (the float32 replay when comparing with a
     float32 forward).  Returns (dL/dX0, dL/dalpha per column)."""
     xs = unrolled_forward(graph, kind, param, alpha, K, X0, precision)
     A = obj.adjacency(graph)
-    c, eta = obj.linear_and_hessian(kind, param)
     lo, hi = obj.box(kind)
     lam = np.asarray(dL_dXK, dtype=np.float64)
     dalpha = np.zeros(lam.shape[1])
     for k in range(K - 1, -1, -1):
         xk = xs[k]
         if precision == "fp64":
-            g = c + eta * (A @ xk)
+            g = obj.gradient(kind, xk, A, param)
             z = xk + alpha * g
         else:
             g32 = gradient32(graph, xk, kind, param)
             z = (xk + F32(alpha) * g32).astype(np.float64)
-            g = c + eta * (A @ xk.astype(np.float64))
+            g = obj.gradient(kind, xk.astype(np.float64), A, param)
         mask = (z >= lo) & (z <= hi)
         mu = np.where(mask, lam, 0.0)
         dalpha += np.einsum("vb,vb->b", mu, g)
-        lam = mu + alpha * eta * (A @ mu)
+        lam = mu + alpha * obj.hessian_vec(kind, A, param, mu)
     return lam, dalpha

@@ -1,0 +1,96 @@
+"""The MaxCut formulations of Sec. 3 besides f_B -- Laplacian f_L (Eq. (4)),
+perturbed Laplacian f_P (Eq. (5)), adjacency f_A (Eq. (6)) -- in the CPU
+oracle, pinned to the paper's statements about them."""
+import itertools
+
+import numpy as np
+import pytest
+
+from synth import graphs, arrays
+from oracle import objectives as obj, discrete, pga
+
+FORMS = [obj.MAXCUT, obj.MAXCUT_L, obj.MAXCUT_P, obj.MAXCUT_A]
+
+
+def _spins(n):
+    return np.array(list(itertools.product([-1, 1], repeat=n)), dtype=np.float64).T
+
+
+@pytest.mark.parametrize("kind", FORMS)
+@pytest.mark.parametrize("weighted", [False, True])
+def test_gradient_central_differences(kind, weighted):
+    g = graphs.erdos_renyi(30, 0.2, 800)
+    if weighted:
+        g = graphs.with_weights(g, 801)
+    A = obj.adjacency(g)
+    X = arrays.uniform((g.n, 3), -1.0, 1.0, 802).astype(np.float64)
+    G = obj.gradient(kind, X, A, 0.3)
+    h = 1e-3  # exact for a quadratic up to rounding
+    for v in range(0, g.n, 7):
+        E = np.zeros_like(X)
+        E[v] = h
+        fd = (obj.objective(kind, X + E, A, 0.3) - obj.objective(kind, X - E, A, 0.3)) / (2 * h)
+        assert np.allclose(fd, G[v], rtol=1e-9, atol=1e-9)
+    # the Hessian-vector product is the gradient's linear part
+    M = arrays.uniform((g.n, 3), -1.0, 1.0, 803).astype(np.float64)
+    assert np.allclose(obj.hessian_vec(kind, A, 0.3, M), G - obj.gradient(kind, X - M, A, 0.3), atol=1e-9)
+
+
+def test_laplacian_is_the_cut_and_adjacency_differs_by_a_constant():
+    """Eq. (4): f_L = Cut on {-1,1}^n; Eq. (6): f_A differs from f_L by a
+    constant there (f_A = 4 f_L - sum of weights)."""
+    for weighted in (False, True):
+        g = graphs.erdos_renyi(8, 0.5, 810)
+        if weighted:
+            g = graphs.with_weights(g, 811, values=(1, 2, 3))
+        A = obj.adjacency(g)
+        S = _spins(g.n)
+        cut = discrete.evaluate_cut(g, S.astype(np.int8))
+        assert np.allclose(obj.f_L(S, A), cut)
+        wsum = A.sum()
+        assert np.allclose(obj.f_A(S, A), 4 * cut - wsum)
+
+
+def test_laplacian_stationary_points_have_zero_cut():
+    """Prop. 3.5: c 1 is stationary for f_L (a PGA fixed point), interior
+    for |c| < 1, binary for c = +-1, and its cut is 0."""
+    g = graphs.erdos_renyi(40, 0.3, 820)
+    A = obj.adjacency(g)
+    for c in (-1.0, -0.375, 0.0, 0.5, 1.0):  # dyadic: the row sums are exact
+        X = np.full((g.n, 1), c)
+        assert np.allclose(obj.grad_f_L(X, A), 0.0)
+        Y, _ = pga.step64(X, A, obj.MAXCUT_L, 0.1, 0.0)
+        assert np.array_equal(Y, X)
+    assert discrete.evaluate_cut(g, discrete.round_x(obj.MAXCUT_L, np.full((g.n, 1), 0.5)))[0] == 0
+
+
+def test_perturbed_laplacian_fixes_every_binary_point():
+    """Thm. 3.3: for lambda > 0 every x in {-1,1}^n is a PGA fixed point of f_P."""
+    g = graphs.erdos_renyi(9, 0.45, 830)
+    A = obj.adjacency(g)
+    S = _spins(g.n)
+    for lam, alpha in ((1e-3, 0.1), (0.5, 0.01)):
+        Y, _ = pga.step64(S, A, obj.MAXCUT_P, alpha, lam)
+        assert np.array_equal(Y, S)
+
+
+def test_adjacency_escapes_one_flip_repairable_points():
+    """Prop. 3.6: a binary x that one flip improves is not a PGA fixed point
+    of f_A."""
+    g = graphs.erdos_renyi(9, 0.45, 840)
+    A = obj.adjacency(g)
+    S = _spins(g.n)
+    repairable = np.any(discrete.gains(obj.MAXCUT, g, S.astype(np.int8)) > 0, axis=0)
+    Y, _ = pga.step64(S, A, obj.MAXCUT_A, 0.1, 0.0)
+    moved = np.any(Y != S, axis=0)
+    assert repairable.any()
+    assert np.all(moved[repairable])
+
+
+@pytest.mark.parametrize("kind", FORMS)
+def test_float32_replay_close_to_float64(kind):
+    g = graphs.with_weights(graphs.erdos_renyi(60, 0.1, 850), 851)
+    X = arrays.uniform((g.n, 4), -1.0, 1.0, 852)
+    y32, _ = pga.step32(g, X, kind, 0.05, 0.2)
+    y64, _ = pga.step64(X.astype(np.float64), obj.adjacency(g), kind, 0.05, 0.2)
+    assert np.abs(y32 - y64).max() <= 1e-5
