@@ -57,7 +57,21 @@ typedef enum {
  * MQO_OBJ_MAXCUT_FB: f_B(x) = -lambda 1^T x - x^T A x on [-1,1]^n,
  *                    0 < lambda < 2 (Sec. 3, Eq. (7), Thm. 3.6);
  *                    grad = -2 A x - lambda.  A_uv = w_uv when weighted. */
-typedef enum { MQO_OBJ_MIS_H = 0, MQO_OBJ_MAXCUT_FB = 1 } mqo_objective;
+/* Relaxed objectives (Sec. 3): MIS h (Eq. (3), parameter gamma > 1);
+ * MaxCut perturbed bias f_B (Eq. (7), lambda in (0,2), the formulation the
+ * algorithms use), Laplacian f_L (Eq. (4), no parameter), perturbed
+ * Laplacian f_P (Eq. (5), lambda > 0) and adjacency f_A (Eq. (6), no
+ * parameter), all on the box [-1,1]^n.  The MaxCut formulations share
+ * rounding, cut evaluation and local search; f_L, f_P and f_A run on the
+ * batched and plain plans (not the persistent one) and without
+ * check_every. */
+typedef enum {
+  MQO_OBJ_MIS_H = 0,
+  MQO_OBJ_MAXCUT_FB = 1,
+  MQO_OBJ_MAXCUT_FL = 2,
+  MQO_OBJ_MAXCUT_FP = 3,
+  MQO_OBJ_MAXCUT_FA = 4
+} mqo_objective;
 
 enum { MQO_INIT_UNIFORM = 0, MQO_INIT_DEGREE = 1 };
 enum { MQO_RESET_ZERO = 0, MQO_RESET_FLIP = 1 };
@@ -132,6 +146,8 @@ typedef struct {
                               1 = never, 0 = autotune                        */
   uint64_t seed;
   double time_budget_s;    /* 0 = none; otherwise no round starts after it      */
+  int32_t maxcut_objective; /* mqo_solve_maxcut: MQO_OBJ_MAXCUT_FB (default),
+                              _FL, _FP or _FA                                  */
 } mqo_params;
 
 /* Outputs of a solve.  Device arrays are written; host fields are set. */

@@ -145,8 +145,19 @@ int check_params(const mqo_params *p, mqo_objective obj) {
   if (!(p->momentum >= 0.0f && p->momentum < 1.0f)) return fail(MQO_ERR_INVALID_ARG, "momentum must be in [0,1)");
   if (obj == MQO_OBJ_MIS_H && !(p->gamma > 1.0f && std::isfinite(p->gamma)))
     return fail(MQO_ERR_INVALID_ARG, "gamma must be > 1 (Eq. 3)");
-  if (obj == MQO_OBJ_MAXCUT_FB && !(p->lambda > 0.0f && p->lambda < 2.0f))
-    return fail(MQO_ERR_INVALID_ARG, "lambda must be in (0, 2) (Thm. 3.6)");
+  if (obj != MQO_OBJ_MIS_H) {
+    // obj: the continuous objective (a solve passes p->maxcut_objective)
+    const int f = obj;
+    if (f < MQO_OBJ_MAXCUT_FB || f > MQO_OBJ_MAXCUT_FA) return fail(MQO_ERR_INVALID_ARG, "bad maxcut_objective");
+    if (f == MQO_OBJ_MAXCUT_FB && !(p->lambda > 0.0f && p->lambda < 2.0f))
+      return fail(MQO_ERR_INVALID_ARG, "lambda must be in (0, 2) (Thm. 3.6)");
+    if (f == MQO_OBJ_MAXCUT_FP && !(p->lambda > 0.0f && std::isfinite(p->lambda)))
+      return fail(MQO_ERR_INVALID_ARG, "lambda must be > 0 for f_P (Eq. 5)");
+    if (f != MQO_OBJ_MAXCUT_FB && p->plan == MQO_PLAN_PERSISTENT)
+      return fail(MQO_ERR_UNSUPPORTED, "the persistent plan runs h and f_B only");
+    if (f != MQO_OBJ_MAXCUT_FB && p->check_every > 0)
+      return fail(MQO_ERR_UNSUPPORTED, "check_every is offered for h and f_B only");
+  }
   if (!(p->rho >= 0.0 && p->rho < 1.0)) return fail(MQO_ERR_INVALID_ARG, "rho must be in [0, 1)");
   if (!(p->init_sigma >= 0.0f) || !std::isfinite(p->init_sigma))
     return fail(MQO_ERR_INVALID_ARG, "init_sigma must be >= 0");
@@ -353,7 +364,8 @@ struct Solve {
   const mqo_graph *g;
   const mqo_params *p;
   mqo_objective obj;
-  bool maxcut;
+  bool maxcut;  // discrete side (rounding, cut, local search)
+  int form;     // continuous objective of the steps (OBJ_* = mqo_objective)
   float param;
   int32_t B, G;
   int64_t n_max;
@@ -473,7 +485,7 @@ void enqueue_steps(Solve &S, const GraphView &gv, float *X, float *Xt, float *V,
   const StepCfg cfg = default_step_cfg(ncols, ld);
   float *a = X, *b = Xt;
   for (int32_t st = 0; st < steps; ++st) {
-    launch_pga_step(S.maxcut, gv, a, b, V, ncols, ld, cfg, S.p->alpha, S.p->momentum, S.param, S.s, colact);
+    launch_pga_step(S.form, gv, a, b, V, ncols, ld, cfg, S.p->alpha, S.p->momentum, S.param, S.s, colact);
     std::swap(a, b);
   }
   if (a != X) launch_copy_f32(a + gv.lo * ld, X + gv.lo * ld, gv.n * ld, S.s);
@@ -661,6 +673,7 @@ bool tile_feasible(const Solve &S, const TileCfg &c) {
 
 // any shape at all fits (plan selection)
 bool tile_possible(const Solve &S) {
+  if (S.form != OBJ_H && S.form != OBJ_FB) return false;  // the persistent kernel runs h and f_B
   for (int T = 1; T <= 64; T <<= 1)
     for (int th : {256, 512, 1024})
       if (tile_feasible(S, TileCfg{T, th, 1, 0, 0, 0})) return true;
@@ -863,7 +876,8 @@ int solve_tile(Solve &S, int32_t *rounds_done, TileCfg *used) {
 int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_result *r, void *ws, size_t ws_bytes,
                  void *stream, mqo_objective obj) {
   TRY(check_graph_args(g, obj == MQO_OBJ_MIS_H));
-  TRY(check_params(p, obj));
+  if (!p) return fail(MQO_ERR_INVALID_ARG, "params is NULL");
+  TRY(check_params(p, obj == MQO_OBJ_MIS_H ? obj : (mqo_objective)p->maxcut_objective));
   if (!r || !r->best_x || !r->best_value) return fail(MQO_ERR_INVALID_ARG, "result arrays best_x/best_value required");
   const Layout L = make_layout(g, p->batch);
   if (!ws || ws_bytes < L.total) return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", L.total);
@@ -879,7 +893,8 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
   S.g = g;
   S.p = p;
   S.obj = obj;
-  S.maxcut = obj == MQO_OBJ_MAXCUT_FB;
+  S.maxcut = obj != MQO_OBJ_MIS_H;
+  S.form = S.maxcut ? p->maxcut_objective : (int)MQO_OBJ_MIS_H;
   S.param = S.maxcut ? p->lambda : p->gamma;
   S.B = p->batch;
   S.G = g->num_graphs;
@@ -957,8 +972,8 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
 
 // per-graph helper for the asynchronous entry points
 int check_async(const mqo_graph *g, mqo_objective obj, int32_t B) {
+  if (obj < MQO_OBJ_MIS_H || obj > MQO_OBJ_MAXCUT_FA) return fail(MQO_ERR_INVALID_ARG, "bad objective");
   TRY(check_graph_args(g, obj == MQO_OBJ_MIS_H));
-  if (obj != MQO_OBJ_MIS_H && obj != MQO_OBJ_MAXCUT_FB) return fail(MQO_ERR_INVALID_ARG, "bad objective");
   if (B < 1) return fail(MQO_ERR_INVALID_ARG, "B must be >= 1");
   return MQO_OK;
 }
@@ -968,6 +983,8 @@ int check_param(mqo_objective obj, float param) {
     return fail(MQO_ERR_INVALID_ARG, "gamma must be > 1 (Eq. 3)");
   if (obj == MQO_OBJ_MAXCUT_FB && !(param > 0.0f && param < 2.0f))
     return fail(MQO_ERR_INVALID_ARG, "lambda must be in (0, 2) (Thm. 3.6)");
+  if (obj == MQO_OBJ_MAXCUT_FP && !(param > 0.0f && std::isfinite(param)))
+    return fail(MQO_ERR_INVALID_ARG, "lambda must be > 0 for f_P (Eq. 5)");
   return MQO_OK;
 }
 
@@ -1013,6 +1030,7 @@ void mqo_params_default(mqo_params *p) {
   p->plan = MQO_PLAN_AUTO;
   p->seed = 0;
   p->time_budget_s = 0.0;
+  p->maxcut_objective = MQO_OBJ_MAXCUT_FB;
 }
 
 size_t mqo_workspace_size(const mqo_graph *g, const mqo_params *p, mqo_objective obj) {
@@ -1051,14 +1069,15 @@ int mqo_objective_grad(const mqo_graph *g, mqo_objective obj, float param, const
   if (f_out && (!ws || ws_bytes < mqo_objective_workspace_size(g, B)))
     return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", mqo_objective_workspace_size(g, B));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const bool mc = obj == MQO_OBJ_MAXCUT_FB;
+  const bool mc = obj != MQO_OBJ_MIS_H;
+  const int form = (int)obj;
   const StepCfg cfg = default_step_cfg(B, B);
   for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
     const GraphView gv = view_of(g, gi);
     const float *sc = scale ? scale + (int64_t)gi * B : nullptr;
     double *part = f_out ? reinterpret_cast<double *>(ws) : nullptr;
-    launch_objective_grad(mc, gv, X, sc, grad_out, part, B, B, cfg, param, s);
-    if (f_out) launch_reduce_partials(part, spmm_row_blocks(gv, cfg) + gv.nhub, B, f_out + (int64_t)gi * B, false, s);
+    launch_objective_grad(form, gv, X, sc, grad_out, part, B, B, cfg, param, s);
+    if (f_out) launch_reduce_partials(part, spmm_row_blocks(gv, cfg, form) + gv.nhub, B, f_out + (int64_t)gi * B, false, s);
   }
   HIP_TRY(hipGetLastError());
   return MQO_OK;
@@ -1082,7 +1101,8 @@ int mqo_pga_unrolled_forward(const mqo_graph *g, mqo_objective obj, float param,
   if (!ws || ws_bytes < mqo_unrolled_workspace_size(g, B, ckpt_every))
     return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", mqo_unrolled_workspace_size(g, B, ckpt_every));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const bool mc = obj == MQO_OBJ_MAXCUT_FB;
+  const bool mc = obj != MQO_OBJ_MIS_H;
+  const int form = (int)obj;
   const StepCfg cfg = default_step_cfg(B, B);
   const int64_t nb = g->n_total * B;
   float *W = reinterpret_cast<float *>(ws);
@@ -1097,7 +1117,7 @@ int mqo_pga_unrolled_forward(const mqo_graph *g, mqo_objective obj, float param,
       float *target = j == nseg - 1 ? XK : ckpt + (int64_t)(j + 1) * nb;
       for (int32_t i = 1; i <= ckpt_every; ++i) {
         float *dst = ((ckpt_every - i) % 2 == 0) ? target : W;
-        launch_pga_step(mc, gv, src, dst, nullptr, B, B, cfg, alpha, 0.0f, param, s);
+        launch_pga_step(form, gv, src, dst, nullptr, B, B, cfg, alpha, 0.0f, param, s);
         src = dst;
       }
     }
@@ -1118,7 +1138,8 @@ int mqo_pga_unrolled_backward(const mqo_graph *g, mqo_objective obj, float param
   if (!ws || ws_bytes < mqo_unrolled_workspace_size(g, B, ckpt_every))
     return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", mqo_unrolled_workspace_size(g, B, ckpt_every));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const bool mc = obj == MQO_OBJ_MAXCUT_FB;
+  const bool mc = obj != MQO_OBJ_MIS_H;
+  const int form = (int)obj;
   const StepCfg cfg = default_step_cfg(B, B);
   const int64_t nb = g->n_total * B;
   const size_t slot = align_up((size_t)nb * sizeof(float));
@@ -1132,16 +1153,16 @@ int mqo_pga_unrolled_backward(const mqo_graph *g, mqo_objective obj, float param
   const int32_t nseg = K / ckpt_every;
   for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
     const GraphView gv = view_of(g, gi);
-    const int64_t nblk = spmm_row_blocks(gv, cfg) + gv.nhub;
+    const int64_t nblk = spmm_row_blocks(gv, cfg, form) + gv.nhub;
     launch_copy_f32(dL_dXK + gv.lo * B, lamA + gv.lo * B, gv.n * B, s);
     launch_fill_i64(reinterpret_cast<int64_t *>(dL_dalpha + (int64_t)gi * B), B, 0, s);  // +0.0
     float *cur = lamA, *nxt = lamB;
     for (int32_t j = nseg - 1; j >= 0; --j) {
       states[0] = const_cast<float *>(ckpt + (int64_t)j * nb);
       for (int32_t i = 1; i < ckpt_every; ++i)
-        launch_pga_step(mc, gv, states[i - 1], states[i], nullptr, B, B, cfg, alpha, 0.0f, param, s);
+        launch_pga_step(form, gv, states[i - 1], states[i], nullptr, B, B, cfg, alpha, 0.0f, param, s);
       for (int32_t i = ckpt_every - 1; i >= 0; --i) {
-        launch_adjoint_step(mc, gv, states[i], cur, mu, nxt, part, B, B, cfg, alpha, param, s);
+        launch_adjoint_step(form, gv, states[i], cur, mu, nxt, part, B, B, cfg, alpha, param, s);
         launch_reduce_partials(part, nblk, B, dL_dalpha + (int64_t)gi * B, true, s);
         std::swap(cur, nxt);
       }
@@ -1160,7 +1181,8 @@ int mqo_init_iterate(const mqo_graph *g, mqo_objective obj, const mqo_params *p,
   if (!X) return fail(MQO_ERR_INVALID_ARG, "X is NULL");
   TRY(ensure_resources());
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const bool mc = obj == MQO_OBJ_MAXCUT_FB;
+  const bool mc = obj != MQO_OBJ_MIS_H;
+  const int form = (int)obj;
   const int32_t B = p->batch;
   for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
     const GraphView gv = view_of(g, gi);
@@ -1181,7 +1203,8 @@ int mqo_pga_steps(const mqo_graph *g, mqo_objective obj, const mqo_params *p, fl
   if (!X || !tmp || nsteps < 0) return fail(MQO_ERR_INVALID_ARG, "X and tmp are required, nsteps >= 0");
   if (p->momentum != 0.0f && !V) return fail(MQO_ERR_INVALID_ARG, "V is required when momentum != 0");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const bool mc = obj == MQO_OBJ_MAXCUT_FB;
+  const bool mc = obj != MQO_OBJ_MIS_H;
+  const int form = (int)obj;
   const int32_t B = p->batch;
   const float param = mc ? p->lambda : p->gamma;
   const StepCfg cfg = default_step_cfg(B, B);
@@ -1189,7 +1212,7 @@ int mqo_pga_steps(const mqo_graph *g, mqo_objective obj, const mqo_params *p, fl
     const GraphView gv = view_of(g, gi);
     float *a = X, *b = tmp;
     for (int32_t st = 0; st < nsteps; ++st) {
-      launch_pga_step(mc, gv, a, b, p->momentum != 0.0f ? V : nullptr, B, B, cfg, p->alpha, p->momentum, param, s);
+      launch_pga_step(form, gv, a, b, p->momentum != 0.0f ? V : nullptr, B, B, cfg, p->alpha, p->momentum, param, s);
       std::swap(a, b);
     }
     if (a != X) launch_copy_f32(a + gv.lo * B, X + gv.lo * B, gv.n * B, s);
@@ -1205,7 +1228,8 @@ int mqo_round_evaluate(const mqo_graph *g, mqo_objective obj, const float *X, in
   const Layout L = make_layout(g, B);
   if (!ws || ws_bytes < L.total) return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", L.total);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const bool mc = obj == MQO_OBJ_MAXCUT_FB;
+  const bool mc = obj != MQO_OBJ_MIS_H;
+  const int form = (int)obj;
   for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
     const GraphView gv = view_of(g, gi);
     const int64_t t = (int64_t)gi * B;
@@ -1226,7 +1250,8 @@ int mqo_local_search(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t 
   TRY(ensure_resources());
   std::lock_guard<std::mutex> host_lock(res().host_mu);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const bool mc = obj == MQO_OBJ_MAXCUT_FB;
+  const bool mc = obj != MQO_OBJ_MIS_H;
+  const int form = (int)obj;
   int64_t total = 0;
   for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
     const GraphView gv = view_of(g, gi);
@@ -1250,7 +1275,8 @@ int mqo_reset(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t seed, i
   const Layout L = make_layout(g, B);
   if (!ws || ws_bytes < L.total) return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", L.total);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const bool mc = obj == MQO_OBJ_MAXCUT_FB;
+  const bool mc = obj != MQO_OBJ_MIS_H;
+  const int form = (int)obj;
   for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
     const GraphView gv = view_of(g, gi);
     const int32_t k = (int32_t)std::floor(rho * (double)gv.n);

@@ -76,6 +76,17 @@ __device__ __forceinline__ float grad_from_sum(float acc, float param) {
   }
 }
 
+// The continuous objective of a PGA step: MIS h (Eq. (3)) or one of the
+// MaxCut formulations of Sec. 3 (the algorithms use f_B).
+enum : int { OBJ_H = 0, OBJ_FB = 1, OBJ_FL = 2, OBJ_FP = 3, OBJ_FA = 4 };
+
+// Gradient at x_v from acc = (A x)_v and the weighted degree W_v (used by
+// f_L, f_P), one float32 rounding per operation in the order written:
+// f_L 0.5 (W x - acc) (Eq. (4)), f_P 2 ((W x - acc) + lambda x) (Eq. (5)),
+// f_A -2 acc (Eq. (6)); h and f_B as grad_from_sum.
+template <int OBJ>
+__device__ __forceinline__ float grad_of(float acc, float x, float W, float param);
+
 template <bool MAXCUT>
 __device__ __forceinline__ float box_lo() { return MAXCUT ? -1.0f : 0.0f; }
 __device__ __forceinline__ float box_hi() { return 1.0f; }
@@ -83,6 +94,25 @@ __device__ __forceinline__ float box_hi() { return 1.0f; }
 template <bool MAXCUT>
 __device__ __forceinline__ float clip_box(float y) {
   return fminf(fmaxf(y, box_lo<MAXCUT>()), box_hi());
+}
+
+template <int OBJ>
+__device__ __forceinline__ float grad_of(float acc, float x, float W, float param) {
+  if constexpr (OBJ == OBJ_H || OBJ == OBJ_FB) {
+    return grad_from_sum<OBJ == OBJ_FB>(acc, param);
+  } else if constexpr (OBJ == OBJ_FA) {
+    return -2.0f * acc;
+  } else {
+    const float t1 = W * x;
+    const float t2 = t1 - acc;
+    if constexpr (OBJ == OBJ_FL) {
+      return 0.5f * t2;
+    } else {
+      const float t3 = param * x;
+      const float t4 = t2 + t3;
+      return 2.0f * t4;
+    }
+  }
 }
 
 // Threshold rounding of Sec. 3: MIS x > 0.5 -> 1 else 0; MaxCut x > 0 -> +1 else -1.

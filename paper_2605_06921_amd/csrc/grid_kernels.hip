@@ -372,9 +372,21 @@ __device__ __forceinline__ void group_gather(const GraphView &g, const float *__
 }
 
 // One PGA step of Sec. 3 (with optional heavy-ball momentum) for a single column.
-template <bool MAXCUT, bool MOMENTUM>
-__device__ __forceinline__ void step_update(float &x, float &vv, float acc, float alpha, float mu, float param) {
-  const float gr = grad_from_sum<MAXCUT>(acc, param);
+// W_v, the row's weight sum (its degree when unweighted), for f_L and f_P
+template <bool WEIGHTED>
+__device__ __forceinline__ float weighted_degree(const GraphView &g, int64_t v) {
+  const int32_t beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+  if (!WEIGHTED) return (float)(end - beg);
+  int32_t w = 0;
+  for (int32_t j = beg; j < end; ++j) w += g.weight[j];
+  return (float)w;
+}
+
+template <int OBJ, bool MOMENTUM>
+__device__ __forceinline__ void step_update(float &x, float &vv, float acc, float W, float alpha, float mu,
+                                            float param) {
+  constexpr bool MAXCUT = OBJ != OBJ_H;
+  const float gr = grad_of<OBJ>(acc, x, W, param);
   float d = gr;
   if (MOMENTUM) {
     const float t = mu * vv;
@@ -389,7 +401,7 @@ __device__ __forceinline__ void step_update(float &x, float &vv, float acc, floa
 // colact[c] = 0 marks a trajectory that stopped stepping for the rest of
 // the round (early exit): its iterate and momentum are copied through.
 // nullptr = all active.
-template <int VEC, bool MAXCUT, bool WEIGHTED, bool MOMENTUM, int ROWS>
+template <int VEC, int OBJ, bool WEIGHTED, bool MOMENTUM, int ROWS>
 __global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__restrict__ X, float *__restrict__ Xn,
                                                   float *__restrict__ V, int32_t ncols, int32_t ld,
                                                   int32_t lanes_log2, float alpha, float mu, float param,
@@ -402,7 +414,8 @@ __global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__re
     if ((int32_t)threadIdx.x < it.cw) {
       const int64_t e = it.v * ld + it.c0 + threadIdx.x;
       float x = X[e], vv = MOMENTUM ? V[e] : 0.0f;
-      if (!colact || colact[it.c0 + threadIdx.x]) step_update<MAXCUT, MOMENTUM>(x, vv, acc, alpha, mu, param);
+      const float W = OBJ == OBJ_FL || OBJ == OBJ_FP ? weighted_degree<WEIGHTED>(g, it.v) : 0.0f;
+      if (!colact || colact[it.c0 + threadIdx.x]) step_update<OBJ, MOMENTUM>(x, vv, acc, W, alpha, mu, param);
       Xn[e] = x;
       if (MOMENTUM) V[e] = vv;
     }
@@ -420,9 +433,10 @@ __global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__re
     float x[VEC], vv[VEC];
     load_vec<VEC>(X + v[k] * ld + col, x);
     if (MOMENTUM) load_vec<VEC>(V + v[k] * ld + col, vv);
+    const float W = OBJ == OBJ_FL || OBJ == OBJ_FP ? weighted_degree<WEIGHTED>(g, v[k]) : 0.0f;
 #pragma unroll
     for (int i = 0; i < VEC; ++i)
-      if (!colact || colact[col + i]) step_update<MAXCUT, MOMENTUM>(x[i], vv[i], acc[k][i], alpha, mu, param);
+      if (!colact || colact[col + i]) step_update<OBJ, MOMENTUM>(x[i], vv[i], acc[k][i], W, alpha, mu, param);
     store_vec<VEC>(Xn + v[k] * ld + col, x);
     if (MOMENTUM) store_vec<VEC>(V + v[k] * ld + col, vv);
   }
@@ -976,16 +990,29 @@ __device__ __forceinline__ void block_column_partials(const double (&val)[VEC], 
 // Partials of the objective and gradient of Eq. (3) / (7):
 // f_b = sum_v x_v (c + eta/2 (A x)_v), grad = scale_b (c + eta A x).
 // Partial rows: one per row workgroup, then one per hub row.
-template <bool MAXCUT>
-__device__ __forceinline__ void objective_terms(float x, float acc, float param, float sc, float &gr, double &fv) {
-  const double c = MAXCUT ? -(double)param : 1.0;
-  const double eta = MAXCUT ? -2.0 : -(double)param;
-  const float gg = grad_from_sum<MAXCUT>(acc, param);
+// per-vertex objective contribution (float64): h x (1 - gamma/2 acc),
+// f_B x (-lambda - acc), f_A -x acc, f_L x (W x - acc) / 4,
+// f_P x (W x - acc + lambda x)
+template <int OBJ>
+__device__ __forceinline__ void objective_terms(float x, float acc, float W, float param, float sc, float &gr,
+                                                double &fv) {
+  const float gg = grad_of<OBJ>(acc, x, W, param);
   gr = sc * gg;
-  fv = (double)x * (c + 0.5 * eta * (double)acc);
+  const double xd = x, ad = acc;
+  if constexpr (OBJ == OBJ_H) {
+    fv = xd * (1.0 - 0.5 * (double)param * ad);
+  } else if constexpr (OBJ == OBJ_FB) {
+    fv = xd * (-(double)param - ad);
+  } else if constexpr (OBJ == OBJ_FA) {
+    fv = -xd * ad;
+  } else if constexpr (OBJ == OBJ_FL) {
+    fv = 0.25 * xd * ((double)W * xd - ad);
+  } else {
+    fv = xd * ((double)W * xd - ad + (double)param * xd);
+  }
 }
 
-template <int VEC, bool MAXCUT, bool WEIGHTED, int ROWS>
+template <int VEC, int OBJ, bool WEIGHTED, int ROWS>
 __global__ __launch_bounds__(256) void k_objective_grad(GraphView g, const float *__restrict__ X,
                                                         const float *__restrict__ scale, float *__restrict__ grad,
                                                         double *__restrict__ part, int32_t ncols, int32_t ld,
@@ -1001,7 +1028,8 @@ __global__ __launch_bounds__(256) void k_objective_grad(GraphView g, const float
       const int64_t e = it.v * ld + c;
       float gr;
       double fv;
-      objective_terms<MAXCUT>(X[e], acc, param, scale ? scale[c] : 1.0f, gr, fv);
+      const float W = OBJ == OBJ_FL || OBJ == OBJ_FP ? weighted_degree<WEIGHTED>(g, it.v) : 0.0f;
+      objective_terms<OBJ>(X[e], acc, W, param, scale ? scale[c] : 1.0f, gr, fv);
       if (grad) grad[e] = gr;
       if (part) part[(nrb + it.h) * ncols + c] = fv;
     }
@@ -1022,10 +1050,11 @@ __global__ __launch_bounds__(256) void k_objective_grad(GraphView g, const float
     any = true;
     float x[VEC], gr[VEC];
     load_vec<VEC>(X + v[k] * ld + col, x);
+    const float W = OBJ == OBJ_FL || OBJ == OBJ_FP ? weighted_degree<WEIGHTED>(g, v[k]) : 0.0f;
 #pragma unroll
     for (int i = 0; i < VEC; ++i) {
       double f;
-      objective_terms<MAXCUT>(x[i], acc[k][i], param, scale ? scale[col + i] : 1.0f, gr[i], f);
+      objective_terms<OBJ>(x[i], acc[k][i], W, param, scale ? scale[col + i] : 1.0f, gr[i], f);
       fv[i] += f;
     }
     if (grad) store_vec<VEC>(grad + v[k] * ld + col, gr);
@@ -1069,10 +1098,11 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double *__restric
 
 // adjoint, part 1: recompute g(x_k), the clip mask, mu = mask * lam_next,
 // and partials of <mu, g> for dL/dalpha (rows as in k_objective_grad)
-template <bool MAXCUT>
-__device__ __forceinline__ void adjoint_mu(float x, float ln, float acc, float alpha, float param, float &mu,
+template <int OBJ>
+__device__ __forceinline__ void adjoint_mu(float x, float ln, float acc, float W, float alpha, float param, float &mu,
                                            double &dv) {
-  const float gr = grad_from_sum<MAXCUT>(acc, param);
+  constexpr bool MAXCUT = OBJ != OBJ_H;
+  const float gr = grad_of<OBJ>(acc, x, W, param);
   const float s = alpha * gr;
   const float z = x + s;
   const bool mask = z >= box_lo<MAXCUT>() && z <= box_hi();
@@ -1080,7 +1110,7 @@ __device__ __forceinline__ void adjoint_mu(float x, float ln, float acc, float a
   dv = (double)mu * (double)gr;
 }
 
-template <int VEC, bool MAXCUT, bool WEIGHTED, int ROWS>
+template <int VEC, int OBJ, bool WEIGHTED, int ROWS>
 __global__ __launch_bounds__(256) void k_adj_mu(GraphView g, const float *__restrict__ Xk,
                                                 const float *__restrict__ lam_next, float *__restrict__ mu_out,
                                                 double *__restrict__ part, int32_t ncols, int32_t ld,
@@ -1096,7 +1126,8 @@ __global__ __launch_bounds__(256) void k_adj_mu(GraphView g, const float *__rest
       const int64_t e = it.v * ld + c;
       float mu;
       double dv;
-      adjoint_mu<MAXCUT>(Xk[e], lam_next[e], acc, alpha, param, mu, dv);
+      const float W = OBJ == OBJ_FL || OBJ == OBJ_FP ? weighted_degree<WEIGHTED>(g, it.v) : 0.0f;
+      adjoint_mu<OBJ>(Xk[e], lam_next[e], acc, W, alpha, param, mu, dv);
       mu_out[e] = mu;
       part[(nrb + it.h) * ncols + c] = dv;
     }
@@ -1118,10 +1149,11 @@ __global__ __launch_bounds__(256) void k_adj_mu(GraphView g, const float *__rest
     float x[VEC], ln[VEC], mu[VEC];
     load_vec<VEC>(Xk + v[k] * ld + col, x);
     load_vec<VEC>(lam_next + v[k] * ld + col, ln);
+    const float W = OBJ == OBJ_FL || OBJ == OBJ_FP ? weighted_degree<WEIGHTED>(g, v[k]) : 0.0f;
 #pragma unroll
     for (int i = 0; i < VEC; ++i) {
       double d;
-      adjoint_mu<MAXCUT>(x[i], ln[i], acc[k][i], alpha, param, mu[i], d);
+      adjoint_mu<OBJ>(x[i], ln[i], acc[k][i], W, alpha, param, mu[i], d);
       dv[i] += d;
     }
     store_vec<VEC>(mu_out + v[k] * ld + col, mu);
@@ -1129,17 +1161,34 @@ __global__ __launch_bounds__(256) void k_adj_mu(GraphView g, const float *__rest
   block_column_partials<VEC>(dv, any, col, ncols, lanes_log2, part, blockIdx.x - nhb);
 }
 
-// adjoint, part 2: lam_k = mu + alpha * (eta * (A mu))
-__device__ __forceinline__ float adjoint_lambda(float mv, float acc, float alpha, float eta) {
-  const float t1 = eta * acc;
-  const float t2 = alpha * t1;
-  return mv + t2;
+// adjoint, part 2: lam_k = mu + alpha (H mu), H the objective's Hessian:
+// -gamma A (h), -2 A (f_B, f_A), (D - A) / 2 (f_L), 2 (D - A + lambda I) (f_P)
+template <int OBJ>
+__device__ __forceinline__ float adjoint_lambda(float mv, float acc, float W, float alpha, float param) {
+  float hm;
+  if constexpr (OBJ == OBJ_H) {
+    hm = (-param) * acc;
+  } else if constexpr (OBJ == OBJ_FB || OBJ == OBJ_FA) {
+    hm = -2.0f * acc;
+  } else {
+    const float t1 = W * mv;
+    const float t2 = t1 - acc;
+    if constexpr (OBJ == OBJ_FL) {
+      hm = 0.5f * t2;
+    } else {
+      const float t3 = param * mv;
+      const float t4 = t2 + t3;
+      hm = 2.0f * t4;
+    }
+  }
+  const float t = alpha * hm;
+  return mv + t;
 }
 
-template <int VEC, bool WEIGHTED, int ROWS>
+template <int VEC, int OBJ, bool WEIGHTED, int ROWS>
 __global__ __launch_bounds__(256) void k_adj_lambda(GraphView g, const float *__restrict__ mu, float *__restrict__ lam,
                                                     int32_t ncols, int32_t ld, int32_t lanes_log2, float alpha,
-                                                    float eta) {
+                                                    float param) {
   const int64_t nhb = hub_blocks(g, ncols);
   if (blockIdx.x < nhb) {
     if (blockIdx.y != 0) return;
@@ -1147,7 +1196,8 @@ __global__ __launch_bounds__(256) void k_adj_lambda(GraphView g, const float *__
     const float acc = hub_gather<WEIGHTED>(g, mu, it, ld);
     if ((int32_t)threadIdx.x < it.cw) {
       const int64_t e = it.v * ld + it.c0 + threadIdx.x;
-      lam[e] = adjoint_lambda(mu[e], acc, alpha, eta);
+      const float W = OBJ == OBJ_FL || OBJ == OBJ_FP ? weighted_degree<WEIGHTED>(g, it.v) : 0.0f;
+      lam[e] = adjoint_lambda<OBJ>(mu[e], acc, W, alpha, param);
     }
     return;
   }
@@ -1162,8 +1212,9 @@ __global__ __launch_bounds__(256) void k_adj_lambda(GraphView g, const float *__
     if (!own[k]) continue;
     float mv[VEC], out[VEC];
     load_vec<VEC>(mu + v[k] * ld + col, mv);
+    const float W = OBJ == OBJ_FL || OBJ == OBJ_FP ? weighted_degree<WEIGHTED>(g, v[k]) : 0.0f;
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) out[i] = adjoint_lambda(mv[i], acc[k][i], alpha, eta);
+    for (int i = 0; i < VEC; ++i) out[i] = adjoint_lambda<OBJ>(mv[i], acc[k][i], W, alpha, param);
     store_vec<VEC>(lam + v[k] * ld + col, out);
   }
 }
@@ -1222,65 +1273,82 @@ StepCfg default_step_cfg(int32_t ncols, int32_t ld) {
 // Row workgroups of a sparse-product kernel plus, in front, one workgroup per
 // (hub row, column slice).
 // rows per lane group of the sparse-product kernels: pairs on near-regular
-// graphs when a row has 4 or more lanes (the lockstep gather shuffles indices)
-static inline int spmm_rows(const GraphView &g, int ll) { return g.pairs && ll >= 2 ? 2 : 1; }
+// graphs when a row has 4 or more lanes (the lockstep gather shuffles
+// indices), for h and f_B
+static inline int spmm_rows(const GraphView &g, int ll, int form) {
+  return g.pairs && ll >= 2 && (form == OBJ_H || form == OBJ_FB) ? 2 : 1;
+}
 
-static inline dim3 spmm_grid(const GraphView &g, int32_t ncols, int ll, int vec) {
-  const int rows = spmm_rows(g, ll);
+static inline dim3 spmm_grid(const GraphView &g, int32_t ncols, int ll, int vec, int form) {
+  const int rows = spmm_rows(g, ll, form);
   dim3 grid = grid_rows((g.n + rows - 1) / rows, ncols, ll, vec, 256);
   grid.x = (unsigned)(grid.x + hub_blocks(g, ncols));
   return grid;
 }
 
-template <int VEC, bool MC, bool W, bool M>
-static void step_t(const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols, int32_t ld, int ll,
-                   float alpha, float mu, float param, const int8_t *colact, hipStream_t s) {
-  const size_t lds = g.nhub ? hub_lds(W) : 0;
-  if (spmm_rows(g, ll) == 2)
-    MQO_LAUNCH((k_pga_step<VEC, MC, W, M, 2>), spmm_grid(g, ncols, ll, VEC), dim3(256), lds, s, g, X, Xn, V, ncols,
-               ld, ll, alpha, mu, param, colact);
-  else
-    MQO_LAUNCH((k_pga_step<VEC, MC, W, M, 1>), spmm_grid(g, ncols, ll, VEC), dim3(256), lds, s, g, X, Xn, V, ncols,
-               ld, ll, alpha, mu, param, colact);
-}
-
-template <int VEC>
-static void step_v(bool mc, bool w, bool m, const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols,
-                   int32_t ld, int ll, float alpha, float mu, float param, const int8_t *colact, hipStream_t s) {
-  if (mc) {
-    if (w) {
-      if (m)
-        step_t<VEC, true, true, true>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, colact, s);
-      else
-        step_t<VEC, true, true, false>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, colact, s);
-    } else {
-      if (m)
-        step_t<VEC, true, false, true>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, colact, s);
-      else
-        step_t<VEC, true, false, false>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, colact, s);
-    }
-  } else {
-    if (m)
-      step_t<VEC, false, false, true>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, colact, s);
-    else
-      step_t<VEC, false, false, false>(g, X, Xn, V, ncols, ld, ll, alpha, mu, param, colact, s);
-  }
-}
-
-void launch_pga_step(bool maxcut, const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols, int32_t ld,
-                     StepCfg cfg, float alpha, float mu, float param, hipStream_t s, const int8_t *colact) {
-  const bool w = g.weight != nullptr, m = mu != 0.0f;
-  switch (cfg.vec) {
-    case 4:
-      step_v<4>(maxcut, w, m, g, X, Xn, V, ncols, ld, cfg.lanes_log2, alpha, mu, param, colact, s);
+// Calls F::template run<OBJ, WEIGHTED>(args...) for the launch's objective
+// form and weights: MIS only unweighted, every MaxCut formulation either.
+template <typename F, typename... Args>
+static void dispatch_form(int form, bool weighted, Args &&...args) {
+  switch (form) {
+    case OBJ_H:
+      F::template run<OBJ_H, false>(args...);
       break;
-    case 2:
-      step_v<2>(maxcut, w, m, g, X, Xn, V, ncols, ld, cfg.lanes_log2, alpha, mu, param, colact, s);
+    case OBJ_FB:
+      if (weighted) F::template run<OBJ_FB, true>(args...);
+      else F::template run<OBJ_FB, false>(args...);
+      break;
+    case OBJ_FL:
+      if (weighted) F::template run<OBJ_FL, true>(args...);
+      else F::template run<OBJ_FL, false>(args...);
+      break;
+    case OBJ_FP:
+      if (weighted) F::template run<OBJ_FP, true>(args...);
+      else F::template run<OBJ_FP, false>(args...);
       break;
     default:
-      step_v<1>(maxcut, w, m, g, X, Xn, V, ncols, ld, cfg.lanes_log2, alpha, mu, param, colact, s);
+      if (weighted) F::template run<OBJ_FA, true>(args...);
+      else F::template run<OBJ_FA, false>(args...);
       break;
   }
+}
+
+template <int VEC, bool MOMENTUM>
+struct StepLaunch {
+  template <int OBJ, bool W>
+  static void run(const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols, int32_t ld, int ll,
+                  float alpha, float mu, float param, const int8_t *colact, hipStream_t s) {
+    const size_t lds = g.nhub ? hub_lds(W) : 0;
+    const dim3 grid = spmm_grid(g, ncols, ll, VEC, OBJ);
+    if constexpr (OBJ == OBJ_H || OBJ == OBJ_FB) {
+      if (spmm_rows(g, ll, OBJ) == 2) {
+        MQO_LAUNCH((k_pga_step<VEC, OBJ, W, MOMENTUM, 2>), grid, dim3(256), lds, s, g, X, Xn, V, ncols, ld, ll, alpha,
+                   mu, param, colact);
+        return;
+      }
+    }
+    MQO_LAUNCH((k_pga_step<VEC, OBJ, W, MOMENTUM, 1>), grid, dim3(256), lds, s, g, X, Xn, V, ncols, ld, ll, alpha,
+               mu, param, colact);
+  }
+};
+
+void launch_pga_step(int form, const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols, int32_t ld,
+                     StepCfg cfg, float alpha, float mu, float param, hipStream_t s, const int8_t *colact) {
+  const bool w = g.weight != nullptr, m = mu != 0.0f;
+  const int ll = cfg.lanes_log2;
+#define MQO_STEP(VV)                                                                                              \
+  if (m)                                                                                                         \
+    dispatch_form<StepLaunch<VV, true>>(form, w, g, X, Xn, V, ncols, ld, ll, alpha, mu, param, colact, s);   \
+  else                                                                                                           \
+    dispatch_form<StepLaunch<VV, false>>(form, w, g, X, Xn, V, ncols, ld, ll, alpha, mu, param, colact, s);
+  if (cfg.vec == 4) {
+    MQO_STEP(4)
+  } else if (cfg.vec == 2) {
+    MQO_STEP(2)
+  } else {
+    MQO_STEP(1)
+  }
+#undef MQO_STEP
 }
 
 void launch_copy_f32(const float *a, float *b, int64_t count, hipStream_t s) {
@@ -1505,44 +1573,40 @@ void launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, const 
 
 int64_t grid_blocks_x(int64_t nrows, StepCfg cfg) { return grid_rows(nrows, 1, cfg.lanes_log2, 1, 256).x; }
 
-int64_t spmm_row_blocks(const GraphView &g, StepCfg cfg) {
-  const int rows = spmm_rows(g, cfg.lanes_log2);
+int64_t spmm_row_blocks(const GraphView &g, StepCfg cfg, int form) {
+  const int rows = spmm_rows(g, cfg.lanes_log2, form);
   return grid_rows((g.n + rows - 1) / rows, 1, cfg.lanes_log2, 1, 256).x;
 }
 
-template <int VEC, bool MC, bool W>
-static void obj_t(const GraphView &g, const float *X, const float *scale, float *grad, double *part, int32_t ncols,
+template <int VEC>
+struct ObjLaunch {
+  template <int OBJ, bool W>
+  static void run(const GraphView &g, const float *X, const float *scale, float *grad, double *part, int32_t ncols,
                   int32_t ld, int ll, float param, hipStream_t s) {
-  const size_t lds = std::max(g.nhub ? hub_lds(W) : 0, part ? PARTIAL_LDS(VEC) : 0);
-  if (spmm_rows(g, ll) == 2)
-    MQO_LAUNCH((k_objective_grad<VEC, MC, W, 2>), spmm_grid(g, ncols, ll, VEC), dim3(256), lds, s, g, X, scale, grad,
-               part, ncols, ld, ll, param);
-  else
-    MQO_LAUNCH((k_objective_grad<VEC, MC, W, 1>), spmm_grid(g, ncols, ll, VEC), dim3(256), lds, s, g, X, scale, grad,
-               part, ncols, ld, ll, param);
-}
+    const size_t lds = std::max(g.nhub ? hub_lds(W) : 0, part ? PARTIAL_LDS(VEC) : 0);
+    const dim3 grid = spmm_grid(g, ncols, ll, VEC, OBJ);
+    if constexpr (OBJ == OBJ_H || OBJ == OBJ_FB) {
+      if (spmm_rows(g, ll, OBJ) == 2) {
+        MQO_LAUNCH((k_objective_grad<VEC, OBJ, W, 2>), grid, dim3(256), lds, s, g, X, scale, grad, part, ncols, ld, ll,
+                   param);
+        return;
+      }
+    }
+    MQO_LAUNCH((k_objective_grad<VEC, OBJ, W, 1>), grid, dim3(256), lds, s, g, X, scale, grad, part, ncols, ld, ll,
+               param);
+  }
+};
 
-void launch_objective_grad(bool maxcut, const GraphView &g, const float *X, const float *scale, float *grad,
+void launch_objective_grad(int form, const GraphView &g, const float *X, const float *scale, float *grad,
                            double *part, int32_t ncols, int32_t ld, StepCfg cfg, float param, hipStream_t s) {
   const bool w = g.weight != nullptr;
   const int ll = cfg.lanes_log2;
-#define MQO_OBJ(V)                                                    \
-  if (maxcut) {                                                       \
-    if (w)                                                            \
-      obj_t<V, true, true>(g, X, scale, grad, part, ncols, ld, ll, param, s);  \
-    else                                                              \
-      obj_t<V, true, false>(g, X, scale, grad, part, ncols, ld, ll, param, s); \
-  } else {                                                            \
-    obj_t<V, false, false>(g, X, scale, grad, part, ncols, ld, ll, param, s);  \
-  }
-  if (cfg.vec == 4) {
-    MQO_OBJ(4)
-  } else if (cfg.vec == 2) {
-    MQO_OBJ(2)
-  } else {
-    MQO_OBJ(1)
-  }
-#undef MQO_OBJ
+  if (cfg.vec == 4)
+    dispatch_form<ObjLaunch<4>>(form, w, g, X, scale, grad, part, ncols, ld, ll, param, s);
+  else if (cfg.vec == 2)
+    dispatch_form<ObjLaunch<2>>(form, w, g, X, scale, grad, part, ncols, ld, ll, param, s);
+  else
+    dispatch_form<ObjLaunch<1>>(form, w, g, X, scale, grad, part, ncols, ld, ll, param, s);
 }
 
 void launch_reduce_partials(double *part, int64_t nblk, int32_t ncols, double *out, bool accumulate, hipStream_t s) {
@@ -1567,45 +1631,39 @@ void launch_reduce_partials(double *part, int64_t nblk, int32_t ncols, double *o
   MQO_LAUNCH(k_reduce_partials, dim3(cx, 1), dim3(256), 0, s, src, rows, ncols, wlog2, rows, out, (int32_t)accumulate);
 }
 
-template <int VEC, bool MC, bool W>
-static void adj_t(const GraphView &g, const float *Xk, const float *lam_next, float *mu, float *lam, double *part,
+template <int VEC>
+struct AdjLaunch {
+  template <int OBJ, bool W>
+  static void run(const GraphView &g, const float *Xk, const float *lam_next, float *mu, float *lam, double *part,
                   int32_t ncols, int32_t ld, int ll, float alpha, float param, hipStream_t s) {
-  const dim3 grid = spmm_grid(g, ncols, ll, VEC);
-  const size_t lds_mu = std::max(g.nhub ? hub_lds(W) : 0, PARTIAL_LDS(VEC)), lds_lam = g.nhub ? hub_lds(W) : 0;
-  const float eta = MC ? -2.0f : -param;
-  if (spmm_rows(g, ll) == 2) {
-    MQO_LAUNCH((k_adj_mu<VEC, MC, W, 2>), grid, dim3(256), lds_mu, s, g, Xk, lam_next, mu, part, ncols, ld, ll, alpha,
-               param);
-    MQO_LAUNCH((k_adj_lambda<VEC, W, 2>), grid, dim3(256), lds_lam, s, g, mu, lam, ncols, ld, ll, alpha, eta);
-  } else {
-    MQO_LAUNCH((k_adj_mu<VEC, MC, W, 1>), grid, dim3(256), lds_mu, s, g, Xk, lam_next, mu, part, ncols, ld, ll, alpha,
-               param);
-    MQO_LAUNCH((k_adj_lambda<VEC, W, 1>), grid, dim3(256), lds_lam, s, g, mu, lam, ncols, ld, ll, alpha, eta);
+    const dim3 grid = spmm_grid(g, ncols, ll, VEC, OBJ);
+    const size_t lds_mu = std::max(g.nhub ? hub_lds(W) : 0, PARTIAL_LDS(VEC)), lds_lam = g.nhub ? hub_lds(W) : 0;
+    if constexpr (OBJ == OBJ_H || OBJ == OBJ_FB) {
+      if (spmm_rows(g, ll, OBJ) == 2) {
+        MQO_LAUNCH((k_adj_mu<VEC, OBJ, W, 2>), grid, dim3(256), lds_mu, s, g, Xk, lam_next, mu, part, ncols, ld, ll,
+                   alpha, param);
+        MQO_LAUNCH((k_adj_lambda<VEC, OBJ, W, 2>), grid, dim3(256), lds_lam, s, g, mu, lam, ncols, ld, ll, alpha,
+                   param);
+        return;
+      }
+    }
+    MQO_LAUNCH((k_adj_mu<VEC, OBJ, W, 1>), grid, dim3(256), lds_mu, s, g, Xk, lam_next, mu, part, ncols, ld, ll,
+               alpha, param);
+    MQO_LAUNCH((k_adj_lambda<VEC, OBJ, W, 1>), grid, dim3(256), lds_lam, s, g, mu, lam, ncols, ld, ll, alpha, param);
   }
-}
+};
 
-void launch_adjoint_step(bool maxcut, const GraphView &g, const float *Xk, const float *lam_next, float *mu,
+void launch_adjoint_step(int form, const GraphView &g, const float *Xk, const float *lam_next, float *mu,
                          float *lam, double *part, int32_t ncols, int32_t ld, StepCfg cfg, float alpha, float param,
                          hipStream_t s) {
   const bool w = g.weight != nullptr;
   const int ll = cfg.lanes_log2;
-#define MQO_ADJ(V)                                                                 \
-  if (maxcut) {                                                                    \
-    if (w)                                                                         \
-      adj_t<V, true, true>(g, Xk, lam_next, mu, lam, part, ncols, ld, ll, alpha, param, s);  \
-    else                                                                           \
-      adj_t<V, true, false>(g, Xk, lam_next, mu, lam, part, ncols, ld, ll, alpha, param, s); \
-  } else {                                                                         \
-    adj_t<V, false, false>(g, Xk, lam_next, mu, lam, part, ncols, ld, ll, alpha, param, s);  \
-  }
-  if (cfg.vec == 4) {
-    MQO_ADJ(4)
-  } else if (cfg.vec == 2) {
-    MQO_ADJ(2)
-  } else {
-    MQO_ADJ(1)
-  }
-#undef MQO_ADJ
+  if (cfg.vec == 4)
+    dispatch_form<AdjLaunch<4>>(form, w, g, Xk, lam_next, mu, lam, part, ncols, ld, ll, alpha, param, s);
+  else if (cfg.vec == 2)
+    dispatch_form<AdjLaunch<2>>(form, w, g, Xk, lam_next, mu, lam, part, ncols, ld, ll, alpha, param, s);
+  else
+    dispatch_form<AdjLaunch<1>>(form, w, g, Xk, lam_next, mu, lam, part, ncols, ld, ll, alpha, param, s);
 }
 
 }  // namespace mqo

@@ -18,16 +18,17 @@ struct StepCfg {
 StepCfg default_step_cfg(int32_t ncols, int32_t ld);
 int64_t grid_blocks_x(int64_t nrows, StepCfg cfg);
 // row workgroups of a sparse-product launch over graph g (without hub workgroups)
-int64_t spmm_row_blocks(const GraphView &g, StepCfg cfg);
+int64_t spmm_row_blocks(const GraphView &g, StepCfg cfg, int form);
 
 void launch_init_uniform(bool maxcut, float *X, int64_t lo, int64_t n, int32_t ncols, int32_t ld, uint64_t seed,
                          uint64_t traj0, hipStream_t s);
 void launch_init_degree(bool maxcut, float *X, const int32_t *row_ptr, int32_t *dmax_scratch, int64_t lo, int64_t n,
                         int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0, float sigma, hipStream_t s);
 void launch_degree_max(const int32_t *row_ptr, int64_t n, int32_t *out, hipStream_t s);
+// form: OBJ_H / OBJ_FB / OBJ_FL / OBJ_FP / OBJ_FA (common.h).
 // colact: per-column active flags (0 = stopped for the round: copied
 // through), or nullptr for all active
-void launch_pga_step(bool maxcut, const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols, int32_t ld,
+void launch_pga_step(int form, const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols, int32_t ld,
                      StepCfg cfg, float alpha, float mu, float param, hipStream_t s, const int8_t *colact = nullptr);
 void launch_active_update(int8_t *colact, const int8_t *fixed, int32_t ncols, hipStream_t s);
 void launch_fill_i8(int8_t *p, int64_t count, int8_t v, hipStream_t s);
@@ -68,13 +69,13 @@ void launch_count_hubs(const int32_t *row_ptr, int64_t n, int32_t min_deg, int32
 // safe to run in the same pass as the row check (skips rows with a bad range)
 void launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, const int32_t *weight, const int64_t *voff,
                           int32_t G, int64_t n, int64_t nnz, int32_t *err, hipStream_t s);
-void launch_objective_grad(bool maxcut, const GraphView &g, const float *X, const float *scale, float *grad,
+void launch_objective_grad(int form, const GraphView &g, const float *X, const float *scale, float *grad,
                            double *part, int32_t ncols, int32_t ld, StepCfg cfg, float param, hipStream_t s);
 // partial rows [nblk][ncols] followed by room for reduce_rows(nblk) more
 // rows (the reduction's intermediate levels)
 inline int64_t reduce_rows(int64_t nblk) { return nblk / 7 + 64; }
 void launch_reduce_partials(double *part, int64_t nblk, int32_t ncols, double *out, bool accumulate, hipStream_t s);
-void launch_adjoint_step(bool maxcut, const GraphView &g, const float *Xk, const float *lam_next, float *mu,
+void launch_adjoint_step(int form, const GraphView &g, const float *Xk, const float *lam_next, float *mu,
                          float *lam, double *part, int32_t ncols, int32_t ld, StepCfg cfg, float alpha, float param,
                          hipStream_t s);
 

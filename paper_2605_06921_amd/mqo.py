@@ -18,7 +18,9 @@ LIB_PATH = os.environ.get("MQO_LIBRARY") or os.path.join(_HERE, "libmqo.so")
 
 MIS = 0
 MAXCUT = 1
-_KIND = {"mis": MIS, "maxcut": MAXCUT, MIS: MIS, MAXCUT: MAXCUT}
+MAXCUT_FL, MAXCUT_FP, MAXCUT_FA = 2, 3, 4  # Eq. (4), (5), (6); MAXCUT is f_B, Eq. (7)
+_KIND = {"mis": MIS, "maxcut": MAXCUT, "maxcut_fl": MAXCUT_FL, "maxcut_fp": MAXCUT_FP, "maxcut_fa": MAXCUT_FA,
+         MIS: MIS, MAXCUT: MAXCUT, MAXCUT_FL: MAXCUT_FL, MAXCUT_FP: MAXCUT_FP, MAXCUT_FA: MAXCUT_FA}
 PLANS = {"auto": 0, "plain": 1, "batched": 2, "persistent": 3}
 PLAN_NAMES = {v: k for k, v in PLANS.items()}
 INIT = {"uniform": 0, "degree": 1}
@@ -48,7 +50,7 @@ class _Params(ctypes.Structure):
                 ("reset_mode", ctypes.c_int32), ("local_search", ctypes.c_int32), ("plan", ctypes.c_int32),
                 ("tile_cols", ctypes.c_int32), ("tile_threads", ctypes.c_int32), ("tile_vec", ctypes.c_int32),
                 ("tile_csr", ctypes.c_int32), ("tile_reg", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("time_budget_s", ctypes.c_double)]
+                ("time_budget_s", ctypes.c_double), ("maxcut_objective", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -256,6 +258,8 @@ def solve(kind, dg: DeviceGraph, x0: Optional[torch.Tensor] = None, workspace: O
     Returns a dict of device tensors and host counters."""
     k = _KIND[kind]
     p = make_params(**params)
+    if k != MIS:
+        p.maxcut_objective = k  # the formulation of the MaxCut steps
     B, G = p.batch, dg.num_graphs
     nbytes = _lib.mqo_workspace_size(dg.struct, ctypes.byref(p), k)
     if nbytes == 0:

@@ -528,3 +528,72 @@ def test_early_exit_bit_exact(mqo, ci, check, plan, tile):
     nnz_g = np.diff(g.row_ptr[g.vtx_offset])
     eu = int((ref["traj_steps"].reshape(g.num_graphs, -1) * nnz_g[:, None]).sum())
     assert out["edge_updates"] == eu
+
+
+# --------------------------------------------------------------------------
+# the other MaxCut formulations: f_L (Eq. (4)), f_P (Eq. (5)), f_A (Eq. (6))
+# --------------------------------------------------------------------------
+
+FORMS = ["maxcut_fl", "maxcut_fp", "maxcut_fa"]
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("name", ["er300", "torus", "cut_batch"])
+@pytest.mark.parametrize("B", [1, 5, 32])
+def test_formulation_steps_objective_adjoint(mqo, form, name, B):
+    g = CASES[name][1]
+    dg = mqo.DeviceGraph(g, DEV)
+    lam = 0.3
+    X0 = _x("maxcut", g.n, B, 171 + B)
+    for mu in (0.0, 0.5):
+        X = torch.from_numpy(X0).to(DEV)
+        V = torch.zeros_like(X)
+        mqo.pga_steps(form, dg, X, 6, alpha=0.05, lam=lam, momentum=mu, V=V)
+        ref, Vr = X0, None
+        for _ in range(6):
+            ref, Vr = pga.step32(g, ref, form, 0.05, lam, mu, Vr)
+        assert np.array_equal(X.cpu().numpy(), ref)
+    f, grad = mqo.objective_grad(form, dg, torch.from_numpy(X0).to(DEV), lam)
+    for gi in range(g.num_graphs):
+        sub = g.subgraph(gi)
+        lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+        fr, gr = pga.objective_and_grad(sub, form, lam, X0[lo:hi].astype(np.float64), np.ones(B))
+        assert np.allclose(f.cpu().numpy()[gi * B:(gi + 1) * B], fr, rtol=1e-5,
+                           atol=1e-5 * (np.abs(X0[lo:hi]).sum() + 1))
+        assert np.abs(grad.cpu().numpy()[lo:hi] - gr).max() / max(1.0, np.abs(gr).max()) <= 1e-5
+    if g.num_graphs == 1:
+        K, c, alpha = 10, 5, 0.02
+        XK, ckpt = mqo.unrolled_forward(form, dg, torch.from_numpy(X0).to(DEV), alpha, K, c, lam)
+        xs = pga.unrolled_forward(g, form, lam, alpha, K, X0, precision="fp32")
+        assert np.array_equal(XK.cpu().numpy(), xs[K])
+        dL = obj.gradient(form, xs[K].astype(np.float64), obj.adjacency(g), lam).astype(np.float32)
+        dX0, da = mqo.unrolled_backward(form, dg, ckpt, torch.from_numpy(dL).to(DEV), alpha, K, c, lam)
+        rX0, ra = pga.unrolled_backward(g, form, lam, alpha, K, X0, dL.astype(np.float64), precision="fp32")
+        assert np.abs(dX0.cpu().numpy() - rX0).max() / max(1.0, np.abs(rX0).max()) <= 1e-4
+        assert np.allclose(da.cpu().numpy(), ra, rtol=1e-4, atol=1e-4 * max(1.0, np.abs(ra).max()))
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("plan", ["auto", "batched", "plain"])
+def test_formulation_solves_bit_exact(mqo, form, plan):
+    g = CASES["cut_batch"][1]
+    kw = dict(batch=4, steps_per_round=30, rounds=3, alpha=0.05, rho=0.2, seed=29, lam=0.3)
+    out = mqo.solve(form, mqo.DeviceGraph(g, DEV), plan=plan, **kw)
+    assert out["plan"] in ("batched", "plain")
+    p = solver.Params(batch=4, steps_per_round=30, rounds=3, alpha=0.05, seed=29, lam=0.3, rho=0.2)
+    ref = solver.solve(form, g, p)
+    assert np.array_equal(out["traj_best_value"].cpu().numpy(), ref["traj_best_value"])
+    assert np.array_equal(out["traj_best_x"].cpu().numpy(), ref["traj_best_x"])
+
+
+def test_formulations_rejected_where_not_offered(mqo):
+    dg = mqo.DeviceGraph(CASES["reg3"][1], DEV)
+    with pytest.raises(mqo.MqoError) as e:
+        mqo.solve("maxcut_fl", dg, batch=2, steps_per_round=4, plan="persistent")
+    assert e.value.status == -5
+    with pytest.raises(mqo.MqoError) as e:
+        mqo.solve("maxcut_fa", dg, batch=2, steps_per_round=4, check_every=2)
+    assert e.value.status == -5
+    with pytest.raises(mqo.MqoError) as e:
+        mqo.objective_grad("maxcut_fp", dg, torch.zeros(dg.n, 2, device=DEV), 0.0)
+    assert e.value.status == -1
