@@ -157,7 +157,7 @@ def bench_differentiation(args, wl):
     res = dict(metric="edge-updates/s of the differentiation path; HBM GB/s", value=eu / el, unit="edge-updates/s",
                n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=1e3 * el / args.steps,
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
-               config=dict(workload=wl.name, mode=args.mode, description=wl.description, n=g.n, nnz=g.nnz, batch=B,
+               config=dict(workload=wl.name, objective=wl.problem, mode=args.mode, description=wl.description, n=g.n, nnz=g.nnz, batch=B,
                            sparse_product_passes=passes, hubs=dg.num_hubs, parallelism="dp1"))
     # algorithmic bytes per pass: CSR once, X read, output written (float64
     # objective partials are small); average over the timed region
@@ -183,6 +183,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--objective", default="", choices=["", "maxcut", "maxcut_fl", "maxcut_fp", "maxcut_fa"],
+                    help="MaxCut workloads: the formulation of the steps (default f_B, Eq. (7); f_L, f_P, f_A are "
+                         "Eq. (4)-(6))")
     ap.add_argument("--mode", default="solve", choices=["solve", "grad", "unrolled"],
                     help="solve: whole batched solves; grad: objective + SpMM gradient over the batch; "
                          "unrolled: K = 20 unrolled PGA steps forward and their adjoint (checkpoints every 5)")
@@ -201,6 +204,13 @@ def main():
     from paper_2605_06921_amd import mqo
 
     wl = WORKLOADS[args.workload]
+    if args.objective:
+        if wl.problem == "mis":
+            raise SystemExit("--objective selects a MaxCut formulation; the workload is MIS")
+        import dataclasses
+        if args.objective != wl.problem:
+            # counter records are per workload and formulation
+            wl = dataclasses.replace(wl, problem=args.objective, name=f"{wl.name}:{args.objective}")
     if args.mode != "solve":
         return bench_differentiation(args, wl)
     if args.copy_calibration_mb:
@@ -244,7 +254,8 @@ def main():
                value=value, unit="edge-updates/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=ms_per_step, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
                data="synthetic",
-               config=dict(workload=wl.name, description=wl.description, graphs=g.num_graphs, n=g.n, nnz=g.nnz,
+               config=dict(workload=wl.name, objective=wl.problem, description=wl.description, graphs=g.num_graphs,
+                           n=g.n, nnz=g.nnz,
                            batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=wl.rounds, alpha=wl.alpha,
                            rho=wl.rho, reset_mode=wl.reset_mode, plan=out["plan"], tile_cols=out["tile_cols"],
                            tile_threads=out["tile_threads"], tile_vec=out["tile_vec"],

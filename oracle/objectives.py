@@ -80,7 +80,7 @@ def f_P(X, A, lam):
 
 
 def grad_f_L(X, A):
-    """Gradient of Eq. (4): (1/2) L x.  (The text's proof of Prop. 3.5 writes
+    """Gradient of Eq. (4): (1/2) L x.  (The text's proof of Prop. 3.2 writes
     L x; differentiating (1/4) x^T L x with L symmetric gives L x / 2.)"""
     X = np.asarray(X, dtype=np.float64)
     return 0.5 * (laplacian(A) @ X)

@@ -597,3 +597,86 @@ def test_formulations_rejected_where_not_offered(mqo):
     with pytest.raises(mqo.MqoError) as e:
         mqo.objective_grad("maxcut_fp", dg, torch.zeros(dg.n, 2, device=DEV), 0.0)
     assert e.value.status == -1
+
+
+# Appendix B's escapability set-up: ten ER graphs n = 100, p = 0.66, step
+# 0.1, lambda 1e-3, no local search and no reset.  What the propositions
+# fix is checked exactly: c*1 is stationary for f_L (Prop. 3.2) and not for
+# f_P, f_B; every binary point is PGA-fixed under f_L and f_P (Prop. 3.2,
+# Thm. 3.3); a 1-flip repairable point is not PGA-fixed under f_A (Prop. 3.4)
+# nor f_B (Thm. 3.6).  Dyadic c keeps every sum exact in float32.
+
+def _appendix_b_graphs():
+    return graphs.concat([graphs.erdos_renyi(100, 0.66, 700 + i) for i in range(10)])
+
+
+def _one_flip_repairable(g, X):
+    A = obj.adjacency(g)
+    return np.array([bool(np.any(X[:, j] * (A @ X[:, j]) > 0)) for j in range(X.shape[1])])
+
+
+@pytest.mark.parametrize("form", ["maxcut_fl", "maxcut_fp", "maxcut"])
+def test_escapability_of_laplacian_stationary_points(mqo, form):
+    g = _appendix_b_graphs()
+    dg = mqo.DeviceGraph(g, DEV)
+    cs = np.array([-0.75, -0.25, 0.375, 0.5, -0.5, 0.125], dtype=np.float32)
+    X0 = np.tile(cs, (g.n, 1))
+    X = torch.from_numpy(X0).to(DEV)
+    mqo.pga_steps(form, dg, X, 1, alpha=0.1, lam=1e-3)
+    moved = ~np.all(X.cpu().numpy() == X0, axis=0)
+    assert np.all(moved == (form != "maxcut_fl"))
+    X = torch.from_numpy(X0).to(DEV)
+    mqo.pga_steps(form, dg, X, 200, alpha=0.1, lam=1e-3)
+    ref = X0
+    for _ in range(200):
+        ref, _v = pga.step32(g, ref, form, 0.1, 1e-3, 0.0, None)
+    assert np.array_equal(X.cpu().numpy(), ref)
+    if form == "maxcut_fl":
+        _, value, _, _ = mqo.round_evaluate(form, dg, X)
+        assert np.all(value.cpu().numpy() == 0)
+
+
+@pytest.mark.parametrize("form", ["maxcut_fl", "maxcut_fp", "maxcut_fa", "maxcut"])
+def test_escapability_of_one_flip_repairable_points(mqo, form):
+    g = _appendix_b_graphs()
+    dg = mqo.DeviceGraph(g, DEV)
+    rng = np.random.default_rng(31)
+    X0 = np.where(rng.random((g.n, 24)) < 0.5, -1.0, 1.0).astype(np.float32)
+    for gi in range(g.num_graphs):
+        lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+        assert _one_flip_repairable(g.subgraph(gi), X0[lo:hi]).all()
+    X = torch.from_numpy(X0).to(DEV)
+    mqo.pga_steps(form, dg, X, 1, alpha=0.1, lam=1e-3)
+    X1 = X.cpu().numpy()
+    for gi in range(g.num_graphs):
+        lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+        fixed = np.all(X1[lo:hi] == X0[lo:hi], axis=0)
+        assert np.all(fixed == (form in ("maxcut_fl", "maxcut_fp")))
+    ref, _v = pga.step32(g, X0, form, 0.1, 1e-3, 0.0, None)
+    assert np.array_equal(X1, ref)
+
+
+def test_formulation_comparison_ordering(mqo):
+    """Appendix B's comparison on synthetic ER graphs (n = 100, mean degree
+    50; three graphs, eight common starts, step 0.01, no search, no reset):
+    the GPU trajectories equal the oracle's bit for bit, and the adjacency
+    formulations end at larger cuts than the Laplacian ones."""
+    g = graphs.concat([graphs.erdos_renyi(100, 50 / 99, 900 + i) for i in range(3)])
+    dg = mqo.DeviceGraph(g, DEV)
+    X0 = arrays.uniform((g.n, 8), -1.0, 1.0, 77)
+    mean_cut = {}
+    for form in ["maxcut_fl", "maxcut_fp", "maxcut_fa", "maxcut"]:
+        X = torch.from_numpy(X0).to(DEV)
+        mqo.pga_steps(form, dg, X, 300, alpha=0.01, lam=1e-3)
+        ref = X0
+        for _ in range(300):
+            ref, _v = pga.step32(g, ref, form, 0.01, 1e-3, 0.0, None)
+        assert np.array_equal(X.cpu().numpy(), ref)
+        _, value, _, _ = mqo.round_evaluate(form, dg, X)
+        cuts = value.cpu().numpy()
+        for gi in range(g.num_graphs):
+            lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+            S = np.where(ref[lo:hi] > 0, 1, -1).astype(np.int8)
+            assert np.array_equal(cuts[gi * 8:(gi + 1) * 8], discrete.evaluate_cut(g.subgraph(gi), S))
+        mean_cut[form] = cuts.mean()
+    assert min(mean_cut["maxcut_fa"], mean_cut["maxcut"]) > 1.05 * max(mean_cut["maxcut_fl"], mean_cut["maxcut_fp"])

@@ -52,7 +52,7 @@ def test_laplacian_is_the_cut_and_adjacency_differs_by_a_constant():
 
 
 def test_laplacian_stationary_points_have_zero_cut():
-    """Prop. 3.5: c 1 is stationary for f_L (a PGA fixed point), interior
+    """Prop. 3.2: c 1 is stationary for f_L (a PGA fixed point), interior
     for |c| < 1, binary for c = +-1, and its cut is 0."""
     g = graphs.erdos_renyi(40, 0.3, 820)
     A = obj.adjacency(g)
@@ -75,7 +75,7 @@ def test_perturbed_laplacian_fixes_every_binary_point():
 
 
 def test_adjacency_escapes_one_flip_repairable_points():
-    """Prop. 3.6: a binary x that one flip improves is not a PGA fixed point
+    """Prop. 3.4: a binary x that one flip improves is not a PGA fixed point
     of f_A."""
     g = graphs.erdos_renyi(9, 0.45, 840)
     A = obj.adjacency(g)
