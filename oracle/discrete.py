@@ -256,3 +256,160 @@ def reset_apply(kind, Zbest, mask, mode="zero"):
     else:
         rv = -base
     return np.where(mask, rv, base).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# the paper's own local searches: OneTwoSwap (MIS) and OneTwoFlip (MaxCut)
+# --------------------------------------------------------------------------
+#
+# Sec. 4 describes both searches as sequential sweeps that apply a move
+# whenever one exists and repeat until none does: the (1,2)-swap of Def. 2.3
+# for MIS, and for MaxCut the 2-flip of Def. 2.5 alternated with the 1-flip
+# of Def. 2.4.  As for the 1-flip search, the rule used on both sides is a
+# parallel one: alternate (a) the 1-flip search above to a 1-flip optimum
+# (for MIS: a maximal independent set, the precondition of Def. 2.3) and
+# (b) one parallel iteration of the pair move, applying a set of moves whose
+# gains add exactly; stop when (b) finds no move.  Every applied move raises
+# the objective by at least one, so the search ends.
+
+def _rows(graph):
+    return graph.row_ptr.astype(np.int64), graph.col_idx.astype(np.int64)
+
+
+def _swap_proposal(rp, ci, z, m, v):
+    """Def. 2.3 move at v in I: the first pair (u, w) of v's neighbours, in
+    CSR order, with m_u = m_w = 1 (v is their only neighbour in I, so
+    I - v + u + w is independent iff u, w are not adjacent) and u !~ w."""
+    tight = [int(u) for u in ci[rp[v]:rp[v + 1]] if z[u] == 0 and m[u] == 1]
+    for i, u in enumerate(tight):
+        nu = ci[rp[u]:rp[u + 1]]
+        for w in tight[i + 1:]:
+            k = np.searchsorted(nu, w)
+            if k == len(nu) or nu[k] != w:
+                return u, w
+    return None
+
+
+def swap_iteration_mis(graph, z, m, prio):
+    """One parallel (1,2)-swap iteration on one column (z in {0,1}, m = A z
+    unweighted).  Each v in I proposes its first valid pair; proposals at v
+    and v' conflict when a vertex v inserts is adjacent to one v' inserts
+    (the inserted sets are disjoint: an inserted vertex has one I-neighbour);
+    a proposal is applied when its key (prio_v, -v) beats the key of every
+    proposal it conflicts with.  Returns the list of applied (v, u, w)."""
+    rp, ci = _rows(graph)
+    prop, owner = {}, {}
+    for v in range(graph.n):
+        if z[v] == 1:
+            pw = _swap_proposal(rp, ci, z, m, v)
+            if pw is not None:
+                prop[v] = pw
+                owner[pw[0]] = v
+                owner[pw[1]] = v
+
+    def beats(a, b):
+        return prio[a] > prio[b] or (prio[a] == prio[b] and a < b)
+
+    applied = []
+    for v, (u, w) in prop.items():
+        lose = False
+        for x in (u, w):
+            for y in ci[rp[x]:rp[x + 1]]:
+                o = owner.get(int(y))
+                if o is not None and o != v and beats(o, v):
+                    lose = True
+                    break
+            if lose:
+                break
+        if not lose:
+            applied.append((v, u, w))
+    return applied
+
+
+def _pair_key(gain2, pv, pu, v, u):
+    """Total order of 2-flip pairs: larger gain, then larger
+    (prio_v + prio_u) mod 2^32, then smaller (min, max) vertex pair."""
+    return (int(gain2), (int(pv) + int(pu)) & 0xFFFFFFFF, -min(v, u), -max(v, u))
+
+
+def flip2_iteration_cut(graph, s, t, prio):
+    """One parallel 2-flip iteration on one column (s in {-1,+1}, t = A s
+    weighted).  The gain of flipping both ends of a cut edge (v, u) of
+    weight w (Def. 2.5) is g_v + g_u + 2 w, g = s t the 1-flip gains: the
+    edge stays cut while each single flip would uncut it.  Every v picks its
+    best improving cut edge by the pair key; a pair is applied when both
+    ends picked each other and no other vertex adjacent to the pair holds a
+    larger best key.  Applied pairs are then non-adjacent, so their gains
+    add.  Returns the list of applied (v, u)."""
+    rp, ci = _rows(graph)
+    w = np.ones(graph.nnz, dtype=np.int64) if graph.weight is None else graph.weight.astype(np.int64)
+    g = s * t
+    best = [None] * graph.n
+    part = [-1] * graph.n
+    for v in range(graph.n):
+        for j in range(rp[v], rp[v + 1]):
+            u = int(ci[j])
+            if s[u] == s[v]:
+                continue
+            gain2 = g[v] + g[u] + 2 * w[j]
+            if gain2 <= 0:
+                continue
+            k = _pair_key(gain2, prio[v], prio[u], v, u)
+            if best[v] is None or k > best[v]:
+                best[v], part[v] = k, u
+    applied = []
+    for v in range(graph.n):
+        u = part[v]
+        if u < 0 or v > u or part[u] != v:
+            continue
+        k = best[v]
+        lose = False
+        for x in (v, u):
+            for y in ci[rp[x]:rp[x + 1]]:
+                y = int(y)
+                if y != v and y != u and best[y] is not None and best[y] > k:
+                    lose = True
+                    break
+            if lose:
+                break
+        if not lose:
+            applied.append((v, u))
+    return applied
+
+
+def pair_search(kind, graph, Z, seed, traj, rnd, max_alternations=None):
+    """OneTwoSwap (MIS) / OneTwoFlip (MaxCut) on every column, parallel rule
+    above: the 1-flip search (seed, traj, rnd as for ``local_search``), then
+    pair iterations with priorities of purpose SWAP for (traj, rnd, v), each
+    followed by the 1-flip search again, until an iteration applies nothing.
+    Returns (Z', pair moves applied per column)."""
+    Z = np.array(Z, dtype=np.int64)
+    n, B = Z.shape
+    traj = np.asarray(traj, dtype=np.uint64)
+    prio = philox.vertex_u32(seed, philox.PURPOSE_SWAP, traj[None, :], rnd,
+                             np.arange(n, dtype=np.uint64)[:, None]).astype(np.int64)
+    Aint = _int_adj(graph)  # MIS graphs carry no weights
+    moves = np.zeros(B, dtype=np.int64)
+    wsum = graph.nnz if graph.weight is None else int(np.abs(graph.weight.astype(np.int64)).sum())
+    cap = max_alternations if max_alternations is not None else n + wsum + 2
+    alternations = 0
+    while True:
+        Z = local_search(kind, graph, Z, seed, traj, rnd)[0].astype(np.int64)
+        nb = Aint @ Z
+        any_move = False
+        for b in range(B):
+            if kind == obj.MIS:
+                app = swap_iteration_mis(graph, Z[:, b], nb[:, b], prio[:, b])
+                for v, u, w in app:
+                    Z[v, b], Z[u, b], Z[w, b] = 0, 1, 1
+            else:
+                app = flip2_iteration_cut(graph, Z[:, b], nb[:, b], prio[:, b])
+                for v, u in app:
+                    Z[v, b], Z[u, b] = -Z[v, b], -Z[u, b]
+            moves[b] += len(app)
+            any_move = any_move or bool(app)
+        if not any_move:
+            return Z.astype(np.int8), moves
+        alternations += 1
+        if alternations > cap:
+            raise RuntimeError("pair search did not terminate")

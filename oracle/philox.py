@@ -29,6 +29,7 @@ PURPOSE_INIT = 1
 PURPOSE_RESET = 2
 PURPOSE_LS = 3
 PURPOSE_NOISE = 4
+PURPOSE_SWAP = 5
 
 
 def philox4x64_10(ctr, key):
