@@ -15,6 +15,10 @@ Round r = 0 .. rounds-1 of trajectory t = g*B + b:
   * optional 1-flip local search (parallel rule, ``discrete.local_search``);
   * exact evaluation; accept iff strictly better than the incumbent
     (Sec. 4), round 0 always initialises the incumbent.
+With ``final_search`` the paper's own search (OneTwoSwap / OneTwoFlip,
+``discrete.pair_search`` with round index ``rounds``) runs on every
+incumbent after the last round and replaces it when strictly better
+(Alg. 1 / Alg. 2, the local search after the reset loop).
 The answer of graph g is the best incumbent over its B trajectories, ties
 to the lowest b.
 Test infrastructure only.
@@ -46,6 +50,7 @@ class Params:
     init_mode: str = "uniform"
     init_sigma: float = 0.0
     check_every: int = 0
+    final_search: bool = False
 
 
 def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32", trace=None, cols=None,
@@ -103,6 +108,12 @@ def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32"
         zbest[:, take] = Z[:, take]
         if trace is not None:
             trace.append(dict(round=r, value=val.copy(), best=best.copy()))
+    if p.final_search:
+        Z, _ = discrete.pair_search(kind, graph, zbest, p.seed, traj, p.rounds)
+        val = discrete.value(kind, graph, Z)
+        take = val > best
+        best = np.where(take, val, best)
+        zbest[:, take] = Z[:, take]
     if stats is not None:
         stats["steps"] = steps
     return best, zbest

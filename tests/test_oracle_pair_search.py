@@ -195,3 +195,23 @@ def test_two_flip_never_applies_on_odd_regular_graphs():
     out, moves = discrete.pair_search("maxcut", g, S, 2, np.arange(8), 0)
     ls, _ = discrete.local_search("maxcut", g, S, 2, np.arange(8), 0)
     assert np.array_equal(out, ls) and np.all(moves == 0)
+
+
+@pytest.mark.parametrize("kind", ["mis", "maxcut"])
+def test_solver_final_search_ends_at_pair_optima(kind):
+    """Alg. 1 / Alg. 2: the search after the reset loop leaves incumbents
+    that no 1-flip, (1,2)-swap or 2-flip improves, never worse than
+    without it."""
+    from oracle import solver
+    g = graphs.erdos_renyi(18, 0.25, 4800)
+    kw = dict(batch=5, steps_per_round=30, rounds=3, alpha=0.05, seed=48)
+    plain = solver.solve(kind, g, solver.Params(**kw))
+    fin = solver.solve(kind, g, solver.Params(final_search=True, **kw))
+    assert np.all(fin["traj_best_value"] >= plain["traj_best_value"])
+    for b in range(5):
+        z = fin["traj_best_x"][:, b]
+        if kind == "mis":
+            assert _maximal_independent(g, z) and not _swap_repairable(g, z)
+        else:
+            s = z.astype(np.int64)
+            assert not _one_flip_repairable(g, s) and not _two_flip_repairable(g, s)
