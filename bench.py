@@ -104,6 +104,99 @@ def cpu_baseline(wl, g, budget_s=15.0):
                        f"numpy/scipy, {el:.1f} s")
 
 
+def pair_cpu_baseline(kind, wl, g, Zs, budget_s):
+    """The oracle's pair search on graph 0, from the same 1-flip optima,
+    over as many trajectories as fit in about half the budget."""
+    from oracle import discrete as odisc
+    sub = g.subgraph(0)
+    lo, hi = int(g.vtx_offset[0]), int(g.vtx_offset[1])
+    ncols = 1
+    while True:
+        t0 = time.perf_counter()
+        odisc.pair_search(kind, sub, Zs[lo:hi, :ncols], wl.seed, np.arange(ncols), 0)
+        el = time.perf_counter() - t0
+        if ncols == wl.batch or el >= budget_s / 2:
+            break
+        ncols = int(min(wl.batch, max(2 * ncols, ncols * budget_s / 2 / max(el, 1e-3))))
+    return dict(value=sub.nnz * ncols / el, unit="edge-trajectories/s", cores=1, kind="oracle",
+                sample=f"graph 0 of {g.num_graphs} (n={sub.n}, nnz={sub.nnz}), trajectories 0..{ncols - 1} of "
+                       f"{wl.batch}, one complete pair search each from the same 1-flip optima, pure-Python "
+                       f"loops with numpy, single-threaded, {el:.1f} s")
+
+
+def bench_pair(args, wl):
+    """The paper's own search (OneTwoSwap / OneTwoFlip) over the workload's
+    batch, started from 1-flip optima (what the search meets after a solve
+    with 1-flip search): the rounded uniform iterate of every trajectory
+    after the 1-flip search, untimed.  A step is one complete search of every
+    trajectory of every graph; value = stored CSR entries x trajectories
+    searched per second."""
+    import torch
+    from synth import arrays
+    from oracle import objectives as oobj
+    from paper_2605_06921_amd import mqo
+
+    g = wl.make_graph()
+    dev = torch.device("cuda:0")
+    dg = mqo.DeviceGraph(g, dev)
+    B = wl.batch
+    kind = "mis" if wl.problem == "mis" else "maxcut"
+    lo, hi = oobj.box(kind)
+    X = arrays.uniform((g.n, B), lo, hi, wl.seed)
+    Z0 = torch.from_numpy((X > 0.5).astype(np.int8) if kind == "mis" else np.where(X > 0, 1, -1).astype(np.int8))
+    Z0 = Z0.to(dev)
+    ws = mqo.Workspace(dev)
+    mqo.local_search(kind, dg, Z0, wl.seed, 0, workspace=ws)
+    Z = torch.empty_like(Z0)
+    alt = 0
+    for i in range(args.warmup):
+        Z.copy_(Z0)
+        alt = mqo.pair_search(kind, dg, Z, wl.seed, 0, workspace=ws)
+        torch.cuda.synchronize()
+        log(f"[bench] pair warmup {i}: {alt} pair iterations")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    cand_ms, launches = 0.0, 0
+    for _ in range(args.steps):
+        Z.copy_(Z0)
+        tm = {}
+        alt = mqo.pair_search(kind, dg, Z, wl.seed, 0, workspace=ws, timing=tm)
+        cand_ms += tm["candidate_kernel_ms"]
+        launches += alt + 1
+    e1.record()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gpu_s = e0.elapsed_time(e1) / 1e3
+    improved = float((Z0 != Z).any(dim=0).float().mean())
+    res = dict(metric="CSR entries x trajectories searched per second (OneTwoSwap / OneTwoFlip)",
+               value=g.nnz * B * args.steps / el, unit="edge-trajectories/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=1e3 * el / args.steps, higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="int32", data="synthetic",
+               config=dict(workload=wl.name, mode="pair", description=wl.description, graphs=g.num_graphs, n=g.n,
+                           nnz=g.nnz, batch=B, start="1-flip optima of the rounded uniform iterate",
+                           pair_iterations=alt, trajectories_improved=improved, parallelism="dp1"),
+               gpu_ms_per_step=1e3 * gpu_s / args.steps)
+    # dominant kernel: the candidate launch of every pair iteration.
+    # Compulsory bytes: the CSR once, the per-vertex state of every
+    # trajectory once (MaxCut: s, t, priority read, best gain / hash /
+    # position written; MIS: z and m read (every vertex outside a maximal
+    # I neighbours it), the owner array cleared, the proposal pair written)
+    csr = 4 * (g.n + 1) + 4 * g.nnz + (4 * g.nnz if g.weight is not None else 0)
+    per_launch = csr + (21 if kind == "maxcut" else 17) * g.n * B
+    avg_s = cand_ms / 1e3 / max(1, launches)
+    res["roofline"] = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
+                           frac=per_launch / avg_s / HBM_PEAK, traffic=None,
+                           kernel="k_flip2_best" if kind == "maxcut" else "k_fill_rows_i32 + k_swap_propose",
+                           avg_launch_ms=avg_s * 1e3, algorithmic_bytes_per_launch=per_launch,
+                           launches=launches)
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline (pair search)")
+        res["cpu_baseline"] = pair_cpu_baseline(kind, wl, g, Z0.cpu().numpy(), args.cpu_budget)
+    return res
+
+
 def bench_differentiation(args, wl):
     """Objective + gradient (grad) or the unrolled adjoint (unrolled) over the
     workload's batch.  EU = one stored CSR entry x one trajectory in one
@@ -186,7 +279,7 @@ def main():
     ap.add_argument("--objective", default="", choices=["", "maxcut", "maxcut_fl", "maxcut_fp", "maxcut_fa"],
                     help="MaxCut workloads: the formulation of the steps (default f_B, Eq. (7); f_L, f_P, f_A are "
                          "Eq. (4)-(6))")
-    ap.add_argument("--mode", default="solve", choices=["solve", "grad", "unrolled"],
+    ap.add_argument("--mode", default="solve", choices=["solve", "grad", "unrolled", "pair"],
                     help="solve: whole batched solves; grad: objective + SpMM gradient over the batch; "
                          "unrolled: K = 20 unrolled PGA steps forward and their adjoint (checkpoints every 5)")
     ap.add_argument("--tile", default="",
@@ -211,6 +304,9 @@ def main():
         if args.objective != wl.problem:
             # counter records are per workload and formulation
             wl = dataclasses.replace(wl, problem=args.objective, name=f"{wl.name}:{args.objective}")
+    if args.mode == "pair":
+        print(json.dumps(bench_pair(args, wl)), flush=True)
+        return
     if args.mode != "solve":
         return bench_differentiation(args, wl)
     if args.copy_calibration_mb:

@@ -24,7 +24,7 @@
  *     one rounding gives the same result), so every launch plan gives
  *     bit-identical iterates.
  *   - The blocking entry points (the solves, mqo_local_search,
- *     mqo_validate_graph) share the library's pinned read-back buffer and
+ *     mqo_pair_search, mqo_validate_graph) share the library's pinned read-back buffer and
  *     internal stream and run one at a time per process (an internal lock);
  *     the asynchronous ones may be called concurrently on different
  *     streams with different workspaces.
@@ -76,6 +76,8 @@ typedef enum {
 enum { MQO_INIT_UNIFORM = 0, MQO_INIT_DEGREE = 1 };
 enum { MQO_RESET_ZERO = 0, MQO_RESET_FLIP = 1 };
 enum { MQO_LS_NONE = 0, MQO_LS_ONE_FLIP = 1 };
+/* search on the incumbents after the last round (mqo_params.final_search) */
+enum { MQO_FINAL_NONE = 0, MQO_FINAL_PAIR = 1 };
 enum { MQO_PLAN_AUTO = 0, MQO_PLAN_PLAIN = 1, MQO_PLAN_BATCHED = 2, MQO_PLAN_PERSISTENT = 3 };
 
 /* Graph (notation of Sec. 2): one undirected graph, or G graphs as one
@@ -148,6 +150,12 @@ typedef struct {
   double time_budget_s;    /* 0 = none; otherwise no round starts after it      */
   int32_t maxcut_objective; /* mqo_solve_maxcut: MQO_OBJ_MAXCUT_FB (default),
                               _FL, _FP or _FA                                  */
+  int32_t final_search;    /* MQO_FINAL_NONE (default) or MQO_FINAL_PAIR: after
+                              the last round every incumbent goes through
+                              mqo_pair_search (round index = rounds) and is
+                              replaced when strictly better (Alg. 1 / Alg. 2,
+                              the local search after the reset loop); runs
+                              batched over the B trajectories in every plan */
 } mqo_params;
 
 /* Outputs of a solve.  Device arrays are written; host fields are set. */
@@ -175,6 +183,8 @@ typedef struct {
                                   whole-round tile kernel), on the stream
                                   they run on                               */
   int64_t step_kernel_launches;/* (host) number of such launches            */
+  int64_t final_search_alternations; /* (host) final_search: pair iterations
+                                  that applied a move (largest over graphs) */
 } mqo_result;
 
 void mqo_params_default(mqo_params *p);
@@ -261,6 +271,33 @@ int mqo_round_evaluate(const mqo_graph *g, mqo_objective obj, const float *X, in
 int mqo_local_search(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t seed,
                      int32_t round, int8_t *Z, int64_t *iterations,
                      void *ws, size_t ws_bytes, void *stream);
+
+/* The paper's own local search in place on Z: OneTwoSwap for MIS (the
+ * (1,2)-swap of Def. 2.3) and OneTwoFlip for MaxCut (the 2-flip of
+ * Def. 2.5 with the 1-flip of Def. 2.4), as described in Sec. 4, in a
+ * parallel form: the 1-flip search of mqo_local_search (same seed and
+ * round), then pair iterations, each followed by the 1-flip search again,
+ * until an iteration applies no move.  A pair iteration applies a set of
+ * moves whose gains add: MIS -- every v in I proposes the first pair (u, w)
+ * of its neighbours in CSR order whose only neighbour in I is v and that
+ * are not adjacent; a proposal is applied when its key (Philox priority of
+ * purpose SWAP for (t, round, v), -v) beats every proposal that inserts a
+ * neighbour of u or w.  MaxCut -- every v picks the cut edge (v, u) of
+ * largest pair key (gain g_v + g_u + 2 w_vu > 0 with g = s (A s), then
+ * (prio_v + prio_u) mod 2^32, then the smaller vertex pair); a mutual pair
+ * is applied when no other vertex adjacent to it holds a larger key.
+ * Z ([n_total*B]) may be any binary point (MIS: the 1-flip stage repairs
+ * conflicts first).  Every graph of the batch is searched at once.  MIS
+ * graphs carry no weights; MaxCut weights enter the gains.
+ * alternations: (host) out or NULL, the pair iterations that applied a move
+ * (the search runs one more, which finds none).  candidate_kernel_ms: (host)
+ * out or NULL, HIP-event time on `stream` of the candidate launches of every
+ * pair iteration (MIS: owner clear + proposals; MaxCut: best pair per
+ * vertex), summed.  Blocks (the stopping tests read device flags).
+ * ws: mqo_workspace_size() bytes for this graph and B. */
+int mqo_pair_search(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t seed,
+                    int32_t round, int8_t *Z, int64_t *alternations,
+                    double *candidate_kernel_ms, void *ws, size_t ws_bytes, void *stream);
 
 /* Mutation reset (Sec. 4): X = Zbest as float, then in every trajectory the
  * k = floor(rho n_g) vertices with the smallest (key, v) are set to 0

@@ -377,6 +377,52 @@ def flip2_iteration_cut(graph, s, t, prio):
     return applied
 
 
+def flip2_iteration_cut_np(graph, s, t, prio):
+    """``flip2_iteration_cut`` over whole edge arrays (numpy) for large
+    graphs; same result (checked against the loop form in the tests)."""
+    rp, ci = _rows(graph)
+    n = graph.n
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    w = np.ones(graph.nnz, dtype=np.int64) if graph.weight is None else graph.weight.astype(np.int64)
+    s = np.asarray(s, dtype=np.int64)
+    g = s * np.asarray(t, dtype=np.int64)
+    prio = np.asarray(prio, dtype=np.int64)
+    gain2 = g[rows] + g[ci] + 2 * w
+    ok = np.flatnonzero((s[rows] != s[ci]) & (gain2 > 0))
+    if ok.size == 0:
+        return []
+    r, c = rows[ok], ci[ok]
+    h = (prio[r] + prio[c]) & 0xFFFFFFFF
+    mn, mx = np.minimum(r, c), np.maximum(r, c)
+    # rank of every candidate edge in the pair order (both directions of a
+    # pair share the key, so they share the rank)
+    order = np.lexsort((-mx, -mn, h, gain2[ok]))
+    key_sorted = np.stack([gain2[ok][order], h[order], -mn[order], -mx[order]], axis=1)
+    new = np.ones(len(order), dtype=bool)
+    new[1:] = np.any(key_sorted[1:] != key_sorted[:-1], axis=1)
+    rank = np.empty(len(order), dtype=np.int64)
+    rank[order] = np.cumsum(new)
+    best = np.zeros(n, dtype=np.int64)  # 0 = no improving pair
+    np.maximum.at(best, r, rank)
+    part = np.full(n, -1, dtype=np.int64)
+    top = rank == best[r]
+    part[r[top]] = c[top]
+    v = np.flatnonzero(part >= 0)
+    u = part[v]
+    cand = v[(v < u) & (part[u] == v)]
+    if cand.size == 0:
+        return []
+    pu = part[cand]
+    # largest best key among the other vertices adjacent to each end
+    nb_best = np.zeros(n, dtype=np.int64)  # per vertex x: max best[y], y ~ x, y != partner(x)
+    e_rows, e_cols = rows, ci
+    keep = e_cols != part[e_rows]
+    np.maximum.at(nb_best, e_rows[keep], best[e_cols[keep]])
+    mine = best[cand]
+    win = (nb_best[cand] <= mine) & (nb_best[pu] <= mine)
+    return [(int(a), int(b)) for a, b in zip(cand[win], pu[win])]
+
+
 def pair_search(kind, graph, Z, seed, traj, rnd, max_alternations=None):
     """OneTwoSwap (MIS) / OneTwoFlip (MaxCut) on every column, parallel rule
     above: the 1-flip search (seed, traj, rnd as for ``local_search``), then
@@ -403,7 +449,8 @@ def pair_search(kind, graph, Z, seed, traj, rnd, max_alternations=None):
                 for v, u, w in app:
                     Z[v, b], Z[u, b], Z[w, b] = 0, 1, 1
             else:
-                app = flip2_iteration_cut(graph, Z[:, b], nb[:, b], prio[:, b])
+                it = flip2_iteration_cut if graph.n <= 4096 else flip2_iteration_cut_np
+                app = it(graph, Z[:, b], nb[:, b], prio[:, b])
                 for v, u in app:
                     Z[v, b], Z[u, b] = -Z[v, b], -Z[u, b]
             moves[b] += len(app)

@@ -167,6 +167,8 @@ int check_params(const mqo_params *p, mqo_objective obj) {
     return fail(MQO_ERR_INVALID_ARG, "bad reset_mode");
   if (p->local_search != MQO_LS_NONE && p->local_search != MQO_LS_ONE_FLIP)
     return fail(MQO_ERR_INVALID_ARG, "bad local_search");
+  if (p->final_search != MQO_FINAL_NONE && p->final_search != MQO_FINAL_PAIR)
+    return fail(MQO_ERR_INVALID_ARG, "bad final_search");
   if (p->plan < MQO_PLAN_AUTO || p->plan > MQO_PLAN_PERSISTENT) return fail(MQO_ERR_INVALID_ARG, "bad plan");
   if (p->tile_cols != 0 && (p->tile_cols < 1 || p->tile_cols > 64 || (p->tile_cols & (p->tile_cols - 1))))
     return fail(MQO_ERR_INVALID_ARG, "tile_cols must be 0 or a power of two <= 64");
@@ -223,8 +225,8 @@ Layout make_layout(const mqo_graph *g, int32_t B) {
   L.err = take(64);
   L.reset = take(reset_scratch_bytes(B));
   L.tzs = take(tiles_elems);
-  L.tnb = take(tiles_elems * 4);
-  L.tprio = take(tiles_elems * 4);
+  L.tnb = take(tiles_elems * 4);  // also the pair search's tightness bits (8 n_total ceil(B/64) bytes)
+  L.tprio = take(tiles_elems * 4);  // also the pair search's SWAP priorities (n_total * B <= tiles_elems)
   L.tfl = take(tiles_elems);
   L.tvm = take(tiles_elems * 4);
   L.tls = take(G * (int64_t)(B + 63) * 4);
@@ -428,12 +430,22 @@ int init_x(Solve &S, float *X) {
 // at ld).  Iterations are enqueued Q at a time; each one is skipped on the
 // device once an earlier one found no positive gain, and the host reads the
 // Q flags to decide whether to continue.
+int ls_loop(bool maxcut, const GraphView &gv, int64_t nnz_total, int8_t *Z, int32_t *NB, const uint32_t *PRIO,
+            int8_t *F, int32_t *act, int32_t ncols, int32_t ld, hipStream_t s, int64_t *iters_out);
+
 int ls_core(bool maxcut, const GraphView &gv, int64_t nnz_total, uint64_t seed, int32_t round, int8_t *Z, int32_t *NB,
             uint32_t *PRIO, int8_t *F, int32_t *act, long long *acc, int64_t *value_scratch, int32_t ncols,
             int32_t ld, uint64_t traj0, hipStream_t s, int64_t *iters_out) {
   // neighbour counts for the current Z (the values computed here are discarded)
   launch_evaluate(maxcut, gv, Z, NB, acc, value_scratch, nullptr, nullptr, ncols, ld, s);
   launch_ls_prio(PRIO, gv.lo, gv.n, ncols, ld, seed, traj0, (uint64_t)round, s);
+  return ls_loop(maxcut, gv, nnz_total, Z, NB, PRIO, F, act, ncols, ld, s, iters_out);
+}
+
+// The iterations of the 1-flip search on rows gv (NB = A Z and the
+// priorities already in place).
+int ls_loop(bool maxcut, const GraphView &gv, int64_t nnz_total, int8_t *Z, int32_t *NB, const uint32_t *PRIO,
+            int8_t *F, int32_t *act, int32_t ncols, int32_t ld, hipStream_t s, int64_t *iters_out) {
   const int Q = 8;
   int64_t iters = 0;
   const int64_t cap = 4 * (gv.n + nnz_total) + 64;  // never reached: every iteration gains
@@ -458,6 +470,86 @@ int ls_core(bool maxcut, const GraphView &gv, int64_t nnz_total, uint64_t seed, 
   }
   if (iters_out) *iters_out = iters;
   return MQO_OK;
+}
+
+// Rows of every graph of a batch as one view (the search kernels only
+// follow edges, which stay inside each graph).
+GraphView whole_view(const mqo_graph *g) {
+  GraphView v{};
+  v.row_ptr = g->row_ptr;
+  v.col_idx = g->col_idx;
+  v.weight = g->weight;
+  v.lo = 0;
+  v.n = g->n_total;
+  v.hubs = nullptr;
+  v.nhub = 0;
+  v.hub_deg = 0x7fffffff;
+  v.pairs = 0;
+  return v;
+}
+
+// OneTwoSwap / OneTwoFlip on all B columns of every graph of g at once: the
+// 1-flip search, then pair iterations each followed by the 1-flip search,
+// until an iteration applies no move anywhere (columns that are done stay
+// unchanged, so each column's result is its own search's).  The priorities
+// (purpose LS and SWAP, trajectory g_i * B + c, local vertex index) are
+// drawn once.  T0..T2: int32 scratch [n_total][B] each.
+// cand_ms (or nullptr): HIP-event time of the candidate launches, summed.
+int pair_core(bool maxcut, const mqo_graph *g, uint64_t seed, int32_t round, int8_t *Z, int32_t *NB,
+              uint32_t *PRIO, uint32_t *PRIO_SW, int8_t *F, int32_t *act, long long *acc, int64_t *value_scratch,
+              int32_t *T0, int32_t *T1, int32_t *T2, uint32_t *TB, int32_t B, hipStream_t s, int64_t *ls_iters,
+              int64_t *alternations, double *cand_ms) {
+  const GraphView all = whole_view(g);
+  for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
+    const int64_t lo = g->vtx_offset[gi], n = g->vtx_offset[gi + 1] - lo;
+    launch_ls_prio(PRIO, lo, n, B, B, seed, (uint64_t)gi * B, (uint64_t)round, s);
+    launch_swap_prio(PRIO_SW, lo, n, B, B, seed, (uint64_t)gi * B, (uint64_t)round, s);
+  }
+  launch_evaluate(maxcut, all, Z, NB, acc, value_scratch, nullptr, nullptr, B, B, s);  // NB = A Z
+  const int64_t cap = 4 * (g->n_total + g->nnz_total) + 64;  // every applied iteration gains
+  int64_t alt = 0;
+  std::vector<int32_t> flag;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (cand_ms) {
+    *cand_ms = 0.0;
+    HIP_TRY(hipEventCreate(&ev[0]));
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+      (void)hipEventDestroy(ev[0]);
+      return fail(MQO_ERR_HIP, "hipEventCreate failed");
+    }
+  }
+  int rc = MQO_OK;
+  while (rc == MQO_OK) {
+    int64_t it = 0;
+    rc = ls_loop(maxcut, all, g->nnz_total, Z, NB, PRIO, F, act, B, B, s, &it);
+    if (rc != MQO_OK) break;
+    if (ls_iters) *ls_iters += it;
+    launch_fill_i32(act, 1, 0, s);
+    if (cand_ms) (void)hipEventRecord(ev[0], s);
+    launch_pair_candidates(maxcut, all, Z, NB, PRIO_SW, T0, T1, T2, TB, B, B,
+                           (double)g->nnz_total / (double)std::max<int64_t>(1, g->n_total), s);
+    if (cand_ms) (void)hipEventRecord(ev[1], s);
+    launch_pair_apply(maxcut, all, Z, NB, PRIO_SW, F, T0, T1, T2, act, B, B, s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      rc = fail(MQO_ERR_HIP, "pair iteration: %s", hipGetErrorString(e));
+      break;
+    }
+    rc = read_back_i32(act, 1, flag, s);  // synchronises the stream
+    if (rc != MQO_OK) break;
+    if (cand_ms) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) *cand_ms += ms;
+    }
+    if (!flag[0]) break;
+    if (++alt > cap) rc = fail(MQO_ERR_INTERNAL, "pair search did not terminate");
+  }
+  if (cand_ms) {
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+  }
+  if (rc == MQO_OK && alternations) *alternations = alt;
+  return rc;
 }
 
 int run_local_search(Solve &S, const GraphView &gv, int8_t *Z, int32_t *NB, uint32_t *PRIO, int8_t *F, int32_t ncols,
@@ -873,6 +965,47 @@ int solve_tile(Solve &S, int32_t *rounds_done, TileCfg *used) {
   return MQO_OK;
 }
 
+// Consume the tile counters the persistent plan left in the pinned buffer
+// (after a synchronisation), before anything else reads back through it.
+int settle_deferred(Solve &S) {
+  if (!S.deferred_tile_wg) return MQO_OK;
+  HIP_TRY(hipStreamSynchronize(S.s));
+  const int32_t *pin = res().pinned;
+  int64_t mx = 0;
+  for (int32_t i = 0; i < S.deferred_tile_wg; ++i) mx = std::max<int64_t>(mx, pin[i]);
+  S.ls_iters += mx;
+  const bool bad = pin[S.deferred_tile_wg] != 0;
+  S.deferred_tile_wg = 0;
+  if (bad) return fail(MQO_ERR_INTERNAL, "local search did not terminate");
+  return MQO_OK;
+}
+
+// Alg. 1 / Alg. 2 after the reset loop: the pair search on every incumbent
+// (batched over all trajectories and graphs, round index = rounds),
+// replacing it when strictly better.  The iterate buffers and the tile
+// scratch serve as scratch.
+int final_search(Solve &S, int64_t *alternations) {
+  TRY(settle_deferred(S));
+  int8_t *Z = at<int8_t>(S.ws, S.L.Z), *Zb = at<int8_t>(S.ws, S.L.Zb);
+  int64_t *value = at<int64_t>(S.ws, S.L.value), *best = at<int64_t>(S.ws, S.L.best);
+  const int32_t B = S.B;
+  HIP_TRY(hipMemcpyAsync(Z, Zb, (size_t)S.g->n_total * B, hipMemcpyDeviceToDevice, S.s));
+  TRY(pair_core(S.maxcut, S.g, S.p->seed, S.p->rounds, Z, at<int32_t>(S.ws, S.L.NB), at<uint32_t>(S.ws, S.L.PRIO),
+                at<uint32_t>(S.ws, S.L.tprio), at<int8_t>(S.ws, S.L.F), at<int32_t>(S.ws, S.L.act),
+                at<long long>(S.ws, S.L.acc), value, at<int32_t>(S.ws, S.L.X), at<int32_t>(S.ws, S.L.Xt),
+                at<int32_t>(S.ws, S.L.V), at<uint32_t>(S.ws, S.L.tnb), B, S.s, &S.ls_iters, alternations,
+                nullptr));
+  for (int32_t gi = 0; gi < S.G; ++gi) {
+    const GraphView gv = view_of(S.g, gi, S.max_deg);
+    const int64_t t = (int64_t)gi * B;
+    launch_evaluate(S.maxcut, gv, Z, at<int32_t>(S.ws, S.L.NB), at<long long>(S.ws, S.L.acc), value + t, nullptr,
+                    nullptr, B, B, S.s);
+    launch_accept(Z, Zb, value + t, best + t, gv.lo, gv.n, B, B, B, false, S.s);
+  }
+  HIP_TRY(hipGetLastError());
+  return MQO_OK;
+}
+
 int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_result *r, void *ws, size_t ws_bytes,
                  void *stream, mqo_objective obj) {
   TRY(check_graph_args(g, obj == MQO_OBJ_MIS_H));
@@ -932,6 +1065,8 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
     TRY(solve_batched(S, &rounds_done));
   else
     TRY(solve_plain(S, &rounds_done));
+  int64_t final_alt = 0;
+  if (p->final_search == MQO_FINAL_PAIR) TRY(final_search(S, &final_alt));
 
   int64_t *best = at<int64_t>(ws, L.best);
   int32_t *bestb = at<int32_t>(ws, L.bestb);
@@ -948,13 +1083,7 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
   HIP_TRY(hipMemcpyAsync(eu_host, eu_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
-  if (S.deferred_tile_wg) {
-    const int32_t *pin = res().pinned;
-    int64_t mx = 0;
-    for (int32_t i = 0; i < S.deferred_tile_wg; ++i) mx = std::max<int64_t>(mx, pin[i]);
-    S.ls_iters += mx;
-    if (pin[S.deferred_tile_wg]) return fail(MQO_ERR_INTERNAL, "local search did not terminate");
-  }
+  TRY(settle_deferred(S));
   r->rounds_executed = rounds_done;
   r->steps_executed = (int64_t)rounds_done * p->steps_per_round;
   r->edge_updates = *eu_host;
@@ -967,6 +1096,7 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
   r->ls_iterations = S.ls_iters;
   r->step_kernel_ms = S.timed_ms();
   r->step_kernel_launches = (int64_t)S.timed.size();
+  r->final_search_alternations = final_alt;
   return MQO_OK;
 }
 
@@ -1031,6 +1161,7 @@ void mqo_params_default(mqo_params *p) {
   p->seed = 0;
   p->time_budget_s = 0.0;
   p->maxcut_objective = MQO_OBJ_MAXCUT_FB;
+  p->final_search = MQO_FINAL_NONE;
 }
 
 size_t mqo_workspace_size(const mqo_graph *g, const mqo_params *p, mqo_objective obj) {
@@ -1251,18 +1382,37 @@ int mqo_local_search(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t 
   std::lock_guard<std::mutex> host_lock(res().host_mu);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const bool mc = obj != MQO_OBJ_MIS_H;
-  const int form = (int)obj;
-  int64_t total = 0;
+  // every graph of the batch at once: the search only follows edges, which
+  // stay inside each graph, so a column that is done stays unchanged
+  uint32_t *PRIO = at<uint32_t>(ws, L.PRIO);
   for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
-    const GraphView gv = view_of(g, gi);
-    int64_t it = 0;
-    TRY(ls_core(mc, gv, g->nnz_total, seed, round, Z, at<int32_t>(ws, L.NB), at<uint32_t>(ws, L.PRIO),
-                at<int8_t>(ws, L.F), at<int32_t>(ws, L.act), at<long long>(ws, L.acc), at<int64_t>(ws, L.value), B, B,
-                (uint64_t)gi * B, s, &it));
-    total = std::max(total, it);
+    const int64_t lo = g->vtx_offset[gi], n = g->vtx_offset[gi + 1] - lo;
+    launch_ls_prio(PRIO, lo, n, B, B, seed, (uint64_t)gi * B, (uint64_t)round, s);
   }
-  if (iterations) *iterations = total;
+  const GraphView all = whole_view(g);
+  int32_t *NB = at<int32_t>(ws, L.NB);
+  launch_evaluate(mc, all, Z, NB, at<long long>(ws, L.acc), at<int64_t>(ws, L.value), nullptr, nullptr, B, B, s);
+  int64_t it = 0;
+  TRY(ls_loop(mc, all, g->nnz_total, Z, NB, PRIO, at<int8_t>(ws, L.F), at<int32_t>(ws, L.act), B, B, s, &it));
+  if (iterations) *iterations = it;
   return MQO_OK;
+}
+
+int mqo_pair_search(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t seed, int32_t round, int8_t *Z,
+                    int64_t *alternations, double *candidate_kernel_ms, void *ws, size_t ws_bytes, void *stream) {
+  TRY(check_async(g, obj, B));
+  if (!Z) return fail(MQO_ERR_INVALID_ARG, "Z is NULL");
+  const bool mc = obj != MQO_OBJ_MIS_H;
+  if (!mc && g->weight) return fail(MQO_ERR_INVALID_ARG, "MIS graphs carry no weights");
+  const Layout L = make_layout(g, B);
+  if (!ws || ws_bytes < L.total) return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", L.total);
+  TRY(ensure_resources());
+  std::lock_guard<std::mutex> host_lock(res().host_mu);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return pair_core(mc, g, seed, round, Z, at<int32_t>(ws, L.NB), at<uint32_t>(ws, L.PRIO), at<uint32_t>(ws, L.tprio),
+                   at<int8_t>(ws, L.F), at<int32_t>(ws, L.act), at<long long>(ws, L.acc), at<int64_t>(ws, L.value),
+                   at<int32_t>(ws, L.X), at<int32_t>(ws, L.Xt), at<int32_t>(ws, L.V), at<uint32_t>(ws, L.tnb), B, s,
+                   nullptr, alternations, candidate_kernel_ms);
 }
 
 int mqo_reset(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t seed, int32_t round, double rho,

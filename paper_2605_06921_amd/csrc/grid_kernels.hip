@@ -570,14 +570,15 @@ __global__ void k_value_finalize(const long long *__restrict__ acc, int32_t ncol
 // 1-flip local search, parallel rule
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_ls_prio(uint32_t *__restrict__ PRIO, int64_t lo, int64_t n, int32_t ncols,
-                                                 int32_t ld, uint64_t seed, uint64_t traj0, uint64_t round) {
+                                                 int32_t ld, uint64_t seed, uint64_t traj0, uint64_t round,
+                                                 uint64_t purpose) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nvb = (n + 7) >> 3;
   if (idx >= nvb * ncols) return;
   const int32_t c = (int32_t)(idx % ncols);
   const int64_t vb = idx / ncols;
   uint32_t r[8];
-  philox_block8(r, seed, PURPOSE_LS, traj0 + c, round, (uint64_t)vb);
+  philox_block8(r, seed, purpose, traj0 + c, round, (uint64_t)vb);
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int64_t v = vb * 8 + i;
@@ -640,6 +641,332 @@ __global__ __launch_bounds__(256) void k_ls_apply(GraphView g, const int8_t *__r
   for (int32_t j = beg; j < end; ++j) {
     const int64_t u = g.col_idx[j];
     atomicAdd(&NB[u * ld + m.col], WEIGHTED ? d * g.weight[j] : d);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pair moves of the paper's own searches, parallel rule: the (1,2)-swap of
+// Def. 2.3 (MIS) and the 2-flip of Def. 2.5 (MaxCut).  One thread per
+// (vertex, column); every array is [n][ld], one column per trajectory.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool has_edge(const GraphView &g, int32_t a, int32_t b) {
+  // rows are strictly ascending
+  int32_t lo = g.row_ptr[a], hi = g.row_ptr[a + 1];
+  const int32_t end = hi;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (g.col_idx[mid] < b)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo < end && g.col_idx[lo] == b;
+}
+
+__global__ __launch_bounds__(256) void k_fill_rows_i32(int32_t *__restrict__ A, int64_t lo, int64_t n, int32_t v,
+                                                       int32_t ncols, int32_t ld, int32_t lanes_log2) {
+  const RowMap m = map_rows<1>(n, ncols, lanes_log2);
+  if (m.active) A[(lo + m.row) * ld + m.col] = v;
+}
+
+// Tightness bits: word (u, chunk) bit l = 1 iff column 64 chunk + l has
+// z_u = 0 and m_u = 1 (u is outside I with exactly one neighbour in I).
+// One wavefront per (row, chunk of 64 columns).
+__global__ __launch_bounds__(256) void k_tight_bits(GraphView g, const int8_t *__restrict__ Z,
+                                                    const int32_t *__restrict__ NB,
+                                                    unsigned long long *__restrict__ TB, int32_t ncols, int32_t ld) {
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= g.n) return;  // the whole wavefront
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t col = (int32_t)blockIdx.y * 64 + lane;
+  bool t = false;
+  if (col < ncols) {
+    const int64_t e = (g.lo + row) * ld + col;
+    t = Z[e] == 0 && NB[e] == 1;
+  }
+  const unsigned long long bal = __ballot(t);
+  if (lane == 0) TB[(g.lo + row) * gridDim.y + blockIdx.y] = bal;
+}
+
+// v in I proposes the first pair (u, w) of its neighbours in CSR order with
+// m_u = m_w = 1 (v is their only neighbour in I) and u, w not adjacent:
+// then I - v + u + w is independent.  PU/PW = u, w or -1; OWN[u] = OWN[w] = v.
+// One wavefront per (row v, chunk of 64 columns); its lanes span v's
+// neighbour positions, 64 at a time.  For each column with v in I the
+// tight positions come from one ballot per neighbour chunk over the
+// tightness words (k_tight_bits, 64 columns per chunk), and the partners of
+// a tight u are tested for adjacency in parallel, the lowest position
+// winning; so the first pair in CSR order is found in a few wavefront-wide
+// steps.
+__global__ __launch_bounds__(256) void k_swap_propose(GraphView g, const int8_t *__restrict__ Z,
+                                                      const unsigned long long *__restrict__ TB,
+                                                      int32_t *__restrict__ PU, int32_t *__restrict__ PW,
+                                                      int32_t *__restrict__ OWN, int32_t ncols, int32_t ld) {
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= g.n) return;  // the whole wavefront
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t c0 = (int32_t)blockIdx.y * 64;
+  const int32_t cc = ncols - c0 < 64 ? ncols - c0 : 64;  // columns in this chunk
+  const int64_t nchunk = gridDim.y;
+  const int32_t v = __builtin_amdgcn_readfirstlane((int32_t)(g.lo + row));
+  const int64_t e = (int64_t)v * ld + c0 + lane;
+  const bool in_i = lane < cc && Z[e] == 1;
+  unsigned long long act = __ballot(in_i);
+  const int32_t beg = __builtin_amdgcn_readfirstlane(g.row_ptr[v]);
+  const int32_t deg = __builtin_amdgcn_readfirstlane(g.row_ptr[v + 1]) - beg;
+  const int32_t nk = (deg + 63) >> 6;
+  int32_t my_u = -1, my_w = -1;  // lane l: result of column c0 + l
+  while (act) {
+    const int32_t c = __builtin_ctzll(act);
+    act &= act - 1;
+    bool found = false;
+    int32_t fu = -1, fw = -1;
+    for (int32_t k = 0; k < nk && !found; ++k) {
+      const int32_t pk = 64 * k + lane;
+      const int32_t uk = pk < deg ? g.col_idx[beg + pk] : 0;
+      const bool tk = pk < deg && ((TB[(int64_t)uk * nchunk + blockIdx.y] >> c) & 1ull);
+      unsigned long long mk = __ballot(tk);
+      while (mk && !found) {
+        const int32_t i = __builtin_ctzll(mk);
+        mk &= mk - 1;
+        const int32_t u = __builtin_amdgcn_readlane(uk, i);
+        for (int32_t k2 = k; k2 < nk && !found; ++k2) {
+          const int32_t p2 = 64 * k2 + lane;
+          const int32_t w2 = p2 < deg ? g.col_idx[beg + p2] : 0;
+          const bool t2 = p2 < deg && (k2 > k || lane > i) && ((TB[(int64_t)w2 * nchunk + blockIdx.y] >> c) & 1ull);
+          const bool ok = t2 && !has_edge(g, u, w2);
+          const unsigned long long b = __ballot(ok);
+          if (b) {
+            fu = u;
+            fw = __builtin_amdgcn_readlane(w2, __builtin_ctzll(b));
+            found = true;
+          }
+        }
+      }
+    }
+    if (lane == c) {
+      my_u = fu;
+      my_w = fw;
+    }
+  }
+  if (lane >= cc) return;
+  if (my_u >= 0) {
+    OWN[(int64_t)my_u * ld + c0 + lane] = v;
+    OWN[(int64_t)my_w * ld + c0 + lane] = v;
+  }
+  PU[e] = my_u;
+  PW[e] = my_w;
+}
+
+// The same proposals with one thread per (v, column), for graphs of small
+// degree, where a wavefront per row would leave most lanes idle.
+__global__ __launch_bounds__(256) void k_swap_propose_lanes(GraphView g, const int8_t *__restrict__ Z,
+                                                            const unsigned long long *__restrict__ TB,
+                                                            int32_t *__restrict__ PU, int32_t *__restrict__ PW,
+                                                            int32_t *__restrict__ OWN, int32_t ncols, int32_t ld,
+                                                            int32_t lanes_log2) {
+  const RowMap m = map_rows<1>(g.n, ncols, lanes_log2);
+  if (!m.active) return;
+  const int64_t v = g.lo + m.row;
+  const int64_t e = v * ld + m.col;
+  const int64_t nchunk = (ncols + 63) >> 6;
+  const int64_t chunk = m.col >> 6;
+  const int32_t bit = m.col & 63;
+  auto tight = [&](int32_t u) { return ((TB[(int64_t)u * nchunk + chunk] >> bit) & 1ull) != 0; };
+  int32_t pu = -1, pw = -1;
+  if (Z[e] == 1) {
+    const int32_t beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+    for (int32_t i = beg; i < end && pu < 0; ++i) {
+      const int32_t u = g.col_idx[i];
+      if (!tight(u)) continue;
+      for (int32_t j = i + 1; j < end; ++j) {
+        const int32_t w = g.col_idx[j];
+        if (tight(w) && !has_edge(g, u, w)) {
+          pu = u;
+          pw = w;
+          break;
+        }
+      }
+    }
+    if (pu >= 0) {
+      OWN[(int64_t)pu * ld + m.col] = (int32_t)v;
+      OWN[(int64_t)pw * ld + m.col] = (int32_t)v;
+    }
+  }
+  PU[e] = pu;
+  PW[e] = pw;
+}
+
+// A proposal is applied (F = 1) when its key (prio_v, -v) beats the key of
+// every other proposal owning a neighbour of u or w.
+__global__ __launch_bounds__(256) void k_swap_select(GraphView g, const int32_t *__restrict__ PU,
+                                                     const int32_t *__restrict__ PW, const int32_t *__restrict__ OWN,
+                                                     const uint32_t *__restrict__ PRIO, int8_t *__restrict__ F,
+                                                     int32_t *active, int32_t ncols, int32_t ld, int32_t lanes_log2) {
+  const RowMap m = map_rows<1>(g.n, ncols, lanes_log2);
+  if (!m.active) return;
+  const int64_t v = g.lo + m.row;
+  const int64_t e = v * ld + m.col;
+  const int32_t pu = PU[e];
+  bool f = pu >= 0;
+  if (f) {
+    const uint32_t pv = PRIO[e];
+    const int32_t pw = PW[e];
+    for (int k = 0; k < 2 && f; ++k) {
+      const int32_t x = k ? pw : pu;
+      const int32_t beg = g.row_ptr[x], end = g.row_ptr[x + 1];
+      for (int32_t j = beg; j < end; ++j) {
+        const int32_t o = OWN[(int64_t)g.col_idx[j] * ld + m.col];
+        if (o >= 0 && o != v && key_beats(0, PRIO[(int64_t)o * ld + m.col], o, 0, pv, v)) {
+          f = false;
+          break;
+        }
+      }
+    }
+  }
+  const unsigned long long bal = __ballot(f);
+  if (f && (int)(threadIdx.x & 63) == __builtin_ctzll(bal)) *active = 1;
+  F[e] = f ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_swap_apply(GraphView g, const int8_t *__restrict__ F,
+                                                    const int32_t *__restrict__ PU, const int32_t *__restrict__ PW,
+                                                    int8_t *__restrict__ Z, int32_t *__restrict__ NB,
+                                                    const int32_t *active, int32_t ncols, int32_t ld,
+                                                    int32_t lanes_log2) {
+  if (*active == 0) return;
+  const RowMap m = map_rows<1>(g.n, ncols, lanes_log2);
+  if (!m.active) return;
+  const int64_t v = g.lo + m.row;
+  const int64_t e = v * ld + m.col;
+  if (!F[e]) return;
+  const int32_t x3[3] = {(int32_t)v, PU[e], PW[e]};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int32_t x = x3[k];
+    const int32_t d = k ? 1 : -1;
+    Z[(int64_t)x * ld + m.col] = (int8_t)(k ? 1 : 0);
+    const int32_t beg = g.row_ptr[x], end = g.row_ptr[x + 1];
+    for (int32_t j = beg; j < end; ++j) atomicAdd(&NB[(int64_t)g.col_idx[j] * ld + m.col], d);
+  }
+}
+
+// Total order of 2-flip pairs (gain, (prio_v + prio_u) mod 2^32, -min, -max):
+// true iff pair a beats pair b.
+__device__ __forceinline__ bool pair_beats(int32_t ga, uint32_t ha, int32_t mina, int32_t maxa, int32_t gb,
+                                           uint32_t hb, int32_t minb, int32_t maxb) {
+  if (ga != gb) return ga > gb;
+  if (ha != hb) return ha > hb;
+  if (mina != minb) return mina < minb;
+  return maxa < maxb;
+}
+
+// Best improving cut edge at v: gain g_v + g_u + 2 w > 0 (g = s t the 1-flip
+// gains), largest pair key.  BG = gain, BH = hash, BP = CSR position or -1.
+template <bool WEIGHTED>
+__global__ __launch_bounds__(256) void k_flip2_best(GraphView g, const int8_t *__restrict__ Z,
+                                                    const int32_t *__restrict__ NB, const uint32_t *__restrict__ PRIO,
+                                                    int32_t *__restrict__ BG, uint32_t *__restrict__ BH,
+                                                    int32_t *__restrict__ BP, int32_t ncols, int32_t ld,
+                                                    int32_t lanes_log2) {
+  const RowMap m = map_rows<1>(g.n, ncols, lanes_log2);
+  if (!m.active) return;
+  const int64_t v = g.lo + m.row;
+  const int64_t e = v * ld + m.col;
+  const int32_t sv = Z[e];
+  const int32_t gv = sv * NB[e];
+  const uint32_t pv = PRIO[e];
+  int32_t bg = 0, bp = -1, bmin = 0, bmax = 0;
+  uint32_t bh = 0;
+  const int32_t beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+  for (int32_t j = beg; j < end; ++j) {
+    const int32_t u = g.col_idx[j];
+    const int64_t eu = (int64_t)u * ld + m.col;
+    const int32_t su = Z[eu];
+    if (su == sv) continue;
+    const int32_t gain = gv + su * NB[eu] + 2 * (WEIGHTED ? g.weight[j] : 1);
+    if (gain <= 0) continue;
+    const uint32_t h = pv + PRIO[eu];
+    const int32_t mn = (int32_t)v < u ? (int32_t)v : u, mx = (int32_t)v < u ? u : (int32_t)v;
+    if (bp < 0 || pair_beats(gain, h, mn, mx, bg, bh, bmin, bmax)) {
+      bg = gain;
+      bh = h;
+      bp = j;
+      bmin = mn;
+      bmax = mx;
+    }
+  }
+  BG[e] = bg;
+  BH[e] = bh;
+  BP[e] = bp;
+}
+
+// The lower end v of a mutual pair (v, u) applies it (F[v] = 1) when no
+// other vertex adjacent to v or u holds a larger best-pair key.
+__global__ __launch_bounds__(256) void k_flip2_select(GraphView g, const int32_t *__restrict__ BG,
+                                                      const uint32_t *__restrict__ BH,
+                                                      const int32_t *__restrict__ BP, int8_t *__restrict__ F,
+                                                      int32_t *active, int32_t ncols, int32_t ld,
+                                                      int32_t lanes_log2) {
+  const RowMap m = map_rows<1>(g.n, ncols, lanes_log2);
+  if (!m.active) return;
+  const int64_t v = g.lo + m.row;
+  const int64_t e = v * ld + m.col;
+  const int32_t bp = BP[e];
+  bool f = false;
+  if (bp >= 0) {
+    const int32_t u = g.col_idx[bp];
+    const int64_t eu = (int64_t)u * ld + m.col;
+    const int32_t bpu = BP[eu];
+    if ((int32_t)v < u && bpu >= 0 && g.col_idx[bpu] == (int32_t)v) {
+      const int32_t gk = BG[e];
+      const uint32_t hk = BH[e];
+      f = true;
+      for (int k = 0; k < 2 && f; ++k) {
+        const int32_t x = k ? u : (int32_t)v;
+        const int32_t beg = g.row_ptr[x], end = g.row_ptr[x + 1];
+        for (int32_t j = beg; j < end; ++j) {
+          const int32_t y = g.col_idx[j];
+          if (y == (int32_t)v || y == u) continue;
+          const int64_t ey = (int64_t)y * ld + m.col;
+          const int32_t bpy = BP[ey];
+          if (bpy < 0) continue;
+          const int32_t yp = g.col_idx[bpy];
+          if (pair_beats(BG[ey], BH[ey], y < yp ? y : yp, y < yp ? yp : y, gk, hk, (int32_t)v, u)) {
+            f = false;
+            break;
+          }
+        }
+      }
+    }
+  }
+  const unsigned long long bal = __ballot(f);
+  if (f && (int)(threadIdx.x & 63) == __builtin_ctzll(bal)) *active = 1;
+  F[e] = f ? 1 : 0;
+}
+
+template <bool WEIGHTED>
+__global__ __launch_bounds__(256) void k_flip2_apply(GraphView g, const int8_t *__restrict__ F,
+                                                     const int32_t *__restrict__ BP, int8_t *__restrict__ Z,
+                                                     int32_t *__restrict__ NB, const int32_t *active, int32_t ncols,
+                                                     int32_t ld, int32_t lanes_log2) {
+  if (*active == 0) return;
+  const RowMap m = map_rows<1>(g.n, ncols, lanes_log2);
+  if (!m.active) return;
+  const int64_t v = g.lo + m.row;
+  const int64_t e = v * ld + m.col;
+  if (!F[e]) return;
+  const int32_t x2[2] = {(int32_t)v, g.col_idx[BP[e]]};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int32_t x = x2[k];
+    const int64_t ex = (int64_t)x * ld + m.col;
+    const int32_t sx = Z[ex];
+    Z[ex] = (int8_t)(-sx);
+    const int32_t d = -2 * sx;
+    const int32_t beg = g.row_ptr[x], end = g.row_ptr[x + 1];
+    for (int32_t j = beg; j < end; ++j)
+      atomicAdd(&NB[(int64_t)g.col_idx[j] * ld + m.col], WEIGHTED ? d * g.weight[j] : d);
   }
 }
 
@@ -1466,7 +1793,59 @@ void launch_evaluate(bool maxcut, const GraphView &g, const int8_t *Z, int32_t *
 void launch_ls_prio(uint32_t *PRIO, int64_t lo, int64_t n, int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0,
                     uint64_t round, hipStream_t s) {
   const int64_t count = ((n + 7) >> 3) * ncols;
-  MQO_LAUNCH(k_ls_prio, dim3(blocks_for(count)), dim3(256), 0, s, PRIO, lo, n, ncols, ld, seed, traj0, round);
+  MQO_LAUNCH(k_ls_prio, dim3(blocks_for(count)), dim3(256), 0, s, PRIO, lo, n, ncols, ld, seed, traj0, round,
+             (uint64_t)PURPOSE_LS);
+}
+
+void launch_swap_prio(uint32_t *PRIO, int64_t lo, int64_t n, int32_t ncols, int32_t ld, uint64_t seed,
+                      uint64_t traj0, uint64_t round, hipStream_t s) {
+  const int64_t count = ((n + 7) >> 3) * ncols;
+  MQO_LAUNCH(k_ls_prio, dim3(blocks_for(count)), dim3(256), 0, s, PRIO, lo, n, ncols, ld, seed, traj0, round,
+             (uint64_t)PURPOSE_SWAP);
+}
+
+void launch_pair_candidates(bool maxcut, const GraphView &g, const int8_t *Z, const int32_t *NB,
+                            const uint32_t *PRIO, int32_t *T0, int32_t *T1, int32_t *T2, uint32_t *TB, int32_t ncols,
+                            int32_t ld, double mean_degree, hipStream_t s) {
+  const int ll = lanes_log2_for(ncols);
+  const dim3 grid = grid_rows(g.n, ncols, ll, 1, 256);
+  if (maxcut) {
+    if (g.weight)
+      MQO_LAUNCH(k_flip2_best<true>, grid, dim3(256), 0, s, g, Z, NB, PRIO, T0, reinterpret_cast<uint32_t *>(T1), T2,
+                 ncols, ld, ll);
+    else
+      MQO_LAUNCH(k_flip2_best<false>, grid, dim3(256), 0, s, g, Z, NB, PRIO, T0, reinterpret_cast<uint32_t *>(T1),
+                 T2, ncols, ld, ll);
+  } else {
+    // owners of the proposed insertions, -1 elsewhere
+    MQO_LAUNCH(k_fill_rows_i32, grid, dim3(256), 0, s, T2, g.lo, g.n, -1, ncols, ld, ll);
+    // one wavefront per (row, 64 columns)
+    const dim3 wgrid = grid_rows(g.n, ncols, 6, 1, 256);
+    unsigned long long *tb = reinterpret_cast<unsigned long long *>(TB);
+    MQO_LAUNCH(k_tight_bits, wgrid, dim3(256), 0, s, g, Z, NB, tb, ncols, ld);
+    if (mean_degree >= 24.0)
+      MQO_LAUNCH(k_swap_propose, wgrid, dim3(256), 0, s, g, Z, tb, T0, T1, T2, ncols, ld);
+    else
+      MQO_LAUNCH(k_swap_propose_lanes, grid, dim3(256), 0, s, g, Z, tb, T0, T1, T2, ncols, ld, ll);
+  }
+}
+
+void launch_pair_apply(bool maxcut, const GraphView &g, int8_t *Z, int32_t *NB, const uint32_t *PRIO, int8_t *F,
+                       const int32_t *T0, const int32_t *T1, const int32_t *T2, int32_t *active, int32_t ncols,
+                       int32_t ld, hipStream_t s) {
+  const int ll = lanes_log2_for(ncols);
+  const dim3 grid = grid_rows(g.n, ncols, ll, 1, 256);
+  if (maxcut) {
+    MQO_LAUNCH(k_flip2_select, grid, dim3(256), 0, s, g, T0, reinterpret_cast<const uint32_t *>(T1), T2, F, active,
+               ncols, ld, ll);
+    if (g.weight)
+      MQO_LAUNCH(k_flip2_apply<true>, grid, dim3(256), 0, s, g, F, T2, Z, NB, active, ncols, ld, ll);
+    else
+      MQO_LAUNCH(k_flip2_apply<false>, grid, dim3(256), 0, s, g, F, T2, Z, NB, active, ncols, ld, ll);
+  } else {
+    MQO_LAUNCH(k_swap_select, grid, dim3(256), 0, s, g, T0, T1, T2, PRIO, F, active, ncols, ld, ll);
+    MQO_LAUNCH(k_swap_apply, grid, dim3(256), 0, s, g, F, T0, T1, Z, NB, active, ncols, ld, ll);
+  }
 }
 
 void launch_ls_iteration(bool maxcut, const GraphView &g, int8_t *Z, int32_t *NB, const uint32_t *PRIO, int8_t *F,

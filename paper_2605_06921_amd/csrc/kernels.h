@@ -52,6 +52,21 @@ void launch_ls_prio(uint32_t *PRIO, int64_t lo, int64_t n, int32_t ncols, int32_
                     uint64_t round, hipStream_t s);
 void launch_ls_iteration(bool maxcut, const GraphView &g, int8_t *Z, int32_t *NB, const uint32_t *PRIO, int8_t *F,
                          int32_t *active, const int32_t *prev_active, int32_t ncols, int32_t ld, hipStream_t s);
+// priorities of purpose SWAP for the pair moves
+void launch_swap_prio(uint32_t *PRIO, int64_t lo, int64_t n, int32_t ncols, int32_t ld, uint64_t seed,
+                      uint64_t traj0, uint64_t round, hipStream_t s);
+// One parallel pair-move iteration ((1,2)-swap for MIS, 2-flip for MaxCut)
+// on a 1-flip optimum, in two launches: the candidates (MIS proposals /
+// best improving pair per vertex) into T0..T2 (int32 scratch [n][ld] each),
+// then selection and application.  NB must hold A Z; *active is set when a
+// move was applied (the caller clears it).
+// TB: tightness bits, 8 * rows * ceil(ncols / 64) bytes, 8-byte aligned
+void launch_pair_candidates(bool maxcut, const GraphView &g, const int8_t *Z, const int32_t *NB,
+                            const uint32_t *PRIO, int32_t *T0, int32_t *T1, int32_t *T2, uint32_t *TB, int32_t ncols,
+                            int32_t ld, double mean_degree, hipStream_t s);
+void launch_pair_apply(bool maxcut, const GraphView &g, int8_t *Z, int32_t *NB, const uint32_t *PRIO, int8_t *F,
+                       const int32_t *T0, const int32_t *T1, const int32_t *T2, int32_t *active, int32_t ncols,
+                       int32_t ld, hipStream_t s);
 void launch_accept(const int8_t *Z, int8_t *Zb, const int64_t *value, int64_t *best, int64_t lo, int64_t n,
                    int32_t ncols, int32_t ld, int32_t ldb, bool first, hipStream_t s);
 size_t reset_scratch_bytes(int32_t ncols);

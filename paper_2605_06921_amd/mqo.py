@@ -50,7 +50,8 @@ class _Params(ctypes.Structure):
                 ("reset_mode", ctypes.c_int32), ("local_search", ctypes.c_int32), ("plan", ctypes.c_int32),
                 ("tile_cols", ctypes.c_int32), ("tile_threads", ctypes.c_int32), ("tile_vec", ctypes.c_int32),
                 ("tile_csr", ctypes.c_int32), ("tile_reg", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("time_budget_s", ctypes.c_double), ("maxcut_objective", ctypes.c_int32)]
+                ("time_budget_s", ctypes.c_double), ("maxcut_objective", ctypes.c_int32),
+                ("final_search", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -61,7 +62,8 @@ class _Result(ctypes.Structure):
                 ("tile_threads_used", ctypes.c_int32), ("tile_vec_used", ctypes.c_int32),
                 ("tile_csr_lds_used", ctypes.c_int32), ("tile_reg_degree_used", ctypes.c_int32),
                 ("ls_iterations", ctypes.c_int64),
-                ("step_kernel_ms", ctypes.c_double), ("step_kernel_launches", ctypes.c_int64)]
+                ("step_kernel_ms", ctypes.c_double), ("step_kernel_launches", ctypes.c_int64),
+                ("final_search_alternations", ctypes.c_int64)]
 
 
 def _load():
@@ -85,6 +87,8 @@ def _load():
         "mqo_pga_steps": (i32, [G, i32, P, vp, vp, vp, i32, vp]),
         "mqo_round_evaluate": (i32, [G, i32, vp, i32, vp, vp, vp, vp, vp, sz, vp]),
         "mqo_local_search": (i32, [G, i32, i32, u64, i32, vp, ctypes.POINTER(i64), vp, sz, vp]),
+        "mqo_pair_search": (i32, [G, i32, i32, u64, i32, vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
+                                  vp, sz, vp]),
         "mqo_reset": (i32, [G, i32, i32, u64, i32, f64, i32, vp, vp, vp, vp, sz, vp]),
         "mqo_validate_graph_host": (i32, [i64, i64, vp, vp, vp]),
         "mqo_validate_graph": (i32, [G, vp]),
@@ -208,7 +212,7 @@ def last_error() -> str:
 def make_params(batch=1, steps_per_round=200, rounds=1, alpha=0.01, momentum=0.0, gamma=2.0, lam=1e-3,
                 rho=0.05, init_sigma=0.0, init_mode="uniform", reset_mode="zero", local_search=True,
                 plan="auto", seed=0, time_budget_s=0.0, tile_cols=0, tile_threads=0, tile_vec=0, tile_csr=0,
-                tile_reg=0, check_every=0) -> _Params:
+                tile_reg=0, check_every=0, final_search=False) -> _Params:
     p = _Params()
     _lib.mqo_params_default(ctypes.byref(p))
     p.batch, p.steps_per_round, p.rounds, p.check_every = batch, steps_per_round, rounds, check_every
@@ -220,6 +224,7 @@ def make_params(batch=1, steps_per_round=200, rounds=1, alpha=0.01, momentum=0.0
     p.tile_cols, p.tile_threads, p.tile_vec, p.tile_csr = tile_cols, tile_threads, tile_vec, tile_csr
     p.tile_reg = tile_reg
     p.seed, p.time_budget_s = seed, time_budget_s
+    p.final_search = 1 if final_search else 0
     return p
 
 
@@ -284,7 +289,8 @@ def solve(kind, dg: DeviceGraph, x0: Optional[torch.Tensor] = None, workspace: O
                tile_threads=r.tile_threads_used, tile_vec=r.tile_vec_used, tile_csr_lds=r.tile_csr_lds_used,
                tile_reg_degree=r.tile_reg_degree_used,
                ls_iterations=r.ls_iterations,
-               step_kernel_ms=r.step_kernel_ms, step_kernel_launches=r.step_kernel_launches)
+               step_kernel_ms=r.step_kernel_ms, step_kernel_launches=r.step_kernel_launches,
+               final_search_alternations=r.final_search_alternations)
     if want_traj:
         out["traj_best_value"] = traj_v
         out["traj_best_x"] = traj_x.view(dg.n, B)
@@ -350,6 +356,23 @@ def local_search(kind, dg: DeviceGraph, Z: torch.Tensor, seed: int, rnd: int, wo
     _check(_lib.mqo_local_search(dg.struct, _KIND[kind], B, seed, rnd, _ptr(Z), ctypes.byref(it),
                                  ctypes.c_void_p(ws.data_ptr()), nbytes, _stream(dg.device)), "mqo_local_search")
     return it.value
+
+
+def pair_search(kind, dg: DeviceGraph, Z: torch.Tensor, seed: int, rnd: int, workspace=None, timing=None):
+    """In-place OneTwoSwap (MIS) / OneTwoFlip (MaxCut) on Z [n][B] (int8);
+    returns the pair iterations that applied a move.  ``timing`` (a dict)
+    receives candidate_kernel_ms, the HIP-event time of the candidate
+    launches."""
+    B = Z.shape[1]
+    ws, nbytes = _solve_ws(dg, kind, B, workspace)
+    alt = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    _check(_lib.mqo_pair_search(dg.struct, _KIND[kind], B, seed, rnd, _ptr(Z), ctypes.byref(alt),
+                                ctypes.byref(ms) if timing is not None else None,
+                                ctypes.c_void_p(ws.data_ptr()), nbytes, _stream(dg.device)), "mqo_pair_search")
+    if timing is not None:
+        timing["candidate_kernel_ms"] = ms.value
+    return alt.value
 
 
 def reset(kind, dg: DeviceGraph, Zbest: torch.Tensor, seed: int, rnd: int, rho: float, mode="zero",

@@ -680,3 +680,75 @@ def test_formulation_comparison_ordering(mqo):
             assert np.array_equal(cuts[gi * 8:(gi + 1) * 8], discrete.evaluate_cut(g.subgraph(gi), S))
         mean_cut[form] = cuts.mean()
     assert min(mean_cut["maxcut_fa"], mean_cut["maxcut"]) > 1.05 * max(mean_cut["maxcut_fl"], mean_cut["maxcut_fp"])
+
+
+# --------------------------------------------------------------------------
+# the paper's own searches: OneTwoSwap (Def. 2.3), OneTwoFlip (Def. 2.5)
+# --------------------------------------------------------------------------
+
+PAIR_CASES = {
+    "mis_er300": ("mis", CASES["er300"][1]),
+    "mis_batch": ("mis", graphs.concat([CASES["er_batch"][1], graphs.star(7), graphs.path(3), graphs.path(2)])),
+    # mean degree >= 24: proposals by one wavefront per row
+    "mis_dense": ("mis", graphs.concat([graphs.erdos_renyi(150, 0.3, 4904), graphs.erdos_renyi(90, 0.5, 4905),
+                                        graphs.complete(5)])),
+    "cut_reg4": ("maxcut", graphs.random_regular(240, 4, 4900)),
+    "cut_torus": ("maxcut", CASES["torus"][1]),
+    "cut_batch": ("maxcut", graphs.concat([CASES["cut_batch"][1], graphs.cycle(4), graphs.empty(2)])),
+    "cut_weighted": ("maxcut", graphs.with_weights(graphs.erdos_renyi(150, 0.06, 4901), 4902, values=(-2, -1, 1, 3))),
+}
+
+
+def _pair_ref(kind, g, Z, seed, rnd, B):
+    out = np.empty_like(Z)
+    for gi in range(g.num_graphs):
+        lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+        out[lo:hi], _ = discrete.pair_search(kind, g.subgraph(gi), Z[lo:hi], seed, gi * B + np.arange(B), rnd)
+    return out
+
+
+@pytest.mark.parametrize("name", list(PAIR_CASES))
+@pytest.mark.parametrize("B", [1, 5, 64])
+def test_pair_search_bit_exact(mqo, name, B):
+    kind, g = PAIR_CASES[name]
+    dg = mqo.DeviceGraph(g, DEV)
+    Z0 = discrete.round_x(kind, _x(kind, g.n, B, 311 + B))
+    if kind == "mis":
+        Z0 = (arrays.uniform((g.n, B), 0.0, 1.0, 312 + B) < 0.25).astype(np.int8)  # infeasible starts too
+    Z = torch.from_numpy(Z0).to(DEV)
+    alt = mqo.pair_search(kind, dg, Z, 41, 7)
+    ref = _pair_ref(kind, g, Z0, 41, 7, B)
+    assert np.array_equal(Z.cpu().numpy(), ref)
+    ls = torch.from_numpy(Z0).to(DEV)
+    mqo.local_search(kind, dg, ls, 41, 7)
+    moved = not np.array_equal(ls.cpu().numpy(), ref)
+    assert (alt > 0) == moved
+    if name in ("mis_er300", "cut_reg4", "cut_weighted"):
+        assert moved
+
+
+@pytest.mark.parametrize("B", [65, 130])
+def test_pair_search_dense_column_chunks(mqo, B):
+    """Several 64-column chunks, the last one partial."""
+    kind, g = PAIR_CASES["mis_dense"]
+    dg = mqo.DeviceGraph(g, DEV)
+    Z0 = (arrays.uniform((g.n, B), 0.0, 1.0, 313 + B) < 0.2).astype(np.int8)
+    Z = torch.from_numpy(Z0).to(DEV)
+    mqo.pair_search(kind, dg, Z, 42, 3)
+    assert np.array_equal(Z.cpu().numpy(), _pair_ref(kind, g, Z0, 42, 3, B))
+
+
+@pytest.mark.parametrize("kind", ["mis", "maxcut"])
+@pytest.mark.parametrize("plan", ["persistent", "batched", "plain"])
+def test_solve_final_search_bit_exact(mqo, kind, plan):
+    g = CASES["er_batch"][1] if kind == "mis" else graphs.concat([graphs.random_regular(120, 4, 4903),
+                                                                  CASES["cut_batch"][1]])
+    kw = dict(batch=8, steps_per_round=30, rounds=3, alpha=0.05, rho=0.1, seed=43)
+    out = mqo.solve(kind, mqo.DeviceGraph(g, DEV), plan=plan, final_search=True, **kw)
+    assert out["plan"] == plan
+    ref = solver.solve(kind, g, solver.Params(final_search=True, **kw))
+    assert np.array_equal(out["traj_best_value"].cpu().numpy(), ref["traj_best_value"])
+    assert np.array_equal(out["traj_best_x"].cpu().numpy(), ref["traj_best_x"])
+    assert np.array_equal(out["best_value"].cpu().numpy(), ref["best_value"])
+    base = solver.solve(kind, g, solver.Params(**kw))
+    assert np.all(ref["traj_best_value"] >= base["traj_best_value"])

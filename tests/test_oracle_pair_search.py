@@ -215,3 +215,21 @@ def test_solver_final_search_ends_at_pair_optima(kind):
         else:
             s = z.astype(np.int64)
             assert not _one_flip_repairable(g, s) and not _two_flip_repairable(g, s)
+
+
+def test_two_flip_numpy_form_equals_loop_form():
+    for seed in range(12):
+        g = graphs.erdos_renyi(60, 0.08, 4950 + seed)
+        if seed % 3 == 1:
+            g = graphs.with_weights(g, 4970 + seed, values=(-2, -1, 1, 3))
+        if seed % 3 == 2:
+            g = graphs.torus_pm1(7, 4990 + seed)
+        rng = np.random.default_rng(seed)
+        s = np.where(rng.random(g.n) < 0.5, 1, -1).astype(np.int64)
+        s = discrete.local_search("maxcut", g, s.reshape(-1, 1), seed, np.arange(1), 0)[0][:, 0].astype(np.int64)
+        t = discrete.neighbour_counts(g, s.reshape(-1, 1))[:, 0]
+        prio = rng.integers(0, 1 << 32, g.n)
+        prio[: g.n // 3] = prio[0]  # ties in the hash
+        a = discrete.flip2_iteration_cut(g, s, t, prio)
+        b = discrete.flip2_iteration_cut_np(g, s, t, prio)
+        assert sorted(a) == sorted(b)
