@@ -197,6 +197,72 @@ def bench_pair(args, wl):
     return res
 
 
+def bench_toy(args):
+    """Prop. 4.1's toy at n = 64: 2^20 independent trials of the
+    single-coordinate global reset for R = ceil(2 log(n / delta)) rounds of n
+    attempts (delta = 0.01), 128 descent steps per reset.  A step is one
+    launch over every trial; value = reset attempts per second.  The full
+    restart comparison runs once, untimed, at n = 12."""
+    import math
+    import torch
+    from oracle import toy as otoy
+    from paper_2605_06921_amd import mqo
+
+    n, delta, steps, trials = 64, 0.01, 128, 1 << 20
+    R = math.ceil(2 * math.log(n / delta))
+    m = R * n
+    dev = torch.device("cuda:0")
+    first = None
+    for _ in range(args.warmup):
+        first, _ = mqo.toy_reset(11, n, trials, m, steps=steps, device=dev, want_x=False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        first, _ = mqo.toy_reset(11, n, trials, m, steps=steps, device=dev, want_x=False)
+    e1.record()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gpu_s = e0.elapsed_time(e1) / 1e3
+    f = first.cpu().numpy()
+    rs, _ = mqo.toy_reset(12, 12, 1 << 16, 4096, mode="restart", steps=steps, device=dev)
+    rs = rs.cpu().numpy()
+    attempts = trials * m * args.steps
+    res = dict(metric="reset attempts per second (Prop. 4.1 toy, single-coordinate global reset)",
+               value=attempts / el, unit="attempts/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=1e3 * el / args.steps, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f32", data="synthetic",
+               config=dict(workload="prop41_toy_n64", mode="toy", n=n, trials=trials, rounds=R, attempts=m,
+                           descent_steps=steps, alpha=0.5, beta=0.5, parallelism="dp1"),
+               result=dict(success_fraction=float((f >= 0).mean()), failure_bound=float(otoy.failure_bound(n, R)),
+                           delta=delta, mean_attempts_to_hit=float(f[f >= 0].mean()),
+                           full_restart_n12_success_fraction_within_4096=float((rs >= 0).mean()),
+                           full_restart_n12_exact=float(1 - (1 - 2.0 ** -12) ** 4097)))
+    # ALU-bound: 5 float32 operations per descent step (the clip is two
+    # compares, not counted), 128 steps per attempt; Philox and the float64
+    # acceptance test are extra work not counted
+    flops = 5.0 * steps * attempts
+    res["roofline"] = dict(bound="alu", achieved=flops / gpu_s / 1e12, peak=157.3, unit="TFLOP/s",
+                           frac=flops / gpu_s / 157.3e12, traffic=None, kernel="k_toy_global_reset",
+                           avg_launch_ms=1e3 * gpu_s / args.steps, flops_per_launch=flops / args.steps)
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline (toy)")
+        T = 256
+        t0 = time.perf_counter()
+        otoy.global_reset(11, n, T, m, steps=steps)
+        cel = time.perf_counter() - t0
+        while cel < args.cpu_budget / 2 and T < trials:
+            T *= 2
+            t0 = time.perf_counter()
+            otoy.global_reset(11, n, T, m, steps=steps)
+            cel = time.perf_counter() - t0
+        res["cpu_baseline"] = dict(value=T * m / cel, unit="attempts/s", cores=1, kind="oracle",
+                                   sample=f"trials 0..{T - 1} of {trials}, all {m} attempts each, numpy "
+                                          f"vectorised over trials, single-threaded, {cel:.1f} s")
+    return res
+
+
 def bench_differentiation(args, wl):
     """Objective + gradient (grad) or the unrolled adjoint (unrolled) over the
     workload's batch.  EU = one stored CSR entry x one trajectory in one
@@ -279,7 +345,7 @@ def main():
     ap.add_argument("--objective", default="", choices=["", "maxcut", "maxcut_fl", "maxcut_fp", "maxcut_fa"],
                     help="MaxCut workloads: the formulation of the steps (default f_B, Eq. (7); f_L, f_P, f_A are "
                          "Eq. (4)-(6))")
-    ap.add_argument("--mode", default="solve", choices=["solve", "grad", "unrolled", "pair"],
+    ap.add_argument("--mode", default="solve", choices=["solve", "grad", "unrolled", "pair", "toy"],
                     help="solve: whole batched solves; grad: objective + SpMM gradient over the batch; "
                          "unrolled: K = 20 unrolled PGA steps forward and their adjoint (checkpoints every 5)")
     ap.add_argument("--tile", default="",
@@ -304,6 +370,9 @@ def main():
         if args.objective != wl.problem:
             # counter records are per workload and formulation
             wl = dataclasses.replace(wl, problem=args.objective, name=f"{wl.name}:{args.objective}")
+    if args.mode == "toy":
+        print(json.dumps(bench_toy(args)), flush=True)
+        return
     if args.mode == "pair":
         print(json.dumps(bench_pair(args, wl)), flush=True)
         return

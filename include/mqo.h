@@ -307,6 +307,30 @@ int mqo_reset(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t seed, i
               double rho, int32_t mode, const int8_t *Zbest, const uint32_t *keys,
               float *X, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- Prop. 4.1's separable toy ---- */
+
+enum { MQO_TOY_GLOBAL_RESET = 0, MQO_TOY_FULL_RESTART = 1 };
+
+/* Independent trials of the analysis of Prop. 4.1 (Sec. 4): minimise
+ * F(x) = sum_i phi(x_i) on [-1,1]^n, phi(x) = -x^2/2 - beta x^3/3, whose
+ * projected descent x <- Pi(x + alpha (x + beta x^2)) (`steps` float32 steps,
+ * no fused operations) sends (0,1] to 1 and [-1,0) to -1; x* = (1,...,1).
+ * Value draws: Philox4x64-10, y = (2 (w >> 8) + 1 - 2^24) / 2^24.
+ * MQO_TOY_GLOBAL_RESET: the start is restart 0 descended; then `attempts`
+ * times one coordinate i = (w0 n) >> 32 is reset to a drawn y, descended,
+ * and kept iff phi (float64) strictly decreases; first_hit[t] = the number
+ * of attempts after which the point first equals x* (0 = at the start), else
+ * -1; x_out ([trials][n], or NULL) = the final points.
+ * MQO_TOY_FULL_RESTART: restarts j = 0 .. attempts draw and descend a whole
+ * point; first_hit[t] = the first j that gives x*, else -1 (x_out unused).
+ * Keys: (seed, 6) for resets with counter (0, t, attempt, 0) lanes 0-1, and
+ * (seed, 7) for restart j with counter (v >> 3, t, j, 0) lane v & 7.
+ * 1 <= n <= 64, 0 < beta < 1, alpha > 0, steps, attempts >= 0, trials >= 0.
+ * Asynchronous on `stream`. */
+int mqo_toy_reset(uint64_t seed, int32_t n, float alpha, float beta, int32_t steps,
+                  int32_t attempts, int32_t trials, int32_t mode, int32_t *first_hit,
+                  float *x_out, void *stream);
+
 /* ---- validation and misc ---- */
 
 /* Canonical-form check of a host CSR (no GPU needed). */

@@ -38,8 +38,11 @@ F32 = np.float32
 
 
 def phi(x, beta):
+    """float64, in the order written: a = x x, b = a x, -0.5 a - (beta b) / 3."""
     x = np.asarray(x, dtype=np.float64)
-    return -0.5 * x * x - beta * x ** 3 / 3.0
+    a = x * x
+    b = a * x
+    return -0.5 * a - (beta * b) / 3.0
 
 
 def value_from_u32(w):

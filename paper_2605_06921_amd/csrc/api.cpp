@@ -1439,6 +1439,21 @@ int mqo_reset(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t seed, i
 
 // ---- validation and misc ----
 
+int mqo_toy_reset(uint64_t seed, int32_t n, float alpha, float beta, int32_t steps, int32_t attempts,
+                  int32_t trials, int32_t mode, int32_t *first_hit, float *x_out, void *stream) {
+  if (n < 1 || n > 64) return fail(MQO_ERR_INVALID_ARG, "n must be in [1, 64]");
+  if (!(alpha > 0.0f) || !std::isfinite(alpha)) return fail(MQO_ERR_INVALID_ARG, "alpha must be > 0");
+  if (!(beta > 0.0f && beta < 1.0f)) return fail(MQO_ERR_INVALID_ARG, "beta must be in (0, 1)");
+  if (steps < 0 || attempts < 0 || trials < 0) return fail(MQO_ERR_INVALID_ARG, "negative count");
+  if (mode != MQO_TOY_GLOBAL_RESET && mode != MQO_TOY_FULL_RESTART) return fail(MQO_ERR_INVALID_ARG, "bad mode");
+  if (trials == 0) return MQO_OK;
+  if (!first_hit) return fail(MQO_ERR_INVALID_ARG, "first_hit is NULL");
+  launch_toy(mode, seed, n, alpha, beta, steps, attempts, trials, first_hit,
+             mode == MQO_TOY_GLOBAL_RESET ? x_out : nullptr, reinterpret_cast<hipStream_t>(stream));
+  HIP_TRY(hipGetLastError());
+  return MQO_OK;
+}
+
 int mqo_validate_graph_host(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                             const int32_t *weight) {
   if (n < 1 || n >= (int64_t)1 << 31) return fail(MQO_ERR_INVALID_GRAPH, "n out of range");

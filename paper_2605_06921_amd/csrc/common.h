@@ -13,7 +13,15 @@ namespace mqo {
 // Stream layout: key = (seed, purpose), counter = (v >> 3, t, round, 0);
 // vertex v takes 32-bit lane v & 7 (word (v & 7) >> 1, low half if even).
 // ---------------------------------------------------------------------------
-enum : uint64_t { PURPOSE_INIT = 1, PURPOSE_RESET = 2, PURPOSE_LS = 3, PURPOSE_NOISE = 4, PURPOSE_SWAP = 5 };
+enum : uint64_t {
+  PURPOSE_INIT = 1,
+  PURPOSE_RESET = 2,
+  PURPOSE_LS = 3,
+  PURPOSE_NOISE = 4,
+  PURPOSE_SWAP = 5,
+  PURPOSE_TOY_RESET = 6,
+  PURPOSE_TOY_START = 7
+};
 
 __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
   const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;

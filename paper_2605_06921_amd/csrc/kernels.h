@@ -131,5 +131,9 @@ struct TileArgs {
 bool tile_shape_ok(int64_t n_max, int T, int threads, int vec, bool csr_lds, int dreg, int ipt);
 size_t tile_lds_bytes(int64_t n_max, int T, int64_t nnz_max, bool csr_lds, bool state_lds);
 hipError_t launch_tile_round(bool maxcut, bool weighted, const TileArgs &a, int threads, hipStream_t s);
+// Prop. 4.1 toy: mode 0 = single-coordinate global reset, 1 = full restarts
+// (attempts = restarts); n <= 64; x_out [trials][n] or nullptr (mode 0).
+void launch_toy(int32_t mode, uint64_t seed, int32_t n, float alpha, float beta, int32_t steps, int32_t attempts,
+                int32_t trials, int32_t *first, float *x_out, hipStream_t s);
 
 }  // namespace mqo

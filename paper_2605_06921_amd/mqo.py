@@ -87,6 +87,7 @@ def _load():
         "mqo_pga_steps": (i32, [G, i32, P, vp, vp, vp, i32, vp]),
         "mqo_round_evaluate": (i32, [G, i32, vp, i32, vp, vp, vp, vp, vp, sz, vp]),
         "mqo_local_search": (i32, [G, i32, i32, u64, i32, vp, ctypes.POINTER(i64), vp, sz, vp]),
+        "mqo_toy_reset": (i32, [u64, i32, ctypes.c_float, ctypes.c_float, i32, i32, i32, i32, vp, vp, vp]),
         "mqo_pair_search": (i32, [G, i32, i32, u64, i32, vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                   vp, sz, vp]),
         "mqo_reset": (i32, [G, i32, i32, u64, i32, f64, i32, vp, vp, vp, vp, sz, vp]),
@@ -373,6 +374,19 @@ def pair_search(kind, dg: DeviceGraph, Z: torch.Tensor, seed: int, rnd: int, wor
     if timing is not None:
         timing["candidate_kernel_ms"] = ms.value
     return alt.value
+
+
+def toy_reset(seed: int, n: int, trials: int, attempts: int, mode="global", alpha=0.5, beta=0.5, steps=128,
+              device="cuda", want_x=True):
+    """Prop. 4.1's toy (mqo_toy_reset) on the current stream of ``device``:
+    returns (first_hit int32[trials], final points [trials][n] or None)."""
+    dev = torch.device(device)
+    first = torch.empty(trials, dtype=torch.int32, device=dev)
+    x = torch.empty(trials, n, dtype=torch.float32, device=dev) if (want_x and mode == "global") else None
+    m = 0 if mode == "global" else 1
+    _check(_lib.mqo_toy_reset(seed, n, alpha, beta, steps, attempts, trials, m, _ptr(first), _ptr(x), _stream(dev)),
+           "mqo_toy_reset")
+    return first, x
 
 
 def reset(kind, dg: DeviceGraph, Zbest: torch.Tensor, seed: int, rnd: int, rho: float, mode="zero",
