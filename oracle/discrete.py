@@ -460,3 +460,69 @@ def pair_search(kind, graph, Z, seed, traj, rnd, max_alternations=None):
         alternations += 1
         if alternations > cap:
             raise RuntimeError("pair search did not terminate")
+
+
+# --------------------------------------------------------------------------
+# the pmQO pool (Alg. 3 / Alg. 4): top-K distinct solutions per graph
+# --------------------------------------------------------------------------
+
+_SM_GAMMA = 0x9E3779B97F4A7C15
+_SM_M1 = 0xBF58476D1CE4E5B9
+_SM_M2 = 0x94D049BB133111EB
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(x):
+    """SplitMix64 output for state x (Steele, Lea and Flood, OOPSLA 2014):
+    z = x + gamma; z = (z ^ z >> 30) m1; z = (z ^ z >> 27) m2; z ^ z >> 31."""
+    x = np.asarray(x, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = x + np.uint64(_SM_GAMMA)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(_SM_M1)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(_SM_M2)
+        return z ^ (z >> np.uint64(31))
+
+
+def solution_hash(Z):
+    """Per column: sum over the vertices v in the set (z_v = 1 for MIS,
+    s_v = +1 for MaxCut) of splitmix64(v), mod 2^64 (v = local index)."""
+    Z = np.asarray(Z)
+    h = splitmix64(np.arange(Z.shape[0], dtype=np.uint64))
+    with np.errstate(over="ignore"):
+        return np.where(Z > 0, h[:, None], np.uint64(0)).sum(axis=0, dtype=np.uint64)
+
+
+def pool_update(kind, pool_val, pool_z, val, Z, K):
+    """TopK of the pool united with the new candidates (Alg. 3 / 4): the
+    union is a set, so a solution already held (equal value and hash, the
+    vectors then checked equal) enters once; MIS candidates that are not
+    independent (value -1) are not solutions and never enter; ranking by
+    value, ties to the earlier source (pool members in rank order, then
+    columns in order).  Returns (values int64[k], solutions int8[n][k])."""
+    pool_val = np.asarray(pool_val, dtype=np.int64)
+    cands = [(int(pool_val[i]), i, pool_z[:, i]) for i in range(len(pool_val))]
+    cands += [(int(val[b]), len(pool_val) + b, Z[:, b]) for b in range(Z.shape[1])
+              if not (kind == obj.MIS and val[b] < 0)]
+    cands.sort(key=lambda c: (-c[0], c[1]))
+    hashes = {}
+    out_v, out_z = [], []
+    for value, _, z in cands:
+        key = (value, int(solution_hash(z.reshape(-1, 1))[0]))
+        if key in hashes:
+            assert np.array_equal(hashes[key], z), "hash collision between different solutions"
+            continue
+        hashes[key] = z
+        out_v.append(value)
+        out_z.append(z)
+        if len(out_v) == K:
+            break
+    n = Z.shape[0]
+    zs = np.stack(out_z, axis=1).astype(np.int8) if out_z else np.zeros((n, 0), dtype=np.int8)
+    return np.array(out_v, dtype=np.int64), zs
+
+
+def pool_bases(seed, traj, rnd, size):
+    """Pool slot each trajectory restarts from: (u * size) >> 32 with u the
+    uint32 Philox draw of purpose POOL for (traj, round)."""
+    u = philox.vertex_u32(seed, philox.PURPOSE_POOL, np.asarray(traj, dtype=np.uint64), rnd, np.uint64(0))
+    return ((u.astype(np.uint64) * np.uint64(size)) >> np.uint64(32)).astype(np.int64)

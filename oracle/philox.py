@@ -30,6 +30,7 @@ PURPOSE_RESET = 2
 PURPOSE_LS = 3
 PURPOSE_NOISE = 4
 PURPOSE_SWAP = 5
+PURPOSE_POOL = 8
 
 
 def philox4x64_10(ctr, key):

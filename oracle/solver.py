@@ -19,6 +19,14 @@ With ``final_search`` the paper's own search (OneTwoSwap / OneTwoFlip,
 ``discrete.pair_search`` with round index ``rounds``) runs on every
 incumbent after the last round and replaces it when strictly better
 (Alg. 1 / Alg. 2, the local search after the reset loop).
+With ``pool_k`` = K > 0 the graph's trajectories share the pmQO pool of
+Alg. 3 / Alg. 4: after every round the pool becomes the top K distinct
+solutions of the pool and the round's candidates (``discrete.pool_update``),
+and a round r > 0 restarts trajectory t from pool slot
+``discrete.pool_bases`` (its own incumbent while the pool is empty).  The
+answer is then the best pool member, and ``final_search`` searches every
+pool member (trajectory ids g K + slot) instead of the incumbents,
+replacing a member when strictly better.
 The answer of graph g is the best incumbent over its B trajectories, ties
 to the lowest b.
 Test infrastructure only.
@@ -51,6 +59,7 @@ class Params:
     init_sigma: float = 0.0
     check_every: int = 0
     final_search: bool = False
+    pool_k: int = 0
 
 
 def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32", trace=None, cols=None,
@@ -71,6 +80,10 @@ def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32"
     best = np.full(B, np.iinfo(np.int64).min, dtype=np.int64)
     zbest = np.zeros((n, B), dtype=np.int8)
     steps = np.zeros(B, dtype=np.int64)
+    K = p.pool_k
+    if K:
+        assert B == p.batch, "the pool couples all trajectories of a graph"
+    pool_val, pool_z = np.zeros(0, dtype=np.int64), np.zeros((n, 0), dtype=np.int8)
     for r in range(p.rounds):
         if r == 0:
             if x0 is not None:
@@ -81,7 +94,10 @@ def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32"
                 X = pga.init_degree(kind, graph.degrees(), traj, p.seed, p.init_sigma).astype(np.float32)
         else:
             mask = discrete.reset_set(n, k, p.seed, traj, r)
-            X = discrete.reset_apply(kind, zbest, mask, p.reset_mode)
+            base = zbest
+            if K and len(pool_val):
+                base = pool_z[:, discrete.pool_bases(p.seed, traj, r, len(pool_val))]
+            X = discrete.reset_apply(kind, base, mask, p.reset_mode)
         V = None
         active = np.ones(B, dtype=bool)
         for st in range(p.steps_per_round):
@@ -106,16 +122,27 @@ def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32"
         take = (val > best) if r else np.ones(B, dtype=bool)
         best = np.where(take, val, best)
         zbest[:, take] = Z[:, take]
+        if K:
+            pool_val, pool_z = discrete.pool_update(kind, pool_val, pool_z, val, Z, K)
         if trace is not None:
             trace.append(dict(round=r, value=val.copy(), best=best.copy()))
-    if p.final_search:
+    if p.final_search and not K:
         Z, _ = discrete.pair_search(kind, graph, zbest, p.seed, traj, p.rounds)
         val = discrete.value(kind, graph, Z)
         take = val > best
         best = np.where(take, val, best)
         zbest[:, take] = Z[:, take]
+    if p.final_search and K and len(pool_val):
+        Zp, _ = discrete.pair_search(kind, graph, pool_z, p.seed, graph_index * K + np.arange(len(pool_val)),
+                                     p.rounds)
+        vp = discrete.value(kind, graph, Zp)
+        take = vp > pool_val
+        pool_val = np.where(take, vp, pool_val)
+        pool_z[:, take] = Zp[:, take]
     if stats is not None:
         stats["steps"] = steps
+        if K:
+            stats["pool_value"], stats["pool_z"] = pool_val, pool_z
     return best, zbest
 
 
@@ -130,6 +157,9 @@ def solve(kind, graph, p: Params, x0=None, precision="fp32"):
     best_value = np.zeros(G, dtype=np.int64)
     best_x = np.zeros(graph.n, dtype=np.int8)
     out_steps = np.zeros(G * p.batch, dtype=np.int64)
+    # empty pool slots: value INT64_MIN, solution zeros
+    pool_value = np.full(G * p.pool_k, np.iinfo(np.int64).min, dtype=np.int64)
+    pool_x = np.zeros((graph.n, p.pool_k), dtype=np.int8)
     for g in range(G):
         sub = graph.subgraph(g)
         lo, hi = int(offs[g]), int(offs[g + 1])
@@ -139,8 +169,23 @@ def solve(kind, graph, p: Params, x0=None, precision="fp32"):
         out_steps[g * p.batch:(g + 1) * p.batch] = st["steps"]
         out_vals[g * p.batch:(g + 1) * p.batch] = vals
         out_z[lo:hi] = zb
+        if p.pool_k:
+            pv, pz = st["pool_value"], st["pool_z"]
+            K = p.pool_k
+            pool_value[g * K:g * K + len(pv)] = pv
+            pool_x[lo:hi, :len(pv)] = pz
+            if len(pv):
+                b = int(np.argmax(pv))  # first slot of the maximum
+                best_value[g] = pv[b]
+                best_x[lo:hi] = pz[:, b]
+            else:
+                best_value[g] = -1
+            continue
         b = int(np.argmax(vals))  # first index of the maximum
         best_value[g] = vals[b]
         best_x[lo:hi] = zb[:, b]
-    return dict(best_value=best_value, best_x=best_x, traj_best_value=out_vals, traj_best_x=out_z,
-                traj_steps=out_steps)
+    out = dict(best_value=best_value, best_x=best_x, traj_best_value=out_vals, traj_best_x=out_z,
+               traj_steps=out_steps)
+    if p.pool_k:
+        out["pool_value"], out["pool_x"] = pool_value, pool_x
+    return out
