@@ -70,7 +70,7 @@ def step_bytes(g, B, momentum=False):
     return b
 
 
-def cpu_baseline(wl, g, budget_s=15.0):
+def cpu_baseline(wl, g, budget_s=15.0, pool_k=0, final_search=False):
     """The oracle (float32 replay, as used for parity) on a bounded sample of
     the workload: the first graph, whole rounds of the first trajectories,
     sized from a one-round probe to take about budget_s."""
@@ -79,14 +79,15 @@ def cpu_baseline(wl, g, budget_s=15.0):
     def params(rounds):
         return osolver.Params(batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=rounds, alpha=wl.alpha,
                               seed=wl.seed, gamma=wl.gamma, lam=wl.lam, rho=wl.rho, reset_mode=wl.reset_mode,
-                              local_search=wl.local_search)
+                              local_search=wl.local_search, pool_k=pool_k, final_search=final_search)
 
     sub = g.subgraph(0)
+    # the pool couples every trajectory of the graph: then all columns
+    ncols = wl.batch if pool_k else 1
     t0 = time.perf_counter()
-    osolver.solve_graph(wl.problem, sub, params(1), 0, cols=np.arange(1))
+    osolver.solve_graph(wl.problem, sub, params(1), 0, cols=np.arange(ncols))
     probe = time.perf_counter() - t0
     rounds = int(min(wl.rounds, max(1, budget_s // probe)))
-    ncols = 1
     while True:
         t0 = time.perf_counter()
         osolver.solve_graph(wl.problem, sub, params(rounds), 0, cols=np.arange(ncols))
@@ -345,6 +346,10 @@ def main():
     ap.add_argument("--objective", default="", choices=["", "maxcut", "maxcut_fl", "maxcut_fp", "maxcut_fa"],
                     help="MaxCut workloads: the formulation of the steps (default f_B, Eq. (7); f_L, f_P, f_A are "
                          "Eq. (4)-(6))")
+    ap.add_argument("--pool", type=int, default=0,
+                    help="solve mode: pmQO pool of K solutions per graph (Alg. 3 / 4; batched plan)")
+    ap.add_argument("--final-search", action="store_true",
+                    help="solve mode: the paper's own search on the incumbents (or the pool) after the rounds")
     ap.add_argument("--mode", default="solve", choices=["solve", "grad", "unrolled", "pair", "toy"],
                     help="solve: whole batched solves; grad: objective + SpMM gradient over the batch; "
                          "unrolled: K = 20 unrolled PGA steps forward and their adjoint (checkpoints every 5)")
@@ -378,6 +383,10 @@ def main():
         return
     if args.mode != "solve":
         return bench_differentiation(args, wl)
+    if args.pool or args.final_search:
+        import dataclasses
+        tag = (f":pool{args.pool}" if args.pool else "") + (":final" if args.final_search else "")
+        wl = dataclasses.replace(wl, name=wl.name + tag)
     if args.copy_calibration_mb:
         a = torch.empty(args.copy_calibration_mb << 18, dtype=torch.float32, device="cuda:0").fill_(1.0)
         b = torch.empty_like(a)
@@ -390,7 +399,8 @@ def main():
     dev = torch.device("cuda:0")
     dg = mqo.DeviceGraph(g, dev)
     kw = dict(batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=wl.rounds, alpha=wl.alpha, gamma=wl.gamma,
-              lam=wl.lam, rho=wl.rho, reset_mode=wl.reset_mode, local_search=wl.local_search, seed=wl.seed)
+              lam=wl.lam, rho=wl.rho, reset_mode=wl.reset_mode, local_search=wl.local_search, seed=wl.seed,
+              pool_k=args.pool, final_search=args.final_search)
     if args.tile:
         t = [int(v) for v in args.tile.split(",")]
         kw.update(tile_cols=t[0], tile_threads=t[1], tile_vec=t[2], tile_csr=t[3], tile_reg=t[4])
@@ -425,7 +435,7 @@ def main():
                            rho=wl.rho, reset_mode=wl.reset_mode, plan=out["plan"], tile_cols=out["tile_cols"],
                            tile_threads=out["tile_threads"], tile_vec=out["tile_vec"],
                            tile_csr_lds=out["tile_csr_lds"], tile_reg_degree=out["tile_reg_degree"],
-                           parallelism="dp1"))
+                           pool_k=args.pool, final_search=args.final_search, parallelism="dp1"))
 
     # dominant kernel: the launches that run the PGA steps
     steps_per_launch = wl.steps_per_round * wl.rounds / max(1, out["step_kernel_launches"])
@@ -447,7 +457,9 @@ def main():
         res["lds_roofline"] = dict(achieved=lds_bytes / avg_launch_s / 1e9, peak=LDS_PEAK / 1e9, unit="GB/s",
                                    frac=lds_bytes / avg_launch_s / LDS_PEAK, bytes_per_launch=lds_bytes)
 
-    if not args.no_plain:
+    if not args.no_plain and args.pool:
+        log("[bench] no plain comparison: the pool runs on the batched plan only")
+    if not args.no_plain and not args.pool:
         log("[bench] plain per-trajectory solve")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -466,7 +478,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
-        res["cpu_baseline"] = cpu_baseline(wl, g, args.cpu_budget)
+        res["cpu_baseline"] = cpu_baseline(wl, g, args.cpu_budget, args.pool, args.final_search)
         log(f"[bench] cpu oracle {res['cpu_baseline']['value']:.4e} EU/s")
     print(json.dumps(res), flush=True)
 

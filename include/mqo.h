@@ -156,6 +156,21 @@ typedef struct {
                               replaced when strictly better (Alg. 1 / Alg. 2,
                               the local search after the reset loop); runs
                               batched over the B trajectories in every plan */
+  int32_t pool_k;          /* 0 = independent trajectories (default); K in
+                              [1, min(64, batch)]: the pmQO pool of Alg. 3 /
+                              Alg. 4 -- after every round the K best distinct
+                              solutions of the pool and the round's
+                              candidates (MIS: independent sets only) form the
+                              pool, ranked by value, ties to the earlier
+                              (pool slots, then trajectories); duplicates are
+                              recognised by value and a 64-bit SplitMix64 sum
+                              hash of the set; round r > 0 restarts
+                              trajectory t from slot (u K') >> 32 of the pool
+                              (K' filled slots, u the Philox draw (seed, 8)
+                              for counter (0, t, r, 0)).  The answer is then
+                              the best pool member and final_search searches
+                              the pool members (trajectory ids g K + slot).
+                              Batched plan only (MQO_ERR_UNSUPPORTED else)  */
 } mqo_params;
 
 /* Outputs of a solve.  Device arrays are written; host fields are set. */
@@ -185,6 +200,10 @@ typedef struct {
   int64_t step_kernel_launches;/* (host) number of such launches            */
   int64_t final_search_alternations; /* (host) final_search: pair iterations
                                   that applied a move (largest over graphs) */
+  int8_t *pool_x;              /* [n_total*K] pool solutions (pool_k > 0), or
+                                  NULL; empty slots are zeros               */
+  int64_t *pool_value;         /* [G*K] pool values, INT64_MIN = empty slot,
+                                  or NULL                                   */
 } mqo_result;
 
 void mqo_params_default(mqo_params *p);

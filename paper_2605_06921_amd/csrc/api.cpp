@@ -169,6 +169,10 @@ int check_params(const mqo_params *p, mqo_objective obj) {
     return fail(MQO_ERR_INVALID_ARG, "bad local_search");
   if (p->final_search != MQO_FINAL_NONE && p->final_search != MQO_FINAL_PAIR)
     return fail(MQO_ERR_INVALID_ARG, "bad final_search");
+  if (p->pool_k < 0 || p->pool_k > 64 || p->pool_k > p->batch)
+    return fail(MQO_ERR_INVALID_ARG, "pool_k must be in [0, min(64, batch)]");
+  if (p->pool_k > 0 && (p->plan == MQO_PLAN_PERSISTENT || p->plan == MQO_PLAN_PLAIN))
+    return fail(MQO_ERR_UNSUPPORTED, "the pool couples the trajectories of a graph: batched plan only");
   if (p->plan < MQO_PLAN_AUTO || p->plan > MQO_PLAN_PERSISTENT) return fail(MQO_ERR_INVALID_ARG, "bad plan");
   if (p->tile_cols != 0 && (p->tile_cols < 1 || p->tile_cols > 64 || (p->tile_cols & (p->tile_cols - 1))))
     return fail(MQO_ERR_INVALID_ARG, "tile_cols must be 0 or a power of two <= 64");
@@ -193,10 +197,12 @@ int64_t max_graph_rows(const mqo_graph *g) {
 // ---------------------------------------------------------------------------
 struct Layout {
   size_t X, Xt, V, Z, Zb, NB, PRIO, F, value, best, acc, act, voff, rpat, bestb, dmax, err, reset, tzs, tnb, tprio,
-      tfl, tvm, tls, pX, pXt, pV, colact, fixedc, steps, total;
+      tfl, tvm, tls, pX, pXt, pV, colact, fixedc, steps, pz[2], pv[2], ph[2], chash, ptaken, psrc, pbase, total;
 };
 
-Layout make_layout(const mqo_graph *g, int32_t B) {
+// K: pool slots per graph (0 = no pool); the pool buffers come last, so the
+// other offsets do not depend on K
+Layout make_layout(const mqo_graph *g, int32_t B, int32_t K = 0) {
   Layout L{};
   const int64_t n = g->n_total, G = g->num_graphs, nb = n * B;
   const int64_t tiles_elems = G * (int64_t)(B + 63) * max_graph_rows(g);  // tile scratch, any T <= 64
@@ -236,6 +242,15 @@ Layout make_layout(const mqo_graph *g, int32_t B) {
   L.colact = take(G * B);  // early exit: trajectory still stepping in this round
   L.fixedc = take(B);      // early exit: rounded point fixed (per column of one graph)
   L.steps = take(G * B * 8);  // PGA steps each trajectory executed
+  for (int i = 0; i < 2; ++i) {  // pool, double buffered across rounds
+    L.pz[i] = take(n * K);
+    L.pv[i] = take(G * K * 8);
+    L.ph[i] = take(G * K * 8);
+  }
+  L.chash = take(K ? G * B * 8 : 0);
+  L.ptaken = take(K ? K + B : 0);
+  L.psrc = take(G * K * 4);
+  L.pbase = take(K ? G * B * 4 : 0);
   L.total = o;
   return L;
 }
@@ -640,14 +655,16 @@ double now_s() {
 // colact: the columns' early-exit flags; its address is recorded in the
 // captured step loops, so a loop shared by several trajectories (plain
 // plan) gets one fixed slot
+// Zp / base_slot: the pool this round restarts from (nullptr: incumbents)
 int grid_round(Solve &S, StepLoop &loop, bool use_graph, const GraphView &gv, int32_t r, float *X, float *Xt,
                float *V, int8_t *Z, int8_t *Zb, int32_t ldb, int32_t *NB, uint32_t *PRIO, int8_t *F, int64_t *value,
-               int64_t *best, int32_t ncols, int32_t ld, uint64_t traj0, int8_t *colact) {
+               int64_t *best, int32_t ncols, int32_t ld, uint64_t traj0, int8_t *colact, const int8_t *Zp = nullptr,
+               int32_t ldp = 0, const int32_t *base_slot = nullptr) {
   int64_t *steps_ctr = at<int64_t>(S.ws, S.L.steps) + traj0;
   const bool mom = S.p->momentum != 0.0f;
   if (r > 0) {
     launch_reset(S.maxcut, Zb, ldb, nullptr, X, mom ? V : nullptr, gv.lo, gv.n, ncols, ld, S.p->seed, traj0,
-                 (uint64_t)r, k_of(S, gv.n), S.p->reset_mode, at<void>(S.ws, S.L.reset), S.s);
+                 (uint64_t)r, k_of(S, gv.n), S.p->reset_mode, at<void>(S.ws, S.L.reset), S.s, Zp, ldp, base_slot);
   } else if (mom) {
     launch_fill_f32(V + gv.lo * ld, gv.n * ld, 0.0f, S.s);
   }
@@ -683,6 +700,8 @@ int solve_batched(Solve &S, int32_t *rounds_done) {
     TRY(init_x(S, X));
   const bool use_graph = S.G <= 16 && S.p->steps_per_round >= 4;
   std::vector<StepLoop> loops(S.G);
+  const int32_t K = S.p->pool_k;
+  if (K) launch_fill_i64(at<int64_t>(S.ws, S.L.pv[0]), (int64_t)S.G * K, INT64_MIN, S.s);  // empty pool
   const double t0 = now_s();
   int32_t r = 0;
   for (r = 0; r < S.p->rounds; ++r) {
@@ -690,13 +709,29 @@ int solve_batched(Solve &S, int32_t *rounds_done) {
       HIP_TRY(hipStreamSynchronize(S.s));
       if (now_s() - t0 >= S.p->time_budget_s) break;
     }
+    const int cur = r & 1, nxt = cur ^ 1;
     for (int32_t gi = 0; gi < S.G; ++gi) {
       const GraphView gv = view_of(S.g, gi, S.max_deg);
       const int64_t t = (int64_t)gi * B;
+      const int8_t *Zp = nullptr;
+      int32_t *base = nullptr;
+      if (K && r > 0) {
+        Zp = at<int8_t>(S.ws, S.L.pz[cur]);
+        base = at<int32_t>(S.ws, S.L.pbase) + t;
+        launch_pool_bases(at<int64_t>(S.ws, S.L.pv[cur]) + (int64_t)gi * K, K, B, S.p->seed, (uint64_t)t,
+                          (uint64_t)r, base, S.s);
+      }
       TRY(grid_round(S, loops[gi], use_graph, gv, r, X, Xt, V, Z, Zb, B, NB, PRIO, F, value + t, best + t, B, B,
-                     (uint64_t)t, at<int8_t>(S.ws, S.L.colact) + t));
+                     (uint64_t)t, at<int8_t>(S.ws, S.L.colact) + t, Zp, K, base));
+      if (K)
+        launch_pool_update(S.maxcut, Z, B, gv.lo, gv.n, gi, B, K, value, at<unsigned long long>(S.ws, S.L.chash),
+                           at<int8_t>(S.ws, S.L.ptaken), at<int8_t>(S.ws, S.L.pz[cur]),
+                           at<int64_t>(S.ws, S.L.pv[cur]), at<unsigned long long>(S.ws, S.L.ph[cur]),
+                           at<int8_t>(S.ws, S.L.pz[nxt]), at<int64_t>(S.ws, S.L.pv[nxt]),
+                           at<unsigned long long>(S.ws, S.L.ph[nxt]), at<int32_t>(S.ws, S.L.psrc), S.s);
     }
   }
+  HIP_TRY(hipGetLastError());
   *rounds_done = r;
   return MQO_OK;
 }
@@ -766,6 +801,7 @@ bool tile_feasible(const Solve &S, const TileCfg &c) {
 // any shape at all fits (plan selection)
 bool tile_possible(const Solve &S) {
   if (S.form != OBJ_H && S.form != OBJ_FB) return false;  // the persistent kernel runs h and f_B
+  if (S.p->pool_k > 0) return false;                      // the pool needs every trajectory between rounds
   for (int T = 1; T <= 64; T <<= 1)
     for (int th : {256, 512, 1024})
       if (tile_feasible(S, TileCfg{T, th, 1, 0, 0, 0})) return true;
@@ -1006,13 +1042,41 @@ int final_search(Solve &S, int64_t *alternations) {
   return MQO_OK;
 }
 
+// Alg. 4 step 13 (and Alg. 3 step 13 on every member): the pair search on
+// every pool member (trajectory ids g K + slot, round index = rounds),
+// replacing a member when strictly better; empty slots are never taken.
+int final_search_pool(Solve &S, int8_t *PZ, int64_t *PV, int64_t *alternations) {
+  const int32_t K = S.p->pool_k;
+  int8_t *Z = at<int8_t>(S.ws, S.L.Z);
+  int64_t *value = at<int64_t>(S.ws, S.L.value);
+  HIP_TRY(hipMemcpyAsync(Z, PZ, (size_t)S.g->n_total * K, hipMemcpyDeviceToDevice, S.s));
+  TRY(pair_core(S.maxcut, S.g, S.p->seed, S.p->rounds, Z, at<int32_t>(S.ws, S.L.NB), at<uint32_t>(S.ws, S.L.PRIO),
+                at<uint32_t>(S.ws, S.L.tprio), at<int8_t>(S.ws, S.L.F), at<int32_t>(S.ws, S.L.act),
+                at<long long>(S.ws, S.L.acc), value, at<int32_t>(S.ws, S.L.X), at<int32_t>(S.ws, S.L.Xt),
+                at<int32_t>(S.ws, S.L.V), at<uint32_t>(S.ws, S.L.tnb), K, S.s, &S.ls_iters, alternations, nullptr));
+  for (int32_t gi = 0; gi < S.G; ++gi) {
+    const GraphView gv = view_of(S.g, gi, S.max_deg);
+    const int64_t t = (int64_t)gi * K;
+    launch_evaluate(S.maxcut, gv, Z, at<int32_t>(S.ws, S.L.NB), at<long long>(S.ws, S.L.acc), value + t, nullptr,
+                    nullptr, K, K, S.s);
+  }
+  launch_mask_empty(value, PV, (int64_t)S.G * K, S.s);
+  for (int32_t gi = 0; gi < S.G; ++gi) {
+    const GraphView gv = view_of(S.g, gi, S.max_deg);
+    const int64_t t = (int64_t)gi * K;
+    launch_accept(Z, PZ, value + t, PV + t, gv.lo, gv.n, K, K, K, false, S.s);
+  }
+  HIP_TRY(hipGetLastError());
+  return MQO_OK;
+}
+
 int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_result *r, void *ws, size_t ws_bytes,
                  void *stream, mqo_objective obj) {
   TRY(check_graph_args(g, obj == MQO_OBJ_MIS_H));
   if (!p) return fail(MQO_ERR_INVALID_ARG, "params is NULL");
   TRY(check_params(p, obj == MQO_OBJ_MIS_H ? obj : (mqo_objective)p->maxcut_objective));
   if (!r || !r->best_x || !r->best_value) return fail(MQO_ERR_INVALID_ARG, "result arrays best_x/best_value required");
-  const Layout L = make_layout(g, p->batch);
+  const Layout L = make_layout(g, p->batch, p->pool_k);
   if (!ws || ws_bytes < L.total) return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", L.total);
   TRY(ensure_resources());
   std::lock_guard<std::mutex> host_lock(res().host_mu);
@@ -1066,12 +1130,29 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
   else
     TRY(solve_plain(S, &rounds_done));
   int64_t final_alt = 0;
-  if (p->final_search == MQO_FINAL_PAIR) TRY(final_search(S, &final_alt));
+  const int32_t K = p->pool_k;
+  const int pool_buf = rounds_done & 1;  // the pool after the last round
+  int8_t *PZ = K ? at<int8_t>(ws, L.pz[pool_buf]) : nullptr;
+  int64_t *PV = K ? at<int64_t>(ws, L.pv[pool_buf]) : nullptr;
+  if (p->final_search == MQO_FINAL_PAIR) {
+    if (K)
+      TRY(final_search_pool(S, PZ, PV, &final_alt));
+    else
+      TRY(final_search(S, &final_alt));
+  }
 
   int64_t *best = at<int64_t>(ws, L.best);
   int32_t *bestb = at<int32_t>(ws, L.bestb);
-  launch_pick_best(best, S.G, S.B, r->best_value, bestb, s);
-  launch_copy_best_x(at<int8_t>(ws, L.Zb), S.B, voff, S.G, bestb, r->best_x, g->n_total, s);
+  if (K) {  // the answer is the best pool member
+    launch_pick_best(PV, S.G, K, r->best_value, bestb, s);
+    launch_copy_best_x(PZ, K, voff, S.G, bestb, r->best_x, g->n_total, s);
+    if (r->pool_x) HIP_TRY(hipMemcpyAsync(r->pool_x, PZ, (size_t)g->n_total * K, hipMemcpyDeviceToDevice, s));
+    if (r->pool_value)
+      HIP_TRY(hipMemcpyAsync(r->pool_value, PV, (size_t)S.G * K * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+  } else {
+    launch_pick_best(best, S.G, S.B, r->best_value, bestb, s);
+    launch_copy_best_x(at<int8_t>(ws, L.Zb), S.B, voff, S.G, bestb, r->best_x, g->n_total, s);
+  }
   if (r->traj_best_value)
     HIP_TRY(hipMemcpyAsync(r->traj_best_value, best, (size_t)S.G * S.B * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
   if (r->traj_best_x)
@@ -1162,11 +1243,12 @@ void mqo_params_default(mqo_params *p) {
   p->time_budget_s = 0.0;
   p->maxcut_objective = MQO_OBJ_MAXCUT_FB;
   p->final_search = MQO_FINAL_NONE;
+  p->pool_k = 0;
 }
 
 size_t mqo_workspace_size(const mqo_graph *g, const mqo_params *p, mqo_objective obj) {
   if (check_graph_args(g, obj == MQO_OBJ_MIS_H) != MQO_OK || !p || p->batch < 1) return 0;
-  return make_layout(g, p->batch).total;
+  return make_layout(g, p->batch, p->pool_k >= 0 && p->pool_k <= 64 ? p->pool_k : 0).total;
 }
 
 int mqo_solve_mis(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_result *r, void *ws,

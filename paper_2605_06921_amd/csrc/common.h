@@ -20,7 +20,8 @@ enum : uint64_t {
   PURPOSE_NOISE = 4,
   PURPOSE_SWAP = 5,
   PURPOSE_TOY_RESET = 6,
-  PURPOSE_TOY_START = 7
+  PURPOSE_TOY_START = 7,
+  PURPOSE_POOL = 8
 };
 
 __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {

@@ -1121,12 +1121,16 @@ __global__ __launch_bounds__(256) void k_reset_ties(SelState *st, const uint32_t
   }
 }
 
+// base: per column the pool slot to start from (or -1 / nullptr: the
+// column's own incumbent in Zb)
 template <bool MAXCUT>
 __global__ __launch_bounds__(256) void k_reset_apply(const SelState *__restrict__ st, const uint32_t *__restrict__ keys,
                                                      const int8_t *__restrict__ Zb, float *__restrict__ X,
                                                      float *__restrict__ V, int64_t lo, int64_t n, int32_t ncols,
                                                      int32_t ld, int32_t ldb, uint64_t seed, uint64_t traj0,
-                                                     uint64_t round, int32_t k, int32_t mode) {
+                                                     uint64_t round, int32_t k, int32_t mode,
+                                                     const int8_t *__restrict__ Zp, int32_t ldp,
+                                                     const int32_t *__restrict__ base_slot) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nvb = (n + 7) >> 3;
   if (idx >= nvb * ncols) return;
@@ -1135,11 +1139,12 @@ __global__ __launch_bounds__(256) void k_reset_apply(const SelState *__restrict_
   uint32_t r[8];
   if (k > 0 && !keys) philox_block8(r, seed, PURPOSE_RESET, traj0 + c, round, (uint64_t)vb);
   SelState s = k > 0 ? st[c] : SelState{0u, 0u, 0u, 0u};
+  const int32_t bs = base_slot ? base_slot[c] : -1;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int64_t v = vb * 8 + i;
     if (v >= n) break;
-    const float base = (float)Zb[(lo + v) * ldb + c];
+    const float base = (float)(bs >= 0 ? Zp[(lo + v) * ldp + bs] : Zb[(lo + v) * ldb + c]);
     float x = base;
     if (k > 0) {
       const uint32_t key = keys ? keys[(lo + v) * ld + c] : r[i];
@@ -1149,6 +1154,151 @@ __global__ __launch_bounds__(256) void k_reset_apply(const SelState *__restrict_
     X[(lo + v) * ld + c] = x;
     if (V) V[(lo + v) * ld + c] = 0.0f;
   }
+}
+
+// ---------------------------------------------------------------------------
+// the pmQO pool (Alg. 3 / Alg. 4): top-K distinct solutions per graph
+// ---------------------------------------------------------------------------
+// SplitMix64 output for state x (Steele, Lea and Flood, OOPSLA 2014).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// H[c] += sum over the rows v of [lo, lo + n) with Z[v][c] > 0 of
+// splitmix64(v - lo), mod 2^64 (H cleared by the caller).  Thread per
+// (chunk of 256 rows, column); the additions commute, so the sum is exact.
+__global__ __launch_bounds__(256) void k_col_hash(const int8_t *__restrict__ Z, int64_t lo, int64_t n, int32_t ncols,
+                                                  int32_t ld, unsigned long long *__restrict__ H) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t chunks = (n + 255) >> 8;
+  if (idx >= chunks * ncols) return;
+  const int32_t c = (int32_t)(idx % ncols);
+  const int64_t r0 = (idx / ncols) << 8;
+  const int64_t r1 = r0 + 256 < n ? r0 + 256 : n;
+  uint64_t h = 0;
+  for (int64_t v = r0; v < r1; ++v)
+    if (Z[(lo + v) * ld + c] > 0) h += splitmix64((uint64_t)v);
+  if (h) atomicAdd(H + c, (unsigned long long)h);
+}
+
+// One workgroup per graph.  Candidates i < K: the old pool's slots (empty
+// = INT64_MIN); i >= K: the round's columns (MIS: value -1 = not a
+// solution).  K times: the valid, untaken candidate of largest (value,
+// -i) fills the next slot, and every candidate with its (value, hash) is
+// taken (the union is a set).  SRC[k] = i of slot k or -1.
+__global__ __launch_bounds__(256) void k_pool_select(const int64_t *__restrict__ pv_old,
+                                                     const unsigned long long *__restrict__ ph_old,
+                                                     const int64_t *__restrict__ value,
+                                                     const unsigned long long *__restrict__ hash, int32_t K,
+                                                     int32_t B, int32_t mis, int8_t *__restrict__ taken,
+                                                     int64_t *__restrict__ pv_new,
+                                                     unsigned long long *__restrict__ ph_new,
+                                                     int32_t *__restrict__ src) {
+  __shared__ int64_t sv[4];
+  __shared__ int32_t si[4];
+  __shared__ int64_t wv;
+  __shared__ unsigned long long wh;
+  __shared__ int32_t wi;
+  const int32_t g = blockIdx.x;
+  const int32_t N = K + B;
+  pv_old += (int64_t)g * K;
+  ph_old += (int64_t)g * K;
+  value += (int64_t)g * B;
+  hash += (int64_t)g * B;
+  taken += (int64_t)g * N;
+  auto cand_v = [&](int32_t i) { return i < K ? pv_old[i] : value[i - K]; };
+  auto cand_h = [&](int32_t i) { return i < K ? ph_old[i] : hash[i - K]; };
+  auto valid = [&](int32_t i) {
+    const int64_t v = cand_v(i);
+    return i < K ? v != INT64_MIN : !(mis && v < 0);
+  };
+  for (int32_t i = threadIdx.x; i < N; i += blockDim.x) taken[i] = valid(i) ? 0 : 1;
+  __syncthreads();
+  for (int32_t k = 0; k < K; ++k) {
+    int64_t bv = INT64_MIN;
+    int32_t bi = 0x7fffffff;
+    for (int32_t i = threadIdx.x; i < N; i += blockDim.x) {
+      if (taken[i]) continue;
+      const int64_t v = cand_v(i);
+      if (bi == 0x7fffffff || v > bv) {  // i ascends within the thread
+        bv = v;
+        bi = i;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const int64_t ov = __shfl_down(bv, off, 64);
+      const int32_t oi = __shfl_down(bi, off, 64);
+      if (oi != 0x7fffffff && (bi == 0x7fffffff || ov > bv || (ov == bv && oi < bi))) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if ((threadIdx.x & 63) == 0) {
+      sv[threadIdx.x >> 6] = bv;
+      si[threadIdx.x >> 6] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+        if (si[w] != 0x7fffffff && (bi == 0x7fffffff || sv[w] > bv || (sv[w] == bv && si[w] < bi))) {
+          bv = sv[w];
+          bi = si[w];
+        }
+      wi = bi;
+      wv = bv;
+      if (bi != 0x7fffffff) {
+        wh = cand_h(bi);
+        pv_new[(int64_t)g * K + k] = bv;
+        ph_new[(int64_t)g * K + k] = wh;
+        src[(int64_t)g * K + k] = bi;
+      } else {
+        pv_new[(int64_t)g * K + k] = INT64_MIN;
+        ph_new[(int64_t)g * K + k] = 0;
+        src[(int64_t)g * K + k] = -1;
+      }
+    }
+    __syncthreads();
+    if (wi != 0x7fffffff)
+      for (int32_t i = threadIdx.x; i < N; i += blockDim.x)
+        if (!taken[i] && cand_v(i) == wv && cand_h(i) == wh) taken[i] = 1;
+    __syncthreads();
+  }
+}
+
+// New pool solutions of one graph: slot k <- old slot SRC[k] (< K), column
+// SRC[k] - K of Z, or zeros (empty).
+__global__ __launch_bounds__(256) void k_pool_copy(const int8_t *__restrict__ pz_old, const int8_t *__restrict__ Z,
+                                                   const int32_t *__restrict__ src, int8_t *__restrict__ pz_new,
+                                                   int64_t lo, int64_t n, int32_t K, int32_t ld) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * K) return;
+  const int64_t v = lo + idx / K;
+  const int32_t k = (int32_t)(idx % K);
+  const int32_t s = src[k];
+  pz_new[v * K + k] = s < 0 ? (int8_t)0 : s < K ? pz_old[v * K + s] : Z[v * ld + (s - K)];
+}
+
+// Pool slot each trajectory restarts from: (u * size) >> 32, u the Philox
+// draw of purpose POOL for (trajectory, round), lane 0; -1 if empty.
+__global__ void k_pool_bases(const int64_t *__restrict__ pv, int32_t K, int32_t ncols, uint64_t seed,
+                             uint64_t traj0, uint64_t round, int32_t *__restrict__ base) {
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  int32_t size = 0;
+  for (int32_t k = 0; k < K; ++k) size += pv[k] != INT64_MIN;
+  uint32_t r[8];
+  philox_block8(r, seed, PURPOSE_POOL, traj0 + c, round, 0);
+  base[c] = size ? (int32_t)(((uint64_t)r[0] * (uint64_t)size) >> 32) : -1;
+}
+
+// value[k] = INT64_MIN where the pool slot is empty (so a search of an empty
+// slot is never accepted)
+__global__ void k_mask_empty(int64_t *__restrict__ value, const int64_t *__restrict__ pv, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count && pv[i] == INT64_MIN) value[i] = INT64_MIN;
 }
 
 // ---------------------------------------------------------------------------
@@ -1190,8 +1340,9 @@ __global__ __launch_bounds__(256) void k_pick_best(const int64_t *__restrict__ b
         bv = sv[w];
         bb = sb[w];
       }
-    best_value[g] = bv;
-    best_b[g] = bb;
+    // nothing but empty pool slots: no answer (-1), slot 0
+    best_value[g] = bv == INT64_MIN ? -1 : bv;
+    best_b[g] = bb == 0x7fffffff ? 0 : bb;
   }
 }
 
@@ -1877,7 +2028,7 @@ size_t reset_scratch_bytes(int32_t ncols) { return (size_t)ncols * (sizeof(SelSt
 
 void launch_reset(bool maxcut, const int8_t *Zb, int32_t ldb, const uint32_t *keys, float *X, float *V, int64_t lo,
                   int64_t n, int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0, uint64_t round, int32_t k,
-                  int32_t mode, void *scratch, hipStream_t s) {
+                  int32_t mode, void *scratch, hipStream_t s, const int8_t *Zp, int32_t ldp, const int32_t *base_slot) {
   SelState *st = reinterpret_cast<SelState *>(scratch);
   uint32_t *hist = reinterpret_cast<uint32_t *>(st + ncols);
   const int64_t cnt = ((n + 7) >> 3) * ncols;
@@ -1893,10 +2044,36 @@ void launch_reset(bool maxcut, const int8_t *Zb, int32_t ldb, const uint32_t *ke
   }
   if (maxcut)
     MQO_LAUNCH(k_reset_apply<true>, dim3(blocks_for(cnt)), dim3(256), 0, s, st, keys, Zb, X, V, lo, n, ncols, ld, ldb,
-               seed, traj0, round, k, mode);
+               seed, traj0, round, k, mode, Zp, ldp, base_slot);
   else
     MQO_LAUNCH(k_reset_apply<false>, dim3(blocks_for(cnt)), dim3(256), 0, s, st, keys, Zb, X, V, lo, n, ncols, ld,
-               ldb, seed, traj0, round, k, mode);
+               ldb, seed, traj0, round, k, mode, Zp, ldp, base_slot);
+}
+
+void launch_pool_update(bool maxcut, const int8_t *Z, int32_t ld, int64_t lo, int64_t n, int32_t g, int32_t B,
+                        int32_t K, const int64_t *value, unsigned long long *hash, int8_t *taken,
+                        const int8_t *pz_old, const int64_t *pv_old, const unsigned long long *ph_old,
+                        int8_t *pz_new, int64_t *pv_new, unsigned long long *ph_new, int32_t *src, hipStream_t s) {
+  // hashes of the round's columns of graph g
+  MQO_LAUNCH(k_fill_i64, dim3(blocks_for(B)), dim3(256), 0, s, reinterpret_cast<int64_t *>(hash + (int64_t)g * B),
+             (int64_t)B, (int64_t)0);
+  MQO_LAUNCH(k_col_hash, dim3(blocks_for(((n + 255) >> 8) * B)), dim3(256), 0, s, Z, lo, n, B, ld,
+             hash + (int64_t)g * B);
+  // one workgroup: graph g's selection (pointers offset to g inside)
+  MQO_LAUNCH(k_pool_select, dim3(1), dim3(256), 0, s, pv_old + (int64_t)g * K, ph_old + (int64_t)g * K,
+             value + (int64_t)g * B, hash + (int64_t)g * B, K, B, maxcut ? 0 : 1, taken, pv_new + (int64_t)g * K,
+             ph_new + (int64_t)g * K, src + (int64_t)g * K);
+  MQO_LAUNCH(k_pool_copy, dim3(blocks_for(n * K)), dim3(256), 0, s, pz_old, Z, src + (int64_t)g * K, pz_new, lo, n,
+             K, ld);
+}
+
+void launch_pool_bases(const int64_t *pv, int32_t K, int32_t ncols, uint64_t seed, uint64_t traj0, uint64_t round,
+                       int32_t *base, hipStream_t s) {
+  MQO_LAUNCH(k_pool_bases, dim3(blocks_for(ncols)), dim3(256), 0, s, pv, K, ncols, seed, traj0, round, base);
+}
+
+void launch_mask_empty(int64_t *value, const int64_t *pv, int64_t count, hipStream_t s) {
+  MQO_LAUNCH(k_mask_empty, dim3(blocks_for(count)), dim3(256), 0, s, value, pv, count);
 }
 
 void launch_pick_best(const int64_t *best, int32_t G, int32_t B, int64_t *best_value, int32_t *best_b,

@@ -70,9 +70,24 @@ void launch_pair_apply(bool maxcut, const GraphView &g, int8_t *Z, int32_t *NB, 
 void launch_accept(const int8_t *Z, int8_t *Zb, const int64_t *value, int64_t *best, int64_t lo, int64_t n,
                    int32_t ncols, int32_t ld, int32_t ldb, bool first, hipStream_t s);
 size_t reset_scratch_bytes(int32_t ncols);
+// Zp / base_slot (optional): column c starts from pool slot base_slot[c] of
+// Zp ([n][ldp]) instead of its incumbent when base_slot[c] >= 0
 void launch_reset(bool maxcut, const int8_t *Zb, int32_t ldb, const uint32_t *keys, float *X, float *V, int64_t lo,
                   int64_t n, int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0, uint64_t round, int32_t k,
-                  int32_t mode, void *scratch, hipStream_t s);
+                  int32_t mode, void *scratch, hipStream_t s, const int8_t *Zp = nullptr, int32_t ldp = 0,
+                  const int32_t *base_slot = nullptr);
+// pmQO pool of graph g (rows [lo, lo + n)): TopK of the old pool
+// (pz_old [n_total][K], pv_old / ph_old [G][K]) united with the round's
+// columns of Z (values value [G][B]) into pz_new / pv_new / ph_new.  hash:
+// [G][B] scratch, taken: K + B bytes, src: [G][K].
+void launch_pool_update(bool maxcut, const int8_t *Z, int32_t ld, int64_t lo, int64_t n, int32_t g, int32_t B,
+                        int32_t K, const int64_t *value, unsigned long long *hash, int8_t *taken,
+                        const int8_t *pz_old, const int64_t *pv_old, const unsigned long long *ph_old,
+                        int8_t *pz_new, int64_t *pv_new, unsigned long long *ph_new, int32_t *src, hipStream_t s);
+// base slot of every column of a graph (pv: its K pool values)
+void launch_pool_bases(const int64_t *pv, int32_t K, int32_t ncols, uint64_t seed, uint64_t traj0, uint64_t round,
+                       int32_t *base, hipStream_t s);
+void launch_mask_empty(int64_t *value, const int64_t *pv, int64_t count, hipStream_t s);
 void launch_pick_best(const int64_t *best, int32_t G, int32_t B, int64_t *best_value, int32_t *best_b, hipStream_t s);
 void launch_copy_best_x(const int8_t *Zb, int32_t B, const int64_t *voff, int32_t G, const int32_t *best_b,
                         int8_t *out, int64_t n_total, hipStream_t s);

@@ -51,7 +51,7 @@ class _Params(ctypes.Structure):
                 ("tile_cols", ctypes.c_int32), ("tile_threads", ctypes.c_int32), ("tile_vec", ctypes.c_int32),
                 ("tile_csr", ctypes.c_int32), ("tile_reg", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("time_budget_s", ctypes.c_double), ("maxcut_objective", ctypes.c_int32),
-                ("final_search", ctypes.c_int32)]
+                ("final_search", ctypes.c_int32), ("pool_k", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -63,7 +63,8 @@ class _Result(ctypes.Structure):
                 ("tile_csr_lds_used", ctypes.c_int32), ("tile_reg_degree_used", ctypes.c_int32),
                 ("ls_iterations", ctypes.c_int64),
                 ("step_kernel_ms", ctypes.c_double), ("step_kernel_launches", ctypes.c_int64),
-                ("final_search_alternations", ctypes.c_int64)]
+                ("final_search_alternations", ctypes.c_int64), ("pool_x", ctypes.c_void_p),
+                ("pool_value", ctypes.c_void_p)]
 
 
 def _load():
@@ -213,7 +214,7 @@ def last_error() -> str:
 def make_params(batch=1, steps_per_round=200, rounds=1, alpha=0.01, momentum=0.0, gamma=2.0, lam=1e-3,
                 rho=0.05, init_sigma=0.0, init_mode="uniform", reset_mode="zero", local_search=True,
                 plan="auto", seed=0, time_budget_s=0.0, tile_cols=0, tile_threads=0, tile_vec=0, tile_csr=0,
-                tile_reg=0, check_every=0, final_search=False) -> _Params:
+                tile_reg=0, check_every=0, final_search=False, pool_k=0) -> _Params:
     p = _Params()
     _lib.mqo_params_default(ctypes.byref(p))
     p.batch, p.steps_per_round, p.rounds, p.check_every = batch, steps_per_round, rounds, check_every
@@ -226,6 +227,7 @@ def make_params(batch=1, steps_per_round=200, rounds=1, alpha=0.01, momentum=0.0
     p.tile_reg = tile_reg
     p.seed, p.time_budget_s = seed, time_budget_s
     p.final_search = 1 if final_search else 0
+    p.pool_k = pool_k
     return p
 
 
@@ -282,6 +284,11 @@ def solve(kind, dg: DeviceGraph, x0: Optional[torch.Tensor] = None, workspace: O
         x0 = x0.contiguous()
     r = _Result(best_x.data_ptr(), best_value.data_ptr(), None if traj_v is None else traj_v.data_ptr(),
                 None if traj_x is None else traj_x.data_ptr())
+    K = p.pool_k
+    pool_x = torch.empty(dg.n * K, dtype=torch.int8, device=dev) if K else None
+    pool_v = torch.empty(G * K, dtype=torch.int64, device=dev) if K else None
+    if K:
+        r.pool_x, r.pool_value = pool_x.data_ptr(), pool_v.data_ptr()
     fn = _lib.mqo_solve_mis if k == MIS else _lib.mqo_solve_maxcut
     _check(fn(dg.struct, ctypes.byref(p), _ptr(x0), ctypes.byref(r), ctypes.c_void_p(ws.data_ptr()), nbytes,
               _stream(dev)), "mqo_solve")
@@ -295,6 +302,9 @@ def solve(kind, dg: DeviceGraph, x0: Optional[torch.Tensor] = None, workspace: O
     if want_traj:
         out["traj_best_value"] = traj_v
         out["traj_best_x"] = traj_x.view(dg.n, B)
+    if K:
+        out["pool_value"] = pool_v
+        out["pool_x"] = pool_x.view(dg.n, K)
     return out
 
 

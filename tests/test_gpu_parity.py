@@ -752,3 +752,34 @@ def test_solve_final_search_bit_exact(mqo, kind, plan):
     assert np.array_equal(out["best_value"].cpu().numpy(), ref["best_value"])
     base = solver.solve(kind, g, solver.Params(**kw))
     assert np.all(ref["traj_best_value"] >= base["traj_best_value"])
+
+
+# --------------------------------------------------------------------------
+# the pmQO pool (Alg. 3 / Alg. 4)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", ["mis", "maxcut"])
+@pytest.mark.parametrize("K,B,final", [(1, 4, False), (3, 8, True), (8, 8, False), (5, 33, True)])
+def test_pool_solve_bit_exact(mqo, kind, K, B, final):
+    g = CASES["er_batch"][1] if kind == "mis" else CASES["cut_batch"][1]
+    kw = dict(batch=B, steps_per_round=25, rounds=4, alpha=0.05, rho=0.15, seed=61 + K, pool_k=K,
+              final_search=final, reset_mode="flip" if K == 3 else "zero")
+    out = mqo.solve(kind, mqo.DeviceGraph(g, DEV), **kw)
+    assert out["plan"] == "batched"
+    ref = solver.solve(kind, g, solver.Params(**kw))
+    assert np.array_equal(out["traj_best_value"].cpu().numpy(), ref["traj_best_value"])
+    assert np.array_equal(out["traj_best_x"].cpu().numpy(), ref["traj_best_x"])
+    assert np.array_equal(out["pool_value"].cpu().numpy(), ref["pool_value"])
+    assert np.array_equal(out["pool_x"].cpu().numpy(), ref["pool_x"])
+    assert np.array_equal(out["best_value"].cpu().numpy(), ref["best_value"])
+    assert np.array_equal(out["best_x"].cpu().numpy(), ref["best_x"])
+
+
+def test_pool_rejected_where_not_offered(mqo):
+    dg = mqo.DeviceGraph(CASES["reg3"][1], DEV)
+    for plan in ("persistent", "plain"):
+        with pytest.raises(mqo.MqoError) as e:
+            mqo.solve("maxcut", dg, batch=4, steps_per_round=4, pool_k=2, plan=plan)
+        assert e.value.status == -5
+    with pytest.raises(mqo.MqoError):
+        mqo.solve("maxcut", dg, batch=4, steps_per_round=4, pool_k=5)
