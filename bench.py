@@ -32,7 +32,9 @@ HBM_PEAK = 8.0e12  # bytes/s, MI355X
 LDS_PEAK = 256 * 128 * 2.4e9
 KERNEL_SOURCES = {"k_tile_round": "paper_2605_06921_amd/csrc/tile_kernel.hip",
                   "k_pga_step": "paper_2605_06921_amd/csrc/grid_kernels.hip",
-                  "k_objective_grad": "paper_2605_06921_amd/csrc/grid_kernels.hip"}
+                  "k_objective_grad": "paper_2605_06921_amd/csrc/grid_kernels.hip",
+                  "k_flip2_best": "paper_2605_06921_amd/csrc/grid_kernels.hip",
+                  "k_swap_propose": "paper_2605_06921_amd/csrc/grid_kernels.hip"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
@@ -187,9 +189,10 @@ def bench_pair(args, wl):
     csr = 4 * (g.n + 1) + 4 * g.nnz + (4 * g.nnz if g.weight is not None else 0)
     per_launch = csr + (21 if kind == "maxcut" else 17) * g.n * B
     avg_s = cand_ms / 1e3 / max(1, launches)
+    kname = "k_flip2_best" if kind == "maxcut" else "k_swap_propose"
     res["roofline"] = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
-                           frac=per_launch / avg_s / HBM_PEAK, traffic=None,
-                           kernel="k_flip2_best" if kind == "maxcut" else "k_fill_rows_i32 + k_swap_propose",
+                           frac=per_launch / avg_s / HBM_PEAK, traffic=measured_traffic(f"{wl.name}:pair", kname),
+                           kernel=kname if kind == "maxcut" else "k_fill_rows_i32 + k_tight_bits + k_swap_propose",
                            avg_launch_ms=avg_s * 1e3, algorithmic_bytes_per_launch=per_launch,
                            launches=launches)
     if not args.no_cpu_baseline:
@@ -273,12 +276,6 @@ def bench_differentiation(args, wl):
     from synth import arrays
     from paper_2605_06921_amd import mqo
 
-    if args.copy_calibration_mb:
-        a = torch.empty(args.copy_calibration_mb << 18, dtype=torch.float32, device="cuda:0").fill_(1.0)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
     g = wl.make_graph()
     dev = torch.device("cuda:0")
     dg = mqo.DeviceGraph(g, dev)
@@ -375,6 +372,14 @@ def main():
         if args.objective != wl.problem:
             # counter records are per workload and formulation
             wl = dataclasses.replace(wl, problem=args.objective, name=f"{wl.name}:{args.objective}")
+    if args.copy_calibration_mb:
+        # a plain device copy of known size: the scale of the HBM counters
+        a = torch.empty(args.copy_calibration_mb << 18, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.copy_calibration_mb} MiB done")
+        del a, b
     if args.mode == "toy":
         print(json.dumps(bench_toy(args)), flush=True)
         return
@@ -387,13 +392,6 @@ def main():
         import dataclasses
         tag = (f":pool{args.pool}" if args.pool else "") + (":final" if args.final_search else "")
         wl = dataclasses.replace(wl, name=wl.name + tag)
-    if args.copy_calibration_mb:
-        a = torch.empty(args.copy_calibration_mb << 18, dtype=torch.float32, device="cuda:0").fill_(1.0)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy of {args.copy_calibration_mb} MiB done")
-        del a, b
     log(f"[bench] building graph {wl.name}")
     g = wl.make_graph()
     dev = torch.device("cuda:0")
