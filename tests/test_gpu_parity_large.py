@@ -198,3 +198,97 @@ def test_differentiation_full_size(mqo, name):
     got = dX0.cpu().numpy()[:, cols]
     assert np.abs(got - rX0).max() / max(1.0, np.abs(rX0).max()) <= 1e-4
     assert np.allclose(da.cpu().numpy()[cols], ra, rtol=1e-4, atol=1e-4 * np.abs(ra).max())
+
+
+# --------------------------------------------------------------------------
+# the paper's own searches, the pool and the Prop. 4.1 toy at the sizes
+# `bench.py` times (--mode pair / --pool 8 --final-search / --mode toy)
+# --------------------------------------------------------------------------
+
+def _pair_start(mqo, wl, g, dg):
+    """The bench's start: the 1-flip optima of the rounded uniform iterate."""
+    kind = "mis" if wl.problem == "mis" else "maxcut"
+    lo, hi = obj.box(kind)
+    X = arrays.uniform((g.n, wl.batch), lo, hi, wl.seed)
+    Z0 = (X > 0.5).astype(np.int8) if kind == "mis" else np.where(X > 0, 1, -1).astype(np.int8)
+    Z = torch.from_numpy(Z0).to(DEV)
+    mqo.local_search(kind, dg, Z, wl.seed, 0)
+    return kind, Z
+
+
+def test_one_two_swap_er_batch_full_size_sampled(mqo):
+    wl = WORKLOADS["er_batch_mis"]
+    g = _graph("er_batch_mis")
+    dg = mqo.DeviceGraph(g, DEV)
+    kind, Z = _pair_start(mqo, wl, g, dg)
+    Zs = Z.cpu().numpy()
+    mqo.pair_search(kind, dg, Z, wl.seed, 0)
+    out = Z.cpu().numpy()
+    for gi, cols in ((0, [0, 511]), (64, [17]), (127, [300, 301])):
+        sub = g.subgraph(gi)
+        lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+        ref, _ = discrete.pair_search(kind, sub, Zs[lo:hi][:, cols], wl.seed,
+                                      gi * wl.batch + np.array(cols), 0)
+        assert np.array_equal(out[lo:hi][:, cols], ref)
+    # every result is a maximal independent set, no smaller than its start
+    for gi in range(0, 128, 9):
+        sub = g.subgraph(gi)
+        lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+        assert np.all(discrete.is_maximal_independent(sub, out[lo:hi]))
+        assert np.all(out[lo:hi].astype(np.int64).sum(0) >= Zs[lo:hi].astype(np.int64).sum(0))
+
+
+def test_one_two_flip_torus_full_size(mqo):
+    wl = WORKLOADS["torus1m_maxcut"]
+    g = _graph("torus1m_maxcut")
+    dg = mqo.DeviceGraph(g, DEV)
+    kind, Z = _pair_start(mqo, wl, g, dg)
+    Zs = Z.cpu().numpy()
+    mqo.pair_search(kind, dg, Z, wl.seed, 0)
+    out = Z.cpu().numpy()
+    ref, _ = discrete.pair_search(kind, g, Zs[:, [5]], wl.seed, np.array([5]), 0)
+    assert np.array_equal(out[:, [5]], ref)
+    # every column: no improving 1-flip and no improving 2-flip of a cut
+    # edge (gains from exact integer neighbour sums), cut never lower
+    S = out.astype(np.int64)
+    t = discrete.neighbour_counts(g, S)
+    gain1 = S * t
+    assert gain1.max() <= 0
+    u, v, w = g.edges()
+    cut = S[u] != S[v]
+    gain2 = np.where(cut, gain1[u] + gain1[v] + 2 * w[:, None], -1)
+    assert gain2.max() <= 0
+    assert np.all(discrete.evaluate_cut(g, out) >= discrete.evaluate_cut(g, Zs))
+
+
+def test_pool_torus_full_size_properties(mqo):
+    wl = WORKLOADS["torus1m_maxcut"]
+    g = _graph("torus1m_maxcut")
+    dg = mqo.DeviceGraph(g, DEV)
+    K = 8
+    out = mqo.solve("maxcut", dg, batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=wl.rounds,
+                    alpha=wl.alpha, lam=wl.lam, rho=wl.rho, reset_mode=wl.reset_mode, seed=wl.seed, pool_k=K,
+                    final_search=True)
+    pv = out["pool_value"].cpu().numpy()
+    pz = out["pool_x"].cpu().numpy()
+    assert np.all(pv > np.iinfo(np.int64).min)  # the pool is full
+    assert np.array_equal(discrete.evaluate_cut(g, pz), pv)
+    assert len({pz[:, k].tobytes() for k in range(K)}) == K
+    assert out["best_value"].item() == pv.max()
+    assert out["best_value"].item() >= out["traj_best_value"].cpu().numpy().max()
+    assert np.array_equal(out["best_x"].cpu().numpy(), pz[:, int(np.argmax(pv))])
+
+
+def test_toy_bench_size_sampled(mqo):
+    """The bench's 2^20 trials at n = 64; the first 192 trials against the
+    oracle (trials are independent) and the success fraction against the
+    proposition's bound."""
+    import math
+    from oracle import toy
+    n, R = 64, math.ceil(2 * math.log(64 / 0.01))
+    first, x = mqo.toy_reset(11, n, 1 << 20, R * n, device=DEV)
+    f = first.cpu().numpy()
+    rf, rx = toy.global_reset(11, n, 192, R * n)
+    assert np.array_equal(f[:192], rf)
+    assert np.array_equal(x[:192].cpu().numpy(), rx)
+    assert (f < 0).mean() <= toy.failure_bound(n, R)
