@@ -433,15 +433,36 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
     // ------------------------------------------- rounding and neighbour counts
     for (int32_t L = tid; L < nT; L += nthr) zs[L] = round_x<MAXCUT>(xf[L]);
     __syncthreads();
-    for (int32_t L = tid; L < nT; L += nthr) {
-      const int32_t v = L >> lt, c = L & (T - 1);
-      int32_t s = 0;
-      for (int32_t j = rps[v]; j < rps[v + 1]; ++j) {
-        const int32_t u = CSR_LDS ? (int32_t)cls[j] : cig[j] - ilo;
-        const int32_t zu = zs[(u << lt) | c];
-        s += WEIGHTED ? wtg[j] * zu : zu;
+    // With the degree-3 register adjacency the lane's neighbour items come
+    // from its offset registers (item index = offset into xa; the padding
+    // points past the last item) instead of the CSR in global memory (wider
+    // shapes keep the CSR loops: the extra live registers would spill).
+    constexpr bool REG_NBRS = DREG == 3;
+    if constexpr (REG_NBRS) {
+#pragma unroll
+      for (int i = 0; i < IPT; ++i) {
+        const int32_t L = tid + i * nthr;
+        if (L < nT) {
+          int32_t s = 0;
+#pragma unroll
+          for (int kk = 0; kk < DREG; ++kk) {
+            const int32_t Lu = (int32_t)(pa[i][kk] - xa);
+            if (Lu < nT) s += zs[Lu];
+          }
+          nb[L] = s;
+        }
       }
-      nb[L] = s;
+    } else {
+      for (int32_t L = tid; L < nT; L += nthr) {
+        const int32_t v = L >> lt, c = L & (T - 1);
+        int32_t s = 0;
+        for (int32_t j = rps[v]; j < rps[v + 1]; ++j) {
+          const int32_t u = CSR_LDS ? (int32_t)cls[j] : cig[j] - ilo;
+          const int32_t zu = zs[(u << lt) | c];
+          s += WEIGHTED ? wtg[j] * zu : zu;
+        }
+        nb[L] = s;
+      }
     }
 
     // ------------------------------------------------------- local search
@@ -454,25 +475,51 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
       __syncthreads();
       int32_t it = 0;
       while (true) {
-        for (int32_t L = tid; L < nT; L += nthr) {
-          const int32_t v = L >> lt, c = L & (T - 1);
-          int8_t f = 0;
-          int32_t k1;
-          if (c < cols && ls_candidate_t<MAXCUT>(zs[L], nb[L], k1)) {
-            s_active[it & 1] = 1;
-            const uint32_t pv = prio[L];
-            f = 1;
-            for (int32_t j = rps[v]; j < rps[v + 1]; ++j) {
-              const int32_t u = CSR_LDS ? (int32_t)cls[j] : cig[j] - ilo;
-              const int32_t Lu = (u << lt) | c;
-              int32_t k1u;
-              if (ls_candidate_t<MAXCUT>(zs[Lu], nb[Lu], k1u) && key_beats(k1u, prio[Lu], u, k1, pv, v)) {
-                f = 0;
-                break;
+        if constexpr (REG_NBRS) {
+#pragma unroll
+          for (int i = 0; i < IPT; ++i) {
+            const int32_t L = tid + i * nthr;
+            if (L < nT) {
+              const int32_t v = L >> lt, c = L & (T - 1);
+              int8_t f = 0;
+              int32_t k1;
+              if (c < cols && ls_candidate_t<MAXCUT>(zs[L], nb[L], k1)) {
+                s_active[it & 1] = 1;
+                const uint32_t pv = prio[L];
+                f = 1;
+#pragma unroll
+                for (int kk = 0; kk < DREG; ++kk) {
+                  const int32_t Lu = (int32_t)(pa[i][kk] - xa);
+                  int32_t k1u;
+                  if (Lu < nT && ls_candidate_t<MAXCUT>(zs[Lu], nb[Lu], k1u) &&
+                      key_beats(k1u, prio[Lu], Lu >> lt, k1, pv, v))
+                    f = 0;
+                }
               }
+              fl[L] = f;
             }
           }
-          fl[L] = f;
+        } else {
+          for (int32_t L = tid; L < nT; L += nthr) {
+            const int32_t v = L >> lt, c = L & (T - 1);
+            int8_t f = 0;
+            int32_t k1;
+            if (c < cols && ls_candidate_t<MAXCUT>(zs[L], nb[L], k1)) {
+              s_active[it & 1] = 1;
+              const uint32_t pv = prio[L];
+              f = 1;
+              for (int32_t j = rps[v]; j < rps[v + 1]; ++j) {
+                const int32_t u = CSR_LDS ? (int32_t)cls[j] : cig[j] - ilo;
+                const int32_t Lu = (u << lt) | c;
+                int32_t k1u;
+                if (ls_candidate_t<MAXCUT>(zs[Lu], nb[Lu], k1u) && key_beats(k1u, prio[Lu], u, k1, pv, v)) {
+                  f = 0;
+                  break;
+                }
+              }
+            }
+            fl[L] = f;
+          }
         }
         __syncthreads();
         if (!s_active[it & 1]) break;
@@ -481,16 +528,34 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
           break;
         }
         if (tid == 0) s_active[(it + 1) & 1] = 0;
-        for (int32_t L = tid; L < nT; L += nthr) {
-          if (fl[L]) {
-            const int32_t v = L >> lt, c = L & (T - 1);
-            const int32_t z = zs[L];
-            const int32_t zn = MAXCUT ? -z : 1 - z;
-            zs[L] = (int8_t)zn;
-            const int32_t dz = zn - z;
-            for (int32_t j = rps[v]; j < rps[v + 1]; ++j) {
-              const int32_t u = CSR_LDS ? (int32_t)cls[j] : cig[j] - ilo;
-              atomicAdd(&nb[(u << lt) | c], WEIGHTED ? dz * wtg[j] : dz);
+        if constexpr (REG_NBRS) {
+#pragma unroll
+          for (int i = 0; i < IPT; ++i) {
+            const int32_t L = tid + i * nthr;
+            if (L < nT && fl[L]) {
+              const int32_t z = zs[L];
+              const int32_t zn = MAXCUT ? -z : 1 - z;
+              zs[L] = (int8_t)zn;
+              const int32_t dz = zn - z;
+#pragma unroll
+              for (int kk = 0; kk < DREG; ++kk) {
+                const int32_t Lu = (int32_t)(pa[i][kk] - xa);
+                if (Lu < nT) atomicAdd(&nb[Lu], dz);
+              }
+            }
+          }
+        } else {
+          for (int32_t L = tid; L < nT; L += nthr) {
+            if (fl[L]) {
+              const int32_t v = L >> lt, c = L & (T - 1);
+              const int32_t z = zs[L];
+              const int32_t zn = MAXCUT ? -z : 1 - z;
+              zs[L] = (int8_t)zn;
+              const int32_t dz = zn - z;
+              for (int32_t j = rps[v]; j < rps[v + 1]; ++j) {
+                const int32_t u = CSR_LDS ? (int32_t)cls[j] : cig[j] - ilo;
+                atomicAdd(&nb[(u << lt) | c], WEIGHTED ? dz * wtg[j] : dz);
+              }
             }
           }
         }
