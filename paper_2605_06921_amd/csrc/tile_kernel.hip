@@ -66,6 +66,7 @@ template <bool MAXCUT, bool WEIGHTED, int VEC, bool CSR_LDS, int DREG, int IPT>
 __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a) {
   extern __shared__ __align__(16) float smem[];
   __shared__ uint32_t s_prefix[TILE_MAX_T], s_krem[TILE_MAX_T], s_cnteq[TILE_MAX_T], s_tie[TILE_MAX_T];
+  __shared__ int32_t s_sel_done[TILE_MAX_T], s_sel_left;
   __shared__ unsigned long long s_acc[2][TILE_MAX_T];
   __shared__ int32_t s_take[TILE_MAX_T];
   __shared__ int32_t s_active[2];
@@ -182,29 +183,42 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
           s_krem[tid] = (uint32_t)k;
           s_tie[tid] = (uint32_t)n;
           s_cnteq[tid] = 0u;
+          s_sel_done[tid] = 0;
         }
+        if (tid == 0) s_sel_left = cols;
         for (int pass = 0; pass < 4; ++pass) {
           for (int32_t h = tid; h < T * 256; h += nthr) hist[h] = 0u;
           __syncthreads();
           const int hs = 32 - 8 * pass, ds = 24 - 8 * pass;
           for (int32_t L = tid; L < nT; L += nthr) {
             const int32_t c = L & (T - 1);
-            if (c < cols) {
+            if (c < cols && !s_sel_done[c]) {
               const uint32_t key = prio[L];
               if (pass == 0 || (key >> hs) == s_prefix[c]) atomicAdd(&hist[c * 256 + ((key >> ds) & 255u)], 1u);
             }
           }
           __syncthreads();
           for (int32_t c = wave; c < cols; c += nwaves) {  // one wavefront per column
+            if (s_sel_done[c]) continue;
             uint32_t d, before, at;
             wave_select_digit(hist + c * 256, s_krem[c], d, before, at);
             if ((tid & 63) == 0) {
-              s_prefix[c] = (s_prefix[c] << 8) | d;
-              s_krem[c] -= before;
+              uint32_t pre = (s_prefix[c] << 8) | d;
+              const uint32_t krem = s_krem[c] - before;
+              s_krem[c] = krem;
               s_cnteq[c] = at;
+              if (at == krem && pass < 3) {
+                // every key with this prefix is taken: the selection is the
+                // keys up to the prefix's largest completion, all ties kept
+                pre = (uint32_t)((((uint64_t)pre + 1) << (24 - 8 * pass)) - 1);
+                s_sel_done[c] = 1;
+                atomicSub(&s_sel_left, 1);
+              }
+              s_prefix[c] = pre;
             }
           }
           __syncthreads();
+          if (s_sel_left == 0) break;  // uniform
         }
         // more vertices share the threshold key than remain to be taken:
         // the lowest indices are kept (rare; sequential scan per column)
