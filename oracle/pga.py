@@ -106,12 +106,14 @@ def step32(graph, X, kind, alpha, param, mu=0.0, V=None):
 # initialisation
 # --------------------------------------------------------------------------
 
-def init_uniform(kind, n, traj, seed):
+def init_uniform(kind, n, traj, seed, start=0):
     """x0 ~ U[0,1)^n for MIS; for MaxCut the same draw mapped by 2u - 1 onto
     the box [-1,1]^n (the affine map of the MaxCut degree initialisation,
-    Alg. 2).  ``traj`` is the array of trajectory ids (one per column)."""
+    Alg. 2).  ``traj`` is the array of trajectory ids (one per column);
+    ``start`` numbers the fresh starts of the outer loop (the round field
+    of the Philox counter)."""
     traj = np.asarray(traj, dtype=np.uint64)
-    u = philox.u32_to_unit_f32(philox.vertex_u32(seed, philox.PURPOSE_INIT, traj[None, :], 0,
+    u = philox.u32_to_unit_f32(philox.vertex_u32(seed, philox.PURPOSE_INIT, traj[None, :], start,
                                                  np.arange(n, dtype=np.uint64)[:, None]))
     if kind == obj.MIS:
         return u
@@ -127,13 +129,14 @@ def degree_base(kind, deg):
     return base if kind == obj.MIS else 2.0 * base - 1.0
 
 
-def init_degree(kind, deg, traj, seed, sigma):
+def init_degree(kind, deg, traj, seed, sigma, start=0):
     """Pi(d_base + eps), eps ~ N(0, sigma^2 I) (Alg. 1 / Alg. 2 initialisation).
     The Gaussian comes from the Box-Muller transform of two uniforms
-    u1 in (0,1], u2 in [0,1) drawn with purpose NOISE."""
+    u1 in (0,1], u2 in [0,1) drawn with purpose NOISE (round field =
+    ``start``)."""
     n = len(deg)
     traj = np.asarray(traj, dtype=np.uint64)
-    a, b = philox.vertex_pair_u32(seed, philox.PURPOSE_NOISE, traj[None, :], 0,
+    a, b = philox.vertex_pair_u32(seed, philox.PURPOSE_NOISE, traj[None, :], start,
                                   np.arange(n, dtype=np.uint64)[:, None])
     u1 = ((a >> np.uint32(8)).astype(np.float64) + 1.0) * 2.0**-24
     u2 = (b >> np.uint32(8)).astype(np.float64) * 2.0**-24

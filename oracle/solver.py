@@ -19,6 +19,11 @@ With ``final_search`` the paper's own search (OneTwoSwap / OneTwoFlip,
 ``discrete.pair_search`` with round index ``rounds``) runs on every
 incumbent after the last round and replaces it when strictly better
 (Alg. 1 / Alg. 2, the local search after the reset loop).
+With ``restart_every`` = R > 0 the outer loop of Alg. 1-4 ("while the
+time budget permits: initialise, ...") is unrolled into the rounds: every
+round r > 0 with r % R == 0 starts from a fresh initial point (the
+initialisation rule, start index r // R) instead of a reset; acceptance,
+incumbents and the pool carry over.
 With ``pool_k`` = K > 0 the graph's trajectories share the pmQO pool of
 Alg. 3 / Alg. 4: after every round the pool becomes the top K distinct
 solutions of the pool and the round's candidates (``discrete.pool_update``),
@@ -60,6 +65,7 @@ class Params:
     check_every: int = 0
     final_search: bool = False
     pool_k: int = 0
+    restart_every: int = 0
 
 
 def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32", trace=None, cols=None,
@@ -85,13 +91,15 @@ def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32"
         assert B == p.batch, "the pool couples all trajectories of a graph"
     pool_val, pool_z = np.zeros(0, dtype=np.int64), np.zeros((n, 0), dtype=np.int8)
     for r in range(p.rounds):
-        if r == 0:
-            if x0 is not None:
-                X = np.asarray(x0, dtype=np.float32)
-            elif p.init_mode == "uniform":
-                X = pga.init_uniform(kind, n, traj, p.seed)
+        fresh = r > 0 and p.restart_every > 0 and r % p.restart_every == 0
+        start = r // p.restart_every if fresh else 0
+        if r == 0 and x0 is not None:
+            X = np.asarray(x0, dtype=np.float32)
+        elif r == 0 or fresh:
+            if p.init_mode == "uniform":
+                X = pga.init_uniform(kind, n, traj, p.seed, start)
             else:
-                X = pga.init_degree(kind, graph.degrees(), traj, p.seed, p.init_sigma).astype(np.float32)
+                X = pga.init_degree(kind, graph.degrees(), traj, p.seed, p.init_sigma, start).astype(np.float32)
         else:
             mask = discrete.reset_set(n, k, p.seed, traj, r)
             base = zbest

@@ -94,3 +94,26 @@ def test_pool_of_one_restarts_everyone_from_the_best():
     best_so_far = max(int(t["value"].max()) for t in trace)
     r = solver.solve("mis", g, p)
     assert r["best_value"][0] == best_so_far
+
+
+def test_restarts_unroll_the_outer_loop():
+    """restart_every = R: rounds 0, R, 2R, ... start from fresh points (start
+    index r // R); a restart round with no reset rounds between is the same
+    as an independent solve from that start, and incumbents carry over."""
+    from oracle import pga
+    g = graphs.erdos_renyi(60, 0.1, 5300)
+    # no local search: its priorities depend on the round index
+    kw = dict(batch=4, steps_per_round=30, alpha=0.05, seed=53, local_search=False)
+    trace = []
+    solver.solve_graph("mis", g, solver.Params(rounds=6, restart_every=2, **kw), trace=trace)
+    # round 2 is the second start: its candidate equals round 0 of a solve
+    # started from init start 1
+    x1 = pga.init_uniform("mis", g.n, np.arange(4), 53, start=1)
+    t2 = []
+    solver.solve_graph("mis", g, solver.Params(rounds=1, **kw), x0=x1, trace=t2)
+    assert np.array_equal(trace[2]["value"], t2[0]["value"])
+    # incumbents never decrease across restarts
+    bests = np.array([t["best"] for t in trace])
+    assert np.all(np.diff(bests, axis=0) >= 0)
+    # the fresh starts differ from the first one
+    assert not np.array_equal(x1, pga.init_uniform("mis", g.n, np.arange(4), 53))
