@@ -171,6 +171,12 @@ typedef struct {
                               the best pool member and final_search searches
                               the pool members (trajectory ids g K + slot).
                               Batched plan only (MQO_ERR_UNSUPPORTED else)  */
+  int32_t restart_every;   /* 0 = off (default); R > 0: the outer loop of
+                              Alg. 1-4 -- every round r > 0 with r % R == 0
+                              starts from a fresh point of the initialisation
+                              rule (Philox round field = r / R) instead of a
+                              reset; incumbents and the pool carry over.
+                              Streaming plans (batched, plain) only         */
 } mqo_params;
 
 /* Outputs of a solve.  Device arrays are written; host fields are set. */

@@ -169,6 +169,9 @@ int check_params(const mqo_params *p, mqo_objective obj) {
     return fail(MQO_ERR_INVALID_ARG, "bad local_search");
   if (p->final_search != MQO_FINAL_NONE && p->final_search != MQO_FINAL_PAIR)
     return fail(MQO_ERR_INVALID_ARG, "bad final_search");
+  if (p->restart_every < 0) return fail(MQO_ERR_INVALID_ARG, "restart_every must be >= 0");
+  if (p->restart_every > 0 && p->plan == MQO_PLAN_PERSISTENT)
+    return fail(MQO_ERR_UNSUPPORTED, "fresh starts run on the streaming plans (batched, plain)");
   if (p->pool_k < 0 || p->pool_k > 64 || p->pool_k > p->batch)
     return fail(MQO_ERR_INVALID_ARG, "pool_k must be in [0, min(64, batch)]");
   if (p->pool_k > 0 && (p->plan == MQO_PLAN_PERSISTENT || p->plan == MQO_PLAN_PLAIN))
@@ -662,7 +665,18 @@ int grid_round(Solve &S, StepLoop &loop, bool use_graph, const GraphView &gv, in
                int32_t ldp = 0, const int32_t *base_slot = nullptr) {
   int64_t *steps_ctr = at<int64_t>(S.ws, S.L.steps) + traj0;
   const bool mom = S.p->momentum != 0.0f;
-  if (r > 0) {
+  const int32_t R = S.p->restart_every;
+  if (r > 0 && R > 0 && r % R == 0) {
+    // a fresh start of the outer loop (Alg. 1-4): the initialisation rule
+    // with start index r / R; incumbents (and the pool) carry over
+    const uint64_t start = (uint64_t)(r / R);
+    if (S.p->init_mode == MQO_INIT_UNIFORM)
+      launch_init_uniform(S.maxcut, X, gv.lo, gv.n, ncols, ld, S.p->seed, traj0, S.s, start);
+    else
+      launch_init_degree(S.maxcut, X, S.g->row_ptr, at<int32_t>(S.ws, S.L.dmax), gv.lo, gv.n, ncols, ld, S.p->seed,
+                         traj0, S.p->init_sigma, S.s, start);
+    if (mom) launch_fill_f32(V + gv.lo * ld, gv.n * ld, 0.0f, S.s);
+  } else if (r > 0) {
     launch_reset(S.maxcut, Zb, ldb, nullptr, X, mom ? V : nullptr, gv.lo, gv.n, ncols, ld, S.p->seed, traj0,
                  (uint64_t)r, k_of(S, gv.n), S.p->reset_mode, at<void>(S.ws, S.L.reset), S.s, Zp, ldp, base_slot);
   } else if (mom) {
@@ -802,6 +816,7 @@ bool tile_feasible(const Solve &S, const TileCfg &c) {
 bool tile_possible(const Solve &S) {
   if (S.form != OBJ_H && S.form != OBJ_FB) return false;  // the persistent kernel runs h and f_B
   if (S.p->pool_k > 0) return false;                      // the pool needs every trajectory between rounds
+  if (S.p->restart_every > 0) return false;               // fresh starts: streaming plans
   for (int T = 1; T <= 64; T <<= 1)
     for (int th : {256, 512, 1024})
       if (tile_feasible(S, TileCfg{T, th, 1, 0, 0, 0})) return true;
@@ -1244,6 +1259,7 @@ void mqo_params_default(mqo_params *p) {
   p->maxcut_objective = MQO_OBJ_MAXCUT_FB;
   p->final_search = MQO_FINAL_NONE;
   p->pool_k = 0;
+  p->restart_every = 0;
 }
 
 size_t mqo_workspace_size(const mqo_graph *g, const mqo_params *p, mqo_objective obj) {

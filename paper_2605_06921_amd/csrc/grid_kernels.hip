@@ -33,16 +33,17 @@ static inline dim3 grid_rows(int64_t nrows, int ncols, int lanes_log2, int vec, 
 // ---------------------------------------------------------------------------
 // initialisation
 // ---------------------------------------------------------------------------
+// start: index of the fresh start (the round field of the Philox counter)
 template <bool MAXCUT>
 __global__ __launch_bounds__(256) void k_init_uniform(float *__restrict__ X, int64_t lo, int64_t n, int32_t ncols,
-                                                      int32_t ld, uint64_t seed, uint64_t traj0) {
+                                                      int32_t ld, uint64_t seed, uint64_t traj0, uint64_t start) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nvb = (n + 7) >> 3;
   if (idx >= nvb * ncols) return;
   const int32_t c = (int32_t)(idx % ncols);
   const int64_t vb = idx / ncols;
   uint32_t r[8];
-  philox_block8(r, seed, PURPOSE_INIT, traj0 + c, 0, (uint64_t)vb);
+  philox_block8(r, seed, PURPOSE_INIT, traj0 + c, start, (uint64_t)vb);
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int64_t v = vb * 8 + i;
@@ -64,7 +65,7 @@ template <bool MAXCUT>
 __global__ __launch_bounds__(256) void k_init_degree(float *__restrict__ X, const int32_t *__restrict__ row_ptr,
                                                      const int32_t *__restrict__ dmax_p, int64_t lo, int64_t n,
                                                      int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0,
-                                                     float sigma) {
+                                                     float sigma, uint64_t start) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n * ncols) return;
   const int32_t c = (int32_t)(idx % ncols);
@@ -73,7 +74,7 @@ __global__ __launch_bounds__(256) void k_init_degree(float *__restrict__ X, cons
   const float d = (float)(row_ptr[lo + v + 1] - row_ptr[lo + v]);
   float base = dmax == 0 ? 1.0f : 1.0f - d / (float)dmax;
   if (MAXCUT) base = 2.0f * base - 1.0f;
-  uint64_t w[4] = {(uint64_t)v >> 2, traj0 + c, 0, 0};
+  uint64_t w[4] = {(uint64_t)v >> 2, traj0 + c, start, 0};
   philox4x64_10(w, seed, PURPOSE_NOISE);
   const uint64_t word = w[v & 3];
   const float u1 = ((float)((uint32_t)word >> 8) + 1.0f) * (1.0f / 16777216.0f);
@@ -1711,12 +1712,14 @@ static inline unsigned blocks_for(int64_t count, int threads = 256) {
 }
 
 void launch_init_uniform(bool maxcut, float *X, int64_t lo, int64_t n, int32_t ncols, int32_t ld, uint64_t seed,
-                         uint64_t traj0, hipStream_t s) {
+                         uint64_t traj0, hipStream_t s, uint64_t start) {
   const int64_t count = ((n + 7) >> 3) * ncols;
   if (maxcut)
-    MQO_LAUNCH(k_init_uniform<true>, dim3(blocks_for(count)), dim3(256), 0, s, X, lo, n, ncols, ld, seed, traj0);
+    MQO_LAUNCH(k_init_uniform<true>, dim3(blocks_for(count)), dim3(256), 0, s, X, lo, n, ncols, ld, seed, traj0,
+               start);
   else
-    MQO_LAUNCH(k_init_uniform<false>, dim3(blocks_for(count)), dim3(256), 0, s, X, lo, n, ncols, ld, seed, traj0);
+    MQO_LAUNCH(k_init_uniform<false>, dim3(blocks_for(count)), dim3(256), 0, s, X, lo, n, ncols, ld, seed, traj0,
+               start);
 }
 
 void launch_degree_max(const int32_t *row_ptr, int64_t n, int32_t *out, hipStream_t s) {
@@ -1725,16 +1728,17 @@ void launch_degree_max(const int32_t *row_ptr, int64_t n, int32_t *out, hipStrea
 }
 
 void launch_init_degree(bool maxcut, float *X, const int32_t *row_ptr, int32_t *dmax_scratch, int64_t lo, int64_t n,
-                        int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0, float sigma, hipStream_t s) {
+                        int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0, float sigma, hipStream_t s,
+                        uint64_t start) {
   MQO_LAUNCH(k_fill_i32, dim3(1), dim3(64), 0, s, dmax_scratch, (int64_t)1, 0);
   MQO_LAUNCH(k_degree_max, dim3(blocks_for(n < 65536 ? n : 65536)), dim3(256), 0, s, row_ptr, lo, n, dmax_scratch);
   const int64_t count = n * ncols;
   if (maxcut)
     MQO_LAUNCH(k_init_degree<true>, dim3(blocks_for(count)), dim3(256), 0, s, X, row_ptr, dmax_scratch, lo, n, ncols,
-               ld, seed, traj0, sigma);
+               ld, seed, traj0, sigma, start);
   else
     MQO_LAUNCH(k_init_degree<false>, dim3(blocks_for(count)), dim3(256), 0, s, X, row_ptr, dmax_scratch, lo, n,
-               ncols, ld, seed, traj0, sigma);
+               ncols, ld, seed, traj0, sigma, start);
 }
 
 StepCfg default_step_cfg(int32_t ncols, int32_t ld) {

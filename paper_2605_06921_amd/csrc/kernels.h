@@ -20,10 +20,13 @@ int64_t grid_blocks_x(int64_t nrows, StepCfg cfg);
 // row workgroups of a sparse-product launch over graph g (without hub workgroups)
 int64_t spmm_row_blocks(const GraphView &g, StepCfg cfg, int form);
 
+// start: index of the fresh start (0 = the first; the outer loop's later
+// starts use 1, 2, ...)
 void launch_init_uniform(bool maxcut, float *X, int64_t lo, int64_t n, int32_t ncols, int32_t ld, uint64_t seed,
-                         uint64_t traj0, hipStream_t s);
+                         uint64_t traj0, hipStream_t s, uint64_t start = 0);
 void launch_init_degree(bool maxcut, float *X, const int32_t *row_ptr, int32_t *dmax_scratch, int64_t lo, int64_t n,
-                        int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0, float sigma, hipStream_t s);
+                        int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0, float sigma, hipStream_t s,
+                        uint64_t start = 0);
 void launch_degree_max(const int32_t *row_ptr, int64_t n, int32_t *out, hipStream_t s);
 // form: OBJ_H / OBJ_FB / OBJ_FL / OBJ_FP / OBJ_FA (common.h).
 // colact: per-column active flags (0 = stopped for the round: copied

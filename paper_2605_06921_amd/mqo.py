@@ -51,7 +51,8 @@ class _Params(ctypes.Structure):
                 ("tile_cols", ctypes.c_int32), ("tile_threads", ctypes.c_int32), ("tile_vec", ctypes.c_int32),
                 ("tile_csr", ctypes.c_int32), ("tile_reg", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("time_budget_s", ctypes.c_double), ("maxcut_objective", ctypes.c_int32),
-                ("final_search", ctypes.c_int32), ("pool_k", ctypes.c_int32)]
+                ("final_search", ctypes.c_int32), ("pool_k", ctypes.c_int32),
+                ("restart_every", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -214,7 +215,7 @@ def last_error() -> str:
 def make_params(batch=1, steps_per_round=200, rounds=1, alpha=0.01, momentum=0.0, gamma=2.0, lam=1e-3,
                 rho=0.05, init_sigma=0.0, init_mode="uniform", reset_mode="zero", local_search=True,
                 plan="auto", seed=0, time_budget_s=0.0, tile_cols=0, tile_threads=0, tile_vec=0, tile_csr=0,
-                tile_reg=0, check_every=0, final_search=False, pool_k=0) -> _Params:
+                tile_reg=0, check_every=0, final_search=False, pool_k=0, restart_every=0) -> _Params:
     p = _Params()
     _lib.mqo_params_default(ctypes.byref(p))
     p.batch, p.steps_per_round, p.rounds, p.check_every = batch, steps_per_round, rounds, check_every
@@ -228,6 +229,7 @@ def make_params(batch=1, steps_per_round=200, rounds=1, alpha=0.01, momentum=0.0
     p.seed, p.time_budget_s = seed, time_budget_s
     p.final_search = 1 if final_search else 0
     p.pool_k = pool_k
+    p.restart_every = restart_every
     return p
 
 

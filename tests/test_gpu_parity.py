@@ -783,3 +783,29 @@ def test_pool_rejected_where_not_offered(mqo):
         assert e.value.status == -5
     with pytest.raises(mqo.MqoError):
         mqo.solve("maxcut", dg, batch=4, steps_per_round=4, pool_k=5)
+
+
+# --------------------------------------------------------------------------
+# the outer loop of Alg. 1-4: fresh starts every restart_every rounds
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", ["mis", "maxcut"])
+@pytest.mark.parametrize("plan,pool", [("batched", 0), ("plain", 0), ("batched", 3)])
+def test_restarts_bit_exact(mqo, kind, plan, pool):
+    g = CASES["er_batch"][1] if kind == "mis" else CASES["cut_batch"][1]
+    kw = dict(batch=6, steps_per_round=20, rounds=7, alpha=0.05, rho=0.15, seed=71, restart_every=3, pool_k=pool)
+    out = mqo.solve(kind, mqo.DeviceGraph(g, DEV), plan=plan, **kw)
+    assert out["plan"] == plan
+    ref = solver.solve(kind, g, solver.Params(**kw))
+    assert np.array_equal(out["traj_best_value"].cpu().numpy(), ref["traj_best_value"])
+    assert np.array_equal(out["traj_best_x"].cpu().numpy(), ref["traj_best_x"])
+    assert np.array_equal(out["best_value"].cpu().numpy(), ref["best_value"])
+
+
+def test_restarts_rejected_on_the_persistent_plan(mqo):
+    dg = mqo.DeviceGraph(CASES["reg3"][1], DEV)
+    with pytest.raises(mqo.MqoError) as e:
+        mqo.solve("maxcut", dg, batch=2, steps_per_round=4, rounds=4, restart_every=2, plan="persistent")
+    assert e.value.status == -5
+    out = mqo.solve("maxcut", dg, batch=2, steps_per_round=4, rounds=4, restart_every=2)
+    assert out["plan"] == "batched"
