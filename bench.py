@@ -107,24 +107,26 @@ def cpu_baseline(wl, g, budget_s=15.0, pool_k=0, final_search=False):
                        f"numpy/scipy, {el:.1f} s")
 
 
-def pair_cpu_baseline(kind, wl, g, Zs, budget_s):
-    """The oracle's pair search on graph 0, from the same 1-flip optima,
+def pair_cpu_baseline(kind, wl, g, Z0, budget_s):
+    """The oracle's pair search on graph 0, from the 1-flip optima that the
+    oracle's own 1-flip search makes of the same rounded start (untimed),
     over as many trajectories as fit in about half the budget."""
     from oracle import discrete as odisc
     sub = g.subgraph(0)
     lo, hi = int(g.vtx_offset[0]), int(g.vtx_offset[1])
     ncols = 1
     while True:
+        start, _ = odisc.local_search(kind, sub, Z0[lo:hi, :ncols], wl.seed, np.arange(ncols), 0)
         t0 = time.perf_counter()
-        odisc.pair_search(kind, sub, Zs[lo:hi, :ncols], wl.seed, np.arange(ncols), 0)
+        odisc.pair_search(kind, sub, start, wl.seed, np.arange(ncols), 0)
         el = time.perf_counter() - t0
         if ncols == wl.batch or el >= budget_s / 2:
             break
         ncols = int(min(wl.batch, max(2 * ncols, ncols * budget_s / 2 / max(el, 1e-3))))
     return dict(value=sub.nnz * ncols / el, unit="edge-trajectories/s", cores=1, kind="oracle",
                 sample=f"graph 0 of {g.num_graphs} (n={sub.n}, nnz={sub.nnz}), trajectories 0..{ncols - 1} of "
-                       f"{wl.batch}, one complete pair search each from the same 1-flip optima, pure-Python "
-                       f"loops with numpy, single-threaded, {el:.1f} s")
+                       f"{wl.batch}, one complete pair search each from the oracle's own 1-flip optima of the "
+                       f"same rounded start, pure-Python loops with numpy, single-threaded, {el:.1f} s")
 
 
 def bench_pair(args, wl):
@@ -146,8 +148,8 @@ def bench_pair(args, wl):
     kind = "mis" if wl.problem == "mis" else "maxcut"
     lo, hi = oobj.box(kind)
     X = arrays.uniform((g.n, B), lo, hi, wl.seed)
-    Z0 = torch.from_numpy((X > 0.5).astype(np.int8) if kind == "mis" else np.where(X > 0, 1, -1).astype(np.int8))
-    Z0 = Z0.to(dev)
+    Zr = (X > 0.5).astype(np.int8) if kind == "mis" else np.where(X > 0, 1, -1).astype(np.int8)
+    Z0 = torch.from_numpy(Zr).to(dev)
     ws = mqo.Workspace(dev)
     mqo.local_search(kind, dg, Z0, wl.seed, 0, workspace=ws)
     Z = torch.empty_like(Z0)
@@ -197,7 +199,7 @@ def bench_pair(args, wl):
                            launches=launches)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline (pair search)")
-        res["cpu_baseline"] = pair_cpu_baseline(kind, wl, g, Z0.cpu().numpy(), args.cpu_budget)
+        res["cpu_baseline"] = pair_cpu_baseline(kind, wl, g, Zr, args.cpu_budget)
     return res
 
 

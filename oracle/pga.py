@@ -106,15 +106,16 @@ def step32(graph, X, kind, alpha, param, mu=0.0, V=None):
 # initialisation
 # --------------------------------------------------------------------------
 
-def init_uniform(kind, n, traj, seed, start=0):
+def init_uniform(kind, n, traj, seed, start=0, rows=None):
     """x0 ~ U[0,1)^n for MIS; for MaxCut the same draw mapped by 2u - 1 onto
     the box [-1,1]^n (the affine map of the MaxCut degree initialisation,
     Alg. 2).  ``traj`` is the array of trajectory ids (one per column);
     ``start`` numbers the fresh starts of the outer loop (the round field
-    of the Philox counter)."""
+    of the Philox counter); ``rows`` (optional) selects the vertices
+    returned."""
     traj = np.asarray(traj, dtype=np.uint64)
-    u = philox.u32_to_unit_f32(philox.vertex_u32(seed, philox.PURPOSE_INIT, traj[None, :], start,
-                                                 np.arange(n, dtype=np.uint64)[:, None]))
+    v = np.arange(n, dtype=np.uint64) if rows is None else np.asarray(rows, dtype=np.uint64)
+    u = philox.u32_to_unit_f32(philox.vertex_u32(seed, philox.PURPOSE_INIT, traj[None, :], start, v[:, None]))
     if kind == obj.MIS:
         return u
     return F32(2.0) * u - F32(1.0)

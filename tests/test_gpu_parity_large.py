@@ -134,6 +134,9 @@ def _rows_step32(g, X, rows, kind, alpha, param):
 
 @pytest.mark.parametrize("name", ["er1m_mis", "torus1m_maxcut"])
 def test_million_vertex_round_pieces(mqo, name):
+    """Every expected value comes from the oracle's own arrays: its start on
+    the sampled rows and their neighbours (all columns), and its whole start,
+    step, rounding, search and reset on one column."""
     wl = WORKLOADS[name]
     g = _graph(name)
     dg = mqo.DeviceGraph(g, DEV)
@@ -142,27 +145,37 @@ def test_million_vertex_round_pieces(mqo, name):
     X0 = mqo.init_iterate(wl.problem, dg, B, seed=wl.seed)
     x0 = X0.cpu().numpy()
     rows = np.concatenate([np.arange(5), np.random.default_rng(1).integers(0, g.n, 300), [g.n - 1]])
-    assert np.array_equal(x0[rows], pga.init_uniform(wl.problem, g.n, np.arange(B), wl.seed)[rows])
+    nbr = np.concatenate([g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]] for v in rows])
+    need = np.unique(np.concatenate([rows, nbr]))
+    x0r = np.zeros((g.n, B), dtype=np.float32)
+    x0r[need] = pga.init_uniform(wl.problem, g.n, np.arange(B), wl.seed, rows=need)
+    assert np.array_equal(x0[need], x0r[need])
     X = X0.clone()
     mqo.pga_steps(wl.problem, dg, X, 1, alpha=wl.alpha, gamma=wl.gamma, lam=wl.lam)
     x1 = X.cpu().numpy()
-    assert np.array_equal(x1[rows], _rows_step32(g, x0, rows, wl.problem, wl.alpha, param))
-    # rounding and exact evaluation on the whole arrays
+    assert np.array_equal(x1[rows], _rows_step32(g, x0r, rows, wl.problem, wl.alpha, param))
+    # one whole column against the oracle's own start, step and rounding
+    c = 17
+    x0c = pga.init_uniform(wl.problem, g.n, np.array([c]), wl.seed)
+    x1c, _ = pga.step32(g, x0c, wl.problem, wl.alpha, param)
+    assert np.array_equal(x1[:, [c]], x1c)
     Z, value, conf, fixed = mqo.round_evaluate(wl.problem, dg, X)
-    Zr = discrete.round_x(wl.problem, x1)
-    assert np.array_equal(Z.cpu().numpy(), Zr)
-    assert np.array_equal(value.cpu().numpy(), discrete.value(wl.problem, g, Zr))
-    # local search on a sampled column (columns are independent)
-    cols = [17]
+    Zg = Z.cpu().numpy()
+    Zrc = discrete.round_x(wl.problem, x1c)
+    assert np.array_equal(Zg[:, [c]], Zrc)
+    assert value.cpu().numpy()[c] == discrete.value(wl.problem, g, Zrc)[0]
+    # every column: the rounding is the threshold of the GPU's own iterate
+    thr = (x1 > 0.5).astype(np.int8) if wl.problem == "mis" else np.where(x1 > 0, 1, -1).astype(np.int8)
+    assert np.array_equal(Zg, thr)
+    # local search and reset of that column
     Zc = Z.clone()
     mqo.local_search(wl.problem, dg, Zc, seed=wl.seed, rnd=3)
-    ref, _ = discrete.local_search(wl.problem, g, Zr[:, cols], wl.seed, np.array(cols), 3)
-    assert np.array_equal(Zc.cpu().numpy()[:, cols], ref)
-    # reset of the searched incumbents, sampled columns
+    ref, _ = discrete.local_search(wl.problem, g, Zrc, wl.seed, np.array([c]), 3)
+    assert np.array_equal(Zc.cpu().numpy()[:, [c]], ref)
     Xr = mqo.reset(wl.problem, dg, Zc, seed=wl.seed, rnd=4, rho=wl.rho).cpu().numpy()
     k = discrete.reset_count(wl.rho, g.n)
-    mask = discrete.reset_set(g.n, k, wl.seed, np.array(cols), 4)
-    assert np.array_equal(Xr[:, cols], discrete.reset_apply(wl.problem, Zc.cpu().numpy()[:, cols], mask))
+    mask = discrete.reset_set(g.n, k, wl.seed, np.array([c]), 4)
+    assert np.array_equal(Xr[:, [c]], discrete.reset_apply(wl.problem, ref, mask))
     assert np.all((Xr == 0).sum(0) >= k) if wl.problem == "mis" else np.all((Xr == 0).sum(0) == k)
 
 
@@ -190,7 +203,7 @@ def test_differentiation_full_size(mqo, name):
     cols = [0, 63]
     xs = pga.unrolled_forward(g, wl.problem, param, wl.alpha, K, X0[:, cols], precision="fp32")
     assert np.array_equal(XK.cpu().numpy()[:, cols], xs[K])
-    dL = obj.gradient(wl.problem, XK.cpu().numpy().astype(np.float64), obj.adjacency(g), param)
+    dL = arrays.uniform((g.n, B), -1.0, 1.0, 602).astype(np.float64)  # seeded, independent of either side
     dX0, da = mqo.unrolled_backward(wl.problem, dg, ckpt, torch.from_numpy(dL.astype(np.float32)).to(DEV),
                                     wl.alpha, K, c, param)
     rX0, ra = pga.unrolled_backward(g, wl.problem, param, wl.alpha, K, X0[:, cols],
@@ -205,26 +218,36 @@ def test_differentiation_full_size(mqo, name):
 # `bench.py` times (--mode pair / --pool 8 --final-search / --mode toy)
 # --------------------------------------------------------------------------
 
-def _pair_start(mqo, wl, g, dg):
-    """The bench's start: the 1-flip optima of the rounded uniform iterate."""
+def _pair_start(mqo, wl, g, dg, sampled):
+    """The bench's start: the 1-flip optima of the rounded uniform iterate.
+    The sampled (graph, columns) that are compared with the oracle take the
+    oracle's own 1-flip search; the other columns the GPU's (they are only
+    checked for properties).  Returns (kind, device Z, host copy of Z)."""
     kind = "mis" if wl.problem == "mis" else "maxcut"
     lo, hi = obj.box(kind)
     X = arrays.uniform((g.n, wl.batch), lo, hi, wl.seed)
     Z0 = (X > 0.5).astype(np.int8) if kind == "mis" else np.where(X > 0, 1, -1).astype(np.int8)
     Z = torch.from_numpy(Z0).to(DEV)
     mqo.local_search(kind, dg, Z, wl.seed, 0)
-    return kind, Z
+    Zs = Z.cpu().numpy()
+    for gi, cols in sampled:
+        sub = g.subgraph(gi)
+        r0, r1 = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+        cols = np.array(cols)
+        Zs[r0:r1, cols], _ = discrete.local_search(kind, sub, Z0[r0:r1][:, cols], wl.seed,
+                                                   gi * wl.batch + cols, 0)
+    return kind, torch.from_numpy(Zs).to(DEV), Zs
 
 
 def test_one_two_swap_er_batch_full_size_sampled(mqo):
     wl = WORKLOADS["er_batch_mis"]
     g = _graph("er_batch_mis")
     dg = mqo.DeviceGraph(g, DEV)
-    kind, Z = _pair_start(mqo, wl, g, dg)
-    Zs = Z.cpu().numpy()
+    sampled = ((0, [0, 511]), (64, [17]), (127, [300, 301]))
+    kind, Z, Zs = _pair_start(mqo, wl, g, dg, sampled)
     mqo.pair_search(kind, dg, Z, wl.seed, 0)
     out = Z.cpu().numpy()
-    for gi, cols in ((0, [0, 511]), (64, [17]), (127, [300, 301])):
+    for gi, cols in sampled:
         sub = g.subgraph(gi)
         lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
         ref, _ = discrete.pair_search(kind, sub, Zs[lo:hi][:, cols], wl.seed,
@@ -242,8 +265,7 @@ def test_one_two_flip_torus_full_size(mqo):
     wl = WORKLOADS["torus1m_maxcut"]
     g = _graph("torus1m_maxcut")
     dg = mqo.DeviceGraph(g, DEV)
-    kind, Z = _pair_start(mqo, wl, g, dg)
-    Zs = Z.cpu().numpy()
+    kind, Z, Zs = _pair_start(mqo, wl, g, dg, ((0, [5]),))
     mqo.pair_search(kind, dg, Z, wl.seed, 0)
     out = Z.cpu().numpy()
     ref, _ = discrete.pair_search(kind, g, Zs[:, [5]], wl.seed, np.array([5]), 0)
