@@ -47,7 +47,7 @@ typedef enum {
   MQO_ERR_INVALID_GRAPH = -2, /* the CSR is not canonical (see mqo_graph)    */
   MQO_ERR_WORKSPACE = -3,     /* workspace NULL or smaller than required     */
   MQO_ERR_HIP = -4,           /* a HIP runtime call failed                   */
-  MQO_ERR_UNSUPPORTED = -5,   /* valid request this build does not implement */
+  MQO_ERR_UNSUPPORTED = -5,   /* valid request not offered for these arguments */
   MQO_ERR_INTERNAL = -6       /* an internal invariant failed                */
 } mqo_status;
 

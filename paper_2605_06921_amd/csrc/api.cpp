@@ -1057,7 +1057,7 @@ int final_search(Solve &S, int64_t *alternations) {
   return MQO_OK;
 }
 
-// Alg. 4 step 13 (and Alg. 3 step 13 on every member): the pair search on
+// The search after the reset loop of Alg. 4 (Alg. 3's, on every member): the pair search on
 // every pool member (trajectory ids g K + slot, round index = rounds),
 // replacing a member when strictly better; empty slots are never taken.
 int final_search_pool(Solve &S, int8_t *PZ, int64_t *PV, int64_t *alternations) {
