@@ -10,5 +10,5 @@ libmqo.so has not been built (``paper_2605_06921_amd.build.build()``).
 from . import mqo  # noqa: F401
 from .mqo import (DeviceGraph, MqoError, Objective, UnrolledPGA, Workspace, init_iterate,  # noqa: F401
                   local_search, objective, objective_grad, pair_search, pga_steps, reset, round_evaluate, solve,
-                  solve_maxcut, solve_mis, unrolled_backward, unrolled_forward, unrolled_pga,
+                  solve_maxcut, solve_mis, toy_reset, unrolled_backward, unrolled_forward, unrolled_pga,
                   validate_graph_host)
