@@ -395,6 +395,8 @@ struct Solve {
   Layout L;
   hipStream_t s;
   const float *x0;
+  int8_t *Zb = nullptr;    // incumbents [n_total][B]: the caller's traj_best_x when given, else workspace
+  int64_t *best = nullptr; // incumbent values [G*B]: the caller's traj_best_value when given, else workspace
   int64_t ls_iters = 0;
   int32_t deferred_tile_wg = 0;  // > 0: the tile counters sit in the pinned buffer after the final sync
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;  // around the step launches
@@ -703,10 +705,10 @@ int grid_round(Solve &S, StepLoop &loop, bool use_graph, const GraphView &gv, in
 
 int solve_batched(Solve &S, int32_t *rounds_done) {
   float *X = at<float>(S.ws, S.L.X), *Xt = at<float>(S.ws, S.L.Xt), *V = at<float>(S.ws, S.L.V);
-  int8_t *Z = at<int8_t>(S.ws, S.L.Z), *Zb = at<int8_t>(S.ws, S.L.Zb), *F = at<int8_t>(S.ws, S.L.F);
+  int8_t *Z = at<int8_t>(S.ws, S.L.Z), *Zb = S.Zb, *F = at<int8_t>(S.ws, S.L.F);
   int32_t *NB = at<int32_t>(S.ws, S.L.NB);
   uint32_t *PRIO = at<uint32_t>(S.ws, S.L.PRIO);
-  int64_t *value = at<int64_t>(S.ws, S.L.value), *best = at<int64_t>(S.ws, S.L.best);
+  int64_t *value = at<int64_t>(S.ws, S.L.value), *best = S.best;
   const int32_t B = S.B;
   if (S.x0)
     HIP_TRY(hipMemcpyAsync(X, S.x0, S.g->n_total * B * sizeof(float), hipMemcpyDeviceToDevice, S.s));
@@ -754,10 +756,10 @@ int solve_plain(Solve &S, int32_t *rounds_done) {
   // One trajectory at a time on contiguous vectors (ld = 1) with the same
   // kernels; incumbents go straight into column b of Zb ([n][B]).
   float *X = at<float>(S.ws, S.L.pX), *Xt = at<float>(S.ws, S.L.pXt), *V = at<float>(S.ws, S.L.pV);
-  int8_t *Z = at<int8_t>(S.ws, S.L.Z), *Zb = at<int8_t>(S.ws, S.L.Zb), *F = at<int8_t>(S.ws, S.L.F);
+  int8_t *Z = at<int8_t>(S.ws, S.L.Z), *Zb = S.Zb, *F = at<int8_t>(S.ws, S.L.F);
   int32_t *NB = at<int32_t>(S.ws, S.L.NB);
   uint32_t *PRIO = at<uint32_t>(S.ws, S.L.PRIO);
-  int64_t *value = at<int64_t>(S.ws, S.L.value), *best = at<int64_t>(S.ws, S.L.best);
+  int64_t *value = at<int64_t>(S.ws, S.L.value), *best = S.best;
   const int32_t B = S.B;
   const float *start = S.x0;
   if (!start) {
@@ -850,8 +852,8 @@ TileArgs tile_args(Solve &S, const TileCfg &c, const float *x0) {
   a.rho = S.p->rho;
   a.seed = S.p->seed;
   a.x0 = x0;
-  a.zbest = at<int8_t>(S.ws, S.L.Zb);
-  a.best = at<int64_t>(S.ws, S.L.best);
+  a.zbest = S.Zb;
+  a.best = S.best;
   a.zs = at<int8_t>(S.ws, S.L.tzs);
   a.nb = at<int32_t>(S.ws, S.L.tnb);
   a.prio = at<uint32_t>(S.ws, S.L.tprio);
@@ -1037,8 +1039,8 @@ int settle_deferred(Solve &S) {
 // scratch serve as scratch.
 int final_search(Solve &S, int64_t *alternations) {
   TRY(settle_deferred(S));
-  int8_t *Z = at<int8_t>(S.ws, S.L.Z), *Zb = at<int8_t>(S.ws, S.L.Zb);
-  int64_t *value = at<int64_t>(S.ws, S.L.value), *best = at<int64_t>(S.ws, S.L.best);
+  int8_t *Z = at<int8_t>(S.ws, S.L.Z), *Zb = S.Zb;
+  int64_t *value = at<int64_t>(S.ws, S.L.value), *best = S.best;
   const int32_t B = S.B;
   HIP_TRY(hipMemcpyAsync(Z, Zb, (size_t)S.g->n_total * B, hipMemcpyDeviceToDevice, S.s));
   TRY(pair_core(S.maxcut, S.g, S.p->seed, S.p->rounds, Z, at<int32_t>(S.ws, S.L.NB), at<uint32_t>(S.ws, S.L.PRIO),
@@ -1115,6 +1117,8 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
   S.L = L;
   S.s = s;
   S.x0 = x0;
+  S.Zb = r->traj_best_x ? r->traj_best_x : at<int8_t>(ws, L.Zb);
+  S.best = r->traj_best_value ? r->traj_best_value : at<int64_t>(ws, L.best);
 
   int64_t *voff = at<int64_t>(ws, L.voff);
   const size_t nvo = (size_t)g->num_graphs + 1;
@@ -1156,7 +1160,7 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
       TRY(final_search(S, &final_alt));
   }
 
-  int64_t *best = at<int64_t>(ws, L.best);
+  int64_t *best = S.best;
   int32_t *bestb = at<int32_t>(ws, L.bestb);
   if (K) {  // the answer is the best pool member
     launch_pick_best(PV, S.G, K, r->best_value, bestb, s);
@@ -1166,12 +1170,9 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
       HIP_TRY(hipMemcpyAsync(r->pool_value, PV, (size_t)S.G * K * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
   } else {
     launch_pick_best(best, S.G, S.B, r->best_value, bestb, s);
-    launch_copy_best_x(at<int8_t>(ws, L.Zb), S.B, voff, S.G, bestb, r->best_x, g->n_total, s);
+    launch_copy_best_x(S.Zb, S.B, voff, S.G, bestb, r->best_x, g->n_total, s);
   }
-  if (r->traj_best_value)
-    HIP_TRY(hipMemcpyAsync(r->traj_best_value, best, (size_t)S.G * S.B * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-  if (r->traj_best_x)
-    HIP_TRY(hipMemcpyAsync(r->traj_best_x, at<int8_t>(ws, L.Zb), (size_t)g->n_total * S.B, hipMemcpyDeviceToDevice, s));
+  // traj_best_value / traj_best_x, when given, held the incumbents all along
   // exact edge updates: sum over trajectories of executed steps x nnz of the graph
   int64_t *eu_dev = at<int64_t>(ws, L.dmax);  // max degree is on the host already
   launch_edge_updates(at<int64_t>(ws, L.steps), at<int32_t>(ws, L.rpat), S.G, S.B, eu_dev, s);

@@ -663,9 +663,18 @@ template <bool MC, bool W, int VEC, bool CL, int DREG, int IPT>
 static hipError_t tile_launch_t(const TileArgs &a, int threads, hipStream_t s) {
   const size_t lds = tile_lds_bytes(a.n_max, a.T, a.nnz_max, CL, DREG > 0);
   auto kern = k_tile_round<MC, W, VEC, CL, DREG, IPT>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  // the dynamic-LDS limit only ever grows; raise it when a launch needs more
+  // (per device; callers hold the library's host lock)
+  static int limit_set[64] = {0};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64 || (int)lds > limit_set[dev]) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+    if (e != hipSuccess) return e;
+    if (dev >= 0 && dev < 64) limit_set[dev] = (int)lds;
+  }
   hipLaunchKernelGGL(kern, dim3((unsigned)(a.G * a.tiles)), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
