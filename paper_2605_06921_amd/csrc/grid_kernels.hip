@@ -716,6 +716,34 @@ __global__ __launch_bounds__(256) void k_swap_propose(GraphView g, const int8_t 
   const int32_t beg = __builtin_amdgcn_readfirstlane(g.row_ptr[v]);
   const int32_t deg = __builtin_amdgcn_readfirstlane(g.row_ptr[v + 1]) - beg;
   const int32_t nk = (deg + 63) >> 6;
+  // The row's neighbours and their tightness words do not depend on the
+  // column: the first 128 are loaded once per wavefront into registers.
+  int32_t ru0 = 0, ru1 = 0;
+  unsigned long long rt0 = 0ull, rt1 = 0ull;
+  if (act) {  // uniform: some column has v in I
+    if (lane < deg) {
+      ru0 = g.col_idx[beg + lane];
+      rt0 = TB[(int64_t)ru0 * nchunk + blockIdx.y];
+    }
+    if (nk > 1 && 64 + lane < deg) {
+      ru1 = g.col_idx[beg + 64 + lane];
+      rt1 = TB[(int64_t)ru1 * nchunk + blockIdx.y];
+    }
+  }
+  // neighbour chunk k of the row: its ids and tightness words (0 past the row)
+  auto chunk = [&](int32_t k, int32_t &uk, unsigned long long &tk) {
+    if (k == 0) {
+      uk = ru0;
+      tk = rt0;
+    } else if (k == 1) {
+      uk = ru1;
+      tk = rt1;
+    } else {
+      const int32_t pk = 64 * k + lane;
+      uk = pk < deg ? g.col_idx[beg + pk] : 0;
+      tk = pk < deg ? TB[(int64_t)uk * nchunk + blockIdx.y] : 0ull;
+    }
+  };
   int32_t my_u = -1, my_w = -1;  // lane l: result of column c0 + l
   while (act) {
     const int32_t c = __builtin_ctzll(act);
@@ -723,24 +751,40 @@ __global__ __launch_bounds__(256) void k_swap_propose(GraphView g, const int8_t 
     bool found = false;
     int32_t fu = -1, fw = -1;
     for (int32_t k = 0; k < nk && !found; ++k) {
-      const int32_t pk = 64 * k + lane;
-      const int32_t uk = pk < deg ? g.col_idx[beg + pk] : 0;
-      const bool tk = pk < deg && ((TB[(int64_t)uk * nchunk + blockIdx.y] >> c) & 1ull);
-      unsigned long long mk = __ballot(tk);
+      int32_t uk;
+      unsigned long long tbk;
+      chunk(k, uk, tbk);
+      unsigned long long mk = __ballot(((tbk >> c) & 1ull) != 0);
       while (mk && !found) {
         const int32_t i = __builtin_ctzll(mk);
         mk &= mk - 1;
         const int32_t u = __builtin_amdgcn_readlane(uk, i);
+        // u's row across the lanes (the first 128 neighbours kept in
+        // registers); a partner w is adjacent to u iff some lane holds w
+        const int32_t ub = __builtin_amdgcn_readfirstlane(g.row_ptr[u]);
+        const int32_t ud = __builtin_amdgcn_readfirstlane(g.row_ptr[u + 1]) - ub;
+        const int32_t un0 = lane < ud ? g.col_idx[ub + lane] : -1;
+        const int32_t un1 = 64 + lane < ud ? g.col_idx[ub + 64 + lane] : -1;
         for (int32_t k2 = k; k2 < nk && !found; ++k2) {
-          const int32_t p2 = 64 * k2 + lane;
-          const int32_t w2 = p2 < deg ? g.col_idx[beg + p2] : 0;
-          const bool t2 = p2 < deg && (k2 > k || lane > i) && ((TB[(int64_t)w2 * nchunk + blockIdx.y] >> c) & 1ull);
-          const bool ok = t2 && !has_edge(g, u, w2);
-          const unsigned long long b = __ballot(ok);
-          if (b) {
-            fu = u;
-            fw = __builtin_amdgcn_readlane(w2, __builtin_ctzll(b));
-            found = true;
+          int32_t w2;
+          unsigned long long tb2;
+          chunk(k2, w2, tb2);
+          const bool t2 = (k2 > k || lane > i) && ((tb2 >> c) & 1ull);
+          unsigned long long cm = __ballot(t2);  // candidate partners, in CSR order
+          while (cm && !found) {
+            const int32_t j = __builtin_ctzll(cm);
+            cm &= cm - 1;
+            const int32_t w = __builtin_amdgcn_readlane(w2, j);
+            bool adj = __ballot(un0 == w || un1 == w) != 0;
+            for (int32_t m = 128; m < ud && !adj; m += 64) {
+              const int32_t x = m + lane < ud ? g.col_idx[ub + m + lane] : -1;
+              adj = __ballot(x == w) != 0;
+            }
+            if (!adj) {
+              fu = u;
+              fw = w;
+              found = true;
+            }
           }
         }
       }
