@@ -549,7 +549,8 @@ int pair_core(bool maxcut, const mqo_graph *g, uint64_t seed, int32_t round, int
     launch_pair_candidates(maxcut, all, Z, NB, PRIO_SW, T0, T1, T2, TB, B, B,
                            (double)g->nnz_total / (double)std::max<int64_t>(1, g->n_total), s);
     if (cand_ms) (void)hipEventRecord(ev[1], s);
-    launch_pair_apply(maxcut, all, Z, NB, PRIO_SW, F, T0, T1, T2, act, B, B, s);
+    launch_pair_apply(maxcut, all, Z, NB, PRIO_SW, F, T0, T1, T2, act, B, B,
+                      (double)g->nnz_total / (double)std::max<int64_t>(1, g->n_total), s);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
       rc = fail(MQO_ERR_HIP, "pair iteration: %s", hipGetErrorString(e));

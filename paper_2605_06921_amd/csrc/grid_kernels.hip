@@ -896,6 +896,90 @@ __global__ __launch_bounds__(256) void k_swap_apply(GraphView g, const int8_t *_
   }
 }
 
+// The same selection and application with one wavefront per (row v, 64
+// columns), for graphs of large mean degree: each proposing column's
+// inserted vertices are scanned with the lanes over their neighbours (one
+// coalesced index load and one owner gather per 64 neighbours) instead of
+// one lane walking 2 x degree neighbours, and the neighbour-count updates
+// of a winner are issued 64 at a time.
+__global__ __launch_bounds__(256) void k_swap_select_rows(GraphView g, const int32_t *__restrict__ PU,
+                                                          const int32_t *__restrict__ PW,
+                                                          const int32_t *__restrict__ OWN,
+                                                          const uint32_t *__restrict__ PRIO, int8_t *__restrict__ F,
+                                                          int32_t *active, int32_t ncols, int32_t ld) {
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= g.n) return;  // the whole wavefront
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t c0 = (int32_t)blockIdx.y * 64;
+  const int32_t cc = ncols - c0 < 64 ? ncols - c0 : 64;
+  const int32_t v = __builtin_amdgcn_readfirstlane((int32_t)(g.lo + row));
+  const int64_t e = (int64_t)v * ld + c0 + lane;
+  const int32_t pu = lane < cc ? PU[e] : -1;
+  const int32_t pw = lane < cc ? PW[e] : -1;
+  const uint32_t pv = lane < cc ? PRIO[e] : 0u;
+  bool win = pu >= 0;
+  unsigned long long prop = __ballot(pu >= 0);
+  while (prop) {
+    const int32_t c = __builtin_ctzll(prop);
+    prop &= prop - 1;
+    const int32_t col = c0 + c;
+    const uint32_t pvc = (uint32_t)__builtin_amdgcn_readlane((int32_t)pv, c);
+    bool lose = false;
+    for (int k = 0; k < 2 && !lose; ++k) {
+      const int32_t x = __builtin_amdgcn_readlane(k ? pw : pu, c);
+      const int32_t xb = __builtin_amdgcn_readfirstlane(g.row_ptr[x]);
+      const int32_t xd = __builtin_amdgcn_readfirstlane(g.row_ptr[x + 1]) - xb;
+      for (int32_t m = 0; m < xd && !lose; m += 64) {
+        bool beats = false;
+        if (m + lane < xd) {
+          const int32_t y = g.col_idx[xb + m + lane];
+          const int32_t o = OWN[(int64_t)y * ld + col];
+          beats = o >= 0 && o != v && key_beats(0, PRIO[(int64_t)o * ld + col], o, 0, pvc, v);
+        }
+        lose = __ballot(beats) != 0;
+      }
+    }
+    if (lane == c) win = !lose;
+  }
+  const unsigned long long bal = __ballot(win);
+  if (win && lane == __builtin_ctzll(bal)) *active = 1;
+  if (lane < cc) F[e] = win ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_swap_apply_rows(GraphView g, const int8_t *__restrict__ F,
+                                                         const int32_t *__restrict__ PU,
+                                                         const int32_t *__restrict__ PW, int8_t *__restrict__ Z,
+                                                         int32_t *__restrict__ NB, const int32_t *active,
+                                                         int32_t ncols, int32_t ld) {
+  if (*active == 0) return;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= g.n) return;  // the whole wavefront
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t c0 = (int32_t)blockIdx.y * 64;
+  const int32_t cc = ncols - c0 < 64 ? ncols - c0 : 64;
+  const int32_t v = __builtin_amdgcn_readfirstlane((int32_t)(g.lo + row));
+  const int64_t e = (int64_t)v * ld + c0 + lane;
+  const bool f = lane < cc && F[e] != 0;
+  const int32_t pu = f ? PU[e] : -1;
+  const int32_t pw = f ? PW[e] : -1;
+  unsigned long long wins = __ballot(f);
+  while (wins) {
+    const int32_t c = __builtin_ctzll(wins);
+    wins &= wins - 1;
+    const int32_t col = c0 + c;
+    const int32_t x3[3] = {v, __builtin_amdgcn_readlane(pu, c), __builtin_amdgcn_readlane(pw, c)};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int32_t x = x3[k];
+      const int32_t d = k ? 1 : -1;
+      if (lane == 0) Z[(int64_t)x * ld + col] = (int8_t)(k ? 1 : 0);
+      const int32_t xb = __builtin_amdgcn_readfirstlane(g.row_ptr[x]);
+      const int32_t xd = __builtin_amdgcn_readfirstlane(g.row_ptr[x + 1]) - xb;
+      for (int32_t m = lane; m < xd; m += 64) atomicAdd(&NB[(int64_t)g.col_idx[xb + m] * ld + col], d);
+    }
+  }
+}
+
 // Total order of 2-flip pairs (gain, (prio_v + prio_u) mod 2^32, -min, -max):
 // true iff pair a beats pair b.
 __device__ __forceinline__ bool pair_beats(int32_t ga, uint32_t ha, int32_t mina, int32_t maxa, int32_t gb,
@@ -2031,7 +2115,7 @@ void launch_pair_candidates(bool maxcut, const GraphView &g, const int8_t *Z, co
 
 void launch_pair_apply(bool maxcut, const GraphView &g, int8_t *Z, int32_t *NB, const uint32_t *PRIO, int8_t *F,
                        const int32_t *T0, const int32_t *T1, const int32_t *T2, int32_t *active, int32_t ncols,
-                       int32_t ld, hipStream_t s) {
+                       int32_t ld, double mean_degree, hipStream_t s) {
   const int ll = lanes_log2_for(ncols);
   const dim3 grid = grid_rows(g.n, ncols, ll, 1, 256);
   if (maxcut) {
@@ -2042,8 +2126,14 @@ void launch_pair_apply(bool maxcut, const GraphView &g, int8_t *Z, int32_t *NB, 
     else
       MQO_LAUNCH(k_flip2_apply<false>, grid, dim3(256), 0, s, g, F, T2, Z, NB, active, ncols, ld, ll);
   } else {
-    MQO_LAUNCH(k_swap_select, grid, dim3(256), 0, s, g, T0, T1, T2, PRIO, F, active, ncols, ld, ll);
-    MQO_LAUNCH(k_swap_apply, grid, dim3(256), 0, s, g, F, T0, T1, Z, NB, active, ncols, ld, ll);
+    if (mean_degree >= 24.0) {
+      const dim3 wgrid = grid_rows(g.n, ncols, 6, 1, 256);  // one wavefront per (row, 64 columns)
+      MQO_LAUNCH(k_swap_select_rows, wgrid, dim3(256), 0, s, g, T0, T1, T2, PRIO, F, active, ncols, ld);
+      MQO_LAUNCH(k_swap_apply_rows, wgrid, dim3(256), 0, s, g, F, T0, T1, Z, NB, active, ncols, ld);
+    } else {
+      MQO_LAUNCH(k_swap_select, grid, dim3(256), 0, s, g, T0, T1, T2, PRIO, F, active, ncols, ld, ll);
+      MQO_LAUNCH(k_swap_apply, grid, dim3(256), 0, s, g, F, T0, T1, Z, NB, active, ncols, ld, ll);
+    }
   }
 }
 

@@ -69,7 +69,7 @@ void launch_pair_candidates(bool maxcut, const GraphView &g, const int8_t *Z, co
                             int32_t ld, double mean_degree, hipStream_t s);
 void launch_pair_apply(bool maxcut, const GraphView &g, int8_t *Z, int32_t *NB, const uint32_t *PRIO, int8_t *F,
                        const int32_t *T0, const int32_t *T1, const int32_t *T2, int32_t *active, int32_t ncols,
-                       int32_t ld, hipStream_t s);
+                       int32_t ld, double mean_degree, hipStream_t s);
 void launch_accept(const int8_t *Z, int8_t *Zb, const int64_t *value, int64_t *best, int64_t lo, int64_t n,
                    int32_t ncols, int32_t ld, int32_t ldb, bool first, hipStream_t s);
 size_t reset_scratch_bytes(int32_t ncols);
