@@ -44,14 +44,17 @@ def source_sha256(path):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(workload, kernel):
+def measured_traffic(workload, kernel, tile=None):
     """HBM bytes per launch of `kernel` on `workload` from the committed
     calibrated FETCH_SIZE / WRITE_SIZE counter runs, or None when there is
-    no record or the kernel source changed since the counters were taken."""
+    no record, the kernel source changed since the counters were taken, or
+    the record was taken on another persistent-plan shape than `tile`."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     rec = json.load(open(TRAFFIC_FILE)).get(workload, {}).get(kernel)
     if not rec or rec.get("source_sha256") != source_sha256(KERNEL_SOURCES[kernel]):
+        return None
+    if tile is not None and rec.get("tile", tile) != tile:
         return None
     return rec["hbm_bytes_per_launch"]
 
@@ -245,13 +248,22 @@ def bench_toy(args):
                            delta=delta, mean_attempts_to_hit=float(f[f >= 0].mean()),
                            full_restart_n12_success_fraction_within_4096=float((rs >= 0).mean()),
                            full_restart_n12_exact=float(1 - (1 - 2.0 ** -12) ** 4097)))
-    # ALU-bound: 5 float32 operations per descent step (the clip is two
-    # compares, not counted), 128 steps per attempt; Philox and the float64
-    # acceptance test are extra work not counted
+    # ALU-bound: 5 float32 operations per descent step (the clip is one
+    # more instruction, not counted), 128 steps per attempt; Philox and the
+    # float64 acceptance test are extra work not counted.  Peak for this
+    # mix: every operation is rounded on its own (no fused multiply-add)
+    # and packed float32 is not used, so each lane retires one flop per
+    # clock: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.  The published 157.3
+    # TFLOP/s counts packed fused multiply-adds (4 flops per lane-clock).
     flops = 5.0 * steps * attempts
-    res["roofline"] = dict(bound="alu", achieved=flops / gpu_s / 1e12, peak=157.3, unit="TFLOP/s",
-                           frac=flops / gpu_s / 157.3e12, traffic=None, kernel="k_toy_global_reset",
-                           avg_launch_ms=1e3 * gpu_s / args.steps, flops_per_launch=flops / args.steps)
+    alu_peak = 256 * 64 * 2.4e9
+    res["roofline"] = dict(bound="alu", achieved=flops / gpu_s / 1e12, peak=alu_peak / 1e12, unit="TFLOP/s",
+                           frac=flops / gpu_s / alu_peak, traffic=None, kernel="k_toy_global_reset",
+                           avg_launch_ms=1e3 * gpu_s / args.steps, flops_per_launch=flops / args.steps,
+                           published_peak=157.3, frac_of_published=flops / gpu_s / 157.3e12,
+                           issue_slots_per_step=6,
+                           note="peak = 256 CUs x 64 lanes x 2.4 GHz, one separately rounded float32 "
+                                "operation per lane-clock; the clamp takes a sixth issue slot per step")
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline (toy)")
         T = 256
@@ -443,7 +455,11 @@ def main():
     avg_launch_s = kms / 1e3 / max(1, klaunch)
     achieved = per_launch_bytes / avg_launch_s
     kernel = "k_tile_round" if out["plan"] == "persistent" else "k_pga_step"
-    traffic = measured_traffic(wl.name, kernel)
+    tile = None
+    if out["plan"] == "persistent":
+        tile = ",".join(str(out[k]) for k in ("tile_cols", "tile_threads", "tile_vec", "tile_csr_lds",
+                                              "tile_reg_degree"))
+    traffic = measured_traffic(wl.name, kernel, tile)
     res["roofline"] = dict(bound="hbm", achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
                            frac=achieved / HBM_PEAK, traffic=traffic, kernel=kernel,
                            avg_launch_ms=avg_launch_s * 1e3, algorithmic_bytes_per_launch=per_launch_bytes,
