@@ -446,26 +446,34 @@ int init_x(Solve &S, float *X) {
   return MQO_OK;
 }
 
+// Mean degree of a batch: it only selects kernel shapes (one wavefront per
+// row for the searches on dense graphs), never results.
+double mean_degree_of(const mqo_graph *g) {
+  return (double)g->nnz_total / (double)std::max<int64_t>(1, g->n_total);
+}
+
 // 1-flip local search on columns [traj0, traj0+ncols) of one graph (arrays
 // at ld).  Iterations are enqueued Q at a time; each one is skipped on the
 // device once an earlier one found no positive gain, and the host reads the
 // Q flags to decide whether to continue.
-int ls_loop(bool maxcut, const GraphView &gv, int64_t nnz_total, int8_t *Z, int32_t *NB, const uint32_t *PRIO,
-            int8_t *F, int32_t *act, int32_t ncols, int32_t ld, hipStream_t s, int64_t *iters_out);
+int ls_loop(bool maxcut, const GraphView &gv, int64_t nnz_total, double mean_degree, int8_t *Z, int32_t *NB,
+            const uint32_t *PRIO, int8_t *F, int32_t *act, int32_t ncols, int32_t ld, hipStream_t s,
+            int64_t *iters_out);
 
-int ls_core(bool maxcut, const GraphView &gv, int64_t nnz_total, uint64_t seed, int32_t round, int8_t *Z, int32_t *NB,
-            uint32_t *PRIO, int8_t *F, int32_t *act, long long *acc, int64_t *value_scratch, int32_t ncols,
-            int32_t ld, uint64_t traj0, hipStream_t s, int64_t *iters_out) {
+int ls_core(bool maxcut, const GraphView &gv, int64_t nnz_total, double mean_degree, uint64_t seed, int32_t round,
+            int8_t *Z, int32_t *NB, uint32_t *PRIO, int8_t *F, int32_t *act, long long *acc, int64_t *value_scratch,
+            int32_t ncols, int32_t ld, uint64_t traj0, hipStream_t s, int64_t *iters_out) {
   // neighbour counts for the current Z (the values computed here are discarded)
   launch_evaluate(maxcut, gv, Z, NB, acc, value_scratch, nullptr, nullptr, ncols, ld, s);
   launch_ls_prio(PRIO, gv.lo, gv.n, ncols, ld, seed, traj0, (uint64_t)round, s);
-  return ls_loop(maxcut, gv, nnz_total, Z, NB, PRIO, F, act, ncols, ld, s, iters_out);
+  return ls_loop(maxcut, gv, nnz_total, mean_degree, Z, NB, PRIO, F, act, ncols, ld, s, iters_out);
 }
 
 // The iterations of the 1-flip search on rows gv (NB = A Z and the
 // priorities already in place).
-int ls_loop(bool maxcut, const GraphView &gv, int64_t nnz_total, int8_t *Z, int32_t *NB, const uint32_t *PRIO,
-            int8_t *F, int32_t *act, int32_t ncols, int32_t ld, hipStream_t s, int64_t *iters_out) {
+int ls_loop(bool maxcut, const GraphView &gv, int64_t nnz_total, double mean_degree, int8_t *Z, int32_t *NB,
+            const uint32_t *PRIO, int8_t *F, int32_t *act, int32_t ncols, int32_t ld, hipStream_t s,
+            int64_t *iters_out) {
   const int Q = 8;
   int64_t iters = 0;
   const int64_t cap = 4 * (gv.n + nnz_total) + 64;  // never reached: every iteration gains
@@ -473,7 +481,7 @@ int ls_loop(bool maxcut, const GraphView &gv, int64_t nnz_total, int8_t *Z, int3
   while (true) {
     launch_fill_i32(act, Q, 0, s);
     for (int q = 0; q < Q; ++q)
-      launch_ls_iteration(maxcut, gv, Z, NB, PRIO, F, act + q, q ? act + q - 1 : nullptr, ncols, ld, s);
+      launch_ls_iteration(maxcut, gv, Z, NB, PRIO, F, act + q, q ? act + q - 1 : nullptr, ncols, ld, mean_degree, s);
     HIP_TRY(hipGetLastError());
     TRY(read_back_i32(act, Q, flags, s));
     int done = 0;
@@ -541,16 +549,14 @@ int pair_core(bool maxcut, const mqo_graph *g, uint64_t seed, int32_t round, int
   int rc = MQO_OK;
   while (rc == MQO_OK) {
     int64_t it = 0;
-    rc = ls_loop(maxcut, all, g->nnz_total, Z, NB, PRIO, F, act, B, B, s, &it);
+    rc = ls_loop(maxcut, all, g->nnz_total, mean_degree_of(g), Z, NB, PRIO, F, act, B, B, s, &it);
     if (rc != MQO_OK) break;
     if (ls_iters) *ls_iters += it;
     launch_fill_i32(act, 1, 0, s);
     if (cand_ms) (void)hipEventRecord(ev[0], s);
-    launch_pair_candidates(maxcut, all, Z, NB, PRIO_SW, T0, T1, T2, TB, B, B,
-                           (double)g->nnz_total / (double)std::max<int64_t>(1, g->n_total), s);
+    launch_pair_candidates(maxcut, all, Z, NB, PRIO_SW, T0, T1, T2, TB, B, B, mean_degree_of(g), s);
     if (cand_ms) (void)hipEventRecord(ev[1], s);
-    launch_pair_apply(maxcut, all, Z, NB, PRIO_SW, F, T0, T1, T2, act, B, B,
-                      (double)g->nnz_total / (double)std::max<int64_t>(1, g->n_total), s);
+    launch_pair_apply(maxcut, all, Z, NB, PRIO_SW, F, T0, T1, T2, act, B, B, mean_degree_of(g), s);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
       rc = fail(MQO_ERR_HIP, "pair iteration: %s", hipGetErrorString(e));
@@ -575,8 +581,9 @@ int pair_core(bool maxcut, const mqo_graph *g, uint64_t seed, int32_t round, int
 
 int run_local_search(Solve &S, const GraphView &gv, int8_t *Z, int32_t *NB, uint32_t *PRIO, int8_t *F, int32_t ncols,
                      int32_t ld, uint64_t traj0, int32_t round, int64_t *iters_out) {
-  return ls_core(S.maxcut, gv, S.g->nnz_total, S.p->seed, round, Z, NB, PRIO, F, at<int32_t>(S.ws, S.L.act),
-                 at<long long>(S.ws, S.L.acc), at<int64_t>(S.ws, S.L.value), ncols, ld, traj0, S.s, iters_out);
+  return ls_core(S.maxcut, gv, S.g->nnz_total, mean_degree_of(S.g), S.p->seed, round, Z, NB, PRIO, F,
+                 at<int32_t>(S.ws, S.L.act), at<long long>(S.ws, S.L.acc), at<int64_t>(S.ws, S.L.value), ncols, ld,
+                 traj0, S.s, iters_out);
 }
 
 // steps on one graph, ping-pong X <-> Xt, result back in X
@@ -1493,7 +1500,8 @@ int mqo_local_search(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t 
   int32_t *NB = at<int32_t>(ws, L.NB);
   launch_evaluate(mc, all, Z, NB, at<long long>(ws, L.acc), at<int64_t>(ws, L.value), nullptr, nullptr, B, B, s);
   int64_t it = 0;
-  TRY(ls_loop(mc, all, g->nnz_total, Z, NB, PRIO, at<int8_t>(ws, L.F), at<int32_t>(ws, L.act), B, B, s, &it));
+  TRY(ls_loop(mc, all, g->nnz_total, mean_degree_of(g), Z, NB, PRIO, at<int8_t>(ws, L.F), at<int32_t>(ws, L.act), B,
+              B, s, &it));
   if (iterations) *iterations = it;
   return MQO_OK;
 }

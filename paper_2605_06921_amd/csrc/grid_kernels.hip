@@ -645,6 +645,118 @@ __global__ __launch_bounds__(256) void k_ls_apply(GraphView g, const int8_t *__r
   }
 }
 
+// The same iteration with one wavefront per (row v, 64 columns), for graphs
+// of large mean degree.  When few of the 64 columns move (the usual case
+// once the search has settled) each candidate column's neighbours are tested
+// 64 at a time, one lane per neighbour and a ballot, and a flipped column's
+// count updates are issued 64 at a time; with many, every lane walks the
+// row for its own column as above.  F and the updates are the same either
+// way: a candidate wins iff no neighbouring candidate has a larger key.
+constexpr int LS_ROW_FEW = 16;
+
+template <bool MAXCUT>
+__global__ __launch_bounds__(256) void k_ls_select_rows(GraphView g, const int8_t *__restrict__ Z,
+                                                        const int32_t *__restrict__ NB,
+                                                        const uint32_t *__restrict__ PRIO, int8_t *__restrict__ F,
+                                                        int32_t *active, const int32_t *prev_active, int32_t ncols,
+                                                        int32_t ld) {
+  if (prev_active && *prev_active == 0) return;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= g.n) return;  // the whole wavefront
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t c0 = (int32_t)blockIdx.y * 64;
+  const int32_t cc = ncols - c0 < 64 ? ncols - c0 : 64;
+  const int32_t v = __builtin_amdgcn_readfirstlane((int32_t)(g.lo + row));
+  const int64_t e = (int64_t)v * ld + c0 + lane;
+  int32_t k1 = 0;
+  const bool p = lane < cc && ls_candidate_t<MAXCUT>(Z[e], NB[e], k1);
+  const uint32_t pv = p ? PRIO[e] : 0u;
+  unsigned long long cand = __ballot(p);
+  if (p && lane == __builtin_ctzll(cand)) *active = 1;
+  bool win = p;
+  if (cand) {
+    const int32_t vb = __builtin_amdgcn_readfirstlane(g.row_ptr[v]);
+    const int32_t vd = __builtin_amdgcn_readfirstlane(g.row_ptr[v + 1]) - vb;
+    if (__builtin_popcountll(cand) > LS_ROW_FEW) {
+      if (p) {
+        const int64_t col = c0 + lane;
+        for (int32_t j = 0; j < vd; ++j) {
+          const int32_t u = g.col_idx[vb + j];
+          const int64_t eu = (int64_t)u * ld + col;
+          int32_t k1u;
+          if (ls_candidate_t<MAXCUT>(Z[eu], NB[eu], k1u) && key_beats(k1u, PRIO[eu], u, k1, pv, v)) {
+            win = false;
+            break;
+          }
+        }
+      }
+    } else {
+      // the row's first 128 neighbours stay in registers across columns
+      const int32_t u0 = lane < vd ? g.col_idx[vb + lane] : 0;
+      const int32_t u1 = 64 + lane < vd ? g.col_idx[vb + 64 + lane] : 0;
+      while (cand) {
+        const int32_t c = __builtin_ctzll(cand);
+        cand &= cand - 1;
+        const int64_t col = c0 + c;
+        const int32_t k1c = __builtin_amdgcn_readlane(k1, c);
+        const uint32_t pvc = (uint32_t)__builtin_amdgcn_readlane((int32_t)pv, c);
+        bool lose = false;
+        for (int32_t m = 0; m < vd && !lose; m += 64) {
+          bool beats = false;
+          if (m + lane < vd) {
+            const int32_t u = m == 0 ? u0 : m == 64 ? u1 : g.col_idx[vb + m + lane];
+            const int64_t eu = (int64_t)u * ld + col;
+            int32_t k1u;
+            beats = ls_candidate_t<MAXCUT>(Z[eu], NB[eu], k1u) && key_beats(k1u, PRIO[eu], u, k1c, pvc, v);
+          }
+          lose = __ballot(beats) != 0;
+        }
+        if (lane == c) win = !lose;
+      }
+    }
+  }
+  if (lane < cc) F[e] = win ? 1 : 0;
+}
+
+template <bool MAXCUT, bool WEIGHTED>
+__global__ __launch_bounds__(256) void k_ls_apply_rows(GraphView g, const int8_t *__restrict__ F,
+                                                       int8_t *__restrict__ Z, int32_t *__restrict__ NB,
+                                                       const int32_t *active, int32_t ncols, int32_t ld) {
+  if (*active == 0) return;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= g.n) return;  // the whole wavefront
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t c0 = (int32_t)blockIdx.y * 64;
+  const int32_t cc = ncols - c0 < 64 ? ncols - c0 : 64;
+  const int32_t v = __builtin_amdgcn_readfirstlane((int32_t)(g.lo + row));
+  const int64_t e = (int64_t)v * ld + c0 + lane;
+  const bool f = lane < cc && F[e] != 0;
+  int32_t d = 0;
+  if (f) {
+    const int32_t z = Z[e];
+    const int32_t zn = MAXCUT ? -z : 1 - z;
+    Z[e] = (int8_t)zn;
+    d = zn - z;
+  }
+  unsigned long long fl = __ballot(f);
+  if (!fl) return;
+  const int32_t vb = __builtin_amdgcn_readfirstlane(g.row_ptr[v]);
+  const int32_t vd = __builtin_amdgcn_readfirstlane(g.row_ptr[v + 1]) - vb;
+  if (__builtin_popcountll(fl) > LS_ROW_FEW) {
+    if (f)
+      for (int32_t j = 0; j < vd; ++j)
+        atomicAdd(&NB[(int64_t)g.col_idx[vb + j] * ld + c0 + lane], WEIGHTED ? d * g.weight[vb + j] : d);
+    return;
+  }
+  while (fl) {
+    const int32_t c = __builtin_ctzll(fl);
+    fl &= fl - 1;
+    const int32_t dc = __builtin_amdgcn_readlane(d, c);
+    for (int32_t m = lane; m < vd; m += 64)
+      atomicAdd(&NB[(int64_t)g.col_idx[vb + m] * ld + c0 + c], WEIGHTED ? dc * g.weight[vb + m] : dc);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // pair moves of the paper's own searches, parallel rule: the (1,2)-swap of
 // Def. 2.3 (MIS) and the 2-flip of Def. 2.5 (MaxCut).  One thread per
@@ -2138,10 +2250,25 @@ void launch_pair_apply(bool maxcut, const GraphView &g, int8_t *Z, int32_t *NB, 
 }
 
 void launch_ls_iteration(bool maxcut, const GraphView &g, int8_t *Z, int32_t *NB, const uint32_t *PRIO, int8_t *F,
-                         int32_t *active, const int32_t *prev_active, int32_t ncols, int32_t ld, hipStream_t s) {
+                         int32_t *active, const int32_t *prev_active, int32_t ncols, int32_t ld, double mean_degree,
+                         hipStream_t s) {
   const int ll = lanes_log2_for(ncols);
   const dim3 grid = grid_rows(g.n, ncols, ll, 1, 256);
   const bool w = g.weight != nullptr;
+  if (mean_degree >= 24.0) {
+    const dim3 wgrid = grid_rows(g.n, ncols, 6, 1, 256);  // one wavefront per (row, 64 columns)
+    if (maxcut) {
+      MQO_LAUNCH(k_ls_select_rows<true>, wgrid, dim3(256), 0, s, g, Z, NB, PRIO, F, active, prev_active, ncols, ld);
+      if (w)
+        MQO_LAUNCH((k_ls_apply_rows<true, true>), wgrid, dim3(256), 0, s, g, F, Z, NB, active, ncols, ld);
+      else
+        MQO_LAUNCH((k_ls_apply_rows<true, false>), wgrid, dim3(256), 0, s, g, F, Z, NB, active, ncols, ld);
+    } else {
+      MQO_LAUNCH(k_ls_select_rows<false>, wgrid, dim3(256), 0, s, g, Z, NB, PRIO, F, active, prev_active, ncols, ld);
+      MQO_LAUNCH((k_ls_apply_rows<false, false>), wgrid, dim3(256), 0, s, g, F, Z, NB, active, ncols, ld);
+    }
+    return;
+  }
   if (maxcut) {
     MQO_LAUNCH(k_ls_select<true>, grid, dim3(256), 0, s, g, Z, NB, PRIO, F, active, prev_active, ncols, ld, ll);
     if (w)
@@ -2307,19 +2434,19 @@ void launch_reduce_partials(double *part, int64_t nblk, int32_t ncols, double *o
   int32_t wlog2 = 0;
   while ((1 << wlog2) < ncols && wlog2 < 6) ++wlog2;
   const unsigned cx = (unsigned)((ncols + (1 << wlog2) - 1) >> wlog2);
-  // levels of slices of 8 R partial rows (8 loads per thread), written after
-  // the partials, until one workgroup per column chunk finishes
-  const int64_t per = 8 * (int64_t)(256 >> wlog2);
+  // at most two launches: one workgroup per column chunk sums up to F = 8 R
+  // rows (8 loads per thread), so more than F partial rows first go through
+  // one level of at most F slices of at least F rows each, written after
+  // the partials (reduce_rows() leaves room for nblk / F + 1 of them)
+  const int64_t F = 8 * (int64_t)(256 >> wlog2);
   const double *src = part;
-  double *next = part + nblk * ncols;
   int64_t rows = nblk;
-  while (rows > per) {
-    int64_t p = per;
-    while ((rows + p - 1) / p > 65535) p *= 2;
+  if (rows > F) {
+    const int64_t p = std::max(F, (rows + F - 1) / F);
     const int64_t slices = (rows + p - 1) / p;
+    double *next = part + nblk * ncols;
     MQO_LAUNCH(k_reduce_partials, dim3(cx, (unsigned)slices), dim3(256), 0, s, src, rows, ncols, wlog2, p, next, 0);
     src = next;
-    next += slices * ncols;
     rows = slices;
   }
   MQO_LAUNCH(k_reduce_partials, dim3(cx, 1), dim3(256), 0, s, src, rows, ncols, wlog2, rows, out, (int32_t)accumulate);

@@ -54,7 +54,8 @@ void launch_evaluate(bool maxcut, const GraphView &g, const int8_t *Z, int32_t *
 void launch_ls_prio(uint32_t *PRIO, int64_t lo, int64_t n, int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0,
                     uint64_t round, hipStream_t s);
 void launch_ls_iteration(bool maxcut, const GraphView &g, int8_t *Z, int32_t *NB, const uint32_t *PRIO, int8_t *F,
-                         int32_t *active, const int32_t *prev_active, int32_t ncols, int32_t ld, hipStream_t s);
+                         int32_t *active, const int32_t *prev_active, int32_t ncols, int32_t ld, double mean_degree,
+                         hipStream_t s);
 // priorities of purpose SWAP for the pair moves
 void launch_swap_prio(uint32_t *PRIO, int64_t lo, int64_t n, int32_t ncols, int32_t ld, uint64_t seed,
                       uint64_t traj0, uint64_t round, hipStream_t s);

@@ -161,6 +161,37 @@ def test_local_search_bit_exact(mqo, name, B):
     assert it == max(its)
 
 
+DENSE_LS_CASES = {
+    # mean degree >= 24: one wavefront per (row, 64 columns); random starts
+    # move many columns of a row at first (each lane walks the row) and few
+    # later (lanes over the neighbours)
+    "mis_dense": ("mis", graphs.concat([graphs.erdos_renyi(150, 0.3, 4904), graphs.erdos_renyi(90, 0.5, 4905),
+                                        graphs.complete(5)])),
+    "cut_dense": ("maxcut", graphs.concat([graphs.erdos_renyi(130, 0.35, 4906), graphs.complete(7)])),
+    "cut_dense_weighted": ("maxcut", graphs.with_weights(graphs.erdos_renyi(140, 0.3, 4907), 4908,
+                                                         values=(-2, -1, 1, 3))),
+}
+
+
+@pytest.mark.parametrize("name", list(DENSE_LS_CASES))
+@pytest.mark.parametrize("B", [1, 5, 64, 130])
+def test_local_search_dense_rows_bit_exact(mqo, name, B):
+    kind, g = DENSE_LS_CASES[name]
+    assert g.nnz / g.n >= 24
+    dg = mqo.DeviceGraph(g, DEV)
+    Z0 = arrays.binary01((g.n, B), 62) if kind == "mis" else arrays.spins((g.n, B), 62)
+    Z = torch.from_numpy(Z0.copy()).to(DEV)
+    it = mqo.local_search(kind, dg, Z, seed=98, rnd=2)
+    got = Z.cpu().numpy()
+    its = []
+    for gi in range(g.num_graphs):
+        lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+        ref, i = discrete.local_search(kind, g.subgraph(gi), Z0[lo:hi], 98, gi * B + np.arange(B), 2)
+        assert np.array_equal(got[lo:hi], ref)
+        its.append(i)
+    assert it == max(its)
+
+
 # --------------------------------------------------------------------------
 # a10 reset
 # --------------------------------------------------------------------------
