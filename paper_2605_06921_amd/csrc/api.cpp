@@ -453,9 +453,11 @@ double mean_degree_of(const mqo_graph *g) {
 }
 
 // 1-flip local search on columns [traj0, traj0+ncols) of one graph (arrays
-// at ld).  Iterations are enqueued Q at a time; each one is skipped on the
-// device once an earlier one found no positive gain, and the host reads the
-// Q flags to decide whether to continue.
+// at ld).  Iterations are enqueued Q at a time (Q = 2, 4, 8, 8, ...: a
+// search that is already near its end, as inside the pair searches, wastes
+// few launches); each one is skipped on the device once an earlier one
+// found no positive gain, and the host reads the Q flags to decide whether
+// to continue.
 int ls_loop(bool maxcut, const GraphView &gv, int64_t nnz_total, double mean_degree, int8_t *Z, int32_t *NB,
             const uint32_t *PRIO, int8_t *F, int32_t *act, int32_t ncols, int32_t ld, hipStream_t s,
             int64_t *iters_out);
@@ -474,7 +476,8 @@ int ls_core(bool maxcut, const GraphView &gv, int64_t nnz_total, double mean_deg
 int ls_loop(bool maxcut, const GraphView &gv, int64_t nnz_total, double mean_degree, int8_t *Z, int32_t *NB,
             const uint32_t *PRIO, int8_t *F, int32_t *act, int32_t ncols, int32_t ld, hipStream_t s,
             int64_t *iters_out) {
-  const int Q = 8;
+  constexpr int QMAX = 8;  // flags in act
+  int Q = 2;
   int64_t iters = 0;
   const int64_t cap = 4 * (gv.n + nnz_total) + 64;  // never reached: every iteration gains
   std::vector<int32_t> flags;
@@ -495,6 +498,7 @@ int ls_loop(bool maxcut, const GraphView &gv, int64_t nnz_total, double mean_deg
     }
     if (done) break;
     if (iters > cap) return fail(MQO_ERR_INTERNAL, "local search did not terminate");
+    Q = std::min(2 * Q, QMAX);
   }
   if (iters_out) *iters_out = iters;
   return MQO_OK;
