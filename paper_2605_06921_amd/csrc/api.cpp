@@ -453,14 +453,14 @@ double mean_degree_of(const mqo_graph *g) {
 }
 
 // 1-flip local search on columns [traj0, traj0+ncols) of one graph (arrays
-// at ld).  Iterations are enqueued Q at a time (Q = 2, 4, 8, 8, ...: a
-// search that is already near its end, as inside the pair searches, wastes
-// few launches); each one is skipped on the device once an earlier one
-// found no positive gain, and the host reads the Q flags to decide whether
-// to continue.
+// at ld).  Iterations are enqueued Q at a time; each one is skipped on the
+// device once an earlier one found no positive gain, and the host reads the
+// Q flags to decide whether to continue.  Q starts at q_first and doubles
+// up to 8: the searches inside the pair searches, which start at or near
+// a 1-flip optimum, start at 2 and waste few launches.
 int ls_loop(bool maxcut, const GraphView &gv, int64_t nnz_total, double mean_degree, int8_t *Z, int32_t *NB,
             const uint32_t *PRIO, int8_t *F, int32_t *act, int32_t ncols, int32_t ld, hipStream_t s,
-            int64_t *iters_out);
+            int64_t *iters_out, int q_first = 8);
 
 int ls_core(bool maxcut, const GraphView &gv, int64_t nnz_total, double mean_degree, uint64_t seed, int32_t round,
             int8_t *Z, int32_t *NB, uint32_t *PRIO, int8_t *F, int32_t *act, long long *acc, int64_t *value_scratch,
@@ -475,9 +475,9 @@ int ls_core(bool maxcut, const GraphView &gv, int64_t nnz_total, double mean_deg
 // priorities already in place).
 int ls_loop(bool maxcut, const GraphView &gv, int64_t nnz_total, double mean_degree, int8_t *Z, int32_t *NB,
             const uint32_t *PRIO, int8_t *F, int32_t *act, int32_t ncols, int32_t ld, hipStream_t s,
-            int64_t *iters_out) {
+            int64_t *iters_out, int q_first) {
   constexpr int QMAX = 8;  // flags in act
-  int Q = 2;
+  int Q = std::max(1, std::min(q_first, QMAX));
   int64_t iters = 0;
   const int64_t cap = 4 * (gv.n + nnz_total) + 64;  // never reached: every iteration gains
   std::vector<int32_t> flags;
@@ -553,7 +553,7 @@ int pair_core(bool maxcut, const mqo_graph *g, uint64_t seed, int32_t round, int
   int rc = MQO_OK;
   while (rc == MQO_OK) {
     int64_t it = 0;
-    rc = ls_loop(maxcut, all, g->nnz_total, mean_degree_of(g), Z, NB, PRIO, F, act, B, B, s, &it);
+    rc = ls_loop(maxcut, all, g->nnz_total, mean_degree_of(g), Z, NB, PRIO, F, act, B, B, s, &it, 2);
     if (rc != MQO_OK) break;
     if (ls_iters) *ls_iters += it;
     launch_fill_i32(act, 1, 0, s);
