@@ -1236,9 +1236,9 @@ int64_t max_graph_hubs(const mqo_graph *g) {
 
 // float64 partial rows of the objective / adjoint kernels of one graph: one
 // per row workgroup, one per hub row, then room for the reduction's slices
-size_t partial_count(const mqo_graph *g, int32_t B) {
+size_t partial_count(const mqo_graph *g, int32_t B, int32_t copies = 1) {
   const StepCfg cfg = default_step_cfg(B, B);
-  const int64_t nblk = grid_blocks_x(max_graph_rows(g), cfg) + max_graph_hubs(g);
+  const int64_t nblk = (grid_blocks_x(max_graph_rows(g), cfg) + max_graph_hubs(g)) * copies;
   return (size_t)(nblk + reduce_rows(nblk)) * B;
 }
 
@@ -1328,7 +1328,8 @@ int mqo_objective_grad(const mqo_graph *g, mqo_objective obj, float param, const
 size_t mqo_unrolled_workspace_size(const mqo_graph *g, int32_t B, int32_t ckpt_every) {
   if (check_graph_args(g, false) != MQO_OK || B < 1 || ckpt_every < 1) return 0;
   const size_t nb = (size_t)g->n_total * B * sizeof(float);
-  return align_up(nb) * (size_t)(ckpt_every + 3) + align_up(partial_count(g, B) * sizeof(double));
+  // the adjoint's float64 partials of one segment's ckpt_every steps, reduced together
+  return align_up(nb) * (size_t)(ckpt_every + 3) + align_up(partial_count(g, B, ckpt_every) * sizeof(double));
 }
 
 int mqo_pga_unrolled_forward(const mqo_graph *g, mqo_objective obj, float param, float alpha, int32_t K,
@@ -1403,11 +1404,14 @@ int mqo_pga_unrolled_backward(const mqo_graph *g, mqo_objective obj, float param
       states[0] = const_cast<float *>(ckpt + (int64_t)j * nb);
       for (int32_t i = 1; i < ckpt_every; ++i)
         launch_pga_step(form, gv, states[i - 1], states[i], nullptr, B, B, cfg, alpha, 0.0f, param, s);
+      // the segment's steps write consecutive partial slabs of nblk rows,
+      // summed in one fixed-order reduction per segment
       for (int32_t i = ckpt_every - 1; i >= 0; --i) {
-        launch_adjoint_step(form, gv, states[i], cur, mu, nxt, part, B, B, cfg, alpha, param, s);
-        launch_reduce_partials(part, nblk, B, dL_dalpha + (int64_t)gi * B, true, s);
+        double *slab = part + (int64_t)(ckpt_every - 1 - i) * nblk * B;
+        launch_adjoint_step(form, gv, states[i], cur, mu, nxt, slab, B, B, cfg, alpha, param, s);
         std::swap(cur, nxt);
       }
+      launch_reduce_partials(part, (int64_t)ckpt_every * nblk, B, dL_dalpha + (int64_t)gi * B, true, s);
     }
     launch_copy_f32(cur + gv.lo * B, dL_dX0 + gv.lo * B, gv.n * B, s);
   }
