@@ -19,8 +19,9 @@ With ``final_search`` the paper's own search (OneTwoSwap / OneTwoFlip,
 ``discrete.pair_search`` with round index ``rounds``) runs on every
 incumbent after the last round and replaces it when strictly better
 (Alg. 1 / Alg. 2, the local search after the reset loop).
-With ``restart_every`` = R > 0 the outer loop of Alg. 1-4 ("while the
-time budget permits: initialise, ...") is unrolled into the rounds: every
+With ``restart_every`` = R > 0 the outer loop of Alg. 1-4 (a fresh
+initialisation followed by reset rounds, repeated while time remains) is
+unrolled into the rounds: every
 round r > 0 with r % R == 0 starts from a fresh initial point (the
 initialisation rule, start index r // R) instead of a reset; acceptance,
 incumbents and the pool carry over.
