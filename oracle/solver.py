@@ -16,9 +16,12 @@ Round r = 0 .. rounds-1 of trajectory t = g*B + b:
   * exact evaluation; accept iff strictly better than the incumbent
     (Sec. 4), round 0 always initialises the incumbent.
 With ``final_search`` the paper's own search (OneTwoSwap / OneTwoFlip,
-``discrete.pair_search`` with round index ``rounds``) runs on every
-incumbent after the last round and replaces it when strictly better
-(Alg. 1 / Alg. 2, the local search after the reset loop).
+``discrete.pair_search``) runs at the end of every outer iteration (below;
+without ``restart_every`` the one iteration ends after the last round),
+with round index ``rounds + j`` for outer iteration j: on every incumbent,
+replacing it when strictly better, so the reset rounds of the next
+iteration start from the searched set (Alg. 1 / Alg. 2, the local search
+closing each pass of the outer loop).
 With ``restart_every`` = R > 0 the outer loop of Alg. 1-4 (a fresh
 initialisation followed by reset rounds, repeated while time remains) is
 unrolled into the rounds: every
@@ -30,9 +33,12 @@ Alg. 3 / Alg. 4: after every round the pool becomes the top K distinct
 solutions of the pool and the round's candidates (``discrete.pool_update``),
 and a round r > 0 restarts trajectory t from pool slot
 ``discrete.pool_bases`` (its own incumbent while the pool is empty).  The
-answer is then the best pool member, and ``final_search`` searches every
-pool member (trajectory ids g K + slot) instead of the incumbents,
-replacing a member when strictly better.
+graph also keeps its best set I_sol / S_sol, replaced by the best pool
+member after every round when that is strictly better; it is the answer.
+``final_search`` then leaves the pool alone and at the end of every outer
+iteration searches I_sol alone (MIS, Alg. 3, trajectory id g K) or every
+pool member (MaxCut, Alg. 4, trajectory ids g K + slot, offered to S_sol
+in slot order, each taken when strictly better).
 The answer of graph g is the best incumbent over its B trajectories, ties
 to the lowest b.
 Test infrastructure only.
@@ -91,6 +97,8 @@ def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32"
     if K:
         assert B == p.batch, "the pool couples all trajectories of a graph"
     pool_val, pool_z = np.zeros(0, dtype=np.int64), np.zeros((n, 0), dtype=np.int8)
+    NONE = int(np.iinfo(np.int64).min)
+    sol_val, sol_z = NONE, np.zeros(n, dtype=np.int8)  # I_sol / S_sol of the pool mode
     for r in range(p.rounds):
         fresh = r > 0 and p.restart_every > 0 and r % p.restart_every == 0
         start = r // p.restart_every if fresh else 0
@@ -133,25 +141,44 @@ def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32"
         zbest[:, take] = Z[:, take]
         if K:
             pool_val, pool_z = discrete.pool_update(kind, pool_val, pool_z, val, Z, K)
+            # Alg. 3 / Alg. 4: the best set follows the pool's best member
+            if len(pool_val) and pool_val[0] > sol_val:
+                sol_val, sol_z = int(pool_val[0]), pool_z[:, 0].copy()
         if trace is not None:
             trace.append(dict(round=r, value=val.copy(), best=best.copy()))
-    if p.final_search and not K:
-        Z, _ = discrete.pair_search(kind, graph, zbest, p.seed, traj, p.rounds)
-        val = discrete.value(kind, graph, Z)
-        take = val > best
-        best = np.where(take, val, best)
-        zbest[:, take] = Z[:, take]
-    if p.final_search and K and len(pool_val):
-        Zp, _ = discrete.pair_search(kind, graph, pool_z, p.seed, graph_index * K + np.arange(len(pool_val)),
-                                     p.rounds)
-        vp = discrete.value(kind, graph, Zp)
-        take = vp > pool_val
-        pool_val = np.where(take, vp, pool_val)
-        pool_z[:, take] = Zp[:, take]
+        # the outer iteration ends after the last of its R rounds, or after
+        # the last round of the run
+        ends = (p.restart_every > 0 and (r + 1) % p.restart_every == 0) or r == p.rounds - 1
+        if p.final_search and ends:
+            rnd = p.rounds + (r // p.restart_every if p.restart_every > 0 else 0)
+            if not K:
+                # Alg. 1 / Alg. 2: every chain's own best set
+                Zs, _ = discrete.pair_search(kind, graph, zbest, p.seed, traj, rnd)
+                vs = discrete.value(kind, graph, Zs)
+                take = vs > best
+                best = np.where(take, vs, best)
+                zbest[:, take] = Zs[:, take]
+            elif kind == obj.MIS:
+                # Alg. 3: I_sol alone
+                if sol_val != NONE:
+                    Zs, _ = discrete.pair_search(kind, graph, sol_z[:, None], p.seed,
+                                                 np.array([graph_index * K]), rnd)
+                    vs = int(discrete.value(kind, graph, Zs)[0])
+                    if vs > sol_val:
+                        sol_val, sol_z = vs, Zs[:, 0].copy()
+            elif len(pool_val):
+                # Alg. 4: every pool member, each offered to S_sol in slot order
+                Zs, _ = discrete.pair_search(kind, graph, pool_z, p.seed,
+                                             graph_index * K + np.arange(len(pool_val)), rnd)
+                vs = discrete.value(kind, graph, Zs)
+                for i in range(len(pool_val)):
+                    if vs[i] > sol_val:
+                        sol_val, sol_z = int(vs[i]), Zs[:, i].copy()
     if stats is not None:
         stats["steps"] = steps
         if K:
             stats["pool_value"], stats["pool_z"] = pool_val, pool_z
+            stats["sol_value"], stats["sol_z"] = sol_val, sol_z
     return best, zbest
 
 
@@ -183,12 +210,9 @@ def solve(kind, graph, p: Params, x0=None, precision="fp32"):
             K = p.pool_k
             pool_value[g * K:g * K + len(pv)] = pv
             pool_x[lo:hi, :len(pv)] = pz
-            if len(pv):
-                b = int(np.argmax(pv))  # first slot of the maximum
-                best_value[g] = pv[b]
-                best_x[lo:hi] = pz[:, b]
-            else:
-                best_value[g] = -1
+            # the answer is I_sol / S_sol (-1 while no solution was found)
+            best_value[g] = st["sol_value"] if len(pv) else -1
+            best_x[lo:hi] = st["sol_z"]
             continue
         b = int(np.argmax(vals))  # first index of the maximum
         best_value[g] = vals[b]
