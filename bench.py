@@ -86,39 +86,100 @@ def step_bytes(g, B, momentum=False):
     return b
 
 
+def host_cores():
+    """Cores this process may run on, capped at the 16 a one-GPU share of
+    the machine provides, and the CPU model."""
+    n = len(os.sched_getaffinity(0))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return min(n, 16), n, model
+
+
+def _oracle_params(wl, rounds, pool_k=0, final_search=False):
+    from oracle import solver as osolver
+    return osolver.Params(batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=rounds, alpha=wl.alpha,
+                          seed=wl.seed, gamma=wl.gamma, lam=wl.lam, rho=wl.rho, reset_mode=wl.reset_mode,
+                          local_search=wl.local_search, pool_k=pool_k, final_search=final_search)
+
+
+_WORKER = {}
+
+
+def _worker_init(name):
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from synth.workloads import WORKLOADS
+    wl = WORKLOADS[name]
+    _WORKER["wl"] = wl
+    _WORKER["sub"] = wl.make_graph().subgraph(0)
+
+
+def _worker_run(task):
+    """One worker's share: trajectories `cols` of graph 0 for `rounds` rounds."""
+    from oracle import solver as osolver
+    cols, rounds = task
+    wl, sub = _WORKER["wl"], _WORKER["sub"]
+    t0 = time.perf_counter()
+    osolver.solve_graph(wl.problem, sub, _oracle_params(wl, rounds), 0, cols=np.asarray(cols))
+    return time.perf_counter() - t0
+
+
 def cpu_baseline(wl, g, budget_s=15.0, pool_k=0, final_search=False):
     """The oracle (float32 replay, as used for parity) on a bounded sample of
-    the workload: the first graph, whole rounds of the first trajectories,
-    sized from a one-round probe to take about budget_s."""
+    the workload, graph 0, run before the GPU is touched.  Independent
+    trajectories: one oracle process per host core, each on its own
+    trajectories for whole rounds (the pool couples every trajectory of the
+    graph: then one process on all of them).  The sample is sized from
+    single-process probes to take about budget_s / 2 of wall time."""
+    import multiprocessing as mp
     from oracle import solver as osolver
 
-    def params(rounds):
-        return osolver.Params(batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=rounds, alpha=wl.alpha,
-                              seed=wl.seed, gamma=wl.gamma, lam=wl.lam, rho=wl.rho, reset_mode=wl.reset_mode,
-                              local_search=wl.local_search, pool_k=pool_k, final_search=final_search)
-
     sub = g.subgraph(0)
-    # the pool couples every trajectory of the graph: then all columns
-    ncols = wl.batch if pool_k else 1
+    cores, visible, model = host_cores()
+    coupled = pool_k > 0
+    ncols = wl.batch if coupled else 1
     t0 = time.perf_counter()
-    osolver.solve_graph(wl.problem, sub, params(1), 0, cols=np.arange(ncols))
+    osolver.solve_graph(wl.problem, sub, _oracle_params(wl, 1, pool_k, final_search), 0, cols=np.arange(ncols))
     probe = time.perf_counter() - t0
-    rounds = int(min(wl.rounds, max(1, budget_s // probe)))
-    while True:
+    rounds = int(min(wl.rounds, max(1, budget_s / 2 // probe)))
+    per = 1 if not coupled else wl.batch
+    workers = 1 if coupled else cores
+    if not coupled:
+        # columns per process: grow while one process stays under budget / 2
+        while per * 2 * workers <= wl.batch:
+            t0 = time.perf_counter()
+            osolver.solve_graph(wl.problem, sub, _oracle_params(wl, rounds), 0, cols=np.arange(per))
+            if time.perf_counter() - t0 >= budget_s / 4:
+                break
+            per *= 2
+    if workers == 1:
         t0 = time.perf_counter()
-        osolver.solve_graph(wl.problem, sub, params(rounds), 0, cols=np.arange(ncols))
+        osolver.solve_graph(wl.problem, sub, _oracle_params(wl, rounds, pool_k, final_search), 0,
+                            cols=np.arange(per))
         el = time.perf_counter() - t0
-        # the oracle is vectorised over trajectories: grow the sample until
-        # it fills about half the budget
-        if rounds < wl.rounds or ncols == wl.batch or el >= budget_s / 2:
-            break
-        ncols = int(min(wl.batch, max(2 * ncols, ncols * budget_s / max(el, 1e-3))))
-    eu = sub.nnz * ncols * wl.steps_per_round * rounds
-    return dict(value=eu / el, unit="edge-updates/s", cores=1, kind="oracle",
-                sample=f"graph 0 of {g.num_graphs} (n={sub.n}, nnz={sub.nnz}), trajectories 0..{ncols - 1} "
-                       f"of {wl.batch}, rounds 1..{rounds} of {wl.rounds} ({wl.steps_per_round} steps each, "
-                       f"reset, 1-flip search and evaluation included), float32 replay, single-threaded "
-                       f"numpy/scipy, {el:.1f} s")
+        nt = per
+    else:
+        tasks = [(list(range(w * per, (w + 1) * per)), rounds) for w in range(workers)]
+        ctx = mp.get_context("spawn")  # the GPU is not initialised yet
+        with ctx.Pool(workers, initializer=_worker_init, initargs=(wl.name,)) as pool:
+            pool.map(_worker_run, [([0], 1)] * workers)  # every process up and warm
+            t0 = time.perf_counter()
+            pool.map(_worker_run, tasks, chunksize=1)
+            el = time.perf_counter() - t0
+        nt = per * workers
+    eu = sub.nnz * nt * wl.steps_per_round * rounds
+    return dict(value=eu / el, unit="edge-updates/s", cores=workers, kind="oracle",
+                cpu_model=model, cores_visible=visible,
+                sample=f"graph 0 of {g.num_graphs} (n={sub.n}, nnz={sub.nnz}), trajectories 0..{nt - 1} of "
+                       f"{wl.batch}, rounds 1..{rounds} of {wl.rounds} ({wl.steps_per_round} steps each, reset, "
+                       f"1-flip search and evaluation included), float32 replay in numpy/scipy, {workers} "
+                       f"process(es) of one thread each over disjoint trajectories, {el:.1f} s wall")
 
 
 def pair_cpu_baseline(kind, wl, g, Z0, budget_s):
@@ -143,6 +204,29 @@ def pair_cpu_baseline(kind, wl, g, Z0, budget_s):
                        f"same rounded start, pure-Python loops with numpy, single-threaded, {el:.1f} s")
 
 
+def plain_sample(G, B, per_graph=32, graphs=8):
+    """Trajectory ids of the plain comparison: `per_graph` trajectories spread
+    over the batch of each of `graphs` graphs spread over the workload (all
+    of them when it is smaller)."""
+    gs = np.unique(np.linspace(0, G - 1, min(G, graphs)).round().astype(np.int64))
+    bs = np.unique(np.linspace(0, B - 1, min(B, per_graph)).round().astype(np.int64))
+    return (gs[:, None] * B + bs[None, :]).ravel()
+
+
+def same_trajectories(g, B, ids, a, b):
+    """Incumbent values and sets of trajectories `ids` equal in both solves."""
+    va, vb = a["traj_best_value"].cpu().numpy(), b["traj_best_value"].cpu().numpy()
+    if not np.array_equal(va[ids], vb[ids]):
+        return False
+    xa, xb = a["traj_best_x"].cpu().numpy(), b["traj_best_x"].cpu().numpy()
+    for t in ids:
+        gi, c = divmod(int(t), B)
+        lo, hi = int(g.vtx_offset[gi]), int(g.vtx_offset[gi + 1])
+        if not np.array_equal(xa[lo:hi, c], xb[lo:hi, c]):
+            return False
+    return True
+
+
 def bench_pair(args, wl):
     """The paper's own search (OneTwoSwap / OneTwoFlip) over the workload's
     batch, started from 1-flip optima (what the search meets after a solve
@@ -152,7 +236,6 @@ def bench_pair(args, wl):
     searched per second."""
     import torch
     from synth import arrays
-    from oracle import objectives as oobj
     from paper_2605_06921_amd import mqo
 
     g = wl.make_graph()
@@ -160,7 +243,7 @@ def bench_pair(args, wl):
     dg = mqo.DeviceGraph(g, dev)
     B = wl.batch
     kind = "mis" if wl.problem == "mis" else "maxcut"
-    lo, hi = oobj.box(kind)
+    lo, hi = (0.0, 1.0) if kind == "mis" else (-1.0, 1.0)  # the box of h (Eq. (3)) / f_B (Eq. (7))
     X = arrays.uniform((g.n, B), lo, hi, wl.seed)
     Zr = (X > 0.5).astype(np.int8) if kind == "mis" else np.where(X > 0, 1, -1).astype(np.int8)
     Z0 = torch.from_numpy(Zr).to(dev)
@@ -225,7 +308,6 @@ def bench_toy(args):
     restart comparison runs once, untimed, at n = 12."""
     import math
     import torch
-    from oracle import toy as otoy
     from paper_2605_06921_amd import mqo
 
     n, delta, steps, trials = 64, 0.01, 128, 1 << 20
@@ -255,7 +337,7 @@ def bench_toy(args):
                dtype="f32", data="synthetic",
                config=dict(workload="prop41_toy_n64", mode="toy", n=n, trials=trials, rounds=R, attempts=m,
                            descent_steps=steps, alpha=0.5, beta=0.5, parallelism="dp1"),
-               result=dict(success_fraction=float((f >= 0).mean()), failure_bound=float(otoy.failure_bound(n, R)),
+               result=dict(success_fraction=float((f >= 0).mean()), failure_bound=float(n * math.exp(-R / 2.0)),
                            delta=delta, mean_attempts_to_hit=float(f[f >= 0].mean()),
                            full_restart_n12_success_fraction_within_4096=float((rs >= 0).mean()),
                            full_restart_n12_exact=float(1 - (1 - 2.0 ** -12) ** 4097)))
@@ -276,6 +358,7 @@ def bench_toy(args):
                            note="peak = 256 CUs x 64 lanes x 2.4 GHz, one separately rounded float32 "
                                 "operation per lane-clock; the clamp takes a sixth issue slot per step")
     if not args.no_cpu_baseline:
+        from oracle import toy as otoy
         log("[bench] CPU oracle baseline (toy)")
         T = 256
         t0 = time.perf_counter()
@@ -384,7 +467,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="reg3_maxcut")
+    ap.add_argument("--workload", default="er_batch_mis")
     ap.add_argument("--plan", default="auto")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -443,6 +526,12 @@ def main():
         wl = dataclasses.replace(wl, name=wl.name + tag)
     log(f"[bench] building graph {wl.name}")
     g = wl.make_graph()
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before the GPU is touched: the oracle's worker processes are started fresh
+        log("[bench] CPU oracle baseline")
+        cpu = cpu_baseline(wl, g, args.cpu_budget, args.pool, args.final_search)
+        log(f"[bench] cpu oracle {cpu['value']:.4e} EU/s on {cpu['cores']} cores")
     dev = torch.device("cuda:0")
     dg = mqo.DeviceGraph(g, dev)
     kw = dict(batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=wl.rounds, alpha=wl.alpha, gamma=wl.gamma,
@@ -530,26 +619,27 @@ def main():
     if not args.no_plain and args.pool:
         log("[bench] no plain comparison: the pool runs on the batched plan only")
     if not args.no_plain and not args.pool:
-        log("[bench] plain per-trajectory solve")
+        ids = plain_sample(g.num_graphs, wl.batch)
+        log(f"[bench] plain per-trajectory solve of {len(ids)} trajectories")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        pout = mqo.solve(wl.problem, dg, plan="plain", workspace=ws, **kw)
+        pout = mqo.solve(wl.problem, dg, plan="plain", workspace=ws, trajectories=ids, **kw)
         torch.cuda.synchronize()
         pel = time.perf_counter() - t1
-        equal = bool(torch.equal(pout["traj_best_value"], out["traj_best_value"]) and
-                     torch.equal(pout["best_value"], out["best_value"]))
+        equal = same_trajectories(g, wl.batch, ids, pout, out)
         pval = pout["edge_updates"] / pel
-        res["plain"] = dict(value=pval, unit="edge-updates/s", seconds=pel, equal_best=equal,
-                            batched_over_plain=value / pval)
+        res["plain"] = dict(value=pval, unit="edge-updates/s", seconds=pel, trajectories=len(ids),
+                            graphs=len(np.unique(ids // wl.batch)), equal_best=equal,
+                            batched_over_plain=value / pval,
+                            note="the same kernels one trajectory at a time (captured step loops), on a sample "
+                                 "of the batched run's trajectories; equal_best: their incumbent values and "
+                                 "sets are identical to the batched run's")
         log(f"[bench] plain {pval:.4e} EU/s, batched/plain = {value / pval:.1f}x, equal best: {equal}")
         if not equal:
             raise SystemExit("plain and batched incumbents differ")
     res["best_value"] = out["best_value"].cpu().tolist()[:8]
-
-    if not args.no_cpu_baseline:
-        log("[bench] CPU oracle baseline")
-        res["cpu_baseline"] = cpu_baseline(wl, g, args.cpu_budget, args.pool, args.final_search)
-        log(f"[bench] cpu oracle {res['cpu_baseline']['value']:.4e} EU/s")
+    if cpu is not None:
+        res["cpu_baseline"] = cpu
     print(json.dumps(with_measured_rate(res)), flush=True)
 
 

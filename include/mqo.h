@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define MQO_VERSION 100
+#define MQO_VERSION 110
 
 typedef enum {
   MQO_OK = 0,
@@ -147,15 +147,21 @@ typedef struct {
                               <= 16: 2 = neighbour offsets in registers,
                               1 = never, 0 = autotune                        */
   uint64_t seed;
-  double time_budget_s;    /* 0 = none; otherwise no round starts after it      */
+  double time_budget_s;    /* 0 = none; otherwise no round r > 0 starts after
+                              it (round 0 of every trajectory always runs, so
+                              every incumbent is written); the pass it cuts
+                              short still ends with the final_search         */
   int32_t maxcut_objective; /* mqo_solve_maxcut: MQO_OBJ_MAXCUT_FB (default),
                               _FL, _FP or _FA                                  */
-  int32_t final_search;    /* MQO_FINAL_NONE (default) or MQO_FINAL_PAIR: after
-                              the last round every incumbent goes through
-                              mqo_pair_search (round index = rounds) and is
-                              replaced when strictly better (Alg. 1 / Alg. 2,
-                              the local search after the reset loop); runs
-                              batched over the B trajectories in every plan */
+  int32_t final_search;    /* MQO_FINAL_NONE (default) or MQO_FINAL_PAIR: the
+                              paper's own search closes every pass of the
+                              outer loop (Alg. 1 / Alg. 2; a pass ends after
+                              every restart_every-th round and after the last
+                              round): every incumbent goes through
+                              mqo_pair_search (round index = rounds + the
+                              pass number) and is replaced when strictly
+                              better, so the next pass resets from the
+                              searched sets.  With pool_k see there        */
   int32_t pool_k;          /* 0 = independent trajectories (default); K in
                               [1, min(64, batch)]: the pmQO pool of Alg. 3 /
                               Alg. 4 -- after every round the K best distinct
@@ -167,9 +173,16 @@ typedef struct {
                               hash of the set; round r > 0 restarts
                               trajectory t from slot (u K') >> 32 of the pool
                               (K' filled slots, u the Philox draw (seed, 8)
-                              for counter (0, t, r, 0)).  The answer is then
-                              the best pool member and final_search searches
-                              the pool members (trajectory ids g K + slot).
+                              for counter (0, t, r, 0)).  Each graph keeps
+                              its best set (I_sol / S_sol), replaced by the
+                              pool's best member after every round when that
+                              is strictly better; it is the answer.  With
+                              final_search the pool is left alone and each
+                              pass ends with the search of I_sol alone (MIS,
+                              Alg. 3, trajectory id g K) or of every pool
+                              member (MaxCut, Alg. 4, trajectory ids g K +
+                              slot, offered to S_sol in slot order and each
+                              taken when strictly better).
                               Batched plan only (MQO_ERR_UNSUPPORTED else)  */
   int32_t restart_every;   /* 0 = off (default); R > 0: the outer loop of
                               Alg. 1-4 -- every round r > 0 with r % R == 0
@@ -177,6 +190,15 @@ typedef struct {
                               rule (Philox round field = r / R) instead of a
                               reset; incumbents and the pool carry over.
                               Streaming plans (batched, plain) only         */
+  int32_t traj_count;      /* plain plan: 0 = every trajectory (default);
+                              c > 0: only the c trajectories traj_ids[0..c)
+                              run (ids t = g B + b, strictly ascending, each
+                              < G B), each exactly as in a full solve (the
+                              trajectories are independent chains); the
+                              others keep traj_best_value INT64_MIN and
+                              traj_best_x zeros.  Other plans:
+                              MQO_ERR_UNSUPPORTED                          */
+  const int64_t *traj_ids; /* (host) [traj_count], read during the call     */
 } mqo_params;
 
 /* Outputs of a solve.  Device arrays are written; host fields are set. */
@@ -205,7 +227,8 @@ typedef struct {
                                   they run on                               */
   int64_t step_kernel_launches;/* (host) number of such launches            */
   int64_t final_search_alternations; /* (host) final_search: pair iterations
-                                  that applied a move (largest over graphs) */
+                                  that applied a move, summed over the
+                                  searches that closed the passes           */
   int8_t *pool_x;              /* [n_total*K] pool solutions (pool_k > 0), or
                                   NULL; empty slots are zeros               */
   int64_t *pool_value;         /* [G*K] pool values, INT64_MIN = empty slot,
@@ -257,19 +280,27 @@ size_t mqo_unrolled_workspace_size(const mqo_graph *g, int32_t B, int32_t ckpt_e
 int mqo_pga_unrolled_forward(const mqo_graph *g, mqo_objective obj, float param, float alpha,
                              int32_t K, int32_t ckpt_every, const float *X0, float *ckpt,
                              float *XK, int32_t B, void *ws, size_t ws_bytes, void *stream);
+/* dL_dalpha_sum (device, or NULL): the sum of dL_dalpha over all G*B
+ * trajectories (one float64, summed in a fixed order), the derivative of
+ * the loss with respect to a step size shared by every trajectory. */
 int mqo_pga_unrolled_backward(const mqo_graph *g, mqo_objective obj, float param, float alpha,
                               int32_t K, int32_t ckpt_every, const float *ckpt,
                               const float *dL_dXK, float *dL_dX0, double *dL_dalpha,
-                              int32_t B, void *ws, size_t ws_bytes, void *stream);
+                              double *dL_dalpha_sum, int32_t B, void *ws, size_t ws_bytes,
+                              void *stream);
 
 /* ---- building blocks of one round (asynchronous, stream-ordered) ---- */
 
 /* x0 by the initialisation rule: MQO_INIT_UNIFORM draws u ~ U[0,1) with 24
  * random bits (MIS x = u; MaxCut x = 2u - 1); MQO_INIT_DEGREE is
  * Pi(d_base + N(0, sigma^2)) of Alg. 1 / Alg. 2.  Uses p->batch, seed,
- * init_mode, init_sigma. */
+ * init_mode, init_sigma.  ws: caller-owned device scratch of at least
+ * MQO_INIT_WORKSPACE_BYTES bytes for MQO_INIT_DEGREE (the graphs' largest
+ * degrees are measured into it), NULL allowed for MQO_INIT_UNIFORM; calls on
+ * different streams need different ws. */
+#define MQO_INIT_WORKSPACE_BYTES 256
 int mqo_init_iterate(const mqo_graph *g, mqo_objective obj, const mqo_params *p,
-                     float *X, void *stream);
+                     float *X, void *ws, size_t ws_bytes, void *stream);
 
 /* `nsteps` PGA steps in place on X (and V, the momentum, when
  * p->momentum != 0; V may be NULL otherwise).  Uses p->batch, alpha,

@@ -41,6 +41,10 @@ pool member (MaxCut, Alg. 4, trajectory ids g K + slot, offered to S_sol
 in slot order, each taken when strictly better).
 The answer of graph g is the best incumbent over its B trajectories, ties
 to the lowest b.
+``rounds_run`` = q (1 <= q <= rounds) stands for a time budget that runs out
+after q rounds (the outer loop of Alg. 1-4 repeats while time remains): the
+later rounds never start, the pass they cut short still ends with the
+search, and the searches keep their round indices ``rounds + j``.
 Test infrastructure only.
 """
 from __future__ import annotations
@@ -73,6 +77,7 @@ class Params:
     final_search: bool = False
     pool_k: int = 0
     restart_every: int = 0
+    rounds_run: int | None = None
 
 
 def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32", trace=None, cols=None,
@@ -99,7 +104,9 @@ def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32"
     pool_val, pool_z = np.zeros(0, dtype=np.int64), np.zeros((n, 0), dtype=np.int8)
     NONE = int(np.iinfo(np.int64).min)
     sol_val, sol_z = NONE, np.zeros(n, dtype=np.int8)  # I_sol / S_sol of the pool mode
-    for r in range(p.rounds):
+    last = (p.rounds if p.rounds_run is None else p.rounds_run) - 1
+    assert 0 <= last < p.rounds
+    for r in range(last + 1):
         fresh = r > 0 and p.restart_every > 0 and r % p.restart_every == 0
         start = r // p.restart_every if fresh else 0
         if r == 0 and x0 is not None:
@@ -148,7 +155,7 @@ def solve_graph(kind, graph, p: Params, graph_index=0, x0=None, precision="fp32"
             trace.append(dict(round=r, value=val.copy(), best=best.copy()))
         # the outer iteration ends after the last of its R rounds, or after
         # the last round of the run
-        ends = (p.restart_every > 0 and (r + 1) % p.restart_every == 0) or r == p.rounds - 1
+        ends = (p.restart_every > 0 and (r + 1) % p.restart_every == 0) or r == last
         if p.final_search and ends:
             rnd = p.rounds + (r // p.restart_every if p.restart_every > 0 else 0)
             if not K:

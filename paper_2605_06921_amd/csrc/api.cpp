@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -70,7 +71,6 @@ struct Resources {
   int64_t *pinned_voff = nullptr;  // staging of vtx_offset for its upload
   size_t pinned_voff_n = 0;
   hipEvent_t input_ready = nullptr;  // caller's stream -> internal stream
-  int32_t *small = nullptr;   // 64 device ints of scratch for entry points without a workspace
   int device = -1;
   int lds_limit = 0;
   std::map<std::string, TileCfg> tile_tuning;  // shape key -> tuned tile shape
@@ -93,8 +93,6 @@ int ensure_resources() {
   if (!r.pinned) HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&r.pinned), 1024 * sizeof(int32_t), 0));
   if (!r.input_ready) HIP_TRY(hipEventCreateWithFlags(&r.input_ready, hipEventDisableTiming));
   HIP_TRY(hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking));
-  if (r.small) (void)hipFree(r.small);
-  HIP_TRY(hipMalloc(reinterpret_cast<void **>(&r.small), 64 * sizeof(int32_t)));
   int lds = 0;
   HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   r.lds_limit = lds;
@@ -177,6 +175,10 @@ int check_params(const mqo_params *p, mqo_objective obj) {
   if (p->pool_k > 0 && (p->plan == MQO_PLAN_PERSISTENT || p->plan == MQO_PLAN_PLAIN))
     return fail(MQO_ERR_UNSUPPORTED, "the pool couples the trajectories of a graph: batched plan only");
   if (p->plan < MQO_PLAN_AUTO || p->plan > MQO_PLAN_PERSISTENT) return fail(MQO_ERR_INVALID_ARG, "bad plan");
+  if (p->traj_count < 0 || (p->traj_count > 0 && !p->traj_ids))
+    return fail(MQO_ERR_INVALID_ARG, "traj_count must be >= 0, with traj_ids when > 0");
+  if (p->traj_count > 0 && p->plan != MQO_PLAN_PLAIN)
+    return fail(MQO_ERR_UNSUPPORTED, "a trajectory subset runs on the plain plan only");
   if (p->tile_cols != 0 && (p->tile_cols < 1 || p->tile_cols > 64 || (p->tile_cols & (p->tile_cols - 1))))
     return fail(MQO_ERR_INVALID_ARG, "tile_cols must be 0 or a power of two <= 64");
   if (p->tile_threads != 0 && p->tile_threads != 256 && p->tile_threads != 512 && p->tile_threads != 1024)
@@ -200,7 +202,8 @@ int64_t max_graph_rows(const mqo_graph *g) {
 // ---------------------------------------------------------------------------
 struct Layout {
   size_t X, Xt, V, Z, Zb, NB, PRIO, F, value, best, acc, act, voff, rpat, bestb, dmax, err, reset, tzs, tnb, tprio,
-      tfl, tvm, tls, pX, pXt, pV, colact, fixedc, steps, pz[2], pv[2], ph[2], chash, ptaken, psrc, pbase, total;
+      tfl, tvm, tls, pX, pXt, pV, colact, fixedc, steps, pz[2], pv[2], ph[2], chash, ptaken, psrc, pbase, solz, solv,
+      choice, total;
 };
 
 // K: pool slots per graph (0 = no pool); the pool buffers come last, so the
@@ -254,6 +257,9 @@ Layout make_layout(const mqo_graph *g, int32_t B, int32_t K = 0) {
   L.ptaken = take(K ? K + B : 0);
   L.psrc = take(G * K * 4);
   L.pbase = take(K ? G * B * 4 : 0);
+  L.solz = take(K ? n : 0);  // the pool modes' best set (I_sol / S_sol) and its value
+  L.solv = take(K ? G * 8 : 0);
+  L.choice = take(K ? G * 4 : 0);
   L.total = o;
   return L;
 }
@@ -398,6 +404,7 @@ struct Solve {
   int8_t *Zb = nullptr;    // incumbents [n_total][B]: the caller's traj_best_x when given, else workspace
   int64_t *best = nullptr; // incumbent values [G*B]: the caller's traj_best_value when given, else workspace
   int64_t ls_iters = 0;
+  int64_t search_alt = 0;  // pair iterations that applied a move, summed over the pass searches
   int32_t deferred_tile_wg = 0;  // > 0: the tile counters sit in the pinned buffer after the final sync
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;  // around the step launches
 
@@ -527,17 +534,31 @@ GraphView whole_view(const mqo_graph *g) {
 // (purpose LS and SWAP, trajectory g_i * B + c, local vertex index) are
 // drawn once.  T0..T2: int32 scratch [n_total][B] each.
 // cand_ms (or nullptr): HIP-event time of the candidate launches, summed.
-int pair_core(bool maxcut, const mqo_graph *g, uint64_t seed, int32_t round, int8_t *Z, int32_t *NB,
-              uint32_t *PRIO, uint32_t *PRIO_SW, int8_t *F, int32_t *act, long long *acc, int64_t *value_scratch,
-              int32_t *T0, int32_t *T1, int32_t *T2, uint32_t *TB, int32_t B, hipStream_t s, int64_t *ls_iters,
-              int64_t *alternations, double *cand_ms) {
-  const GraphView all = whole_view(g);
-  for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
+// Which columns a pair search runs on: graphs [g0, g1) (rows `view`, which
+// covers exactly those graphs), ncols columns at leading dimension ld, and
+// column c of graph gi is trajectory gi * traj_stride + traj_off + c.
+struct PairCols {
+  GraphView view;
+  int32_t g0, g1;
+  int64_t traj_stride, traj_off;
+  int32_t ncols, ld;
+};
+
+PairCols all_cols(const mqo_graph *g, int32_t B) { return PairCols{whole_view(g), 0, g->num_graphs, B, 0, B, B}; }
+
+int pair_core(bool maxcut, const mqo_graph *g, const PairCols &pc, uint64_t seed, int32_t round, int8_t *Z,
+              int32_t *NB, uint32_t *PRIO, uint32_t *PRIO_SW, int8_t *F, int32_t *act, long long *acc,
+              int64_t *value_scratch, int32_t *T0, int32_t *T1, int32_t *T2, uint32_t *TB, hipStream_t s,
+              int64_t *ls_iters, int64_t *alternations, double *cand_ms) {
+  const GraphView &all = pc.view;
+  const int32_t B = pc.ncols, ld = pc.ld;
+  for (int32_t gi = pc.g0; gi < pc.g1; ++gi) {
     const int64_t lo = g->vtx_offset[gi], n = g->vtx_offset[gi + 1] - lo;
-    launch_ls_prio(PRIO, lo, n, B, B, seed, (uint64_t)gi * B, (uint64_t)round, s);
-    launch_swap_prio(PRIO_SW, lo, n, B, B, seed, (uint64_t)gi * B, (uint64_t)round, s);
+    const uint64_t t0 = (uint64_t)(gi * pc.traj_stride + pc.traj_off);
+    launch_ls_prio(PRIO, lo, n, B, ld, seed, t0, (uint64_t)round, s);
+    launch_swap_prio(PRIO_SW, lo, n, B, ld, seed, t0, (uint64_t)round, s);
   }
-  launch_evaluate(maxcut, all, Z, NB, acc, value_scratch, nullptr, nullptr, B, B, s);  // NB = A Z
+  launch_evaluate(maxcut, all, Z, NB, acc, value_scratch, nullptr, nullptr, B, ld, s);  // NB = A Z
   const int64_t cap = 4 * (g->n_total + g->nnz_total) + 64;  // every applied iteration gains
   int64_t alt = 0;
   std::vector<int32_t> flag;
@@ -553,14 +574,14 @@ int pair_core(bool maxcut, const mqo_graph *g, uint64_t seed, int32_t round, int
   int rc = MQO_OK;
   while (rc == MQO_OK) {
     int64_t it = 0;
-    rc = ls_loop(maxcut, all, g->nnz_total, mean_degree_of(g), Z, NB, PRIO, F, act, B, B, s, &it, 2);
+    rc = ls_loop(maxcut, all, g->nnz_total, mean_degree_of(g), Z, NB, PRIO, F, act, B, ld, s, &it, 2);
     if (rc != MQO_OK) break;
     if (ls_iters) *ls_iters += it;
     launch_fill_i32(act, 1, 0, s);
     if (cand_ms) (void)hipEventRecord(ev[0], s);
-    launch_pair_candidates(maxcut, all, Z, NB, PRIO_SW, T0, T1, T2, TB, B, B, mean_degree_of(g), s);
+    launch_pair_candidates(maxcut, all, Z, NB, PRIO_SW, T0, T1, T2, TB, B, ld, mean_degree_of(g), s);
     if (cand_ms) (void)hipEventRecord(ev[1], s);
-    launch_pair_apply(maxcut, all, Z, NB, PRIO_SW, F, T0, T1, T2, act, B, B, mean_degree_of(g), s);
+    launch_pair_apply(maxcut, all, Z, NB, PRIO_SW, F, T0, T1, T2, act, B, ld, mean_degree_of(g), s);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
       rc = fail(MQO_ERR_HIP, "pair iteration: %s", hipGetErrorString(e));
@@ -715,6 +736,16 @@ int grid_round(Solve &S, StepLoop &loop, bool use_graph, const GraphView &gv, in
   return MQO_OK;
 }
 
+int32_t search_round(const Solve &S, int32_t r);
+bool pass_ends(const Solve &S, int32_t r);
+int search_incumbents(Solve &S, int32_t rnd, int64_t *alternations);
+int search_one(Solve &S, const GraphView &gv, int32_t gi, int32_t b, int32_t rnd, int64_t *alternations);
+void offer_pool(Solve &S, const int8_t *PZ, const int64_t *PV);
+int search_pool_pass(Solve &S, const int8_t *PZ, const int64_t *PV, int32_t rnd, int64_t *alternations);
+
+// Every trajectory runs round 0; with a time budget no later round starts
+// after it.  With final_search the pair search closes every pass of the
+// outer loop (and a pass the budget cut short).
 int solve_batched(Solve &S, int32_t *rounds_done) {
   float *X = at<float>(S.ws, S.L.X), *Xt = at<float>(S.ws, S.L.Xt), *V = at<float>(S.ws, S.L.V);
   int8_t *Z = at<int8_t>(S.ws, S.L.Z), *Zb = S.Zb, *F = at<int8_t>(S.ws, S.L.F);
@@ -729,7 +760,13 @@ int solve_batched(Solve &S, int32_t *rounds_done) {
   const bool use_graph = S.G <= 16 && S.p->steps_per_round >= 4;
   std::vector<StepLoop> loops(S.G);
   const int32_t K = S.p->pool_k;
-  if (K) launch_fill_i64(at<int64_t>(S.ws, S.L.pv[0]), (int64_t)S.G * K, INT64_MIN, S.s);  // empty pool
+  const bool search = S.p->final_search == MQO_FINAL_PAIR;
+  if (K) {
+    launch_fill_i64(at<int64_t>(S.ws, S.L.pv[0]), (int64_t)S.G * K, INT64_MIN, S.s);  // empty pool
+    launch_fill_i64(at<int64_t>(S.ws, S.L.solv), S.G, INT64_MIN, S.s);              // no best set yet
+    launch_fill_i8(at<int8_t>(S.ws, S.L.solz), S.g->n_total, 0, S.s);
+  }
+  bool searched = false;  // the last round run closed its pass with the search
   const double t0 = now_s();
   int32_t r = 0;
   for (r = 0; r < S.p->rounds; ++r) {
@@ -758,6 +795,24 @@ int solve_batched(Solve &S, int32_t *rounds_done) {
                            at<int8_t>(S.ws, S.L.pz[nxt]), at<int64_t>(S.ws, S.L.pv[nxt]),
                            at<unsigned long long>(S.ws, S.L.ph[nxt]), at<int32_t>(S.ws, S.L.psrc), S.s);
     }
+    if (K) offer_pool(S, at<int8_t>(S.ws, S.L.pz[nxt]), at<int64_t>(S.ws, S.L.pv[nxt]));
+    searched = false;
+    if (search && pass_ends(S, r)) {
+      if (K)
+        TRY(search_pool_pass(S, at<int8_t>(S.ws, S.L.pz[nxt]), at<int64_t>(S.ws, S.L.pv[nxt]), search_round(S, r),
+                             &S.search_alt));
+      else
+        TRY(search_incumbents(S, search_round(S, r), &S.search_alt));
+      searched = true;
+    }
+  }
+  if (search && !searched && r > 0) {  // the time budget cut the last pass short
+    const int last = r & 1;            // the pool after round r - 1
+    if (K)
+      TRY(search_pool_pass(S, at<int8_t>(S.ws, S.L.pz[last]), at<int64_t>(S.ws, S.L.pv[last]),
+                           search_round(S, r - 1), &S.search_alt));
+    else
+      TRY(search_incumbents(S, search_round(S, r - 1), &S.search_alt));
   }
   HIP_TRY(hipGetLastError());
   *rounds_done = r;
@@ -766,42 +821,63 @@ int solve_batched(Solve &S, int32_t *rounds_done) {
 
 int solve_plain(Solve &S, int32_t *rounds_done) {
   // One trajectory at a time on contiguous vectors (ld = 1) with the same
-  // kernels; incumbents go straight into column b of Zb ([n][B]).
+  // kernels; incumbents go straight into column b of Zb ([n][B]).  Every
+  // trajectory runs round 0, so every incumbent is written; once the time
+  // budget has run out no later round starts.  With final_search the pair
+  // search closes every pass of the trajectory's outer loop (and a pass the
+  // budget cut short).
   float *X = at<float>(S.ws, S.L.pX), *Xt = at<float>(S.ws, S.L.pXt), *V = at<float>(S.ws, S.L.pV);
   int8_t *Z = at<int8_t>(S.ws, S.L.Z), *Zb = S.Zb, *F = at<int8_t>(S.ws, S.L.F);
   int32_t *NB = at<int32_t>(S.ws, S.L.NB);
   uint32_t *PRIO = at<uint32_t>(S.ws, S.L.PRIO);
   int64_t *value = at<int64_t>(S.ws, S.L.value), *best = S.best;
   const int32_t B = S.B;
+  const bool search = S.p->final_search == MQO_FINAL_PAIR;
   const float *start = S.x0;
   if (!start) {
     TRY(init_x(S, at<float>(S.ws, S.L.X)));
     start = at<float>(S.ws, S.L.X);
   }
   const bool use_graph = S.p->steps_per_round >= 4;
+  const int64_t *ids = S.p->traj_count > 0 ? S.p->traj_ids : nullptr;
+  const int64_t count = ids ? S.p->traj_count : (int64_t)S.G * B;
+  if (ids) {  // trajectories that do not run: no incumbent
+    launch_fill_i64(best, (int64_t)S.G * B, INT64_MIN, S.s);
+    launch_fill_i8(Zb, S.g->n_total * B, 0, S.s);
+  }
   const double t0 = now_s();
   int32_t rmax = 0;
   bool out_of_time = false;
-  for (int32_t gi = 0; gi < S.G && !out_of_time; ++gi) {
-    const GraphView gv = view_of(S.g, gi, S.max_deg);
-    StepLoop loop;  // the captured step loop serves every trajectory of the graph
-    for (int32_t b = 0; b < B && !out_of_time; ++b) {
-      const int64_t t = (int64_t)gi * B + b;
-      launch_strided_copy_f32(start, B, b, X, 1, 0, gv.lo, gv.n, S.s);
-      int32_t r = 0;
-      for (r = 0; r < S.p->rounds; ++r) {
-        if (r > 0 && S.p->time_budget_s > 0.0) {
-          HIP_TRY(hipStreamSynchronize(S.s));
-          if (now_s() - t0 >= S.p->time_budget_s) {
-            out_of_time = true;
-            break;
-          }
-        }
-        TRY(grid_round(S, loop, use_graph, gv, r, X, Xt, V, Z, Zb + b, B, NB, PRIO, F, value + t, best + t, 1, 1,
-                       (uint64_t)t, at<int8_t>(S.ws, S.L.colact)));
-      }
-      rmax = std::max(rmax, r);
+  int32_t cur_g = -1;
+  GraphView gv{};
+  std::unique_ptr<StepLoop> loop;  // the captured step loop serves every trajectory of a graph
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t t = ids ? ids[i] : i;
+    const int32_t gi = (int32_t)(t / B), b = (int32_t)(t % B);
+    if (gi != cur_g) {
+      gv = view_of(S.g, gi, S.max_deg);
+      loop.reset(new StepLoop);
+      cur_g = gi;
     }
+    launch_strided_copy_f32(start, B, b, X, 1, 0, gv.lo, gv.n, S.s);
+    int32_t r = 0;
+    bool searched = false;
+    for (r = 0; r < S.p->rounds; ++r) {
+      if (r > 0 && S.p->time_budget_s > 0.0 && !out_of_time) {
+        HIP_TRY(hipStreamSynchronize(S.s));
+        out_of_time = now_s() - t0 >= S.p->time_budget_s;
+      }
+      if (r > 0 && out_of_time) break;
+      TRY(grid_round(S, *loop, use_graph, gv, r, X, Xt, V, Z, Zb + b, B, NB, PRIO, F, value + t, best + t, 1, 1,
+                     (uint64_t)t, at<int8_t>(S.ws, S.L.colact)));
+      searched = false;
+      if (search && pass_ends(S, r)) {
+        TRY(search_one(S, gv, gi, b, search_round(S, r), &S.search_alt));
+        searched = true;
+      }
+    }
+    if (search && !searched) TRY(search_one(S, gv, gi, b, search_round(S, r - 1), &S.search_alt));
+    rmax = std::max(rmax, r);
   }
   *rounds_done = rmax;
   return MQO_OK;
@@ -1045,21 +1121,42 @@ int settle_deferred(Solve &S) {
   return MQO_OK;
 }
 
-// Alg. 1 / Alg. 2 after the reset loop: the pair search on every incumbent
-// (batched over all trajectories and graphs, round index = rounds),
-// replacing it when strictly better.  The iterate buffers and the tile
-// scratch serve as scratch.
-int final_search(Solve &S, int64_t *alternations) {
+// Philox round index of the search closing the pass of the outer loop that
+// round r belongs to: rounds + the pass number
+int32_t search_round(const Solve &S, int32_t r) {
+  const int32_t R = S.p->restart_every;
+  return S.p->rounds + (R > 0 ? r / R : 0);
+}
+
+// round r is the last of its pass: the R-th of a fresh start, or the last round
+bool pass_ends(const Solve &S, int32_t r) {
+  const int32_t R = S.p->restart_every;
+  return (R > 0 && (r + 1) % R == 0) || r == S.p->rounds - 1;
+}
+
+int pair_on(Solve &S, const PairCols &pc, int32_t rnd, int8_t *Z, int64_t *alternations) {
+  int64_t alt = 0;
+  TRY(pair_core(S.maxcut, S.g, pc, S.p->seed, rnd, Z, at<int32_t>(S.ws, S.L.NB), at<uint32_t>(S.ws, S.L.PRIO),
+                at<uint32_t>(S.ws, S.L.tprio), at<int8_t>(S.ws, S.L.F), at<int32_t>(S.ws, S.L.act),
+                at<long long>(S.ws, S.L.acc), at<int64_t>(S.ws, S.L.value), at<int32_t>(S.ws, S.L.X),
+                at<int32_t>(S.ws, S.L.Xt), at<int32_t>(S.ws, S.L.V), at<uint32_t>(S.ws, S.L.tnb), S.s, &S.ls_iters,
+                &alt, nullptr));
+  *alternations += alt;
+  return MQO_OK;
+}
+
+// Alg. 1 / Alg. 2, the search closing a pass of the outer loop: the pair
+// search on every incumbent (all trajectories of all graphs, round index
+// rnd), each replaced when strictly better, so the next pass resets from
+// the searched sets.  The iterate buffers and the tile scratch serve as
+// scratch.
+int search_incumbents(Solve &S, int32_t rnd, int64_t *alternations) {
   TRY(settle_deferred(S));
   int8_t *Z = at<int8_t>(S.ws, S.L.Z), *Zb = S.Zb;
   int64_t *value = at<int64_t>(S.ws, S.L.value), *best = S.best;
   const int32_t B = S.B;
   HIP_TRY(hipMemcpyAsync(Z, Zb, (size_t)S.g->n_total * B, hipMemcpyDeviceToDevice, S.s));
-  TRY(pair_core(S.maxcut, S.g, S.p->seed, S.p->rounds, Z, at<int32_t>(S.ws, S.L.NB), at<uint32_t>(S.ws, S.L.PRIO),
-                at<uint32_t>(S.ws, S.L.tprio), at<int8_t>(S.ws, S.L.F), at<int32_t>(S.ws, S.L.act),
-                at<long long>(S.ws, S.L.acc), value, at<int32_t>(S.ws, S.L.X), at<int32_t>(S.ws, S.L.Xt),
-                at<int32_t>(S.ws, S.L.V), at<uint32_t>(S.ws, S.L.tnb), B, S.s, &S.ls_iters, alternations,
-                nullptr));
+  TRY(pair_on(S, all_cols(S.g, B), rnd, Z, alternations));
   for (int32_t gi = 0; gi < S.G; ++gi) {
     const GraphView gv = view_of(S.g, gi, S.max_deg);
     const int64_t t = (int64_t)gi * B;
@@ -1071,30 +1168,54 @@ int final_search(Solve &S, int64_t *alternations) {
   return MQO_OK;
 }
 
-// The search after the reset loop of Alg. 4 (Alg. 3's, on every member): the pair search on
-// every pool member (trajectory ids g K + slot, round index = rounds),
-// replacing a member when strictly better; empty slots are never taken.
-int final_search_pool(Solve &S, int8_t *PZ, int64_t *PV, int64_t *alternations) {
+// The same for the one trajectory t = gi B + b of the plain plan (its
+// incumbent is column b of Zb); column 0 of the Z scratch (ld 1) holds the
+// searched copy.
+int search_one(Solve &S, const GraphView &gv, int32_t gi, int32_t b, int32_t rnd, int64_t *alternations) {
+  int8_t *Z = at<int8_t>(S.ws, S.L.Z);
+  int64_t *value = at<int64_t>(S.ws, S.L.value);
+  const int64_t t = (int64_t)gi * S.B + b;
+  launch_strided_copy_i8(S.Zb, S.B, b, Z, 1, 0, gv.lo, gv.n, S.s);
+  TRY(pair_on(S, PairCols{gv, gi, gi + 1, S.B, b, 1, 1}, rnd, Z, alternations));
+  launch_evaluate(S.maxcut, gv, Z, at<int32_t>(S.ws, S.L.NB), at<long long>(S.ws, S.L.acc), value + t, nullptr,
+                  nullptr, 1, 1, S.s);
+  launch_accept(Z, S.Zb + b, value + t, S.best + t, gv.lo, gv.n, 1, 1, S.B, false, S.s);
+  HIP_TRY(hipGetLastError());
+  return MQO_OK;
+}
+
+// The pool modes' best set I_sol / S_sol takes the pool's best member when
+// that is strictly better (after every round; PZ / PV: the pool).
+void offer_pool(Solve &S, const int8_t *PZ, const int64_t *PV) {
+  const int32_t K = S.p->pool_k;
+  launch_offer(PZ, K, PV, PV, K, S.G, false, at<int64_t>(S.ws, S.L.voff), S.g->n_total, at<int64_t>(S.ws, S.L.solv),
+               at<int8_t>(S.ws, S.L.solz), at<int32_t>(S.ws, S.L.choice), S.s);
+}
+
+// The search closing a pass in the pool modes (round index rnd); the pool
+// itself is left as it is.  MIS (Alg. 3): I_sol alone, as trajectory g K,
+// replacing it when strictly better.  MaxCut (Alg. 4): every pool member
+// (trajectory g K + slot), each offered to S_sol in slot order and taken
+// when strictly better.
+int search_pool_pass(Solve &S, const int8_t *PZ, const int64_t *PV, int32_t rnd, int64_t *alternations) {
   const int32_t K = S.p->pool_k;
   int8_t *Z = at<int8_t>(S.ws, S.L.Z);
   int64_t *value = at<int64_t>(S.ws, S.L.value);
-  HIP_TRY(hipMemcpyAsync(Z, PZ, (size_t)S.g->n_total * K, hipMemcpyDeviceToDevice, S.s));
-  TRY(pair_core(S.maxcut, S.g, S.p->seed, S.p->rounds, Z, at<int32_t>(S.ws, S.L.NB), at<uint32_t>(S.ws, S.L.PRIO),
-                at<uint32_t>(S.ws, S.L.tprio), at<int8_t>(S.ws, S.L.F), at<int32_t>(S.ws, S.L.act),
-                at<long long>(S.ws, S.L.acc), value, at<int32_t>(S.ws, S.L.X), at<int32_t>(S.ws, S.L.Xt),
-                at<int32_t>(S.ws, S.L.V), at<uint32_t>(S.ws, S.L.tnb), K, S.s, &S.ls_iters, alternations, nullptr));
+  int64_t *solv = at<int64_t>(S.ws, S.L.solv);
+  const int32_t ncols = S.maxcut ? K : 1;
+  if (S.maxcut)
+    HIP_TRY(hipMemcpyAsync(Z, PZ, (size_t)S.g->n_total * K, hipMemcpyDeviceToDevice, S.s));
+  else
+    HIP_TRY(hipMemcpyAsync(Z, at<int8_t>(S.ws, S.L.solz), (size_t)S.g->n_total, hipMemcpyDeviceToDevice, S.s));
+  TRY(pair_on(S, PairCols{whole_view(S.g), 0, S.G, K, 0, ncols, ncols}, rnd, Z, alternations));
   for (int32_t gi = 0; gi < S.G; ++gi) {
     const GraphView gv = view_of(S.g, gi, S.max_deg);
-    const int64_t t = (int64_t)gi * K;
-    launch_evaluate(S.maxcut, gv, Z, at<int32_t>(S.ws, S.L.NB), at<long long>(S.ws, S.L.acc), value + t, nullptr,
-                    nullptr, K, K, S.s);
+    launch_evaluate(S.maxcut, gv, Z, at<int32_t>(S.ws, S.L.NB), at<long long>(S.ws, S.L.acc),
+                    value + (int64_t)gi * ncols, nullptr, nullptr, ncols, ncols, S.s);
   }
-  launch_mask_empty(value, PV, (int64_t)S.G * K, S.s);
-  for (int32_t gi = 0; gi < S.G; ++gi) {
-    const GraphView gv = view_of(S.g, gi, S.max_deg);
-    const int64_t t = (int64_t)gi * K;
-    launch_accept(Z, PZ, value + t, PV + t, gv.lo, gv.n, K, K, K, false, S.s);
-  }
+  // MIS: a graph with no I_sol yet searched an empty vector, which is not offered
+  launch_offer(Z, ncols, value, S.maxcut ? PV : nullptr, ncols, S.G, !S.maxcut, at<int64_t>(S.ws, S.L.voff),
+               S.g->n_total, solv, at<int8_t>(S.ws, S.L.solz), at<int32_t>(S.ws, S.L.choice), S.s);
   HIP_TRY(hipGetLastError());
   return MQO_OK;
 }
@@ -1105,6 +1226,11 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
   if (!p) return fail(MQO_ERR_INVALID_ARG, "params is NULL");
   TRY(check_params(p, obj == MQO_OBJ_MIS_H ? obj : (mqo_objective)p->maxcut_objective));
   if (!r || !r->best_x || !r->best_value) return fail(MQO_ERR_INVALID_ARG, "result arrays best_x/best_value required");
+  for (int32_t i = 0; i < p->traj_count; ++i) {
+    const int64_t t = p->traj_ids[i];
+    if (t < 0 || t >= (int64_t)g->num_graphs * p->batch || (i > 0 && t <= p->traj_ids[i - 1]))
+      return fail(MQO_ERR_INVALID_ARG, "traj_ids must be strictly ascending trajectory ids below G * batch");
+  }
   const Layout L = make_layout(g, p->batch, p->pool_k);
   if (!ws || ws_bytes < L.total) return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", L.total);
   TRY(ensure_resources());
@@ -1160,23 +1286,19 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
     TRY(solve_batched(S, &rounds_done));
   else
     TRY(solve_plain(S, &rounds_done));
-  int64_t final_alt = 0;
+  // the persistent plan runs one pass (no fresh starts): its search follows
+  if (plan == MQO_PLAN_PERSISTENT && p->final_search == MQO_FINAL_PAIR && rounds_done > 0)
+    TRY(search_incumbents(S, search_round(S, rounds_done - 1), &S.search_alt));
   const int32_t K = p->pool_k;
   const int pool_buf = rounds_done & 1;  // the pool after the last round
   int8_t *PZ = K ? at<int8_t>(ws, L.pz[pool_buf]) : nullptr;
   int64_t *PV = K ? at<int64_t>(ws, L.pv[pool_buf]) : nullptr;
-  if (p->final_search == MQO_FINAL_PAIR) {
-    if (K)
-      TRY(final_search_pool(S, PZ, PV, &final_alt));
-    else
-      TRY(final_search(S, &final_alt));
-  }
 
   int64_t *best = S.best;
   int32_t *bestb = at<int32_t>(ws, L.bestb);
-  if (K) {  // the answer is the best pool member
-    launch_pick_best(PV, S.G, K, r->best_value, bestb, s);
-    launch_copy_best_x(PZ, K, voff, S.G, bestb, r->best_x, g->n_total, s);
+  if (K) {  // the answer is the best set I_sol / S_sol (-1 and zeros while there is none)
+    launch_pick_best(at<int64_t>(ws, L.solv), S.G, 1, r->best_value, bestb, s);
+    launch_copy_best_x(at<int8_t>(ws, L.solz), 1, voff, S.G, bestb, r->best_x, g->n_total, s);
     if (r->pool_x) HIP_TRY(hipMemcpyAsync(r->pool_x, PZ, (size_t)g->n_total * K, hipMemcpyDeviceToDevice, s));
     if (r->pool_value)
       HIP_TRY(hipMemcpyAsync(r->pool_value, PV, (size_t)S.G * K * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
@@ -1205,7 +1327,7 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
   r->ls_iterations = S.ls_iters;
   r->step_kernel_ms = S.timed_ms();
   r->step_kernel_launches = (int64_t)S.timed.size();
-  r->final_search_alternations = final_alt;
+  r->final_search_alternations = S.search_alt;
   return MQO_OK;
 }
 
@@ -1371,7 +1493,8 @@ int mqo_pga_unrolled_forward(const mqo_graph *g, mqo_objective obj, float param,
 
 int mqo_pga_unrolled_backward(const mqo_graph *g, mqo_objective obj, float param, float alpha, int32_t K,
                               int32_t ckpt_every, const float *ckpt, const float *dL_dXK, float *dL_dX0,
-                              double *dL_dalpha, int32_t B, void *ws, size_t ws_bytes, void *stream) {
+                              double *dL_dalpha, double *dL_dalpha_sum, int32_t B, void *ws, size_t ws_bytes,
+                              void *stream) {
   TRY(check_async(g, obj, B));
   TRY(check_param(obj, param));
   if (!(alpha > 0.0f) || !std::isfinite(alpha)) return fail(MQO_ERR_INVALID_ARG, "alpha must be > 0");
@@ -1415,17 +1538,20 @@ int mqo_pga_unrolled_backward(const mqo_graph *g, mqo_objective obj, float param
     }
     launch_copy_f32(cur + gv.lo * B, dL_dX0 + gv.lo * B, gv.n * B, s);
   }
+  if (dL_dalpha_sum) launch_sum_f64(dL_dalpha, (int64_t)g->num_graphs * B, dL_dalpha_sum, s);
   HIP_TRY(hipGetLastError());
   return MQO_OK;
 }
 
 // ---- building blocks ----
 
-int mqo_init_iterate(const mqo_graph *g, mqo_objective obj, const mqo_params *p, float *X, void *stream) {
+int mqo_init_iterate(const mqo_graph *g, mqo_objective obj, const mqo_params *p, float *X, void *ws, size_t ws_bytes,
+                     void *stream) {
   TRY(check_async(g, obj, p ? p->batch : 0));
   TRY(check_params(p, obj));
   if (!X) return fail(MQO_ERR_INVALID_ARG, "X is NULL");
-  TRY(ensure_resources());
+  if (p->init_mode == MQO_INIT_DEGREE && (!ws || ws_bytes < MQO_INIT_WORKSPACE_BYTES))
+    return fail(MQO_ERR_WORKSPACE, "the degree initialisation needs %d bytes of workspace", MQO_INIT_WORKSPACE_BYTES);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const bool mc = obj != MQO_OBJ_MIS_H;
   const int form = (int)obj;
@@ -1435,8 +1561,8 @@ int mqo_init_iterate(const mqo_graph *g, mqo_objective obj, const mqo_params *p,
     if (p->init_mode == MQO_INIT_UNIFORM)
       launch_init_uniform(mc, X, gv.lo, gv.n, B, B, p->seed, (uint64_t)gi * B, s);
     else
-      launch_init_degree(mc, X, g->row_ptr, res().small, gv.lo, gv.n, B, B, p->seed, (uint64_t)gi * B,
-                         p->init_sigma, s);
+      launch_init_degree(mc, X, g->row_ptr, reinterpret_cast<int32_t *>(ws), gv.lo, gv.n, B, B, p->seed,
+                         (uint64_t)gi * B, p->init_sigma, s);
   }
   HIP_TRY(hipGetLastError());
   return MQO_OK;
@@ -1525,10 +1651,10 @@ int mqo_pair_search(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t s
   TRY(ensure_resources());
   std::lock_guard<std::mutex> host_lock(res().host_mu);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return pair_core(mc, g, seed, round, Z, at<int32_t>(ws, L.NB), at<uint32_t>(ws, L.PRIO), at<uint32_t>(ws, L.tprio),
-                   at<int8_t>(ws, L.F), at<int32_t>(ws, L.act), at<long long>(ws, L.acc), at<int64_t>(ws, L.value),
-                   at<int32_t>(ws, L.X), at<int32_t>(ws, L.Xt), at<int32_t>(ws, L.V), at<uint32_t>(ws, L.tnb), B, s,
-                   nullptr, alternations, candidate_kernel_ms);
+  return pair_core(mc, g, all_cols(g, B), seed, round, Z, at<int32_t>(ws, L.NB), at<uint32_t>(ws, L.PRIO),
+                   at<uint32_t>(ws, L.tprio), at<int8_t>(ws, L.F), at<int32_t>(ws, L.act), at<long long>(ws, L.acc),
+                   at<int64_t>(ws, L.value), at<int32_t>(ws, L.X), at<int32_t>(ws, L.Xt), at<int32_t>(ws, L.V),
+                   at<uint32_t>(ws, L.tnb), s, nullptr, alternations, candidate_kernel_ms);
 }
 
 int mqo_reset(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t seed, int32_t round, double rho,

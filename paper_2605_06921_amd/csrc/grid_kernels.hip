@@ -454,6 +454,12 @@ __global__ void k_strided_copy_f32(const float *__restrict__ src, int32_t lds, i
   if (v < n) dst[(lo + v) * ldd + cd] = src[(lo + v) * lds + cs];
 }
 
+__global__ void k_strided_copy_i8(const int8_t *__restrict__ src, int32_t lds, int32_t cs, int8_t *__restrict__ dst,
+                                  int32_t ldd, int32_t cd, int64_t lo, int64_t n) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) dst[(lo + v) * ldd + cd] = src[(lo + v) * lds + cs];
+}
+
 __global__ void k_fill_i32(int32_t *p, int64_t count, int32_t value) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = value;
@@ -1542,6 +1548,68 @@ __global__ void k_mask_empty(int64_t *__restrict__ value, const int64_t *__restr
   if (i < count && pv[i] == INT64_MIN) value[i] = INT64_MIN;
 }
 
+// sum of count doubles in a fixed order (one workgroup: lane-strided partial
+// sums, then a tree over the 256 lanes), so repeated calls agree bit for bit
+__global__ __launch_bounds__(256) void k_sum_f64(const double *__restrict__ in, int64_t count,
+                                                 double *__restrict__ out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += 256) acc += in[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+// ---------------------------------------------------------------------------
+// best set of the pool modes (I_sol of Alg. 3, S_sol of Alg. 4): graph g is
+// offered K candidate values cand[g K + c] in column order and takes each one
+// that is strictly above what it holds, so it ends with the first candidate of
+// the largest value when that beats sol_v[g].  filled (optional): a candidate
+// counts only where filled[g K + c] != INT64_MIN (a pool slot in use);
+// need_sol: a graph that holds no set yet (INT64_MIN) takes nothing.
+// choice[g] = the column taken, -1 for none.
+// ---------------------------------------------------------------------------
+__global__ void k_offer_pick(const int64_t *__restrict__ cand, const int64_t *__restrict__ filled, int32_t K,
+                             int32_t G, int32_t need_sol, int64_t *__restrict__ sol_v, int32_t *__restrict__ choice) {
+  const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  int64_t cur = sol_v[g];
+  int32_t pick = -1;
+  if (!(need_sol && cur == INT64_MIN)) {
+    for (int32_t c = 0; c < K; ++c) {
+      const int64_t i = (int64_t)g * K + c;
+      if (filled && filled[i] == INT64_MIN) continue;
+      if (cand[i] > cur) {
+        cur = cand[i];
+        pick = c;
+      }
+    }
+  }
+  choice[g] = pick;
+  if (pick >= 0) sol_v[g] = cur;
+}
+
+// rows of every graph that took a candidate: sol_z[v] = Z[v ld + choice[g]]
+__global__ void k_offer_copy(const int8_t *__restrict__ Z, int32_t ld, const int32_t *__restrict__ choice,
+                             const int64_t *__restrict__ voff, int32_t G, int8_t *__restrict__ sol_z, int64_t n_total) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n_total) return;
+  int32_t lo = 0, hi = G;  // g with voff[g] <= v < voff[g+1]
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (voff[mid] <= v)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const int32_t c = choice[lo];
+  if (c >= 0) sol_z[v] = Z[v * ld + c];
+}
+
 // ---------------------------------------------------------------------------
 // answer per graph: best incumbent, ties to the lowest trajectory
 // ---------------------------------------------------------------------------
@@ -2339,6 +2407,22 @@ void launch_pool_bases(const int64_t *pv, int32_t K, int32_t ncols, uint64_t see
 
 void launch_mask_empty(int64_t *value, const int64_t *pv, int64_t count, hipStream_t s) {
   MQO_LAUNCH(k_mask_empty, dim3(blocks_for(count)), dim3(256), 0, s, value, pv, count);
+}
+
+void launch_sum_f64(const double *in, int64_t count, double *out, hipStream_t s) {
+  MQO_LAUNCH(k_sum_f64, dim3(1), dim3(256), 0, s, in, count, out);
+}
+
+void launch_offer(const int8_t *Z, int32_t ld, const int64_t *cand, const int64_t *filled, int32_t K, int32_t G,
+                  bool need_sol, const int64_t *voff, int64_t n_total, int64_t *sol_v, int8_t *sol_z,
+                  int32_t *choice, hipStream_t s) {
+  MQO_LAUNCH(k_offer_pick, dim3(blocks_for(G)), dim3(256), 0, s, cand, filled, K, G, (int32_t)need_sol, sol_v, choice);
+  MQO_LAUNCH(k_offer_copy, dim3(blocks_for(n_total)), dim3(256), 0, s, Z, ld, choice, voff, G, sol_z, n_total);
+}
+
+void launch_strided_copy_i8(const int8_t *src, int32_t lds, int32_t cs, int8_t *dst, int32_t ldd, int32_t cd,
+                            int64_t lo, int64_t n, hipStream_t s) {
+  MQO_LAUNCH(k_strided_copy_i8, dim3(blocks_for(n)), dim3(256), 0, s, src, lds, cs, dst, ldd, cd, lo, n);
 }
 
 void launch_pick_best(const int64_t *best, int32_t G, int32_t B, int64_t *best_value, int32_t *best_b,

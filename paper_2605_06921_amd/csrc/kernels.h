@@ -92,6 +92,18 @@ void launch_pool_update(bool maxcut, const int8_t *Z, int32_t ld, int64_t lo, in
 void launch_pool_bases(const int64_t *pv, int32_t K, int32_t ncols, uint64_t seed, uint64_t traj0, uint64_t round,
                        int32_t *base, hipStream_t s);
 void launch_mask_empty(int64_t *value, const int64_t *pv, int64_t count, hipStream_t s);
+// *out = sum of in[0 .. count) in a fixed order (one workgroup)
+void launch_sum_f64(const double *in, int64_t count, double *out, hipStream_t s);
+// best set of the pool modes: graph g is offered the K candidates
+// cand[g K + c] (columns c of Z, leading dimension ld) in column order and
+// takes each that is strictly above sol_v[g]; filled (optional): only
+// columns with filled[g K + c] != INT64_MIN count; need_sol: graphs with no
+// set yet (sol_v == INT64_MIN) take nothing.  choice: [G] scratch.
+void launch_offer(const int8_t *Z, int32_t ld, const int64_t *cand, const int64_t *filled, int32_t K, int32_t G,
+                  bool need_sol, const int64_t *voff, int64_t n_total, int64_t *sol_v, int8_t *sol_z,
+                  int32_t *choice, hipStream_t s);
+void launch_strided_copy_i8(const int8_t *src, int32_t lds, int32_t cs, int8_t *dst, int32_t ldd, int32_t cd,
+                            int64_t lo, int64_t n, hipStream_t s);
 void launch_pick_best(const int64_t *best, int32_t G, int32_t B, int64_t *best_value, int32_t *best_b, hipStream_t s);
 void launch_copy_best_x(const int8_t *Zb, int32_t B, const int64_t *voff, int32_t G, const int32_t *best_b,
                         int8_t *out, int64_t n_total, hipStream_t s);

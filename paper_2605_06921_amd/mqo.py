@@ -52,7 +52,8 @@ class _Params(ctypes.Structure):
                 ("tile_csr", ctypes.c_int32), ("tile_reg", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("time_budget_s", ctypes.c_double), ("maxcut_objective", ctypes.c_int32),
                 ("final_search", ctypes.c_int32), ("pool_k", ctypes.c_int32),
-                ("restart_every", ctypes.c_int32)]
+                ("restart_every", ctypes.c_int32), ("traj_count", ctypes.c_int32),
+                ("traj_ids", ctypes.POINTER(ctypes.c_int64))]
 
 
 class _Result(ctypes.Structure):
@@ -84,8 +85,8 @@ def _load():
         "mqo_objective_grad": (i32, [G, i32, f32, vp, i32, vp, vp, vp, vp, sz, vp]),
         "mqo_unrolled_workspace_size": (sz, [G, i32, i32]),
         "mqo_pga_unrolled_forward": (i32, [G, i32, f32, f32, i32, i32, vp, vp, vp, i32, vp, sz, vp]),
-        "mqo_pga_unrolled_backward": (i32, [G, i32, f32, f32, i32, i32, vp, vp, vp, vp, i32, vp, sz, vp]),
-        "mqo_init_iterate": (i32, [G, i32, P, vp, vp]),
+        "mqo_pga_unrolled_backward": (i32, [G, i32, f32, f32, i32, i32, vp, vp, vp, vp, vp, i32, vp, sz, vp]),
+        "mqo_init_iterate": (i32, [G, i32, P, vp, vp, sz, vp]),
         "mqo_pga_steps": (i32, [G, i32, P, vp, vp, vp, i32, vp]),
         "mqo_round_evaluate": (i32, [G, i32, vp, i32, vp, vp, vp, vp, vp, sz, vp]),
         "mqo_local_search": (i32, [G, i32, i32, u64, i32, vp, ctypes.POINTER(i64), vp, sz, vp]),
@@ -254,20 +255,30 @@ _default_ws = {}
 
 
 def _ws_for(device, ws: Optional[Workspace]) -> Workspace:
+    """The caller's workspace, else the default one of (device, current
+    stream): calls queued on different streams never share scratch, and each
+    default buffer is allocated while its stream is current."""
     if ws is not None:
         return ws
-    key = str(device)
+    dev = torch.device(device)
+    key = (str(dev), torch.cuda.current_stream(dev).cuda_stream)
     if key not in _default_ws:
-        _default_ws[key] = Workspace(device)
+        _default_ws[key] = Workspace(dev)
     return _default_ws[key]
 
 
 def solve(kind, dg: DeviceGraph, x0: Optional[torch.Tensor] = None, workspace: Optional[Workspace] = None,
-          want_traj: bool = True, **params):
+          want_traj: bool = True, trajectories=None, **params):
     """Batched mutation-guided search (mqo_solve_mis / mqo_solve_maxcut).
-    Returns a dict of device tensors and host counters."""
+    ``trajectories`` (plain plan): ascending ids g * batch + b of the only
+    trajectories to run.  Returns a dict of device tensors and host counters."""
     k = _KIND[kind]
     p = make_params(**params)
+    ids = None
+    if trajectories is not None:
+        ids = np.ascontiguousarray(np.asarray(trajectories, dtype=np.int64))
+        p.traj_count = len(ids)
+        p.traj_ids = ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     if k != MIS:
         p.maxcut_objective = k  # the formulation of the MaxCut steps
     B, G = p.batch, dg.num_graphs
@@ -328,11 +339,16 @@ def _solve_ws(dg, kind, B, workspace=None):
     return _ws_for(dg.device, workspace).get(nbytes), nbytes
 
 
-def init_iterate(kind, dg: DeviceGraph, batch: int, seed: int, init_mode="uniform", init_sigma=0.0):
+INIT_WORKSPACE_BYTES = 256  # MQO_INIT_WORKSPACE_BYTES
+
+
+def init_iterate(kind, dg: DeviceGraph, batch: int, seed: int, init_mode="uniform", init_sigma=0.0,
+                 workspace=None):
     p = make_params(batch=batch, seed=seed, init_mode=init_mode, init_sigma=init_sigma)
     X = torch.empty(dg.n * batch, dtype=torch.float32, device=dg.device)
-    _check(_lib.mqo_init_iterate(dg.struct, _KIND[kind], ctypes.byref(p), _ptr(X), _stream(dg.device)),
-           "mqo_init_iterate")
+    ws = _ws_for(dg.device, workspace).get(INIT_WORKSPACE_BYTES)
+    _check(_lib.mqo_init_iterate(dg.struct, _KIND[kind], ctypes.byref(p), _ptr(X), ctypes.c_void_p(ws.data_ptr()),
+                                 INIT_WORKSPACE_BYTES, _stream(dg.device)), "mqo_init_iterate")
     return X.view(dg.n, batch)
 
 
@@ -420,13 +436,13 @@ def reset(kind, dg: DeviceGraph, Zbest: torch.Tensor, seed: int, rnd: int, rho: 
 # --------------------------------------------------------------------------
 
 def objective_grad(kind, dg: DeviceGraph, X: torch.Tensor, param: float, scale: Optional[torch.Tensor] = None,
-                   want_f=True, want_grad=True):
+                   want_f=True, want_grad=True, workspace=None):
     B = X.shape[1]
     G = dg.num_graphs
     f = torch.empty(G * B, dtype=torch.float64, device=dg.device) if want_f else None
     grad = torch.empty_like(X) if want_grad else None
     nbytes = _lib.mqo_objective_workspace_size(dg.struct, B)
-    ws = _ws_for(dg.device, None).get(nbytes) if want_f else None
+    ws = _ws_for(dg.device, workspace).get(nbytes) if want_f else None
     if scale is not None:
         scale = scale.to(torch.float32).contiguous()
     _check(_lib.mqo_objective_grad(dg.struct, _KIND[kind], float(param), _ptr(X.contiguous()), B, _ptr(scale),
@@ -457,13 +473,14 @@ def objective(X, dg, kind, param):
     return Objective.apply(X, dg, kind, param)
 
 
-def unrolled_forward(kind, dg: DeviceGraph, X0: torch.Tensor, alpha: float, K: int, ckpt_every: int, param: float):
+def unrolled_forward(kind, dg: DeviceGraph, X0: torch.Tensor, alpha: float, K: int, ckpt_every: int, param: float,
+                     workspace=None):
     B = X0.shape[1]
     nseg = K // ckpt_every
     ckpt = torch.empty(nseg, dg.n, B, dtype=torch.float32, device=dg.device)
     XK = torch.empty_like(X0)
     nbytes = _lib.mqo_unrolled_workspace_size(dg.struct, B, ckpt_every)
-    ws = _ws_for(dg.device, None).get(nbytes)
+    ws = _ws_for(dg.device, workspace).get(nbytes)
     _check(_lib.mqo_pga_unrolled_forward(dg.struct, _KIND[kind], float(param), float(alpha), K, ckpt_every,
                                          _ptr(X0.contiguous()), _ptr(ckpt), _ptr(XK), B,
                                          ctypes.c_void_p(ws.data_ptr()), nbytes, _stream(dg.device)),
@@ -472,17 +489,20 @@ def unrolled_forward(kind, dg: DeviceGraph, X0: torch.Tensor, alpha: float, K: i
 
 
 def unrolled_backward(kind, dg: DeviceGraph, ckpt: torch.Tensor, dL_dXK: torch.Tensor, alpha: float, K: int,
-                      ckpt_every: int, param: float):
+                      ckpt_every: int, param: float, workspace=None, want_sum=False):
+    """dL/dx_0 [n][B] and dL/dalpha per trajectory [G*B] (float64); with
+    ``want_sum`` also their sum over all trajectories (a 0-d float64 tensor)."""
     B = dL_dXK.shape[1]
     dX0 = torch.empty_like(dL_dXK)
     dalpha = torch.empty(dg.num_graphs * B, dtype=torch.float64, device=dg.device)
+    dsum = torch.empty((), dtype=torch.float64, device=dg.device) if want_sum else None
     nbytes = _lib.mqo_unrolled_workspace_size(dg.struct, B, ckpt_every)
-    ws = _ws_for(dg.device, None).get(nbytes)
+    ws = _ws_for(dg.device, workspace).get(nbytes)
     _check(_lib.mqo_pga_unrolled_backward(dg.struct, _KIND[kind], float(param), float(alpha), K, ckpt_every,
-                                          _ptr(ckpt), _ptr(dL_dXK.contiguous()), _ptr(dX0), _ptr(dalpha), B,
-                                          ctypes.c_void_p(ws.data_ptr()), nbytes, _stream(dg.device)),
-           "mqo_pga_unrolled_backward")
-    return dX0, dalpha
+                                          _ptr(ckpt), _ptr(dL_dXK.contiguous()), _ptr(dX0), _ptr(dalpha),
+                                          _ptr(dsum), B, ctypes.c_void_p(ws.data_ptr()), nbytes,
+                                          _stream(dg.device)), "mqo_pga_unrolled_backward")
+    return (dX0, dalpha, dsum) if want_sum else (dX0, dalpha)
 
 
 class UnrolledPGA(torch.autograd.Function):
@@ -500,8 +520,8 @@ class UnrolledPGA(torch.autograd.Function):
     def backward(ctx, grad_XK):
         (ckpt,) = ctx.saved_tensors
         dg, kind, param, alpha, K, c, adt, adev = ctx.meta
-        dX0, dalpha = unrolled_backward(kind, dg, ckpt, grad_XK.contiguous(), alpha, K, c, param)
-        return dX0, dalpha.sum().to(adt).to(adev), None, None, None, None, None
+        dX0, _, dsum = unrolled_backward(kind, dg, ckpt, grad_XK.contiguous(), alpha, K, c, param, want_sum=True)
+        return dX0, dsum.to(adt).to(adev), None, None, None, None, None
 
 
 def unrolled_pga(X0, alpha, dg, kind, param, K=20, ckpt_every=5):

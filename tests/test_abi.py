@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(m):
 
 
 def test_version_status_and_params(m):
-    assert m.version() == 100
+    assert m.version() == 110
     L = m.lib()
     assert L.mqo_status_string(0) == b"ok"
     assert L.mqo_status_string(-2) == b"invalid graph"
@@ -174,3 +174,34 @@ def test_async_entry_points_reject_bad_arguments(m):
                                       ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 4, None, 0, None) == -1
     assert L.mqo_reset(ctypes.byref(s), 0, 4, 0, 1, 1.5, 0, ctypes.c_void_p(0x1000), None, ctypes.c_void_p(0x1000),
                        None, 0, None) == -1
+
+
+def test_degree_init_needs_its_scratch(m):
+    """The degree initialisation measures the largest degree into caller
+    scratch (so calls on different streams never share it): without it the
+    call is refused before anything runs."""
+    L = m.lib()
+    s, off = _struct(m)
+    p = m.make_params(batch=4, init_mode="degree")
+    X = ctypes.c_void_p(0x1000)
+    assert L.mqo_init_iterate(ctypes.byref(s), 0, ctypes.byref(p), X, None, 0, None) == -3
+    assert L.mqo_init_iterate(ctypes.byref(s), 0, ctypes.byref(p), X, ctypes.c_void_p(0x1000),
+                              m.INIT_WORKSPACE_BYTES - 1, None) == -3
+
+
+def test_trajectory_subset_checked_on_host(m):
+    L = m.lib()
+    s, off = _struct(m)  # one graph
+    r = m._Result(0x1000, 0x1000)  # output pointers, never written: the call stops first
+    for ids, plan, status in [([0, 2], "batched", -5), ([2, 1], "plain", -1), ([0, 4], "plain", -1),
+                              ([1, 1], "plain", -1), ([-1], "plain", -1), ([0, 3], "plain", -3)]:
+        p = m.make_params(batch=4, plan=plan)
+        arr = np.array(ids, dtype=np.int64)
+        p.traj_count = len(arr)
+        p.traj_ids = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        # no workspace: a valid subset gets as far as the workspace check
+        assert L.mqo_solve_mis(ctypes.byref(s), ctypes.byref(p), None, ctypes.byref(r), ctypes.c_void_p(0x1000),
+                               0, None) == status, (ids, plan, m.last_error())
+    p = m.make_params(batch=4, plan="plain")
+    p.traj_count = 2
+    assert L.mqo_solve_mis(ctypes.byref(s), ctypes.byref(p), None, ctypes.byref(r), None, 0, None) == -1

@@ -305,14 +305,81 @@ def test_degree_init_close_to_oracle(mqo):
         assert np.abs(X - ref).max() < 1e-5
 
 
-def test_time_budget_stops_early(mqo):
-    g = graphs.erdos_renyi(300, 0.03, 93)
+@pytest.mark.parametrize("kind", ["mis", "maxcut"])
+def test_plain_trajectory_subset(mqo, kind):
+    """The plain plan on a subset of trajectory ids runs each of them exactly
+    as the full batched solve does; the others hold no incumbent."""
+    g = CASES["er_batch"][1] if kind == "mis" else CASES["cut_batch"][1]
     dg = mqo.DeviceGraph(g, DEV)
-    for plan in ("persistent", "batched"):
-        out = mqo.solve("mis", dg, batch=4, steps_per_round=10, rounds=1000, alpha=0.01, seed=1, plan=plan,
-                        time_budget_s=1e-9)
-        assert out["rounds_executed"] == 1
-        assert out["steps_executed"] == 10
+    B = 8
+    kw = dict(batch=B, steps_per_round=20, rounds=3, alpha=0.05, rho=0.15, seed=81, final_search=True)
+    ids = np.array([1, 6, B + 0, 2 * B + 3, (g.num_graphs - 1) * B + 7])
+    full = mqo.solve(kind, dg, plan="batched", **kw)
+    sub = mqo.solve(kind, dg, plan="plain", trajectories=ids, **kw)
+    tv, tx = sub["traj_best_value"].cpu().numpy(), sub["traj_best_x"].cpu().numpy()
+    assert np.array_equal(tv[ids], full["traj_best_value"].cpu().numpy()[ids])
+    fx = full["traj_best_x"].cpu().numpy()
+    ran = np.zeros_like(tx, dtype=bool)
+    for t in ids:
+        gi, b = divmod(int(t), B)
+        lo, hi = g.vtx_offset[gi], g.vtx_offset[gi + 1]
+        assert np.array_equal(tx[lo:hi, b], fx[lo:hi, b])
+        ran[lo:hi, b] = True
+    assert np.all(tx[~ran] == 0)
+    rest = np.setdiff1d(np.arange(g.num_graphs * B), ids)
+    assert np.all(tv[rest] == np.iinfo(np.int64).min)
+    nnz = np.diff(g.row_ptr[g.vtx_offset])
+    assert sub["edge_updates"] == sum(int(nnz[t // B]) for t in ids) * 20 * 3
+    ref = solver.solve(kind, g, solver.Params(**kw))
+    assert np.array_equal(tv[ids], ref["traj_best_value"][ids])
+
+
+def test_two_streams_at_once(mqo):
+    """Degree initialisation and objective + gradient queued on two streams
+    at the same time, each with its default workspace (one per stream):
+    both results equal the oracle's."""
+    g = graphs.barabasi_albert(3000, 3, 97)
+    dg = mqo.DeviceGraph(g, DEV)
+    B = 16
+    Xm = torch.from_numpy(_x("mis", g.n, B, 98)).to(DEV)
+    Xc = torch.from_numpy(_x("maxcut", g.n, B, 99)).to(DEV)
+    main = torch.cuda.current_stream()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(main)
+    s2.wait_stream(main)
+    with torch.cuda.stream(s1):
+        Ia = mqo.init_iterate("mis", dg, B, seed=8, init_mode="degree", init_sigma=0.2)
+        fa, ga = mqo.objective_grad("mis", dg, Xm, 2.0)
+    with torch.cuda.stream(s2):
+        Ib = mqo.init_iterate("maxcut", dg, B, seed=9, init_mode="degree", init_sigma=0.3)
+        fb, gb = mqo.objective_grad("maxcut", dg, Xc, 1e-3)
+    torch.cuda.synchronize()
+    deg = g.degrees()
+    assert np.abs(Ia.cpu().numpy() - pga.init_degree("mis", deg, np.arange(B), 8, 0.2)).max() < 1e-5
+    assert np.abs(Ib.cpu().numpy() - pga.init_degree("maxcut", deg, np.arange(B), 9, 0.3)).max() < 1e-5
+    for kind, X, param, f, gr in (("mis", Xm, 2.0, fa, ga), ("maxcut", Xc, 1e-3, fb, gb)):
+        X0 = X.cpu().numpy()
+        fr, grr = pga.objective_and_grad(g, kind, param, X0.astype(np.float64))
+        assert np.allclose(f.cpu().numpy(), fr, rtol=1e-5, atol=1e-5 * np.abs(X0).sum())
+        assert np.abs(gr.cpu().numpy() - grr).max() / max(1.0, np.abs(grr).max()) <= 1e-5
+
+
+@pytest.mark.parametrize("plan,pool", [("persistent", 0), ("batched", 0), ("plain", 0), ("batched", 2)])
+@pytest.mark.parametrize("kind", ["mis", "maxcut"])
+def test_time_budget_stops_after_round_0(mqo, plan, pool, kind):
+    # a budget that has run out before round 1: every trajectory runs round 0
+    # (the plain plan too, one trajectory after the other), and the pass the
+    # budget cut short ends with the pair search (round index = rounds)
+    g = CASES["er_batch"][1] if kind == "mis" else CASES["cut_batch"][1]
+    dg = mqo.DeviceGraph(g, DEV)
+    kw = dict(batch=4, steps_per_round=10, rounds=1000, alpha=0.01, rho=0.1, seed=1, final_search=True, pool_k=pool)
+    out = mqo.solve(kind, dg, plan=plan, time_budget_s=1e-9, **kw)
+    assert out["plan"] == plan
+    assert out["rounds_executed"] == 1
+    assert out["steps_executed"] == 10
+    ref = solver.solve(kind, g, solver.Params(rounds_run=1, **kw))
+    for key in ("traj_best_value", "traj_best_x", "best_value", "best_x") + (("pool_value", "pool_x") if pool else ()):
+        assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
 
 
 def test_invalid_graph_rejected_before_launch(mqo):
@@ -834,6 +901,23 @@ def test_restarts_bit_exact(mqo, kind, plan, pool):
     assert np.array_equal(out["traj_best_value"].cpu().numpy(), ref["traj_best_value"])
     assert np.array_equal(out["traj_best_x"].cpu().numpy(), ref["traj_best_x"])
     assert np.array_equal(out["best_value"].cpu().numpy(), ref["best_value"])
+
+
+@pytest.mark.parametrize("kind", ["mis", "maxcut"])
+@pytest.mark.parametrize("plan,pool", [("batched", 0), ("plain", 0), ("batched", 3), ("batched", 6)])
+def test_restarts_with_pass_searches_bit_exact(mqo, kind, plan, pool):
+    # the pair search closes every pass of the outer loop (rounds 2, 5 and the
+    # last, 6): Alg. 1 / 2 reset the next pass from the searched incumbents,
+    # Alg. 3 searches I_sol, Alg. 4 every pool member into S_sol
+    g = CASES["er_batch"][1] if kind == "mis" else CASES["cut_batch"][1]
+    kw = dict(batch=6, steps_per_round=20, rounds=7, alpha=0.05, rho=0.15, seed=75, restart_every=3, pool_k=pool,
+              final_search=True)
+    out = mqo.solve(kind, mqo.DeviceGraph(g, DEV), plan=plan, **kw)
+    assert out["plan"] == plan
+    ref = solver.solve(kind, g, solver.Params(**kw))
+    for key in ("traj_best_value", "traj_best_x", "best_value", "best_x") + (("pool_value", "pool_x") if pool else ()):
+        assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
+    assert out["final_search_alternations"] >= 0
 
 
 def test_restarts_rejected_on_the_persistent_plan(mqo):

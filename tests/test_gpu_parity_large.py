@@ -40,11 +40,32 @@ def _params(wl, cols=None):
                          local_search=wl.local_search)
 
 
-def _solve_gpu(mqo, wl, g):
+def _solve_gpu(mqo, wl, g, **kw):
     dg = mqo.DeviceGraph(g, DEV)
-    return mqo.solve(wl.problem, dg, batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=wl.rounds,
-                     alpha=wl.alpha, gamma=wl.gamma, lam=wl.lam, rho=wl.rho, reset_mode=wl.reset_mode,
-                     local_search=wl.local_search, seed=wl.seed)
+    args = dict(batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=wl.rounds, alpha=wl.alpha,
+                gamma=wl.gamma, lam=wl.lam, rho=wl.rho, reset_mode=wl.reset_mode, local_search=wl.local_search,
+                seed=wl.seed)
+    args.update(kw)
+    return mqo.solve(wl.problem, dg, **args)
+
+
+# --------------------------------------------------------------------------
+# the one-trajectory MIS workload at its exact parameters, every plan
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("plan", ["plain", "persistent", "batched"])
+def test_er100_mis_exact_parameters(mqo, plan):
+    """ER G(100, 0.1), gamma = 2, one trajectory, 1000 steps of 0.01 in one
+    round, rounding at 0.5, then the 1-flip search (repair + maximalisation)."""
+    wl = WORKLOADS["er100_mis"]
+    g = _graph("er100_mis")
+    assert (wl.batch, wl.steps_per_round, wl.rounds, wl.alpha, wl.gamma) == (1, 1000, 1, 0.01, 2.0)
+    out = _solve_gpu(mqo, wl, g, plan=plan)
+    assert out["plan"] == plan and out["steps_executed"] == 1000
+    ref = solver.solve(wl.problem, g, _params(wl))
+    for key in ("traj_best_value", "traj_best_x", "best_value", "best_x"):
+        assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
+    assert discrete.is_maximal_independent(g, out["best_x"].cpu().numpy()[:, None])[0]
 
 
 # --------------------------------------------------------------------------
@@ -179,6 +200,28 @@ def test_million_vertex_round_pieces(mqo, name):
     assert np.all((Xr == 0).sum(0) >= k) if wl.problem == "mis" else np.all((Xr == 0).sum(0) == k)
 
 
+@pytest.mark.parametrize("name", ["er1m_mis", "torus1m_maxcut"])
+def test_million_vertex_full_round_and_next_reset(mqo, name):
+    """One whole round at full size in the launch shape of the benchmark
+    (32 trajectories, 200 captured steps, rounding, 1-flip search,
+    evaluation, acceptance) and the reset that starts round 1, compared with
+    the oracle on one sampled trajectory."""
+    wl = WORKLOADS[name]
+    g = _graph(name)
+    dg = mqo.DeviceGraph(g, DEV)
+    out = _solve_gpu(mqo, wl, g, rounds=1)
+    c = 21
+    vals, zb = solver.solve_graph(wl.problem, g, _params(wl), 0, cols=[c])
+    tv = out["traj_best_value"].cpu().numpy()
+    assert tv[c] == vals[0]
+    Zb = out["traj_best_x"]
+    assert np.array_equal(Zb.cpu().numpy()[:, [c]], zb)
+    assert out["best_value"].item() == tv.max()
+    Xr = mqo.reset(wl.problem, dg, Zb, seed=wl.seed, rnd=1, rho=wl.rho, mode=wl.reset_mode).cpu().numpy()
+    mask = discrete.reset_set(g.n, discrete.reset_count(wl.rho, g.n), wl.seed, np.array([c]), 1)
+    assert np.array_equal(Xr[:, [c]], discrete.reset_apply(wl.problem, zb, mask, wl.reset_mode))
+
+
 # --------------------------------------------------------------------------
 # differentiation at the 1e5-vertex shapes, batch 64
 # --------------------------------------------------------------------------
@@ -296,9 +339,11 @@ def test_pool_torus_full_size_properties(mqo):
     assert np.all(pv > np.iinfo(np.int64).min)  # the pool is full
     assert np.array_equal(discrete.evaluate_cut(g, pz), pv)
     assert len({pz[:, k].tobytes() for k in range(K)}) == K
-    assert out["best_value"].item() == pv.max()
+    # S_sol: at least the pool's best, then improved by the search of every member
+    bx = out["best_x"].cpu().numpy()
+    assert out["best_value"].item() >= pv.max()
     assert out["best_value"].item() >= out["traj_best_value"].cpu().numpy().max()
-    assert np.array_equal(out["best_x"].cpu().numpy(), pz[:, int(np.argmax(pv))])
+    assert discrete.evaluate_cut(g, bx[:, None])[0] == out["best_value"].item()
 
 
 def test_toy_bench_size_sampled(mqo):

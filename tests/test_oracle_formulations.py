@@ -94,3 +94,50 @@ def test_float32_replay_close_to_float64(kind):
     y32, _ = pga.step32(g, X, kind, 0.05, 0.2)
     y64, _ = pga.step64(X.astype(np.float64), obj.adjacency(g), kind, 0.05, 0.2)
     assert np.abs(y32 - y64).max() <= 1e-5
+
+
+def _run_to_convergence(kind, A, X, alpha, steps):
+    for _ in range(steps):
+        Y, _ = pga.step64(X, A, kind, alpha, 1e-3)
+        if np.array_equal(Y, X):
+            break
+        X = Y
+    return X
+
+
+def test_escape_from_c1_cut_at_convergence():
+    """App. B's first escapability set-up (ER(100, 0.66), x0 = c 1,
+    lambda = 1e-3), with the cut recorded at convergence in float64.
+    Exact arithmetic: c 1 is stationary for f_L (Prop. 3.2) and PGA on f_P
+    stays uniform (its gradient there is 2 lambda c 1), so both end at cut 0;
+    f_B's gradient -lambda - 2 c d varies with the degree d.  Float64: the
+    row sums of L (c 1) are exactly zero only when c d is exact (c = 0.375);
+    otherwise their rounding grows by the ascent on the positive
+    semi-definite x^T L x and f_L and f_P leave the diagonal to large cuts.
+    f_B at the appendix's alpha = 0.1 overshoots: within two steps every
+    coordinate sits at the same bound, and the iterate alternates between
+    -1 and +1 with cut 0; at alpha = 1e-3 it converges to cuts near 1800."""
+    g = graphs.erdos_renyi(100, 0.66, 700)
+    A = obj.adjacency(g)
+    cs = np.array([[-0.83, -0.07, 0.3, 0.77]])
+    X0 = np.repeat(cs, g.n, 0)
+    cut = lambda kind, X: discrete.evaluate_cut(g, discrete.round_x(kind, X))  # noqa: E731
+    # f_L from an exactly representable c 1: stationary, nothing moves
+    X = np.full((g.n, 1), 0.375)
+    assert np.array_equal(_run_to_convergence(obj.MAXCUT_L, A, X, 0.1, 50), X)
+    assert cut(obj.MAXCUT_L, X)[0] == 0
+    # f_P from an exact c 1: the exact gradient is 2 lambda c 1
+    assert np.array_equal(obj.grad_f_P(X, A, 1e-3), np.full((g.n, 1), 2 * 1e-3 * 0.375))
+    # float64 rounding: f_L and f_P escape from generic c (f_P also from 0.375)
+    assert np.all(cut(obj.MAXCUT_L, _run_to_convergence(obj.MAXCUT_L, A, X0, 0.1, 200)) >= 1300)
+    XP = np.concatenate([X0, X], 1)
+    assert np.all(cut(obj.MAXCUT_P, _run_to_convergence(obj.MAXCUT_P, A, XP, 0.1, 200)) >= 1300)
+    # f_B at alpha = 0.1: a uniform +-1 iterate after two steps, cut 0
+    XB = X0
+    for _ in range(2):
+        XB, _ = pga.step64(XB, A, obj.MAXCUT, 0.1, 1e-3)
+    assert np.all(np.abs(XB) == 1) and np.all(XB == XB[:1])
+    XB2, _ = pga.step64(XB, A, obj.MAXCUT, 0.1, 1e-3)
+    assert np.array_equal(XB2, -XB) and np.all(cut(obj.MAXCUT, XB) == 0)
+    # f_B at alpha = 1e-3 leaves the diagonal in exact arithmetic too
+    assert np.all(cut(obj.MAXCUT, _run_to_convergence(obj.MAXCUT, A, X0, 1e-3, 1500)) >= 1750)

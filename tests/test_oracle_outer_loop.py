@@ -128,3 +128,22 @@ def test_answers_are_pair_optimal_after_every_pass(kind, pool_k):
         # the pool is the same with and without the search of Alg. 3 / 4
         assert np.array_equal(fin["pool_value"], plain["pool_value"])
         assert np.array_equal(fin["pool_x"], plain["pool_x"])
+
+
+def test_budget_cut_runs_the_first_rounds_and_still_searches_the_cut_pass():
+    """rounds_run = q stands for a time budget that runs out after q rounds:
+    without the search the run is a q-round run; with it the pass the budget
+    cut short still ends with the search (on the path, round 0 holds {b}
+    and the search makes it {a, c})."""
+    g = graphs.path(3)
+    x0 = np.array([[0.2], [0.9], [0.2]], dtype=np.float32)
+    for q in (1, 2, 3):
+        cut = solver.solve_graph("mis", g, _params(seed=3, final_search=False, rounds_run=q), x0=x0)
+        short = solver.solve_graph("mis", g, _params(seed=3, final_search=False, rounds=q), x0=x0)
+        assert np.array_equal(cut[0], short[0]) and np.array_equal(cut[1], short[1])
+    trace = []
+    best, zb = solver.solve_graph("mis", g, _params(seed=3, rounds_run=1), x0=x0, trace=trace)
+    assert len(trace) == 1 and int(trace[0]["value"][0]) == 1
+    assert best.tolist() == [2] and zb[:, 0].tolist() == [1, 0, 1]
+    with pytest.raises(AssertionError):
+        solver.solve_graph("mis", g, _params(seed=3, rounds_run=5), x0=x0)
