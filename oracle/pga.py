@@ -44,7 +44,37 @@ def step64(X, A, kind, alpha, param, mu=0.0, V=None):
 
 
 def neighbour_sum32(graph, X):
-    """float32 sum over neighbours in ascending CSR order, one rounding per add."""
+    """float32 sum over neighbours in ascending CSR order, one rounding per add.
+
+    Unweighted or +-1 weights: scipy's CSR product in float32, which starts
+    every row at 0 and adds its terms into a float32 accumulator in stored
+    order; the products by +-1 are exact, so a fused multiply-add in the
+    library could not change a rounding.  (Pinned bit for bit against the
+    position-by-position loop, ``neighbour_sum32_positions``, which serves
+    every other weight.)"""
+    X = np.asarray(X, dtype=F32)
+    if graph.weight is not None and not np.all(np.abs(graph.weight) == 1):
+        return neighbour_sum32_positions(graph, X)
+    A = _csr32(graph)
+    return np.asarray(A @ X, dtype=F32).reshape(X.shape)
+
+
+def _csr32(graph):
+    """The graph's float32 CSR matrix, built once per graph object."""
+    import scipy.sparse as sp
+    cached = getattr(graph, "_oracle_csr32", None)
+    if cached is not None and cached[0] is graph.row_ptr and cached[1] is graph.col_idx:
+        return cached[2]
+    data = np.ones(graph.nnz, dtype=F32) if graph.weight is None else graph.weight.astype(F32)
+    A = sp.csr_matrix((data, graph.col_idx, graph.row_ptr), shape=(graph.n, graph.n))
+    graph._oracle_csr32 = (graph.row_ptr, graph.col_idx, A)
+    return A
+
+
+def neighbour_sum32_positions(graph, X):
+    """The definition, vectorised over rows: the k-th stored neighbour of
+    every row of degree > k is added for k = 0, 1, ... (float32, one
+    rounding per add, each row in ascending CSR order)."""
     X = np.asarray(X, dtype=F32)
     acc = np.zeros_like(X)
     deg = np.diff(graph.row_ptr).astype(np.int64)

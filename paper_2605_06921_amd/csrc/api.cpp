@@ -81,6 +81,12 @@ Resources &res() {
   return r;
 }
 
+// hipGetLastError reports the last error any runtime call of this host
+// thread returned, including calls the caller made before ours.  Every
+// entry point drops such an error before its first launch, so the check
+// after its launches sees only its own.
+inline void drop_stale_error() { (void)hipGetLastError(); }
+
 int ensure_resources() {
   Resources &r = res();
   int dev = 0;
@@ -407,6 +413,25 @@ struct Solve {
   int64_t search_alt = 0;  // pair iterations that applied a move, summed over the pass searches
   int32_t deferred_tile_wg = 0;  // > 0: the tile counters sit in the pinned buffer after the final sync
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;  // around the step launches
+  // MQO_TRACE: HIP events around every phase of the solve, on its stream
+  bool tracing = false;
+  std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> phases;
+
+  hipEvent_t phase_begin() {
+    hipEvent_t e = nullptr;
+    if (tracing && hipEventCreate(&e) == hipSuccess) (void)hipEventRecord(e, s);
+    return e;
+  }
+  void phase_end(int ph, hipEvent_t e0) {
+    if (!e0) return;
+    hipEvent_t e1 = nullptr;
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return;
+    }
+    (void)hipEventRecord(e1, s);
+    phases.emplace_back(ph, e0, e1);
+  }
 
   int begin_timed(hipEvent_t *e0) {
     HIP_TRY(hipEventCreate(e0));
@@ -434,8 +459,65 @@ struct Solve {
       (void)hipEventDestroy(p.first);
       (void)hipEventDestroy(p.second);
     }
+    for (auto &p : phases) {
+      (void)hipEventDestroy(std::get<1>(p));
+      (void)hipEventDestroy(std::get<2>(p));
+    }
   }
 };
+
+// Phases of a solve reported by MQO_TRACE.
+enum Phase { PH_INIT, PH_RESET, PH_STEPS, PH_LOCAL_SEARCH, PH_EVALUATE, PH_POOL, PH_PAIR_SEARCH, PH_TILE, PH_COUNT };
+const char *const PHASE_NAMES[PH_COUNT] = {"init",     "reset", "steps",       "local_search",
+                                           "evaluate", "pool",  "pair_search", "persistent_rounds"};
+
+// MQO_TRACE unset or "0": off; "1" or "stderr": one JSON line per solve on
+// stderr; anything else: a file the line is appended to.
+const char *trace_target() {
+  const char *t = std::getenv("MQO_TRACE");
+  if (!t || !*t || std::strcmp(t, "0") == 0) return nullptr;
+  return t;
+}
+
+// After the stream is synchronised: per-phase totals of the HIP-event
+// times, one JSON line.
+void write_trace(Solve &S, int plan, int32_t rounds_done, double wall_ms) {
+  const char *target = trace_target();
+  if (!target) return;
+  double ms[PH_COUNT] = {};
+  int64_t cnt[PH_COUNT] = {};
+  for (auto &p : S.phases) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, std::get<1>(p), std::get<2>(p)) == hipSuccess) ms[std::get<0>(p)] += t;
+    ++cnt[std::get<0>(p)];
+  }
+  static const char *const plans[] = {"auto", "plain", "batched", "persistent"};
+  std::string line = "{\"mqo_trace\": \"solve\", \"problem\": \"";
+  line += S.maxcut ? "maxcut" : "mis";
+  char buf[512];
+  snprintf(buf, sizeof(buf),
+           "\", \"plan\": \"%s\", \"graphs\": %d, \"batch\": %d, \"n_total\": %lld, \"nnz_total\": %lld, "
+           "\"rounds_executed\": %d, \"wall_ms\": %.4f, \"phases\": {",
+           plans[plan], S.G, S.B, (long long)S.g->n_total, (long long)S.g->nnz_total, rounds_done, wall_ms);
+  line += buf;
+  bool first = true;
+  for (int i = 0; i < PH_COUNT; ++i) {
+    if (!cnt[i]) continue;
+    snprintf(buf, sizeof(buf), "%s\"%s\": {\"ms\": %.4f, \"count\": %lld}", first ? "" : ", ", PHASE_NAMES[i],
+             ms[i], (long long)cnt[i]);
+    line += buf;
+    first = false;
+  }
+  line += "}}\n";
+  const bool to_stderr = std::strcmp(target, "1") == 0 || std::strcmp(target, "stderr") == 0;
+  FILE *f = to_stderr ? stderr : std::fopen(target, "a");
+  if (!f) return;
+  std::fputs(line.c_str(), f);
+  if (to_stderr)
+    std::fflush(f);
+  else
+    std::fclose(f);
+}
 
 int k_of(const Solve &S, int64_t n) { return (int)std::floor(S.p->rho * (double)n); }
 
@@ -701,6 +783,7 @@ int grid_round(Solve &S, StepLoop &loop, bool use_graph, const GraphView &gv, in
   int64_t *steps_ctr = at<int64_t>(S.ws, S.L.steps) + traj0;
   const bool mom = S.p->momentum != 0.0f;
   const int32_t R = S.p->restart_every;
+  hipEvent_t ph = S.phase_begin();
   if (r > 0 && R > 0 && r % R == 0) {
     // a fresh start of the outer loop (Alg. 1-4): the initialisation rule
     // with start index r / R; incumbents (and the pool) carry over
@@ -717,21 +800,28 @@ int grid_round(Solve &S, StepLoop &loop, bool use_graph, const GraphView &gv, in
   } else if (mom) {
     launch_fill_f32(V + gv.lo * ld, gv.n * ld, 0.0f, S.s);
   }
+  S.phase_end(r > 0 && !(R > 0 && r % R == 0) ? PH_RESET : PH_INIT, ph);
   if (S.p->steps_per_round > 0) {
     hipEvent_t e0;
     TRY(S.begin_timed(&e0));
+    ph = S.phase_begin();
     TRY(run_steps(S, loop, use_graph, gv, X, Xt, mom ? V : nullptr, ncols, ld, colact, steps_ctr, Z, NB, value));
     if (S.p->check_every <= 0) launch_add_i64(steps_ctr, ncols, S.p->steps_per_round, S.s);
+    S.phase_end(PH_STEPS, ph);
     TRY(S.end_timed(e0));
   }
+  ph = S.phase_begin();
   launch_round(S.maxcut, X, Z, gv.lo, gv.n, ncols, ld, S.s);
   if (S.p->local_search == MQO_LS_ONE_FLIP) {
     int64_t it = 0;
     TRY(run_local_search(S, gv, Z, NB, PRIO, F, ncols, ld, traj0, r, &it));
     S.ls_iters += it;
   }
+  S.phase_end(PH_LOCAL_SEARCH, ph);
+  ph = S.phase_begin();
   launch_evaluate(S.maxcut, gv, Z, NB, at<long long>(S.ws, S.L.acc), value, nullptr, nullptr, ncols, ld, S.s);
   launch_accept(Z, Zb, value, best, gv.lo, gv.n, ncols, ld, ldb, r == 0, S.s);
+  S.phase_end(PH_EVALUATE, ph);
   HIP_TRY(hipGetLastError());
   return MQO_OK;
 }
@@ -788,12 +878,14 @@ int solve_batched(Solve &S, int32_t *rounds_done) {
       }
       TRY(grid_round(S, loops[gi], use_graph, gv, r, X, Xt, V, Z, Zb, B, NB, PRIO, F, value + t, best + t, B, B,
                      (uint64_t)t, at<int8_t>(S.ws, S.L.colact) + t, Zp, K, base));
+      hipEvent_t ph = K ? S.phase_begin() : nullptr;
       if (K)
         launch_pool_update(S.maxcut, Z, B, gv.lo, gv.n, gi, B, K, value, at<unsigned long long>(S.ws, S.L.chash),
                            at<int8_t>(S.ws, S.L.ptaken), at<int8_t>(S.ws, S.L.pz[cur]),
                            at<int64_t>(S.ws, S.L.pv[cur]), at<unsigned long long>(S.ws, S.L.ph[cur]),
                            at<int8_t>(S.ws, S.L.pz[nxt]), at<int64_t>(S.ws, S.L.pv[nxt]),
                            at<unsigned long long>(S.ws, S.L.ph[nxt]), at<int32_t>(S.ws, S.L.psrc), S.s);
+      S.phase_end(PH_POOL, ph);
     }
     if (K) offer_pool(S, at<int8_t>(S.ws, S.L.pz[nxt]), at<int64_t>(S.ws, S.L.pv[nxt]));
     searched = false;
@@ -1079,8 +1171,10 @@ int solve_tile(Solve &S, int32_t *rounds_done, TileCfg *used) {
     a.r1 = budget ? r + 1 : S.p->rounds;
     hipEvent_t e0;
     TRY(S.begin_timed(&e0));
+    hipEvent_t ph = S.phase_begin();
     hipError_t e = launch_tile_round(mc, w, a, cfg.threads, S.s);
     if (e != hipSuccess) return fail(MQO_ERR_HIP, "tile launch: %s", hipGetErrorString(e));
+    S.phase_end(PH_TILE, ph);
     TRY(S.end_timed(e0));
     r = a.r1;
     if (!budget && nwg < 1019) {
@@ -1134,13 +1228,18 @@ bool pass_ends(const Solve &S, int32_t r) {
   return (R > 0 && (r + 1) % R == 0) || r == S.p->rounds - 1;
 }
 
-int pair_on(Solve &S, const PairCols &pc, int32_t rnd, int8_t *Z, int64_t *alternations) {
+// T: three int32 scratch arrays of [n_total][pc.ld] for the pair
+// candidates, whose contents are lost (the streaming plans' iterate buffers:
+// the round after a search rewrites them whole, by a reset or a fresh start)
+int pair_on(Solve &S, const PairCols &pc, int32_t rnd, int8_t *Z, float *const (&T)[3], int64_t *alternations) {
   int64_t alt = 0;
+  hipEvent_t ph = S.phase_begin();
   TRY(pair_core(S.maxcut, S.g, pc, S.p->seed, rnd, Z, at<int32_t>(S.ws, S.L.NB), at<uint32_t>(S.ws, S.L.PRIO),
                 at<uint32_t>(S.ws, S.L.tprio), at<int8_t>(S.ws, S.L.F), at<int32_t>(S.ws, S.L.act),
-                at<long long>(S.ws, S.L.acc), at<int64_t>(S.ws, S.L.value), at<int32_t>(S.ws, S.L.X),
-                at<int32_t>(S.ws, S.L.Xt), at<int32_t>(S.ws, S.L.V), at<uint32_t>(S.ws, S.L.tnb), S.s, &S.ls_iters,
-                &alt, nullptr));
+                at<long long>(S.ws, S.L.acc), at<int64_t>(S.ws, S.L.value), reinterpret_cast<int32_t *>(T[0]),
+                reinterpret_cast<int32_t *>(T[1]), reinterpret_cast<int32_t *>(T[2]), at<uint32_t>(S.ws, S.L.tnb),
+                S.s, &S.ls_iters, &alt, nullptr));
+  S.phase_end(PH_PAIR_SEARCH, ph);
   *alternations += alt;
   return MQO_OK;
 }
@@ -1156,7 +1255,8 @@ int search_incumbents(Solve &S, int32_t rnd, int64_t *alternations) {
   int64_t *value = at<int64_t>(S.ws, S.L.value), *best = S.best;
   const int32_t B = S.B;
   HIP_TRY(hipMemcpyAsync(Z, Zb, (size_t)S.g->n_total * B, hipMemcpyDeviceToDevice, S.s));
-  TRY(pair_on(S, all_cols(S.g, B), rnd, Z, alternations));
+  float *const T[3] = {at<float>(S.ws, S.L.X), at<float>(S.ws, S.L.Xt), at<float>(S.ws, S.L.V)};
+  TRY(pair_on(S, all_cols(S.g, B), rnd, Z, T, alternations));
   for (int32_t gi = 0; gi < S.G; ++gi) {
     const GraphView gv = view_of(S.g, gi, S.max_deg);
     const int64_t t = (int64_t)gi * B;
@@ -1170,13 +1270,15 @@ int search_incumbents(Solve &S, int32_t rnd, int64_t *alternations) {
 
 // The same for the one trajectory t = gi B + b of the plain plan (its
 // incumbent is column b of Zb); column 0 of the Z scratch (ld 1) holds the
-// searched copy.
+// searched copy.  The pair candidates go to the plan's one-trajectory
+// vectors: the [n][B] buffer holds every trajectory's start.
 int search_one(Solve &S, const GraphView &gv, int32_t gi, int32_t b, int32_t rnd, int64_t *alternations) {
   int8_t *Z = at<int8_t>(S.ws, S.L.Z);
   int64_t *value = at<int64_t>(S.ws, S.L.value);
   const int64_t t = (int64_t)gi * S.B + b;
   launch_strided_copy_i8(S.Zb, S.B, b, Z, 1, 0, gv.lo, gv.n, S.s);
-  TRY(pair_on(S, PairCols{gv, gi, gi + 1, S.B, b, 1, 1}, rnd, Z, alternations));
+  float *const T[3] = {at<float>(S.ws, S.L.pX), at<float>(S.ws, S.L.pXt), at<float>(S.ws, S.L.pV)};
+  TRY(pair_on(S, PairCols{gv, gi, gi + 1, S.B, b, 1, 1}, rnd, Z, T, alternations));
   launch_evaluate(S.maxcut, gv, Z, at<int32_t>(S.ws, S.L.NB), at<long long>(S.ws, S.L.acc), value + t, nullptr,
                   nullptr, 1, 1, S.s);
   launch_accept(Z, S.Zb + b, value + t, S.best + t, gv.lo, gv.n, 1, 1, S.B, false, S.s);
@@ -1207,7 +1309,8 @@ int search_pool_pass(Solve &S, const int8_t *PZ, const int64_t *PV, int32_t rnd,
     HIP_TRY(hipMemcpyAsync(Z, PZ, (size_t)S.g->n_total * K, hipMemcpyDeviceToDevice, S.s));
   else
     HIP_TRY(hipMemcpyAsync(Z, at<int8_t>(S.ws, S.L.solz), (size_t)S.g->n_total, hipMemcpyDeviceToDevice, S.s));
-  TRY(pair_on(S, PairCols{whole_view(S.g), 0, S.G, K, 0, ncols, ncols}, rnd, Z, alternations));
+  float *const T[3] = {at<float>(S.ws, S.L.X), at<float>(S.ws, S.L.Xt), at<float>(S.ws, S.L.V)};
+  TRY(pair_on(S, PairCols{whole_view(S.g), 0, S.G, K, 0, ncols, ncols}, rnd, Z, T, alternations));
   for (int32_t gi = 0; gi < S.G; ++gi) {
     const GraphView gv = view_of(S.g, gi, S.max_deg);
     launch_evaluate(S.maxcut, gv, Z, at<int32_t>(S.ws, S.L.NB), at<long long>(S.ws, S.L.acc),
@@ -1237,11 +1340,14 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
   std::lock_guard<std::mutex> host_lock(res().host_mu);
   Resources &R = res();
   hipStream_t s = R.stream;
+  drop_stale_error();
   // the internal stream waits for the work the caller has queued on `stream`
   HIP_TRY(hipEventRecord(R.input_ready, reinterpret_cast<hipStream_t>(stream)));
   HIP_TRY(hipStreamWaitEvent(s, R.input_ready, 0));
 
+  const double wall0 = now_s();
   Solve S;
+  S.tracing = trace_target() != nullptr;
   S.g = g;
   S.p = p;
   S.obj = obj;
@@ -1328,6 +1434,7 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
   r->step_kernel_ms = S.timed_ms();
   r->step_kernel_launches = (int64_t)S.timed.size();
   r->final_search_alternations = S.search_alt;
+  if (S.tracing) write_trace(S, plan, rounds_done, 1e3 * (now_s() - wall0));
   return MQO_OK;
 }
 
@@ -1433,6 +1540,7 @@ int mqo_objective_grad(const mqo_graph *g, mqo_objective obj, float param, const
   if (f_out && (!ws || ws_bytes < mqo_objective_workspace_size(g, B)))
     return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", mqo_objective_workspace_size(g, B));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  drop_stale_error();
   const bool mc = obj != MQO_OBJ_MIS_H;
   const int form = (int)obj;
   const StepCfg cfg = default_step_cfg(B, B);
@@ -1466,6 +1574,7 @@ int mqo_pga_unrolled_forward(const mqo_graph *g, mqo_objective obj, float param,
   if (!ws || ws_bytes < mqo_unrolled_workspace_size(g, B, ckpt_every))
     return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", mqo_unrolled_workspace_size(g, B, ckpt_every));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  drop_stale_error();
   const bool mc = obj != MQO_OBJ_MIS_H;
   const int form = (int)obj;
   const StepCfg cfg = default_step_cfg(B, B);
@@ -1504,6 +1613,7 @@ int mqo_pga_unrolled_backward(const mqo_graph *g, mqo_objective obj, float param
   if (!ws || ws_bytes < mqo_unrolled_workspace_size(g, B, ckpt_every))
     return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", mqo_unrolled_workspace_size(g, B, ckpt_every));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  drop_stale_error();
   const bool mc = obj != MQO_OBJ_MIS_H;
   const int form = (int)obj;
   const StepCfg cfg = default_step_cfg(B, B);
@@ -1553,6 +1663,7 @@ int mqo_init_iterate(const mqo_graph *g, mqo_objective obj, const mqo_params *p,
   if (p->init_mode == MQO_INIT_DEGREE && (!ws || ws_bytes < MQO_INIT_WORKSPACE_BYTES))
     return fail(MQO_ERR_WORKSPACE, "the degree initialisation needs %d bytes of workspace", MQO_INIT_WORKSPACE_BYTES);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  drop_stale_error();
   const bool mc = obj != MQO_OBJ_MIS_H;
   const int form = (int)obj;
   const int32_t B = p->batch;
@@ -1575,6 +1686,7 @@ int mqo_pga_steps(const mqo_graph *g, mqo_objective obj, const mqo_params *p, fl
   if (!X || !tmp || nsteps < 0) return fail(MQO_ERR_INVALID_ARG, "X and tmp are required, nsteps >= 0");
   if (p->momentum != 0.0f && !V) return fail(MQO_ERR_INVALID_ARG, "V is required when momentum != 0");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  drop_stale_error();
   const bool mc = obj != MQO_OBJ_MIS_H;
   const int form = (int)obj;
   const int32_t B = p->batch;
@@ -1600,6 +1712,7 @@ int mqo_round_evaluate(const mqo_graph *g, mqo_objective obj, const float *X, in
   const Layout L = make_layout(g, B);
   if (!ws || ws_bytes < L.total) return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", L.total);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  drop_stale_error();
   const bool mc = obj != MQO_OBJ_MIS_H;
   const int form = (int)obj;
   for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
@@ -1622,6 +1735,7 @@ int mqo_local_search(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t 
   TRY(ensure_resources());
   std::lock_guard<std::mutex> host_lock(res().host_mu);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  drop_stale_error();
   const bool mc = obj != MQO_OBJ_MIS_H;
   // every graph of the batch at once: the search only follows edges, which
   // stay inside each graph, so a column that is done stays unchanged
@@ -1651,6 +1765,7 @@ int mqo_pair_search(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t s
   TRY(ensure_resources());
   std::lock_guard<std::mutex> host_lock(res().host_mu);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  drop_stale_error();
   return pair_core(mc, g, all_cols(g, B), seed, round, Z, at<int32_t>(ws, L.NB), at<uint32_t>(ws, L.PRIO),
                    at<uint32_t>(ws, L.tprio), at<int8_t>(ws, L.F), at<int32_t>(ws, L.act), at<long long>(ws, L.acc),
                    at<int64_t>(ws, L.value), at<int32_t>(ws, L.X), at<int32_t>(ws, L.Xt), at<int32_t>(ws, L.V),
@@ -1667,6 +1782,7 @@ int mqo_reset(const mqo_graph *g, mqo_objective obj, int32_t B, uint64_t seed, i
   const Layout L = make_layout(g, B);
   if (!ws || ws_bytes < L.total) return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", L.total);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  drop_stale_error();
   const bool mc = obj != MQO_OBJ_MIS_H;
   const int form = (int)obj;
   for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
@@ -1690,6 +1806,7 @@ int mqo_toy_reset(uint64_t seed, int32_t n, float alpha, float beta, int32_t ste
   if (mode != MQO_TOY_GLOBAL_RESET && mode != MQO_TOY_FULL_RESTART) return fail(MQO_ERR_INVALID_ARG, "bad mode");
   if (trials == 0) return MQO_OK;
   if (!first_hit) return fail(MQO_ERR_INVALID_ARG, "first_hit is NULL");
+  drop_stale_error();
   launch_toy(mode, seed, n, alpha, beta, steps, attempts, trials, first_hit,
              mode == MQO_TOY_GLOBAL_RESET ? x_out : nullptr, reinterpret_cast<hipStream_t>(stream));
   HIP_TRY(hipGetLastError());
@@ -1731,6 +1848,7 @@ int mqo_validate_graph(const mqo_graph *g, void *stream) {
   TRY(ensure_resources());
   std::lock_guard<std::mutex> host_lock(res().host_mu);
   hipStream_t s = res().stream;
+  drop_stale_error();
   if (stream) HIP_TRY(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
   void *buf = nullptr;
   const size_t bytes = align_up((g->num_graphs + 1) * sizeof(int64_t)) + 256;

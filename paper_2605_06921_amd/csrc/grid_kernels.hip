@@ -30,6 +30,26 @@ static inline dim3 grid_rows(int64_t nrows, int ncols, int lanes_log2, int vec, 
   return dim3((unsigned)(gx > 0 ? gx : 1), (unsigned)(gy > 0 ? gy : 1), 1);
 }
 
+// Workgroups are handed to the 8 XCDs (each with its own L2) round-robin in
+// launch order, linear id x + y gridDim.x.  The sparse-product kernels
+// renumber them so that each XCD runs one contiguous range of the (row
+// block, column slice) space: rows close in the vertex order, which gather
+// many of the same rows of X on graphs with locality (grids, tori, banded
+// orders), then share one L2 instead of fetching those rows once per XCD.
+// A bijection of the launch, so every result is unchanged.
+struct Blk {
+  int64_t x;
+  int32_t y;
+};
+
+__device__ __forceinline__ Blk xcd_blk() {
+  const int64_t gx = gridDim.x, nb = gx * gridDim.y;
+  const int64_t b = blockIdx.x + (int64_t)blockIdx.y * gx;
+  const int64_t q = nb >> 3, r = nb & 7, xcd = b & 7, j = b >> 3;
+  const int64_t l = xcd * q + (xcd < r ? xcd : r) + j;
+  return Blk{l % gx, (int32_t)(l / gx)};
+}
+
 // ---------------------------------------------------------------------------
 // initialisation
 // ---------------------------------------------------------------------------
@@ -278,11 +298,11 @@ struct HubItem {
   int32_t cw;  // columns in the slice
 };
 
-__device__ __forceinline__ HubItem hub_item(const GraphView &g, int32_t ncols) {
+__device__ __forceinline__ HubItem hub_item(const GraphView &g, int32_t ncols, int64_t bx) {
   HubItem it;
   const int32_t ns = hub_slices(ncols);
-  it.h = (int32_t)(blockIdx.x / ns);
-  it.c0 = (int32_t)(blockIdx.x % ns) * HUB_SW;
+  it.h = (int32_t)(bx / ns);
+  it.c0 = (int32_t)(bx % ns) * HUB_SW;
   it.cw = min(HUB_SW, ncols - it.c0);
   it.v = g.hubs[it.h];
   return it;
@@ -346,13 +366,13 @@ __device__ __forceinline__ bool is_hub_row(const GraphView &g, int64_t v) {
 // launched for near-regular graphs only: two rows of equal degree go in
 // lockstep, otherwise one after the other.
 template <int VEC, bool WEIGHTED, int ROWS>
-__device__ __forceinline__ void group_gather(const GraphView &g, const float *__restrict__ X, int64_t bx,
+__device__ __forceinline__ void group_gather(const GraphView &g, const float *__restrict__ X, int64_t bx, int32_t by,
                                              int32_t ncols, int32_t ld, int32_t lanes_log2, int64_t (&v)[ROWS],
                                              bool (&own)[ROWS], int32_t &col, float (&acc)[ROWS][VEC]) {
   const int32_t lanes = 1 << lanes_log2;
   const int32_t rpb = blockDim.x >> lanes_log2;
   const int64_t r0 = bx * ROWS * rpb + (threadIdx.x >> lanes_log2);
-  col = (int32_t)(blockIdx.y * lanes + (threadIdx.x & (lanes - 1))) * VEC;
+  col = (int32_t)(by * lanes + (threadIdx.x & (lanes - 1))) * VEC;
   const bool colok = col < ncols;
 #pragma unroll
   for (int k = 0; k < ROWS; ++k) {
@@ -408,9 +428,10 @@ __global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__re
                                                   int32_t lanes_log2, float alpha, float mu, float param,
                                                   const int8_t *__restrict__ colact) {
   const int64_t nhb = hub_blocks(g, ncols);
-  if (blockIdx.x < nhb) {
-    if (blockIdx.y != 0) return;
-    const HubItem it = hub_item(g, ncols);
+  const Blk blk = xcd_blk();
+  if (blk.x < nhb) {
+    if (blk.y != 0) return;
+    const HubItem it = hub_item(g, ncols, blk.x);
     const float acc = hub_gather<WEIGHTED>(g, X, it, ld);
     if ((int32_t)threadIdx.x < it.cw) {
       const int64_t e = it.v * ld + it.c0 + threadIdx.x;
@@ -426,7 +447,7 @@ __global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__re
   bool own[ROWS];
   int32_t col;
   float acc[ROWS][VEC];
-  group_gather<VEC, WEIGHTED, ROWS>(g, X, blockIdx.x - nhb, ncols, ld, lanes_log2, v, own, col, acc);
+  group_gather<VEC, WEIGHTED, ROWS>(g, X, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc);
   if (col >= ncols) return;
 #pragma unroll
   for (int k = 0; k < ROWS; ++k) {
@@ -1806,9 +1827,10 @@ __global__ __launch_bounds__(256) void k_objective_grad(GraphView g, const float
                                                         int32_t lanes_log2, float param) {
   const int64_t nhb = hub_blocks(g, ncols);
   const int64_t nrb = gridDim.x - nhb;  // row workgroups
-  if (blockIdx.x < nhb) {
-    if (blockIdx.y != 0) return;
-    const HubItem it = hub_item(g, ncols);
+  const Blk blk = xcd_blk();
+  if (blk.x < nhb) {
+    if (blk.y != 0) return;
+    const HubItem it = hub_item(g, ncols, blk.x);
     const float acc = hub_gather<WEIGHTED>(g, X, it, ld);
     if ((int32_t)threadIdx.x < it.cw) {
       const int32_t c = it.c0 + threadIdx.x;
@@ -1826,7 +1848,7 @@ __global__ __launch_bounds__(256) void k_objective_grad(GraphView g, const float
   bool own[ROWS];
   int32_t col;
   float acc[ROWS][VEC];
-  group_gather<VEC, WEIGHTED, ROWS>(g, X, blockIdx.x - nhb, ncols, ld, lanes_log2, v, own, col, acc);
+  group_gather<VEC, WEIGHTED, ROWS>(g, X, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc);
   double fv[VEC];
 #pragma unroll
   for (int i = 0; i < VEC; ++i) fv[i] = 0.0;
@@ -1846,7 +1868,7 @@ __global__ __launch_bounds__(256) void k_objective_grad(GraphView g, const float
     }
     if (grad) store_vec<VEC>(grad + v[k] * ld + col, gr);
   }
-  if (part) block_column_partials<VEC>(fv, any, col, ncols, lanes_log2, part, blockIdx.x - nhb);
+  if (part) block_column_partials<VEC>(fv, any, col, ncols, lanes_log2, part, blk.x - nhb);
 }
 
 // Column sums of per-block partials part[nblk][ncols] in a fixed order.
@@ -1904,9 +1926,10 @@ __global__ __launch_bounds__(256) void k_adj_mu(GraphView g, const float *__rest
                                                 int32_t lanes_log2, float alpha, float param) {
   const int64_t nhb = hub_blocks(g, ncols);
   const int64_t nrb = gridDim.x - nhb;
-  if (blockIdx.x < nhb) {
-    if (blockIdx.y != 0) return;
-    const HubItem it = hub_item(g, ncols);
+  const Blk blk = xcd_blk();
+  if (blk.x < nhb) {
+    if (blk.y != 0) return;
+    const HubItem it = hub_item(g, ncols, blk.x);
     const float acc = hub_gather<WEIGHTED>(g, Xk, it, ld);
     if ((int32_t)threadIdx.x < it.cw) {
       const int32_t c = it.c0 + threadIdx.x;
@@ -1924,7 +1947,7 @@ __global__ __launch_bounds__(256) void k_adj_mu(GraphView g, const float *__rest
   bool own[ROWS];
   int32_t col;
   float acc[ROWS][VEC];
-  group_gather<VEC, WEIGHTED, ROWS>(g, Xk, blockIdx.x - nhb, ncols, ld, lanes_log2, v, own, col, acc);
+  group_gather<VEC, WEIGHTED, ROWS>(g, Xk, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc);
   double dv[VEC];
 #pragma unroll
   for (int i = 0; i < VEC; ++i) dv[i] = 0.0;
@@ -1945,7 +1968,7 @@ __global__ __launch_bounds__(256) void k_adj_mu(GraphView g, const float *__rest
     }
     store_vec<VEC>(mu_out + v[k] * ld + col, mu);
   }
-  block_column_partials<VEC>(dv, any, col, ncols, lanes_log2, part, blockIdx.x - nhb);
+  block_column_partials<VEC>(dv, any, col, ncols, lanes_log2, part, blk.x - nhb);
 }
 
 // adjoint, part 2: lam_k = mu + alpha (H mu), H the objective's Hessian:
@@ -1977,9 +2000,10 @@ __global__ __launch_bounds__(256) void k_adj_lambda(GraphView g, const float *__
                                                     int32_t ncols, int32_t ld, int32_t lanes_log2, float alpha,
                                                     float param) {
   const int64_t nhb = hub_blocks(g, ncols);
-  if (blockIdx.x < nhb) {
-    if (blockIdx.y != 0) return;
-    const HubItem it = hub_item(g, ncols);
+  const Blk blk = xcd_blk();
+  if (blk.x < nhb) {
+    if (blk.y != 0) return;
+    const HubItem it = hub_item(g, ncols, blk.x);
     const float acc = hub_gather<WEIGHTED>(g, mu, it, ld);
     if ((int32_t)threadIdx.x < it.cw) {
       const int64_t e = it.v * ld + it.c0 + threadIdx.x;
@@ -1992,7 +2016,7 @@ __global__ __launch_bounds__(256) void k_adj_lambda(GraphView g, const float *__
   bool own[ROWS];
   int32_t col;
   float acc[ROWS][VEC];
-  group_gather<VEC, WEIGHTED, ROWS>(g, mu, blockIdx.x - nhb, ncols, ld, lanes_log2, v, own, col, acc);
+  group_gather<VEC, WEIGHTED, ROWS>(g, mu, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc);
   if (col >= ncols) return;
 #pragma unroll
   for (int k = 0; k < ROWS; ++k) {

@@ -334,6 +334,31 @@ def test_plain_trajectory_subset(mqo, kind):
     assert np.array_equal(tv[ids], ref["traj_best_value"][ids])
 
 
+def test_trace_reports_every_phase(mqo, tmp_path, monkeypatch):
+    """MQO_TRACE=<file>: one JSON line per solve with HIP-event totals per
+    phase; unset: nothing is written."""
+    import json
+    kind, g = CASES["er_batch"]
+    dg = mqo.DeviceGraph(g, DEV)
+    path = tmp_path / "trace.jsonl"
+    monkeypatch.setenv("MQO_TRACE", str(path))
+    kw = dict(batch=8, steps_per_round=20, rounds=3, alpha=0.05, rho=0.15, seed=3)
+    mqo.solve(kind, dg, plan="batched", final_search=True, **kw)
+    mqo.solve(kind, dg, plan="persistent", **kw)
+    monkeypatch.setenv("MQO_TRACE", "0")
+    mqo.solve(kind, dg, plan="batched", **kw)
+    lines = [json.loads(x) for x in path.read_text().splitlines()]
+    assert len(lines) == 2
+    b, t = lines
+    assert b["plan"] == "batched" and t["plan"] == "persistent" and b["rounds_executed"] == 3
+    G = g.num_graphs
+    assert b["phases"]["steps"]["count"] == 3 * G and b["phases"]["reset"]["count"] == 2 * G
+    assert b["phases"]["local_search"]["count"] == 3 * G and b["phases"]["evaluate"]["count"] == 3 * G
+    assert b["phases"]["pair_search"]["count"] == 1
+    assert all(v["ms"] >= 0 for v in b["phases"].values())
+    assert t["phases"]["persistent_rounds"]["count"] >= 1 and "steps" not in t["phases"]
+
+
 def test_two_streams_at_once(mqo):
     """Degree initialisation and objective + gradient queued on two streams
     at the same time, each with its default workspace (one per stream):

@@ -211,7 +211,9 @@ def test_million_vertex_full_round_and_next_reset(mqo, name):
     dg = mqo.DeviceGraph(g, DEV)
     out = _solve_gpu(mqo, wl, g, rounds=1)
     c = 21
-    vals, zb = solver.solve_graph(wl.problem, g, _params(wl), 0, cols=[c])
+    p = _params(wl)
+    p.rounds = 1
+    vals, zb = solver.solve_graph(wl.problem, g, p, 0, cols=[c])
     tv = out["traj_best_value"].cpu().numpy()
     assert tv[c] == vals[0]
     Zb = out["traj_best_x"]

@@ -251,3 +251,26 @@ def test_evaluate_mis_against_edges():
     u, v, _ = g.edges()
     assert np.array_equal(conf, ((Z[u] == 1) & (Z[v] == 1)).sum(0))
     assert np.array_equal(size, Z.sum(0))
+
+
+@pytest.mark.parametrize("which", ["er", "torus_pm1", "star", "batch"])
+def test_float32_neighbour_sums_follow_csr_order(which):
+    """The library route of the float32 neighbour sums equals the
+    position-by-position definition bit for bit, on values whose sums depend
+    on the order of addition (a reversed order changes some of them)."""
+    from oracle import pga
+    g = {"er": graphs.erdos_renyi(800, 0.03, 61), "torus_pm1": graphs.torus_pm1(40, 62),
+         "star": graphs.star(500),
+         "batch": graphs.concat([graphs.erdos_renyi(97, 0.08, 63), graphs.empty(3), graphs.star(40)])}[which]
+    rng = np.random.default_rng(64)
+    X = (rng.uniform(-1, 1, (g.n, 6)) * 10.0 ** rng.integers(-6, 4, (g.n, 6))).astype(np.float32)
+    a = pga.neighbour_sum32(g, X)
+    assert a.dtype == np.float32
+    assert np.array_equal(a, pga.neighbour_sum32_positions(g, X))
+    # the order matters on these values: summing each row backwards differs somewhere
+    rev = np.zeros_like(X)
+    for v in range(g.n):
+        for j in range(g.row_ptr[v + 1] - 1, g.row_ptr[v] - 1, -1):
+            w = np.float32(1.0) if g.weight is None else np.float32(g.weight[j])
+            rev[v] = rev[v] + w * X[g.col_idx[j]]
+    assert not np.array_equal(rev, a)
