@@ -269,6 +269,23 @@ int mqo_objective_grad(const mqo_graph *g, mqo_objective obj, float param,
                        double *f_out, float *grad_out,
                        void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * as mqo_objective_grad, with the float64 partial sums of f_out in the
+ * library's own device scratch of MQO_STATIC_SCRATCH_BYTES bytes instead of
+ * a caller workspace.  Allocates nothing, neither on the device nor pinned.
+ * When f_out is requested and mqo_objective_workspace_size(g, B) exceeds
+ * MQO_STATIC_SCRATCH_BYTES it returns MQO_ERR_WORKSPACE before anything is
+ * enqueued.  Each GPU holds one copy of the scratch until the process ends
+ * and every call on that GPU uses it: calls that overlap on one GPU (on
+ * different streams, or from different threads) race and must be
+ * serialised by the caller; calls in one stream order are safe.  The
+ * partial sums are written whole by every call, nothing is carried over. */
+#define MQO_STATIC_SCRATCH_BYTES (16u << 20)
+int mqo_objective_grad_static(const mqo_graph *g, mqo_objective obj, float param,
+                              const float *X, int32_t B, const float *scale,
+                              double *f_out, float *grad_out, void *stream);
+
 /* K unrolled PGA steps x_{k+1} = Pi(x_k + alpha grad(x_k)) (momentum 0).
  * Forward stores x_{j*ckpt_every} in ckpt[j] ([K/ckpt_every][n_total*B])
  * and x_K in XK.  K must be a multiple of ckpt_every.  Backward takes

@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmqo.so")
-SOURCES = ["api.cpp", "grid_kernels.hip", "tile_kernel.hip", "toy_kernel.hip"]
+SOURCES = ["api.cpp", "grid_kernels.hip", "tile_kernel.hip", "toy_kernel.hip", "static_scratch.hip"]
 ARCH = os.environ.get("MQO_OFFLOAD_ARCH", "gfx950")
 
 

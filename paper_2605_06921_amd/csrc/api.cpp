@@ -1471,6 +1471,26 @@ size_t partial_count(const mqo_graph *g, int32_t B, int32_t copies = 1) {
   return (size_t)(nblk + reduce_rows(nblk)) * B;
 }
 
+// objective and gradient of every graph after validation; part: the float64
+// partial rows (partial_count doubles), needed when f_out is requested
+int objective_grad_run(const mqo_graph *g, mqo_objective obj, float param, const float *X, int32_t B,
+                       const float *scale, double *f_out, float *grad_out, void *part_ws, void *stream) {
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  drop_stale_error();
+  const bool mc = obj != MQO_OBJ_MIS_H;
+  const int form = (int)obj;
+  const StepCfg cfg = default_step_cfg(B, B);
+  for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
+    const GraphView gv = view_of(g, gi);
+    const float *sc = scale ? scale + (int64_t)gi * B : nullptr;
+    double *part = f_out ? reinterpret_cast<double *>(part_ws) : nullptr;
+    launch_objective_grad(form, gv, X, sc, grad_out, part, B, B, cfg, param, s);
+    if (f_out) launch_reduce_partials(part, spmm_row_blocks(gv, cfg, form) + gv.nhub, B, f_out + (int64_t)gi * B, false, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return MQO_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1539,22 +1559,24 @@ int mqo_objective_grad(const mqo_graph *g, mqo_objective obj, float param, const
   if (!X) return fail(MQO_ERR_INVALID_ARG, "X is NULL");
   if (f_out && (!ws || ws_bytes < mqo_objective_workspace_size(g, B)))
     return fail(MQO_ERR_WORKSPACE, "workspace needs %zu bytes", mqo_objective_workspace_size(g, B));
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  drop_stale_error();
-  const bool mc = obj != MQO_OBJ_MIS_H;
-  const int form = (int)obj;
-  const StepCfg cfg = default_step_cfg(B, B);
-  for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
-    const GraphView gv = view_of(g, gi);
-    const float *sc = scale ? scale + (int64_t)gi * B : nullptr;
-    double *part = f_out ? reinterpret_cast<double *>(ws) : nullptr;
-    launch_objective_grad(form, gv, X, sc, grad_out, part, B, B, cfg, param, s);
-    if (f_out) launch_reduce_partials(part, spmm_row_blocks(gv, cfg, form) + gv.nhub, B, f_out + (int64_t)gi * B, false, s);
-  }
-  HIP_TRY(hipGetLastError());
-  return MQO_OK;
+  return objective_grad_run(g, obj, param, X, B, scale, f_out, grad_out, ws, stream);
 }
 
+int mqo_objective_grad_static(const mqo_graph *g, mqo_objective obj, float param, const float *X, int32_t B,
+                              const float *scale, double *f_out, float *grad_out, void *stream) {
+  TRY(check_async(g, obj, B));
+  TRY(check_param(obj, param));
+  if (!X) return fail(MQO_ERR_INVALID_ARG, "X is NULL");
+  void *ws = nullptr;
+  if (f_out) {
+    const size_t need = mqo_objective_workspace_size(g, B);
+    if (need > MQO_STATIC_SCRATCH_BYTES)
+      return fail(MQO_ERR_WORKSPACE, "the partial sums need %zu bytes, above the static scratch of %u bytes", need,
+                  (unsigned)MQO_STATIC_SCRATCH_BYTES);
+    HIP_TRY(static_scratch_address(&ws));
+  }
+  return objective_grad_run(g, obj, param, X, B, scale, f_out, grad_out, ws, stream);
+}
 size_t mqo_unrolled_workspace_size(const mqo_graph *g, int32_t B, int32_t ckpt_every) {
   if (check_graph_args(g, false) != MQO_OK || B < 1 || ckpt_every < 1) return 0;
   const size_t nb = (size_t)g->n_total * B * sizeof(float);

@@ -125,6 +125,10 @@ void launch_adjoint_step(int form, const GraphView &g, const float *Xk, const fl
                          float *lam, double *part, int32_t ncols, int32_t ld, StepCfg cfg, float alpha, float param,
                          hipStream_t s);
 
+// address on the current device of the library's own MQO_STATIC_SCRATCH_BYTES
+// of device scratch (looked up once per device)
+hipError_t static_scratch_address(void **out);
+
 // ---------------------------------------------------------------------------
 // persistent tile plan: one workgroup owns (graph, T trajectories) with the
 // iterate tile resident in LDS for a whole round

@@ -83,6 +83,7 @@ def _load():
         "mqo_solve_maxcut": (i32, [G, P, vp, R, vp, sz, vp]),
         "mqo_objective_workspace_size": (sz, [G, i32]),
         "mqo_objective_grad": (i32, [G, i32, f32, vp, i32, vp, vp, vp, vp, sz, vp]),
+        "mqo_objective_grad_static": (i32, [G, i32, f32, vp, i32, vp, vp, vp, vp]),
         "mqo_unrolled_workspace_size": (sz, [G, i32, i32]),
         "mqo_pga_unrolled_forward": (i32, [G, i32, f32, f32, i32, i32, vp, vp, vp, i32, vp, sz, vp]),
         "mqo_pga_unrolled_backward": (i32, [G, i32, f32, f32, i32, i32, vp, vp, vp, vp, vp, i32, vp, sz, vp]),
@@ -448,6 +449,22 @@ def objective_grad(kind, dg: DeviceGraph, X: torch.Tensor, param: float, scale: 
     _check(_lib.mqo_objective_grad(dg.struct, _KIND[kind], float(param), _ptr(X.contiguous()), B, _ptr(scale),
                                    _ptr(f), _ptr(grad), None if ws is None else ctypes.c_void_p(ws.data_ptr()),
                                    nbytes if want_f else 0, _stream(dg.device)), "mqo_objective_grad")
+    return f, grad
+
+
+STATIC_SCRATCH_BYTES = 16 << 20  # MQO_STATIC_SCRATCH_BYTES
+
+
+def objective_grad_static(kind, dg: DeviceGraph, X: torch.Tensor, param: float, f: Optional[torch.Tensor] = None,
+                          grad: Optional[torch.Tensor] = None, scale: Optional[torch.Tensor] = None):
+    """mqo_objective_grad_static: the objective into ``f`` ([G*B] float64)
+    and the gradient into ``grad`` (like X), either may be None; both are
+    the caller's.  The library allocates nothing: its partial sums go to its
+    own device scratch, shared by every call on the GPU (calls that overlap
+    on one GPU race)."""
+    B = X.shape[1]
+    _check(_lib.mqo_objective_grad_static(dg.struct, _KIND[kind], float(param), _ptr(X), B, _ptr(scale), _ptr(f),
+                                          _ptr(grad), _stream(dg.device)), "mqo_objective_grad_static")
     return f, grad
 
 

@@ -205,3 +205,19 @@ def test_trajectory_subset_checked_on_host(m):
     p = m.make_params(batch=4, plan="plain")
     p.traj_count = 2
     assert L.mqo_solve_mis(ctypes.byref(s), ctypes.byref(p), None, ctypes.byref(r), None, 0, None) == -1
+
+
+def test_static_scratch_variant_checks_its_limit_on_host(m):
+    """The no-allocation objective entry point refuses, before anything is
+    enqueued, a batch whose partial sums exceed its static scratch."""
+    L = m.lib()
+    n = 200_000
+    s, off = _struct(m, n=n)
+    B = 256
+    need = L.mqo_objective_workspace_size(ctypes.byref(s), B)
+    assert need > m.STATIC_SCRATCH_BYTES
+    X = ctypes.c_void_p(0x1000)
+    assert L.mqo_objective_grad_static(ctypes.byref(s), 0, 2.0, X, B, None, ctypes.c_void_p(0x1000), None,
+                                       None) == -3
+    assert "static scratch" in m.last_error()
+    assert L.mqo_objective_grad_static(ctypes.byref(s), 0, 0.5, X, B, None, None, None, None) == -1  # gamma <= 1
