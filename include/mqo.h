@@ -199,6 +199,11 @@ typedef struct {
                               traj_best_x zeros.  Other plans:
                               MQO_ERR_UNSUPPORTED                          */
   const int64_t *traj_ids; /* (host) [traj_count], read during the call     */
+  int32_t step_vec;        /* streaming step kernel (batched plan): columns per
+                              lane, 1, 2 or 4, 0 = autotune                 */
+  int32_t step_lanes;      /* streaming step kernel: lanes per row, a power of
+                              two <= 64, 0 = autotune (every shape computes
+                              the same sums in the same order)              */
 } mqo_params;
 
 /* Outputs of a solve.  Device arrays are written; host fields are set. */
@@ -233,6 +238,9 @@ typedef struct {
                                   NULL; empty slots are zeros               */
   int64_t *pool_value;         /* [G*K] pool values, INT64_MIN = empty slot,
                                   or NULL                                   */
+  int32_t step_vec_used;       /* (host) streaming plans: columns per lane of
+                                  the step kernel (0 on the persistent plan) */
+  int32_t step_lanes_used;     /* (host) streaming plans: lanes per row       */
 } mqo_result;
 
 void mqo_params_default(mqo_params *p);
@@ -415,7 +423,26 @@ int mqo_validate_graph(const mqo_graph *g, void *stream);
 const char *mqo_status_string(int status);
 const char *mqo_last_error(void);
 int mqo_version(void);
+/* Forgets every autotuner choice held in memory (the file is not touched). */
 void mqo_clear_caches(void);
+
+/* The autotuner (the batch form of the step-size / batch choice of Alg. 3:
+ * the persistent plan's tile shape, the streaming step kernel's columns per
+ * lane and lanes per row, and the plan chosen for MQO_PLAN_AUTO) times the
+ * candidate launch shapes of a shape key once and keeps the fastest.  Keys
+ * hold the kind of choice, the GPU (architecture and compute units), the
+ * problem and objective, the graph size range, its mean degree and the
+ * batch.  Choices never change results, only speed.  The cache lives in
+ * memory; with MQO_TUNE_CACHE=<path> in the environment the file's entries
+ * are read at the first use and every new choice is appended to it.  The
+ * file is text, one "key<TAB>value" per line ('#' lines are comments).
+ * Host only: no GPU is needed for these three calls.
+ * load: merges the file's entries (MQO_ERR_INVALID_ARG and nothing merged on
+ * a malformed line or an unreadable file); save: writes every entry;
+ * size: the number of entries held. */
+int mqo_tune_cache_load(const char *path);
+int mqo_tune_cache_save(const char *path);
+int64_t mqo_tune_cache_size(void);
 
 #ifdef __cplusplus
 }

@@ -73,7 +73,11 @@ struct Resources {
   hipEvent_t input_ready = nullptr;  // caller's stream -> internal stream
   int device = -1;
   int lds_limit = 0;
-  std::map<std::string, TileCfg> tile_tuning;  // shape key -> tuned tile shape
+  std::string gpu;  // architecture and compute-unit count, part of every tuning key
+  // autotuner cache: shape key -> chosen launch shape (text), mirrored to the
+  // MQO_TUNE_CACHE file when that is set
+  std::map<std::string, std::string> tune;
+  bool tune_env_loaded = false;
 };
 
 Resources &res() {
@@ -102,8 +106,83 @@ int ensure_resources() {
   int lds = 0;
   HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   r.lds_limit = lds;
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  std::string arch(prop.gcnArchName);
+  arch = arch.substr(0, arch.find(':'));
+  r.gpu = arch + "x" + std::to_string(prop.multiProcessorCount);
   r.device = dev;
   return MQO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner cache.  One entry per line of the text file: key, a tab, value.
+// Keys start with the kind of choice (tile, step, plan) and hold the shape
+// they were tuned on (graph size range, mean degree, batch, problem, GPU);
+// values are the launch shape chosen and the time it measured.
+// ---------------------------------------------------------------------------
+int parse_tune_file(const char *path, std::map<std::string, std::string> &out) {
+  FILE *f = std::fopen(path, "r");
+  if (!f) return fail(MQO_ERR_INVALID_ARG, "cannot open tuning cache %s", path);
+  char line[1024];
+  int lineno = 0, st = MQO_OK;
+  std::map<std::string, std::string> got;
+  while (std::fgets(line, sizeof(line), f)) {
+    ++lineno;
+    std::string l(line);
+    while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+    if (l.empty() || l[0] == '#') continue;
+    const size_t tab = l.find('\t');
+    if (tab == std::string::npos || tab == 0 || tab + 1 >= l.size() || l.find('\t', tab + 1) != std::string::npos) {
+      st = fail(MQO_ERR_INVALID_ARG, "tuning cache %s line %d: expected key<TAB>value", path, lineno);
+      break;
+    }
+    got[l.substr(0, tab)] = l.substr(tab + 1);
+  }
+  std::fclose(f);
+  if (st == MQO_OK)
+    for (auto &kv : got) out[kv.first] = kv.second;
+  return st;
+}
+
+// with R.mu held: the MQO_TUNE_CACHE file's entries, once per process
+void tune_env_load_locked(Resources &R) {
+  if (R.tune_env_loaded) return;
+  R.tune_env_loaded = true;
+  const char *path = std::getenv("MQO_TUNE_CACHE");
+  if (path && *path) {
+    std::map<std::string, std::string> got;
+    FILE *probe = std::fopen(path, "r");
+    if (probe) {
+      std::fclose(probe);
+      if (parse_tune_file(path, got) == MQO_OK) R.tune.insert(got.begin(), got.end());
+    }
+  }
+}
+
+bool tune_get(const std::string &key, std::string *val) {
+  Resources &R = res();
+  std::lock_guard<std::mutex> lk(R.mu);
+  tune_env_load_locked(R);
+  auto it = R.tune.find(key);
+  if (it == R.tune.end()) return false;
+  *val = it->second;
+  return true;
+}
+
+void tune_put(const std::string &key, const std::string &val) {
+  Resources &R = res();
+  std::lock_guard<std::mutex> lk(R.mu);
+  tune_env_load_locked(R);
+  R.tune[key] = val;
+  const char *path = std::getenv("MQO_TUNE_CACHE");
+  if (path && *path) {
+    FILE *f = std::fopen(path, "a");
+    if (f) {
+      std::fprintf(f, "%s\t%s\n", key.c_str(), val.c_str());
+      std::fclose(f);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -181,6 +260,10 @@ int check_params(const mqo_params *p, mqo_objective obj) {
   if (p->pool_k > 0 && (p->plan == MQO_PLAN_PERSISTENT || p->plan == MQO_PLAN_PLAIN))
     return fail(MQO_ERR_UNSUPPORTED, "the pool couples the trajectories of a graph: batched plan only");
   if (p->plan < MQO_PLAN_AUTO || p->plan > MQO_PLAN_PERSISTENT) return fail(MQO_ERR_INVALID_ARG, "bad plan");
+  if (p->step_vec != 0 && p->step_vec != 1 && p->step_vec != 2 && p->step_vec != 4)
+    return fail(MQO_ERR_INVALID_ARG, "step_vec must be 0, 1, 2 or 4");
+  if (p->step_lanes < 0 || p->step_lanes > 64 || (p->step_lanes & (p->step_lanes - 1)))
+    return fail(MQO_ERR_INVALID_ARG, "step_lanes must be 0 or a power of two <= 64");
   if (p->traj_count < 0 || (p->traj_count > 0 && !p->traj_ids))
     return fail(MQO_ERR_INVALID_ARG, "traj_count must be >= 0, with traj_ids when > 0");
   if (p->traj_count > 0 && p->plan != MQO_PLAN_PLAIN)
@@ -411,6 +494,7 @@ struct Solve {
   int64_t *best = nullptr; // incumbent values [G*B]: the caller's traj_best_value when given, else workspace
   int64_t ls_iters = 0;
   int64_t search_alt = 0;  // pair iterations that applied a move, summed over the pass searches
+  StepCfg step_cfg{0, 0};  // streaming plans: the step kernel's launch shape (of the first loop)
   int32_t deferred_tile_wg = 0;  // > 0: the tile counters sit in the pinned buffer after the final sync
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;  // around the step launches
   // MQO_TRACE: HIP events around every phase of the solve, on its stream
@@ -609,6 +693,21 @@ GraphView whole_view(const mqo_graph *g) {
   return v;
 }
 
+// Every graph of the batch as one block-diagonal matrix for the sparse
+// product: the hub rows of all graphs (each graph's list is ascending and
+// the graphs follow each other, so the concatenation is too) and the
+// near-regular flag, as view_of gives them per graph.
+GraphView batch_view(const mqo_graph *g, int32_t max_deg) {
+  GraphView v = whole_view(g);
+  if (g->hub_offset && g->hub_offset[g->num_graphs] > 0) {
+    v.hubs = g->hub_rows;
+    v.nhub = (int32_t)g->hub_offset[g->num_graphs];
+    v.hub_deg = g->hub_min_degree;
+  }
+  v.pairs = view_of(g, 0, max_deg).pairs;
+  return v;
+}
+
 // OneTwoSwap / OneTwoFlip on all B columns of every graph of g at once: the
 // 1-flip search, then pair iterations each followed by the 1-flip search,
 // until an iteration applies no move anywhere (columns that are done stay
@@ -699,6 +798,7 @@ struct StepLoop {
   // round), [1] = the shorter last chunk of a round
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   hipGraph_t graph[2] = {nullptr, nullptr};
+  StepCfg cfg{1, 0};  // launch shape of the step kernel (tuned per shape)
   ~StepLoop() {
     for (int i = 0; i < 2; ++i) {
       if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
@@ -707,9 +807,99 @@ struct StepLoop {
   }
 };
 
-void enqueue_steps(Solve &S, const GraphView &gv, float *X, float *Xt, float *V, int32_t ncols, int32_t ld,
-                   int32_t steps, const int8_t *colact) {
-  const StepCfg cfg = default_step_cfg(ncols, ld);
+// Launch shapes of the step kernel for ncols columns at leading dimension
+// ld: vec columns per lane (dividing ncols and ld), 2^ll lanes per row, up
+// to one lane per column group (more columns than lanes x vec take further
+// column slices).  Every shape computes the same sums in the same order.
+std::vector<StepCfg> step_candidates(int32_t ncols, int32_t ld) {
+  std::vector<StepCfg> out;
+  for (int vec : {1, 2, 4}) {
+    if (vec > 1 && (ncols % vec != 0 || ld % vec != 0 || ncols < 2 * vec)) continue;
+    const int32_t groups = (ncols + vec - 1) / vec;
+    for (int ll = 0; ll <= 6; ++ll) {
+      if (ll > 0 && (1 << (ll - 1)) >= groups) break;
+      out.push_back(StepCfg{vec, ll});
+    }
+  }
+  return out;
+}
+
+// The step kernel's launch shape for the rows of gv, by timing every
+// candidate on X -> Xt (plain steps: the momentum buffer is not touched)
+// once per shape key (graph size range, mean degree, columns, objective,
+// weights, hubs, GPU); the key's choice is cached.
+// step_vec / step_lanes of the parameters (0 = free) narrow the candidates.
+int tune_step(Solve &S, const GraphView &gv, int64_t nnz, const float *X, float *Xt, int32_t ncols, int32_t ld,
+              StepCfg *out, double *ms_out = nullptr) {
+  if (ms_out) *ms_out = -1.0;  // not timed
+  std::vector<StepCfg> cands;
+  for (const StepCfg &c : step_candidates(ncols, ld))
+    if ((!S.p->step_vec || c.vec == S.p->step_vec) && (!S.p->step_lanes || (1 << c.lanes_log2) == S.p->step_lanes))
+      cands.push_back(c);
+  if (cands.empty())
+    return fail(MQO_ERR_INVALID_ARG, "no step shape with %d columns per lane and %d lanes per row for %d columns",
+                S.p->step_vec, S.p->step_lanes, ncols);
+  const bool fixed = S.p->step_vec || S.p->step_lanes;
+  if (cands.size() == 1 || (!fixed && gv.n * (int64_t)ncols < 4096)) {
+    *out = fixed ? cands[0] : default_step_cfg(ncols, ld);  // nothing to choose, or too little work to time
+    return MQO_OK;
+  }
+  const double deg = (double)nnz / (double)gv.n;
+  char key[256];
+  snprintf(key, sizeof(key), "step|%s|%d|%d|%d|%d|%d|%d|%d|%d|%d", res().gpu.c_str(), S.form, gv.weight != nullptr,
+           gv.nhub > 0, (int)std::lround(std::log2((double)gv.n) * 2), (int)std::lround(std::log2(deg + 1.0) * 4),
+           ncols, ld, S.p->step_vec, S.p->step_lanes);
+  std::string cached;
+  if (tune_get(key, &cached)) {
+    StepCfg c{};
+    double ms = 0.0;
+    if (std::sscanf(cached.c_str(), "%d %d %lf", &c.vec, &c.lanes_log2, &ms) == 3)
+      for (const StepCfg &k : cands)
+        if (k.vec == c.vec && k.lanes_log2 == c.lanes_log2) {
+          *out = c;
+          if (ms_out) *ms_out = ms;
+          return MQO_OK;
+        }
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(MQO_ERR_HIP, "hipEventCreate failed");
+  }
+  StepCfg best = cands[0];
+  double best_t = 1e30;
+  int rc = MQO_OK;
+  for (const StepCfg &c : cands) {
+    launch_pga_step(S.form, gv, X, Xt, nullptr, ncols, ld, c, S.p->alpha, 0.0f, S.param, S.s);  // warm-up
+    (void)hipEventRecord(e0, S.s);
+    for (int rep = 0; rep < 3; ++rep)
+      launch_pga_step(S.form, gv, X, Xt, nullptr, ncols, ld, c, S.p->alpha, 0.0f, S.param, S.s);
+    (void)hipEventRecord(e1, S.s);
+    const hipError_t e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = fail(MQO_ERR_HIP, "step tuning: %s", hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    if (ms / 3.0 < best_t) {
+      best_t = ms / 3.0;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  TRY(rc);
+  char val[64];
+  snprintf(val, sizeof(val), "%d %d %.6f", best.vec, best.lanes_log2, best_t);
+  tune_put(key, val);
+  *out = best;
+  if (ms_out) *ms_out = best_t;
+  return MQO_OK;
+}
+
+void enqueue_steps(Solve &S, const GraphView &gv, const StepCfg &cfg, float *X, float *Xt, float *V, int32_t ncols,
+                   int32_t ld, int32_t steps, const int8_t *colact) {
   float *a = X, *b = Xt;
   for (int32_t st = 0; st < steps; ++st) {
     launch_pga_step(S.form, gv, a, b, V, ncols, ld, cfg, S.p->alpha, S.p->momentum, S.param, S.s, colact);
@@ -721,13 +911,13 @@ void enqueue_steps(Solve &S, const GraphView &gv, float *X, float *Xt, float *V,
 int run_chunk(Solve &S, StepLoop &loop, int slot, bool use_graph, const GraphView &gv, float *X, float *Xt,
               float *V, int32_t ncols, int32_t ld, int32_t steps, const int8_t *colact) {
   if (!use_graph) {
-    enqueue_steps(S, gv, X, Xt, V, ncols, ld, steps, colact);
+    enqueue_steps(S, gv, loop.cfg, X, Xt, V, ncols, ld, steps, colact);
     HIP_TRY(hipGetLastError());
     return MQO_OK;
   }
   if (!loop.exec[slot]) {
     HIP_TRY(hipStreamBeginCapture(S.s, hipStreamCaptureModeThreadLocal));
-    enqueue_steps(S, gv, X, Xt, V, ncols, ld, steps, colact);
+    enqueue_steps(S, gv, loop.cfg, X, Xt, V, ncols, ld, steps, colact);
     hipError_t e = hipStreamEndCapture(S.s, &loop.graph[slot]);
     if (e != hipSuccess) return fail(MQO_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
     HIP_TRY(hipGraphInstantiate(&loop.exec[slot], loop.graph[slot], nullptr, nullptr, 0));
@@ -776,11 +966,12 @@ double now_s() {
 // captured step loops, so a loop shared by several trajectories (plain
 // plan) gets one fixed slot
 // Zp / base_slot: the pool this round restarts from (nullptr: incumbents)
-int grid_round(Solve &S, StepLoop &loop, bool use_graph, const GraphView &gv, int32_t r, float *X, float *Xt,
-               float *V, int8_t *Z, int8_t *Zb, int32_t ldb, int32_t *NB, uint32_t *PRIO, int8_t *F, int64_t *value,
-               int64_t *best, int32_t ncols, int32_t ld, uint64_t traj0, int8_t *colact, const int8_t *Zp = nullptr,
-               int32_t ldp = 0, const int32_t *base_slot = nullptr) {
-  int64_t *steps_ctr = at<int64_t>(S.ws, S.L.steps) + traj0;
+// The start of round r of one graph: r = 0 the given start (momentum
+// cleared), a fresh start of the outer loop, or the reset of the incumbent
+// (or of pool slot base_slot[c] of Zp).
+void round_start(Solve &S, const GraphView &gv, int32_t r, float *X, float *V, const int8_t *Zb, int32_t ldb,
+                 int32_t ncols, int32_t ld, uint64_t traj0, const int8_t *Zp = nullptr, int32_t ldp = 0,
+                 const int32_t *base_slot = nullptr) {
   const bool mom = S.p->momentum != 0.0f;
   const int32_t R = S.p->restart_every;
   hipEvent_t ph = S.phase_begin();
@@ -801,16 +992,32 @@ int grid_round(Solve &S, StepLoop &loop, bool use_graph, const GraphView &gv, in
     launch_fill_f32(V + gv.lo * ld, gv.n * ld, 0.0f, S.s);
   }
   S.phase_end(r > 0 && !(R > 0 && r % R == 0) ? PH_RESET : PH_INIT, ph);
-  if (S.p->steps_per_round > 0) {
-    hipEvent_t e0;
-    TRY(S.begin_timed(&e0));
-    ph = S.phase_begin();
-    TRY(run_steps(S, loop, use_graph, gv, X, Xt, mom ? V : nullptr, ncols, ld, colact, steps_ctr, Z, NB, value));
-    if (S.p->check_every <= 0) launch_add_i64(steps_ctr, ncols, S.p->steps_per_round, S.s);
-    S.phase_end(PH_STEPS, ph);
-    TRY(S.end_timed(e0));
-  }
-  ph = S.phase_begin();
+}
+
+// The round's PGA steps on the rows of gv (one graph, or every graph of the
+// batch at once when nothing stops early); steps_ctr: the executed-step
+// counters of those ncols_ctr trajectories.
+int round_steps(Solve &S, StepLoop &loop, bool use_graph, const GraphView &gv, float *X, float *Xt, float *V,
+                int32_t ncols, int32_t ld, int8_t *colact, int64_t *steps_ctr, int64_t ncols_ctr, int8_t *Z,
+                int32_t *NB, int64_t *value) {
+  if (S.p->steps_per_round <= 0) return MQO_OK;
+  const bool mom = S.p->momentum != 0.0f;
+  hipEvent_t e0;
+  TRY(S.begin_timed(&e0));
+  hipEvent_t ph = S.phase_begin();
+  TRY(run_steps(S, loop, use_graph, gv, X, Xt, mom ? V : nullptr, ncols, ld, colact, steps_ctr, Z, NB, value));
+  if (S.p->check_every <= 0) launch_add_i64(steps_ctr, ncols_ctr, S.p->steps_per_round, S.s);
+  S.phase_end(PH_STEPS, ph);
+  TRY(S.end_timed(e0));
+  return MQO_OK;
+}
+
+// The end of round r of one graph: rounding, 1-flip search, exact
+// evaluation and acceptance (strict improvement; round 0 initialises).
+int round_finish(Solve &S, const GraphView &gv, int32_t r, const float *X, int8_t *Z, int8_t *Zb, int32_t ldb,
+                 int32_t *NB, uint32_t *PRIO, int8_t *F, int64_t *value, int64_t *best, int32_t ncols, int32_t ld,
+                 uint64_t traj0) {
+  hipEvent_t ph = S.phase_begin();
   launch_round(S.maxcut, X, Z, gv.lo, gv.n, ncols, ld, S.s);
   if (S.p->local_search == MQO_LS_ONE_FLIP) {
     int64_t it = 0;
@@ -824,6 +1031,17 @@ int grid_round(Solve &S, StepLoop &loop, bool use_graph, const GraphView &gv, in
   S.phase_end(PH_EVALUATE, ph);
   HIP_TRY(hipGetLastError());
   return MQO_OK;
+}
+
+// one whole round of one graph (start, steps, end)
+int grid_round(Solve &S, StepLoop &loop, bool use_graph, const GraphView &gv, int32_t r, float *X, float *Xt,
+               float *V, int8_t *Z, int8_t *Zb, int32_t ldb, int32_t *NB, uint32_t *PRIO, int8_t *F, int64_t *value,
+               int64_t *best, int32_t ncols, int32_t ld, uint64_t traj0, int8_t *colact, const int8_t *Zp = nullptr,
+               int32_t ldp = 0, const int32_t *base_slot = nullptr) {
+  round_start(S, gv, r, X, V, Zb, ldb, ncols, ld, traj0, Zp, ldp, base_slot);
+  TRY(round_steps(S, loop, use_graph, gv, X, Xt, V, ncols, ld, colact, at<int64_t>(S.ws, S.L.steps) + traj0, ncols,
+                  Z, NB, value));
+  return round_finish(S, gv, r, X, Z, Zb, ldb, NB, PRIO, F, value, best, ncols, ld, traj0);
 }
 
 int32_t search_round(const Solve &S, int32_t r);
@@ -847,8 +1065,21 @@ int solve_batched(Solve &S, int32_t *rounds_done) {
     HIP_TRY(hipMemcpyAsync(X, S.x0, S.g->n_total * B * sizeof(float), hipMemcpyDeviceToDevice, S.s));
   else
     TRY(init_x(S, X));
-  const bool use_graph = S.G <= 16 && S.p->steps_per_round >= 4;
-  std::vector<StepLoop> loops(S.G);
+  // Without early exit the steps of every graph go in one launch over the
+  // block-diagonal batch (each row's sums are those of its own graph), one
+  // captured loop per round whatever the number of graphs; with it, each
+  // graph steps on its own (its trajectories stop independently).
+  const bool whole = S.p->check_every <= 0;
+  const bool use_graph = S.p->steps_per_round >= 4 && (whole || S.G <= 16);
+  const GraphView bv = batch_view(S.g, S.max_deg);
+  StepLoop whole_loop;
+  std::vector<StepLoop> loops(whole ? 0 : S.G);
+  if (whole)
+    TRY(tune_step(S, bv, S.g->nnz_total, X, Xt, B, B, &whole_loop.cfg));
+  else
+    for (int32_t gi = 0; gi < S.G; ++gi)
+      TRY(tune_step(S, view_of(S.g, gi, S.max_deg), S.nnz_g[gi], X, Xt, B, B, &loops[gi].cfg));
+  S.step_cfg = whole ? whole_loop.cfg : (S.G ? loops[0].cfg : StepCfg{1, 0});
   const int32_t K = S.p->pool_k;
   const bool search = S.p->final_search == MQO_FINAL_PAIR;
   if (K) {
@@ -859,6 +1090,8 @@ int solve_batched(Solve &S, int32_t *rounds_done) {
   bool searched = false;  // the last round run closed its pass with the search
   const double t0 = now_s();
   int32_t r = 0;
+  int64_t *steps_ctr = at<int64_t>(S.ws, S.L.steps);
+  int8_t *colact = at<int8_t>(S.ws, S.L.colact);
   for (r = 0; r < S.p->rounds; ++r) {
     if (r > 0 && S.p->time_budget_s > 0.0) {
       HIP_TRY(hipStreamSynchronize(S.s));
@@ -876,8 +1109,17 @@ int solve_batched(Solve &S, int32_t *rounds_done) {
         launch_pool_bases(at<int64_t>(S.ws, S.L.pv[cur]) + (int64_t)gi * K, K, B, S.p->seed, (uint64_t)t,
                           (uint64_t)r, base, S.s);
       }
-      TRY(grid_round(S, loops[gi], use_graph, gv, r, X, Xt, V, Z, Zb, B, NB, PRIO, F, value + t, best + t, B, B,
-                     (uint64_t)t, at<int8_t>(S.ws, S.L.colact) + t, Zp, K, base));
+      round_start(S, gv, r, X, V, Zb, B, B, B, (uint64_t)t, Zp, K, base);
+      if (!whole)
+        TRY(round_steps(S, loops[gi], use_graph, gv, X, Xt, V, B, B, colact + t, steps_ctr + t, B, Z, NB, value + t));
+    }
+    if (whole)
+      TRY(round_steps(S, whole_loop, use_graph, bv, X, Xt, V, B, B, nullptr, steps_ctr, (int64_t)S.G * B, Z, NB,
+                      value));
+    for (int32_t gi = 0; gi < S.G; ++gi) {
+      const GraphView gv = view_of(S.g, gi, S.max_deg);
+      const int64_t t = (int64_t)gi * B;
+      TRY(round_finish(S, gv, r, X, Z, Zb, B, NB, PRIO, F, value + t, best + t, B, B, (uint64_t)t));
       hipEvent_t ph = K ? S.phase_begin() : nullptr;
       if (K)
         launch_pool_update(S.maxcut, Z, B, gv.lo, gv.n, gi, B, K, value, at<unsigned long long>(S.ws, S.L.chash),
@@ -949,6 +1191,8 @@ int solve_plain(Solve &S, int32_t *rounds_done) {
     if (gi != cur_g) {
       gv = view_of(S.g, gi, S.max_deg);
       loop.reset(new StepLoop);
+      loop->cfg = default_step_cfg(1, 1);  // one column: one lane per row
+      S.step_cfg = loop->cfg;
       cur_g = gi;
     }
     launch_strided_copy_f32(start, B, b, X, 1, 0, gv.lo, gv.n, S.s);
@@ -1049,9 +1293,9 @@ TileArgs tile_args(Solve &S, const TileCfg &c, const float *x0) {
 std::string tile_key(const Solve &S) {
   char buf[256];
   const double deg = (double)S.g->nnz_total / (double)S.g->n_total;
-  snprintf(buf, sizeof(buf), "%d|%d|%d|%lld|%d|%d|%d|%d|%d", (int)S.maxcut, S.g->weight != nullptr,
+  snprintf(buf, sizeof(buf), "%d|%d|%d|%lld|%d|%d|%d|%d", (int)S.maxcut, S.g->weight != nullptr,
            S.p->momentum != 0.0f, (long long)S.n_max, (int)std::lround(std::log2(deg + 1.0) * 4), S.B, S.G,
-           S.p->local_search, res().device);
+           S.p->local_search);
   return buf;
 }
 
@@ -1088,28 +1332,34 @@ std::vector<TileCfg> tile_candidates(const Solve &S) {
 
 // Time one round of up to 32 steps per candidate; keep the fastest.  Every
 // candidate computes bit-identical results, so this only affects speed.
-int tune_tile(Solve &S, const float *x0, TileCfg *out) {
+// ms_per_step (or nullptr): the chosen shape's time per PGA step.
+int tune_tile(Solve &S, const float *x0, TileCfg *out, double *ms_per_step = nullptr) {
   Resources &R = res();
   char fixed[64];
   snprintf(fixed, sizeof(fixed), "|%d|%d|%d|%d|%d|%d", S.p->tile_cols, S.p->tile_threads, S.p->tile_vec,
            S.p->tile_csr, S.p->tile_reg, S.max_deg);
-  const std::string key = tile_key(S) + fixed;
-  {
-    std::lock_guard<std::mutex> lk(R.mu);
-    auto it = R.tile_tuning.find(key);
-    if (it != R.tile_tuning.end()) {
-      *out = it->second;
+  const std::string key = "tile|" + R.gpu + "|" + tile_key(S) + fixed;
+  std::string cached;
+  if (tune_get(key, &cached)) {
+    TileCfg c{};
+    double ms = 0.0;
+    if (std::sscanf(cached.c_str(), "%d %d %d %d %d %d %lf", &c.T, &c.threads, &c.vec, &c.csr, &c.dreg, &c.ipt,
+                    &ms) == 7 &&
+        tile_feasible(S, c)) {
+      *out = c;
+      if (ms_per_step) *ms_per_step = ms;
       return MQO_OK;
     }
   }
   const std::vector<TileCfg> cands = tile_candidates(S);
   if (cands.empty()) return fail(MQO_ERR_UNSUPPORTED, "no persistent tile shape fits these graphs");
   TileCfg best_c = cands[0];
-  if (cands.size() > 1) {
+  double best_t = 1e30;
+  const int tsteps = std::max(1, std::min(S.p->steps_per_round, 64));
+  {
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    double best_t = 1e30;
     const bool mc = S.maxcut, w = S.g->weight != nullptr;
     for (const TileCfg &c : cands) {
       // the shapes differ only in the step loop: time one round of up to 64
@@ -1117,7 +1367,7 @@ int tune_tile(Solve &S, const float *x0, TileCfg *out) {
       TileArgs a = tile_args(S, c, x0);
       a.r0 = 0;
       a.r1 = 1;
-      a.steps = std::min(S.p->steps_per_round, 64);
+      a.steps = tsteps;
       a.ls = 0;
       float ms = 0.f;
       if (launch_tile_round(mc, w, a, c.threads, S.s) != hipSuccess) continue;  // warm-up
@@ -1126,6 +1376,7 @@ int tune_tile(Solve &S, const float *x0, TileCfg *out) {
       HIP_TRY(hipEventRecord(e1, S.s));
       HIP_TRY(hipEventSynchronize(e1));
       HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      ms /= 2.0f * (float)tsteps;  // per step
       if (ms < best_t) {
         best_t = ms;
         best_c = c;
@@ -1134,11 +1385,12 @@ int tune_tile(Solve &S, const float *x0, TileCfg *out) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   }
-  {
-    std::lock_guard<std::mutex> lk(R.mu);
-    R.tile_tuning[key] = best_c;
-  }
+  char val[128];
+  snprintf(val, sizeof(val), "%d %d %d %d %d %d %.6f", best_c.T, best_c.threads, best_c.vec, best_c.csr, best_c.dreg,
+           best_c.ipt, best_t);
+  tune_put(key, val);
   *out = best_c;
+  if (ms_per_step) *ms_per_step = best_t;
   return MQO_OK;
 }
 
@@ -1323,6 +1575,49 @@ int search_pool_pass(Solve &S, const int8_t *PZ, const int64_t *PV, int32_t rnd,
   return MQO_OK;
 }
 
+// MQO_PLAN_AUTO: the streaming (batched) plan when no persistent tile shape
+// fits, else the faster of the two per PGA step over the whole batch --
+// the best persistent tile shape's round of steps against the best
+// streaming step launch -- timed once per shape key and cached.
+int choose_plan(Solve &S, int *plan) {
+  if (!tile_possible(S)) {
+    *plan = MQO_PLAN_BATCHED;
+    return MQO_OK;
+  }
+  const std::string key = "plan|" + res().gpu + "|" + tile_key(S);
+  std::string cached;
+  if (tune_get(key, &cached)) {
+    if (cached.rfind("persistent", 0) == 0) {
+      *plan = MQO_PLAN_PERSISTENT;
+      return MQO_OK;
+    }
+    if (cached.rfind("batched", 0) == 0) {
+      *plan = MQO_PLAN_BATCHED;
+      return MQO_OK;
+    }
+  }
+  float *X = at<float>(S.ws, S.L.X), *Xt = at<float>(S.ws, S.L.Xt);
+  if (S.x0)
+    HIP_TRY(hipMemcpyAsync(X, S.x0, S.g->n_total * S.B * sizeof(float), hipMemcpyDeviceToDevice, S.s));
+  else
+    TRY(init_x(S, X));
+  TileCfg tc{};
+  double tile_ms = -1.0, step_ms = -1.0;
+  TRY(tune_tile(S, X, &tc, &tile_ms));
+  StepCfg sc{};
+  TRY(tune_step(S, batch_view(S.g, S.max_deg), S.g->nnz_total, X, Xt, S.B, S.B, &sc, &step_ms));
+  if (step_ms < 0.0) {  // too little work to time a step: the persistent plan
+    *plan = MQO_PLAN_PERSISTENT;
+    return MQO_OK;
+  }
+  *plan = step_ms < tile_ms ? MQO_PLAN_BATCHED : MQO_PLAN_PERSISTENT;
+  char val[96];
+  snprintf(val, sizeof(val), "%s %.6f %.6f", *plan == MQO_PLAN_PERSISTENT ? "persistent" : "batched", tile_ms,
+           step_ms);
+  tune_put(key, val);
+  return MQO_OK;
+}
+
 int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_result *r, void *ws, size_t ws_bytes,
                  void *stream, mqo_objective obj) {
   TRY(check_graph_args(g, obj == MQO_OBJ_MIS_H));
@@ -1381,9 +1676,9 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
   S.nnz_g.resize(S.G);
   for (int32_t i = 0; i < S.G; ++i) S.nnz_g[i] = rp[i + 1] - rp[i];
 
-  launch_fill_i64(at<int64_t>(ws, L.steps), (int64_t)S.G * S.B, 0, s);
   int plan = p->plan;
-  if (plan == MQO_PLAN_AUTO) plan = tile_possible(S) ? MQO_PLAN_PERSISTENT : MQO_PLAN_BATCHED;
+  if (plan == MQO_PLAN_AUTO) TRY(choose_plan(S, &plan));
+  launch_fill_i64(at<int64_t>(ws, L.steps), (int64_t)S.G * S.B, 0, s);  // after the plan's trial rounds
   int32_t rounds_done = 0;
   TileCfg used{0, 0, 0, 0, 0, 0};
   if (plan == MQO_PLAN_PERSISTENT)
@@ -1434,6 +1729,8 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
   r->step_kernel_ms = S.timed_ms();
   r->step_kernel_launches = (int64_t)S.timed.size();
   r->final_search_alternations = S.search_alt;
+  r->step_vec_used = plan == MQO_PLAN_PERSISTENT ? 0 : S.step_cfg.vec;
+  r->step_lanes_used = plan == MQO_PLAN_PERSISTENT ? 0 : 1 << S.step_cfg.lanes_log2;
   if (S.tracing) write_trace(S, plan, rounds_done, 1e3 * (now_s() - wall0));
   return MQO_OK;
 }
@@ -1916,7 +2213,35 @@ int mqo_version(void) { return MQO_VERSION; }
 void mqo_clear_caches(void) {
   Resources &r = res();
   std::lock_guard<std::mutex> lk(r.mu);
-  r.tile_tuning.clear();
+  r.tune.clear();
+}
+
+int mqo_tune_cache_load(const char *path) {
+  if (!path) return fail(MQO_ERR_INVALID_ARG, "path is NULL");
+  std::map<std::string, std::string> got;
+  TRY(parse_tune_file(path, got));
+  Resources &r = res();
+  std::lock_guard<std::mutex> lk(r.mu);
+  for (auto &kv : got) r.tune[kv.first] = kv.second;
+  return MQO_OK;
+}
+
+int mqo_tune_cache_save(const char *path) {
+  if (!path) return fail(MQO_ERR_INVALID_ARG, "path is NULL");
+  Resources &r = res();
+  std::lock_guard<std::mutex> lk(r.mu);
+  FILE *f = std::fopen(path, "w");
+  if (!f) return fail(MQO_ERR_INVALID_ARG, "cannot write tuning cache %s", path);
+  std::fprintf(f, "# libmqo autotuner cache: key<TAB>value\n");
+  for (auto &kv : r.tune) std::fprintf(f, "%s\t%s\n", kv.first.c_str(), kv.second.c_str());
+  const bool ok = std::fclose(f) == 0;
+  return ok ? MQO_OK : fail(MQO_ERR_INVALID_ARG, "cannot write tuning cache %s", path);
+}
+
+int64_t mqo_tune_cache_size(void) {
+  Resources &r = res();
+  std::lock_guard<std::mutex> lk(r.mu);
+  return (int64_t)r.tune.size();
 }
 
 

@@ -53,7 +53,8 @@ class _Params(ctypes.Structure):
                 ("time_budget_s", ctypes.c_double), ("maxcut_objective", ctypes.c_int32),
                 ("final_search", ctypes.c_int32), ("pool_k", ctypes.c_int32),
                 ("restart_every", ctypes.c_int32), ("traj_count", ctypes.c_int32),
-                ("traj_ids", ctypes.POINTER(ctypes.c_int64))]
+                ("traj_ids", ctypes.POINTER(ctypes.c_int64)), ("step_vec", ctypes.c_int32),
+                ("step_lanes", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -66,7 +67,8 @@ class _Result(ctypes.Structure):
                 ("ls_iterations", ctypes.c_int64),
                 ("step_kernel_ms", ctypes.c_double), ("step_kernel_launches", ctypes.c_int64),
                 ("final_search_alternations", ctypes.c_int64), ("pool_x", ctypes.c_void_p),
-                ("pool_value", ctypes.c_void_p)]
+                ("pool_value", ctypes.c_void_p), ("step_vec_used", ctypes.c_int32),
+                ("step_lanes_used", ctypes.c_int32)]
 
 
 def _load():
@@ -101,6 +103,9 @@ def _load():
         "mqo_last_error": (ctypes.c_char_p, []),
         "mqo_version": (i32, []),
         "mqo_clear_caches": (None, []),
+        "mqo_tune_cache_load": (i32, [ctypes.c_char_p]),
+        "mqo_tune_cache_save": (i32, [ctypes.c_char_p]),
+        "mqo_tune_cache_size": (i64, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -135,6 +140,18 @@ def _stream(device) -> ctypes.c_void_p:
 
 def version() -> int:
     return _lib.mqo_version()
+
+
+def tune_cache_load(path: str) -> None:
+    _check(_lib.mqo_tune_cache_load(os.fsencode(path)), "mqo_tune_cache_load")
+
+
+def tune_cache_save(path: str) -> None:
+    _check(_lib.mqo_tune_cache_save(os.fsencode(path)), "mqo_tune_cache_save")
+
+
+def tune_cache_size() -> int:
+    return _lib.mqo_tune_cache_size()
 
 
 # --------------------------------------------------------------------------
@@ -217,7 +234,8 @@ def last_error() -> str:
 def make_params(batch=1, steps_per_round=200, rounds=1, alpha=0.01, momentum=0.0, gamma=2.0, lam=1e-3,
                 rho=0.05, init_sigma=0.0, init_mode="uniform", reset_mode="zero", local_search=True,
                 plan="auto", seed=0, time_budget_s=0.0, tile_cols=0, tile_threads=0, tile_vec=0, tile_csr=0,
-                tile_reg=0, check_every=0, final_search=False, pool_k=0, restart_every=0) -> _Params:
+                tile_reg=0, check_every=0, final_search=False, pool_k=0, restart_every=0, step_vec=0,
+                step_lanes=0) -> _Params:
     p = _Params()
     _lib.mqo_params_default(ctypes.byref(p))
     p.batch, p.steps_per_round, p.rounds, p.check_every = batch, steps_per_round, rounds, check_every
@@ -232,6 +250,7 @@ def make_params(batch=1, steps_per_round=200, rounds=1, alpha=0.01, momentum=0.0
     p.final_search = 1 if final_search else 0
     p.pool_k = pool_k
     p.restart_every = restart_every
+    p.step_vec, p.step_lanes = step_vec, step_lanes
     return p
 
 
@@ -312,7 +331,8 @@ def solve(kind, dg: DeviceGraph, x0: Optional[torch.Tensor] = None, workspace: O
                tile_reg_degree=r.tile_reg_degree_used,
                ls_iterations=r.ls_iterations,
                step_kernel_ms=r.step_kernel_ms, step_kernel_launches=r.step_kernel_launches,
-               final_search_alternations=r.final_search_alternations)
+               final_search_alternations=r.final_search_alternations, step_vec=r.step_vec_used,
+               step_lanes=r.step_lanes_used)
     if want_traj:
         out["traj_best_value"] = traj_v
         out["traj_best_x"] = traj_x.view(dg.n, B)

@@ -221,3 +221,33 @@ def test_static_scratch_variant_checks_its_limit_on_host(m):
                                        None) == -3
     assert "static scratch" in m.last_error()
     assert L.mqo_objective_grad_static(ctypes.byref(s), 0, 0.5, X, B, None, None, None, None) == -1  # gamma <= 1
+
+
+def test_tuning_cache_file_round_trip(m, tmp_path):
+    """The autotuner cache is host data: load merges a file's entries, save
+    writes every entry back, malformed files are refused whole."""
+    L = m.lib()
+    L.mqo_clear_caches()
+    src = tmp_path / "in.txt"
+    src.write_text("# comment\nstep|gfx950x256|0|0|0|14|13|32|32|0|0\t4 3 0.051200\n\n"
+                   "tile|gfx950x256|0|0|0|800|15|512|128|1|0|0|0|0|0|16\t8 1024 1 0 0 0 0.120000\n"
+                   "plan|gfx950x256|0|0|0|800|15|512|128|1\tpersistent 0.12 0.90\n")
+    m.tune_cache_load(str(src))
+    assert m.tune_cache_size() == 3
+    out = tmp_path / "out.txt"
+    m.tune_cache_save(str(out))
+    lines = [ln for ln in out.read_text().splitlines() if ln and not ln.startswith("#")]
+    want = [ln for ln in src.read_text().splitlines() if ln and not ln.startswith("#")]
+    assert sorted(lines) == sorted(want)
+    L.mqo_clear_caches()
+    m.tune_cache_load(str(out))
+    assert m.tune_cache_size() == 3
+    bad = tmp_path / "bad.txt"
+    bad.write_text("step|x\t1 2 3\nno tab here\n")
+    with pytest.raises(m.MqoError):
+        m.tune_cache_load(str(bad))
+    assert m.tune_cache_size() == 3  # nothing of the malformed file merged
+    with pytest.raises(m.MqoError):
+        m.tune_cache_load(str(tmp_path / "missing.txt"))
+    L.mqo_clear_caches()
+    assert m.tune_cache_size() == 0

@@ -352,11 +352,83 @@ def test_trace_reports_every_phase(mqo, tmp_path, monkeypatch):
     b, t = lines
     assert b["plan"] == "batched" and t["plan"] == "persistent" and b["rounds_executed"] == 3
     G = g.num_graphs
-    assert b["phases"]["steps"]["count"] == 3 * G and b["phases"]["reset"]["count"] == 2 * G
+    # one step launch per round over the whole batch of graphs
+    assert b["phases"]["steps"]["count"] == 3 and b["phases"]["reset"]["count"] == 2 * G
     assert b["phases"]["local_search"]["count"] == 3 * G and b["phases"]["evaluate"]["count"] == 3 * G
     assert b["phases"]["pair_search"]["count"] == 1
     assert all(v["ms"] >= 0 for v in b["phases"].values())
     assert t["phases"]["persistent_rounds"]["count"] >= 1 and "steps" not in t["phases"]
+
+
+def _step_shapes(B):
+    out = []
+    for vec in (1, 2, 4):
+        if vec > 1 and (B % vec or B < 2 * vec):
+            continue
+        groups = -(-B // vec)
+        lanes = 1
+        while True:
+            out.append((vec, lanes))
+            if lanes >= groups or lanes == 64:
+                break
+            lanes *= 2
+    return out
+
+
+_SHAPE_REF = {}
+
+
+@pytest.mark.parametrize("kind,B,vec,lanes", [(k, B, v, l) for k in ("mis", "maxcut") for B in (8, 13)
+                                              for v, l in _step_shapes(B)])
+def test_forced_step_shapes_bit_exact(mqo, kind, B, vec, lanes):
+    """Every launch shape of the streaming step kernel (columns per lane x
+    lanes per row, more columns than lanes x vec in further column slices)
+    on the batched plan, over a ragged batch with a hub row (MIS) or a
+    weighted batch (MaxCut), equals the oracle bit for bit."""
+    g = graphs.concat([graphs.erdos_renyi(150, 0.05, 31), graphs.star(200), graphs.path(3)]) if kind == "mis" else \
+        graphs.concat([graphs.torus_pm1(9, 32), graphs.with_weights(graphs.erdos_renyi(80, 0.1, 33), 34)])
+    dg = mqo.DeviceGraph(g, DEV, hub_min_degree=64)
+    kw = dict(batch=B, steps_per_round=20, rounds=2, alpha=0.05, rho=0.15, seed=35)
+    out = mqo.solve(kind, dg, plan="batched", step_vec=vec, step_lanes=lanes, **kw)
+    assert (out["step_vec"], out["step_lanes"]) == (vec, lanes)
+    if (kind, B) not in _SHAPE_REF:
+        _SHAPE_REF[(kind, B)] = solver.solve(kind, g, solver.Params(**kw))
+    ref = _SHAPE_REF[(kind, B)]
+    for key in ("traj_best_value", "traj_best_x", "best_value"):
+        assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
+
+
+def test_step_shape_rejected_when_it_does_not_fit(mqo):
+    dg = mqo.DeviceGraph(CASES["reg3"][1], DEV)
+    with pytest.raises(mqo.MqoError) as e:
+        mqo.solve("maxcut", dg, plan="batched", batch=6, steps_per_round=4, step_vec=4)
+    assert e.value.status == -1
+    with pytest.raises(mqo.MqoError):
+        mqo.solve("maxcut", dg, plan="batched", batch=6, steps_per_round=4, step_lanes=3)
+
+
+def test_auto_plan_is_tuned_and_cached(mqo, tmp_path, monkeypatch):
+    """MQO_PLAN_AUTO times the persistent and streaming shapes once per shape
+    key; the choice is in the cache file, reused by the next solve, and
+    either plan gives the same result."""
+    kind, g = CASES["er_batch"]
+    dg = mqo.DeviceGraph(g, DEV)
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("MQO_TUNE_CACHE", str(path))
+    mqo.lib().mqo_clear_caches()
+    kw = dict(batch=16, steps_per_round=20, rounds=2, alpha=0.05, rho=0.15, seed=36)
+    a = mqo.solve(kind, dg, **kw)
+    assert a["plan"] in ("persistent", "batched")
+    keys = [ln.split("\t")[0] for ln in path.read_text().splitlines() if ln and not ln.startswith("#")]
+    assert any(k.startswith("plan|") for k in keys) and any(k.startswith("tile|") for k in keys)
+    n = mqo.tune_cache_size()
+    b = mqo.solve(kind, dg, **kw)
+    assert b["plan"] == a["plan"] and mqo.tune_cache_size() == n  # nothing timed again
+    other = "batched" if a["plan"] == "persistent" else "persistent"
+    c = mqo.solve(kind, dg, plan=other, **kw)
+    for key in ("traj_best_value", "traj_best_x", "best_value", "best_x"):
+        assert torch.equal(a[key], c[key]), key
+    mqo.lib().mqo_clear_caches()
 
 
 def test_two_streams_at_once(mqo):
