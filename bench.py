@@ -28,8 +28,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12  # bytes/s, MI355X
-# LDS: 256 CUs x 128 bytes/clock x 2.4 GHz
-LDS_PEAK = 256 * 128 * 2.4e9
+# LDS read peak: 256 CUs x 256 bytes/clock x 2.4 GHz.  CDNA 4 doubles the
+# LDS read bandwidth of CDNA 3 (128 bytes/clock/CU) along with its size
+# (160 KiB); a plain 128-bit LDS read loop over all CUs measured 168
+# bytes/clock/CU on MI355X, above the CDNA 3 figure, so 256 is the bound.
+LDS_PEAK = 256 * 256 * 2.4e9
 KERNEL_SOURCES = {"k_tile_round": "paper_2605_06921_amd/csrc/tile_kernel.hip",
                   "k_pga_step": "paper_2605_06921_amd/csrc/grid_kernels.hip",
                   "k_objective_grad": "paper_2605_06921_amd/csrc/grid_kernels.hip",
@@ -106,7 +109,9 @@ def _oracle_params(wl, rounds, pool_k=0, final_search=False):
     from oracle import solver as osolver
     return osolver.Params(batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=rounds, alpha=wl.alpha,
                           seed=wl.seed, gamma=wl.gamma, lam=wl.lam, rho=wl.rho, reset_mode=wl.reset_mode,
-                          local_search=wl.local_search, pool_k=pool_k, final_search=final_search)
+                          local_search=wl.local_search, pool_k=pool_k, final_search=final_search or wl.final_search,
+                          mu=wl.momentum, check_every=wl.check_every, init_mode=wl.init_mode,
+                          init_sigma=wl.init_sigma)
 
 
 _WORKER = {}
@@ -300,6 +305,44 @@ def bench_pair(args, wl):
     return res
 
 
+def bench_quality(args, wl):
+    """Best value at fixed wall-time budgets: the workload's solve with as
+    many rounds as fit in each budget (the outer loop of Alg. 1-4 runs
+    while time remains; no round starts after the budget), then its own
+    full run of `rounds` rounds.  Each budget is one solve; its best value,
+    the rounds run and the wall time are reported."""
+    import torch
+    from paper_2605_06921_amd import mqo
+
+    g = wl.make_graph()
+    dev = torch.device("cuda:0")
+    dg = mqo.DeviceGraph(g, dev)
+    kw = dict(batch=wl.batch, steps_per_round=wl.steps_per_round, alpha=wl.alpha, gamma=wl.gamma, lam=wl.lam,
+              rho=wl.rho, reset_mode=wl.reset_mode, local_search=wl.local_search, seed=wl.seed)
+    ws = mqo.Workspace(dev)
+    mqo.solve(wl.problem, dg, workspace=ws, rounds=1, **kw)  # tuning and warm-up
+    torch.cuda.synchronize()
+    runs = []
+    for budget in [float(b) for b in args.budgets.split(",") if b] + [None]:
+        rounds = wl.rounds if budget is None else 1 << 30
+        t0 = time.perf_counter()
+        out = mqo.solve(wl.problem, dg, workspace=ws, rounds=rounds, time_budget_s=budget or 0.0, **kw)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        runs.append(dict(budget_s=budget, wall_s=el, rounds=out["rounds_executed"],
+                         steps=out["steps_executed"], best_value=int(out["best_value"][0]),
+                         edge_updates_per_s=out["edge_updates"] / el, plan=out["plan"]))
+        log(f"[bench] quality budget={budget}: best {runs[-1]['best_value']} after {out['rounds_executed']} rounds "
+            f"in {el:.1f} s")
+    return dict(metric="best MIS size / cut at fixed wall time", value=runs[0]["best_value"],
+                unit="MIS size" if wl.problem == "mis" else "cut weight", n_gpus=1, steps=len(runs), warmup=1,
+                ms_per_step=1e3 * runs[0]["wall_s"], higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f32", data="synthetic",
+                config=dict(workload=wl.name, mode="quality", description=wl.description, n=g.n, nnz=g.nnz,
+                            batch=wl.batch, steps_per_round=wl.steps_per_round, rho=wl.rho, parallelism="dp1"),
+                runs=runs)
+
+
 def bench_toy(args):
     """Prop. 4.1's toy at n = 64: 2^20 independent trials of the
     single-coordinate global reset for R = ceil(2 log(n / delta)) rounds of n
@@ -479,7 +522,9 @@ def main():
                     help="solve mode: pmQO pool of K solutions per graph (Alg. 3 / 4; batched plan)")
     ap.add_argument("--final-search", action="store_true",
                     help="solve mode: the paper's own search on the incumbents (or the pool) after the rounds")
-    ap.add_argument("--mode", default="solve", choices=["solve", "grad", "unrolled", "pair", "toy"],
+    ap.add_argument("--budgets", default="10,60",
+                    help="quality mode: wall-time budgets in seconds, comma separated")
+    ap.add_argument("--mode", default="solve", choices=["solve", "grad", "unrolled", "pair", "toy", "quality"],
                     help="solve: whole batched solves; grad: objective + SpMM gradient over the batch; "
                          "unrolled: K = 20 unrolled PGA steps forward and their adjoint (checkpoints every 5)")
     ap.add_argument("--tile", default="",
@@ -518,6 +563,9 @@ def main():
     if args.mode == "pair":
         print(json.dumps(with_measured_rate(bench_pair(args, wl))), flush=True)
         return
+    if args.mode == "quality":
+        print(json.dumps(bench_quality(args, wl)), flush=True)
+        return
     if args.mode != "solve":
         return bench_differentiation(args, wl)
     if args.pool or args.final_search:
@@ -536,7 +584,8 @@ def main():
     dg = mqo.DeviceGraph(g, dev)
     kw = dict(batch=wl.batch, steps_per_round=wl.steps_per_round, rounds=wl.rounds, alpha=wl.alpha, gamma=wl.gamma,
               lam=wl.lam, rho=wl.rho, reset_mode=wl.reset_mode, local_search=wl.local_search, seed=wl.seed,
-              pool_k=args.pool, final_search=args.final_search)
+              pool_k=args.pool, final_search=args.final_search or wl.final_search, momentum=wl.momentum,
+              check_every=wl.check_every, init_mode=wl.init_mode, init_sigma=wl.init_sigma)
     if args.tile:
         t = [int(v) for v in args.tile.split(",")]
         kw.update(tile_cols=t[0], tile_threads=t[1], tile_vec=t[2], tile_csr=t[3], tile_reg=t[4])
@@ -611,8 +660,8 @@ def main():
                                unit="GB/s", frac=lds_bytes / avg_launch_s / LDS_PEAK, traffic=traffic, kernel=kernel,
                                avg_launch_ms=avg_launch_s * 1e3, algorithmic_bytes_per_launch=lds_bytes,
                                steps_per_launch=steps_per_launch,
-                               note="LDS peak = 256 CUs x 128 bytes/clock x 2.4 GHz; traffic = measured HBM "
-                                    "bytes per launch")
+                               note="LDS peak = 256 CUs x 256 bytes/clock x 2.4 GHz (CDNA 4 LDS reads); "
+                                    "traffic = measured HBM bytes per launch")
         res["hbm_equivalent"] = dict(rate=hbm_eq["achieved"], unit="GB/s", bytes_per_launch=per_launch_bytes,
                                      note="the bytes a streaming step would move through HBM (CSR once, X read "
                                           "once, X' written once), over the same launch time; the persistent "

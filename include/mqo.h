@@ -110,6 +110,14 @@ typedef struct {
    * kernel shapes (near-regular graphs take rows in pairs); results do not
    * depend on it, and the solves measure the degree themselves. */
   int32_t max_degree;
+  /* Optional hint: 1 when the neighbours of a row are mostly close to it in
+   * the vertex order (grids, tori, banded orders: mean |u - v| over the
+   * stored entries well below n_g / 8), 0 if not or unknown.  With 1 the
+   * sparse-product kernels hand each XCD one contiguous range of rows, so
+   * that rows sharing neighbours share an L2; with 0 rows are spread over
+   * the XCDs, which balances graphs whose heavy rows are clustered in the
+   * vertex order (preferential attachment).  Results do not depend on it. */
+  int32_t local_rows;
 } mqo_graph;
 
 /* Search parameters.  Fill with mqo_params_default() first. */

@@ -379,6 +379,7 @@ GraphView view_of(const mqo_graph *g, int32_t i, int32_t max_deg = -1) {
   // the common case
   const int64_t md = max_deg >= 0 ? max_deg : g->max_degree;
   v.pairs = md > 0 && 10 * g->nnz_total >= 9 * g->n_total * md ? 1 : 0;
+  v.xcd_local = g->local_rows == 1;
   return v;
 }
 
@@ -690,6 +691,7 @@ GraphView whole_view(const mqo_graph *g) {
   v.nhub = 0;
   v.hub_deg = 0x7fffffff;
   v.pairs = 0;
+  v.xcd_local = g->local_rows == 1;
   return v;
 }
 
@@ -1604,11 +1606,31 @@ int choose_plan(Solve &S, int *plan) {
   TileCfg tc{};
   double tile_ms = -1.0, step_ms = -1.0;
   TRY(tune_tile(S, X, &tc, &tile_ms));
-  StepCfg sc{};
-  TRY(tune_step(S, batch_view(S.g, S.max_deg), S.g->nnz_total, X, Xt, S.B, S.B, &sc, &step_ms));
-  if (step_ms < 0.0) {  // too little work to time a step: the persistent plan
-    *plan = MQO_PLAN_PERSISTENT;
-    return MQO_OK;
+  const GraphView bv = batch_view(S.g, S.max_deg);
+  // the streaming step in its default shape first: only when that is within
+  // twice the persistent round's time per step are its other shapes timed
+  {
+    const StepCfg dc = default_step_cfg(S.B, S.B);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    launch_pga_step(S.form, bv, X, Xt, nullptr, S.B, S.B, dc, S.p->alpha, 0.0f, S.param, S.s);
+    (void)hipEventRecord(e0, S.s);
+    launch_pga_step(S.form, bv, X, Xt, nullptr, S.B, S.B, dc, S.p->alpha, 0.0f, S.param, S.s);
+    (void)hipEventRecord(e1, S.s);
+    const hipError_t e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_TRY(e);
+    step_ms = ms;
+  }
+  if (step_ms < 2.0 * tile_ms) {
+    StepCfg sc{};
+    double tuned = -1.0;
+    TRY(tune_step(S, bv, S.g->nnz_total, X, Xt, S.B, S.B, &sc, &tuned));
+    if (tuned >= 0.0) step_ms = std::min(step_ms, tuned);
   }
   *plan = step_ms < tile_ms ? MQO_PLAN_BATCHED : MQO_PLAN_PERSISTENT;
   char val[96];

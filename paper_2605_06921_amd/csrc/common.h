@@ -211,6 +211,7 @@ struct GraphView {
   int32_t nhub;           // 0 = no hub list
   int32_t hub_deg;
   int32_t pairs;          // 1: near-regular graph, lane groups take rows in pairs
+  int32_t xcd_local;      // 1: rows close in the vertex order share neighbours (one row range per XCD)
 };
 
 // Row x column mapping: W lanes per row (power of two <= 64), each lane

@@ -31,18 +31,22 @@ static inline dim3 grid_rows(int64_t nrows, int ncols, int lanes_log2, int vec, 
 }
 
 // Workgroups are handed to the 8 XCDs (each with its own L2) round-robin in
-// launch order, linear id x + y gridDim.x.  The sparse-product kernels
-// renumber them so that each XCD runs one contiguous range of the (row
-// block, column slice) space: rows close in the vertex order, which gather
-// many of the same rows of X on graphs with locality (grids, tori, banded
-// orders), then share one L2 instead of fetching those rows once per XCD.
-// A bijection of the launch, so every result is unchanged.
+// launch order, linear id x + y gridDim.x.  On graphs with locality (grids,
+// tori, banded orders: the graph's local_rows hint) the sparse-product
+// kernels renumber them so that each XCD runs one contiguous range of the
+// (row block, column slice) space: rows close in the vertex order, which
+// gather many of the same rows of X, then share one L2 instead of fetching
+// those rows once per XCD.  Elsewhere the launch order stands: it spreads
+// rows that are heavy together (the early vertices of preferential
+// attachment) over all XCDs.  A bijection of the launch, so every result is
+// unchanged.
 struct Blk {
   int64_t x;
   int32_t y;
 };
 
-__device__ __forceinline__ Blk xcd_blk() {
+__device__ __forceinline__ Blk xcd_blk(bool local) {
+  if (!local) return Blk{blockIdx.x, (int32_t)blockIdx.y};
   const int64_t gx = gridDim.x, nb = gx * gridDim.y;
   const int64_t b = blockIdx.x + (int64_t)blockIdx.y * gx;
   const int64_t q = nb >> 3, r = nb & 7, xcd = b & 7, j = b >> 3;
@@ -428,7 +432,7 @@ __global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__re
                                                   int32_t lanes_log2, float alpha, float mu, float param,
                                                   const int8_t *__restrict__ colact) {
   const int64_t nhb = hub_blocks(g, ncols);
-  const Blk blk = xcd_blk();
+  const Blk blk = xcd_blk(g.xcd_local);
   if (blk.x < nhb) {
     if (blk.y != 0) return;
     const HubItem it = hub_item(g, ncols, blk.x);
@@ -1827,7 +1831,7 @@ __global__ __launch_bounds__(256) void k_objective_grad(GraphView g, const float
                                                         int32_t lanes_log2, float param) {
   const int64_t nhb = hub_blocks(g, ncols);
   const int64_t nrb = gridDim.x - nhb;  // row workgroups
-  const Blk blk = xcd_blk();
+  const Blk blk = xcd_blk(g.xcd_local);
   if (blk.x < nhb) {
     if (blk.y != 0) return;
     const HubItem it = hub_item(g, ncols, blk.x);
@@ -1926,7 +1930,7 @@ __global__ __launch_bounds__(256) void k_adj_mu(GraphView g, const float *__rest
                                                 int32_t lanes_log2, float alpha, float param) {
   const int64_t nhb = hub_blocks(g, ncols);
   const int64_t nrb = gridDim.x - nhb;
-  const Blk blk = xcd_blk();
+  const Blk blk = xcd_blk(g.xcd_local);
   if (blk.x < nhb) {
     if (blk.y != 0) return;
     const HubItem it = hub_item(g, ncols, blk.x);
@@ -2000,7 +2004,7 @@ __global__ __launch_bounds__(256) void k_adj_lambda(GraphView g, const float *__
                                                     int32_t ncols, int32_t ld, int32_t lanes_log2, float alpha,
                                                     float param) {
   const int64_t nhb = hub_blocks(g, ncols);
-  const Blk blk = xcd_blk();
+  const Blk blk = xcd_blk(g.xcd_local);
   if (blk.x < nhb) {
     if (blk.y != 0) return;
     const HubItem it = hub_item(g, ncols, blk.x);

@@ -39,7 +39,7 @@ class _Graph(ctypes.Structure):
                 ("n_total", ctypes.c_int64), ("nnz_total", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
                 ("col_idx", ctypes.c_void_p), ("weight", ctypes.c_void_p), ("hub_min_degree", ctypes.c_int32),
                 ("hub_offset", ctypes.POINTER(ctypes.c_int64)), ("hub_rows", ctypes.c_void_p),
-                ("max_degree", ctypes.c_int32)]
+                ("max_degree", ctypes.c_int32), ("local_rows", ctypes.c_int32)]
 
 
 class _Params(ctypes.Structure):
@@ -158,6 +158,23 @@ def tune_cache_size() -> int:
 # graphs
 # --------------------------------------------------------------------------
 
+def _local_rows(graph, vtx_offset):
+    """1 when every graph's mean distance |u - v| in the vertex order over its
+    stored entries is below n_g / 64, else 0."""
+    rp = np.asarray(graph.row_ptr, dtype=np.int64)
+    ci = np.asarray(graph.col_idx, dtype=np.int64)
+    if len(ci) == 0:
+        return 0
+    rows = np.repeat(np.arange(len(rp) - 1, dtype=np.int64), np.diff(rp))
+    dist = np.abs(ci - rows).astype(np.float64)
+    for i in range(len(vtx_offset) - 1):
+        lo, hi = int(vtx_offset[i]), int(vtx_offset[i + 1])
+        a, b = int(rp[lo]), int(rp[hi])
+        if b > a and dist[a:b].mean() * 64 >= hi - lo:
+            return 0
+    return 1
+
+
 class DeviceGraph:
     """A canonical CSR (or a block-diagonal batch) resident on the GPU.
 
@@ -165,9 +182,12 @@ class DeviceGraph:
     vtx_offset (int64[G+1]) as numpy arrays.  Rows of degree above
     ``hub_min_degree`` are listed as hubs (their sparse products get
     workgroups of their own); "auto" takes max(128, 8 x mean degree), None
-    lists none.  Results do not depend on it."""
+    lists none.  ``local_rows``: 1 when neighbours are close in the vertex
+    order (rows sharing neighbours then share an XCD's L2), 0 if not, "auto"
+    measures it: 1 when every graph's mean |u - v| over its stored entries
+    is below n_g / 64.  Results depend on neither."""
 
-    def __init__(self, graph, device="cuda", hub_min_degree="auto"):
+    def __init__(self, graph, device="cuda", hub_min_degree="auto", local_rows="auto"):
         self.device = torch.device(device)
         self.n = int(graph.n)
         self.vtx_offset = np.ascontiguousarray(graph.vtx_offset, dtype=np.int64)
@@ -192,6 +212,9 @@ class DeviceGraph:
             if len(hubs):
                 self.hub_offset = np.searchsorted(hubs, self.vtx_offset).astype(np.int64)
                 self.hub_rows = torch.from_numpy(hubs.astype(np.int32)).to(self.device)
+        if local_rows == "auto":
+            local_rows = _local_rows(graph, self.vtx_offset)
+        self.local_rows = int(local_rows)
         self._struct = _Graph(self.num_graphs,
                               self.vtx_offset.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                               self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
@@ -199,7 +222,8 @@ class DeviceGraph:
                               0 if self.hub_offset is None else int(hub_min_degree),
                               None if self.hub_offset is None else
                               self.hub_offset.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                              None if self.hub_rows is None else self.hub_rows.data_ptr(), self.max_degree)
+                              None if self.hub_rows is None else self.hub_rows.data_ptr(), self.max_degree,
+                              self.local_rows)
 
     @property
     def num_hubs(self):

@@ -28,6 +28,11 @@ class Workload:
     rho: float = 0.05
     reset_mode: str = "zero"
     local_search: bool = True
+    momentum: float = 0.0
+    check_every: int = 0
+    init_mode: str = "uniform"
+    init_sigma: float = 0.0
+    final_search: bool = False
     description: str = ""
 
     @property
@@ -64,6 +69,14 @@ def _c5_torus():
     return graphs.torus_pm1(1000, 5001)
 
 
+def _paper_mis():
+    return graphs.erdos_renyi(3000, 100.0 / 2999, 6000)
+
+
+def _paper_maxcut():
+    return graphs.erdos_renyi(1000, 100.0 / 999, 6001)
+
+
 WORKLOADS: Dict[str, Workload] = {
     "er100_mis": Workload(
         "er100_mis", "mis", _c1, batch=1, steps_per_round=1000, rounds=1,
@@ -98,4 +111,20 @@ WORKLOADS: Dict[str, Workload] = {
         alpha=0.01, seed=5001 + 10**6,
         description="1000x1000 torus with +-1 weights, MaxCut f_B, 32 restarts, "
                     "5000 steps in 25 rounds"),
+    # the paper's own hyper-parameters (its ER tables: alpha, momentum, rho,
+    # T_gs) with its algorithm's pieces: degree-based start, momentum, PGA
+    # until a fixed point (checked every 10 steps, at most 200 per round),
+    # T_gs reset rounds, the pair search closing the run; 64 independent chains
+    "er3000_paper_mis": Workload(
+        "er3000_paper_mis", "mis", _paper_mis, batch=64, steps_per_round=200, rounds=61,
+        alpha=0.8, seed=6000 + 10**6, rho=0.6, momentum=0.3, check_every=10, init_mode="degree",
+        init_sigma=0.1, final_search=True,
+        description="ER (n, d) = (3000, 100), MIS h, the paper's alpha 0.8, momentum 0.3, rho 0.6, "
+                    "T_gs = 60, degree start, OneTwoSwap at the end, 64 chains"),
+    "er1000_paper_maxcut": Workload(
+        "er1000_paper_maxcut", "maxcut", _paper_maxcut, batch=64, steps_per_round=200, rounds=91,
+        alpha=0.0025, seed=6001 + 10**6, rho=0.8, momentum=0.8, check_every=10, init_mode="degree",
+        init_sigma=0.1, final_search=True,
+        description="ER (n, d) = (1000, 100), MaxCut f_B, the paper's alpha 0.0025, momentum 0.8, rho 0.8, "
+                    "T_gs = 90, degree start, OneTwoFlip at the end, 64 chains"),
 }

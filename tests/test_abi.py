@@ -251,3 +251,16 @@ def test_tuning_cache_file_round_trip(m, tmp_path):
         m.tune_cache_load(str(tmp_path / "missing.txt"))
     L.mqo_clear_caches()
     assert m.tune_cache_size() == 0
+
+
+def test_local_rows_measured_from_the_vertex_order(m):
+    """The binding's locality hint: a torus (neighbours at +-1 and +-side)
+    is local, a random graph and a star are not."""
+    torus = graphs.torus_pm1(200, 5)
+    er = graphs.erdos_renyi(400, 0.02, 6)
+    star = graphs.star(300)
+    assert m._local_rows(torus, np.asarray(torus.vtx_offset)) == 1
+    assert m._local_rows(er, np.asarray(er.vtx_offset)) == 0
+    assert m._local_rows(star, np.asarray(star.vtx_offset)) == 0
+    both = graphs.concat([graphs.with_weights(er, 7), torus])
+    assert m._local_rows(both, np.asarray(both.vtx_offset)) == 0

@@ -431,6 +431,54 @@ def test_auto_plan_is_tuned_and_cached(mqo, tmp_path, monkeypatch):
     mqo.lib().mqo_clear_caches()
 
 
+@pytest.mark.parametrize("kind", ["mis", "maxcut"])
+@pytest.mark.parametrize("plan", ["batched", "plain"])
+def test_paper_hyperparameters_bit_exact(mqo, kind, plan):
+    """The paper's own settings (its ER tables): MIS alpha 0.8, momentum
+    0.3, rho 0.6; MaxCut alpha 0.0025, momentum 0.8, rho 0.8; a degree-based
+    start (the oracle's, given to both sides: its Gaussian uses log and cos),
+    PGA until a fixed point checked every 10 steps, reset rounds, and the
+    pair search closing the run."""
+    if kind == "mis":
+        g = graphs.erdos_renyi(300, 30.0 / 299, 37)
+        kw = dict(alpha=0.8, mu=0.3, rho=0.6)
+    else:
+        g = graphs.erdos_renyi(200, 20.0 / 199, 38)
+        kw = dict(alpha=0.0025, mu=0.8, rho=0.8)
+    B = 8
+    x0 = pga.init_degree(kind, g.degrees(), np.arange(B), 39, 0.1).astype(np.float32)
+    common = dict(batch=B, steps_per_round=60, rounds=5, seed=39, check_every=10, final_search=True)
+    out = mqo.solve(kind, mqo.DeviceGraph(g, DEV), x0=torch.from_numpy(x0).to(DEV).reshape(-1), plan=plan,
+                    momentum=kw["mu"], alpha=kw["alpha"], rho=kw["rho"], **common)
+    ref = solver.solve(kind, g, solver.Params(**kw, **common), x0=x0)
+    for key in ("traj_best_value", "traj_best_x", "best_value", "best_x"):
+        assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
+    nnz = g.nnz
+    assert out["edge_updates"] == int(ref["traj_steps"].sum()) * nnz
+
+
+@pytest.mark.parametrize("name", ["torus", "er300", "cut_batch"])
+def test_local_rows_hint_keeps_results(mqo, name):
+    """The XCD row-range order (local_rows = 1) and the launch order (0)
+    give the same steps, objective, gradient, adjoint and solves."""
+    kind, g = CASES[name]
+    B = 8
+    X0 = torch.from_numpy(_x(kind, g.n, B, 41)).to(DEV)
+    param = 2.0 if kind == "mis" else 1e-3
+    res = []
+    for lr in (0, 1):
+        dg = mqo.DeviceGraph(g, DEV, local_rows=lr, hub_min_degree=4)
+        X = X0.clone()
+        mqo.pga_steps(kind, dg, X, 3, alpha=0.05)
+        f, gr = mqo.objective_grad(kind, dg, X0, param)
+        XK, ck = mqo.unrolled_forward(kind, dg, X0, 0.05, 4, 2, param)
+        dX, da = mqo.unrolled_backward(kind, dg, ck, torch.ones_like(X0), 0.05, 4, 2, param)
+        out = mqo.solve(kind, dg, plan="batched", batch=B, steps_per_round=10, rounds=2, alpha=0.05, seed=42)
+        res.append([X, f, gr, XK, dX, da, out["traj_best_value"], out["traj_best_x"]])
+    for a, b in zip(*res):
+        assert torch.equal(a, b)
+
+
 def test_two_streams_at_once(mqo):
     """Degree initialisation and objective + gradient queued on two streams
     at the same time, each with its default workspace (one per stream):
