@@ -212,6 +212,11 @@ typedef struct {
   int32_t step_lanes;      /* streaming step kernel: lanes per row, a power of
                               two <= 64, 0 = autotune (every shape computes
                               the same sums in the same order)              */
+  int32_t tile_sb;         /* persistent plan: 1 = two iterate buffers in LDS
+                              (a step reads one, writes the other), 2 = one
+                              buffer (a step gathers into registers, then
+                              writes in place: twice the trajectories per
+                              workgroup fit), 0 = autotune                  */
 } mqo_params;
 
 /* Outputs of a solve.  Device arrays are written; host fields are set. */
@@ -249,6 +254,8 @@ typedef struct {
   int32_t step_vec_used;       /* (host) streaming plans: columns per lane of
                                   the step kernel (0 on the persistent plan) */
   int32_t step_lanes_used;     /* (host) streaming plans: lanes per row       */
+  int32_t tile_single_buffer_used; /* (host) persistent plan: 1 = one iterate
+                                  buffer in LDS                              */
 } mqo_result;
 
 void mqo_params_default(mqo_params *p);

@@ -60,7 +60,7 @@ inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 // persistent-plan shape: trajectories per workgroup, threads, trajectories
 // per lane in the step loop, column indices staged in LDS
 struct TileCfg {
-  int T, threads, vec, csr, dreg, ipt;
+  int T, threads, vec, csr, dreg, ipt, sb;  // sb: one iterate buffer (steps gather into registers first)
 };
 
 struct Resources {
@@ -276,6 +276,7 @@ int check_params(const mqo_params *p, mqo_objective obj) {
     return fail(MQO_ERR_INVALID_ARG, "tile_vec must be 0, 1, 2 or 4");
   if (p->tile_csr < 0 || p->tile_csr > 2) return fail(MQO_ERR_INVALID_ARG, "tile_csr must be 0, 1 or 2");
   if (p->tile_reg < 0 || p->tile_reg > 2) return fail(MQO_ERR_INVALID_ARG, "tile_reg must be 0, 1 or 2");
+  if (p->tile_sb < 0 || p->tile_sb > 2) return fail(MQO_ERR_INVALID_ARG, "tile_sb must be 0, 1 or 2");
   if (p->time_budget_s < 0.0) return fail(MQO_ERR_INVALID_ARG, "time_budget_s must be >= 0");
   return MQO_OK;
 }
@@ -1236,8 +1237,9 @@ int64_t nnz_max_of(const Solve &S) {
 }
 
 bool tile_feasible(const Solve &S, const TileCfg &c) {
-  return tile_shape_ok(S.n_max, c.T, c.threads, c.vec, c.csr != 0, c.dreg, c.ipt) &&
-         (int64_t)tile_lds_bytes(S.n_max, c.T, nnz_max_of(S), c.csr != 0, c.dreg > 0) <= tile_lds_budget();
+  return tile_shape_ok(S.n_max, c.T, c.threads, c.vec, c.csr != 0, c.dreg, c.ipt, c.sb != 0) &&
+         (int64_t)tile_lds_bytes(S.n_max, c.T, nnz_max_of(S), c.csr != 0, c.dreg > 0, c.sb != 0) <=
+             tile_lds_budget();
 }
 
 // any shape at all fits (plan selection)
@@ -1247,7 +1249,8 @@ bool tile_possible(const Solve &S) {
   if (S.p->restart_every > 0) return false;               // fresh starts: streaming plans
   for (int T = 1; T <= 64; T <<= 1)
     for (int th : {256, 512, 1024})
-      if (tile_feasible(S, TileCfg{T, th, 1, 0, 0, 0})) return true;
+      for (int sb = 0; sb < 2; ++sb)
+        if (tile_feasible(S, TileCfg{T, th, 1, 0, 0, 0, sb})) return true;
   return false;
 }
 
@@ -1269,6 +1272,7 @@ TileArgs tile_args(Solve &S, const TileCfg &c, const float *x0) {
   a.csr_lds = c.csr;
   a.dreg = c.dreg;
   a.ipt = c.ipt;
+  a.sb = c.sb;
   a.steps = S.p->steps_per_round;
   a.reset_mode = S.p->reset_mode;
   a.ls = S.p->local_search == MQO_LS_ONE_FLIP;
@@ -1324,8 +1328,11 @@ std::vector<TileCfg> tile_candidates(const Solve &S) {
         for (int csr : {1, 0}) {
           if (S.p->tile_vec && vec != S.p->tile_vec) continue;
           if (S.p->tile_csr && csr != S.p->tile_csr - 1) continue;
-          const TileCfg c{T, th, vec, csr, 0, 0};
-          if (tile_feasible(S, c)) out.push_back(c);
+          for (int sb : {0, 1}) {
+            if (S.p->tile_sb && sb != S.p->tile_sb - 1) continue;
+            const TileCfg c{T, th, vec, csr, 0, 0, sb};
+            if (tile_feasible(S, c)) out.push_back(c);
+          }
         }
     }
   }
@@ -1338,15 +1345,15 @@ std::vector<TileCfg> tile_candidates(const Solve &S) {
 int tune_tile(Solve &S, const float *x0, TileCfg *out, double *ms_per_step = nullptr) {
   Resources &R = res();
   char fixed[64];
-  snprintf(fixed, sizeof(fixed), "|%d|%d|%d|%d|%d|%d", S.p->tile_cols, S.p->tile_threads, S.p->tile_vec,
-           S.p->tile_csr, S.p->tile_reg, S.max_deg);
+  snprintf(fixed, sizeof(fixed), "|%d|%d|%d|%d|%d|%d|%d", S.p->tile_cols, S.p->tile_threads, S.p->tile_vec,
+           S.p->tile_csr, S.p->tile_reg, S.p->tile_sb, S.max_deg);
   const std::string key = "tile|" + R.gpu + "|" + tile_key(S) + fixed;
   std::string cached;
   if (tune_get(key, &cached)) {
     TileCfg c{};
     double ms = 0.0;
-    if (std::sscanf(cached.c_str(), "%d %d %d %d %d %d %lf", &c.T, &c.threads, &c.vec, &c.csr, &c.dreg, &c.ipt,
-                    &ms) == 7 &&
+    if (std::sscanf(cached.c_str(), "%d %d %d %d %d %d %d %lf", &c.T, &c.threads, &c.vec, &c.csr, &c.dreg, &c.ipt,
+                    &c.sb, &ms) == 8 &&
         tile_feasible(S, c)) {
       *out = c;
       if (ms_per_step) *ms_per_step = ms;
@@ -1388,8 +1395,8 @@ int tune_tile(Solve &S, const float *x0, TileCfg *out, double *ms_per_step = nul
     (void)hipEventDestroy(e1);
   }
   char val[128];
-  snprintf(val, sizeof(val), "%d %d %d %d %d %d %.6f", best_c.T, best_c.threads, best_c.vec, best_c.csr, best_c.dreg,
-           best_c.ipt, best_t);
+  snprintf(val, sizeof(val), "%d %d %d %d %d %d %d %.6f", best_c.T, best_c.threads, best_c.vec, best_c.csr,
+           best_c.dreg, best_c.ipt, best_c.sb, best_t);
   tune_put(key, val);
   *out = best_c;
   if (ms_per_step) *ms_per_step = best_t;
@@ -1747,6 +1754,7 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
   r->tile_vec_used = used.vec;
   r->tile_csr_lds_used = used.csr;
   r->tile_reg_degree_used = used.dreg;
+  r->tile_single_buffer_used = used.sb;
   r->ls_iterations = S.ls_iters;
   r->step_kernel_ms = S.timed_ms();
   r->step_kernel_launches = (int64_t)S.timed.size();

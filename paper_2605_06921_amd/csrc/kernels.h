@@ -145,6 +145,7 @@ struct TileArgs {
   int32_t csr_lds;  // stage the graph's columns in LDS (16-bit local ids)
   int32_t dreg;     // > 0: neighbour offsets held in registers, padded to dreg
   int32_t ipt;      // lane items per thread in the register-adjacency path
+  int32_t sb;       // 1: one iterate buffer, steps gather into registers first
   int32_t steps, r0, r1, reset_mode, ls;
   int32_t check_every;  // > 0: early-exit test after every check_every steps of a round
   float alpha, mu, param;
@@ -163,8 +164,8 @@ struct TileArgs {
   int32_t *err;
 };
 
-bool tile_shape_ok(int64_t n_max, int T, int threads, int vec, bool csr_lds, int dreg, int ipt);
-size_t tile_lds_bytes(int64_t n_max, int T, int64_t nnz_max, bool csr_lds, bool state_lds);
+bool tile_shape_ok(int64_t n_max, int T, int threads, int vec, bool csr_lds, int dreg, int ipt, bool sb);
+size_t tile_lds_bytes(int64_t n_max, int T, int64_t nnz_max, bool csr_lds, bool state_lds, bool sb);
 hipError_t launch_tile_round(bool maxcut, bool weighted, const TileArgs &a, int threads, hipStream_t s);
 // Prop. 4.1 toy: mode 0 = single-coordinate global reset, 1 = full restarts
 // (attempts = restarts); n <= 64; x_out [trials][n] or nullptr (mode 0).

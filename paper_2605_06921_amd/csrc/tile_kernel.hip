@@ -10,7 +10,11 @@
 // Step-loop shape (chosen by the autotuner): each lane owns VEC consecutive
 // trajectories of one row (LDS reads of 4*VEC bytes); with CSR_LDS the
 // graph's column indices are staged in LDS as 16-bit local ids so that a
-// step touches no global memory at all.
+// step touches no global memory at all.  With SB (single buffer) the tile
+// is held once: a step gathers into registers (at most SB_ITEMS lane items
+// per thread), then, after a barrier, writes the new iterate in place, so
+// that twice the trajectories fit in LDS -- wider rows of the tile, whose
+// random gathers then meet fewer LDS bank conflicts.
 //
 // Arithmetic per element is identical to the grid kernels (same operation
 // order), so every plan gives bit-identical trajectories.
@@ -22,6 +26,7 @@
 namespace mqo {
 
 constexpr int TILE_MAX_T = 64;
+constexpr int SB_ITEMS = 8;  // lane items per thread of a single-buffered step
 
 template <int VEC>
 __device__ __forceinline__ void lds_load(const float *p, float (&o)[VEC]) {
@@ -51,16 +56,17 @@ __device__ __forceinline__ void lds_store(float *p, const float (&o)[VEC]) {
   }
 }
 
-// Byte offset, in the dynamic LDS, of the end of the iterate buffers, the
+// Byte offset, in the dynamic LDS, of the end of the iterate buffer(s), the
 // graph's row_ptr and (CSR_LDS) its local column ids.
-__host__ __device__ inline size_t tile_state_offset(int64_t n_max, int T, int64_t nnz_max, bool csr_lds) {
+__host__ __device__ inline size_t tile_state_offset(int64_t n_max, int T, int64_t nnz_max, bool csr_lds,
+                                                    bool single_buf = false) {
   const int64_t rowsX = (n_max > 256 ? n_max : 256) + 1;
-  size_t b = (size_t)(2 * rowsX) * T * sizeof(float) + (size_t)(n_max + 1) * sizeof(int32_t);
+  size_t b = (size_t)((single_buf ? 1 : 2) * rowsX) * T * sizeof(float) + (size_t)(n_max + 1) * sizeof(int32_t);
   if (csr_lds) b = ((b + 15) & ~(size_t)15) + (size_t)(nnz_max + 8) * sizeof(uint16_t);
   return (b + 15) & ~(size_t)15;
 }
 
-template <bool MAXCUT, bool WEIGHTED, int VEC, bool CSR_LDS, int DREG, int IPT>
+template <bool MAXCUT, bool WEIGHTED, int VEC, bool CSR_LDS, int DREG, int IPT, bool SB>
 // Four register rows per lane need more than the 128 VGPRs a 1024-thread
 // workgroup leaves, so that variant is built for at most 512 threads.
 __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a) {
@@ -100,18 +106,19 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
   const int32_t rowsX = max(a.n_max, 256) + 1;
   const int32_t zrow = rowsX - 1;
   float *xa = smem;                                                     // [rowsX][T]
-  float *xb = smem + (size_t)rowsX * T;                                 // [rowsX][T]
+  float *xb = SB ? smem : smem + (size_t)rowsX * T;                     // [rowsX][T] (SB: the same buffer)
   int32_t *rps = reinterpret_cast<int32_t *>(xb + (size_t)rowsX * T);  // [n_max+1] row_ptr of the graph
   // [nnz_max + 8] local columns (CSR_LDS), 16-byte aligned for 8-wide reads
-  const size_t cls_off = ((size_t)(2 * rowsX) * T * sizeof(float) + (size_t)(a.n_max + 1) * sizeof(int32_t) + 15) &
-                         ~(size_t)15;
+  const size_t cls_off =
+      ((size_t)((SB ? 1 : 2) * rowsX) * T * sizeof(float) + (size_t)(a.n_max + 1) * sizeof(int32_t) + 15) &
+      ~(size_t)15;
   uint16_t *cls = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(smem) + cls_off);
   // discrete state per (row, trajectory): in LDS after the CSR for the
   // register-adjacency shapes (small tiles), else in the workgroup's region
   // of the global scratch (L2-resident)
   const int64_t sbase = (int64_t)wid * a.n_max * T;
   const int64_t nTmax = (int64_t)a.n_max * T;
-  char *sl = reinterpret_cast<char *>(smem) + tile_state_offset(a.n_max, T, a.nnz_max, CSR_LDS);
+  char *sl = reinterpret_cast<char *>(smem) + tile_state_offset(a.n_max, T, a.nnz_max, CSR_LDS, SB);
   constexpr bool SLDS = DREG > 0;
   int8_t *zs = SLDS ? reinterpret_cast<int8_t *>(sl + 8 * nTmax) : a.zs + sbase;
   int32_t *nb = SLDS ? reinterpret_cast<int32_t *>(sl + 4 * nTmax) : a.nb + sbase;
@@ -327,47 +334,26 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
       }
       if constexpr (DREG == 0) {
         // CHK (compile-time): stopped columns are copied through
-        auto gen_step = [&](auto chk_tag, int32_t st) {
+        // the new iterate of lane item I (VEC trajectories of one row) from src
+        auto item_step = [&](auto chk_tag, const float *src, int32_t I, float (&x)[VEC]) {
           constexpr bool CHK = decltype(chk_tag)::value;
-          const float *src = (st & 1) ? xb : xa;
-          float *dst = (st & 1) ? xa : xb;
-          for (int32_t I = tid; I < nI; I += nthr) {
-            const int32_t L0 = I * VEC;
-            const int32_t v = L0 >> lt, c0 = L0 & (T - 1);
-            const int32_t beg = rps[v], end = rps[v + 1];
-            float acc[VEC];
+          const int32_t L0 = I * VEC;
+          const int32_t v = L0 >> lt, c0 = L0 & (T - 1);
+          const int32_t beg = rps[v], end = rps[v + 1];
+          float acc[VEC];
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
-            if constexpr (CSR_LDS) {
-              // eight local ids per 16-byte LDS read; neighbours still added in
-              // ascending CSR order
-              for (int32_t j0 = beg & ~7; j0 < end; j0 += 8) {
-                const uint4 q = *reinterpret_cast<const uint4 *>(cls + j0);
-                const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
+          for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
+          if constexpr (CSR_LDS) {
+            // eight local ids per 16-byte LDS read; neighbours still added in
+            // ascending CSR order
+            for (int32_t j0 = beg & ~7; j0 < end; j0 += 8) {
+              const uint4 q = *reinterpret_cast<const uint4 *>(cls + j0);
+              const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-                for (int kk = 0; kk < 8; ++kk) {
-                  const int32_t j = j0 + kk;
-                  if (j < beg || j >= end) continue;
-                  const int32_t u = (int32_t)((qw[kk >> 1] >> (16 * (kk & 1))) & 0xffffu);
-                  float xu[VEC];
-                  lds_load<VEC>(src + ((u << lt) | c0), xu);
-                  if (WEIGHTED) {
-                    const float w = (float)wtg[j];
-#pragma unroll
-                    for (int i = 0; i < VEC; ++i) {
-                      const float p = w * xu[i];
-                      acc[i] = acc[i] + p;
-                    }
-                  } else {
-#pragma unroll
-                    for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + xu[i];
-                  }
-                }
-              }
-            } else {
-#pragma unroll 4
-              for (int32_t j = beg; j < end; ++j) {
-                const int32_t u = cig[j] - ilo;
+              for (int kk = 0; kk < 8; ++kk) {
+                const int32_t j = j0 + kk;
+                if (j < beg || j >= end) continue;
+                const int32_t u = (int32_t)((qw[kk >> 1] >> (16 * (kk & 1))) & 0xffffu);
                 float xu[VEC];
                 lds_load<VEC>(src + ((u << lt) | c0), xu);
                 if (WEIGHTED) {
@@ -383,24 +369,67 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
                 }
               }
             }
-            float x[VEC];
-            lds_load<VEC>(src + L0, x);
+          } else {
+#pragma unroll 4
+            for (int32_t j = beg; j < end; ++j) {
+              const int32_t u = cig[j] - ilo;
+              float xu[VEC];
+              lds_load<VEC>(src + ((u << lt) | c0), xu);
+              if (WEIGHTED) {
+                const float w = (float)wtg[j];
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) {
-              const float gr = grad_from_sum<MAXCUT>(acc[i], a.param);
-              float d = gr;
-              if (momentum) {
-                const float t = a.mu * vm[L0 + i];
-                d = t + gr;
-                if (!CHK || s_act[c0 + i]) vm[L0 + i] = d;
+                for (int i = 0; i < VEC; ++i) {
+                  const float p = w * xu[i];
+                  acc[i] = acc[i] + p;
+                }
+              } else {
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + xu[i];
               }
-              const float s = a.alpha * d;
-              const float y = x[i] + s;
-              if (!CHK || s_act[c0 + i]) x[i] = clip_box<MAXCUT>(y);  // else copied through
             }
-            lds_store<VEC>(dst + L0, x);
           }
-          __syncthreads();
+          lds_load<VEC>(src + L0, x);
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) {
+            const float gr = grad_from_sum<MAXCUT>(acc[i], a.param);
+            float d = gr;
+            if (momentum) {
+              const float t = a.mu * vm[L0 + i];
+              d = t + gr;
+              if (!CHK || s_act[c0 + i]) vm[L0 + i] = d;
+            }
+            const float sv = a.alpha * d;
+            const float y = x[i] + sv;
+            if (!CHK || s_act[c0 + i]) x[i] = clip_box<MAXCUT>(y);  // else copied through
+          }
+        };
+        // CHK (compile-time): stopped columns are copied through
+        auto gen_step = [&](auto chk_tag, int32_t st) {
+          if constexpr (SB) {
+            // every item of the thread into registers, then in place
+            float xn[SB_ITEMS][VEC];
+#pragma unroll
+            for (int kq = 0; kq < SB_ITEMS; ++kq) {
+              const int32_t I = tid + kq * nthr;
+              if (I < nI) item_step(chk_tag, xa, I, xn[kq]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int kq = 0; kq < SB_ITEMS; ++kq) {
+              const int32_t I = tid + kq * nthr;
+              if (I < nI) lds_store<VEC>(xa + I * VEC, xn[kq]);
+            }
+            __syncthreads();
+          } else {
+            const float *src = (st & 1) ? xb : xa;
+            float *dst = (st & 1) ? xa : xb;
+            for (int32_t I = tid; I < nI; I += nthr) {
+              float x[VEC];
+              item_step(chk_tag, src, I, x);
+              lds_store<VEC>(dst + I * VEC, x);
+            }
+            __syncthreads();
+          }
         };
         for (int32_t st = done; st < done + len; ++st) {
           if (chk)
@@ -636,11 +665,13 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
   if (tid < cols) a.steps_done[traj0 + tid] += s_cnt[tid];
 }
 
-bool tile_shape_ok(int64_t n_max, int T, int threads, int vec, bool csr_lds, int dreg, int ipt) {
+bool tile_shape_ok(int64_t n_max, int T, int threads, int vec, bool csr_lds, int dreg, int ipt, bool sb) {
   if (!(T >= 1 && T <= TILE_MAX_T && (T & (T - 1)) == 0 && (threads == 256 || threads == 512 || threads == 1024) &&
         n_max >= 1 && n_max * T < (1LL << 30) && (vec == 1 || vec == 2 || vec == 4) && vec <= T &&
         (!csr_lds || n_max <= 65536)))
     return false;
+  // single buffer: every lane item of a step held in registers at once
+  if (sb) return dreg == 0 && n_max * T <= (int64_t)SB_ITEMS * vec * threads;
   if (dreg == 0) return true;
   // register adjacency: one trajectory per lane item, at most ipt items per
   // lane; the shapes below fit the 128-VGPR budget of 1024-thread workgroups
@@ -652,17 +683,17 @@ bool tile_shape_ok(int64_t n_max, int T, int threads, int vec, bool csr_lds, int
          n_max * T <= (int64_t)ipt * threads;
 }
 
-size_t tile_lds_bytes(int64_t n_max, int T, int64_t nnz_max, bool csr_lds, bool state_lds) {
-  size_t b = tile_state_offset(n_max, T, nnz_max, csr_lds);
+size_t tile_lds_bytes(int64_t n_max, int T, int64_t nnz_max, bool csr_lds, bool state_lds, bool sb) {
+  size_t b = tile_state_offset(n_max, T, nnz_max, csr_lds, sb);
   // prio, nb (4 bytes), z, flag (1 byte) per (row, trajectory)
   if (state_lds) b += (size_t)n_max * T * 10;
   return (b + 15) & ~(size_t)15;
 }
 
-template <bool MC, bool W, int VEC, bool CL, int DREG, int IPT>
+template <bool MC, bool W, int VEC, bool CL, int DREG, int IPT, bool SB = false>
 static hipError_t tile_launch_t(const TileArgs &a, int threads, hipStream_t s) {
-  const size_t lds = tile_lds_bytes(a.n_max, a.T, a.nnz_max, CL, DREG > 0);
-  auto kern = k_tile_round<MC, W, VEC, CL, DREG, IPT>;
+  const size_t lds = tile_lds_bytes(a.n_max, a.T, a.nnz_max, CL, DREG > 0, SB);
+  auto kern = k_tile_round<MC, W, VEC, CL, DREG, IPT, SB>;
   // the dynamic-LDS limit only ever grows; raise it when a launch needs more
   // (per device; callers hold the library's host lock)
   static int limit_set[64] = {0};
@@ -696,6 +727,20 @@ static hipError_t tile_launch_mw(const TileArgs &a, int threads, hipStream_t s) 
       default: return tile_launch_reg<MC, 16>(a, threads, s);
     }
   }
+  if (a.sb) {
+    if (a.csr_lds) {
+      switch (a.vec) {
+        case 4: return tile_launch_t<MC, W, 4, true, 0, 1, true>(a, threads, s);
+        case 2: return tile_launch_t<MC, W, 2, true, 0, 1, true>(a, threads, s);
+        default: return tile_launch_t<MC, W, 1, true, 0, 1, true>(a, threads, s);
+      }
+    }
+    switch (a.vec) {
+      case 4: return tile_launch_t<MC, W, 4, false, 0, 1, true>(a, threads, s);
+      case 2: return tile_launch_t<MC, W, 2, false, 0, 1, true>(a, threads, s);
+      default: return tile_launch_t<MC, W, 1, false, 0, 1, true>(a, threads, s);
+    }
+  }
   if (a.csr_lds) {
     switch (a.vec) {
       case 4: return tile_launch_t<MC, W, 4, true, 0, 1>(a, threads, s);
@@ -711,7 +756,8 @@ static hipError_t tile_launch_mw(const TileArgs &a, int threads, hipStream_t s) 
 }
 
 hipError_t launch_tile_round(bool maxcut, bool weighted, const TileArgs &a, int threads, hipStream_t s) {
-  if (!tile_shape_ok(a.n_max, a.T, threads, a.vec, a.csr_lds != 0, a.dreg, a.ipt)) return hipErrorInvalidValue;
+  if (!tile_shape_ok(a.n_max, a.T, threads, a.vec, a.csr_lds != 0, a.dreg, a.ipt, a.sb != 0))
+    return hipErrorInvalidValue;
   if (weighted && a.dreg > 0) return hipErrorInvalidValue;
   if (maxcut) return weighted ? tile_launch_mw<true, true>(a, threads, s) : tile_launch_mw<true, false>(a, threads, s);
   return tile_launch_mw<false, false>(a, threads, s);

@@ -54,7 +54,7 @@ class _Params(ctypes.Structure):
                 ("final_search", ctypes.c_int32), ("pool_k", ctypes.c_int32),
                 ("restart_every", ctypes.c_int32), ("traj_count", ctypes.c_int32),
                 ("traj_ids", ctypes.POINTER(ctypes.c_int64)), ("step_vec", ctypes.c_int32),
-                ("step_lanes", ctypes.c_int32)]
+                ("step_lanes", ctypes.c_int32), ("tile_sb", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -68,7 +68,7 @@ class _Result(ctypes.Structure):
                 ("step_kernel_ms", ctypes.c_double), ("step_kernel_launches", ctypes.c_int64),
                 ("final_search_alternations", ctypes.c_int64), ("pool_x", ctypes.c_void_p),
                 ("pool_value", ctypes.c_void_p), ("step_vec_used", ctypes.c_int32),
-                ("step_lanes_used", ctypes.c_int32)]
+                ("step_lanes_used", ctypes.c_int32), ("tile_single_buffer_used", ctypes.c_int32)]
 
 
 def _load():
@@ -259,7 +259,7 @@ def make_params(batch=1, steps_per_round=200, rounds=1, alpha=0.01, momentum=0.0
                 rho=0.05, init_sigma=0.0, init_mode="uniform", reset_mode="zero", local_search=True,
                 plan="auto", seed=0, time_budget_s=0.0, tile_cols=0, tile_threads=0, tile_vec=0, tile_csr=0,
                 tile_reg=0, check_every=0, final_search=False, pool_k=0, restart_every=0, step_vec=0,
-                step_lanes=0) -> _Params:
+                step_lanes=0, tile_sb=0) -> _Params:
     p = _Params()
     _lib.mqo_params_default(ctypes.byref(p))
     p.batch, p.steps_per_round, p.rounds, p.check_every = batch, steps_per_round, rounds, check_every
@@ -275,6 +275,7 @@ def make_params(batch=1, steps_per_round=200, rounds=1, alpha=0.01, momentum=0.0
     p.pool_k = pool_k
     p.restart_every = restart_every
     p.step_vec, p.step_lanes = step_vec, step_lanes
+    p.tile_sb = tile_sb
     return p
 
 
@@ -356,7 +357,7 @@ def solve(kind, dg: DeviceGraph, x0: Optional[torch.Tensor] = None, workspace: O
                ls_iterations=r.ls_iterations,
                step_kernel_ms=r.step_kernel_ms, step_kernel_launches=r.step_kernel_launches,
                final_search_alternations=r.final_search_alternations, step_vec=r.step_vec_used,
-               step_lanes=r.step_lanes_used)
+               step_lanes=r.step_lanes_used, tile_sb=r.tile_single_buffer_used)
     if want_traj:
         out["traj_best_value"] = traj_v
         out["traj_best_x"] = traj_x.view(dg.n, B)

@@ -78,3 +78,33 @@ def test_register_adjacency_rejected_when_degree_too_high(mqo):
     dg = mqo.DeviceGraph(g, DEV)
     with pytest.raises(mqo.MqoError):
         mqo.solve("mis", dg, batch=4, steps_per_round=5, rounds=1, plan="persistent", tile_reg=2)
+
+
+SB_CASES = {
+    "er_dense": ("mis", graphs.concat([graphs.erdos_renyi(120, 0.2, 25), graphs.erdos_renyi(77, 0.3, 26)])),
+    "cut_w": ("maxcut", graphs.concat([graphs.with_weights(graphs.erdos_renyi(100, 0.15, 27), 28),
+                                       graphs.with_weights(graphs.cycle(40), 29)])),
+}
+
+
+@pytest.mark.parametrize("name", list(SB_CASES))
+@pytest.mark.parametrize("T,vec,csr", [(32, 4, 1), (32, 4, 2), (16, 2, 1), (64, 4, 1), (8, 1, 2)])
+@pytest.mark.parametrize("momentum,check", [(0.0, 0), (0.4, 7)])
+def test_single_buffer_tile_agrees(mqo, name, T, vec, csr, momentum, check):
+    """The single-buffered step (one iterate buffer in LDS, gathers into
+    registers, then in place) forced on: bit-exact against the oracle,
+    with weights, momentum and early exit."""
+    kind, g = SB_CASES[name]
+    B = 40
+    kw = dict(batch=B, steps_per_round=25, rounds=3, alpha=0.02, rho=0.1, seed=6, momentum=momentum,
+              check_every=check)
+    dg = mqo.DeviceGraph(g, DEV)
+    out = mqo.solve(kind, dg, plan="persistent", tile_cols=T, tile_vec=vec, tile_csr=csr, tile_reg=1, tile_sb=2,
+                    **kw)
+    assert out["tile_sb"] == 1 and out["tile_cols"] == T
+    o = solver.solve(kind, g, solver.Params(batch=B, steps_per_round=25, rounds=3, alpha=0.02, rho=0.1, seed=6,
+                                            mu=momentum, check_every=check))
+    for key in ("traj_best_value", "traj_best_x", "best_value"):
+        assert np.array_equal(out[key].cpu().numpy(), o[key]), key
+    nnz_g = np.diff(g.row_ptr[g.vtx_offset])
+    assert out["edge_updates"] == int((o["traj_steps"].reshape(g.num_graphs, -1) * nnz_g[:, None]).sum())
