@@ -196,8 +196,7 @@ typedef struct {
                               Alg. 1-4 -- every round r > 0 with r % R == 0
                               starts from a fresh point of the initialisation
                               rule (Philox round field = r / R) instead of a
-                              reset; incumbents and the pool carry over.
-                              Streaming plans (batched, plain) only         */
+                              reset; incumbents and the pool carry over     */
   int32_t traj_count;      /* plain plan: 0 = every trajectory (default);
                               c > 0: only the c trajectories traj_ids[0..c)
                               run (ids t = g B + b, strictly ascending, each

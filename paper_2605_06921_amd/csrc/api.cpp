@@ -253,8 +253,6 @@ int check_params(const mqo_params *p, mqo_objective obj) {
   if (p->final_search != MQO_FINAL_NONE && p->final_search != MQO_FINAL_PAIR)
     return fail(MQO_ERR_INVALID_ARG, "bad final_search");
   if (p->restart_every < 0) return fail(MQO_ERR_INVALID_ARG, "restart_every must be >= 0");
-  if (p->restart_every > 0 && p->plan == MQO_PLAN_PERSISTENT)
-    return fail(MQO_ERR_UNSUPPORTED, "fresh starts run on the streaming plans (batched, plain)");
   if (p->pool_k < 0 || p->pool_k > 64 || p->pool_k > p->batch)
     return fail(MQO_ERR_INVALID_ARG, "pool_k must be in [0, min(64, batch)]");
   if (p->pool_k > 0 && (p->plan == MQO_PLAN_PERSISTENT || p->plan == MQO_PLAN_PLAIN))
@@ -608,14 +606,15 @@ void write_trace(Solve &S, int plan, int32_t rounds_done, double wall_ms) {
 int k_of(const Solve &S, int64_t n) { return (int)std::floor(S.p->rho * (double)n); }
 
 // initial iterate of every graph into X ([n][B]) unless x0 is given
-int init_x(Solve &S, float *X) {
+// start: index of the fresh start of the outer loop (0 = the first)
+int init_x(Solve &S, float *X, uint64_t start = 0) {
   for (int32_t gi = 0; gi < S.G; ++gi) {
     const GraphView gv = view_of(S.g, gi, S.max_deg);
     if (S.p->init_mode == MQO_INIT_UNIFORM)
-      launch_init_uniform(S.maxcut, X, gv.lo, gv.n, S.B, S.B, S.p->seed, (uint64_t)gi * S.B, S.s);
+      launch_init_uniform(S.maxcut, X, gv.lo, gv.n, S.B, S.B, S.p->seed, (uint64_t)gi * S.B, S.s, start);
     else
       launch_init_degree(S.maxcut, X, S.g->row_ptr, at<int32_t>(S.ws, S.L.dmax), gv.lo, gv.n, S.B, S.B, S.p->seed,
-                         (uint64_t)gi * S.B, S.p->init_sigma, S.s);
+                         (uint64_t)gi * S.B, S.p->init_sigma, S.s, start);
   }
   HIP_TRY(hipGetLastError());
   return MQO_OK;
@@ -1246,7 +1245,6 @@ bool tile_feasible(const Solve &S, const TileCfg &c) {
 bool tile_possible(const Solve &S) {
   if (S.form != OBJ_H && S.form != OBJ_FB) return false;  // the persistent kernel runs h and f_B
   if (S.p->pool_k > 0) return false;                      // the pool needs every trajectory between rounds
-  if (S.p->restart_every > 0) return false;               // fresh starts: streaming plans
   for (int T = 1; T <= 64; T <<= 1)
     for (int th : {256, 512, 1024})
       for (int sb = 0; sb < 2; ++sb)
@@ -1292,6 +1290,7 @@ TileArgs tile_args(Solve &S, const TileCfg &c, const float *x0) {
   a.ls_iters = at<int32_t>(S.ws, S.L.tls);
   a.err = at<int32_t>(S.ws, S.L.err);
   a.check_every = S.p->check_every;
+  a.restart_every = S.p->restart_every;
   a.steps_done = at<int64_t>(S.ws, S.L.steps);
   return a;
 }
@@ -1403,6 +1402,9 @@ int tune_tile(Solve &S, const float *x0, TileCfg *out, double *ms_per_step = nul
   return MQO_OK;
 }
 
+// the launch covers every round of the solve
+bool r0_is_whole(const TileArgs &a, const Solve &S) { return a.r0 == 0 && a.r1 == S.p->rounds; }
+
 int solve_tile(Solve &S, int32_t *rounds_done, TileCfg *used) {
   const float *x0 = S.x0;
   if (!x0) {
@@ -1421,15 +1423,29 @@ int solve_tile(Solve &S, int32_t *rounds_done, TileCfg *used) {
   std::vector<int32_t> lsi;
   int32_t r = 0;
   const bool budget = S.p->time_budget_s > 0.0;
+  const int32_t R = S.p->restart_every;
+  const bool search = S.p->final_search == MQO_FINAL_PAIR;
+  bool searched = false;  // the last round run closed its pass with the search
   const double t0 = now_s();
-  // without a time budget the whole solve is one launch; with one, a launch per round
+  // Without a time budget, fresh starts or searches the whole solve is one
+  // launch.  A budget takes a launch per round; fresh starts (every R
+  // rounds) a launch per pass of the outer loop, whose first round starts
+  // from the initialisation rule written into x0 just before it; the pair
+  // search closing a pass runs between launches.
   for (r = 0; r < S.p->rounds;) {
-    if (r > 0) {
+    if (r > 0 && budget) {
       HIP_TRY(hipStreamSynchronize(S.s));
       if (now_s() - t0 >= S.p->time_budget_s) break;
     }
+    int32_t r1 = budget ? r + 1 : S.p->rounds;
+    if (R > 0) r1 = std::min(r1, (r / R + 1) * R);
+    if (r > 0 && R > 0 && r % R == 0) {
+      float *X = at<float>(S.ws, S.L.X);
+      TRY(init_x(S, X, (uint64_t)(r / R)));
+      a.x0 = X;
+    }
     a.r0 = r;
-    a.r1 = budget ? r + 1 : S.p->rounds;
+    a.r1 = r1;
     hipEvent_t e0;
     TRY(S.begin_timed(&e0));
     hipEvent_t ph = S.phase_begin();
@@ -1438,20 +1454,26 @@ int solve_tile(Solve &S, int32_t *rounds_done, TileCfg *used) {
     S.phase_end(PH_TILE, ph);
     TRY(S.end_timed(e0));
     r = a.r1;
-    if (!budget && nwg < 1019) {
-      // read back with the solve's final synchronisation
-      Resources &R = res();
-      HIP_TRY(hipMemcpyAsync(R.pinned, a.ls_iters, nwg * sizeof(int32_t), hipMemcpyDeviceToHost, S.s));
-      HIP_TRY(hipMemcpyAsync(R.pinned + nwg, at<int32_t>(S.ws, S.L.err), sizeof(int32_t), hipMemcpyDeviceToHost,
+    if (r == S.p->rounds && r0_is_whole(a, S) && nwg < 1019) {
+      // the whole solve in one launch: read back with the final synchronisation
+      Resources &Rs = res();
+      HIP_TRY(hipMemcpyAsync(Rs.pinned, a.ls_iters, nwg * sizeof(int32_t), hipMemcpyDeviceToHost, S.s));
+      HIP_TRY(hipMemcpyAsync(Rs.pinned + nwg, at<int32_t>(S.ws, S.L.err), sizeof(int32_t), hipMemcpyDeviceToHost,
                              S.s));
       S.deferred_tile_wg = nwg;
-      break;
+    } else {
+      TRY(read_back_i32(a.ls_iters, nwg, lsi, S.s));
+      int64_t mx = 0;
+      for (int32_t x : lsi) mx = std::max<int64_t>(mx, x);
+      S.ls_iters += mx;
     }
-    TRY(read_back_i32(a.ls_iters, nwg, lsi, S.s));
-    int64_t mx = 0;
-    for (int32_t x : lsi) mx = std::max<int64_t>(mx, x);
-    S.ls_iters += mx;
+    searched = false;
+    if (search && pass_ends(S, r - 1)) {
+      TRY(search_incumbents(S, search_round(S, r - 1), &S.search_alt));
+      searched = true;
+    }
   }
+  if (search && !searched && r > 0) TRY(search_incumbents(S, search_round(S, r - 1), &S.search_alt));
   if (!S.deferred_tile_wg) {
     std::vector<int32_t> err;
     TRY(read_back_i32(at<int32_t>(S.ws, S.L.err), 1, err, S.s));
@@ -1716,9 +1738,6 @@ int solve_common(const mqo_graph *g, const mqo_params *p, const float *x0, mqo_r
     TRY(solve_batched(S, &rounds_done));
   else
     TRY(solve_plain(S, &rounds_done));
-  // the persistent plan runs one pass (no fresh starts): its search follows
-  if (plan == MQO_PLAN_PERSISTENT && p->final_search == MQO_FINAL_PAIR && rounds_done > 0)
-    TRY(search_incumbents(S, search_round(S, rounds_done - 1), &S.search_alt));
   const int32_t K = p->pool_k;
   const int pool_buf = rounds_done & 1;  // the pool after the last round
   int8_t *PZ = K ? at<int8_t>(ws, L.pz[pool_buf]) : nullptr;

@@ -148,10 +148,11 @@ struct TileArgs {
   int32_t sb;       // 1: one iterate buffer, steps gather into registers first
   int32_t steps, r0, r1, reset_mode, ls;
   int32_t check_every;  // > 0: early-exit test after every check_every steps of a round
+  int32_t restart_every;  // > 0: round r with r % restart_every == 0 starts from x0 (a fresh start)
   float alpha, mu, param;
   double rho;
   uint64_t seed;
-  const float *x0;  // [n_total][B], read when r0 == 0
+  const float *x0;  // [n_total][B], the start of round 0 and of every fresh start
   int8_t *zbest;    // [n_total][B]
   int64_t *best;    // [G*B]
   int8_t *zs;       // private scratch, n_max*T per workgroup

@@ -172,7 +172,9 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
 
   for (int32_t r = a.r0; r < a.r1; ++r) {
     // ------------------------------------------------------------ start point
-    if (r == 0) {
+    // round 0, or a fresh start of the outer loop (the host launches each
+    // pass separately, its start written into x0)
+    if (r == 0 || (a.restart_every > 0 && r % a.restart_every == 0)) {
       for (int32_t L = tid; L < nT; L += nthr) {
         const int32_t v = L >> lt, c = L & (T - 1);
         xa[L] = c < cols ? a.x0[(lo + v) * ldz + b0 + c] : 0.0f;

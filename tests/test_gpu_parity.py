@@ -1065,10 +1065,18 @@ def test_restarts_with_pass_searches_bit_exact(mqo, kind, plan, pool):
     assert out["final_search_alternations"] >= 0
 
 
-def test_restarts_rejected_on_the_persistent_plan(mqo):
-    dg = mqo.DeviceGraph(CASES["reg3"][1], DEV)
-    with pytest.raises(mqo.MqoError) as e:
-        mqo.solve("maxcut", dg, batch=2, steps_per_round=4, rounds=4, restart_every=2, plan="persistent")
-    assert e.value.status == -5
-    out = mqo.solve("maxcut", dg, batch=2, steps_per_round=4, rounds=4, restart_every=2)
-    assert out["plan"] == "batched"
+@pytest.mark.parametrize("kind", ["mis", "maxcut"])
+@pytest.mark.parametrize("search,budget", [(False, 0.0), (True, 0.0), (True, 1e-9)])
+def test_restarts_on_the_persistent_plan(mqo, kind, search, budget):
+    """Fresh starts every R rounds on the persistent plan: one launch per
+    pass of the outer loop, its start written into x0; with final_search the
+    pair search closes each pass between launches; a budget that runs out
+    before round 1 leaves round 0 and the search of its pass."""
+    g = CASES["er_batch"][1] if kind == "mis" else CASES["cut_batch"][1]
+    kw = dict(batch=6, steps_per_round=20, rounds=7, alpha=0.05, rho=0.15, seed=77, restart_every=3,
+              final_search=search)
+    out = mqo.solve(kind, mqo.DeviceGraph(g, DEV), plan="persistent", time_budget_s=budget, **kw)
+    assert out["plan"] == "persistent"
+    ref = solver.solve(kind, g, solver.Params(rounds_run=1 if budget else None, **kw))
+    for key in ("traj_best_value", "traj_best_x", "best_value", "best_x"):
+        assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
