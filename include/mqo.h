@@ -191,7 +191,10 @@ typedef struct {
                               member (MaxCut, Alg. 4, trajectory ids g K +
                               slot, offered to S_sol in slot order and each
                               taken when strictly better).
-                              Batched plan only (MQO_ERR_UNSUPPORTED else)  */
+                              Batched and persistent plans (the persistent
+                              plan launches each round on its own, the pool
+                              updated between launches); the plain plan
+                              returns MQO_ERR_UNSUPPORTED                   */
   int32_t restart_every;   /* 0 = off (default); R > 0: the outer loop of
                               Alg. 1-4 -- every round r > 0 with r % R == 0
                               starts from a fresh point of the initialisation

@@ -255,8 +255,8 @@ int check_params(const mqo_params *p, mqo_objective obj) {
   if (p->restart_every < 0) return fail(MQO_ERR_INVALID_ARG, "restart_every must be >= 0");
   if (p->pool_k < 0 || p->pool_k > 64 || p->pool_k > p->batch)
     return fail(MQO_ERR_INVALID_ARG, "pool_k must be in [0, min(64, batch)]");
-  if (p->pool_k > 0 && (p->plan == MQO_PLAN_PERSISTENT || p->plan == MQO_PLAN_PLAIN))
-    return fail(MQO_ERR_UNSUPPORTED, "the pool couples the trajectories of a graph: batched plan only");
+  if (p->pool_k > 0 && p->plan == MQO_PLAN_PLAIN)
+    return fail(MQO_ERR_UNSUPPORTED, "the pool couples the trajectories of a graph: not on the plain plan");
   if (p->plan < MQO_PLAN_AUTO || p->plan > MQO_PLAN_PERSISTENT) return fail(MQO_ERR_INVALID_ARG, "bad plan");
   if (p->step_vec != 0 && p->step_vec != 1 && p->step_vec != 2 && p->step_vec != 4)
     return fail(MQO_ERR_INVALID_ARG, "step_vec must be 0, 1, 2 or 4");
@@ -1244,7 +1244,6 @@ bool tile_feasible(const Solve &S, const TileCfg &c) {
 // any shape at all fits (plan selection)
 bool tile_possible(const Solve &S) {
   if (S.form != OBJ_H && S.form != OBJ_FB) return false;  // the persistent kernel runs h and f_B
-  if (S.p->pool_k > 0) return false;                      // the pool needs every trajectory between rounds
   for (int T = 1; T <= 64; T <<= 1)
     for (int th : {256, 512, 1024})
       for (int sb = 0; sb < 2; ++sb)
@@ -1424,25 +1423,48 @@ int solve_tile(Solve &S, int32_t *rounds_done, TileCfg *used) {
   int32_t r = 0;
   const bool budget = S.p->time_budget_s > 0.0;
   const int32_t R = S.p->restart_every;
+  const int32_t K = S.p->pool_k;
+  const int32_t B = S.B;
   const bool search = S.p->final_search == MQO_FINAL_PAIR;
   bool searched = false;  // the last round run closed its pass with the search
+  if (K) {
+    launch_fill_i64(at<int64_t>(S.ws, S.L.pv[0]), (int64_t)S.G * K, INT64_MIN, S.s);  // empty pool
+    launch_fill_i64(at<int64_t>(S.ws, S.L.solv), S.G, INT64_MIN, S.s);              // no best set yet
+    launch_fill_i8(at<int8_t>(S.ws, S.L.solz), S.g->n_total, 0, S.s);
+    a.zc = at<int8_t>(S.ws, S.L.Z);  // the round's candidates and values, for the pool
+    a.vc = at<int64_t>(S.ws, S.L.value);
+    a.ldp = K;
+  }
   const double t0 = now_s();
-  // Without a time budget, fresh starts or searches the whole solve is one
-  // launch.  A budget takes a launch per round; fresh starts (every R
-  // rounds) a launch per pass of the outer loop, whose first round starts
-  // from the initialisation rule written into x0 just before it; the pair
-  // search closing a pass runs between launches.
+  // Without a time budget, fresh starts, searches or the pool the whole
+  // solve is one launch.  A budget or the pool (which couples the
+  // trajectories of a graph after every round) takes a launch per round;
+  // fresh starts (every R rounds) a launch per pass of the outer loop, whose
+  // first round starts from the initialisation rule written into x0 just
+  // before it; the pair search closing a pass runs between launches.
   for (r = 0; r < S.p->rounds;) {
     if (r > 0 && budget) {
       HIP_TRY(hipStreamSynchronize(S.s));
       if (now_s() - t0 >= S.p->time_budget_s) break;
     }
-    int32_t r1 = budget ? r + 1 : S.p->rounds;
+    int32_t r1 = budget || K ? r + 1 : S.p->rounds;
     if (R > 0) r1 = std::min(r1, (r / R + 1) * R);
-    if (r > 0 && R > 0 && r % R == 0) {
+    const bool fresh = r > 0 && R > 0 && r % R == 0;
+    if (fresh) {
       float *X = at<float>(S.ws, S.L.X);
       TRY(init_x(S, X, (uint64_t)(r / R)));
       a.x0 = X;
+    }
+    const int cur = r & 1, nxt = cur ^ 1;  // the pool before / after round r
+    a.zp = nullptr;
+    a.base_slot = nullptr;
+    if (K && r > 0 && !fresh) {
+      int32_t *base = at<int32_t>(S.ws, S.L.pbase);
+      for (int32_t gi = 0; gi < S.G; ++gi)
+        launch_pool_bases(at<int64_t>(S.ws, S.L.pv[cur]) + (int64_t)gi * K, K, B, S.p->seed, (uint64_t)gi * B,
+                          (uint64_t)r, base + (int64_t)gi * B, S.s);
+      a.zp = at<int8_t>(S.ws, S.L.pz[cur]);
+      a.base_slot = base;
     }
     a.r0 = r;
     a.r1 = r1;
@@ -1467,13 +1489,38 @@ int solve_tile(Solve &S, int32_t *rounds_done, TileCfg *used) {
       for (int32_t x : lsi) mx = std::max<int64_t>(mx, x);
       S.ls_iters += mx;
     }
+    if (K) {
+      hipEvent_t ph = S.phase_begin();
+      for (int32_t gi = 0; gi < S.G; ++gi) {
+        const GraphView gv = view_of(S.g, gi, S.max_deg);
+        launch_pool_update(S.maxcut, at<int8_t>(S.ws, S.L.Z), B, gv.lo, gv.n, gi, B, K, at<int64_t>(S.ws, S.L.value),
+                           at<unsigned long long>(S.ws, S.L.chash), at<int8_t>(S.ws, S.L.ptaken),
+                           at<int8_t>(S.ws, S.L.pz[cur]), at<int64_t>(S.ws, S.L.pv[cur]),
+                           at<unsigned long long>(S.ws, S.L.ph[cur]), at<int8_t>(S.ws, S.L.pz[nxt]),
+                           at<int64_t>(S.ws, S.L.pv[nxt]), at<unsigned long long>(S.ws, S.L.ph[nxt]),
+                           at<int32_t>(S.ws, S.L.psrc), S.s);
+      }
+      S.phase_end(PH_POOL, ph);
+      offer_pool(S, at<int8_t>(S.ws, S.L.pz[nxt]), at<int64_t>(S.ws, S.L.pv[nxt]));
+    }
     searched = false;
     if (search && pass_ends(S, r - 1)) {
-      TRY(search_incumbents(S, search_round(S, r - 1), &S.search_alt));
+      if (K)
+        TRY(search_pool_pass(S, at<int8_t>(S.ws, S.L.pz[nxt]), at<int64_t>(S.ws, S.L.pv[nxt]),
+                             search_round(S, r - 1), &S.search_alt));
+      else
+        TRY(search_incumbents(S, search_round(S, r - 1), &S.search_alt));
       searched = true;
     }
   }
-  if (search && !searched && r > 0) TRY(search_incumbents(S, search_round(S, r - 1), &S.search_alt));
+  if (search && !searched && r > 0) {  // the time budget cut the last pass short
+    const int last = r & 1;            // the pool after round r - 1
+    if (K)
+      TRY(search_pool_pass(S, at<int8_t>(S.ws, S.L.pz[last]), at<int64_t>(S.ws, S.L.pv[last]),
+                           search_round(S, r - 1), &S.search_alt));
+    else
+      TRY(search_incumbents(S, search_round(S, r - 1), &S.search_alt));
+  }
   if (!S.deferred_tile_wg) {
     std::vector<int32_t> err;
     TRY(read_back_i32(at<int32_t>(S.ws, S.L.err), 1, err, S.s));

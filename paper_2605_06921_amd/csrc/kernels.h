@@ -149,6 +149,14 @@ struct TileArgs {
   int32_t steps, r0, r1, reset_mode, ls;
   int32_t check_every;  // > 0: early-exit test after every check_every steps of a round
   int32_t restart_every;  // > 0: round r with r % restart_every == 0 starts from x0 (a fresh start)
+  // the pmQO pool (launches of one round): the round's candidates out
+  // (zc [n_total][B] with their values vc [G*B]), and the reset of round
+  // r > 0 from pool slot base_slot[t] of zp ([n_total][ldp]) when >= 0
+  int8_t *zc;
+  int64_t *vc;
+  const int8_t *zp;
+  int32_t ldp;
+  const int32_t *base_slot;
   float alpha, mu, param;
   double rho;
   uint64_t seed;

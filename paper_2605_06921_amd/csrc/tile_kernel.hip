@@ -248,7 +248,10 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
         const int32_t v = L >> lt, c = L & (T - 1);
         float x = 0.0f;
         if (c < cols) {
-          const float base = (float)a.zbest[(lo + v) * ldz + b0 + c];
+          // the incumbent, or the pool slot the trajectory restarts from
+          const int32_t bs = a.base_slot ? a.base_slot[traj0 + c] : -1;
+          const float base =
+              (float)(bs >= 0 ? a.zp[(lo + v) * a.ldp + bs] : a.zbest[(lo + v) * ldz + b0 + c]);
           x = base;
           if (k > 0) {
             const uint32_t kk = prio[L];
@@ -655,11 +658,13 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
       const bool take = r == 0 || value > a.best[t];
       s_take[tid] = take ? 1 : 0;
       if (take) a.best[t] = value;
+      if (a.vc) a.vc[t] = value;
     }
     __syncthreads();
     for (int32_t L = tid; L < nT; L += nthr) {
       const int32_t v = L >> lt, c = L & (T - 1);
       if (c < cols && s_take[c]) a.zbest[(lo + v) * ldz + b0 + c] = zs[L];
+      if (c < cols && a.zc) a.zc[(lo + v) * ldz + b0 + c] = zs[L];
     }
     __syncthreads();
   }

@@ -1010,7 +1010,7 @@ def test_pool_solve_bit_exact(mqo, kind, K, B, final):
     g = CASES["er_batch"][1] if kind == "mis" else CASES["cut_batch"][1]
     kw = dict(batch=B, steps_per_round=25, rounds=4, alpha=0.05, rho=0.15, seed=61 + K, pool_k=K,
               final_search=final, reset_mode="flip" if K == 3 else "zero")
-    out = mqo.solve(kind, mqo.DeviceGraph(g, DEV), **kw)
+    out = mqo.solve(kind, mqo.DeviceGraph(g, DEV), plan="batched", **kw)
     assert out["plan"] == "batched"
     ref = solver.solve(kind, g, solver.Params(**kw))
     assert np.array_equal(out["traj_best_value"].cpu().numpy(), ref["traj_best_value"])
@@ -1023,12 +1023,29 @@ def test_pool_solve_bit_exact(mqo, kind, K, B, final):
 
 def test_pool_rejected_where_not_offered(mqo):
     dg = mqo.DeviceGraph(CASES["reg3"][1], DEV)
-    for plan in ("persistent", "plain"):
-        with pytest.raises(mqo.MqoError) as e:
-            mqo.solve("maxcut", dg, batch=4, steps_per_round=4, pool_k=2, plan=plan)
-        assert e.value.status == -5
+    with pytest.raises(mqo.MqoError) as e:
+        mqo.solve("maxcut", dg, batch=4, steps_per_round=4, pool_k=2, plan="plain")
+    assert e.value.status == -5
     with pytest.raises(mqo.MqoError):
         mqo.solve("maxcut", dg, batch=4, steps_per_round=4, pool_k=5)
+
+
+@pytest.mark.parametrize("kind", ["mis", "maxcut"])
+@pytest.mark.parametrize("K,B,final,restart,budget", [(3, 8, False, 0, 0.0), (3, 8, True, 3, 0.0),
+                                                     (8, 8, True, 0, 0.0), (5, 33, True, 2, 0.0),
+                                                     (2, 6, True, 0, 1e-9)])
+def test_pool_on_the_persistent_plan(mqo, kind, K, B, final, restart, budget):
+    """pmQO on the persistent plan: a launch per round writes every
+    trajectory's candidate; the pool, its best set and the pass searches run
+    between launches; bases of the next round's resets come from the pool."""
+    g = CASES["er_batch"][1] if kind == "mis" else CASES["cut_batch"][1]
+    kw = dict(batch=B, steps_per_round=25, rounds=6, alpha=0.05, rho=0.15, seed=91 + K, pool_k=K,
+              final_search=final, restart_every=restart)
+    out = mqo.solve(kind, mqo.DeviceGraph(g, DEV), plan="persistent", time_budget_s=budget, **kw)
+    assert out["plan"] == "persistent"
+    ref = solver.solve(kind, g, solver.Params(rounds_run=1 if budget else None, **kw))
+    for key in ("traj_best_value", "traj_best_x", "pool_value", "pool_x", "best_value", "best_x"):
+        assert np.array_equal(out[key].cpu().numpy(), ref[key]), key
 
 
 # --------------------------------------------------------------------------
