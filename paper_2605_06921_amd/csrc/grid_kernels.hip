@@ -183,7 +183,7 @@ __device__ __forceinline__ void add_neighbour(float (&acc)[VEC], const float (&x
   }
 }
 
-template <int VEC, bool WEIGHTED>
+template <int VEC, bool WEIGHTED, int KB = 4>
 __device__ __forceinline__ void row_gather(const GraphView &g, const float *__restrict__ X, int64_t v, int32_t col,
                                            int32_t ld, int32_t lanes_log2, bool colok, float (&acc)[VEC]) {
 #pragma unroll
@@ -194,8 +194,9 @@ __device__ __forceinline__ void row_gather(const GraphView &g, const float *__re
     const int32_t lane = threadIdx.x & (lanes - 1);
     // batches of KB indices: shuffled out first, then KB gathers issued back
     // to back, then added in order (the shuffles keep a plain loop from
-    // being unrolled, which would leave one gather in flight per lane)
-    constexpr int KB = 4;
+    // being unrolled, which would leave one gather in flight per lane);
+    // 8 in flight suit rows of very uneven degree (graphs with hubs), 4
+    // near-regular ones
     for (int32_t j0 = beg; j0 < end; j0 += lanes) {
       const bool have = j0 + lane < end;
       const int32_t myu = have ? __builtin_nontemporal_load(g.col_idx + j0 + lane) : 0;
@@ -369,7 +370,7 @@ __device__ __forceinline__ bool is_hub_row(const GraphView &g, int64_t v) {
 // neighbour sums.  Every lane of the group must call it.  ROWS = 2 is
 // launched for near-regular graphs only: two rows of equal degree go in
 // lockstep, otherwise one after the other.
-template <int VEC, bool WEIGHTED, int ROWS>
+template <int VEC, bool WEIGHTED, int ROWS, int KB = 4>
 __device__ __forceinline__ void group_gather(const GraphView &g, const float *__restrict__ X, int64_t bx, int32_t by,
                                              int32_t ncols, int32_t ld, int32_t lanes_log2, int64_t (&v)[ROWS],
                                              bool (&own)[ROWS], int32_t &col, float (&acc)[ROWS][VEC]) {
@@ -393,7 +394,7 @@ __device__ __forceinline__ void group_gather(const GraphView &g, const float *__
   }
 #pragma unroll
   for (int k = 0; k < ROWS; ++k)
-    if (own[k]) row_gather<VEC, WEIGHTED>(g, X, v[k], col, ld, lanes_log2, colok, acc[k]);
+    if (own[k]) row_gather<VEC, WEIGHTED, KB>(g, X, v[k], col, ld, lanes_log2, colok, acc[k]);
 }
 
 // One PGA step of Sec. 3 (with optional heavy-ball momentum) for a single column.
@@ -426,7 +427,7 @@ __device__ __forceinline__ void step_update(float &x, float &vv, float acc, floa
 // colact[c] = 0 marks a trajectory that stopped stepping for the rest of
 // the round (early exit): its iterate and momentum are copied through.
 // nullptr = all active.
-template <int VEC, int OBJ, bool WEIGHTED, bool MOMENTUM, int ROWS>
+template <int VEC, int OBJ, bool WEIGHTED, bool MOMENTUM, int ROWS, int KB = 4>
 __global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__restrict__ X, float *__restrict__ Xn,
                                                   float *__restrict__ V, int32_t ncols, int32_t ld,
                                                   int32_t lanes_log2, float alpha, float mu, float param,
@@ -451,7 +452,7 @@ __global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__re
   bool own[ROWS];
   int32_t col;
   float acc[ROWS][VEC];
-  group_gather<VEC, WEIGHTED, ROWS>(g, X, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc);
+  group_gather<VEC, WEIGHTED, ROWS, KB>(g, X, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc);
   if (col >= ncols) return;
 #pragma unroll
   for (int k = 0; k < ROWS; ++k) {
@@ -1824,7 +1825,7 @@ __device__ __forceinline__ void objective_terms(float x, float acc, float W, flo
   }
 }
 
-template <int VEC, int OBJ, bool WEIGHTED, int ROWS>
+template <int VEC, int OBJ, bool WEIGHTED, int ROWS, int KB = 4>
 __global__ __launch_bounds__(256) void k_objective_grad(GraphView g, const float *__restrict__ X,
                                                         const float *__restrict__ scale, float *__restrict__ grad,
                                                         double *__restrict__ part, int32_t ncols, int32_t ld,
@@ -1852,7 +1853,7 @@ __global__ __launch_bounds__(256) void k_objective_grad(GraphView g, const float
   bool own[ROWS];
   int32_t col;
   float acc[ROWS][VEC];
-  group_gather<VEC, WEIGHTED, ROWS>(g, X, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc);
+  group_gather<VEC, WEIGHTED, ROWS, KB>(g, X, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc);
   double fv[VEC];
 #pragma unroll
   for (int i = 0; i < VEC; ++i) fv[i] = 0.0;
@@ -1923,7 +1924,7 @@ __device__ __forceinline__ void adjoint_mu(float x, float ln, float acc, float W
   dv = (double)mu * (double)gr;
 }
 
-template <int VEC, int OBJ, bool WEIGHTED, int ROWS>
+template <int VEC, int OBJ, bool WEIGHTED, int ROWS, int KB = 4>
 __global__ __launch_bounds__(256) void k_adj_mu(GraphView g, const float *__restrict__ Xk,
                                                 const float *__restrict__ lam_next, float *__restrict__ mu_out,
                                                 double *__restrict__ part, int32_t ncols, int32_t ld,
@@ -1951,7 +1952,7 @@ __global__ __launch_bounds__(256) void k_adj_mu(GraphView g, const float *__rest
   bool own[ROWS];
   int32_t col;
   float acc[ROWS][VEC];
-  group_gather<VEC, WEIGHTED, ROWS>(g, Xk, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc);
+  group_gather<VEC, WEIGHTED, ROWS, KB>(g, Xk, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc);
   double dv[VEC];
 #pragma unroll
   for (int i = 0; i < VEC; ++i) dv[i] = 0.0;
@@ -1999,7 +2000,7 @@ __device__ __forceinline__ float adjoint_lambda(float mv, float acc, float W, fl
   return mv + t;
 }
 
-template <int VEC, int OBJ, bool WEIGHTED, int ROWS>
+template <int VEC, int OBJ, bool WEIGHTED, int ROWS, int KB = 4>
 __global__ __launch_bounds__(256) void k_adj_lambda(GraphView g, const float *__restrict__ mu, float *__restrict__ lam,
                                                     int32_t ncols, int32_t ld, int32_t lanes_log2, float alpha,
                                                     float param) {
@@ -2020,7 +2021,7 @@ __global__ __launch_bounds__(256) void k_adj_lambda(GraphView g, const float *__
   bool own[ROWS];
   int32_t col;
   float acc[ROWS][VEC];
-  group_gather<VEC, WEIGHTED, ROWS>(g, mu, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc);
+  group_gather<VEC, WEIGHTED, ROWS, KB>(g, mu, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc);
   if (col >= ncols) return;
 #pragma unroll
   for (int k = 0; k < ROWS; ++k) {
@@ -2145,8 +2146,12 @@ struct StepLaunch {
         return;
       }
     }
-    MQO_LAUNCH((k_pga_step<VEC, OBJ, W, MOMENTUM, 1>), grid, dim3(256), lds, s, g, X, Xn, V, ncols, ld, ll, alpha,
-               mu, param, colact);
+    if (g.nhub > 0)  // uneven degrees: eight gathers in flight per lane group
+      MQO_LAUNCH((k_pga_step<VEC, OBJ, W, MOMENTUM, 1, 8>), grid, dim3(256), lds, s, g, X, Xn, V, ncols, ld, ll,
+                 alpha, mu, param, colact);
+    else
+      MQO_LAUNCH((k_pga_step<VEC, OBJ, W, MOMENTUM, 1>), grid, dim3(256), lds, s, g, X, Xn, V, ncols, ld, ll, alpha,
+                 mu, param, colact);
   }
 };
 
@@ -2525,8 +2530,12 @@ struct ObjLaunch {
         return;
       }
     }
-    MQO_LAUNCH((k_objective_grad<VEC, OBJ, W, 1>), grid, dim3(256), lds, s, g, X, scale, grad, part, ncols, ld, ll,
-               param);
+    if (g.nhub > 0)  // uneven degrees: eight gathers in flight per lane group
+      MQO_LAUNCH((k_objective_grad<VEC, OBJ, W, 1, 8>), grid, dim3(256), lds, s, g, X, scale, grad, part, ncols, ld,
+                 ll, param);
+    else
+      MQO_LAUNCH((k_objective_grad<VEC, OBJ, W, 1>), grid, dim3(256), lds, s, g, X, scale, grad, part, ncols, ld, ll,
+                 param);
   }
 };
 
@@ -2579,6 +2588,13 @@ struct AdjLaunch {
                    param);
         return;
       }
+    }
+    if (g.nhub > 0) {  // uneven degrees: eight gathers in flight per lane group
+      MQO_LAUNCH((k_adj_mu<VEC, OBJ, W, 1, 8>), grid, dim3(256), lds_mu, s, g, Xk, lam_next, mu, part, ncols, ld, ll,
+                 alpha, param);
+      MQO_LAUNCH((k_adj_lambda<VEC, OBJ, W, 1, 8>), grid, dim3(256), lds_lam, s, g, mu, lam, ncols, ld, ll, alpha,
+                 param);
+      return;
     }
     MQO_LAUNCH((k_adj_mu<VEC, OBJ, W, 1>), grid, dim3(256), lds_mu, s, g, Xk, lam_next, mu, part, ncols, ld, ll,
                alpha, param);
