@@ -542,7 +542,7 @@ def main():
                     help="solve: whole batched solves; grad: objective + SpMM gradient over the batch; "
                          "unrolled: K = 20 unrolled PGA steps forward and their adjoint (checkpoints every 5)")
     ap.add_argument("--tile", default="",
-                    help="persistent plan shape T,threads,vec,csr,reg (mqo_params tile_* fields; 0 = autotune)")
+                    help="persistent plan shape T,threads,vec,csr,reg[,sb] (mqo_params tile_* fields; 0 = autotune)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (scale for HBM counters)")
     args = ap.parse_args()
@@ -603,6 +603,8 @@ def main():
     if args.tile:
         t = [int(v) for v in args.tile.split(",")]
         kw.update(tile_cols=t[0], tile_threads=t[1], tile_vec=t[2], tile_csr=t[3], tile_reg=t[4])
+        if len(t) > 5:
+            kw.update(tile_sb=t[5])
     ws = mqo.Workspace(dev)
     for i in range(args.warmup):
         out = mqo.solve(wl.problem, dg, plan=args.plan, workspace=ws, **kw)
@@ -634,7 +636,7 @@ def main():
                            rho=wl.rho, reset_mode=wl.reset_mode, plan=out["plan"], tile_cols=out["tile_cols"],
                            tile_threads=out["tile_threads"], tile_vec=out["tile_vec"],
                            tile_csr_lds=out["tile_csr_lds"], tile_reg_degree=out["tile_reg_degree"],
-                           step_vec=out["step_vec"], step_lanes=out["step_lanes"],
+                           tile_single_buffer=out["tile_sb"], step_vec=out["step_vec"], step_lanes=out["step_lanes"],
                            pool_k=args.pool, final_search=args.final_search, parallelism="dp1"))
 
     # dominant kernel: the launches that run the PGA steps
@@ -646,7 +648,7 @@ def main():
     tile = None
     if out["plan"] == "persistent":
         tile = ",".join(str(out[k]) for k in ("tile_cols", "tile_threads", "tile_vec", "tile_csr_lds",
-                                              "tile_reg_degree"))
+                                              "tile_reg_degree", "tile_sb"))
     traffic = measured_traffic(wl.name, kernel, tile)
     if out["plan"] == "persistent":
         res["roofline"] = dict(bound="hbm", achieved=achieved / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
