@@ -45,6 +45,36 @@ __device__ __forceinline__ void lds_load(const float *p, float (&o)[VEC]) {
   }
 }
 
+// LDS byte addresses as plain 32-bit integers: a neighbour's address is then
+// one shift-and-add of its column id onto a per-lane base (the base folds in
+// the buffer, the lane's trajectory offset and minus the graph's first
+// vertex; the sum wraps modulo 2^32 to the exact in-range address).
+typedef __attribute__((address_space(3))) const float lds_cfloat;
+
+__device__ __forceinline__ uint32_t lds_byte_addr(const float *p) {
+  return (uint32_t)(uintptr_t)(lds_cfloat *)p;
+}
+
+typedef float lds_f2 __attribute__((ext_vector_type(2)));
+typedef float lds_f4 __attribute__((ext_vector_type(4)));
+
+template <int VEC>
+__device__ __forceinline__ void lds_load_addr(uint32_t byte_addr, float (&o)[VEC]) {
+  if constexpr (VEC == 1) {
+    o[0] = *(lds_cfloat *)(uintptr_t)byte_addr;
+  } else if constexpr (VEC == 2) {
+    const lds_f2 t = *(__attribute__((address_space(3))) const lds_f2 *)(uintptr_t)byte_addr;
+    o[0] = t.x;
+    o[1] = t.y;
+  } else {
+    const lds_f4 t = *(__attribute__((address_space(3))) const lds_f4 *)(uintptr_t)byte_addr;
+    o[0] = t.x;
+    o[1] = t.y;
+    o[2] = t.z;
+    o[3] = t.w;
+  }
+}
+
 template <int VEC>
 __device__ __forceinline__ void lds_store(float *p, const float (&o)[VEC]) {
   if constexpr (VEC == 1) {
@@ -348,48 +378,80 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
           float acc[VEC];
 #pragma unroll
           for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
+          // neighbour u's entries at LDS byte (u << (lt + 2)) + ab: ab holds
+          // the buffer, the lane's column c0 and (global column ids) minus
+          // the graph's first vertex
+          const uint32_t sh = (uint32_t)lt + 2u;
+          const uint32_t ab =
+              lds_byte_addr(src) + 4u * (uint32_t)c0 - (CSR_LDS ? 0u : ((uint32_t)ilo << sh));
+          auto add_nbr = [&](int32_t j, int32_t col) {
+            float xu[VEC];
+            lds_load_addr<VEC>(((uint32_t)col << sh) + ab, xu);
+            if (WEIGHTED) {
+              const float w = (float)wtg[j];
+#pragma unroll
+              for (int i = 0; i < VEC; ++i) {
+                const float p = w * xu[i];
+                acc[i] = acc[i] + p;
+              }
+            } else {
+#pragma unroll
+              for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + xu[i];
+            }
+          };
           if constexpr (CSR_LDS) {
-            // eight local ids per 16-byte LDS read; neighbours still added in
-            // ascending CSR order
-            for (int32_t j0 = beg & ~7; j0 < end; j0 += 8) {
+            // eight local ids per 16-byte LDS read, blocks aligned to 8: the
+            // row's first and last blocks masked, full blocks between;
+            // neighbours added in ascending CSR order
+            auto block = [&](int32_t j0, bool masked) {
               const uint4 q = *reinterpret_cast<const uint4 *>(cls + j0);
               const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
               for (int kk = 0; kk < 8; ++kk) {
                 const int32_t j = j0 + kk;
-                if (j < beg || j >= end) continue;
-                const int32_t u = (int32_t)((qw[kk >> 1] >> (16 * (kk & 1))) & 0xffffu);
-                float xu[VEC];
-                lds_load<VEC>(src + ((u << lt) | c0), xu);
-                if (WEIGHTED) {
-                  const float w = (float)wtg[j];
-#pragma unroll
-                  for (int i = 0; i < VEC; ++i) {
-                    const float p = w * xu[i];
-                    acc[i] = acc[i] + p;
-                  }
-                } else {
-#pragma unroll
-                  for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + xu[i];
-                }
+                if (masked && (j < beg || j >= end)) continue;
+                add_nbr(j, (int32_t)((qw[kk >> 1] >> (16 * (kk & 1))) & 0xffffu));
               }
+            };
+            int32_t j0 = beg & ~7;
+            if (j0 < beg && j0 < end) {
+              block(j0, true);
+              j0 += 8;
             }
+            for (; j0 + 8 <= end; j0 += 8) block(j0, false);
+            if (j0 < end) block(j0, true);
           } else {
-#pragma unroll 4
-            for (int32_t j = beg; j < end; ++j) {
-              const int32_t u = cig[j] - ilo;
-              float xu[VEC];
-              lds_load<VEC>(src + ((u << lt) | c0), xu);
-              if (WEIGHTED) {
-                const float w = (float)wtg[j];
+            // ascending CSR order: the first (end - beg) % 4 neighbours one
+            // by one, an odd group of four, then pairs of groups whose column
+            // ids are loaded one group ahead into two register sets in turn
+            // (past the row's end the current pair's first group is loaded
+            // again, in bounds, and not used)
+            int32_t j = beg;
+            for (const int32_t j1 = beg + ((end - beg) & 3); j < j1; ++j) add_nbr(j, cig[j]);
+            if ((end - j) & 4) {
+              int32_t q[4];
 #pragma unroll
-                for (int i = 0; i < VEC; ++i) {
-                  const float p = w * xu[i];
-                  acc[i] = acc[i] + p;
-                }
-              } else {
+              for (int t = 0; t < 4; ++t) q[t] = cig[j + t];
 #pragma unroll
-                for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + xu[i];
+              for (int t = 0; t < 4; ++t) add_nbr(j + t, q[t]);
+              j += 4;
+            }
+            if (j < end) {
+              int32_t qa[4], qb[4];
+#pragma unroll
+              for (int t = 0; t < 4; ++t) qa[t] = cig[j + t];
+              while (true) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) qb[t] = cig[j + 4 + t];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) add_nbr(j + t, qa[t]);
+                const int32_t ja = j + 8 < end ? j + 8 : j;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) qa[t] = cig[ja + t];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) add_nbr(j + 4 + t, qb[t]);
+                j += 8;
+                if (j >= end) break;
               }
             }
           }

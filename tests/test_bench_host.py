@@ -56,4 +56,9 @@ def test_committed_records_name_known_kernels():
         for k, rec in kernels.items():
             assert bench.KERNEL_SOURCES[k] == rec["source"]
             assert rec["hbm_bytes_per_launch"] > 0
-            assert rec["command_fetch"].startswith("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE")
+            # a warm-up run fills the tuning cache, then the counter run
+            assert rec["command_fetch"].startswith("cd /tmp && export TMPDIR=/tmp")
+            assert " && rocprofv3 --pmc FETCH_SIZE -d " in rec["command_fetch"]
+            assert " && rocprofv3 --pmc WRITE_SIZE -d " in rec["command_write"]
+            if k == "k_tile_round":
+                assert len(rec["tile"].split(",")) == 6
