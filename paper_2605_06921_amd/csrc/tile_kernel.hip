@@ -477,7 +477,11 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
             float xn[SB_ITEMS][VEC];
 #pragma unroll
             for (int kq = 0; kq < SB_ITEMS; ++kq) {
-              const int32_t I = tid + kq * nthr;
+              int32_t I = tid + kq * nthr;
+              // opaque per step: keeps the items' row bounds and addresses
+              // from being hoisted out of the step loop (they would hold
+              // the registers the gathers need)
+              __asm__ volatile("" : "+v"(I));
               if (I < nI) item_step(chk_tag, xa, I, xn[kq]);
             }
             __syncthreads();
