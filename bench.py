@@ -533,7 +533,7 @@ def main():
                     help="MaxCut workloads: the formulation of the steps (default f_B, Eq. (7); f_L, f_P, f_A are "
                          "Eq. (4)-(6))")
     ap.add_argument("--pool", type=int, default=0,
-                    help="solve mode: pmQO pool of K solutions per graph (Alg. 3 / 4; batched plan)")
+                    help="solve mode: pmQO pool of K solutions per graph (Alg. 3 / 4)")
     ap.add_argument("--final-search", action="store_true",
                     help="solve mode: the paper's own search on the incumbents (or the pool) after the rounds")
     ap.add_argument("--budgets", default="10,60",
@@ -637,7 +637,7 @@ def main():
                            tile_threads=out["tile_threads"], tile_vec=out["tile_vec"],
                            tile_csr_lds=out["tile_csr_lds"], tile_reg_degree=out["tile_reg_degree"],
                            tile_single_buffer=out["tile_sb"], step_vec=out["step_vec"], step_lanes=out["step_lanes"],
-                           pool_k=args.pool, final_search=args.final_search, parallelism="dp1"))
+                           pool_k=args.pool, final_search=bool(args.final_search or wl.final_search), parallelism="dp1"))
 
     # dominant kernel: the launches that run the PGA steps
     steps_per_launch = wl.steps_per_round * wl.rounds / max(1, out["step_kernel_launches"])
