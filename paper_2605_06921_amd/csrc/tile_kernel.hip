@@ -200,6 +200,78 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
   }
   __syncthreads();
 
+  // The neighbours of row v in the iterate tile at src, VEC columns from c0
+  // on, in ascending CSR order: visit(j, xu) for CSR entry j with the
+  // neighbour's VEC entries (shared by the step's sums and the neighbour
+  // counts of the rounding)
+  auto row_gather = [&](const float *src, int32_t v, int32_t c0, auto &&visit) {
+    const int32_t beg = rps[v], end = rps[v + 1];
+    // neighbour u's entries at LDS byte (u << (lt + 2)) + ab: ab holds the
+    // buffer, the lane's column c0 and (global column ids) minus the
+    // graph's first vertex
+    const uint32_t sh = (uint32_t)lt + 2u;
+    const uint32_t ab = lds_byte_addr(src) + 4u * (uint32_t)c0 - (CSR_LDS ? 0u : ((uint32_t)ilo << sh));
+    auto add_nbr = [&](int32_t j, int32_t col) {
+      float xu[VEC];
+      lds_load_addr<VEC>(((uint32_t)col << sh) + ab, xu);
+      visit(j, xu);
+    };
+    if constexpr (CSR_LDS) {
+      // eight local ids per 16-byte LDS read, blocks aligned to 8: the
+      // row's first and last blocks masked, full blocks between
+      auto block = [&](int32_t j0, bool masked) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(cls + j0);
+        const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+          const int32_t j = j0 + kk;
+          if (masked && (j < beg || j >= end)) continue;
+          add_nbr(j, (int32_t)((qw[kk >> 1] >> (16 * (kk & 1))) & 0xffffu));
+        }
+      };
+      int32_t j0 = beg & ~7;
+      if (j0 < beg && j0 < end) {
+        block(j0, true);
+        j0 += 8;
+      }
+      for (; j0 + 8 <= end; j0 += 8) block(j0, false);
+      if (j0 < end) block(j0, true);
+    } else {
+      // the first (end - beg) % 4 neighbours one by one, an odd group of
+      // four, then pairs of groups whose column ids are loaded one group
+      // ahead into two register sets in turn (past the row's end the
+      // current pair's first group is loaded again, in bounds, and not used)
+      int32_t j = beg;
+      for (const int32_t j1 = beg + ((end - beg) & 3); j < j1; ++j) add_nbr(j, cig[j]);
+      if ((end - j) & 4) {
+        int32_t q[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) q[t] = cig[j + t];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) add_nbr(j + t, q[t]);
+        j += 4;
+      }
+      if (j < end) {
+        int32_t qa[4], qb[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) qa[t] = cig[j + t];
+        while (true) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) qb[t] = cig[j + 4 + t];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) add_nbr(j + t, qa[t]);
+          const int32_t ja = j + 8 < end ? j + 8 : j;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) qa[t] = cig[ja + t];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) add_nbr(j + 4 + t, qb[t]);
+          j += 8;
+          if (j >= end) break;
+        }
+      }
+    }
+  };
+
   for (int32_t r = a.r0; r < a.r1; ++r) {
     // ------------------------------------------------------------ start point
     // round 0, or a fresh start of the outer loop (the host launches each
@@ -374,19 +446,10 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
           constexpr bool CHK = decltype(chk_tag)::value;
           const int32_t L0 = I * VEC;
           const int32_t v = L0 >> lt, c0 = L0 & (T - 1);
-          const int32_t beg = rps[v], end = rps[v + 1];
           float acc[VEC];
 #pragma unroll
           for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
-          // neighbour u's entries at LDS byte (u << (lt + 2)) + ab: ab holds
-          // the buffer, the lane's column c0 and (global column ids) minus
-          // the graph's first vertex
-          const uint32_t sh = (uint32_t)lt + 2u;
-          const uint32_t ab =
-              lds_byte_addr(src) + 4u * (uint32_t)c0 - (CSR_LDS ? 0u : ((uint32_t)ilo << sh));
-          auto add_nbr = [&](int32_t j, int32_t col) {
-            float xu[VEC];
-            lds_load_addr<VEC>(((uint32_t)col << sh) + ab, xu);
+          row_gather(src, v, c0, [&](int32_t j, const float (&xu)[VEC]) {
             if (WEIGHTED) {
               const float w = (float)wtg[j];
 #pragma unroll
@@ -398,63 +461,7 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
 #pragma unroll
               for (int i = 0; i < VEC; ++i) acc[i] = acc[i] + xu[i];
             }
-          };
-          if constexpr (CSR_LDS) {
-            // eight local ids per 16-byte LDS read, blocks aligned to 8: the
-            // row's first and last blocks masked, full blocks between;
-            // neighbours added in ascending CSR order
-            auto block = [&](int32_t j0, bool masked) {
-              const uint4 q = *reinterpret_cast<const uint4 *>(cls + j0);
-              const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-              for (int kk = 0; kk < 8; ++kk) {
-                const int32_t j = j0 + kk;
-                if (masked && (j < beg || j >= end)) continue;
-                add_nbr(j, (int32_t)((qw[kk >> 1] >> (16 * (kk & 1))) & 0xffffu));
-              }
-            };
-            int32_t j0 = beg & ~7;
-            if (j0 < beg && j0 < end) {
-              block(j0, true);
-              j0 += 8;
-            }
-            for (; j0 + 8 <= end; j0 += 8) block(j0, false);
-            if (j0 < end) block(j0, true);
-          } else {
-            // ascending CSR order: the first (end - beg) % 4 neighbours one
-            // by one, an odd group of four, then pairs of groups whose column
-            // ids are loaded one group ahead into two register sets in turn
-            // (past the row's end the current pair's first group is loaded
-            // again, in bounds, and not used)
-            int32_t j = beg;
-            for (const int32_t j1 = beg + ((end - beg) & 3); j < j1; ++j) add_nbr(j, cig[j]);
-            if ((end - j) & 4) {
-              int32_t q[4];
-#pragma unroll
-              for (int t = 0; t < 4; ++t) q[t] = cig[j + t];
-#pragma unroll
-              for (int t = 0; t < 4; ++t) add_nbr(j + t, q[t]);
-              j += 4;
-            }
-            if (j < end) {
-              int32_t qa[4], qb[4];
-#pragma unroll
-              for (int t = 0; t < 4; ++t) qa[t] = cig[j + t];
-              while (true) {
-#pragma unroll
-                for (int t = 0; t < 4; ++t) qb[t] = cig[j + 4 + t];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) add_nbr(j + t, qa[t]);
-                const int32_t ja = j + 8 < end ? j + 8 : j;
-#pragma unroll
-                for (int t = 0; t < 4; ++t) qa[t] = cig[ja + t];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) add_nbr(j + 4 + t, qb[t]);
-                j += 8;
-                if (j >= end) break;
-              }
-            }
-          }
+          });
           lds_load<VEC>(src + L0, x);
 #pragma unroll
           for (int i = 0; i < VEC; ++i) {
@@ -545,8 +552,37 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
     const float *xf = (done & 1) ? xb : xa;
 
     // ------------------------------------------- rounding and neighbour counts
-    for (int32_t L = tid; L < nT; L += nthr) zs[L] = round_x<MAXCUT>(xf[L]);
-    __syncthreads();
+    if constexpr (DREG == 0) {
+      // one pass over the lane items: the item's own entries rounded, its
+      // neighbour counts taken from the rounded neighbours read straight
+      // from the iterate tile in LDS (rounding a neighbour's entry again
+      // gives the same integer the state holds)
+      for (int32_t I = tid; I < nT / VEC; I += nthr) {
+        const int32_t L0 = I * VEC;
+        const int32_t v = L0 >> lt, c0 = L0 & (T - 1);
+        int32_t cnt[VEC];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) cnt[i] = 0;
+        row_gather(xf, v, c0, [&](int32_t j, const float (&xu)[VEC]) {
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) {
+            const int32_t zu = round_x<MAXCUT>(xu[i]);
+            cnt[i] += WEIGHTED ? wtg[j] * zu : zu;
+          }
+        });
+        float x[VEC];
+        lds_load<VEC>(xf + L0, x);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+          zs[L0 + i] = (int8_t)round_x<MAXCUT>(x[i]);
+          nb[L0 + i] = cnt[i];
+        }
+      }
+      __syncthreads();
+    } else {
+      for (int32_t L = tid; L < nT; L += nthr) zs[L] = round_x<MAXCUT>(xf[L]);
+      __syncthreads();
+    }
     // With the degree-3 register adjacency the lane's neighbour items come
     // from its offset registers (item index = offset into xa; the padding
     // points past the last item) instead of the CSR in global memory (wider
@@ -566,7 +602,7 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
           nb[L] = s;
         }
       }
-    } else {
+    } else if constexpr (DREG > 0) {
       for (int32_t L = tid; L < nT; L += nthr) {
         const int32_t v = L >> lt, c = L & (T - 1);
         int32_t s = 0;
