@@ -1653,10 +1653,65 @@ int search_pool_pass(Solve &S, const int8_t *PZ, const int64_t *PV, int32_t rnd,
   return MQO_OK;
 }
 
+// Time a plan on a short copy of the solve: its first min(8, rounds) rounds
+// (round 0 from the start point, then rounds from resets, which early exit
+// and the search shorten differently on the two plans: the persistent plan's
+// workgroups run their rounds independently, the streaming plan's steps wait
+// for the slowest trajectory of each round)
+// without time budget, pool, fresh starts or final search.  Everything the
+// trial writes (incumbents, counters, workspace) the solve writes again; the
+// solve's own counters and trace are left as they were.
+int trial_plan_ms(Solve &S, int plan, double *ms) {
+  mqo_params tp = *S.p;
+  tp.rounds = std::min(8, S.p->rounds);
+  tp.time_budget_s = 0.0;
+  tp.pool_k = 0;
+  tp.restart_every = 0;
+  tp.final_search = MQO_FINAL_NONE;
+  const mqo_params *p0 = S.p;
+  const bool tracing0 = S.tracing;
+  const int64_t ls0 = S.ls_iters, alt0 = S.search_alt;
+  const StepCfg sc0 = S.step_cfg;
+  const size_t timed0 = S.timed.size();
+  S.p = &tp;
+  S.tracing = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int st = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess ? MQO_OK
+                                                                                   : fail(MQO_ERR_HIP, "event create");
+  if (st == MQO_OK) {
+    (void)hipEventRecord(e0, S.s);
+    int32_t rounds_done = 0;
+    TileCfg used{};
+    st = plan == MQO_PLAN_PERSISTENT ? solve_tile(S, &rounds_done, &used) : solve_batched(S, &rounds_done);
+    if (st == MQO_OK) st = settle_deferred(S);
+    (void)hipEventRecord(e1, S.s);
+    if (st == MQO_OK && hipEventSynchronize(e1) != hipSuccess) st = fail(MQO_ERR_HIP, "trial synchronise");
+    float t = 0.0f;
+    if (st == MQO_OK) (void)hipEventElapsedTime(&t, e0, e1);
+    *ms = t;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  for (size_t i = timed0; i < S.timed.size(); ++i) {
+    (void)hipEventDestroy(S.timed[i].first);
+    (void)hipEventDestroy(S.timed[i].second);
+  }
+  S.timed.resize(timed0);
+  S.p = p0;
+  S.tracing = tracing0;
+  S.ls_iters = ls0;
+  S.search_alt = alt0;
+  S.step_cfg = sc0;
+  return st;
+}
+
 // MQO_PLAN_AUTO: the streaming (batched) plan when no persistent tile shape
-// fits, else the faster of the two per PGA step over the whole batch --
-// the best persistent tile shape's round of steps against the best
-// streaming step launch -- timed once per shape key and cached.
+// fits, else the faster of the two: per PGA step over the whole batch (the
+// best persistent tile shape's round of steps against the best streaming
+// step launch) when one is more than twice as fast as the other, else per
+// solve, both plans timed on up to eight rounds of it (the rounds' other work --
+// rounding, search, reset, launches -- then decides).  Timed once per shape
+// key and cached.
 int choose_plan(Solve &S, int *plan) {
   if (!tile_possible(S)) {
     *plan = MQO_PLAN_BATCHED;
@@ -1709,9 +1764,15 @@ int choose_plan(Solve &S, int *plan) {
     if (tuned >= 0.0) step_ms = std::min(step_ms, tuned);
   }
   *plan = step_ms < tile_ms ? MQO_PLAN_BATCHED : MQO_PLAN_PERSISTENT;
-  char val[96];
-  snprintf(val, sizeof(val), "%s %.6f %.6f", *plan == MQO_PLAN_PERSISTENT ? "persistent" : "batched", tile_ms,
-           step_ms);
+  double trial_p = -1.0, trial_b = -1.0;
+  if (step_ms < 2.0 * tile_ms && tile_ms < 2.0 * step_ms) {
+    TRY(trial_plan_ms(S, MQO_PLAN_PERSISTENT, &trial_p));
+    TRY(trial_plan_ms(S, MQO_PLAN_BATCHED, &trial_b));
+    *plan = trial_b < trial_p ? MQO_PLAN_BATCHED : MQO_PLAN_PERSISTENT;
+  }
+  char val[128];
+  snprintf(val, sizeof(val), "%s %.6f %.6f %.3f %.3f", *plan == MQO_PLAN_PERSISTENT ? "persistent" : "batched",
+           tile_ms, step_ms, trial_p, trial_b);
   tune_put(key, val);
   return MQO_OK;
 }

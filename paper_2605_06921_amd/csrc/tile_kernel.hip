@@ -520,26 +520,58 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
       if (done < a.steps) {
         // the early-exit test on the current iterate
         const float *xc = (done & 1) ? xb : xa;
-        for (int32_t L = tid; L < nT; L += nthr) zs[L] = round_x<MAXCUT>(xc[L]);
-        __syncthreads();
-        for (int32_t L = tid; L < nT; L += nthr) {
-          const int32_t v = L >> lt, c = L & (T - 1);
-          if (c >= cols || !s_act[c]) continue;
-          int32_t sum = 0;
-          for (int32_t j = rps[v]; j < rps[v + 1]; ++j) {
-            const int32_t u = CSR_LDS ? (int32_t)cls[j] : cig[j] - ilo;
-            const int32_t zu = zs[(u << lt) | c];
-            sum += WEIGHTED ? wtg[j] * zu : zu;
-          }
-          const int32_t z = zs[L];
-          bool moves;
+        // z_v rounded and sum the (weighted) count of its rounded neighbours;
+        // the column fails when its rounded point moves under a step
+        auto moves = [&](int32_t z, int32_t sum) {
           if (MAXCUT) {
             const int32_t st = z * sum;  // gradient -lambda - 2 t_v, 0 < lambda < 2
-            moves = st > 0 || (st == 0 && z == 1);
+            return st > 0 || (st == 0 && z == 1);
           } else {
-            moves = z ? sum != 0 : sum == 0;  // checker of Eq. (8), gamma > 1
+            return z ? sum != 0 : sum == 0;  // checker of Eq. (8), gamma > 1
           }
-          if (moves) s_viol[c] = 1;
+        };
+        if constexpr (DREG == 0) {
+          // per lane item, the neighbours rounded as read from the tile in
+          // LDS (the gather loop of the steps)
+          for (int32_t I = tid; I < nT / VEC; I += nthr) {
+            const int32_t L0 = I * VEC;
+            const int32_t v = L0 >> lt, c0 = L0 & (T - 1);
+            bool any = false;
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) any |= c0 + i < cols && s_act[c0 + i];
+            if (!any) continue;
+            int32_t cnt[VEC];
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) cnt[i] = 0;
+            row_gather(xc, v, c0, [&](int32_t j, const float (&xu)[VEC]) {
+#pragma unroll
+              for (int i = 0; i < VEC; ++i) {
+                const int32_t zu = round_x<MAXCUT>(xu[i]);
+                cnt[i] += WEIGHTED ? wtg[j] * zu : zu;
+              }
+            });
+            float x[VEC];
+            lds_load<VEC>(xc + L0, x);
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) {
+              const int32_t c = c0 + i;
+              if (c < cols && s_act[c] && moves(round_x<MAXCUT>(x[i]), cnt[i])) s_viol[c] = 1;
+            }
+          }
+        } else {
+          for (int32_t L = tid; L < nT; L += nthr) zs[L] = round_x<MAXCUT>(xc[L]);
+          __syncthreads();
+          for (int32_t L = tid; L < nT; L += nthr) {
+            const int32_t v = L >> lt, c = L & (T - 1);
+            if (c >= cols || !s_act[c]) continue;
+            int32_t sum = 0;
+            for (int32_t j = rps[v]; j < rps[v + 1]; ++j) {
+              const int32_t u = CSR_LDS ? (int32_t)cls[j] : cig[j] - ilo;
+              const int32_t zu = zs[(u << lt) | c];
+              sum += WEIGHTED ? wtg[j] * zu : zu;
+            }
+            if (moves(zs[L], sum)) s_viol[c] = 1;
+          }
         }
         __syncthreads();
         if (tid < T) {

@@ -432,6 +432,30 @@ def test_auto_plan_is_tuned_and_cached(mqo, tmp_path, monkeypatch):
 
 
 @pytest.mark.parametrize("kind", ["mis", "maxcut"])
+def test_auto_plan_trial_leaves_no_trace(mqo, kind):
+    """When the per-step timings are within a factor of two, AUTO times both
+    plans on up to eight rounds of the solve before it runs; the solve that follows
+    reports the same answer and counters as the same plan forced (the
+    trial's writes are all written again), with and without the tuning."""
+    g = graphs.concat([graphs.erdos_renyi(120, 0.1, 61), graphs.erdos_renyi(90, 0.12, 62)])
+    dg = mqo.DeviceGraph(g, DEV)
+    mqo.lib().mqo_clear_caches()
+    kw = dict(batch=24, steps_per_round=30, rounds=3, alpha=0.03, rho=0.1, seed=63, momentum=0.3, check_every=5,
+              final_search=True)
+    first = mqo.solve(kind, dg, **kw)
+    again = mqo.solve(kind, dg, **kw)
+    forced = mqo.solve(kind, dg, plan=first["plan"], **kw)
+    assert again["plan"] == first["plan"]
+    for out in (again, forced):
+        for key in ("traj_best_value", "traj_best_x", "best_value", "best_x"):
+            assert torch.equal(first[key], out[key]), key
+        for key in ("edge_updates", "steps_executed", "rounds_executed", "ls_iterations",
+                    "final_search_alternations"):
+            assert first[key] == out[key], key
+    mqo.lib().mqo_clear_caches()
+
+
+@pytest.mark.parametrize("kind", ["mis", "maxcut"])
 @pytest.mark.parametrize("plan", ["batched", "plain"])
 def test_paper_hyperparameters_bit_exact(mqo, kind, plan):
     """The paper's own settings (its ER tables): MIS alpha 0.8, momentum
