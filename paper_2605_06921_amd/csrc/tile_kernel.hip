@@ -86,13 +86,24 @@ __device__ __forceinline__ void lds_store(float *p, const float (&o)[VEC]) {
   }
 }
 
-// Byte offset, in the dynamic LDS, of the end of the iterate buffer(s), the
-// graph's row_ptr and (CSR_LDS) its local column ids.
-__host__ __device__ inline size_t tile_state_offset(int64_t n_max, int T, int64_t nnz_max, bool csr_lds,
-                                                    bool single_buf = false) {
+// Dynamic LDS, in order: the iterate buffer(s), the graph's row_ptr, (with
+// row order) the rows by descending degree as uint16, (CSR_LDS) the local
+// column ids, (register shapes) the discrete state.  Byte offsets of the
+// row order, the column ids and the state:
+__host__ __device__ inline size_t tile_rord_offset(int64_t n_max, int T, bool single_buf) {
   const int64_t rowsX = (n_max > 256 ? n_max : 256) + 1;
-  size_t b = (size_t)((single_buf ? 1 : 2) * rowsX) * T * sizeof(float) + (size_t)(n_max + 1) * sizeof(int32_t);
-  if (csr_lds) b = ((b + 15) & ~(size_t)15) + (size_t)(nnz_max + 8) * sizeof(uint16_t);
+  const size_t b =
+      (size_t)((single_buf ? 1 : 2) * rowsX) * T * sizeof(float) + (size_t)(n_max + 1) * sizeof(int32_t);
+  return (b + 15) & ~(size_t)15;
+}
+__host__ __device__ inline size_t tile_cls_offset(int64_t n_max, int T, bool single_buf, bool row_order) {
+  const size_t b = tile_rord_offset(n_max, T, single_buf) + (row_order ? (size_t)(n_max + 1) * sizeof(uint16_t) : 0);
+  return (b + 15) & ~(size_t)15;
+}
+__host__ __device__ inline size_t tile_state_offset(int64_t n_max, int T, int64_t nnz_max, bool csr_lds,
+                                                    bool single_buf, bool row_order) {
+  size_t b = tile_cls_offset(n_max, T, single_buf, row_order);
+  if (csr_lds) b += (size_t)(nnz_max + 8) * sizeof(uint16_t);
   return (b + 15) & ~(size_t)15;
 }
 
@@ -138,17 +149,19 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
   float *xa = smem;                                                     // [rowsX][T]
   float *xb = SB ? smem : smem + (size_t)rowsX * T;                     // [rowsX][T] (SB: the same buffer)
   int32_t *rps = reinterpret_cast<int32_t *>(xb + (size_t)rowsX * T);  // [n_max+1] row_ptr of the graph
+  // [n_max + 1] rows by descending degree (the general step loop's lane
+  // items walk rows in this order)
+  constexpr bool ROWORD = DREG == 0;
+  uint16_t *rord = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(smem) + tile_rord_offset(a.n_max, T, SB));
   // [nnz_max + 8] local columns (CSR_LDS), 16-byte aligned for 8-wide reads
-  const size_t cls_off =
-      ((size_t)((SB ? 1 : 2) * rowsX) * T * sizeof(float) + (size_t)(a.n_max + 1) * sizeof(int32_t) + 15) &
-      ~(size_t)15;
-  uint16_t *cls = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(smem) + cls_off);
+  uint16_t *cls =
+      reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(smem) + tile_cls_offset(a.n_max, T, SB, ROWORD));
   // discrete state per (row, trajectory): in LDS after the CSR for the
   // register-adjacency shapes (small tiles), else in the workgroup's region
   // of the global scratch (L2-resident)
   const int64_t sbase = (int64_t)wid * a.n_max * T;
   const int64_t nTmax = (int64_t)a.n_max * T;
-  char *sl = reinterpret_cast<char *>(smem) + tile_state_offset(a.n_max, T, a.nnz_max, CSR_LDS, SB);
+  char *sl = reinterpret_cast<char *>(smem) + tile_state_offset(a.n_max, T, a.nnz_max, CSR_LDS, SB, ROWORD);
   constexpr bool SLDS = DREG > 0;
   int8_t *zs = SLDS ? reinterpret_cast<int8_t *>(sl + 8 * nTmax) : a.zs + sbase;
   int32_t *nb = SLDS ? reinterpret_cast<int32_t *>(sl + 4 * nTmax) : a.nb + sbase;
@@ -199,6 +212,57 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
     }
   }
   __syncthreads();
+
+  if constexpr (ROWORD) {
+    // rows by descending degree: a counting sort over 256 bins of the
+    // degree shifted right until the largest fits (ties in any order: a
+    // row's arithmetic does not depend on the lane that runs it); the tile
+    // is not written yet, so its first 1 KB holds the bins
+    uint32_t *bins = reinterpret_cast<uint32_t *>(xa);
+    if (tid == 0) s_sel_left = 0;
+    for (int32_t h = tid; h < 256; h += nthr) bins[h] = 0u;
+    __syncthreads();
+    for (int32_t v = tid; v < n; v += nthr) atomicMax(&s_sel_left, rps[v + 1] - rps[v]);
+    __syncthreads();
+    int32_t shift = 0;
+    while ((s_sel_left >> shift) > 255) ++shift;
+    auto bin_of = [&](int32_t v) { return 255 - ((rps[v + 1] - rps[v]) >> shift); };
+    for (int32_t v = tid; v < n; v += nthr) atomicAdd(&bins[bin_of(v)], 1u);
+    __syncthreads();
+    if (wave == 0) {  // exclusive scan: four bins per lane, then across the wavefront
+      const int lane = tid & 63;
+      uint32_t c[4], tot = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c[q] = bins[lane * 4 + q];
+        tot += c[q];
+      }
+      uint32_t incl = tot;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+      }
+      uint32_t run = incl - tot;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        bins[lane * 4 + q] = run;
+        run += c[q];
+      }
+    }
+    __syncthreads();
+    for (int32_t v = tid; v < n; v += nthr) rord[atomicAdd(&bins[bin_of(v)], 1u)] = (uint16_t)v;
+    __syncthreads();
+  }
+
+  // lane item I = VEC trajectories (from c0) of row v, the row at slot
+  // I * VEC >> lt of the row order; returns the offset of its entries
+  auto item_pos = [&](int32_t I, int32_t &v, int32_t &c0) {
+    const int32_t L0 = I * VEC;
+    v = ROWORD ? (int32_t)rord[L0 >> lt] : L0 >> lt;
+    c0 = L0 & (T - 1);
+    return (v << lt) | c0;
+  };
 
   // The neighbours of row v in the iterate tile at src, VEC columns from c0
   // on, in ascending CSR order: visit(j, xu) for CSR entry j with the
@@ -444,8 +508,8 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
         // the new iterate of lane item I (VEC trajectories of one row) from src
         auto item_step = [&](auto chk_tag, const float *src, int32_t I, float (&x)[VEC]) {
           constexpr bool CHK = decltype(chk_tag)::value;
-          const int32_t L0 = I * VEC;
-          const int32_t v = L0 >> lt, c0 = L0 & (T - 1);
+          int32_t v, c0;
+          const int32_t L0 = item_pos(I, v, c0);
           float acc[VEC];
 #pragma unroll
           for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
@@ -495,7 +559,8 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
 #pragma unroll
             for (int kq = 0; kq < SB_ITEMS; ++kq) {
               const int32_t I = tid + kq * nthr;
-              if (I < nI) lds_store<VEC>(xa + I * VEC, xn[kq]);
+              int32_t v, c0;
+              if (I < nI) lds_store<VEC>(xa + item_pos(I, v, c0), xn[kq]);
             }
             __syncthreads();
           } else {
@@ -504,7 +569,8 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
             for (int32_t I = tid; I < nI; I += nthr) {
               float x[VEC];
               item_step(chk_tag, src, I, x);
-              lds_store<VEC>(dst + I * VEC, x);
+              int32_t v, c0;
+              lds_store<VEC>(dst + item_pos(I, v, c0), x);
             }
             __syncthreads();
           }
@@ -534,8 +600,8 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
           // per lane item, the neighbours rounded as read from the tile in
           // LDS (the gather loop of the steps)
           for (int32_t I = tid; I < nT / VEC; I += nthr) {
-            const int32_t L0 = I * VEC;
-            const int32_t v = L0 >> lt, c0 = L0 & (T - 1);
+            int32_t v, c0;
+            const int32_t L0 = item_pos(I, v, c0);
             bool any = false;
 #pragma unroll
             for (int i = 0; i < VEC; ++i) any |= c0 + i < cols && s_act[c0 + i];
@@ -590,8 +656,8 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
       // from the iterate tile in LDS (rounding a neighbour's entry again
       // gives the same integer the state holds)
       for (int32_t I = tid; I < nT / VEC; I += nthr) {
-        const int32_t L0 = I * VEC;
-        const int32_t v = L0 >> lt, c0 = L0 & (T - 1);
+        int32_t v, c0;
+        const int32_t L0 = item_pos(I, v, c0);
         int32_t cnt[VEC];
 #pragma unroll
         for (int i = 0; i < VEC; ++i) cnt[i] = 0;
@@ -825,7 +891,7 @@ bool tile_shape_ok(int64_t n_max, int T, int threads, int vec, bool csr_lds, int
 }
 
 size_t tile_lds_bytes(int64_t n_max, int T, int64_t nnz_max, bool csr_lds, bool state_lds, bool sb) {
-  size_t b = tile_state_offset(n_max, T, nnz_max, csr_lds, sb);
+  size_t b = tile_state_offset(n_max, T, nnz_max, csr_lds, sb, !state_lds);
   // prio, nb (4 bytes), z, flag (1 byte) per (row, trajectory)
   if (state_lds) b += (size_t)n_max * T * 10;
   return (b + 15) & ~(size_t)15;
