@@ -290,8 +290,8 @@ int64_t max_graph_rows(const mqo_graph *g) {
 // ---------------------------------------------------------------------------
 struct Layout {
   size_t X, Xt, V, Z, Zb, NB, PRIO, F, value, best, acc, act, voff, rpat, bestb, dmax, err, reset, tzs, tnb, tprio,
-      tfl, tvm, tls, pX, pXt, pV, colact, fixedc, steps, pz[2], pv[2], ph[2], chash, ptaken, psrc, pbase, solz, solv,
-      choice, total;
+      tfl, tvm, tls, gorder, pX, pXt, pV, colact, fixedc, steps, pz[2], pv[2], ph[2], chash, ptaken, psrc, pbase,
+      solz, solv, choice, total;
 };
 
 // K: pool slots per graph (0 = no pool); the pool buffers come last, so the
@@ -330,6 +330,7 @@ Layout make_layout(const mqo_graph *g, int32_t B, int32_t K = 0) {
   L.tfl = take(tiles_elems);
   L.tvm = take(tiles_elems * 4);
   L.tls = take(G * (int64_t)(B + 63) * 4);
+  L.gorder = take(G * 4);  // persistent plan: graphs in launch order
   L.pX = take(n * 4);  // plain plan: one trajectory as contiguous vectors
   L.pXt = take(n * 4);
   L.pV = take(n * 4);
@@ -496,6 +497,7 @@ struct Solve {
   int64_t search_alt = 0;  // pair iterations that applied a move, summed over the pass searches
   StepCfg step_cfg{0, 0};  // streaming plans: the step kernel's launch shape (of the first loop)
   int32_t deferred_tile_wg = 0;  // > 0: the tile counters sit in the pinned buffer after the final sync
+  std::vector<int32_t> gorder;   // persistent plan: graphs in launch order (uploaded once, G > 1)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;  // around the step launches
   // MQO_TRACE: HIP events around every phase of the solve, on its stream
   bool tracing = false;
@@ -1251,8 +1253,38 @@ bool tile_possible(const Solve &S) {
   return false;
 }
 
+// The persistent plan's launch order of the graphs: largest (stored
+// entries) first, so that the last workgroups a CU takes are short ones.
+// When the graphs split evenly over the 8 XCDs (an XCD takes a contiguous
+// range of graph slots, see the kernel's placement), the sorted graphs are
+// dealt to the ranges in snake order, so every XCD gets a like share of the
+// work, each range again largest first.  Uploaded once per solve.
+int tile_graph_order(Solve &S) {
+  if (S.G <= 1 || !S.gorder.empty()) return MQO_OK;
+  const int32_t G = S.G;
+  std::vector<int32_t> idx(G);
+  for (int32_t i = 0; i < G; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return S.nnz_g[x] > S.nnz_g[y]; });
+  std::vector<int32_t> o(G);
+  if (G % 8 == 0) {
+    const int32_t per = G / 8;
+    int32_t fill[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int32_t i = 0; i < G; ++i) {
+      const int32_t pos = i % 8, bin = ((i / 8) & 1) ? 7 - pos : pos;
+      o[bin * per + fill[bin]++] = idx[i];
+    }
+  } else {
+    o = idx;
+  }
+  HIP_TRY(hipMemcpyAsync(at<int32_t>(S.ws, S.L.gorder), o.data(), (size_t)G * sizeof(int32_t), hipMemcpyHostToDevice,
+                         S.s));
+  S.gorder = std::move(o);  // kept until the solve ends
+  return MQO_OK;
+}
+
 TileArgs tile_args(Solve &S, const TileCfg &c, const float *x0) {
   TileArgs a{};
+  a.gorder = S.gorder.empty() ? nullptr : at<int32_t>(S.ws, S.L.gorder);
   a.row_ptr = S.g->row_ptr;
   a.col_idx = S.g->col_idx;
   a.weight = S.g->weight;
@@ -1341,6 +1373,7 @@ std::vector<TileCfg> tile_candidates(const Solve &S) {
 // candidate computes bit-identical results, so this only affects speed.
 // ms_per_step (or nullptr): the chosen shape's time per PGA step.
 int tune_tile(Solve &S, const float *x0, TileCfg *out, double *ms_per_step = nullptr) {
+  TRY(tile_graph_order(S));
   Resources &R = res();
   char fixed[64];
   snprintf(fixed, sizeof(fixed), "|%d|%d|%d|%d|%d|%d|%d", S.p->tile_cols, S.p->tile_threads, S.p->tile_vec,
@@ -1405,6 +1438,7 @@ int tune_tile(Solve &S, const float *x0, TileCfg *out, double *ms_per_step = nul
 bool r0_is_whole(const TileArgs &a, const Solve &S) { return a.r0 == 0 && a.r1 == S.p->rounds; }
 
 int solve_tile(Solve &S, int32_t *rounds_done, TileCfg *used) {
+  TRY(tile_graph_order(S));
   const float *x0 = S.x0;
   if (!x0) {
     float *X = at<float>(S.ws, S.L.X);

@@ -138,6 +138,9 @@ struct TileArgs {
   const int32_t *col_idx;
   const int32_t *weight;
   const int64_t *vtx_off;  // device [G+1]
+  // device [G]: the graph of each graph slot of the launch order (nullptr:
+  // slot g is graph g)
+  const int32_t *gorder;
   int32_t G, B, T, log2T, tiles;
   int32_t n_max;    // scratch stride (rows)
   int32_t nnz_max;  // largest graph's stored entries

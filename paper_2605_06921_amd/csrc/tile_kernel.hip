@@ -129,7 +129,7 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
   const int32_t nwg = a.G * a.tiles;
   int32_t wid = blockIdx.x;
   if ((nwg & 7) == 0) wid = (int32_t)(blockIdx.x & 7) * (nwg >> 3) + (int32_t)(blockIdx.x >> 3);
-  const int32_t g = wid / a.tiles, tile = wid % a.tiles;
+  const int32_t g = a.gorder ? a.gorder[wid / a.tiles] : wid / a.tiles, tile = wid % a.tiles;
   const int64_t lo = a.vtx_off[g];
   const int32_t n = (int32_t)(a.vtx_off[g + 1] - lo);
   const int32_t T = a.T, lt = a.log2T;
