@@ -158,7 +158,9 @@ typedef struct {
   double time_budget_s;    /* 0 = none; otherwise no round r > 0 starts after
                               it (round 0 of every trajectory always runs, so
                               every incumbent is written); the pass it cuts
-                              short still ends with the final_search         */
+                              short still ends with the final_search.  The
+                              clock starts at the first round, after any
+                              autotuning or plan trial (MQO_PLAN_AUTO)       */
   int32_t maxcut_objective; /* mqo_solve_maxcut: MQO_OBJ_MAXCUT_FB (default),
                               _FL, _FP or _FA                                  */
   int32_t final_search;    /* MQO_FINAL_NONE (default) or MQO_FINAL_PAIR: the

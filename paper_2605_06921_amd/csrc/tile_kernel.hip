@@ -875,7 +875,7 @@ __global__ __launch_bounds__(IPT >= 4 ? 512 : 1024) void k_tile_round(TileArgs a
 bool tile_shape_ok(int64_t n_max, int T, int threads, int vec, bool csr_lds, int dreg, int ipt, bool sb) {
   if (!(T >= 1 && T <= TILE_MAX_T && (T & (T - 1)) == 0 && (threads == 256 || threads == 512 || threads == 1024) &&
         n_max >= 1 && n_max * T < (1LL << 30) && (vec == 1 || vec == 2 || vec == 4) && vec <= T &&
-        (!csr_lds || n_max <= 65536)))
+        (!csr_lds || n_max <= 65536) && (dreg > 0 || n_max <= 65536)))  // uint16 local ids / row order
     return false;
   // single buffer: every lane item of a step held in registers at once
   if (sb) return dreg == 0 && n_max * T <= (int64_t)SB_ITEMS * vec * threads;
