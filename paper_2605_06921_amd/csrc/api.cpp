@@ -290,8 +290,8 @@ int64_t max_graph_rows(const mqo_graph *g) {
 // ---------------------------------------------------------------------------
 struct Layout {
   size_t X, Xt, V, Z, Zb, NB, PRIO, F, value, best, acc, act, voff, rpat, bestb, dmax, err, reset, tzs, tnb, tprio,
-      tfl, tvm, tls, gorder, pX, pXt, pV, colact, fixedc, steps, pz[2], pv[2], ph[2], chash, ptaken, psrc, pbase,
-      solz, solv, choice, total;
+      tfl, tvm, tls, gorder, lsval, pX, pXt, pV, colact, fixedc, steps, pz[2], pv[2], ph[2], chash, ptaken, psrc,
+      pbase, solz, solv, choice, total;
 };
 
 // K: pool slots per graph (0 = no pool); the pool buffers come last, so the
@@ -331,6 +331,7 @@ Layout make_layout(const mqo_graph *g, int32_t B, int32_t K = 0) {
   L.tvm = take(tiles_elems * 4);
   L.tls = take(G * (int64_t)(B + 63) * 4);
   L.gorder = take(G * 4);  // persistent plan: graphs in launch order
+  L.lsval = take((size_t)B * 8);  // the 1-flip search's discarded values (not the round's)
   L.pX = take(n * 4);  // plain plan: one trajectory as contiguous vectors
   L.pXt = take(n * 4);
   L.pV = take(n * 4);
@@ -343,7 +344,7 @@ Layout make_layout(const mqo_graph *g, int32_t B, int32_t K = 0) {
     L.ph[i] = take(G * K * 8);
   }
   L.chash = take(K ? G * B * 8 : 0);
-  L.ptaken = take(K ? K + B : 0);
+  L.ptaken = take(K ? G * (K + B) : 0);
   L.psrc = take(G * K * 4);
   L.pbase = take(K ? G * B * 4 : 0);
   L.solz = take(K ? n : 0);  // the pool modes' best set (I_sol / S_sol) and its value
@@ -792,7 +793,7 @@ int pair_core(bool maxcut, const mqo_graph *g, const PairCols &pc, uint64_t seed
 int run_local_search(Solve &S, const GraphView &gv, int8_t *Z, int32_t *NB, uint32_t *PRIO, int8_t *F, int32_t ncols,
                      int32_t ld, uint64_t traj0, int32_t round, int64_t *iters_out) {
   return ls_core(S.maxcut, gv, S.g->nnz_total, mean_degree_of(S.g), S.p->seed, round, Z, NB, PRIO, F,
-                 at<int32_t>(S.ws, S.L.act), at<long long>(S.ws, S.L.acc), at<int64_t>(S.ws, S.L.value), ncols, ld,
+                 at<int32_t>(S.ws, S.L.act), at<long long>(S.ws, S.L.acc), at<int64_t>(S.ws, S.L.lsval), ncols, ld,
                  traj0, S.s, iters_out);
 }
 
@@ -1102,6 +1103,9 @@ int solve_batched(Solve &S, int32_t *rounds_done) {
       if (now_s() - t0 >= S.p->time_budget_s) break;
     }
     const int cur = r & 1, nxt = cur ^ 1;
+    if (K && r > 0)
+      launch_pool_bases(at<int64_t>(S.ws, S.L.pv[cur]), K, S.G, B, S.p->seed, (uint64_t)r,
+                        at<int32_t>(S.ws, S.L.pbase), S.s);
     for (int32_t gi = 0; gi < S.G; ++gi) {
       const GraphView gv = view_of(S.g, gi, S.max_deg);
       const int64_t t = (int64_t)gi * B;
@@ -1110,8 +1114,6 @@ int solve_batched(Solve &S, int32_t *rounds_done) {
       if (K && r > 0) {
         Zp = at<int8_t>(S.ws, S.L.pz[cur]);
         base = at<int32_t>(S.ws, S.L.pbase) + t;
-        launch_pool_bases(at<int64_t>(S.ws, S.L.pv[cur]) + (int64_t)gi * K, K, B, S.p->seed, (uint64_t)t,
-                          (uint64_t)r, base, S.s);
       }
       round_start(S, gv, r, X, V, Zb, B, B, B, (uint64_t)t, Zp, K, base);
       if (!whole)
@@ -1124,13 +1126,15 @@ int solve_batched(Solve &S, int32_t *rounds_done) {
       const GraphView gv = view_of(S.g, gi, S.max_deg);
       const int64_t t = (int64_t)gi * B;
       TRY(round_finish(S, gv, r, X, Z, Zb, B, NB, PRIO, F, value + t, best + t, B, B, (uint64_t)t));
-      hipEvent_t ph = K ? S.phase_begin() : nullptr;
-      if (K)
-        launch_pool_update(S.maxcut, Z, B, gv.lo, gv.n, gi, B, K, value, at<unsigned long long>(S.ws, S.L.chash),
-                           at<int8_t>(S.ws, S.L.ptaken), at<int8_t>(S.ws, S.L.pz[cur]),
-                           at<int64_t>(S.ws, S.L.pv[cur]), at<unsigned long long>(S.ws, S.L.ph[cur]),
-                           at<int8_t>(S.ws, S.L.pz[nxt]), at<int64_t>(S.ws, S.L.pv[nxt]),
-                           at<unsigned long long>(S.ws, S.L.ph[nxt]), at<int32_t>(S.ws, S.L.psrc), S.s);
+    }
+    if (K) {
+      hipEvent_t ph = S.phase_begin();
+      launch_pool_update(S.maxcut, Z, B, at<int64_t>(S.ws, S.L.voff), S.G, S.g->n_total, B, K, value,
+                         at<unsigned long long>(S.ws, S.L.chash), at<int8_t>(S.ws, S.L.ptaken),
+                         at<int8_t>(S.ws, S.L.pz[cur]), at<int64_t>(S.ws, S.L.pv[cur]),
+                         at<unsigned long long>(S.ws, S.L.ph[cur]), at<int8_t>(S.ws, S.L.pz[nxt]),
+                         at<int64_t>(S.ws, S.L.pv[nxt]), at<unsigned long long>(S.ws, S.L.ph[nxt]),
+                         at<int32_t>(S.ws, S.L.psrc), S.s);
       S.phase_end(PH_POOL, ph);
     }
     if (K) offer_pool(S, at<int8_t>(S.ws, S.L.pz[nxt]), at<int64_t>(S.ws, S.L.pv[nxt]));
@@ -1494,9 +1498,7 @@ int solve_tile(Solve &S, int32_t *rounds_done, TileCfg *used) {
     a.base_slot = nullptr;
     if (K && r > 0 && !fresh) {
       int32_t *base = at<int32_t>(S.ws, S.L.pbase);
-      for (int32_t gi = 0; gi < S.G; ++gi)
-        launch_pool_bases(at<int64_t>(S.ws, S.L.pv[cur]) + (int64_t)gi * K, K, B, S.p->seed, (uint64_t)gi * B,
-                          (uint64_t)r, base + (int64_t)gi * B, S.s);
+      launch_pool_bases(at<int64_t>(S.ws, S.L.pv[cur]), K, S.G, B, S.p->seed, (uint64_t)r, base, S.s);
       a.zp = at<int8_t>(S.ws, S.L.pz[cur]);
       a.base_slot = base;
     }
@@ -1525,15 +1527,12 @@ int solve_tile(Solve &S, int32_t *rounds_done, TileCfg *used) {
     }
     if (K) {
       hipEvent_t ph = S.phase_begin();
-      for (int32_t gi = 0; gi < S.G; ++gi) {
-        const GraphView gv = view_of(S.g, gi, S.max_deg);
-        launch_pool_update(S.maxcut, at<int8_t>(S.ws, S.L.Z), B, gv.lo, gv.n, gi, B, K, at<int64_t>(S.ws, S.L.value),
-                           at<unsigned long long>(S.ws, S.L.chash), at<int8_t>(S.ws, S.L.ptaken),
-                           at<int8_t>(S.ws, S.L.pz[cur]), at<int64_t>(S.ws, S.L.pv[cur]),
-                           at<unsigned long long>(S.ws, S.L.ph[cur]), at<int8_t>(S.ws, S.L.pz[nxt]),
-                           at<int64_t>(S.ws, S.L.pv[nxt]), at<unsigned long long>(S.ws, S.L.ph[nxt]),
-                           at<int32_t>(S.ws, S.L.psrc), S.s);
-      }
+      launch_pool_update(S.maxcut, at<int8_t>(S.ws, S.L.Z), B, at<int64_t>(S.ws, S.L.voff), S.G, S.g->n_total, B, K,
+                         at<int64_t>(S.ws, S.L.value), at<unsigned long long>(S.ws, S.L.chash),
+                         at<int8_t>(S.ws, S.L.ptaken), at<int8_t>(S.ws, S.L.pz[cur]), at<int64_t>(S.ws, S.L.pv[cur]),
+                         at<unsigned long long>(S.ws, S.L.ph[cur]), at<int8_t>(S.ws, S.L.pz[nxt]),
+                         at<int64_t>(S.ws, S.L.pv[nxt]), at<unsigned long long>(S.ws, S.L.ph[nxt]),
+                         at<int32_t>(S.ws, S.L.psrc), S.s);
       S.phase_end(PH_POOL, ph);
       offer_pool(S, at<int8_t>(S.ws, S.L.pz[nxt]), at<int64_t>(S.ws, S.L.pv[nxt]));
     }

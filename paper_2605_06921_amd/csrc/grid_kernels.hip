@@ -1440,24 +1440,52 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   return z ^ (z >> 31);
 }
 
-// H[c] += sum over the rows v of [lo, lo + n) with Z[v][c] > 0 of
-// splitmix64(v - lo), mod 2^64 (H cleared by the caller).  Thread per
-// (chunk of 256 rows, column); the additions commute, so the sum is exact.
-__global__ __launch_bounds__(256) void k_col_hash(const int8_t *__restrict__ Z, int64_t lo, int64_t n, int32_t ncols,
-                                                  int32_t ld, unsigned long long *__restrict__ H) {
+// The graph of batch row v: the last g with vtx_off[g] <= v (0 <= v < n_total).
+__device__ __forceinline__ int32_t graph_of_row(const int64_t *__restrict__ vtx_off, int32_t G, int64_t v) {
+  int32_t lo = 0, hi = G;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (vtx_off[mid] <= v)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// H[g][c] += sum over the rows v of graph g with Z[v][c] > 0 of
+// splitmix64(v - lo_g), mod 2^64, for every graph of the batch (H cleared by
+// the caller).  Thread per (chunk of 256 batch rows, column): long enough
+// that few atomics meet on one column of a large graph; a chunk that runs
+// into the next graph adds each part to its own graph.  The additions
+// commute, so the sums are exact.
+__global__ __launch_bounds__(256) void k_col_hash(const int8_t *__restrict__ Z, const int64_t *__restrict__ vtx_off,
+                                                  int32_t G, int64_t n_total, int32_t ncols, int32_t ld,
+                                                  unsigned long long *__restrict__ H) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t chunks = (n + 255) >> 8;
+  const int64_t chunks = (n_total + 255) >> 8;
   if (idx >= chunks * ncols) return;
   const int32_t c = (int32_t)(idx % ncols);
   const int64_t r0 = (idx / ncols) << 8;
-  const int64_t r1 = r0 + 256 < n ? r0 + 256 : n;
+  const int64_t r1 = r0 + 256 < n_total ? r0 + 256 : n_total;
+  int32_t g = graph_of_row(vtx_off, G, r0);
+  int64_t base = vtx_off[g], end = vtx_off[g + 1];
   uint64_t h = 0;
-  for (int64_t v = r0; v < r1; ++v)
-    if (Z[(lo + v) * ld + c] > 0) h += splitmix64((uint64_t)v);
-  if (h) atomicAdd(H + c, (unsigned long long)h);
+  for (int64_t v = r0; v < r1; ++v) {
+    while (v >= end) {
+      if (h) atomicAdd(H + (int64_t)g * ncols + c, (unsigned long long)h);
+      h = 0;
+      ++g;
+      base = end;
+      end = vtx_off[g + 1];
+    }
+    if (Z[v * ld + c] > 0) h += splitmix64((uint64_t)(v - base));
+  }
+  if (h) atomicAdd(H + (int64_t)g * ncols + c, (unsigned long long)h);
 }
 
-// One workgroup per graph.  Candidates i < K: the old pool's slots (empty
+// One workgroup per graph g = blockIdx.x (taken: K + B bytes per graph).
+// Candidates i < K: the old pool's slots (empty
 // = INT64_MIN); i >= K: the round's columns (MIS: value -1 = not a
 // solution).  K times: the valid, untaken candidate of largest (value,
 // -i) fills the next slot, and every candidate with its (value, hash) is
@@ -1541,30 +1569,33 @@ __global__ __launch_bounds__(256) void k_pool_select(const int64_t *__restrict__
   }
 }
 
-// New pool solutions of one graph: slot k <- old slot SRC[k] (< K), column
-// SRC[k] - K of Z, or zeros (empty).
+// New pool solutions of every graph: slot k of row v's graph g <- old slot
+// SRC[g][k] (< K), column SRC[g][k] - K of Z, or zeros (empty).
 __global__ __launch_bounds__(256) void k_pool_copy(const int8_t *__restrict__ pz_old, const int8_t *__restrict__ Z,
                                                    const int32_t *__restrict__ src, int8_t *__restrict__ pz_new,
-                                                   int64_t lo, int64_t n, int32_t K, int32_t ld) {
+                                                   const int64_t *__restrict__ vtx_off, int32_t G, int64_t n_total,
+                                                   int32_t K, int32_t ld) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n * K) return;
-  const int64_t v = lo + idx / K;
+  if (idx >= n_total * K) return;
+  const int64_t v = idx / K;
   const int32_t k = (int32_t)(idx % K);
-  const int32_t s = src[k];
+  const int32_t s = src[(int64_t)graph_of_row(vtx_off, G, v) * K + k];
   pz_new[v * K + k] = s < 0 ? (int8_t)0 : s < K ? pz_old[v * K + s] : Z[v * ld + (s - K)];
 }
 
-// Pool slot each trajectory restarts from: (u * size) >> 32, u the Philox
-// draw of purpose POOL for (trajectory, round), lane 0; -1 if empty.
-__global__ void k_pool_bases(const int64_t *__restrict__ pv, int32_t K, int32_t ncols, uint64_t seed,
-                             uint64_t traj0, uint64_t round, int32_t *__restrict__ base) {
-  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
+// Pool slot each trajectory t = g ncols + c restarts from: (u * size) >> 32,
+// u the Philox draw of purpose POOL for (t, round), lane 0, size the filled
+// slots of graph g's pool (pv [G][K]); -1 if empty.
+__global__ void k_pool_bases(const int64_t *__restrict__ pv, int32_t K, int32_t G, int32_t ncols, uint64_t seed,
+                             uint64_t round, int32_t *__restrict__ base) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)G * ncols) return;
+  const int64_t *p = pv + (t / ncols) * K;
   int32_t size = 0;
-  for (int32_t k = 0; k < K; ++k) size += pv[k] != INT64_MIN;
+  for (int32_t k = 0; k < K; ++k) size += p[k] != INT64_MIN;
   uint32_t r[8];
-  philox_block8(r, seed, PURPOSE_POOL, traj0 + c, round, 0);
-  base[c] = size ? (int32_t)(((uint64_t)r[0] * (uint64_t)size) >> 32) : -1;
+  philox_block8(r, seed, PURPOSE_POOL, (uint64_t)t, round, 0);
+  base[t] = size ? (int32_t)(((uint64_t)r[0] * (uint64_t)size) >> 32) : -1;
 }
 
 // value[k] = INT64_MIN where the pool slot is empty (so a search of an empty
@@ -2416,26 +2447,25 @@ void launch_reset(bool maxcut, const int8_t *Zb, int32_t ldb, const uint32_t *ke
                ldb, seed, traj0, round, k, mode, Zp, ldp, base_slot);
 }
 
-void launch_pool_update(bool maxcut, const int8_t *Z, int32_t ld, int64_t lo, int64_t n, int32_t g, int32_t B,
-                        int32_t K, const int64_t *value, unsigned long long *hash, int8_t *taken,
+void launch_pool_update(bool maxcut, const int8_t *Z, int32_t ld, const int64_t *vtx_off, int32_t G, int64_t n_total,
+                        int32_t B, int32_t K, const int64_t *value, unsigned long long *hash, int8_t *taken,
                         const int8_t *pz_old, const int64_t *pv_old, const unsigned long long *ph_old,
                         int8_t *pz_new, int64_t *pv_new, unsigned long long *ph_new, int32_t *src, hipStream_t s) {
-  // hashes of the round's columns of graph g
-  MQO_LAUNCH(k_fill_i64, dim3(blocks_for(B)), dim3(256), 0, s, reinterpret_cast<int64_t *>(hash + (int64_t)g * B),
-             (int64_t)B, (int64_t)0);
-  MQO_LAUNCH(k_col_hash, dim3(blocks_for(((n + 255) >> 8) * B)), dim3(256), 0, s, Z, lo, n, B, ld,
-             hash + (int64_t)g * B);
-  // one workgroup: graph g's selection (pointers offset to g inside)
-  MQO_LAUNCH(k_pool_select, dim3(1), dim3(256), 0, s, pv_old + (int64_t)g * K, ph_old + (int64_t)g * K,
-             value + (int64_t)g * B, hash + (int64_t)g * B, K, B, maxcut ? 0 : 1, taken, pv_new + (int64_t)g * K,
-             ph_new + (int64_t)g * K, src + (int64_t)g * K);
-  MQO_LAUNCH(k_pool_copy, dim3(blocks_for(n * K)), dim3(256), 0, s, pz_old, Z, src + (int64_t)g * K, pz_new, lo, n,
-             K, ld);
+  // hashes of the round's columns of every graph
+  MQO_LAUNCH(k_fill_i64, dim3(blocks_for((int64_t)G * B)), dim3(256), 0, s, reinterpret_cast<int64_t *>(hash),
+             (int64_t)G * B, (int64_t)0);
+  MQO_LAUNCH(k_col_hash, dim3(blocks_for(((n_total + 255) >> 8) * B)), dim3(256), 0, s, Z, vtx_off, G, n_total, B,
+             ld, hash);
+  // one workgroup per graph: its selection
+  MQO_LAUNCH(k_pool_select, dim3((unsigned)G), dim3(256), 0, s, pv_old, ph_old, value, hash, K, B, maxcut ? 0 : 1,
+             taken, pv_new, ph_new, src);
+  MQO_LAUNCH(k_pool_copy, dim3(blocks_for(n_total * K)), dim3(256), 0, s, pz_old, Z, src, pz_new, vtx_off, G,
+             n_total, K, ld);
 }
 
-void launch_pool_bases(const int64_t *pv, int32_t K, int32_t ncols, uint64_t seed, uint64_t traj0, uint64_t round,
+void launch_pool_bases(const int64_t *pv, int32_t K, int32_t G, int32_t ncols, uint64_t seed, uint64_t round,
                        int32_t *base, hipStream_t s) {
-  MQO_LAUNCH(k_pool_bases, dim3(blocks_for(ncols)), dim3(256), 0, s, pv, K, ncols, seed, traj0, round, base);
+  MQO_LAUNCH(k_pool_bases, dim3(blocks_for((int64_t)G * ncols)), dim3(256), 0, s, pv, K, G, ncols, seed, round, base);
 }
 
 void launch_mask_empty(int64_t *value, const int64_t *pv, int64_t count, hipStream_t s) {

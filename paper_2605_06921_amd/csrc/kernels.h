@@ -80,16 +80,16 @@ void launch_reset(bool maxcut, const int8_t *Zb, int32_t ldb, const uint32_t *ke
                   int64_t n, int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0, uint64_t round, int32_t k,
                   int32_t mode, void *scratch, hipStream_t s, const int8_t *Zp = nullptr, int32_t ldp = 0,
                   const int32_t *base_slot = nullptr);
-// pmQO pool of graph g (rows [lo, lo + n)): TopK of the old pool
-// (pz_old [n_total][K], pv_old / ph_old [G][K]) united with the round's
-// columns of Z (values value [G][B]) into pz_new / pv_new / ph_new.  hash:
-// [G][B] scratch, taken: K + B bytes, src: [G][K].
-void launch_pool_update(bool maxcut, const int8_t *Z, int32_t ld, int64_t lo, int64_t n, int32_t g, int32_t B,
-                        int32_t K, const int64_t *value, unsigned long long *hash, int8_t *taken,
+// pmQO pool of every graph of the batch (vtx_off: device [G+1]): per graph,
+// TopK of the old pool (pz_old [n_total][K], pv_old / ph_old [G][K]) united
+// with the round's columns of Z (values value [G][B]) into pz_new / pv_new /
+// ph_new.  hash: [G][B] scratch, taken: G (K + B) bytes, src: [G][K].
+void launch_pool_update(bool maxcut, const int8_t *Z, int32_t ld, const int64_t *vtx_off, int32_t G, int64_t n_total,
+                        int32_t B, int32_t K, const int64_t *value, unsigned long long *hash, int8_t *taken,
                         const int8_t *pz_old, const int64_t *pv_old, const unsigned long long *ph_old,
                         int8_t *pz_new, int64_t *pv_new, unsigned long long *ph_new, int32_t *src, hipStream_t s);
-// base slot of every column of a graph (pv: its K pool values)
-void launch_pool_bases(const int64_t *pv, int32_t K, int32_t ncols, uint64_t seed, uint64_t traj0, uint64_t round,
+// base slot of every trajectory g ncols + c (pv [G][K]: the pool values)
+void launch_pool_bases(const int64_t *pv, int32_t K, int32_t G, int32_t ncols, uint64_t seed, uint64_t round,
                        int32_t *base, hipStream_t s);
 void launch_mask_empty(int64_t *value, const int64_t *pv, int64_t count, hipStream_t s);
 // *out = sum of in[0 .. count) in a fixed order (one workgroup)
