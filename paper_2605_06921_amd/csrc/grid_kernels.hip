@@ -1152,21 +1152,44 @@ __global__ __launch_bounds__(256) void k_flip2_best(GraphView g, const int8_t *_
   int32_t bg = 0, bp = -1, bmin = 0, bmax = 0;
   uint32_t bh = 0;
   const int32_t beg = g.row_ptr[v], end = g.row_ptr[v + 1];
-  for (int32_t j = beg; j < end; ++j) {
-    const int32_t u = g.col_idx[j];
-    const int64_t eu = (int64_t)u * ld + m.col;
-    const int32_t su = Z[eu];
-    if (su == sv) continue;
-    const int32_t gain = gv + su * NB[eu] + 2 * (WEIGHTED ? g.weight[j] : 1);
-    if (gain <= 0) continue;
-    const uint32_t h = pv + PRIO[eu];
-    const int32_t mn = (int32_t)v < u ? (int32_t)v : u, mx = (int32_t)v < u ? u : (int32_t)v;
-    if (bp < 0 || pair_beats(gain, h, mn, mx, bg, bh, bmin, bmax)) {
-      bg = gain;
-      bh = h;
-      bp = j;
-      bmin = mn;
-      bmax = mx;
+  // the neighbours four at a time: their states loaded together, then
+  // compared (the best pair key is a maximum, so the order of the
+  // comparisons does not change it)
+  for (int32_t j0 = beg; j0 < end; j0 += 4) {
+    int32_t uq[4], sq[4], nq[4], wq[4];
+    uint32_t pq[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) uq[t] = j0 + t < end ? g.col_idx[j0 + t] : -1;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (uq[t] >= 0) {
+        const int64_t eu = (int64_t)uq[t] * ld + m.col;
+        sq[t] = Z[eu];
+        nq[t] = NB[eu];
+        pq[t] = PRIO[eu];
+        wq[t] = WEIGHTED ? g.weight[j0 + t] : 1;
+      } else {
+        sq[t] = sv;  // no neighbour: skipped below
+        nq[t] = 0;
+        pq[t] = 0u;
+        wq[t] = 0;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int32_t u = uq[t], su = sq[t];
+      if (u < 0 || su == sv) continue;
+      const int32_t gain = gv + su * nq[t] + 2 * wq[t];
+      if (gain <= 0) continue;
+      const uint32_t h = pv + pq[t];
+      const int32_t mn = (int32_t)v < u ? (int32_t)v : u, mx = (int32_t)v < u ? u : (int32_t)v;
+      if (bp < 0 || pair_beats(gain, h, mn, mx, bg, bh, bmin, bmax)) {
+        bg = gain;
+        bh = h;
+        bp = j0 + t;
+        bmin = mn;
+        bmax = mx;
+      }
     }
   }
   BG[e] = bg;
