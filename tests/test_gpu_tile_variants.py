@@ -108,3 +108,25 @@ def test_single_buffer_tile_agrees(mqo, name, T, vec, csr, momentum, check):
         assert np.array_equal(out[key].cpu().numpy(), o[key]), key
     nnz_g = np.diff(g.row_ptr[g.vtx_offset])
     assert out["edge_updates"] == int((o["traj_steps"].reshape(g.num_graphs, -1) * nnz_g[:, None]).sum())
+
+
+def test_graph_launch_order_and_row_order(mqo):
+    """A batch of 16 graphs of unequal size (a multiple of 8, so the graphs
+    are dealt to the XCDs' ranges in snake order, largest first) on the
+    general step loop (rows walked in descending degree order), single- and
+    double-buffered: bit-exact against the oracle and the batched plan."""
+    rng = np.random.default_rng(71)
+    gs = [graphs.erdos_renyi(int(n), float(p), 200 + i)
+          for i, (n, p) in enumerate(zip(rng.integers(20, 90, 16), rng.uniform(0.05, 0.3, 16)))]
+    g = graphs.concat(gs)
+    assert g.num_graphs == 16
+    dg = mqo.DeviceGraph(g, DEV)
+    kw = dict(batch=16, steps_per_round=20, rounds=3, alpha=0.03, rho=0.1, seed=72)
+    o = solver.solve("mis", g, solver.Params(**kw))
+    ref = mqo.solve("mis", dg, plan="batched", **kw)
+    for sb in (1, 2):
+        out = mqo.solve("mis", dg, plan="persistent", tile_cols=8, tile_vec=4, tile_reg=1, tile_sb=sb, **kw)
+        assert out["plan"] == "persistent" and out["tile_reg_degree"] == 0 and out["tile_sb"] == sb - 1
+        for key in ("traj_best_value", "traj_best_x", "best_value", "best_x"):
+            assert np.array_equal(out[key].cpu().numpy(), o[key]), key
+            assert torch.equal(out[key], ref[key]), key
