@@ -331,7 +331,7 @@ Layout make_layout(const mqo_graph *g, int32_t B, int32_t K = 0) {
   L.tvm = take(tiles_elems * 4);
   L.tls = take(G * (int64_t)(B + 63) * 4);
   L.gorder = take(G * 4);  // persistent plan: graphs in launch order
-  L.lsval = take((size_t)B * 8);  // the 1-flip search's discarded values (not the round's)
+  L.lsval = take((size_t)B * 8);  // the searches' discarded values (not the round's)
   L.pX = take(n * 4);  // plain plan: one trajectory as contiguous vectors
   L.pXt = take(n * 4);
   L.pV = take(n * 4);
@@ -1599,7 +1599,7 @@ int pair_on(Solve &S, const PairCols &pc, int32_t rnd, int8_t *Z, float *const (
   hipEvent_t ph = S.phase_begin();
   TRY(pair_core(S.maxcut, S.g, pc, S.p->seed, rnd, Z, at<int32_t>(S.ws, S.L.NB), at<uint32_t>(S.ws, S.L.PRIO),
                 at<uint32_t>(S.ws, S.L.tprio), at<int8_t>(S.ws, S.L.F), at<int32_t>(S.ws, S.L.act),
-                at<long long>(S.ws, S.L.acc), at<int64_t>(S.ws, S.L.value), reinterpret_cast<int32_t *>(T[0]),
+                at<long long>(S.ws, S.L.acc), at<int64_t>(S.ws, S.L.lsval), reinterpret_cast<int32_t *>(T[0]),
                 reinterpret_cast<int32_t *>(T[1]), reinterpret_cast<int32_t *>(T[2]), at<uint32_t>(S.ws, S.L.tnb),
                 S.s, &S.ls_iters, &alt, nullptr));
   S.phase_end(PH_PAIR_SEARCH, ph);
