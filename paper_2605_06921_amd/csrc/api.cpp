@@ -1972,7 +1972,7 @@ int objective_grad_run(const mqo_graph *g, mqo_objective obj, float param, const
     const float *sc = scale ? scale + (int64_t)gi * B : nullptr;
     double *part = f_out ? reinterpret_cast<double *>(part_ws) : nullptr;
     launch_objective_grad(form, gv, X, sc, grad_out, part, B, B, cfg, param, s);
-    if (f_out) launch_reduce_partials(part, spmm_row_blocks(gv, cfg, form) + gv.nhub, B, f_out + (int64_t)gi * B, false, s);
+    if (f_out) launch_reduce_partials(part, spmm_row_blocks(gv, cfg) + gv.nhub, B, f_out + (int64_t)gi * B, false, s);
   }
   HIP_TRY(hipGetLastError());
   return MQO_OK;
@@ -2138,7 +2138,7 @@ int mqo_pga_unrolled_backward(const mqo_graph *g, mqo_objective obj, float param
   const int32_t nseg = K / ckpt_every;
   for (int32_t gi = 0; gi < g->num_graphs; ++gi) {
     const GraphView gv = view_of(g, gi);
-    const int64_t nblk = spmm_row_blocks(gv, cfg, form) + gv.nhub;
+    const int64_t nblk = spmm_row_blocks(gv, cfg) + gv.nhub;
     launch_copy_f32(dL_dXK + gv.lo * B, lamA + gv.lo * B, gv.n * B, s);
     launch_fill_i64(reinterpret_cast<int64_t *>(dL_dalpha + (int64_t)gi * B), B, 0, s);  // +0.0
     float *cur = lamA, *nxt = lamB;

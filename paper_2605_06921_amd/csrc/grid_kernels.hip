@@ -2147,13 +2147,11 @@ StepCfg default_step_cfg(int32_t ncols, int32_t ld) {
 // (hub row, column slice).
 // rows per lane group of the sparse-product kernels: pairs on near-regular
 // graphs when a row has 4 or more lanes (the lockstep gather shuffles
-// indices), for h and f_B
-static inline int spmm_rows(const GraphView &g, int ll, int form) {
-  return g.pairs && ll >= 2 && (form == OBJ_H || form == OBJ_FB) ? 2 : 1;
-}
+// indices)
+static inline int spmm_rows(const GraphView &g, int ll) { return g.pairs && ll >= 2 ? 2 : 1; }
 
-static inline dim3 spmm_grid(const GraphView &g, int32_t ncols, int ll, int vec, int form) {
-  const int rows = spmm_rows(g, ll, form);
+static inline dim3 spmm_grid(const GraphView &g, int32_t ncols, int ll, int vec) {
+  const int rows = spmm_rows(g, ll);
   dim3 grid = grid_rows((g.n + rows - 1) / rows, ncols, ll, vec, 256);
   grid.x = (unsigned)(grid.x + hub_blocks(g, ncols));
   return grid;
@@ -2192,13 +2190,11 @@ struct StepLaunch {
   static void run(const GraphView &g, const float *X, float *Xn, float *V, int32_t ncols, int32_t ld, int ll,
                   float alpha, float mu, float param, const int8_t *colact, hipStream_t s) {
     const size_t lds = g.nhub ? hub_lds(W) : 0;
-    const dim3 grid = spmm_grid(g, ncols, ll, VEC, OBJ);
-    if constexpr (OBJ == OBJ_H || OBJ == OBJ_FB) {
-      if (spmm_rows(g, ll, OBJ) == 2) {
-        MQO_LAUNCH((k_pga_step<VEC, OBJ, W, MOMENTUM, 2>), grid, dim3(256), lds, s, g, X, Xn, V, ncols, ld, ll, alpha,
-                   mu, param, colact);
-        return;
-      }
+    const dim3 grid = spmm_grid(g, ncols, ll, VEC);
+    if (spmm_rows(g, ll) == 2) {
+      MQO_LAUNCH((k_pga_step<VEC, OBJ, W, MOMENTUM, 2>), grid, dim3(256), lds, s, g, X, Xn, V, ncols, ld, ll, alpha, mu,
+                 param, colact);
+      return;
     }
     if (g.nhub > 0)  // uneven degrees: eight gathers in flight per lane group
       MQO_LAUNCH((k_pga_step<VEC, OBJ, W, MOMENTUM, 1, 8>), grid, dim3(256), lds, s, g, X, Xn, V, ncols, ld, ll,
@@ -2564,8 +2560,8 @@ void launch_validate_cols(const int32_t *row_ptr, const int32_t *col_idx, const 
 
 int64_t grid_blocks_x(int64_t nrows, StepCfg cfg) { return grid_rows(nrows, 1, cfg.lanes_log2, 1, 256).x; }
 
-int64_t spmm_row_blocks(const GraphView &g, StepCfg cfg, int form) {
-  const int rows = spmm_rows(g, cfg.lanes_log2, form);
+int64_t spmm_row_blocks(const GraphView &g, StepCfg cfg) {
+  const int rows = spmm_rows(g, cfg.lanes_log2);
   return grid_rows((g.n + rows - 1) / rows, 1, cfg.lanes_log2, 1, 256).x;
 }
 
@@ -2575,13 +2571,11 @@ struct ObjLaunch {
   static void run(const GraphView &g, const float *X, const float *scale, float *grad, double *part, int32_t ncols,
                   int32_t ld, int ll, float param, hipStream_t s) {
     const size_t lds = std::max(g.nhub ? hub_lds(W) : 0, part ? PARTIAL_LDS(VEC) : 0);
-    const dim3 grid = spmm_grid(g, ncols, ll, VEC, OBJ);
-    if constexpr (OBJ == OBJ_H || OBJ == OBJ_FB) {
-      if (spmm_rows(g, ll, OBJ) == 2) {
-        MQO_LAUNCH((k_objective_grad<VEC, OBJ, W, 2>), grid, dim3(256), lds, s, g, X, scale, grad, part, ncols, ld, ll,
-                   param);
-        return;
-      }
+    const dim3 grid = spmm_grid(g, ncols, ll, VEC);
+    if (spmm_rows(g, ll) == 2) {
+      MQO_LAUNCH((k_objective_grad<VEC, OBJ, W, 2>), grid, dim3(256), lds, s, g, X, scale, grad, part, ncols, ld, ll,
+                 param);
+      return;
     }
     if (g.nhub > 0)  // uneven degrees: eight gathers in flight per lane group
       MQO_LAUNCH((k_objective_grad<VEC, OBJ, W, 1, 8>), grid, dim3(256), lds, s, g, X, scale, grad, part, ncols, ld,
@@ -2631,16 +2625,13 @@ struct AdjLaunch {
   template <int OBJ, bool W>
   static void run(const GraphView &g, const float *Xk, const float *lam_next, float *mu, float *lam, double *part,
                   int32_t ncols, int32_t ld, int ll, float alpha, float param, hipStream_t s) {
-    const dim3 grid = spmm_grid(g, ncols, ll, VEC, OBJ);
+    const dim3 grid = spmm_grid(g, ncols, ll, VEC);
     const size_t lds_mu = std::max(g.nhub ? hub_lds(W) : 0, PARTIAL_LDS(VEC)), lds_lam = g.nhub ? hub_lds(W) : 0;
-    if constexpr (OBJ == OBJ_H || OBJ == OBJ_FB) {
-      if (spmm_rows(g, ll, OBJ) == 2) {
-        MQO_LAUNCH((k_adj_mu<VEC, OBJ, W, 2>), grid, dim3(256), lds_mu, s, g, Xk, lam_next, mu, part, ncols, ld, ll,
-                   alpha, param);
-        MQO_LAUNCH((k_adj_lambda<VEC, OBJ, W, 2>), grid, dim3(256), lds_lam, s, g, mu, lam, ncols, ld, ll, alpha,
-                   param);
-        return;
-      }
+    if (spmm_rows(g, ll) == 2) {
+      MQO_LAUNCH((k_adj_mu<VEC, OBJ, W, 2>), grid, dim3(256), lds_mu, s, g, Xk, lam_next, mu, part, ncols, ld, ll,
+                 alpha, param);
+      MQO_LAUNCH((k_adj_lambda<VEC, OBJ, W, 2>), grid, dim3(256), lds_lam, s, g, mu, lam, ncols, ld, ll, alpha, param);
+      return;
     }
     if (g.nhub > 0) {  // uneven degrees: eight gathers in flight per lane group
       MQO_LAUNCH((k_adj_mu<VEC, OBJ, W, 1, 8>), grid, dim3(256), lds_mu, s, g, Xk, lam_next, mu, part, ncols, ld, ll,

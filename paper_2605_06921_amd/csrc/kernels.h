@@ -18,7 +18,7 @@ struct StepCfg {
 StepCfg default_step_cfg(int32_t ncols, int32_t ld);
 int64_t grid_blocks_x(int64_t nrows, StepCfg cfg);
 // row workgroups of a sparse-product launch over graph g (without hub workgroups)
-int64_t spmm_row_blocks(const GraphView &g, StepCfg cfg, int form);
+int64_t spmm_row_blocks(const GraphView &g, StepCfg cfg);
 
 // start: index of the fresh start (0 = the first; the outer loop's later
 // starts use 1, 2, ...)
