@@ -183,12 +183,16 @@ __device__ __forceinline__ void add_neighbour(float (&acc)[VEC], const float (&x
   }
 }
 
+// wsum: the row's weight sum W_v (its degree when unweighted), an exact
+// integer sum of the weights the gather loads anyway (valid where colok).
 template <int VEC, bool WEIGHTED, int KB = 4>
 __device__ __forceinline__ void row_gather(const GraphView &g, const float *__restrict__ X, int64_t v, int32_t col,
-                                           int32_t ld, int32_t lanes_log2, bool colok, float (&acc)[VEC]) {
+                                           int32_t ld, int32_t lanes_log2, bool colok, float (&acc)[VEC],
+                                           int32_t &wsum) {
 #pragma unroll
   for (int i = 0; i < VEC; ++i) acc[i] = 0.0f;
   const int32_t beg = g.row_ptr[v], end = g.row_ptr[v + 1];
+  wsum = WEIGHTED ? 0 : end - beg;
   if (lanes_log2 >= 2) {
     const int32_t lanes = 1 << lanes_log2;
     const int32_t lane = threadIdx.x & (lanes - 1);
@@ -218,6 +222,11 @@ __device__ __forceinline__ void row_gather(const GraphView &g, const float *__re
 #pragma unroll
         for (int kk = 0; kk < KB; ++kk)
           if (colok && k0 + kk < cnt) add_neighbour<VEC, WEIGHTED>(acc, x[kk], w[kk]);
+        if (WEIGHTED) {
+#pragma unroll
+          for (int kk = 0; kk < KB; ++kk)
+            if (k0 + kk < cnt) wsum += w[kk];
+        }
       }
     }
     return;
@@ -237,6 +246,7 @@ __device__ __forceinline__ void row_gather(const GraphView &g, const float *__re
       float x[VEC];
       load_vec<VEC>(X + (int64_t)u[k] * ld + col, x);
       add_neighbour<VEC, WEIGHTED>(acc, x, w[k]);
+      if (WEIGHTED) wsum += w[k];
     }
   }
 }
@@ -247,7 +257,7 @@ __device__ __forceinline__ void row_gather(const GraphView &g, const float *__re
 template <int VEC, bool WEIGHTED>
 __device__ __forceinline__ void row_gather2(const GraphView &g, const float *__restrict__ X, int64_t v0, int64_t v1,
                                             int32_t col, int32_t ld, int32_t lanes_log2, bool colok,
-                                            float (&a0)[VEC], float (&a1)[VEC]) {
+                                            float (&a0)[VEC], float (&a1)[VEC], int32_t &ws0, int32_t &ws1) {
 #pragma unroll
   for (int i = 0; i < VEC; ++i) {
     a0[i] = 0.0f;
@@ -255,6 +265,8 @@ __device__ __forceinline__ void row_gather2(const GraphView &g, const float *__r
   }
   const int32_t b0 = g.row_ptr[v0], e0 = g.row_ptr[v0 + 1];
   const int32_t b1 = g.row_ptr[v1];
+  ws0 = WEIGHTED ? 0 : e0 - b0;
+  ws1 = ws0;
   const int32_t lanes = 1 << lanes_log2;
   const int32_t lane = threadIdx.x & (lanes - 1);
   for (int32_t j = 0; j < e0 - b0; j += lanes) {
@@ -268,6 +280,10 @@ __device__ __forceinline__ void row_gather2(const GraphView &g, const float *__r
     for (int32_t k = 0; k < cnt; ++k) {
       const int64_t u0 = __shfl(u0l, k, lanes), u1 = __shfl(u1l, k, lanes);
       const int32_t w0 = WEIGHTED ? __shfl(w0l, k, lanes) : 1, w1 = WEIGHTED ? __shfl(w1l, k, lanes) : 1;
+      if (WEIGHTED) {
+        ws0 += w0;
+        ws1 += w1;
+      }
       if (!colok) continue;
       float x0[VEC], x1[VEC];
       load_vec<VEC>(X + u0 * ld + col, x0);
@@ -366,14 +382,15 @@ __device__ __forceinline__ bool is_hub_row(const GraphView &g, int64_t v) {
 
 // The ROWS rows of a lane group in row workgroup bx (rows grp and grp + rpb
 // of a ROWS * rpb-row block; rpb = lane groups per workgroup), whether the
-// group owns each (in range, not a hub; uniform over the group), and their
-// neighbour sums.  Every lane of the group must call it.  ROWS = 2 is
+// group owns each (in range, not a hub; uniform over the group), their
+// neighbour sums and their weight sums W_v.  Every lane of the group must call it.  ROWS = 2 is
 // launched for near-regular graphs only: two rows of equal degree go in
 // lockstep, otherwise one after the other.
 template <int VEC, bool WEIGHTED, int ROWS, int KB = 4>
 __device__ __forceinline__ void group_gather(const GraphView &g, const float *__restrict__ X, int64_t bx, int32_t by,
                                              int32_t ncols, int32_t ld, int32_t lanes_log2, int64_t (&v)[ROWS],
-                                             bool (&own)[ROWS], int32_t &col, float (&acc)[ROWS][VEC]) {
+                                             bool (&own)[ROWS], int32_t &col, float (&acc)[ROWS][VEC],
+                                             int32_t (&wsum)[ROWS]) {
   const int32_t lanes = 1 << lanes_log2;
   const int32_t rpb = blockDim.x >> lanes_log2;
   const int64_t r0 = bx * ROWS * rpb + (threadIdx.x >> lanes_log2);
@@ -384,21 +401,22 @@ __device__ __forceinline__ void group_gather(const GraphView &g, const float *__
     const int64_t r = r0 + (int64_t)k * rpb;
     v[k] = g.lo + r;
     own[k] = r < g.n && !is_hub_row(g, v[k]);
+    wsum[k] = 0;
   }
   if constexpr (ROWS == 2) {
     if (own[0] && own[1] &&
         g.row_ptr[v[0] + 1] - g.row_ptr[v[0]] == g.row_ptr[v[1] + 1] - g.row_ptr[v[1]]) {
-      row_gather2<VEC, WEIGHTED>(g, X, v[0], v[1], col, ld, lanes_log2, colok, acc[0], acc[1]);
+      row_gather2<VEC, WEIGHTED>(g, X, v[0], v[1], col, ld, lanes_log2, colok, acc[0], acc[1], wsum[0], wsum[1]);
       return;
     }
   }
 #pragma unroll
   for (int k = 0; k < ROWS; ++k)
-    if (own[k]) row_gather<VEC, WEIGHTED, KB>(g, X, v[k], col, ld, lanes_log2, colok, acc[k]);
+    if (own[k]) row_gather<VEC, WEIGHTED, KB>(g, X, v[k], col, ld, lanes_log2, colok, acc[k], wsum[k]);
 }
 
-// One PGA step of Sec. 3 (with optional heavy-ball momentum) for a single column.
 // W_v, the row's weight sum (its degree when unweighted), for f_L and f_P
+// on hub rows (lane groups take it from their gather)
 template <bool WEIGHTED>
 __device__ __forceinline__ float weighted_degree(const GraphView &g, int64_t v) {
   const int32_t beg = g.row_ptr[v], end = g.row_ptr[v + 1];
@@ -408,6 +426,7 @@ __device__ __forceinline__ float weighted_degree(const GraphView &g, int64_t v) 
   return (float)w;
 }
 
+// One PGA step of Sec. 3 (with optional heavy-ball momentum) for a single column.
 template <int OBJ, bool MOMENTUM>
 __device__ __forceinline__ void step_update(float &x, float &vv, float acc, float W, float alpha, float mu,
                                             float param) {
@@ -452,7 +471,8 @@ __global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__re
   bool own[ROWS];
   int32_t col;
   float acc[ROWS][VEC];
-  group_gather<VEC, WEIGHTED, ROWS, KB>(g, X, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc);
+  int32_t wsum[ROWS];
+  group_gather<VEC, WEIGHTED, ROWS, KB>(g, X, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc, wsum);
   if (col >= ncols) return;
 #pragma unroll
   for (int k = 0; k < ROWS; ++k) {
@@ -460,7 +480,7 @@ __global__ __launch_bounds__(256) void k_pga_step(GraphView g, const float *__re
     float x[VEC], vv[VEC];
     load_vec<VEC>(X + v[k] * ld + col, x);
     if (MOMENTUM) load_vec<VEC>(V + v[k] * ld + col, vv);
-    const float W = OBJ == OBJ_FL || OBJ == OBJ_FP ? weighted_degree<WEIGHTED>(g, v[k]) : 0.0f;
+    const float W = OBJ == OBJ_FL || OBJ == OBJ_FP ? (float)wsum[k] : 0.0f;
 #pragma unroll
     for (int i = 0; i < VEC; ++i)
       if (!colact || colact[col + i]) step_update<OBJ, MOMENTUM>(x[i], vv[i], acc[k][i], W, alpha, mu, param);
@@ -1907,7 +1927,8 @@ __global__ __launch_bounds__(256) void k_objective_grad(GraphView g, const float
   bool own[ROWS];
   int32_t col;
   float acc[ROWS][VEC];
-  group_gather<VEC, WEIGHTED, ROWS, KB>(g, X, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc);
+  int32_t wsum[ROWS];
+  group_gather<VEC, WEIGHTED, ROWS, KB>(g, X, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc, wsum);
   double fv[VEC];
 #pragma unroll
   for (int i = 0; i < VEC; ++i) fv[i] = 0.0;
@@ -1918,7 +1939,7 @@ __global__ __launch_bounds__(256) void k_objective_grad(GraphView g, const float
     any = true;
     float x[VEC], gr[VEC];
     load_vec<VEC>(X + v[k] * ld + col, x);
-    const float W = OBJ == OBJ_FL || OBJ == OBJ_FP ? weighted_degree<WEIGHTED>(g, v[k]) : 0.0f;
+    const float W = OBJ == OBJ_FL || OBJ == OBJ_FP ? (float)wsum[k] : 0.0f;
 #pragma unroll
     for (int i = 0; i < VEC; ++i) {
       double f;
@@ -2006,7 +2027,8 @@ __global__ __launch_bounds__(256) void k_adj_mu(GraphView g, const float *__rest
   bool own[ROWS];
   int32_t col;
   float acc[ROWS][VEC];
-  group_gather<VEC, WEIGHTED, ROWS, KB>(g, Xk, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc);
+  int32_t wsum[ROWS];
+  group_gather<VEC, WEIGHTED, ROWS, KB>(g, Xk, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc, wsum);
   double dv[VEC];
 #pragma unroll
   for (int i = 0; i < VEC; ++i) dv[i] = 0.0;
@@ -2018,7 +2040,7 @@ __global__ __launch_bounds__(256) void k_adj_mu(GraphView g, const float *__rest
     float x[VEC], ln[VEC], mu[VEC];
     load_vec<VEC>(Xk + v[k] * ld + col, x);
     load_vec<VEC>(lam_next + v[k] * ld + col, ln);
-    const float W = OBJ == OBJ_FL || OBJ == OBJ_FP ? weighted_degree<WEIGHTED>(g, v[k]) : 0.0f;
+    const float W = OBJ == OBJ_FL || OBJ == OBJ_FP ? (float)wsum[k] : 0.0f;
 #pragma unroll
     for (int i = 0; i < VEC; ++i) {
       double d;
@@ -2075,14 +2097,15 @@ __global__ __launch_bounds__(256) void k_adj_lambda(GraphView g, const float *__
   bool own[ROWS];
   int32_t col;
   float acc[ROWS][VEC];
-  group_gather<VEC, WEIGHTED, ROWS, KB>(g, mu, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc);
+  int32_t wsum[ROWS];
+  group_gather<VEC, WEIGHTED, ROWS, KB>(g, mu, blk.x - nhb, blk.y, ncols, ld, lanes_log2, v, own, col, acc, wsum);
   if (col >= ncols) return;
 #pragma unroll
   for (int k = 0; k < ROWS; ++k) {
     if (!own[k]) continue;
     float mv[VEC], out[VEC];
     load_vec<VEC>(mu + v[k] * ld + col, mv);
-    const float W = OBJ == OBJ_FL || OBJ == OBJ_FP ? weighted_degree<WEIGHTED>(g, v[k]) : 0.0f;
+    const float W = OBJ == OBJ_FL || OBJ == OBJ_FP ? (float)wsum[k] : 0.0f;
 #pragma unroll
     for (int i = 0; i < VEC; ++i) out[i] = adjoint_lambda<OBJ>(mv[i], acc[k][i], W, alpha, param);
     store_vec<VEC>(lam + v[k] * ld + col, out);
