@@ -534,71 +534,107 @@ __global__ __launch_bounds__(256) void k_round(const float *__restrict__ X, int8
   Z[v * ld + c] = round_x<MAXCUT>(X[v * ld + c]);
 }
 
+// VEC int8 states from p (4-byte aligned when VEC = 4), sign-extended
+template <int VEC>
+__device__ __forceinline__ void load_z(const int8_t *p, int32_t (&z)[VEC]) {
+  if constexpr (VEC == 4) {
+    const uint32_t w = *reinterpret_cast<const uint32_t *>(p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) z[i] = (int32_t)(int8_t)(w >> (8 * i));
+  } else {
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) z[i] = p[i];
+  }
+}
+
 // NB = A Z (int32) and per-column accumulators acc[3][ncols] (int64):
 // MIS  : acc0 = |I|, acc1 = sum z m = 2 * edges inside I, acc2 = #{v: z=0, m=0}
 // MaxCut: acc0 = sum_v (W_v - s_v t_v) = 4 Cut(S)   (W_v = sum of row weights),
 //         acc1 = #{v: the projected step would move s_v}
-template <bool MAXCUT, bool WEIGHTED>
+// Each lane takes VEC consecutive columns (VEC = 4: one 4-byte state load
+// per neighbour, one 16-byte count store; needs ncols, ld multiples of 4).
+template <bool MAXCUT, bool WEIGHTED, int VEC>
 __global__ __launch_bounds__(256) void k_nbr_eval(GraphView g, const int8_t *__restrict__ Z, int32_t *__restrict__ NB,
                                                   unsigned long long *__restrict__ acc, int32_t ncols, int32_t ld,
                                                   int32_t lanes_log2) {
   // per-column sums: wavefront shuffle reduction over the lanes of one column,
   // then one LDS add per (wavefront, column) and one global atomic per
   // (block, column)
-  __shared__ long long sacc[3][64];
+  constexpr int SC = 64 * VEC;  // columns of a workgroup's slice, at most
+  __shared__ long long sacc[3][SC];
   const int lanes = 1 << lanes_log2;
-  if (threadIdx.x < 3 * 64) sacc[threadIdx.x / 64][threadIdx.x % 64] = 0;
+  for (int t = threadIdx.x; t < 3 * SC; t += blockDim.x) sacc[t / SC][t % SC] = 0;
   __syncthreads();
   // grid-stride over the row workgroups, so that the per-column global
   // atomics are paid once per resident workgroup, not once per 256 rows
   const int64_t nrb = (g.n + (blockDim.x >> lanes_log2) - 1) / (blockDim.x >> lanes_log2);
-  long long a[3] = {0, 0, 0};
+  long long a[3][VEC];
+#pragma unroll
+  for (int i = 0; i < VEC; ++i) a[0][i] = a[1][i] = a[2][i] = 0;
   for (int64_t bx = blockIdx.x; bx < nrb; bx += gridDim.x) {
-    const RowMap m = map_rows<1>(g.n, ncols, lanes_log2, bx);
+    const RowMap m = map_rows<VEC>(g.n, ncols, lanes_log2, bx);
     if (!m.active) continue;
     const int64_t v = g.lo + m.row;
     const int32_t beg = g.row_ptr[v], end = g.row_ptr[v + 1];
-    int32_t s = 0, wsum = 0;
+    int32_t s[VEC], wsum = 0;
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) s[i] = 0;
 #pragma unroll 4
     for (int32_t j = beg; j < end; ++j) {
       const int64_t u = __builtin_nontemporal_load(g.col_idx + j);
-      const int32_t zu = Z[u * ld + m.col];
+      int32_t zu[VEC];
+      load_z<VEC>(Z + u * ld + m.col, zu);
       if (WEIGHTED) {
         const int32_t w = __builtin_nontemporal_load(g.weight + j);
-        s += w * zu;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) s[i] += w * zu[i];
         wsum += w;
       } else {
-        s += zu;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) s[i] += zu[i];
       }
     }
     if (!WEIGHTED) wsum = end - beg;
-    if (NB) NB[v * ld + m.col] = s;
-    const int32_t zv = Z[v * ld + m.col];
-    if (MAXCUT) {
-      a[0] += (long long)wsum - (long long)zv * s;
-      // the projected f_B step moves s_v off the vertex unless s_v t_v < 0,
-      // or s_v t_v = 0 and s_v = -1 (gradient -lambda - 2 t_v, 0 < lambda < 2)
-      const int32_t st = zv * s;
-      a[1] += (st > 0 || (st == 0 && zv == 1)) ? 1 : 0;
-    } else {
-      a[0] += zv;
-      a[1] += zv ? s : 0;
-      a[2] += (zv == 0 && s == 0) ? 1 : 0;
+    if (NB) {
+      if constexpr (VEC == 4)
+        *reinterpret_cast<int4 *>(NB + v * ld + m.col) = make_int4(s[0], s[1], s[2], s[3]);
+      else
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) NB[v * ld + m.col + i] = s[i];
+    }
+    int32_t zv[VEC];
+    load_z<VEC>(Z + v * ld + m.col, zv);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      if (MAXCUT) {
+        a[0][i] += (long long)wsum - (long long)zv[i] * s[i];
+        // the projected f_B step moves s_v off the vertex unless s_v t_v < 0,
+        // or s_v t_v = 0 and s_v = -1 (gradient -lambda - 2 t_v, 0 < lambda < 2)
+        const int32_t st = zv[i] * s[i];
+        a[1][i] += (st > 0 || (st == 0 && zv[i] == 1)) ? 1 : 0;
+      } else {
+        a[0][i] += zv[i];
+        a[1][i] += zv[i] ? s[i] : 0;
+        a[2][i] += (zv[i] == 0 && s[i] == 0) ? 1 : 0;
+      }
     }
   }
   const int width = lanes < 64 ? lanes : 64;
   const int wl = threadIdx.x & 63;
 #pragma unroll
-  for (int k = 0; k < (MAXCUT ? 2 : 3); ++k) {
-    const long long t = wave_sum_stride(a[k], width);
-    if (wl < width && t) atomicAdd(reinterpret_cast<unsigned long long *>(&sacc[k][wl]), (unsigned long long)t);
-  }
+  for (int k = 0; k < (MAXCUT ? 2 : 3); ++k)
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      const long long t = wave_sum_stride(a[k][i], width);
+      if (wl < width && t)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&sacc[k][wl * VEC + i]), (unsigned long long)t);
+    }
   __syncthreads();
-  if ((int)threadIdx.x < lanes) {
-    const int32_t c = blockIdx.y * lanes + threadIdx.x;
+  for (int t = threadIdx.x; t < lanes * VEC; t += blockDim.x) {
+    const int32_t c = blockIdx.y * lanes * VEC + t;
     if (c < ncols) {
       for (int k = 0; k < (MAXCUT ? 2 : 3); ++k)
-        if (sacc[k][threadIdx.x]) atomicAdd(&acc[k * ncols + c], (unsigned long long)sacc[k][threadIdx.x]);
+        if (sacc[k][t]) atomicAdd(&acc[k * ncols + c], (unsigned long long)sacc[k][t]);
     }
   }
 }
@@ -2340,23 +2376,33 @@ void launch_round(bool maxcut, const float *X, int8_t *Z, int64_t lo, int64_t n,
 void launch_evaluate(bool maxcut, const GraphView &g, const int8_t *Z, int32_t *NB, long long *acc, int64_t *value,
                      int64_t *conflicts, int8_t *fixed, int32_t ncols, int32_t ld, hipStream_t s) {
   launch_fill_i64(reinterpret_cast<int64_t *>(acc), 3LL * ncols, 0, s);
-  const int ll = lanes_log2_for(ncols);
-  dim3 grid = grid_rows(g.n, ncols, ll, 1, 256);
+  // four columns per lane where the rows of Z and NB allow 4- and 16-byte access
+  const bool v4 = ncols % 4 == 0 && ld % 4 == 0 && ((uintptr_t)Z & 3) == 0 && ((uintptr_t)NB & 15) == 0;
+  const int vec = v4 ? 4 : 1;
+  const int ll = lanes_log2_for(ncols / vec);
+  dim3 grid = grid_rows(g.n, ncols, ll, vec, 256);
   if (grid.x > 2048) grid.x = 2048;  // workgroups stride over the rows
   unsigned long long *a = reinterpret_cast<unsigned long long *>(acc);
   const bool w = g.weight != nullptr;
+#define MQO_EVAL(MC, W)                                                                          \
+  if (v4)                                                                                        \
+    MQO_LAUNCH((k_nbr_eval<MC, W, 4>), grid, dim3(256), 0, s, g, Z, NB, a, ncols, ld, ll);       \
+  else                                                                                           \
+    MQO_LAUNCH((k_nbr_eval<MC, W, 1>), grid, dim3(256), 0, s, g, Z, NB, a, ncols, ld, ll);
   if (maxcut) {
-    if (w)
-      MQO_LAUNCH((k_nbr_eval<true, true>), grid, dim3(256), 0, s, g, Z, NB, a, ncols, ld, ll);
-    else
-      MQO_LAUNCH((k_nbr_eval<true, false>), grid, dim3(256), 0, s, g, Z, NB, a, ncols, ld, ll);
+    if (w) {
+      MQO_EVAL(true, true)
+    } else {
+      MQO_EVAL(true, false)
+    }
     MQO_LAUNCH(k_value_finalize<true>, dim3(blocks_for(ncols)), dim3(256), 0, s, acc, ncols, value, conflicts,
                fixed);
   } else {
-    MQO_LAUNCH((k_nbr_eval<false, false>), grid, dim3(256), 0, s, g, Z, NB, a, ncols, ld, ll);
+    MQO_EVAL(false, false)
     MQO_LAUNCH(k_value_finalize<false>, dim3(blocks_for(ncols)), dim3(256), 0, s, acc, ncols, value, conflicts,
                fixed);
   }
+#undef MQO_EVAL
 }
 
 void launch_ls_prio(uint32_t *PRIO, int64_t lo, int64_t n, int32_t ncols, int32_t ld, uint64_t seed, uint64_t traj0,
